@@ -1,0 +1,342 @@
+"""FP64 CPU oracle: BP-approximated tensor network simulation of the kicked Ising circuit.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call or link this
+module: only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` use it.  It shares no code with the HIP path.
+
+What it computes (arXiv 2306.14887, Tindall, Fishman, Stoudenmire, Sels):
+
+* The circuit (Eq. "Propagator"): one Floquet step is
+  U(theta_h) = prod_<v,v'> exp(+i pi/4 Z_v Z_v') . prod_v exp(-i theta_h X_v / 2),
+  the X rotations acting first; the state after n steps is U^n |0...0> (Eq. "State").
+* The state is a tensor network on the lattice graph (Fig. 1): one tensor per site with
+  a physical leg of dimension 2 and one virtual leg per neighbour.  It is kept in an
+  arbitrary gauge together with belief-propagation (BP) message tensors, which the
+  Methods show to be equivalent to working in the Vidal gauge.
+* The X rotations are applied exactly ("State ansatz").
+* Each two-site gate is applied by the reduced-tensor simple update in the BP gauge
+  (Methods, "The simple update procedure", Fig. "SimpleUpdate" steps i-v): the square
+  roots of the incoming messages are absorbed on the environment legs, each side is
+  QR-isolated, the gate is applied to the two R factors, the block is SVD-truncated to at
+  most chi singular values, the inverse square roots are absorbed back, and the message
+  on the updated edge becomes the SVD bond matrix.
+* After every Floquet step the network is regauged by BP (Methods, "Belief propagation
+  on a tensor network state", Eq. "MessageTensorSelfConsistency"): each directed message
+  is the contraction of the site tensor, its conjugate and all other incoming messages,
+  iterated to a fixed point.
+* Single-site expectation values use the rank-one BP environment (Eq. "SingleSIte");
+  Pauli strings on a cluster whose induced subgraph is a tree are contracted exactly
+  inside the cluster with BP messages on the cut legs.
+
+Readings where the paper is silent (all mirrored by the HIP path):
+  message normalisation: unit trace; singular values: unit 2-norm;
+  BP schedule: synchronous sweeps, warm-started from the current messages, residual =
+  max over directed edges of the Frobenius norm of the change, stop when < tol;
+  truncation: keep min(chi, #{sigma_i > eps_svd * sigma_1}) singular values;
+  message square roots: eigenvalues clipped at 0; inverse square roots keep eigenvalues
+  > eps_eig * lambda_max; gate layers: ascending colour of a proper edge colouring.
+
+Conventions: the legs of the tensor of site v are (physical, then neighbours in
+ascending site id).  A message M[a_ket, a_bra] carries the ket index first.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Pauli operators, 1 = X, 2 = Y, 3 = Z
+PAULI = {
+    0: np.eye(2, dtype=complex),
+    1: np.array([[0, 1], [1, 0]], dtype=complex),
+    2: np.array([[0, -1j], [1j, 0]], dtype=complex),
+    3: np.array([[1, 0], [0, -1]], dtype=complex),
+}
+
+
+def rx_matrix(theta: float) -> np.ndarray:
+    """exp(-i theta X / 2) (Eq. "Propagator")."""
+    c, s = math.cos(theta / 2), math.sin(theta / 2)
+    return np.array([[c, -1j * s], [-1j * s, c]], dtype=complex)
+
+
+def zz_gate_phases(sign: float = 1.0) -> np.ndarray:
+    """Diagonal of exp(+i pi/4 Z Z) as g[s_v, s_w] (Eq. "Propagator"); Z|0> = |0>."""
+    g = np.empty((2, 2), dtype=complex)
+    for a in range(2):
+        for b in range(2):
+            za, zb = 1 - 2 * a, 1 - 2 * b
+            g[a, b] = np.exp(1j * sign * math.pi / 4 * za * zb)
+    return g
+
+
+def absorb(T: np.ndarray, axis: int, X: np.ndarray) -> np.ndarray:
+    """Contract leg ``axis`` of T with the row index of X: T'[..b..] = sum_a T[..a..] X[a, b]."""
+    return np.moveaxis(np.tensordot(T, X, axes=([axis], [0])), -1, axis)
+
+
+def msg_sqrt(M: np.ndarray, eps_eig: float):
+    """Hermitian square root X = M^{1/2} and pseudo-inverse square root X+ of a message.
+
+    Used to absorb the BP environment onto the environment legs before the gate and to
+    remove it afterwards (Eq. "SymmetricTensor"; Fig. "SimpleUpdate" steps iv-v).
+    """
+    H = 0.5 * (M + M.conj().T)
+    lam, W = np.linalg.eigh(H)
+    lam = np.clip(lam, 0.0, None)
+    lmax = lam.max() if lam.size else 0.0
+    sq = np.sqrt(lam)
+    inv = np.where(lam > eps_eig * lmax, 1.0 / np.where(sq > 0, sq, 1.0), 0.0)
+    X = (W * sq) @ W.conj().T
+    Xp = (W * inv) @ W.conj().T
+    return X, Xp
+
+
+@dataclass
+class Options:
+    chi: int
+    bp_tol: float = 1e-12
+    bp_max_iter: int = 1000
+    svd_cutoff: float = 1e-12
+    eig_cutoff: float = 1e-12
+    zz_sign: float = 1.0            # +1: exp(+i pi/4 ZZ) as printed in Eq. "Propagator"
+
+
+class Network:
+    """Site tensors and directed BP messages of a tensor network state on a graph."""
+
+    def __init__(self, n_sites: int, edges, colour=None):
+        edges = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+        self.n = int(n_sites)
+        self.edges = [(int(u), int(v)) for u, v in edges.tolist()]
+        self.colour = (np.zeros(len(self.edges), dtype=np.int64) if colour is None
+                       else np.asarray(colour, dtype=np.int64))
+        nb = [[] for _ in range(self.n)]
+        for u, v in self.edges:
+            nb[u].append(v)
+            nb[v].append(u)
+        self.nb = [sorted(x) for x in nb]
+        # |0...0> as a bond-dimension-1 network (Eq. "State": all spins up)
+        self.T = []
+        for v in range(self.n):
+            t = np.zeros((2,) + (1,) * len(self.nb[v]), dtype=complex)
+            t[(0,) + (0,) * len(self.nb[v])] = 1.0
+            self.T.append(t)
+        self.M = {}
+        for u, v in self.edges:
+            self.M[(u, v)] = np.ones((1, 1), dtype=complex)
+            self.M[(v, u)] = np.ones((1, 1), dtype=complex)
+
+    def axis(self, v: int, u: int) -> int:
+        """Leg of T_v that points at neighbour u."""
+        return 1 + self.nb[v].index(u)
+
+    def bond_dim(self, u: int, v: int) -> int:
+        return self.T[u].shape[self.axis(u, v)]
+
+    # -- state evolution ---------------------------------------------------------------
+    def apply_rx(self, theta: float) -> None:
+        """Exact single-site rotation on every physical leg (first factor of U)."""
+        R = rx_matrix(theta)
+        for v in range(self.n):
+            self.T[v] = np.tensordot(R, self.T[v], axes=([1], [0]))
+
+    def _isolate(self, x: int, y: int, eps_eig: float):
+        """Absorb sqrt(messages) on the environment legs of x, then QR-isolate the bond.
+
+        Returns (Q or None, R[r, s, b], layout) with A = Q R, where A is the matricised
+        tensor with rows = environment legs and columns = (physical, bond to y).
+        """
+        T = self.T[x]
+        ax_y = self.axis(x, y)
+        env_axes, Xp = [], {}
+        Tt = T
+        for i, u in enumerate(self.nb[x]):
+            if u == y:
+                continue
+            ax = 1 + i
+            X, Xpinv = msg_sqrt(self.M[(u, x)], eps_eig)
+            Tt = absorb(Tt, ax, X)
+            Xp[ax] = Xpinv
+            env_axes.append(ax)
+        perm = env_axes + [0, ax_y]
+        A = np.transpose(Tt, perm)
+        env_shape = A.shape[:len(env_axes)]
+        rows = int(np.prod(env_shape)) if env_shape else 1
+        d_e = T.shape[ax_y]
+        A = A.reshape(rows, 2 * d_e)
+        if rows > 2 * d_e:
+            Q, R = np.linalg.qr(A, mode="reduced")
+        else:
+            Q, R = None, A
+        layout = (perm, env_shape, env_axes, Xp)
+        return Q, R.reshape(R.shape[0], 2, d_e), layout
+
+    def _rebuild(self, x: int, Q, Rn: np.ndarray, layout) -> None:
+        """T~' = Q R'; then remove the environment with the inverse square roots."""
+        perm, env_shape, env_axes, Xp = layout
+        r, _, k = Rn.shape
+        B = Rn.reshape(r, 2 * k)
+        if Q is not None:
+            B = Q @ B
+        B = B.reshape(tuple(env_shape) + (2, k))
+        inv = np.argsort(perm)
+        Tn = np.transpose(B, inv)
+        for ax in env_axes:
+            Tn = absorb(Tn, ax, Xp[ax])
+        self.T[x] = Tn
+
+    def simple_update(self, v: int, w: int, opt: Options) -> float:
+        """Apply exp(+i pi/4 Z_v Z_w) on edge (v, w); returns the discarded weight."""
+        Qv, Rv, lay_v = self._isolate(v, w, opt.eig_cutoff)
+        Qw, Rw, lay_w = self._isolate(w, v, opt.eig_cutoff)
+        g = zz_gate_phases(opt.zz_sign)
+        theta = np.einsum("isb,jtb->isjt", Rv, Rw) * g[None, :, None, :]
+        rv, rw = Rv.shape[0], Rw.shape[0]
+        mat = theta.reshape(rv * 2, rw * 2)
+        U, sig, Vh = np.linalg.svd(mat, full_matrices=False)
+        if sig.size == 0 or sig[0] <= 0.0:
+            raise FloatingPointError("simple update: zero two-site block")
+        k = int(min(opt.chi, np.count_nonzero(sig > opt.svd_cutoff * sig[0])))
+        total = float(np.sum(sig ** 2))
+        discarded = float(np.sum(sig[k:] ** 2)) / total
+        S = sig[:k] / np.linalg.norm(sig[:k])
+        sq = np.sqrt(S)
+        Rv_new = (U[:, :k] * sq[None, :]).reshape(rv, 2, k)
+        Rw_new = (sq[:, None] * Vh[:k, :]).reshape(k, rw, 2).transpose(1, 2, 0)
+        self._rebuild(v, Qv, Rv_new, lay_v)
+        self._rebuild(w, Qw, Rw_new, lay_w)
+        Mnew = np.diag(S / S.sum()).astype(complex)
+        self.M[(v, w)] = Mnew
+        self.M[(w, v)] = Mnew.copy()
+        return discarded
+
+    # -- belief propagation --------------------------------------------------------------
+    def message(self, v: int, w: int, M: dict) -> np.ndarray:
+        """M'_{v->w} = sum T_v (prod_{u != w} M_{u->v}) conj(T_v), unit trace
+        (Eq. "MessageTensorSelfConsistency")."""
+        T = self.T[v]
+        Y = T
+        for i, u in enumerate(self.nb[v]):
+            if u == w:
+                continue
+            Y = absorb(Y, 1 + i, M[(u, v)])
+        ax = self.axis(v, w)
+        others = [a for a in range(T.ndim) if a != ax]
+        out = np.tensordot(Y, T.conj(), axes=(others, others))
+        # Divide by the complex trace: the result has trace exactly 1.  (Dividing by the
+        # real part only would leave a common phase of the messages undamped; it grows
+        # by a factor degree-1 at every site and destabilises the sweep.)
+        tr = np.trace(out)
+        if not (tr.real > 0.0) or not np.isfinite(tr):
+            raise FloatingPointError(f"BP: non-positive message trace on {v}->{w}")
+        return out / tr
+
+    def bp_sweep(self):
+        new = {}
+        res = 0.0
+        for (v, w), old in self.M.items():
+            m = self.message(v, w, self.M)
+            new[(v, w)] = m
+            res = max(res, float(np.linalg.norm(m - old)))
+        self.M = new
+        return res
+
+    def bp(self, tol: float, max_iter: int):
+        it, res = 0, math.inf
+        while it < max_iter:
+            res = self.bp_sweep()
+            it += 1
+            if res < tol:
+                break
+        return it, res
+
+    # -- observables ---------------------------------------------------------------------
+    def site_density(self, v: int) -> np.ndarray:
+        """rho[s, s'] = sum T_v[s] (prod_u M_{u->v}) conj(T_v[s']) (Eq. "SingleSIte")."""
+        Y = self.T[v]
+        for i, u in enumerate(self.nb[v]):
+            Y = absorb(Y, 1 + i, self.M[(u, v)])
+        legs = list(range(1, Y.ndim))
+        return np.tensordot(Y, self.T[v].conj(), axes=(legs, legs))
+
+    def expect_site(self, v: int, op: int) -> float:
+        rho = self.site_density(v)
+        val = np.trace(PAULI[op] @ rho) / np.trace(rho)
+        return float(val.real)
+
+    def expect_pauli(self, sites, ops) -> float:
+        """<P> of a Pauli string on a cluster whose induced subgraph is a tree.
+
+        The cluster is contracted exactly; every leg that leaves the cluster is closed
+        with the incoming BP message.  Returns Re(<P>_BP / <I>_BP).
+        """
+        sites = [int(s) for s in sites]
+        opmap = {s: int(o) for s, o in zip(sites, ops)}
+        cset = set(sites)
+        inner = [(u, v) for (u, v) in self.edges if u in cset and v in cset]
+        if len(inner) != len(sites) - 1:
+            raise ValueError("Pauli cluster must induce a tree")
+        root = sites[0]
+
+        def value(with_ops: bool) -> complex:
+            def env(v: int, parent) -> np.ndarray:
+                O = PAULI[opmap[v]] if with_ops else PAULI[0]
+                # fold the operator onto the ket: T'[s] = sum_s' O[s, s'] T[s'] gives
+                # sum T' conj(T) = sum_{s,s'} O[s,s'] T[s'] conj(T[s]) = <O> contribution
+                Y = np.tensordot(O, self.T[v], axes=([1], [0]))
+                for i, u in enumerate(self.nb[v]):
+                    if u == parent:
+                        continue
+                    E = env(u, v) if u in cset else self.M[(u, v)]
+                    Y = absorb(Y, 1 + i, E)
+                legs = [a for a in range(Y.ndim)
+                        if parent is None or a != self.axis(v, parent)]
+                return np.tensordot(Y, self.T[v].conj(), axes=(legs, legs))
+            return complex(env(root, None))
+
+        return float((value(True) / value(False)).real)
+
+
+@dataclass
+class Result:
+    z: np.ndarray                       # [depth, n_sites] (or [1, n_sites])
+    pauli: np.ndarray                   # [n_pauli] at the final step
+    bp_iters: list = field(default_factory=list)
+    bp_residual: list = field(default_factory=list)
+    discarded: list = field(default_factory=list)
+    converged: bool = True
+
+
+def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
+          pauli=(), record_every_step: bool = True, net: Network | None = None) -> Result:
+    """Run ``depth`` Floquet steps and measure (Eq. "State"; Methods).
+
+    Each step: exact X rotations, then the simple-update gate layers in ascending
+    colour, then BP to convergence, then <Z_v> for every site.
+    ``pauli`` is a sequence of (sites, ops) evaluated after the final step.
+    """
+    if net is None:
+        net = Network(n_sites, edges, colour)
+    colours = sorted(set(int(c) for c in net.colour.tolist()))
+    zs, iters, resid, disc = [], [], [], []
+    converged = True
+    for _t in range(depth):
+        net.apply_rx(theta)
+        dsum = 0.0
+        for c in colours:
+            for e, (u, v) in enumerate(net.edges):
+                if int(net.colour[e]) == c:
+                    dsum += net.simple_update(u, v, opt)
+        it, res = net.bp(opt.bp_tol, opt.bp_max_iter)
+        converged &= res < opt.bp_tol
+        iters.append(it)
+        resid.append(res)
+        disc.append(dsum)
+        if record_every_step or _t == depth - 1:
+            zs.append([net.expect_site(v, 3) for v in range(net.n)])
+    if depth == 0:
+        zs.append([1.0] * net.n)
+    pv = np.array([net.expect_pauli(s, o) for s, o in pauli], dtype=float)
+    return Result(np.array(zs, dtype=float), pv, iters, resid, disc, converged)
