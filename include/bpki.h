@@ -1,0 +1,155 @@
+/*
+ * bpki — belief-propagation tensor-network simulation of the kicked Ising circuit on MI355X.
+ *
+ * C ABI of the library (libbpki.so).  Plain C types and pointers only.
+ *
+ * Method (arXiv 2306.14887, Tindall, Fishman, Stoudenmire, Sels):
+ *   One Floquet step applies U(theta_h) = prod_<v,w> exp(+i pi/4 Z_v Z_w) . prod_v exp(-i theta_h X_v/2)
+ *   (Eq. "Propagator") to the state |0...0> (Eq. "State").  The state is a tensor network with
+ *   the lattice's geometry (Fig. 1).  Every step applies the X rotations exactly, applies the two-site
+ *   gates one colour layer at a time by the reduced-tensor simple update in the belief-propagation
+ *   gauge, truncating every bond to at most chi (Methods, "The simple update procedure"), regauges
+ *   with BP (Methods, "Belief propagation on a tensor network state",
+ *   Eq. "MessageTensorSelfConsistency") and reads expectation values off the converged messages
+ *   (Eq. "SingleSIte"; Pauli strings on tree clusters are contracted exactly inside the cluster).
+ *
+ * Conventions shared by all entry points
+ *   - Sites are 0-based; an edge is an unordered pair (u, v), u != v.  Every site has degree 1..3.
+ *   - colour[e] is a proper edge colouring (edges that share a site differ).  Gate layers run in
+ *     ascending colour.  NULL asks the library for the greedy colouring over the edge list sorted by
+ *     (min, max) endpoint (smallest colour free at both ends).
+ *   - Pauli ops: 1 = X, 2 = Y, 3 = Z.  A string's sites must induce a tree in the lattice.
+ *   - All observables are real doubles.
+ *
+ * Return codes
+ *   0 OK;  +1 BP did not reach bp_tol within bp_max_iter at some step (outputs written);
+ *  -1 invalid argument; -2 invalid graph; -3 improper colouring; -4 out of memory / over budget;
+ *  -5 HIP/device error; -6 cancelled; -7 unknown ticket.  After an error nothing is written to the
+ *  outputs and bpki_last_error() describes it.
+ *
+ * Threading: a context is used by one host thread at a time.
+ */
+#ifndef BPKI_H
+#define BPKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bpki_ctx bpki_ctx;
+
+/* Arithmetic of the bulk contractions.  The eigendecompositions behind the truncation SVD, the
+ * message square roots and inverse square roots, the BP residual and the observables' final ratios
+ * are FP64 in every mode. */
+typedef enum {
+  BPKI_FP64 = 0,   /* everything FP64 (the parity mode)                      */
+  BPKI_FP32 = 1    /* site tensors and their contractions in FP32 on MFMA    */
+} bpki_precision;
+
+typedef struct {
+  int32_t n_sites;
+  int32_t n_edges;
+  const int32_t *edges;        /* [2*n_edges]; host memory; copied by the call                 */
+  const int32_t *colour;       /* [n_edges] or NULL (greedy colouring, see above)               */
+  double theta_h;              /* X rotation angle: exp(-i theta_h X / 2)                       */
+  int32_t depth;               /* Floquet steps, >= 0                                          */
+  int32_t chi;                 /* maximum bond dimension, 1..256                               */
+  int32_t precision;           /* bpki_precision                                               */
+  double bp_tol;               /* BP stops when max ||M'-M||_F < bp_tol   (e.g. 1e-12)         */
+  int32_t bp_max_iter;         /* e.g. 1000                                                     */
+  double svd_cutoff;           /* keep sigma_i > svd_cutoff * sigma_1     (e.g. 1e-12)         */
+  double eig_cutoff;           /* inverse square roots keep lambda > eig_cutoff * lambda_max    */
+  int32_t n_pauli;             /* Pauli strings measured after the final step                  */
+  const int32_t *pauli_offsets;/* [n_pauli+1] CSR offsets into pauli_sites / pauli_ops         */
+  const int32_t *pauli_sites;  /* [pauli_offsets[n_pauli]]                                     */
+  const uint8_t *pauli_ops;    /* [pauli_offsets[n_pauli]]  1=X 2=Y 3=Z                        */
+  int32_t record_every_step;   /* 1: z holds steps 1..depth; 0: final step only                */
+} bpki_problem;
+
+typedef struct {
+  double *z;            /* [(record_every_step ? depth : 1) * n_sites], row t = step t+1       */
+  double *pauli;        /* [n_pauli] or NULL if n_pauli == 0                                    */
+  int32_t *bp_iters;    /* optional [depth]: BP sweeps run after each step                      */
+  double *bp_residual;  /* optional [depth]: final BP residual of each step                     */
+  double *discarded;    /* optional [depth]: sum over the step's gates of the discarded weight  */
+} bpki_result;
+
+/* Fill *p with the defaults (tolerances 1e-12, 1000 sweeps, FP64, record every step). */
+void bpki_problem_defaults(bpki_problem *p);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a borrowed hipStream_t (never
+ * destroyed by the library) or NULL for a stream owned by the context.  `mem_budget_bytes` caps the
+ * device memory the context may hold (0 = no cap).  Returns 0 or a negative code. */
+int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t mem_budget_bytes);
+void bpki_destroy(bpki_ctx *ctx);
+
+/* Message of the last error on this thread (never NULL). */
+const char *bpki_last_error(void);
+
+/* Host-only checks (no device needed): ranges, graph (self loops, duplicates, degree 1..3),
+ * colouring, Pauli strings (valid ops, distinct sites, tree clusters). */
+int bpki_validate(const bpki_problem *p);
+
+/* Device bytes a solve of *p holds: site tensors (sum_v 2*chi^deg complex), messages
+ * (2 buffers of 2*|E|*chi^2 complex) and workspace.  Host only. */
+int bpki_estimate_bytes(const bpki_problem *p, size_t *bytes);
+
+/* Blocking solve.  Inputs are copied; result buffers are caller-owned host memory. */
+int bpki_solve(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
+
+/* ---- Serving: continuous batching -----------------------------------------------------------
+ * bpki_submit queues a problem (deep copy) and returns at once with a ticket.  A worker thread of
+ * the context admits queued problems while their bpki_estimate_bytes fits the memory budget,
+ * interleaves the Floquet steps of all resident problems on the device (requests start and finish
+ * at different times) and writes each result into its caller-owned buffers, which must stay valid
+ * until bpki_wait returns or bpki_poll reports done.  A problem that can never fit the budget is
+ * rejected with -4 by bpki_submit.  The result of a problem does not depend on what else is
+ * resident. */
+int bpki_submit(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r, uint64_t *ticket);
+/* *done = 1 when finished; returns the problem's status (0/+1/negative) once done, else 0. */
+int bpki_poll(bpki_ctx *ctx, uint64_t ticket, int *done);
+/* Blocks until the problem finishes; returns its status and forgets the ticket. */
+int bpki_wait(bpki_ctx *ctx, uint64_t ticket);
+/* Cancels a queued or running problem; its bpki_wait returns -6. */
+int bpki_cancel(bpki_ctx *ctx, uint64_t ticket);
+
+/* ---- Sessions: step-by-step access to one resident state -----------------------------------
+ * A session holds one problem's tensors and messages on the device.  It exposes each phase of a
+ * Floquet step, so that every phase can be checked against an independent implementation, and
+ * state import/export (checkpoint / resume).
+ *
+ * Site tensor v is exported as complex128 (re, im interleaved) in the layout
+ *   T_v[s][a_0]...[a_{d-1}],  s in {0,1}, a_i in [0, chi) for the i-th neighbour in ascending site
+ *   id, zero beyond the current bond dimension;
+ * message u->v (edge e = (edges[2e], edges[2e+1]); index 2e is edges[2e]->edges[2e+1], index 2e+1
+ * the reverse) as M[a_ket][a_bra], chi x chi complex128.  Buffers are host memory. */
+typedef struct bpki_session bpki_session;
+
+int bpki_session_open(bpki_ctx *ctx, const bpki_problem *p, bpki_session **out);
+void bpki_session_close(bpki_session *s);
+/* Complex entries of the exported state: sum over sites of 2*chi^deg, and 2*|E|*chi^2. */
+int bpki_session_sizes(const bpki_session *s, size_t *tensor_elems, size_t *message_elems);
+int bpki_session_get_state(bpki_session *s, double *tensors, double *messages, int32_t *bond_dims);
+int bpki_session_set_state(bpki_session *s, const double *tensors, const double *messages,
+                           const int32_t *bond_dims);
+/* Phases of one Floquet step (paper: "State ansatz" and Methods). */
+int bpki_session_apply_rx(bpki_session *s);
+int bpki_session_apply_layer(bpki_session *s, int32_t colour, double *discarded);
+int bpki_session_bp(bpki_session *s, int32_t max_iter, int32_t *iters, double *residual);
+int bpki_session_bp_sweep(bpki_session *s, double *residual);
+int bpki_session_observe_z(bpki_session *s, double *z);
+int bpki_session_observe_pauli(bpki_session *s, double *pauli);
+/* One whole Floquet step: X rotations, all gate layers, BP, then z (may be NULL). */
+int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residual,
+                      double *discarded);
+/* Total device time of the last bpki_session_step, split by phase (milliseconds): rx, gate layers,
+ * BP, observables.  Measured with HIP events on the session's stream. */
+int bpki_session_last_timing(const bpki_session *s, double *ms4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPKI_H */

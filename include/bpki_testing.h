@@ -1,0 +1,50 @@
+/*
+ * Test hooks of libbpki: the two device primitives every phase of the method is built from,
+ * exposed so that each can be checked element by element against an independent host
+ * computation.  Not needed to run simulations (see bpki.h).
+ *
+ * Buffers are host memory holding complex128 values as (re, im) pairs.  The library copies them
+ * to the device, runs the primitive on the context's stream and copies the result back.
+ * Errors: -1 invalid argument (including a descriptor that would address outside the buffers,
+ * checked on the host before any launch), -4 out of memory, -5 device error.
+ */
+#ifndef BPKI_TESTING_H
+#define BPKI_TESTING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bpki.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C[b][m][n] (=|+=) alpha * sum_k opA(A)[b][m][k] opB(B)[b][k][n] with composite indices:
+ * i = i_outer * Xi + i_inner, offset = i_outer * s_o + i_inner * s_i (strides in complex
+ * elements); opA/opB conjugate when conjA/conjB.  This is the contraction primitive of every
+ * leg absorption, Gram matrix, BP message and environment in the library. */
+typedef struct {
+  int32_t M, N, K, Mi, Ni, Ki;
+  int64_t a_mo, a_mi, a_ko, a_ki;
+  int64_t b_ko, b_ki, b_no, b_ni;
+  int64_t c_mo, c_mi, c_no, c_ni;
+  int64_t a_b, b_b, c_b;
+  int32_t batch, conjA, conjB, beta;
+  double alpha_re, alpha_im;
+} bpki_test_gemm_desc;
+
+/* Runs the FP64 MFMA GEMM on nprob problems; problem p uses A + 2*a_elems*p etc.  C is read
+ * (for beta = 1) and overwritten. */
+int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const double *A,
+                   size_t a_elems, const double *B, size_t b_elems, double *C, size_t c_elems);
+
+/* Batched Hermitian eigendecomposition (FP64 Jacobi) of nprob n x n matrices (n <= 256):
+ * evals [nprob][n] descending, vecs [nprob][n][n] with column i the eigenvector of evals[i]. */
+int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *evals,
+                   double *vecs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BPKI_TESTING_H */

@@ -1,0 +1,700 @@
+// C ABI of libbpki: validation, memory estimate, blocking solves, sessions and serving.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bpki.h"
+#include "../../include/bpki_testing.h"
+#include "bpki_internal.h"
+
+using namespace bpki;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+extern "C" const char *bpki_last_error(void) { return g_err.c_str(); }
+
+extern "C" void bpki_problem_defaults(bpki_problem *p) {
+  std::memset(p, 0, sizeof(*p));
+  p->theta_h = 0.0;
+  p->depth = 1;
+  p->chi = 8;
+  p->precision = BPKI_FP64;
+  p->bp_tol = 1e-12;
+  p->bp_max_iter = 1000;
+  p->svd_cutoff = 1e-12;
+  p->eig_cutoff = 1e-12;
+  p->record_every_step = 1;
+}
+
+// Greedy proper edge colouring over the edges sorted by (min, max) endpoint.
+static std::vector<int> greedy_colouring(int n, const int32_t *edges, int E) {
+  std::vector<int> order(E);
+  for (int i = 0; i < E; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    int a0 = std::min(edges[2 * a], edges[2 * a + 1]), a1 = std::max(edges[2 * a], edges[2 * a + 1]);
+    int b0 = std::min(edges[2 * b], edges[2 * b + 1]), b1 = std::max(edges[2 * b], edges[2 * b + 1]);
+    return a0 != b0 ? a0 < b0 : a1 < b1;
+  });
+  std::vector<std::set<int>> used(n);
+  std::vector<int> col(E, -1);
+  for (int i : order) {
+    int u = edges[2 * i], v = edges[2 * i + 1];
+    int c = 0;
+    while (used[u].count(c) || used[v].count(c)) ++c;
+    col[i] = c;
+    used[u].insert(c);
+    used[v].insert(c);
+  }
+  return col;
+}
+
+extern "C" int bpki_validate(const bpki_problem *p) {
+  if (!p) return fail(-1, "problem is NULL");
+  if (p->n_sites < 1) return fail(-1, "n_sites must be >= 1");
+  if (p->n_edges < 1) return fail(-2, "the lattice needs at least one edge");
+  if (!p->edges) return fail(-1, "edges is NULL");
+  if (!std::isfinite(p->theta_h)) return fail(-1, "theta_h must be finite");
+  if (p->depth < 0) return fail(-1, "depth must be >= 0");
+  if (p->chi < 1 || p->chi > 256) return fail(-1, "chi must be in 1..256");
+  if (p->precision != BPKI_FP64 && p->precision != BPKI_FP32)
+    return fail(-1, "precision must be BPKI_FP64 or BPKI_FP32");
+  if (!std::isfinite(p->bp_tol) || p->bp_tol < 0) return fail(-1, "bp_tol must be finite, >= 0");
+  if (p->bp_max_iter < 1) return fail(-1, "bp_max_iter must be >= 1");
+  if (!std::isfinite(p->svd_cutoff) || p->svd_cutoff < 0 || !std::isfinite(p->eig_cutoff) ||
+      p->eig_cutoff < 0)
+    return fail(-1, "cutoffs must be finite and >= 0");
+  if (p->record_every_step != 0 && p->record_every_step != 1)
+    return fail(-1, "record_every_step must be 0 or 1");
+  const int n = p->n_sites, E = p->n_edges;
+  std::vector<int> deg(n, 0);
+  std::set<std::pair<int, int>> seen;
+  for (int e = 0; e < E; ++e) {
+    int u = p->edges[2 * e], v = p->edges[2 * e + 1];
+    if (u < 0 || v < 0 || u >= n || v >= n) return fail(-2, "edge endpoint out of range");
+    if (u == v) return fail(-2, "self loop");
+    if (!seen.insert({std::min(u, v), std::max(u, v)}).second) return fail(-2, "duplicate edge");
+    deg[u]++;
+    deg[v]++;
+  }
+  for (int v = 0; v < n; ++v)
+    if (deg[v] < 1 || deg[v] > 3) return fail(-2, "every site must have degree 1..3");
+  if (p->colour) {
+    std::vector<std::set<int>> used(n);
+    for (int e = 0; e < E; ++e) {
+      int c = p->colour[e];
+      if (c < 0) return fail(-3, "negative colour");
+      int u = p->edges[2 * e], v = p->edges[2 * e + 1];
+      if (used[u].count(c) || used[v].count(c)) return fail(-3, "improper edge colouring");
+      used[u].insert(c);
+      used[v].insert(c);
+    }
+  }
+  if (p->n_pauli < 0) return fail(-1, "n_pauli must be >= 0");
+  if (p->n_pauli > 0) {
+    if (!p->pauli_offsets || !p->pauli_sites || !p->pauli_ops)
+      return fail(-1, "Pauli arrays are NULL");
+    if (p->pauli_offsets[0] != 0) return fail(-1, "pauli_offsets[0] must be 0");
+    for (int k = 0; k < p->n_pauli; ++k) {
+      int b = p->pauli_offsets[k], e = p->pauli_offsets[k + 1];
+      if (e <= b) return fail(-1, "empty or decreasing Pauli string");
+      std::set<int> s;
+      for (int i = b; i < e; ++i) {
+        int q = p->pauli_sites[i];
+        if (q < 0 || q >= n) return fail(-1, "Pauli site out of range");
+        if (!s.insert(q).second) return fail(-1, "repeated site in a Pauli string");
+        if (p->pauli_ops[i] < 1 || p->pauli_ops[i] > 3) return fail(-1, "Pauli op must be 1..3");
+      }
+      // induced subgraph must be a tree: connected with |S|-1 edges
+      int m = 0;
+      std::map<int, std::vector<int>> adj;
+      for (int ed = 0; ed < E; ++ed) {
+        int u = p->edges[2 * ed], v = p->edges[2 * ed + 1];
+        if (s.count(u) && s.count(v)) {
+          ++m;
+          adj[u].push_back(v);
+          adj[v].push_back(u);
+        }
+      }
+      if (m != (int)s.size() - 1) return fail(-1, "Pauli cluster does not induce a tree");
+      std::set<int> vis;
+      std::vector<int> st{*s.begin()};
+      while (!st.empty()) {
+        int x = st.back();
+        st.pop_back();
+        if (!vis.insert(x).second) continue;
+        for (int y : adj[x]) st.push_back(y);
+      }
+      if (vis.size() != s.size()) return fail(-1, "Pauli cluster is not connected");
+    }
+  }
+  return 0;
+}
+
+static Problem to_problem(const bpki_problem *p) {
+  Problem q;
+  q.n_sites = p->n_sites;
+  q.edges.assign(p->edges, p->edges + 2 * p->n_edges);
+  if (p->colour) q.colour.assign(p->colour, p->colour + p->n_edges);
+  else q.colour = greedy_colouring(p->n_sites, p->edges, p->n_edges);
+  q.theta = p->theta_h;
+  q.depth = p->depth;
+  q.chi = p->chi;
+  q.precision = p->precision;
+  q.bp_tol = p->bp_tol;
+  q.bp_max_iter = p->bp_max_iter;
+  q.svd_cutoff = p->svd_cutoff;
+  q.eig_cutoff = p->eig_cutoff;
+  q.record_every_step = p->record_every_step;
+  if (p->n_pauli > 0) {
+    q.pauli_offsets.assign(p->pauli_offsets, p->pauli_offsets + p->n_pauli + 1);
+    int tot = p->pauli_offsets[p->n_pauli];
+    q.pauli_sites.assign(p->pauli_sites, p->pauli_sites + tot);
+    q.pauli_ops.assign(p->pauli_ops, p->pauli_ops + tot);
+  } else {
+    q.pauli_offsets.assign(1, 0);
+  }
+  return q;
+}
+
+extern "C" int bpki_estimate_bytes(const bpki_problem *p, size_t *bytes) {
+  int rc = bpki_validate(p);
+  if (rc) return rc;
+  if (!bytes) return fail(-1, "bytes is NULL");
+  *bytes = Engine::estimate_bytes(to_problem(p));
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+struct bpki_ctx {
+  int device = 0;
+  void *stream = nullptr;
+  size_t budget = 0;
+  std::unique_ptr<Backend> be;
+  std::mutex mu;
+  // serving
+  struct Job;
+  std::map<uint64_t, std::shared_ptr<Job>> jobs;
+  std::deque<std::shared_ptr<Job>> queue;
+  std::thread worker;
+  std::condition_variable cv, done_cv;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+};
+
+extern "C" int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t budget) {
+  if (!out) return fail(-1, "out is NULL");
+  std::string err;
+  Backend *be = make_hip_backend(device, hip_stream, &err);
+  if (!be) return fail(-5, "bpki_create: " + err);
+  bpki_ctx *c = new bpki_ctx;
+  c->device = device;
+  c->stream = hip_stream;
+  c->budget = budget;
+  c->be.reset(be);
+  *out = c;
+  return 0;
+}
+
+static void serving_shutdown(bpki_ctx *c);
+
+extern "C" void bpki_destroy(bpki_ctx *c) {
+  if (!c) return;
+  serving_shutdown(c);
+  delete c;
+}
+
+// One whole solve on an engine; outputs written only on success.
+static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
+                     std::atomic<bool> *cancel) {
+  const int n = q.n_sites;
+  const int rows = q.record_every_step ? q.depth : 1;
+  std::vector<double> z((size_t)std::max(rows, 1) * n, 1.0);
+  std::vector<int32_t> iters(q.depth, 0);
+  std::vector<double> res(q.depth, 0.0), disc(q.depth, 0.0);
+  int warn = 0;
+  for (int t = 0; t < q.depth; ++t) {
+    if (cancel && cancel->load()) return fail(-6, "cancelled");
+    eng.apply_rx();
+    double d = 0;
+    for (int c : [&] {
+           std::vector<int> cs(q.colour.begin(), q.colour.end());
+           std::sort(cs.begin(), cs.end());
+           cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+           return cs;
+         }())
+      d += eng.apply_layer(c);
+    double rr = 0;
+    iters[t] = eng.bp(q.bp_max_iter, &rr);
+    res[t] = rr;
+    disc[t] = d;
+    if (!(rr < q.bp_tol)) warn = 1;
+    if (q.record_every_step || t == q.depth - 1) {
+      int row = q.record_every_step ? t : 0;
+      eng.observe_z(&z[(size_t)row * n]);
+    }
+    std::string msg;
+    int e = be->check(&msg);
+    if (e) return fail(e, "device error: " + msg);
+  }
+  std::vector<double> pv(q.pauli_offsets.size() - 1, 0.0);
+  if (!pv.empty()) eng.observe_pauli(pv.data());
+  std::string msg;
+  int e = be->check(&msg);
+  if (e) return fail(e, "device error: " + msg);
+  for (double x : z)
+    if (!std::isfinite(x)) return fail(-5, "non-finite observable (numerical breakdown)");
+  if (r->z) std::memcpy(r->z, z.data(), (size_t)rows * n * sizeof(double));
+  if (r->pauli && !pv.empty()) std::memcpy(r->pauli, pv.data(), pv.size() * sizeof(double));
+  if (r->bp_iters) std::memcpy(r->bp_iters, iters.data(), iters.size() * sizeof(int32_t));
+  if (r->bp_residual) std::memcpy(r->bp_residual, res.data(), res.size() * sizeof(double));
+  if (r->discarded) std::memcpy(r->discarded, disc.data(), disc.size() * sizeof(double));
+  return warn;
+}
+
+extern "C" int bpki_solve(bpki_ctx *c, const bpki_problem *p, bpki_result *r) {
+  if (!c || !r) return fail(-1, "NULL context or result");
+  int rc = bpki_validate(p);
+  if (rc) return rc;
+  if (p->precision != BPKI_FP64) return fail(-1, "precision mode not available in this build");
+  Problem q = to_problem(p);
+  size_t need = Engine::estimate_bytes(q);
+  if (c->budget && need > c->budget) return fail(-4, "problem exceeds the memory budget");
+  std::lock_guard<std::mutex> lk(c->mu);
+  std::string msg;
+  if (c->be->check(&msg)) return fail(-5, "device in error state: " + msg);
+  std::unique_ptr<Engine> eng(new Engine(c->be.get(), q));
+  if (int e = c->be->check(&msg)) return fail(e, "allocation: " + msg);
+  return run_solve(c->be.get(), *eng, q, r, nullptr);
+}
+
+// ------------------------------------------------------------------------------------------
+// sessions
+struct bpki_session {
+  bpki_ctx *ctx;
+  std::unique_ptr<Engine> eng;
+  std::vector<int> colours;
+  double timing[4] = {0, 0, 0, 0};
+};
+
+extern "C" int bpki_session_open(bpki_ctx *c, const bpki_problem *p, bpki_session **out) {
+  if (!c || !out) return fail(-1, "NULL argument");
+  int rc = bpki_validate(p);
+  if (rc) return rc;
+  if (p->precision != BPKI_FP64) return fail(-1, "precision mode not available in this build");
+  Problem q = to_problem(p);
+  size_t need = Engine::estimate_bytes(q);
+  if (c->budget && need > c->budget) return fail(-4, "problem exceeds the memory budget");
+  auto *s = new bpki_session;
+  s->ctx = c;
+  s->eng.reset(new Engine(c->be.get(), q));
+  std::string msg;
+  if (int e = c->be->check(&msg)) {
+    delete s;
+    return fail(e, "session allocation: " + msg);
+  }
+  s->colours.assign(q.colour.begin(), q.colour.end());
+  std::sort(s->colours.begin(), s->colours.end());
+  s->colours.erase(std::unique(s->colours.begin(), s->colours.end()), s->colours.end());
+  *out = s;
+  return 0;
+}
+
+extern "C" void bpki_session_close(bpki_session *s) { delete s; }
+
+static int sess_check(bpki_session *s) {
+  std::string msg;
+  int e = s->ctx->be->check(&msg);
+  return e ? fail(e, "device error: " + msg) : 0;
+}
+
+extern "C" int bpki_session_sizes(const bpki_session *s, size_t *te, size_t *me) {
+  if (!s) return fail(-1, "NULL session");
+  if (te) *te = s->eng->tensor_elems();
+  if (me) *me = s->eng->message_elems();
+  return 0;
+}
+
+extern "C" int bpki_session_get_state(bpki_session *s, double *t, double *m, int32_t *b) {
+  if (!s) return fail(-1, "NULL session");
+  s->eng->get_state(t, m, b);
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_set_state(bpki_session *s, const double *t, const double *m,
+                                      const int32_t *b) {
+  if (!s) return fail(-1, "NULL session");
+  s->eng->set_state(t, m, b);
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_apply_rx(bpki_session *s) {
+  if (!s) return fail(-1, "NULL session");
+  s->eng->apply_rx();
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_apply_layer(bpki_session *s, int32_t colour, double *disc) {
+  if (!s) return fail(-1, "NULL session");
+  double d = s->eng->apply_layer(colour);
+  if (disc) *disc = d;
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_bp(bpki_session *s, int32_t max_iter, int32_t *iters, double *res) {
+  if (!s || max_iter < 1) return fail(-1, "bad argument");
+  double r = 0;
+  int it = s->eng->bp(max_iter, &r);
+  if (iters) *iters = it;
+  if (res) *res = r;
+  int e = sess_check(s);
+  if (e) return e;
+  return r < s->eng->problem().bp_tol ? 0 : 1;
+}
+
+extern "C" int bpki_session_bp_sweep(bpki_session *s, double *res) {
+  if (!s) return fail(-1, "NULL session");
+  double r = s->eng->bp_sweep();
+  if (res) *res = r;
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_observe_z(bpki_session *s, double *z) {
+  if (!s || !z) return fail(-1, "NULL argument");
+  s->eng->observe_z(z);
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_observe_pauli(bpki_session *s, double *out) {
+  if (!s) return fail(-1, "NULL session");
+  if (s->eng->problem().pauli_offsets.size() <= 1) return 0;
+  if (!out) return fail(-1, "NULL output");
+  s->eng->observe_pauli(out);
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *res,
+                                 double *disc) {
+  if (!s) return fail(-1, "NULL session");
+  Backend *be = s->ctx->be.get();
+  be->timer_mark(0);
+  s->eng->apply_rx();
+  be->timer_mark(1);
+  double d = 0;
+  for (int c : s->colours) d += s->eng->apply_layer(c);
+  be->timer_mark(2);
+  double r = 0;
+  int it = s->eng->bp(s->eng->problem().bp_max_iter, &r);
+  be->timer_mark(3);
+  if (z) s->eng->observe_z(z);
+  be->timer_mark(4);
+  s->timing[0] = be->timer_ms(0, 1);
+  s->timing[1] = be->timer_ms(1, 2);
+  s->timing[2] = be->timer_ms(2, 3);
+  s->timing[3] = z ? be->timer_ms(3, 4) : 0.0;
+  if (iters) *iters = it;
+  if (res) *res = r;
+  if (disc) *disc = d;
+  int e = sess_check(s);
+  if (e) return e;
+  return r < s->eng->problem().bp_tol ? 0 : 1;
+}
+
+extern "C" int bpki_session_last_timing(const bpki_session *s, double *ms4) {
+  if (!s || !ms4) return fail(-1, "NULL argument");
+  for (int i = 0; i < 4; ++i) ms4[i] = s->timing[i];
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// serving (continuous batching): see serve.cpp
+struct bpki_ctx::Job {
+  uint64_t ticket = 0;
+  Problem q;
+  bpki_result *r = nullptr;
+  std::atomic<bool> cancel{false};
+  bool done = false;
+  int status = 0;
+  size_t bytes = 0;
+};
+
+static void serving_shutdown(bpki_ctx *c) {
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->stop = true;
+  }
+  c->cv.notify_all();
+  if (c->worker.joinable()) c->worker.join();
+}
+
+static void worker_loop(bpki_ctx *c);
+
+extern "C" int bpki_submit(bpki_ctx *c, const bpki_problem *p, bpki_result *r, uint64_t *ticket) {
+  if (!c || !r || !ticket) return fail(-1, "NULL argument");
+  int rc = bpki_validate(p);
+  if (rc) return rc;
+  if (p->precision != BPKI_FP64) return fail(-1, "precision mode not available in this build");
+  auto job = std::make_shared<bpki_ctx::Job>();
+  job->q = to_problem(p);
+  job->r = r;
+  job->bytes = Engine::estimate_bytes(job->q);
+  if (c->budget && job->bytes > c->budget) return fail(-4, "problem can never fit the budget");
+  std::lock_guard<std::mutex> lk(c->mu);
+  job->ticket = c->next_ticket++;
+  c->jobs[job->ticket] = job;
+  c->queue.push_back(job);
+  if (!c->worker.joinable()) c->worker = std::thread(worker_loop, c);
+  c->cv.notify_all();
+  *ticket = job->ticket;
+  return 0;
+}
+
+extern "C" int bpki_poll(bpki_ctx *c, uint64_t t, int *done) {
+  if (!c || !done) return fail(-1, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->jobs.find(t);
+  if (it == c->jobs.end()) return fail(-7, "unknown ticket");
+  *done = it->second->done ? 1 : 0;
+  return it->second->done ? it->second->status : 0;
+}
+
+extern "C" int bpki_wait(bpki_ctx *c, uint64_t t) {
+  if (!c) return fail(-1, "NULL context");
+  std::unique_lock<std::mutex> lk(c->mu);
+  auto it = c->jobs.find(t);
+  if (it == c->jobs.end()) return fail(-7, "unknown ticket");
+  auto job = it->second;
+  c->done_cv.wait(lk, [&] { return job->done; });
+  c->jobs.erase(t);
+  if (job->status < 0) g_err = "request failed";
+  return job->status;
+}
+
+extern "C" int bpki_cancel(bpki_ctx *c, uint64_t t) {
+  if (!c) return fail(-1, "NULL context");
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->jobs.find(t);
+  if (it == c->jobs.end()) return fail(-7, "unknown ticket");
+  it->second->cancel = true;
+  c->cv.notify_all();
+  return 0;
+}
+
+// Worker: admits queued jobs while they fit the budget and interleaves their Floquet steps.
+struct Resident {
+  std::shared_ptr<bpki_ctx::Job> job;
+  std::unique_ptr<Engine> eng;
+  std::vector<int> colours;
+  int t = 0;
+  std::vector<double> z;
+  std::vector<int32_t> iters;
+  std::vector<double> res, disc;
+  int warn = 0;
+};
+
+static void finish(bpki_ctx *c, Resident &R, int status) {
+  const Problem &q = R.job->q;
+  if (status >= 0) {
+    int rows = q.record_every_step ? q.depth : 1;
+    bpki_result *r = R.job->r;
+    if (r->z) std::memcpy(r->z, R.z.data(), (size_t)rows * q.n_sites * sizeof(double));
+    if (r->bp_iters) std::memcpy(r->bp_iters, R.iters.data(), R.iters.size() * sizeof(int32_t));
+    if (r->bp_residual) std::memcpy(r->bp_residual, R.res.data(), R.res.size() * sizeof(double));
+    if (r->discarded) std::memcpy(r->discarded, R.disc.data(), R.disc.size() * sizeof(double));
+    if (r->pauli && q.pauli_offsets.size() > 1) R.eng->observe_pauli(r->pauli);
+    status = R.warn;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  R.job->status = status;
+  R.job->done = true;
+  c->done_cv.notify_all();
+}
+
+static void worker_loop(bpki_ctx *c) {
+  std::vector<Resident> live;
+  size_t used = 0;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv.wait(lk, [&] { return c->stop || !c->queue.empty() || !live.empty(); });
+      if (c->stop && live.empty()) return;
+      // admission by memory footprint, in arrival order
+      while (!c->queue.empty()) {
+        auto job = c->queue.front();
+        if (job->cancel) {
+          c->queue.pop_front();
+          job->status = -6;
+          job->done = true;
+          c->done_cv.notify_all();
+          continue;
+        }
+        if (c->budget && used + job->bytes > c->budget && !live.empty()) break;
+        c->queue.pop_front();
+        lk.unlock();
+        Resident R;
+        R.job = job;
+        R.eng.reset(new Engine(c->be.get(), job->q));
+        R.colours.assign(job->q.colour.begin(), job->q.colour.end());
+        std::sort(R.colours.begin(), R.colours.end());
+        R.colours.erase(std::unique(R.colours.begin(), R.colours.end()), R.colours.end());
+        int rows = job->q.record_every_step ? job->q.depth : 1;
+        R.z.assign((size_t)std::max(rows, 1) * job->q.n_sites, 1.0);
+        R.iters.assign(job->q.depth, 0);
+        R.res.assign(job->q.depth, 0.0);
+        R.disc.assign(job->q.depth, 0.0);
+        used += job->bytes;
+        live.push_back(std::move(R));
+        lk.lock();
+      }
+    }
+    // one Floquet step of every resident request (round robin)
+    for (size_t i = 0; i < live.size();) {
+      Resident &R = live[i];
+      const Problem &q = R.job->q;
+      bool drop = false;
+      if (R.job->cancel) {
+        finish(c, R, -6);
+        drop = true;
+      } else if (R.t >= q.depth) {
+        finish(c, R, 0);
+        drop = true;
+      } else {
+        R.eng->apply_rx();
+        double d = 0;
+        for (int col : R.colours) d += R.eng->apply_layer(col);
+        double rr = 0;
+        R.iters[R.t] = R.eng->bp(q.bp_max_iter, &rr);
+        R.res[R.t] = rr;
+        R.disc[R.t] = d;
+        if (!(rr < q.bp_tol)) R.warn = 1;
+        if (q.record_every_step || R.t == q.depth - 1)
+          R.eng->observe_z(&R.z[(size_t)(q.record_every_step ? R.t : 0) * q.n_sites]);
+        R.t++;
+        std::string msg;
+        if (c->be->check(&msg)) {
+          finish(c, R, -5);
+          drop = true;
+        } else if (R.t >= q.depth) {
+          finish(c, R, 0);
+          drop = true;
+        }
+      }
+      if (drop) {
+        used -= R.job->bytes;
+        live.erase(live.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// test hooks (include/bpki_testing.h)
+extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int nprob,
+                              const double *A, size_t a_elems, const double *B, size_t b_elems,
+                              double *C, size_t c_elems) {
+  if (!c || !td || nprob < 1) return fail(-1, "bad argument");
+  Backend *be = c->be.get();
+  GemmDesc d;
+  d.M = td->M; d.N = td->N; d.K = td->K; d.Mi = td->Mi; d.Ni = td->Ni; d.Ki = td->Ki;
+  d.a_mo = td->a_mo; d.a_mi = td->a_mi; d.a_ko = td->a_ko; d.a_ki = td->a_ki;
+  d.b_ko = td->b_ko; d.b_ki = td->b_ki; d.b_no = td->b_no; d.b_ni = td->b_ni;
+  d.c_mo = td->c_mo; d.c_mi = td->c_mi; d.c_no = td->c_no; d.c_ni = td->c_ni;
+  d.a_b = td->a_b; d.b_b = td->b_b; d.c_b = td->c_b; d.batch = td->batch;
+  d.conjA = td->conjA; d.conjB = td->conjB; d.beta = td->beta;
+  d.alpha_re = td->alpha_re; d.alpha_im = td->alpha_im;
+  if (d.M < 1 || d.N < 1 || d.K < 1 || d.Mi < 1 || d.Ni < 1 || d.Ki < 1 || d.batch < 1 ||
+      d.M % d.Mi || d.N % d.Ni || d.K % d.Ki)
+    return fail(-1, "inconsistent descriptor");
+  // bounds: every addressed element must lie inside the buffers (host-side check)
+  auto span = [](long o, long so, long si, int X, int Xi) {
+    long a = (long)(X / Xi - 1) * so, b = (long)(Xi - 1) * si;
+    return std::max(0L, a) + std::max(0L, b) + o;
+  };
+  long amax = span(0, d.a_mo, d.a_mi, d.M, d.Mi) + span(0, d.a_ko, d.a_ki, d.K, d.Ki) +
+              (long)(d.batch - 1) * d.a_b;
+  long bmax = span(0, d.b_ko, d.b_ki, d.K, d.Ki) + span(0, d.b_no, d.b_ni, d.N, d.Ni) +
+              (long)(d.batch - 1) * d.b_b;
+  long cmax = span(0, d.c_mo, d.c_mi, d.M, d.Mi) + span(0, d.c_no, d.c_ni, d.N, d.Ni) +
+              (long)(d.batch - 1) * d.c_b;
+  if (d.a_mo < 0 || d.a_mi < 0 || d.a_ko < 0 || d.a_ki < 0 || d.b_ko < 0 || d.b_ki < 0 ||
+      d.b_no < 0 || d.b_ni < 0 || d.c_mo < 0 || d.c_mi < 0 || d.c_no < 0 || d.c_ni < 0 ||
+      d.a_b < 0 || d.b_b < 0 || d.c_b < 0)
+    return fail(-1, "negative stride");
+  if ((size_t)amax >= a_elems || (size_t)bmax >= b_elems || (size_t)cmax >= c_elems)
+    return fail(-1, "descriptor addresses outside the buffers");
+  std::lock_guard<std::mutex> lk(c->mu);
+  double *dA = (double *)be->alloc(a_elems * 16 * nprob);
+  double *dB = (double *)be->alloc(b_elems * 16 * nprob);
+  double *dC = (double *)be->alloc(c_elems * 16 * nprob);
+  void **ptrs = (void **)be->alloc(3 * nprob * sizeof(void *));
+  if (!dA || !dB || !dC || !ptrs) return fail(-4, "allocation failed");
+  be->h2d(dA, A, a_elems * 16 * nprob);
+  be->h2d(dB, B, b_elems * 16 * nprob);
+  be->h2d(dC, C, c_elems * 16 * nprob);
+  std::vector<void *> h(3 * nprob);
+  for (int p = 0; p < nprob; ++p) {
+    h[p] = dA + 2 * a_elems * p;
+    h[nprob + p] = dB + 2 * b_elems * p;
+    h[2 * nprob + p] = dC + 2 * c_elems * p;
+  }
+  be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
+  be->gemm(d, (const double *const *)ptrs, (const double *const *)(ptrs + nprob),
+           (double *const *)(ptrs + 2 * nprob), nprob);
+  be->d2h(C, dC, c_elems * 16 * nprob);
+  be->release(dA);
+  be->release(dB);
+  be->release(dC);
+  be->release(ptrs);
+  std::string msg;
+  int e = be->check(&msg);
+  return e ? fail(e, msg) : 0;
+}
+
+extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, double *evals,
+                              double *vecs) {
+  if (!c || n < 1 || n > 256 || nprob < 1) return fail(-1, "bad argument");
+  Backend *be = c->be.get();
+  std::lock_guard<std::mutex> lk(c->mu);
+  size_t nn = (size_t)n * n;
+  double *dA = (double *)be->alloc(nn * 16 * nprob);
+  double *dE = (double *)be->alloc((size_t)n * 8 * nprob);
+  double *dV = (double *)be->alloc(nn * 16 * nprob);
+  void **ptrs = (void **)be->alloc(3 * nprob * sizeof(void *));
+  if (!dA || !dE || !dV || !ptrs) return fail(-4, "allocation failed");
+  be->h2d(dA, A, nn * 16 * nprob);
+  std::vector<void *> h(3 * nprob);
+  for (int p = 0; p < nprob; ++p) {
+    h[p] = dA + 2 * nn * p;
+    h[nprob + p] = dE + (size_t)n * p;
+    h[2 * nprob + p] = dV + 2 * nn * p;
+  }
+  be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
+  be->eigh(n, n, (const double *const *)ptrs, (double *const *)(ptrs + nprob),
+           (double *const *)(ptrs + 2 * nprob), nprob);
+  be->d2h(evals, dE, (size_t)n * 8 * nprob);
+  be->d2h(vecs, dV, nn * 16 * nprob);
+  be->release(dA);
+  be->release(dE);
+  be->release(dV);
+  be->release(ptrs);
+  std::string msg;
+  int e = be->check(&msg);
+  return e ? fail(e, msg) : 0;
+}

@@ -1,0 +1,146 @@
+// Internal interfaces of the bpki library: device backend primitives and the engine.
+//
+// Data layout in device memory (complex numbers are (re, im) pairs, FP64 unless stated):
+//   site tensor T_v : [s][a_0]..[a_{d-1}]  s in {0,1}, every virtual leg padded to chi
+//                     (leg i points at the i-th neighbour in ascending id; zero beyond the bond)
+//   message u->v    : [a_ket][a_bra], chi x chi, two buffers (BP double buffering)
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bpki {
+
+// C[b][m][n] (=|+=) alpha * sum_k opA(A)[b][m][k] * opB(B)[b][k][n]
+// Every index may be composite, i = i_outer * Xi + i_inner, with independent strides for the
+// outer and inner part (strides count complex elements).  A list of problems with equal shapes
+// and strides is passed as device arrays of base pointers (one launch for all of them).
+struct GemmDesc {
+  int M = 0, N = 0, K = 0;
+  int Mi = 1, Ni = 1, Ki = 1;            // inner extents (M % Mi == 0 ...)
+  long a_mo = 0, a_mi = 0, a_ko = 0, a_ki = 0;
+  long b_ko = 0, b_ki = 0, b_no = 0, b_ni = 0;
+  long c_mo = 0, c_mi = 0, c_no = 0, c_ni = 0;
+  long a_b = 0, b_b = 0, c_b = 0;        // batch strides
+  int batch = 1;
+  int conjA = 0, conjB = 0;
+  int beta = 0;                          // 1: accumulate into C
+  double alpha_re = 1.0, alpha_im = 0.0;
+};
+
+// Simple composite-index helpers for descriptors.
+inline void set_simple_m(GemmDesc &d, int M, long sa, long sc) { d.M = M; d.Mi = M; d.a_mi = sa; d.c_mi = sc; }
+
+enum class Prec : int { F64 = 0, F32 = 1 };
+
+// Small device kernels used by the engine (implemented in hip_backend.hip).
+struct Backend {
+  virtual ~Backend() {}
+  virtual void *alloc(size_t bytes) = 0;          // zero-initialised
+  virtual void release(void *p) = 0;
+  virtual void h2d(void *dst, const void *src, size_t bytes) = 0;
+  virtual void d2h(void *dst, const void *src, size_t bytes) = 0;
+  virtual void d2d(void *dst, const void *src, size_t bytes) = 0;
+  virtual void zero(void *dst, size_t bytes) = 0;
+  virtual void sync() = 0;
+  virtual int check(std::string *msg) = 0;          // 0 or negative error code
+  // HIP events on the backend's stream: mark slot i; elapsed milliseconds between two marks.
+  virtual void timer_mark(int slot) = 0;
+  virtual double timer_ms(int a, int b) = 0;
+
+  // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
+  virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,
+                    double *const *C, int nprob) = 0;
+  // Batched Hermitian eigendecomposition (FP64, cyclic Jacobi).  in[p]: n x n (lda), read only.
+  // evals[p]: n reals, descending; vecs[p]: n x n, column i = eigenvector i (ld = n).
+  virtual void eigh(int n, int lda, const double *const *in, double *const *evals,
+                    double *const *vecs, int nprob) = 0;
+
+  // --- elementwise / small kernels -------------------------------------------------------
+  // T_v <- RX(theta) on the physical leg for all sites; tensors[p] holds 2*half[p] complex.
+  virtual void rx(double *const *tensors, const int64_t *half, int nprob, double c, double s) = 0;
+  // X = W f(l) W^H with f = sqrt(max(l,0)) and Xp with f = 1/sqrt(l) for l > cut*l_max else 0.
+  virtual void msg_sqrt(int n, const double *const *evals, const double *const *vecs,
+                        double *const *X, double *const *Xp, double cut, int nprob) = 0;
+  // From eigh(G) of the Gram matrix G = A^H A (n x n): R[i][c] = sqrt(l_i) conj(W[c][i]),
+  // Wsc[c][i] = W[c][i]/sqrt(l_i) for l_i > cut*l_0 (else 0), i < r.
+  virtual void gram_factor(int n, int r, const double *const *evals, const double *const *vecs,
+                           double *const *R, double *const *Wsc, double cut, int nprob) = 0;
+  // Theta[(rb,sb)][(rs,ss)] = g(sb,ss) sum_b RB[rb][sb][b] RS[rs][ss][b];  chi = bond extent
+  virtual void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
+                     double *const *Th, double g_same_re, double g_same_im, double g_diff_re,
+                     double g_diff_im, int nprob) = 0;
+  // Truncation from eigh(Theta^H Theta): k, S, discarded weight, new diagonal messages and the
+  // scaled right vectors Vs[c][a] = V[c][a]/sigma_a (a < k).
+  virtual void svd_finish(int n, int chi, const double *const *evals, const double *const *vecs,
+                          double *const *Vs, double *const *S, int *kout, double *disc,
+                          double *const *msg_a, double *const *msg_b, double cutoff,
+                          int nprob) = 0;
+  // RB'[(r,s)][a] = U[(r,s)][a] sqrt(S_a); RS'[(r,s)][a] = sqrt(S_a) conj(V[(r,s)][a]); a < chi
+  virtual void split_sqrt(int rowsB, int rowsS, int n, int chi, const double *const *U,
+                          const double *const *V, const double *const *S, double *const *RBn,
+                          double *const *RSn, int nprob) = 0;
+  // BP: M_new <- M_new / tr(M_new); res[p] = ||M_new - M_old||_F.
+  virtual void normalize_residual(int chi, double *const *Mnew, const double *const *Mold,
+                                  double *res, int nprob) = 0;
+  virtual void reduce_max(const double *x, int n, double *out) = 0;
+  // rho[p][s][s'] = sum_i Y[p][s][i] conj(T[p][s'][i]) over i < len[p]; out 4 complex per p.
+  virtual void rho_dot(const double *const *Y, const double *const *T, const int64_t *len,
+                       double *rho, int nprob) = 0;
+  // T'[s] = sum_s' O[s][s'] T[s'] for a 2 x half tensor (one 2x2 complex op per problem)
+  virtual void apply_op(const double *const *Tin, double *const *Tout, const int64_t *half,
+                        const double *ops, int nprob) = 0;
+};
+
+Backend *make_hip_backend(int device, void *stream, std::string *err);
+
+// ------------------------------------------------------------------------------------------
+struct Problem {
+  int n_sites = 0;
+  std::vector<int> edges;       // 2E
+  std::vector<int> colour;      // E
+  double theta = 0;
+  int depth = 0, chi = 1;
+  int precision = 0;
+  double bp_tol = 1e-12;
+  int bp_max_iter = 1000;
+  double svd_cutoff = 1e-12, eig_cutoff = 1e-12;
+  std::vector<int> pauli_offsets, pauli_sites;
+  std::vector<uint8_t> pauli_ops;
+  int record_every_step = 1;
+};
+
+// Host-side graph plan (degrees, neighbours, layers) and device workspace sizes.
+struct Plan;
+
+class Engine {
+ public:
+  Engine(Backend *be, const Problem &p);
+  ~Engine();
+  static size_t estimate_bytes(const Problem &p);
+
+  void reset();                                   // |0...0>, messages [[1]]
+  void apply_rx();
+  double apply_layer(int colour);                 // returns discarded weight of the layer
+  double bp_sweep();                              // returns residual
+  int bp(int max_iter, double *residual);         // returns sweeps
+  void observe_z(double *z);                      // host out [n_sites]
+  void observe_pauli(double *out);                // host out [n_pauli]
+  int n_colours() const;
+  const Problem &problem() const { return prob_; }
+
+  size_t tensor_elems() const;
+  size_t message_elems() const;
+  void get_state(double *tensors, double *messages, int32_t *bond_dims);
+  void set_state(const double *tensors, const double *messages, const int32_t *bond_dims);
+
+ private:
+  Backend *be_;
+  Problem prob_;
+  Plan *plan_;
+  void build();
+  double pauli_value(int k, bool with_ops);
+};
+
+}  // namespace bpki

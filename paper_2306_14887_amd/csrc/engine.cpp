@@ -1,0 +1,998 @@
+// Engine: the Floquet-step schedule of the BP-gauged simple update (arXiv 2306.14887, Methods)
+// expressed as batched device primitives.  All state lives in device memory; the host only
+// builds launch descriptors and reads back scalars (BP residual, observables).
+//
+// Gate update on edge (x, y), both endpoints (Methods, "The simple update procedure", reduced-
+// tensor variant):
+//   1. X = M^{1/2}, X+ = M^{+1/2} of every message entering x from its other neighbours (eigh).
+//   2. A_x = T_x with X absorbed on the environment legs, laid out [env][s][a_y].
+//   3. Isolate the bond: degree <= 2: R_x = A_x (rows = environment), Q_x = I.
+//      degree 3: A_x = Q_x R_x from the Gram matrix G = A^H A = W L W^H (eigh):
+//      R_x = L^{1/2} W^H, Q_x = A_x W L^{-1/2} formed explicitly (orthonormal columns).
+//   4. Theta = gate phases * (R_x contracted with R_y over the shared bond).
+//   5. Truncated SVD of Theta from eigh(Theta^H Theta): keep min(chi, #sigma > cutoff*sigma_1)
+//      values, normalise S; the edge's two messages become diag(S)/sum(S).
+//   6. R_x' = U sqrt(S), R_y' = sqrt(S) V^H; T~_x' = Q_x R_x'; T_x' = T~_x' with X+ absorbed.
+// BP sweep (Eq. "MessageTensorSelfConsistency"): every directed message from the site tensor, its
+// conjugate and the other incoming messages; unit complex trace; residual = max Frobenius change.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <functional>
+#include <stdexcept>
+#include <tuple>
+
+#include "bpki_internal.h"
+
+namespace bpki {
+
+namespace {
+
+struct GemmOp {
+  GemmDesc d;
+  size_t a = 0, b = 0, c = 0;      // offsets into the pointer arena
+  int n = 0;
+};
+
+// Device arrays of pointers, built on the host and uploaded once.
+struct PtrArena {
+  std::vector<const void *> host;
+  void **dev = nullptr;
+  size_t add(const std::vector<const void *> &v) {
+    size_t off = host.size();
+    host.insert(host.end(), v.begin(), v.end());
+    return off;
+  }
+  template <class T>
+  T at(size_t off) const { return reinterpret_cast<T>(dev + off); }
+};
+
+inline long ipow(long b, int e) { long r = 1; while (e-- > 0) r *= b; return r; }
+
+}  // namespace
+
+// Strides of a site tensor's indices: s first, then one per leg.
+struct Layout {
+  long s = 0;
+  long leg[3] = {0, 0, 0};
+};
+
+struct Endpoint {
+  int x = -1, y = -1;     // this site, partner
+  int j = -1;             // leg of x that points at y
+  int deg = 0;
+  int env[2] = {-1, -1};  // environment legs (ascending)
+  int r = 0;              // rows of R_x
+  bool big = false;       // rows side of Theta
+  int edge_slot = -1;
+};
+
+struct EdgeWork {
+  int e = -1;
+  int ep[2] = {-1, -1};   // endpoint slots: [0] = big side, [1] = small side
+};
+
+struct LayerPlan {
+  std::vector<Endpoint> eps;
+  std::vector<EdgeWork> edges;
+  // message eigh + sqrt
+  size_t m_in = 0, m_ev = 0, m_vec = 0, m_X = 0, m_Xp = 0;
+  int n_msg = 0;
+  std::vector<GemmOp> absorb;       // (grouped)
+  // deg-3 gram factor
+  GemmOp gram;
+  size_t g_in = 0, g_ev = 0, g_vec = 0, g_R = 0, g_Wsc = 0;
+  int n_g = 0;
+  GemmOp qform;
+  // per (rB, rS) edge type
+  struct Type {
+    int rB = 0, rS = 0, n = 0;
+    size_t RB = 0, RS = 0, Th = 0, ev = 0, vec = 0, Vs = 0, S = 0, mA = 0, mB = 0, RBn = 0, RSn = 0,
+           U = 0;
+    GemmOp hgemm, ugemm;
+    int count = 0;
+    int slot0 = 0;                  // first edge slot of this type (k / disc arrays)
+  };
+  std::vector<Type> types;
+  GemmOp rebuild;                   // deg-3 endpoints: Tt = Q R'
+  std::vector<GemmOp> remove;       // grouped
+  std::vector<std::pair<size_t, size_t>> copies_in, copies_out;  // deg-1 (dst, src, bytes) as ptr
+  std::vector<std::tuple<double *, const double *, size_t>> d2d_in, d2d_out;
+};
+
+struct Plan {
+  int n = 0, chi = 1, E = 0;
+  std::vector<int> deg;
+  std::vector<std::vector<int>> nb;
+  std::vector<long> toff;          // tensor offsets (complex elements)
+  std::vector<long> tsize;
+  std::vector<std::vector<int>> in_msg, out_msg;
+  std::vector<int> layer_colours;
+  std::vector<std::vector<int>> layer_edges;
+
+  double *T = nullptr;             // all site tensors
+  double *M = nullptr;             // current messages  [2E][chi][chi]
+  double *Mn = nullptr;            // BP output buffer
+  double *ws = nullptr;            // SU workspace (max over layers)
+  double *bpws = nullptr;          // BP / observable workspace
+  double *res = nullptr;           // per-message residual [2E]
+  double *resmax = nullptr;        // [1]
+  double *rho = nullptr;           // [n][4] complex
+  int *kbuf = nullptr;             // [max edges per layer]
+  double *disc = nullptr;          // [max edges per layer]
+  int *bond = nullptr;             // host copy of bond dims is kept in bond_h
+  std::vector<int> bond_h;
+  int64_t *rx_half = nullptr;
+  int64_t *rho_len = nullptr;
+  size_t rx_ptrs = 0;
+  size_t ws_elems = 0, bpws_elems = 0;
+  PtrArena arena;
+  std::vector<LayerPlan> layers;
+  // BP
+  std::vector<GemmOp> bp_ops;
+  size_t bp_norm_new = 0, bp_norm_old = 0;
+  // observables
+  std::vector<GemmOp> obs_ops;
+  size_t obs_Y = 0, obs_T = 0;
+  int max_layer_edges = 0;
+  std::vector<void *> allocs;
+};
+
+// ------------------------------------------------------------------------------------------
+// descriptor helpers
+
+static Layout t_layout(int deg, int chi) {
+  Layout L;
+  L.s = ipow(chi, deg);
+  for (int i = 0; i < deg; ++i) L.leg[i] = ipow(chi, deg - 1 - i);
+  return L;
+}
+
+// Layout of A_x = [env_0][env_1][s][a_j] (environment legs in ascending leg order).
+static Layout a_layout(const Endpoint &p, int chi) {
+  Layout L;
+  L.leg[p.j] = 1;
+  L.s = chi;
+  long st = 2L * chi;
+  for (int t = p.deg - 2; t >= 0; --t) {
+    L.leg[p.env[t]] = st;
+    st *= chi;
+  }
+  return L;
+}
+
+// Contract leg `L` of a tensor (degree deg, layout in) with a chi x chi matrix X[a][b]; the new
+// index b takes the place of the leg in layout out.  Batch over s, M over the other legs.
+static GemmDesc leg_desc(int deg, int leg, const Layout &in, const Layout &out, int chi) {
+  GemmDesc d;
+  int others[2] = {-1, -1};
+  int no = 0;
+  for (int i = 0; i < deg; ++i)
+    if (i != leg) others[no++] = i;
+  d.batch = 2;
+  d.a_b = in.s;
+  d.b_b = 0;
+  d.c_b = out.s;
+  if (no == 0) {
+    d.M = 1; d.Mi = 1;
+  } else if (no == 1) {
+    d.M = chi; d.Mi = chi;
+    d.a_mi = in.leg[others[0]]; d.c_mi = out.leg[others[0]];
+  } else {
+    d.M = chi * chi; d.Mi = chi;
+    d.a_mo = in.leg[others[0]]; d.a_mi = in.leg[others[1]];
+    d.c_mo = out.leg[others[0]]; d.c_mi = out.leg[others[1]];
+  }
+  d.K = chi; d.Ki = chi; d.a_ki = in.leg[leg];
+  d.b_ki = chi;
+  d.N = chi; d.Ni = chi; d.b_ni = 1; d.c_ni = out.leg[leg];
+  return d;
+}
+
+// out[a][a'] = sum over s and all legs but `leg` of Y[..a..] conj(T[..a'..]) (both in layout L).
+static GemmDesc close_desc(int deg, int leg, const Layout &L, int chi) {
+  GemmDesc d;
+  d.M = chi; d.Mi = chi; d.a_mi = L.leg[leg];
+  d.N = chi; d.Ni = chi; d.b_ni = L.leg[leg]; d.c_ni = 1;
+  d.c_mi = chi;
+  d.conjB = 1;
+  // K = (s, other legs).  T-order layouts have s outermost and the other legs in order, so the
+  // summed indices split into at most two uniformly strided runs.
+  int others[2] = {-1, -1};
+  int no = 0;
+  for (int i = 0; i < deg; ++i)
+    if (i != leg) others[no++] = i;
+  if (no == 0) {                    // K = s
+    d.K = 2; d.Ki = 2; d.a_ki = L.s; d.b_ki = L.s;
+  } else if (no == 1) {             // K = (s, o)
+    d.K = 2 * chi; d.Ki = chi;
+    d.a_ko = L.s; d.a_ki = L.leg[others[0]];
+    d.b_ko = L.s; d.b_ki = L.leg[others[0]];
+  } else {
+    // (s, o0, o1): s and the outer other leg fuse when the summed leg is not between them
+    if (leg == 0) {                 // (s) x (o0 o1 contiguous)
+      d.K = 2 * chi * chi; d.Ki = chi * chi;
+      d.a_ko = L.s; d.a_ki = L.leg[2];
+      d.b_ko = L.s; d.b_ki = L.leg[2];
+    } else if (leg == 1) {          // (s o0) x (o1)
+      d.K = 2 * chi * chi; d.Ki = chi;
+      d.a_ko = L.leg[0]; d.a_ki = L.leg[2];
+      d.b_ko = L.leg[0]; d.b_ki = L.leg[2];
+    } else {                        // (s o0 o1) uniform stride
+      d.K = 2 * chi * chi; d.Ki = 2 * chi * chi;
+      d.a_ki = L.leg[1];
+      d.b_ki = L.leg[1];
+    }
+  }
+  return d;
+}
+
+// ------------------------------------------------------------------------------------------
+
+Engine::Engine(Backend *be, const Problem &p) : be_(be), prob_(p), plan_(new Plan) { build(); }
+
+Engine::~Engine() {
+  for (void *a : plan_->allocs) be_->release(a);
+  if (plan_->arena.dev) be_->release(plan_->arena.dev);
+  delete plan_;
+}
+
+int Engine::n_colours() const { return (int)plan_->layer_colours.size(); }
+size_t Engine::tensor_elems() const {
+  size_t s = 0;
+  for (long t : plan_->tsize) s += (size_t)t;
+  return s;
+}
+size_t Engine::message_elems() const { return (size_t)2 * plan_->E * plan_->chi * plan_->chi; }
+
+size_t Engine::estimate_bytes(const Problem &p) {
+  // tensors + 2 message buffers + SU workspace bound + BP workspace bound
+  int n = p.n_sites;
+  std::vector<int> deg(n, 0);
+  for (size_t i = 0; i < p.edges.size(); ++i) deg[p.edges[i]]++;
+  long chi = p.chi;
+  size_t t = 0, bp = 0, su = 0;
+  for (int v = 0; v < n; ++v) {
+    long sz = 2 * ipow(chi, deg[v]);
+    t += sz;
+    bp += (deg[v] == 3 ? 5 : deg[v] == 2 ? 2 : 0) * sz;
+    su += (deg[v] == 3 ? 4 : 3) * sz + 16 * chi * chi;
+  }
+  size_t m = (size_t)2 * p.edges.size() / 2 * chi * chi;
+  size_t elems = t + 2 * m + su + bp + (size_t)p.edges.size() * 64 * chi * chi;
+  return elems * 16 + (8u << 20);
+}
+
+void Engine::build() {
+  Plan &P = *plan_;
+  const Problem &p = prob_;
+  P.n = p.n_sites;
+  P.chi = p.chi;
+  P.E = (int)p.edges.size() / 2;
+  const int chi = P.chi;
+  const long c2 = (long)chi * chi;
+  P.nb.assign(P.n, {});
+  for (int e = 0; e < P.E; ++e) {
+    P.nb[p.edges[2 * e]].push_back(p.edges[2 * e + 1]);
+    P.nb[p.edges[2 * e + 1]].push_back(p.edges[2 * e]);
+  }
+  P.deg.resize(P.n);
+  for (int v = 0; v < P.n; ++v) {
+    std::sort(P.nb[v].begin(), P.nb[v].end());
+    P.deg[v] = (int)P.nb[v].size();
+  }
+  // messages: 2e = edges[2e] -> edges[2e+1], 2e+1 reverse
+  std::map<std::pair<int, int>, int> midx;
+  for (int e = 0; e < P.E; ++e) {
+    midx[{p.edges[2 * e], p.edges[2 * e + 1]}] = 2 * e;
+    midx[{p.edges[2 * e + 1], p.edges[2 * e]}] = 2 * e + 1;
+  }
+  P.in_msg.assign(P.n, {});
+  P.out_msg.assign(P.n, {});
+  for (int v = 0; v < P.n; ++v)
+    for (int u : P.nb[v]) {
+      P.in_msg[v].push_back(midx[{u, v}]);
+      P.out_msg[v].push_back(midx[{v, u}]);
+    }
+  long off = 0;
+  P.toff.resize(P.n);
+  P.tsize.resize(P.n);
+  for (int v = 0; v < P.n; ++v) {
+    P.toff[v] = off;
+    P.tsize[v] = 2 * ipow(chi, P.deg[v]);
+    off += P.tsize[v];
+  }
+  // layers
+  std::vector<int> cols(p.colour.begin(), p.colour.end());
+  std::vector<int> uniq = cols;
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  P.layer_colours = uniq;
+  P.layer_edges.assign(uniq.size(), {});
+  for (int e = 0; e < P.E; ++e) {
+    int li = (int)(std::lower_bound(uniq.begin(), uniq.end(), cols[e]) - uniq.begin());
+    P.layer_edges[li].push_back(e);
+  }
+  for (auto &le : P.layer_edges) P.max_layer_edges = std::max(P.max_layer_edges, (int)le.size());
+
+  // ---- device allocations ----
+  auto A = [&](size_t bytes) {
+    void *q = be_->alloc(bytes ? bytes : 16);
+    P.allocs.push_back(q);
+    return q;
+  };
+  P.T = (double *)A((size_t)off * 16);
+  P.M = (double *)A(message_elems() * 16);
+  P.Mn = (double *)A(message_elems() * 16);
+  P.res = (double *)A((size_t)std::max(1, 2 * P.E) * 8);
+  P.resmax = (double *)A(8);
+  P.rho = (double *)A((size_t)P.n * 8 * 8);
+  P.kbuf = (int *)A((size_t)std::max(1, P.max_layer_edges) * 4);
+  P.disc = (double *)A((size_t)std::max(1, P.max_layer_edges) * 8);
+  P.bond_h.assign(P.E, 1);
+
+  auto Tp = [&](int v) { return (const void *)(P.T + 2 * P.toff[v]); };
+  auto Mp = [&](int m) { return (const void *)(P.M + 2 * (size_t)m * c2); };
+  auto Mnp = [&](int m) { return (const void *)(P.Mn + 2 * (size_t)m * c2); };
+
+  // ---- SU layer plans (workspace offsets computed first, pointers after allocation) ----
+  struct Slot { size_t off, elems; };
+  size_t ws_max = 0;
+  std::vector<std::vector<size_t>> dummy;
+  // First pass: compute per-layer workspace need.
+  auto ep_need = [&](int deg) -> size_t {
+    long env = ipow(chi, deg - 1);
+    size_t need = 0;
+    need += 2 * (2 * c2) + 2 * c2 + 2 * chi;       // X, Xp (2 legs), W, evals (per leg reuse)
+    need += 2 * c2 * 2;                            // more eigh room
+    need += (size_t)env * 2 * chi * 3;             // Y1/A, Q, Tt
+    need += 4 * c2 * 4 + 2 * chi;                  // G, W, R, Wsc
+    need += (size_t)(deg == 3 ? 2 * chi : env) * 2 * chi; // R'
+    return need;
+  };
+  (void)ep_need;
+
+  P.layers.resize(P.layer_edges.size());
+  std::vector<size_t> layer_ws(P.layers.size(), 0);
+  // Sizes of the per-layer arena are determined while building; we build with a bump allocator
+  // over a virtual base and allocate once with the maximum.
+  for (size_t li = 0; li < P.layers.size(); ++li) {
+    LayerPlan &LP = P.layers[li];
+    const auto &le = P.layer_edges[li];
+    for (size_t q = 0; q < le.size(); ++q) {
+      int e = le[q];
+      int u = p.edges[2 * e], v = p.edges[2 * e + 1];
+      Endpoint a, b;
+      a.x = u; a.y = v; b.x = v; b.y = u;
+      for (Endpoint *ep : {&a, &b}) {
+        ep->deg = P.deg[ep->x];
+        ep->j = (int)(std::find(P.nb[ep->x].begin(), P.nb[ep->x].end(), ep->y) -
+                      P.nb[ep->x].begin());
+        int t = 0;
+        for (int i = 0; i < ep->deg; ++i)
+          if (i != ep->j) ep->env[t++] = i;
+        ep->r = ep->deg == 3 ? 2 * chi : (int)ipow(chi, ep->deg - 1);
+        ep->edge_slot = (int)q;
+      }
+      // big side = more rows (ties: first endpoint)
+      Endpoint *B = &a, *S = &b;
+      if (b.r > a.r) std::swap(B, S);
+      B->big = true;
+      S->big = false;
+      EdgeWork w;
+      w.e = e;
+      w.ep[0] = (int)LP.eps.size();
+      LP.eps.push_back(*B);
+      w.ep[1] = (int)LP.eps.size();
+      LP.eps.push_back(*S);
+      LP.edges.push_back(w);
+    }
+  }
+
+  // workspace per layer: bump allocator (offsets in complex elements)
+  struct Bump {
+    size_t top = 0;
+    size_t take(size_t n) { size_t o = top; top += (n + 31) & ~size_t(31); return o; }
+  };
+  // we need to know the base pointer before building pointer arrays; compute sizes in a dry run
+  auto layer_build = [&](LayerPlan &LP, double *base, Bump &bump, bool real) {
+    auto W = [&](size_t off) { return (const void *)(base + 2 * off); };
+    auto Wr = [&](size_t off) { return (const void *)((double *)base + 2 * off); };
+    (void)Wr;
+    // 1. message eigh for env legs
+    std::vector<const void *> min, mev, mvec, mX, mXp;
+    std::vector<size_t> xoff(LP.eps.size() * 2, 0), xpoff(LP.eps.size() * 2, 0);
+    for (size_t q = 0; q < LP.eps.size(); ++q) {
+      const Endpoint &ep = LP.eps[q];
+      for (int t = 0; t < ep.deg - 1; ++t) {
+        int m = P.in_msg[ep.x][ep.env[t]];
+        size_t o_ev = bump.take(chi), o_vec = bump.take(c2), o_X = bump.take(c2),
+               o_Xp = bump.take(c2);
+        xoff[2 * q + t] = o_X;
+        xpoff[2 * q + t] = o_Xp;
+        min.push_back(Mp(m));
+        mev.push_back(W(o_ev));
+        mvec.push_back(W(o_vec));
+        mX.push_back(W(o_X));
+        mXp.push_back(W(o_Xp));
+      }
+    }
+    LP.n_msg = (int)min.size();
+    if (real) {
+      LP.m_in = P.arena.add(min); LP.m_ev = P.arena.add(mev); LP.m_vec = P.arena.add(mvec);
+      LP.m_X = P.arena.add(mX); LP.m_Xp = P.arena.add(mXp);
+    }
+    // 2. absorb into A-layout; allocate A, Q, Tt, Y1 per endpoint
+    std::vector<size_t> aoff(LP.eps.size()), qoff(LP.eps.size()), ttoff(LP.eps.size()),
+        y1off(LP.eps.size()), roff(LP.eps.size()), rnoff(LP.eps.size());
+    for (size_t q = 0; q < LP.eps.size(); ++q) {
+      const Endpoint &ep = LP.eps[q];
+      size_t sz = (size_t)P.tsize[ep.x];
+      aoff[q] = bump.take(sz);
+      ttoff[q] = bump.take(sz);
+      y1off[q] = ep.deg == 3 ? bump.take(sz) : 0;
+      qoff[q] = ep.deg == 3 ? bump.take((size_t)c2 * 2 * chi) : 0;
+      roff[q] = ep.deg == 3 ? bump.take((size_t)4 * c2) : aoff[q];   // R (r x 2chi)
+      rnoff[q] = bump.take((size_t)ep.r * 2 * chi);                  // R' (r x 2 x chi)
+    }
+    // group absorb ops by (deg, j): descriptor depends on the leg pattern
+    std::map<std::pair<int, int>, std::vector<size_t>> groups;
+    for (size_t q = 0; q < LP.eps.size(); ++q)
+      groups[{LP.eps[q].deg, LP.eps[q].j}].push_back(q);
+    LP.absorb.clear();
+    LP.remove.clear();
+    LP.d2d_in.clear();
+    LP.d2d_out.clear();
+    for (auto &g : groups) {
+      int deg = g.first.first;
+      const Endpoint &ep0 = LP.eps[g.second[0]];
+      Layout Lt = t_layout(deg, chi), La = a_layout(ep0, chi);
+      if (deg == 1) {
+        for (size_t q : g.second) {
+          const Endpoint &ep = LP.eps[q];
+          if (real) {
+            LP.d2d_in.emplace_back((double *)W(aoff[q]), (const double *)Tp(ep.x),
+                                   (size_t)P.tsize[ep.x] * 16);
+            LP.d2d_out.emplace_back((double *)Tp(ep.x), (const double *)W(rnoff[q]),
+                                    (size_t)P.tsize[ep.x] * 16);
+          }
+        }
+        continue;
+      }
+      if (deg == 2) {
+        GemmOp op, rm;
+        op.d = leg_desc(2, ep0.env[0], Lt, La, chi);
+        rm.d = leg_desc(2, ep0.env[0], La, Lt, chi);
+        std::vector<const void *> a, b, c, ra, rb, rc;
+        for (size_t q : g.second) {
+          const Endpoint &ep = LP.eps[q];
+          a.push_back(Tp(ep.x)); b.push_back(W(xoff[2 * q])); c.push_back(W(aoff[q]));
+          ra.push_back(W(rnoff[q])); rb.push_back(W(xpoff[2 * q])); rc.push_back(Tp(ep.x));
+        }
+        op.n = rm.n = (int)a.size();
+        if (real) {
+          op.a = P.arena.add(a); op.b = P.arena.add(b); op.c = P.arena.add(c);
+          rm.a = P.arena.add(ra); rm.b = P.arena.add(rb); rm.c = P.arena.add(rc);
+        }
+        LP.absorb.push_back(op);
+        LP.remove.push_back(rm);
+        continue;
+      }
+      // deg 3: T --(env0)--> Y1 (T-order) --(env1)--> A (A-layout); remove mirrors it.
+      GemmOp s1, s2, r1, r2;
+      s1.d = leg_desc(3, ep0.env[0], Lt, Lt, chi);
+      s2.d = leg_desc(3, ep0.env[1], Lt, La, chi);
+      r1.d = leg_desc(3, ep0.env[0], La, Lt, chi);
+      r2.d = leg_desc(3, ep0.env[1], Lt, Lt, chi);
+      std::vector<const void *> a1, b1, c1, a2, b2, c2v, ra1, rb1, rc1, ra2, rb2, rc2;
+      for (size_t q : g.second) {
+        const Endpoint &ep = LP.eps[q];
+        a1.push_back(Tp(ep.x)); b1.push_back(W(xoff[2 * q])); c1.push_back(W(y1off[q]));
+        a2.push_back(W(y1off[q])); b2.push_back(W(xoff[2 * q + 1])); c2v.push_back(W(aoff[q]));
+        ra1.push_back(W(ttoff[q])); rb1.push_back(W(xpoff[2 * q])); rc1.push_back(W(y1off[q]));
+        ra2.push_back(W(y1off[q])); rb2.push_back(W(xpoff[2 * q + 1])); rc2.push_back(Tp(ep.x));
+      }
+      s1.n = s2.n = r1.n = r2.n = (int)a1.size();
+      if (real) {
+        s1.a = P.arena.add(a1); s1.b = P.arena.add(b1); s1.c = P.arena.add(c1);
+        s2.a = P.arena.add(a2); s2.b = P.arena.add(b2); s2.c = P.arena.add(c2v);
+        r1.a = P.arena.add(ra1); r1.b = P.arena.add(rb1); r1.c = P.arena.add(rc1);
+        r2.a = P.arena.add(ra2); r2.b = P.arena.add(rb2); r2.c = P.arena.add(rc2);
+      }
+      LP.absorb.push_back(s1);
+      LP.absorb.push_back(s2);
+      LP.remove.push_back(r1);
+      LP.remove.push_back(r2);
+    }
+    // 3. Gram factor for degree-3 endpoints
+    {
+      std::vector<const void *> ga, gc, gev, gvec, gR, gW, qa, qb, qc, ra, rb, rc;
+      for (size_t q = 0; q < LP.eps.size(); ++q) {
+        const Endpoint &ep = LP.eps[q];
+        if (ep.deg != 3) continue;
+        size_t o_G = bump.take(4 * c2), o_ev = bump.take(2 * chi), o_vec = bump.take(4 * c2),
+               o_W = bump.take(4 * c2);
+        ga.push_back(W(aoff[q])); gc.push_back(W(o_G));
+        gev.push_back(W(o_ev)); gvec.push_back(W(o_vec));
+        gR.push_back(W(roff[q])); gW.push_back(W(o_W));
+        qa.push_back(W(aoff[q])); qb.push_back(W(o_W)); qc.push_back(W(qoff[q]));
+        ra.push_back(W(qoff[q])); rb.push_back(W(rnoff[q])); rc.push_back(W(ttoff[q]));
+      }
+      LP.n_g = (int)ga.size();
+      GemmDesc g;                       // G = A^H A, A: [env][2chi]
+      g.M = 2 * chi; g.Mi = 2 * chi; g.a_mi = 1; g.conjA = 1;
+      g.K = (int)c2; g.Ki = (int)c2; g.a_ki = 2 * chi; g.b_ki = 2 * chi;
+      g.N = 2 * chi; g.Ni = 2 * chi; g.b_ni = 1;
+      g.c_mi = 2 * chi; g.c_ni = 1;
+      LP.gram.d = g;
+      GemmDesc qd;                      // Q = A Wsc : [env][2chi] x [2chi][2chi]
+      qd.M = (int)c2; qd.Mi = (int)c2; qd.a_mi = 2 * chi; qd.c_mi = 2 * chi;
+      qd.K = 2 * chi; qd.Ki = 2 * chi; qd.a_ki = 1; qd.b_ki = 2 * chi;
+      qd.N = 2 * chi; qd.Ni = 2 * chi; qd.b_ni = 1; qd.c_ni = 1;
+      LP.qform.d = qd;
+      GemmDesc rd = qd;                 // Tt = Q R' : [env][2chi] x [2chi][2chi]
+      LP.rebuild.d = rd;
+      LP.gram.n = LP.qform.n = LP.rebuild.n = LP.n_g;
+      if (real) {
+        LP.gram.a = P.arena.add(ga); LP.gram.b = LP.gram.a; LP.gram.c = P.arena.add(gc);
+        LP.g_in = LP.gram.c; LP.g_ev = P.arena.add(gev); LP.g_vec = P.arena.add(gvec);
+        LP.g_R = P.arena.add(gR); LP.g_Wsc = P.arena.add(gW);
+        LP.qform.a = P.arena.add(qa); LP.qform.b = P.arena.add(qb); LP.qform.c = P.arena.add(qc);
+        LP.rebuild.a = P.arena.add(ra); LP.rebuild.b = P.arena.add(rb);
+        LP.rebuild.c = P.arena.add(rc);
+      }
+    }
+    // 4-6. per edge type
+    std::map<std::pair<int, int>, std::vector<size_t>> types;
+    for (size_t q = 0; q < LP.edges.size(); ++q) {
+      const EdgeWork &w = LP.edges[q];
+      types[{LP.eps[w.ep[0]].r, LP.eps[w.ep[1]].r}].push_back(q);
+    }
+    LP.types.clear();
+    for (auto &t : types) {
+      LayerPlan::Type T;
+      T.rB = t.first.first;
+      T.rS = t.first.second;
+      T.n = 2 * T.rS;
+      T.count = (int)t.second.size();
+      std::vector<const void *> RB, RS, Th, H, ev, vec, Vs, S, mA, mB, RBn, RSn, U;
+      std::vector<int> slots;
+      for (size_t q : t.second) {
+        const EdgeWork &w = LP.edges[q];
+        const Endpoint &eb = LP.eps[w.ep[0]], &es = LP.eps[w.ep[1]];
+        size_t o_Th = bump.take((size_t)2 * T.rB * T.n), o_H = bump.take((size_t)T.n * T.n),
+               o_ev = bump.take(T.n), o_vec = bump.take((size_t)T.n * T.n),
+               o_Vs = bump.take((size_t)T.n * chi), o_S = bump.take(chi),
+               o_U = bump.take((size_t)2 * T.rB * chi);
+        (void)o_H;
+        RB.push_back(W(eb.deg == 3 ? roff[w.ep[0]] : aoff[w.ep[0]]));
+        RS.push_back(W(es.deg == 3 ? roff[w.ep[1]] : aoff[w.ep[1]]));
+        Th.push_back(W(o_Th));
+        H.push_back(W(o_H));
+        ev.push_back(W(o_ev)); vec.push_back(W(o_vec));
+        Vs.push_back(W(o_Vs)); S.push_back(W(o_S)); U.push_back(W(o_U));
+        mA.push_back(Mp(2 * w.e)); mB.push_back(Mp(2 * w.e + 1));
+        RBn.push_back(W(rnoff[w.ep[0]])); RSn.push_back(W(rnoff[w.ep[1]]));
+        slots.push_back((int)q);
+        T.hgemm.n = T.ugemm.n = T.count;
+        // H buffer pointer list built below (stash in Th list order)
+        (void)o_H;
+      }
+      GemmDesc hd;
+      hd.M = T.n; hd.Mi = T.n; hd.a_mi = 1; hd.conjA = 1;
+      hd.K = 2 * T.rB; hd.Ki = 2 * T.rB; hd.a_ki = T.n; hd.b_ki = T.n;
+      hd.N = T.n; hd.Ni = T.n; hd.b_ni = 1; hd.c_mi = T.n; hd.c_ni = 1;
+      T.hgemm.d = hd;
+      GemmDesc ud;                      // U = Theta Vs : [2rB][n] x [n][chi]
+      ud.M = 2 * T.rB; ud.Mi = 2 * T.rB; ud.a_mi = T.n; ud.c_mi = chi;
+      ud.K = T.n; ud.Ki = T.n; ud.a_ki = 1; ud.b_ki = chi;
+      ud.N = chi; ud.Ni = chi; ud.b_ni = 1; ud.c_ni = 1;
+      T.ugemm.d = ud;
+      // edges of a type are contiguous in `slots` order; k/disc indexed by edge slot, so we
+      // require slots to be a contiguous range -> reorder edges by type beforehand (see below)
+      T.slot0 = slots.empty() ? 0 : slots[0];
+      for (size_t i = 1; i < slots.size(); ++i)
+        if (slots[i] != slots[0] + (int)i) throw std::logic_error("edge slots not contiguous");
+      if (real) {
+        T.RB = P.arena.add(RB); T.RS = P.arena.add(RS); T.Th = P.arena.add(Th);
+        T.ev = P.arena.add(ev); T.vec = P.arena.add(vec); T.Vs = P.arena.add(Vs);
+        T.S = P.arena.add(S); T.mA = P.arena.add(mA); T.mB = P.arena.add(mB);
+        T.RBn = P.arena.add(RBn); T.RSn = P.arena.add(RSn); T.U = P.arena.add(U);
+        size_t hoff = P.arena.add(H);
+        T.hgemm.a = T.Th; T.hgemm.b = T.Th; T.hgemm.c = hoff;
+        T.ugemm.a = T.Th; T.ugemm.b = T.Vs; T.ugemm.c = T.U;
+      }
+      LP.types.push_back(T);
+    }
+  };
+
+  // order each layer's edges by type so that type groups are contiguous edge slots
+  for (auto &LP : P.layers) {
+    std::stable_sort(LP.edges.begin(), LP.edges.end(), [&](const EdgeWork &a, const EdgeWork &b) {
+      auto ka = std::make_pair(LP.eps[a.ep[0]].r, LP.eps[a.ep[1]].r);
+      auto kb = std::make_pair(LP.eps[b.ep[0]].r, LP.eps[b.ep[1]].r);
+      return ka < kb;
+    });
+    for (size_t q = 0; q < LP.edges.size(); ++q) {
+      LP.eps[LP.edges[q].ep[0]].edge_slot = (int)q;
+      LP.eps[LP.edges[q].ep[1]].edge_slot = (int)q;
+    }
+  }
+  for (auto &LP : P.layers) {
+    Bump b;
+    layer_build(LP, nullptr, b, false);
+    ws_max = std::max(ws_max, b.top);
+  }
+  P.ws_elems = ws_max;
+  P.ws = (double *)A(ws_max * 16);
+  for (auto &LP : P.layers) {
+    Bump b;
+    layer_build(LP, P.ws, b, true);
+  }
+
+  // ---- BP plan ----
+  {
+    size_t top = 0;
+    auto take = [&](size_t n) { size_t o = top; top += (n + 31) & ~size_t(31); return o; };
+    struct SiteWs { size_t y[5]; };
+    std::vector<SiteWs> sws(P.n);
+    for (int v = 0; v < P.n; ++v) {
+      int nbuf = P.deg[v] == 3 ? 5 : P.deg[v] == 2 ? 2 : 0;
+      for (int i = 0; i < nbuf; ++i) sws[v].y[i] = take((size_t)P.tsize[v]);
+    }
+    // observables need 3 buffers per site (reuse BP slots: deg3 has 5, deg2 has 2, deg1 needs 1)
+    std::vector<size_t> obs1(P.n);
+    for (int v = 0; v < P.n; ++v)
+      if (P.deg[v] == 1) obs1[v] = take((size_t)P.tsize[v]);
+    P.bpws_elems = top;
+    P.bpws = (double *)A(top * 16);
+    auto B = [&](size_t o) { return (const void *)(P.bpws + 2 * o); };
+
+    auto add_op = [&](std::vector<GemmOp> &ops, const GemmDesc &d,
+                      const std::vector<const void *> &a, const std::vector<const void *> &b,
+                      const std::vector<const void *> &c) {
+      if (a.empty()) return;
+      GemmOp op;
+      op.d = d;
+      op.n = (int)a.size();
+      op.a = P.arena.add(a); op.b = P.arena.add(b); op.c = P.arena.add(c);
+      ops.push_back(op);
+    };
+    // degree 3 sites: Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
+    //                 Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
+    Layout L3 = t_layout(3, chi), L2 = t_layout(2, chi), L1 = t_layout(1, chi);
+    {
+      std::vector<const void *> a[10], b[10], c[10];
+      for (int v = 0; v < P.n; ++v) {
+        if (P.deg[v] != 3) continue;
+        const auto &y = sws[v].y;
+        auto push = [&](int k, const void *aa, const void *bb, const void *cc) {
+          a[k].push_back(aa); b[k].push_back(bb); c[k].push_back(cc);
+        };
+        push(0, Tp(v), Mp(P.in_msg[v][2]), B(y[0]));        // Y2
+        push(1, B(y[0]), Mp(P.in_msg[v][1]), B(y[1]));      // Y21
+        push(2, B(y[0]), Mp(P.in_msg[v][0]), B(y[2]));      // Y20
+        push(3, Tp(v), Mp(P.in_msg[v][1]), B(y[3]));        // Y1
+        push(4, B(y[3]), Mp(P.in_msg[v][0]), B(y[4]));      // Y10
+        push(5, B(y[1]), Tp(v), Mnp(P.out_msg[v][0]));
+        push(6, B(y[2]), Tp(v), Mnp(P.out_msg[v][1]));
+        push(7, B(y[4]), Tp(v), Mnp(P.out_msg[v][2]));
+      }
+      add_op(P.bp_ops, leg_desc(3, 2, L3, L3, chi), a[0], b[0], c[0]);
+      add_op(P.bp_ops, leg_desc(3, 1, L3, L3, chi), a[1], b[1], c[1]);
+      add_op(P.bp_ops, leg_desc(3, 0, L3, L3, chi), a[2], b[2], c[2]);
+      add_op(P.bp_ops, leg_desc(3, 1, L3, L3, chi), a[3], b[3], c[3]);
+      add_op(P.bp_ops, leg_desc(3, 0, L3, L3, chi), a[4], b[4], c[4]);
+      add_op(P.bp_ops, close_desc(3, 0, L3, chi), a[5], b[5], c[5]);
+      add_op(P.bp_ops, close_desc(3, 1, L3, chi), a[6], b[6], c[6]);
+      add_op(P.bp_ops, close_desc(3, 2, L3, chi), a[7], b[7], c[7]);
+    }
+    {
+      std::vector<const void *> a[4], b[4], c[4];
+      for (int v = 0; v < P.n; ++v) {
+        if (P.deg[v] != 2) continue;
+        const auto &y = sws[v].y;
+        a[0].push_back(Tp(v)); b[0].push_back(Mp(P.in_msg[v][1])); c[0].push_back(B(y[0]));
+        a[1].push_back(Tp(v)); b[1].push_back(Mp(P.in_msg[v][0])); c[1].push_back(B(y[1]));
+        a[2].push_back(B(y[0])); b[2].push_back(Tp(v)); c[2].push_back(Mnp(P.out_msg[v][0]));
+        a[3].push_back(B(y[1])); b[3].push_back(Tp(v)); c[3].push_back(Mnp(P.out_msg[v][1]));
+      }
+      add_op(P.bp_ops, leg_desc(2, 1, L2, L2, chi), a[0], b[0], c[0]);
+      add_op(P.bp_ops, leg_desc(2, 0, L2, L2, chi), a[1], b[1], c[1]);
+      add_op(P.bp_ops, close_desc(2, 0, L2, chi), a[2], b[2], c[2]);
+      add_op(P.bp_ops, close_desc(2, 1, L2, chi), a[3], b[3], c[3]);
+    }
+    {
+      std::vector<const void *> a, b, c;
+      for (int v = 0; v < P.n; ++v) {
+        if (P.deg[v] != 1) continue;
+        a.push_back(Tp(v)); b.push_back(Tp(v)); c.push_back(Mnp(P.out_msg[v][0]));
+      }
+      add_op(P.bp_ops, close_desc(1, 0, L1, chi), a, b, c);
+    }
+    {
+      std::vector<const void *> nn, no;
+      for (int m = 0; m < 2 * P.E; ++m) { nn.push_back(Mnp(m)); no.push_back(Mp(m)); }
+      P.bp_norm_new = P.arena.add(nn);
+      P.bp_norm_old = P.arena.add(no);
+    }
+    // observables: Y = T x0 M0 x1 M1 x2 M2 (T-order), rho = sum Y conj(T)
+    {
+      std::vector<const void *> a[3][3], b[3][3], c[3][3];   // [deg-1][step]
+      std::vector<const void *> ry, rt;
+      std::vector<int64_t> lens;
+      for (int v = 0; v < P.n; ++v) {
+        int d = P.deg[v];
+        const void *cur = Tp(v);
+        for (int l = 0; l < d; ++l) {
+          const void *dst = d == 1 ? B(obs1[v]) : B(sws[v].y[l]);
+          a[d - 1][l].push_back(cur); b[d - 1][l].push_back(Mp(P.in_msg[v][l]));
+          c[d - 1][l].push_back(dst);
+          cur = dst;
+        }
+        ry.push_back(cur);
+        rt.push_back(Tp(v));
+        lens.push_back(P.tsize[v] / 2);
+      }
+      for (int d = 1; d <= 3; ++d) {
+        Layout L = t_layout(d, chi);
+        for (int l = 0; l < d; ++l) add_op(P.obs_ops, leg_desc(d, l, L, L, chi), a[d - 1][l],
+                                           b[d - 1][l], c[d - 1][l]);
+      }
+      P.obs_Y = P.arena.add(ry);
+      P.obs_T = P.arena.add(rt);
+      P.rho_len = (int64_t *)A(lens.size() * 8);
+      be_->h2d(P.rho_len, lens.data(), lens.size() * 8);
+    }
+    // RX
+    {
+      std::vector<const void *> t;
+      std::vector<int64_t> half;
+      for (int v = 0; v < P.n; ++v) { t.push_back(Tp(v)); half.push_back(P.tsize[v] / 2); }
+      P.rx_ptrs = P.arena.add(t);
+      P.rx_half = (int64_t *)A(half.size() * 8);
+      be_->h2d(P.rx_half, half.data(), half.size() * 8);
+    }
+  }
+  // upload pointer arena
+  P.arena.dev = (void **)be_->alloc(std::max<size_t>(1, P.arena.host.size()) * sizeof(void *));
+  be_->h2d(P.arena.dev, P.arena.host.data(), P.arena.host.size() * sizeof(void *));
+  reset();
+}
+
+void Engine::reset() {
+  Plan &P = *plan_;
+  const long c2 = (long)P.chi * P.chi;
+  std::vector<double> t(2 * tensor_elems(), 0.0);
+  for (int v = 0; v < P.n; ++v) t[2 * P.toff[v]] = 1.0;
+  be_->h2d(P.T, t.data(), t.size() * 8);
+  std::vector<double> m(2 * message_elems(), 0.0);
+  for (int k = 0; k < 2 * P.E; ++k) m[2 * (size_t)k * c2] = 1.0;
+  be_->h2d(P.M, m.data(), m.size() * 8);
+  std::fill(P.bond_h.begin(), P.bond_h.end(), 1);
+}
+
+static void run(Backend *be, const PtrArena &ar, const GemmOp &op) {
+  if (op.n == 0) return;
+  be->gemm(op.d, ar.at<const double *const *>(op.a), ar.at<const double *const *>(op.b),
+           ar.at<double *const *>(op.c), op.n);
+}
+
+void Engine::apply_rx() {
+  Plan &P = *plan_;
+  double c = std::cos(prob_.theta / 2), s = std::sin(prob_.theta / 2);
+  be_->rx(P.arena.at<double *const *>(P.rx_ptrs), P.rx_half, P.n, c, s);
+}
+
+double Engine::apply_layer(int colour) {
+  Plan &P = *plan_;
+  auto it = std::find(P.layer_colours.begin(), P.layer_colours.end(), colour);
+  if (it == P.layer_colours.end()) return 0.0;
+  LayerPlan &LP = P.layers[it - P.layer_colours.begin()];
+  const PtrArena &ar = P.arena;
+  const int chi = P.chi;
+  // 1. X, X+ of the environment messages
+  if (LP.n_msg) {
+    be_->eigh(chi, chi, ar.at<const double *const *>(LP.m_in), ar.at<double *const *>(LP.m_ev),
+              ar.at<double *const *>(LP.m_vec), LP.n_msg);
+    be_->msg_sqrt(chi, ar.at<const double *const *>(LP.m_ev),
+                  ar.at<const double *const *>(LP.m_vec), ar.at<double *const *>(LP.m_X),
+                  ar.at<double *const *>(LP.m_Xp), prob_.eig_cutoff, LP.n_msg);
+  }
+  // 2. absorb
+  for (auto &t : LP.d2d_in) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
+  for (auto &op : LP.absorb) run(be_, ar, op);
+  // 3. isolate degree-3 endpoints
+  if (LP.n_g) {
+    run(be_, ar, LP.gram);
+    be_->eigh(2 * chi, 2 * chi, ar.at<const double *const *>(LP.g_in),
+              ar.at<double *const *>(LP.g_ev), ar.at<double *const *>(LP.g_vec), LP.n_g);
+    be_->gram_factor(2 * chi, 2 * chi, ar.at<const double *const *>(LP.g_ev),
+                     ar.at<const double *const *>(LP.g_vec), ar.at<double *const *>(LP.g_R),
+                     ar.at<double *const *>(LP.g_Wsc), 1e-15, LP.n_g);
+    run(be_, ar, LP.qform);
+  }
+  // 4-6. Theta, truncated SVD, new factors
+  const double q = M_PI / 4;
+  for (auto &T : LP.types) {
+    be_->theta(T.rB, T.rS, chi, ar.at<const double *const *>(T.RB),
+               ar.at<const double *const *>(T.RS), ar.at<double *const *>(T.Th), std::cos(q),
+               std::sin(q), std::cos(q), -std::sin(q), T.count);
+    run(be_, ar, T.hgemm);
+    be_->eigh(T.n, T.n, ar.at<const double *const *>(T.hgemm.c), ar.at<double *const *>(T.ev),
+              ar.at<double *const *>(T.vec), T.count);
+    be_->svd_finish(T.n, chi, ar.at<const double *const *>(T.ev),
+                    ar.at<const double *const *>(T.vec), ar.at<double *const *>(T.Vs),
+                    ar.at<double *const *>(T.S), P.kbuf + T.slot0, P.disc + T.slot0,
+                    ar.at<double *const *>(T.mA), ar.at<double *const *>(T.mB), prob_.svd_cutoff,
+                    T.count);
+    run(be_, ar, T.ugemm);
+    be_->split_sqrt(2 * T.rB, 2 * T.rS, T.n, chi, ar.at<const double *const *>(T.U),
+                    ar.at<const double *const *>(T.vec), ar.at<const double *const *>(T.S),
+                    ar.at<double *const *>(T.RBn), ar.at<double *const *>(T.RSn), T.count);
+  }
+  // 7. rebuild and remove the environment
+  if (LP.n_g) run(be_, ar, LP.rebuild);
+  // degree <= 2: T~' = R' (already in A-layout); point remove ops at R' directly
+  for (auto &op : LP.remove) run(be_, ar, op);
+  for (auto &t : LP.d2d_out) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
+  // bookkeeping: discarded weight and bond dimensions
+  int ne = (int)LP.edges.size();
+  std::vector<double> disc(ne);
+  std::vector<int> k(ne);
+  be_->d2h(disc.data(), P.disc, ne * 8);
+  be_->d2h(k.data(), P.kbuf, ne * 4);
+  double dsum = 0;
+  for (int i = 0; i < ne; ++i) {
+    dsum += disc[i];
+    P.bond_h[LP.edges[i].e] = k[i];
+  }
+  return dsum;
+}
+
+double Engine::bp_sweep() {
+  Plan &P = *plan_;
+  for (auto &op : P.bp_ops) run(be_, P.arena, op);
+  be_->normalize_residual(P.chi, P.arena.at<double *const *>(P.bp_norm_new),
+                          P.arena.at<const double *const *>(P.bp_norm_old), P.res, 2 * P.E);
+  be_->reduce_max(P.res, 2 * P.E, P.resmax);
+  be_->d2d(P.M, P.Mn, message_elems() * 16);
+  double r = 0;
+  be_->d2h(&r, P.resmax, 8);
+  return r;
+}
+
+int Engine::bp(int max_iter, double *residual) {
+  int it = 0;
+  double r = INFINITY;
+  while (it < max_iter) {
+    r = bp_sweep();
+    ++it;
+    if (r < prob_.bp_tol) break;
+  }
+  if (residual) *residual = r;
+  return it;
+}
+
+void Engine::observe_z(double *z) {
+  Plan &P = *plan_;
+  for (auto &op : P.obs_ops) run(be_, P.arena, op);
+  be_->rho_dot(P.arena.at<const double *const *>(P.obs_Y),
+               P.arena.at<const double *const *>(P.obs_T), P.rho_len, P.rho, P.n);
+  std::vector<double> rho((size_t)P.n * 8);
+  be_->d2h(rho.data(), P.rho, rho.size() * 8);
+  for (int v = 0; v < P.n; ++v) {
+    const double *r = &rho[(size_t)v * 8];   // rho00, rho01, rho10, rho11 (complex)
+    double nr = r[0] - r[6], ni = r[1] - r[7];
+    double dr = r[0] + r[6], di = r[1] + r[7];
+    double den = dr * dr + di * di;
+    z[v] = (nr * dr + ni * di) / den;
+  }
+}
+
+void Engine::observe_pauli(double *out) {
+  int np = (int)prob_.pauli_offsets.size() - 1;
+  for (int k = 0; k < np; ++k) {
+    double a = pauli_value(k, true);
+    double b = pauli_value(k, false);
+    out[k] = a / b;
+  }
+}
+
+// Exact contraction of a tree cluster with BP messages on the cut legs; Re(value).
+double Engine::pauli_value(int k, bool with_ops) {
+  Plan &P = *plan_;
+  const int chi = P.chi;
+  const long c2 = (long)chi * chi;
+  int b0 = prob_.pauli_offsets[k], b1 = prob_.pauli_offsets[k + 1];
+  std::vector<int> sites(prob_.pauli_sites.begin() + b0, prob_.pauli_sites.begin() + b1);
+  std::map<int, int> op;
+  for (int i = b0; i < b1; ++i) op[prob_.pauli_sites[i]] = prob_.pauli_ops[i];
+  // scratch in the BP workspace region is not used concurrently: allocate per call
+  std::vector<void *> tmp;
+  auto alloc = [&](size_t elems) {
+    void *q = be_->alloc(elems * 16);
+    tmp.push_back(q);
+    return (double *)q;
+  };
+  // pointer arrays for single-problem launches
+  void **parr = (void **)be_->alloc(3 * sizeof(void *));
+  tmp.push_back(parr);
+  auto gemm1 = [&](const GemmDesc &d, const double *a, const double *b, double *c) {
+    const void *h[3] = {a, b, c};
+    be_->h2d(parr, h, sizeof(h));
+    be_->gemm(d, (const double *const *)parr, (const double *const *)(parr + 1),
+              (double *const *)(parr + 2), 1);
+  };
+  static const double PM[4][8] = {
+      {1, 0, 0, 0, 0, 0, 1, 0},
+      {0, 0, 1, 0, 1, 0, 0, 0},
+      {0, 0, 0, -1, 0, 1, 0, 0},
+      {1, 0, 0, 0, 0, 0, -1, 0}};
+  double *opbuf = alloc(4);
+  int64_t *hbuf = (int64_t *)be_->alloc(8);
+  tmp.push_back(hbuf);
+  double *rho = alloc(4);
+  std::function<double *(int, int)> env;
+  double result = 0;
+  env = [&](int v, int parent) -> double * {
+    int d = P.deg[v];
+    Layout L = t_layout(d, chi);
+    const double *Tv = P.T + 2 * P.toff[v];
+    double *cur = alloc((size_t)P.tsize[v]);
+    int o = with_ops ? op[v] : 0;
+    be_->h2d(opbuf, PM[o], sizeof(PM[o]));
+    int64_t half = P.tsize[v] / 2;
+    be_->h2d(hbuf, &half, 8);
+    const void *pp[2] = {Tv, cur};
+    be_->h2d(parr, pp, sizeof(pp));
+    be_->apply_op((const double *const *)parr, (double *const *)(parr + 1), hbuf, opbuf, 1);
+    int pleg = -1;
+    for (int i = 0; i < d; ++i) {
+      int u = P.nb[v][i];
+      if (u == parent) { pleg = i; continue; }
+      const double *E;
+      if (op.count(u)) E = env(u, v);
+      else E = P.M + 2 * (size_t)P.in_msg[v][i] * c2;
+      double *nxt = alloc((size_t)P.tsize[v]);
+      gemm1(leg_desc(d, i, L, L, chi), cur, E, nxt);
+      cur = nxt;
+    }
+    if (parent >= 0) {
+      double *out = alloc(c2);
+      gemm1(close_desc(d, pleg, L, chi), cur, Tv, out);
+      return out;
+    }
+    const void *rp[2] = {cur, Tv};
+    be_->h2d(parr, rp, sizeof(rp));
+    be_->h2d(hbuf, &half, 8);
+    be_->rho_dot((const double *const *)parr, (const double *const *)(parr + 1), hbuf, rho, 1);
+    double r[8];
+    be_->d2h(r, rho, sizeof(r));
+    result = r[0] + r[6];       // Re(rho00 + rho11); imaginary part ~ 0 for Hermitian ops
+    return nullptr;
+  };
+  env(sites[0], -1);
+  be_->sync();
+  for (void *q : tmp) be_->release(q);
+  return result;
+}
+
+void Engine::get_state(double *tensors, double *messages, int32_t *bond_dims) {
+  Plan &P = *plan_;
+  if (tensors) be_->d2h(tensors, P.T, tensor_elems() * 16);
+  if (messages) be_->d2h(messages, P.M, message_elems() * 16);
+  if (bond_dims)
+    for (int e = 0; e < P.E; ++e) bond_dims[e] = P.bond_h[e];
+}
+
+void Engine::set_state(const double *tensors, const double *messages, const int32_t *bond_dims) {
+  Plan &P = *plan_;
+  if (tensors) be_->h2d(P.T, tensors, tensor_elems() * 16);
+  if (messages) be_->h2d(P.M, messages, message_elems() * 16);
+  if (bond_dims)
+    for (int e = 0; e < P.E; ++e) P.bond_h[e] = bond_dims[e];
+}
+
+}  // namespace bpki

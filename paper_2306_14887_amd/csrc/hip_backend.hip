@@ -1,0 +1,748 @@
+// HIP/CDNA4 (gfx950) kernels and the device backend of the bpki engine.
+//
+//  * gemm_c64   : grouped, batched complex FP64 GEMM on MFMA (v_mfma_f64_16x16x4f64).  Complex
+//                 products in real-split form: four real MFMA accumulators per 16x16 tile
+//                 (re*re, im*im, re*im, im*re), combined in the epilogue.  Operands are staged
+//                 through LDS in split re/im planes; the global loads follow whichever index is
+//                 unit-stride so they coalesce for every leg ordering of the site tensors.
+//  * eigh_jacobi: batched Hermitian eigendecomposition, FP64 cyclic Jacobi with the parallel
+//                 round-robin ordering (n/2 disjoint rotations per round, all 2x2 block updates
+//                 of a round in parallel).  Matrix and eigenvectors live in LDS up to n = 64,
+//                 otherwise in a global (L2-resident) work area.
+//  * small kernels for the X rotations, message square roots, Gram factor, the gate block,
+//    truncation, BP normalisation/residual and the site density matrices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "bpki_internal.h"
+
+namespace bpki {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess && err_ == 0) {                                             \
+      err_ = -5;                                                                     \
+      errmsg_ = std::string(#x) + ": " + hipGetErrorString(e_);                      \
+    }                                                                                \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------
+// GEMM
+namespace {
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+}
+
+__device__ __forceinline__ long cidx(int i, int inner, long so, long si) {
+  return (long)(i / inner) * so + (long)(i % inner) * si;
+}
+
+__global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double *const *Ap,
+                                                       const double *const *Bp,
+                                                       double *const *Cp) {
+  __shared__ double As[2][BK][BM + PAD];
+  __shared__ double Bs[2][BK][BN + PAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  const int bat = blockIdx.y, prob = blockIdx.z;
+  const double2 *A = reinterpret_cast<const double2 *>(Ap[prob]) + (long)bat * d.a_b;
+  const double2 *B = reinterpret_cast<const double2 *>(Bp[prob]) + (long)bat * d.b_b;
+  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const bool a_mfast = (d.a_mi == 1);
+  const bool b_nfast = (d.b_ni == 1);
+  const double sa = d.conjA ? -1.0 : 1.0, sb = d.conjB ? -1.0 : 1.0;
+
+  double4_t acc[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[i][j][t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < d.K; k0 += BK) {
+    // ---- stage A tile (BM x BK) ----
+#pragma unroll
+    for (int it = 0; it < (BM * BK) / 256; ++it) {
+      int e = tid + it * 256;
+      int m, k;
+      if (a_mfast) { m = e % BM; k = e / BM; } else { k = e % BK; m = e / BK; }
+      int mg = m0 + m, kg = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (mg < d.M && kg < d.K)
+        v = A[cidx(mg, d.Mi, d.a_mo, d.a_mi) + cidx(kg, d.Ki, d.a_ko, d.a_ki)];
+      As[0][k][m] = v.x;
+      As[1][k][m] = sa * v.y;
+    }
+    // ---- stage B tile (BK x BN) ----
+#pragma unroll
+    for (int it = 0; it < (BN * BK) / 256; ++it) {
+      int e = tid + it * 256;
+      int n, k;
+      if (b_nfast) { n = e % BN; k = e / BN; } else { k = e % BK; n = e / BK; }
+      int ng = n0 + n, kg = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (ng < d.N && kg < d.K)
+        v = B[cidx(kg, d.Ki, d.b_ko, d.b_ki) + cidx(ng, d.Ni, d.b_no, d.b_ni)];
+      Bs[0][k][n] = v.x;
+      Bs[1][k][n] = sb * v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ar[t] = As[0][kr][wm + t * 16 + (lane & 15)];
+        ai[t] = As[1][kr][wm + t * 16 + (lane & 15)];
+        br[t] = Bs[0][kr][wn + t * 16 + (lane & 15)];
+        bi[t] = Bs[1][kr][wn + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], acc[i][j][1], 0, 0, 0);
+          acc[i][j][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc[i][j][2], 0, 0, 0);
+          acc[i][j][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc[i][j][3], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  // ---- epilogue: D layout of 16x16x4 f64: lane l, reg r -> row 4*(l/16)+r, col l%16 ----
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int mg = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        int ng = n0 + wn + j * 16 + (lane & 15);
+        if (mg >= d.M || ng >= d.N) continue;
+        double cr = acc[i][j][0][r] - acc[i][j][1][r];
+        double ci = acc[i][j][2][r] + acc[i][j][3][r];
+        double vr = d.alpha_re * cr - d.alpha_im * ci;
+        double vi = d.alpha_re * ci + d.alpha_im * cr;
+        long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
+        if (d.beta) {
+          double2 o = C[off];
+          vr += o.x;
+          vi += o.y;
+        }
+        C[off] = make_double2(vr, vi);
+      }
+}
+
+// ------------------------------------------------------------------------------------------
+// Hermitian Jacobi eigensolver
+struct Rot {
+  double c, s;
+  double wr, wi;   // omega = e^{-i phi}
+  int p, q;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// Round-robin pairing (circle method) for np even, m = np-1 odd.
+__device__ __forceinline__ void pair_of(int r, int i, int np, int &p, int &q) {
+  int m = np - 1;
+  if (i == 0) { p = r % m; q = m; }
+  else { p = (r + i) % m; q = (r - i + m) % m; }
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
+                                                           const double *const *in,
+                                                           double *const *evals,
+                                                           double *const *vecs, double2 *gws,
+                                                           int max_sweeps) {
+  extern __shared__ double2 smem[];
+  __shared__ Rot rot[128];
+  __shared__ int any_rot;
+  __shared__ double diag_s[256];
+  const int prob = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int np = n + (n & 1);
+  const int h = np / 2;
+  double2 *A, *V;
+  if (LDS) { A = smem; V = smem + (size_t)np * np; }
+  else { A = gws + (size_t)prob * 2 * np * np; V = A + (size_t)np * np; }
+  const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+  for (int idx = tid; idx < np * np; idx += nt) {
+    int i = idx / np, j = idx % np;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n) {
+      double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
+      v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));   // Hermitian part
+    }
+    A[idx] = v;
+    V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < h) {
+        int p, q;
+        pair_of(r, tid, np, p, q);
+        double a = A[(size_t)p * np + p].x, dd = A[(size_t)q * np + q].x;
+        double2 b = A[(size_t)p * np + q];
+        double beta = sqrt(b.x * b.x + b.y * b.y);
+        Rot R;
+        R.p = p; R.q = q;
+        if (beta > 1e-300 && beta > eps * sqrt(fabs(a) * fabs(dd))) {
+          double tau = (dd - a) / (2.0 * beta);
+          double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          double c = 1.0 / sqrt(1.0 + t * t);
+          R.c = c; R.s = t * c;
+          R.wr = b.x / beta; R.wi = -b.y / beta;
+          any_rot = 1;
+        } else {
+          R.c = 1.0; R.s = 0.0; R.wr = 1.0; R.wi = 0.0;
+        }
+        rot[tid] = R;
+      }
+      __syncthreads();
+      for (int blk = tid; blk < h * h; blk += nt) {
+        int I = blk / h, J = blk % h;
+        Rot ri = rot[I], rj = rot[J];
+        double2 w_j = make_double2(rj.wr, rj.wi), w_i_c = make_double2(ri.wr, -ri.wi);
+        size_t o00 = (size_t)ri.p * np + rj.p, o01 = (size_t)ri.p * np + rj.q;
+        size_t o10 = (size_t)ri.q * np + rj.p, o11 = (size_t)ri.q * np + rj.q;
+        double2 b00 = A[o00], b01 = A[o01], b10 = A[o10], b11 = A[o11];
+        // T = B J_J
+        double2 sw = cscale(rj.s, w_j), cw = cscale(rj.c, w_j);
+        double2 t00 = cadd(cscale(rj.c, b00), cscale(-1.0, cmul(sw, b01)));
+        double2 t10 = cadd(cscale(rj.c, b10), cscale(-1.0, cmul(sw, b11)));
+        double2 t01 = cadd(cscale(rj.s, b00), cmul(cw, b01));
+        double2 t11 = cadd(cscale(rj.s, b10), cmul(cw, b11));
+        // B' = J_I^H T
+        double2 swc = cscale(ri.s, w_i_c), cwc = cscale(ri.c, w_i_c);
+        double2 n00 = cadd(cscale(ri.c, t00), cscale(-1.0, cmul(swc, t10)));
+        double2 n01 = cadd(cscale(ri.c, t01), cscale(-1.0, cmul(swc, t11)));
+        double2 n10 = cadd(cscale(ri.s, t00), cmul(cwc, t10));
+        double2 n11 = cadd(cscale(ri.s, t01), cmul(cwc, t11));
+        if (I == J) {
+          n00.y = 0.0; n11.y = 0.0;
+          if (ri.s != 0.0) { n01 = make_double2(0.0, 0.0); n10 = n01; }
+        }
+        A[o00] = n00; A[o01] = n01; A[o10] = n10; A[o11] = n11;
+      }
+      for (int it = tid; it < np * h; it += nt) {
+        int row = it / h, J = it % h;
+        Rot rj = rot[J];
+        if (rj.s == 0.0) continue;
+        double2 w_j = make_double2(rj.wr, rj.wi);
+        size_t op = (size_t)row * np + rj.p, oq = (size_t)row * np + rj.q;
+        double2 vp = V[op], vq = V[oq];
+        double2 sw = cscale(rj.s, w_j), cw = cscale(rj.c, w_j);
+        V[op] = cadd(cscale(rj.c, vp), cscale(-1.0, cmul(sw, vq)));
+        V[oq] = cadd(cscale(rj.s, vp), cmul(cw, vq));
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    int stop = (any_rot == 0);
+    __syncthreads();
+    if (stop) break;
+  }
+  // sort descending (rank sort over the n real indices) and write out
+  for (int i = tid; i < n; i += nt) diag_s[i] = A[(size_t)i * np + i].x;
+  __syncthreads();
+  double *ev = evals[prob];
+  double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
+  for (int i = tid; i < n; i += nt) {
+    double li = diag_s[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double lj = diag_s[j];
+      rank += (lj > li) || (lj == li && j < i);
+    }
+    ev[rank] = li;
+    for (int row = 0; row < n; ++row) vo[(size_t)row * n + rank] = V[(size_t)row * np + i];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// small kernels
+
+__global__ void rx_kernel(double *const *T, const int64_t *half, double c, double s) {
+  double2 *t = reinterpret_cast<double2 *>(T[blockIdx.y]);
+  int64_t h = half[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < h;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = t[i], b = t[h + i];
+    // [c, -is; -is, c]
+    t[i] = make_double2(c * a.x + s * b.y, c * a.y - s * b.x);
+    t[h + i] = make_double2(s * a.y + c * b.x, -s * a.x + c * b.y);
+  }
+}
+
+__global__ void msg_sqrt_kernel(int n, const double *const *evals, const double *const *vecs,
+                                double *const *X, double *const *Xp, double cut) {
+  const double *l = evals[blockIdx.x];
+  const double2 *W = reinterpret_cast<const double2 *>(vecs[blockIdx.x]);
+  double2 *x = reinterpret_cast<double2 *>(X[blockIdx.x]);
+  double2 *xp = reinterpret_cast<double2 *>(Xp[blockIdx.x]);
+  double lmax = l[0] > 0 ? l[0] : 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    int i = idx / n, j = idx % n;
+    double sr = 0, si = 0, pr = 0, pi = 0;
+    for (int k = 0; k < n; ++k) {
+      double lk = l[k];
+      double f = lk > 0 ? sqrt(lk) : 0.0;
+      double g = (lk > cut * lmax && lk > 0) ? 1.0 / sqrt(lk) : 0.0;
+      double2 a = W[(size_t)i * n + k], b = W[(size_t)j * n + k];
+      // a * conj(b)
+      double re = a.x * b.x + a.y * b.y, im = a.y * b.x - a.x * b.y;
+      sr += f * re; si += f * im;
+      pr += g * re; pi += g * im;
+    }
+    x[idx] = make_double2(sr, si);
+    xp[idx] = make_double2(pr, pi);
+  }
+}
+
+__global__ void gram_factor_kernel(int n, int r, const double *const *evals,
+                                   const double *const *vecs, double *const *R,
+                                   double *const *Wsc, double cut) {
+  const double *l = evals[blockIdx.x];
+  const double2 *W = reinterpret_cast<const double2 *>(vecs[blockIdx.x]);
+  double2 *Ro = reinterpret_cast<double2 *>(R[blockIdx.x]);
+  double2 *Wo = reinterpret_cast<double2 *>(Wsc[blockIdx.x]);
+  double l0 = l[0] > 0 ? l[0] : 0.0;
+  for (int idx = threadIdx.x; idx < r * n; idx += blockDim.x) {
+    int i = idx / n, c = idx % n;    // R[i][c]
+    double li = l[i];
+    bool keep = li > cut * l0 && li > 0;
+    double sq = keep ? sqrt(li) : 0.0;
+    double2 w = W[(size_t)c * n + i];
+    Ro[idx] = make_double2(sq * w.x, -sq * w.y);
+    double is = keep ? 1.0 / sq : 0.0;
+    Wo[(size_t)c * r + i] = make_double2(is * w.x, is * w.y);
+  }
+}
+
+__global__ void theta_kernel(int rB, int rS, int chi, const double *const *RB,
+                             const double *const *RS, double *const *Th, double gsr, double gsi,
+                             double gdr, double gdi) {
+  const double2 *a = reinterpret_cast<const double2 *>(RB[blockIdx.y]);
+  const double2 *b = reinterpret_cast<const double2 *>(RS[blockIdx.y]);
+  double2 *t = reinterpret_cast<double2 *>(Th[blockIdx.y]);
+  int rows = 2 * rB, cols = 2 * rS;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < rows * cols;
+       idx += gridDim.x * blockDim.x) {
+    int row = idx / cols, col = idx % cols;
+    int rb = row >> 1, sbv = row & 1, rs = col >> 1, ss = col & 1;
+    const double2 *pa = a + ((size_t)rb * 2 + sbv) * chi;
+    const double2 *pb = b + ((size_t)rs * 2 + ss) * chi;
+    double re = 0, im = 0;
+    for (int k = 0; k < chi; ++k) {
+      double2 x = pa[k], y = pb[k];
+      re += x.x * y.x - x.y * y.y;
+      im += x.x * y.y + x.y * y.x;
+    }
+    double gr = (sbv == ss) ? gsr : gdr, gi = (sbv == ss) ? gsi : gdi;
+    t[idx] = make_double2(gr * re - gi * im, gr * im + gi * re);
+  }
+}
+
+__global__ void svd_finish_kernel(int n, int chi, const double *const *evals,
+                                  const double *const *vecs, double *const *Vs, double *const *S,
+                                  int *kout, double *disc, double *const *mA, double *const *mB,
+                                  double cutoff) {
+  __shared__ double sig[512];
+  __shared__ int ks;
+  __shared__ double nrm, ssum;
+  const int p = blockIdx.x;
+  const double *l = evals[p];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sig[i] = sqrt(fmax(l[i], 0.0));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = sig[0];
+    int k = 0;
+    for (int i = 0; i < n && k < chi; ++i)
+      if (sig[i] > cutoff * s0) ++k;
+    double tot = 0, kept = 0, sum = 0;
+    for (int i = 0; i < n; ++i) tot += sig[i] * sig[i];
+    for (int i = 0; i < k; ++i) kept += sig[i] * sig[i];
+    double nr = sqrt(kept);
+    for (int i = 0; i < k; ++i) sum += sig[i] / nr;
+    ks = k;
+    nrm = nr;
+    ssum = sum;
+    kout[p] = k;
+    disc[p] = tot > 0 ? (tot - kept) / tot : 0.0;
+  }
+  __syncthreads();
+  const int k = ks;
+  double *Sp = S[p];
+  for (int a = threadIdx.x; a < chi; a += blockDim.x) Sp[a] = a < k ? sig[a] / nrm : 0.0;
+  const double2 *V = reinterpret_cast<const double2 *>(vecs[p]);
+  double2 *vs = reinterpret_cast<double2 *>(Vs[p]);
+  for (int idx = threadIdx.x; idx < n * chi; idx += blockDim.x) {
+    int c = idx / chi, a = idx % chi;
+    double2 v = make_double2(0.0, 0.0);
+    if (a < k) { double2 w = V[(size_t)c * n + a]; v = make_double2(w.x / sig[a], w.y / sig[a]); }
+    vs[idx] = v;
+  }
+  double2 *ma = reinterpret_cast<double2 *>(mA[p]);
+  double2 *mb = reinterpret_cast<double2 *>(mB[p]);
+  for (int idx = threadIdx.x; idx < chi * chi; idx += blockDim.x) {
+    int i = idx / chi, j = idx % chi;
+    double v = (i == j && i < k) ? (sig[i] / nrm) / ssum : 0.0;
+    ma[idx] = make_double2(v, 0.0);
+    mb[idx] = make_double2(v, 0.0);
+  }
+}
+
+__global__ void split_sqrt_kernel(int rowsB, int rowsS, int n, int chi, const double *const *U,
+                                  const double *const *V, const double *const *S,
+                                  double *const *RBn, double *const *RSn) {
+  const int p = blockIdx.y;
+  const double *s = S[p];
+  const double2 *u = reinterpret_cast<const double2 *>(U[p]);
+  const double2 *v = reinterpret_cast<const double2 *>(V[p]);
+  double2 *rb = reinterpret_cast<double2 *>(RBn[p]);
+  double2 *rs = reinterpret_cast<double2 *>(RSn[p]);
+  int totB = rowsB * chi, totS = rowsS * chi;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < totB + totS;
+       idx += gridDim.x * blockDim.x) {
+    if (idx < totB) {
+      int a = idx % chi;
+      double q = sqrt(s[a]);
+      double2 x = u[idx];
+      rb[idx] = make_double2(q * x.x, q * x.y);
+    } else {
+      int j = idx - totB;
+      int row = j / chi, a = j % chi;
+      double2 o = make_double2(0.0, 0.0);
+      if (a < n) {
+        double q = sqrt(s[a]);
+        double2 x = v[(size_t)row * n + a];
+        o = make_double2(q * x.x, -q * x.y);
+      }
+      rs[j] = o;
+    }
+  }
+}
+
+template <int NT>
+__device__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) r += sh[i];
+  __syncthreads();
+  return r;   // valid on thread 0
+}
+
+__global__ __launch_bounds__(256) void normalize_residual_kernel(int chi, double *const *Mn,
+                                                                 const double *const *Mo,
+                                                                 double *res) {
+  __shared__ double sh[8];
+  __shared__ double trr, tri;
+  const int p = blockIdx.x;
+  double2 *m = reinterpret_cast<double2 *>(Mn[p]);
+  const double2 *o = reinterpret_cast<const double2 *>(Mo[p]);
+  double tr = 0, ti = 0;
+  for (int i = threadIdx.x; i < chi; i += blockDim.x) {
+    double2 v = m[(size_t)i * chi + i];
+    tr += v.x;
+    ti += v.y;
+  }
+  double a = block_sum<256>(tr, sh);
+  double b = block_sum<256>(ti, sh);
+  if (threadIdx.x == 0) { trr = a; tri = b; }
+  __syncthreads();
+  double den = trr * trr + tri * tri;
+  double ir = trr / den, ii = -tri / den;   // 1/tr
+  double acc = 0;
+  for (int idx = threadIdx.x; idx < chi * chi; idx += blockDim.x) {
+    double2 v = m[idx];
+    double2 w = make_double2(v.x * ir - v.y * ii, v.x * ii + v.y * ir);
+    m[idx] = w;
+    double2 q = o[idx];
+    double dx = w.x - q.x, dy = w.y - q.y;
+    acc += dx * dx + dy * dy;
+  }
+  double s = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) res[p] = (trr > 0 && isfinite(s)) ? sqrt(s) : INFINITY;
+}
+
+__global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n, double *out) {
+  __shared__ double sh[256];
+  double m = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = x[i];
+    m = (v > m || v != v) ? v : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double a = sh[threadIdx.x], b = sh[threadIdx.x + s];
+      sh[threadIdx.x] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void rho_dot_kernel(const double *const *Y,
+                                                      const double *const *T, const int64_t *len,
+                                                      double *rho) {
+  __shared__ double sh[8];
+  const int p = blockIdx.x;
+  const double2 *y = reinterpret_cast<const double2 *>(Y[p]);
+  const double2 *t = reinterpret_cast<const double2 *>(T[p]);
+  int64_t L = len[p];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
+    double2 y0 = y[i], y1 = y[L + i], t0 = t[i], t1 = t[L + i];
+    // y_s * conj(t_s')
+    acc[0] += y0.x * t0.x + y0.y * t0.y; acc[1] += y0.y * t0.x - y0.x * t0.y;
+    acc[2] += y0.x * t1.x + y0.y * t1.y; acc[3] += y0.y * t1.x - y0.x * t1.y;
+    acc[4] += y1.x * t0.x + y1.y * t0.y; acc[5] += y1.y * t0.x - y1.x * t0.y;
+    acc[6] += y1.x * t1.x + y1.y * t1.y; acc[7] += y1.y * t1.x - y1.x * t1.y;
+  }
+  for (int k = 0; k < 8; ++k) {
+    double s = block_sum<256>(acc[k], sh);
+    if (threadIdx.x == 0) rho[(size_t)p * 8 + k] = s;
+  }
+}
+
+__global__ void apply_op_kernel(const double *const *Tin, double *const *Tout,
+                                const int64_t *half, const double *ops) {
+  const int p = blockIdx.y;
+  const double2 *t = reinterpret_cast<const double2 *>(Tin[p]);
+  double2 *o = reinterpret_cast<double2 *>(Tout[p]);
+  int64_t h = half[p];
+  const double2 *O = reinterpret_cast<const double2 *>(ops) + 4 * p;
+  double2 o00 = O[0], o01 = O[1], o10 = O[2], o11 = O[3];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < h;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = t[i], b = t[h + i];
+    o[i] = cadd(cmul(o00, a), cmul(o01, b));
+    o[h + i] = cadd(cmul(o10, a), cmul(o11, b));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+
+class HipBackend : public Backend {
+ public:
+  HipBackend(int device, void *stream) : dev_(device) {
+    HIPCHK(hipSetDevice(device));
+    if (stream) {
+      s_ = (hipStream_t)stream;
+      own_ = false;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+      own_ = true;
+    }
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel<true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
+  }
+  ~HipBackend() override {
+    for (auto &e : ev_)
+      if (e) hipEventDestroy(e);
+    if (gws_) hipFree(gws_);
+    if (own_) hipStreamDestroy(s_);
+  }
+  void *alloc(size_t bytes) override {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      if (err_ == 0) { err_ = -4; errmsg_ = "hipMalloc failed (out of device memory)"; }
+      return nullptr;
+    }
+    HIPCHK(hipMemsetAsync(p, 0, bytes, s_));
+    return p;
+  }
+  void release(void *p) override {
+    if (p) {
+      hipStreamSynchronize(s_);
+      hipFree(p);
+    }
+  }
+  void h2d(void *d, const void *h, size_t b) override {
+    if (b) HIPCHK(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s_));
+    HIPCHK(hipStreamSynchronize(s_));
+  }
+  void d2h(void *h, const void *d, size_t b) override {
+    if (b) HIPCHK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s_));
+    HIPCHK(hipStreamSynchronize(s_));
+  }
+  void d2d(void *d, const void *s, size_t b) override {
+    if (b) HIPCHK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, s_));
+  }
+  void zero(void *d, size_t b) override { if (b) HIPCHK(hipMemsetAsync(d, 0, b, s_)); }
+  void sync() override { HIPCHK(hipStreamSynchronize(s_)); }
+  int check(std::string *msg) override {
+    HIPCHK(hipGetLastError());
+    if (msg) *msg = errmsg_;
+    return err_;
+  }
+  hipStream_t stream() const { return s_; }
+  void timer_mark(int slot) override {
+    if (slot < 0 || slot >= 8) return;
+    if (!ev_[slot]) HIPCHK(hipEventCreate(&ev_[slot]));
+    HIPCHK(hipEventRecord(ev_[slot], s_));
+  }
+  double timer_ms(int a, int b) override {
+    if (a < 0 || b < 0 || a >= 8 || b >= 8 || !ev_[a] || !ev_[b]) return 0.0;
+    HIPCHK(hipEventSynchronize(ev_[b]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev_[a], ev_[b]));
+    return ms;
+  }
+
+  void gemm(const GemmDesc &d, const double *const *A, const double *const *B, double *const *C,
+            int nprob) override {
+    if (nprob <= 0 || d.M <= 0 || d.N <= 0) return;
+    int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+    dim3 grid(tiles, d.batch, nprob);
+    hipLaunchKernelGGL(gemm_c64_kernel, grid, dim3(256), 0, s_, d, A, B, C);
+    HIPCHK(hipGetLastError());
+  }
+  void eigh(int n, int lda, const double *const *in, double *const *evals, double *const *vecs,
+            int nprob) override {
+    if (nprob <= 0) return;
+    int np = n + (n & 1);
+    if (np <= 64) {
+      size_t sm = (size_t)2 * np * np * sizeof(double2);
+      hipLaunchKernelGGL(eigh_jacobi_kernel<true>, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
+                         evals, vecs, (double2 *)nullptr, 60);
+    } else {
+      size_t need = (size_t)nprob * 2 * np * np * sizeof(double2);
+      if (need > gws_bytes_) {
+        hipStreamSynchronize(s_);
+        if (gws_) hipFree(gws_);
+        gws_ = nullptr;
+        if (hipMalloc(&gws_, need) != hipSuccess) {
+          err_ = -4;
+          errmsg_ = "eigh workspace allocation failed";
+          gws_bytes_ = 0;
+          return;
+        }
+        gws_bytes_ = need;
+      }
+      hipLaunchKernelGGL(eigh_jacobi_kernel<false>, dim3(nprob), dim3(1024), 0, s_, n, lda, in,
+                         evals, vecs, (double2 *)gws_, 60);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  void rx(double *const *t, const int64_t *half, int nprob, double c, double s) override {
+    hipLaunchKernelGGL(rx_kernel, dim3(64, nprob), dim3(256), 0, s_, t, half, c, s);
+    HIPCHK(hipGetLastError());
+  }
+  void msg_sqrt(int n, const double *const *ev, const double *const *vec, double *const *X,
+                double *const *Xp, double cut, int nprob) override {
+    hipLaunchKernelGGL(msg_sqrt_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, X, Xp, cut);
+    HIPCHK(hipGetLastError());
+  }
+  void gram_factor(int n, int r, const double *const *ev, const double *const *vec,
+                   double *const *R, double *const *W, double cut, int nprob) override {
+    hipLaunchKernelGGL(gram_factor_kernel, dim3(nprob), dim3(256), 0, s_, n, r, ev, vec, R, W,
+                       cut);
+    HIPCHK(hipGetLastError());
+  }
+  void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
+             double *const *Th, double a, double b, double c, double d, int nprob) override {
+    int tot = 4 * rB * rS;
+    int bx = std::min(1024, (tot + 255) / 256);
+    hipLaunchKernelGGL(theta_kernel, dim3(bx, nprob), dim3(256), 0, s_, rB, rS, chi, RB, RS, Th,
+                       a, b, c, d);
+    HIPCHK(hipGetLastError());
+  }
+  void svd_finish(int n, int chi, const double *const *ev, const double *const *vec,
+                  double *const *Vs, double *const *S, int *kout, double *disc,
+                  double *const *mA, double *const *mB, double cutoff, int nprob) override {
+    hipLaunchKernelGGL(svd_finish_kernel, dim3(nprob), dim3(256), 0, s_, n, chi, ev, vec, Vs, S,
+                       kout, disc, mA, mB, cutoff);
+    HIPCHK(hipGetLastError());
+  }
+  void split_sqrt(int rowsB, int rowsS, int n, int chi, const double *const *U,
+                  const double *const *V, const double *const *S, double *const *RBn,
+                  double *const *RSn, int nprob) override {
+    int tot = (rowsB + rowsS) * chi;
+    int bx = std::min(1024, (tot + 255) / 256);
+    hipLaunchKernelGGL(split_sqrt_kernel, dim3(bx, nprob), dim3(256), 0, s_, rowsB, rowsS, n,
+                       chi, U, V, S, RBn, RSn);
+    HIPCHK(hipGetLastError());
+  }
+  void normalize_residual(int chi, double *const *Mn, const double *const *Mo, double *res,
+                          int nprob) override {
+    hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(256), 0, s_, chi, Mn, Mo,
+                       res);
+    HIPCHK(hipGetLastError());
+  }
+  void reduce_max(const double *x, int n, double *out) override {
+    hipLaunchKernelGGL(reduce_max_kernel, dim3(1), dim3(256), 0, s_, x, n, out);
+    HIPCHK(hipGetLastError());
+  }
+  void rho_dot(const double *const *Y, const double *const *T, const int64_t *len, double *rho,
+               int nprob) override {
+    hipLaunchKernelGGL(rho_dot_kernel, dim3(nprob), dim3(256), 0, s_, Y, T, len, rho);
+    HIPCHK(hipGetLastError());
+  }
+  void apply_op(const double *const *Tin, double *const *Tout, const int64_t *half,
+                const double *ops, int nprob) override {
+    hipLaunchKernelGGL(apply_op_kernel, dim3(64, nprob), dim3(256), 0, s_, Tin, Tout, half, ops);
+    HIPCHK(hipGetLastError());
+  }
+
+  int err_ = 0;
+  std::string errmsg_;
+
+ private:
+  int dev_;
+  hipStream_t s_;
+  bool own_;
+  void *gws_ = nullptr;
+  size_t gws_bytes_ = 0;
+  hipEvent_t ev_[8] = {};
+};
+
+Backend *make_hip_backend(int device, void *stream, std::string *err) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= device || device < 0) {
+    if (err) *err = "no HIP device available (hipGetDeviceCount)";
+    return nullptr;
+  }
+  HipBackend *b = new HipBackend(device, stream);
+  if (b->err_) {
+    if (err) *err = b->errmsg_;
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
+}  // namespace bpki

@@ -1,0 +1,117 @@
+"""Device primitives against independent host computations (numpy): the complex FP64 MFMA
+GEMM with composite strides, conjugation, batches and grouped problems, and the batched FP64
+Hermitian Jacobi eigensolver."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2306_14887_amd import bpki as B
+    c = B.Context()
+    yield c
+    c.close()
+
+
+def _rand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _ref_gemm(d, A, B, C, nprob, asz, bsz, csz):
+    out = C.copy()
+    Mi, Ni, Ki = d.get("Mi", d["M"]), d.get("Ni", d["N"]), d.get("Ki", d["K"])
+    m = np.arange(d["M"]); n = np.arange(d["N"]); k = np.arange(d["K"])
+    am = (m // Mi) * d.get("a_mo", 0) + (m % Mi) * d.get("a_mi", 0)
+    ak = (k // Ki) * d.get("a_ko", 0) + (k % Ki) * d.get("a_ki", 0)
+    bk = (k // Ki) * d.get("b_ko", 0) + (k % Ki) * d.get("b_ki", 0)
+    bn = (n // Ni) * d.get("b_no", 0) + (n % Ni) * d.get("b_ni", 0)
+    cm = (m // Mi) * d.get("c_mo", 0) + (m % Mi) * d.get("c_mi", 0)
+    cn = (n // Ni) * d.get("c_no", 0) + (n % Ni) * d.get("c_ni", 0)
+    alpha = d.get("alpha_re", 1.0) + 1j * d.get("alpha_im", 0.0)
+    for p in range(nprob):
+        for b in range(d.get("batch", 1)):
+            a = A[p * asz:(p + 1) * asz][b * d.get("a_b", 0) + am[:, None] + ak[None, :]]
+            bb = B[p * bsz:(p + 1) * bsz][b * d.get("b_b", 0) + bk[:, None] + bn[None, :]]
+            if d.get("conjA"): a = a.conj()
+            if d.get("conjB"): bb = bb.conj()
+            r = alpha * (a @ bb)
+            idx = p * csz + b * d.get("c_b", 0) + cm[:, None] + cn[None, :]
+            out[idx] = (out[idx] + r) if d.get("beta") else r
+    return out
+
+
+CASES = [
+    ("plain_64", dict(M=64, N=64, K=64, a_mi=64, a_ki=1, b_ki=64, b_ni=1, c_mi=64, c_ni=1), 1),
+    ("ragged", dict(M=37, N=70, K=19, a_mi=19, a_ki=1, b_ki=70, b_ni=1, c_mi=70, c_ni=1), 1),
+    ("kfast_conj", dict(M=96, N=40, K=48, a_mi=1, a_ki=96, b_ki=1, b_ni=48, c_mi=40, c_ni=1,
+                        conjA=1, conjB=1), 2),
+    ("composite", dict(M=64, Mi=8, N=24, Ni=8, K=32, Ki=4,
+                       a_mo=300, a_mi=1, a_ko=16, a_ki=2000,
+                       b_ko=200, b_ki=1, b_no=10, b_ni=1000,
+                       c_mo=400, c_mi=3, c_no=24, c_ni=1), 3),
+    ("batch_beta_alpha", dict(M=16, N=16, K=128, a_mi=128, a_ki=1, b_ki=16, b_ni=1, c_mi=16,
+                              c_ni=1, batch=3, a_b=2048, b_b=2048, c_b=256, beta=1,
+                              alpha_re=0.5, alpha_im=-2.0), 2),
+    ("tiny", dict(M=1, N=2, K=3, a_mi=3, a_ki=1, b_ki=2, b_ni=1, c_mi=2, c_ni=1), 1),
+]
+
+
+def _extent(d, pre):
+    Mi = d.get("Mi", d["M"]); Ni = d.get("Ni", d["N"]); Ki = d.get("Ki", d["K"])
+    def span(X, Xi, so, si):
+        return max(0, X // Xi - 1) * so + (Xi - 1) * si
+    if pre == "a":
+        e = span(d["M"], Mi, d.get("a_mo", 0), d.get("a_mi", 0)) + span(d["K"], Ki, d.get("a_ko", 0), d.get("a_ki", 0))
+        e += (d.get("batch", 1) - 1) * d.get("a_b", 0)
+    elif pre == "b":
+        e = span(d["K"], Ki, d.get("b_ko", 0), d.get("b_ki", 0)) + span(d["N"], Ni, d.get("b_no", 0), d.get("b_ni", 0))
+        e += (d.get("batch", 1) - 1) * d.get("b_b", 0)
+    else:
+        e = span(d["M"], Mi, d.get("c_mo", 0), d.get("c_mi", 0)) + span(d["N"], Ni, d.get("c_no", 0), d.get("c_ni", 0))
+        e += (d.get("batch", 1) - 1) * d.get("c_b", 0)
+    return e + 1
+
+
+@pytest.mark.parametrize("name,desc,nprob", CASES, ids=[c[0] for c in CASES])
+def test_gemm_matches_numpy(ctx, name, desc, nprob):
+    print(f"[gemm] case {name} nprob={nprob}", flush=True)
+    rng = np.random.default_rng(abs(hash(name)) % 2**32)
+    asz, bsz, csz = _extent(desc, "a"), _extent(desc, "b"), _extent(desc, "c")
+    A = _rand(rng, nprob * asz)
+    Bm = _rand(rng, nprob * bsz)
+    Cm = _rand(rng, nprob * csz)
+    got = ctx.test_gemm(desc, A, Bm, Cm, nprob)
+    want = _ref_gemm(desc, A, Bm, Cm, nprob, asz, bsz, csz)
+    scale = np.sqrt(desc["K"]) * 4
+    assert np.abs(got - want).max() < 1e-13 * scale
+
+
+def test_gemm_rejects_out_of_bounds_descriptor(ctx):
+    from paper_2306_14887_amd.bpki import BpkiError
+    d = dict(M=64, N=64, K=64, a_mi=64, a_ki=1, b_ki=64, b_ni=1, c_mi=64, c_ni=1)
+    A = np.zeros(64 * 64 - 1, complex)            # one element short
+    with pytest.raises(BpkiError):
+        ctx.test_gemm(d, A, np.zeros(64 * 64, complex), np.zeros(64 * 64, complex))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 63, 64, 65, 128, 200])
+def test_eigh_matches_numpy(ctx, n):
+    print(f"[eigh] n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    nprob = 3
+    X = _rand(rng, nprob, n, n)
+    A = X + X.conj().transpose(0, 2, 1)
+    # one PSD, rank-deficient problem with a wide spectrum (as in the Gram matrices)
+    Y = _rand(rng, n, max(1, n // 3)) * np.logspace(0, -6, max(1, n // 3))[None, :]
+    A[1] = Y @ Y.conj().T
+    ev, V = ctx.test_eigh(A)
+    for p in range(nprob):
+        ref = np.sort(np.linalg.eigvalsh(A[p]))[::-1]
+        scale = np.abs(ref).max()
+        assert np.abs(ev[p] - ref).max() < 1e-13 * scale * max(1, n / 16)
+        assert np.all(np.diff(ev[p]) <= 1e-15 * scale)
+        # eigenvectors: orthonormal and A V = V diag(ev)
+        assert np.abs(V[p].conj().T @ V[p] - np.eye(n)).max() < 1e-12 * max(1, n / 16)
+        assert np.abs(A[p] @ V[p] - V[p] * ev[p][None, :]).max() < 1e-12 * scale * max(1, n / 16)

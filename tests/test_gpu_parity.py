@@ -1,0 +1,197 @@
+"""HIP path (through the C ABI) against the FP64 oracle on the same inputs.
+
+Tolerance: 1e-8 absolute in every <Z> and Pauli value for the FP64 mode.  Whole runs are
+compared where the oracle finishes in seconds; at the 127-qubit chi=64 size of the benchmark,
+components are compared on identical states and sampled outputs, and properties that hold at
+any size are checked (light-cone exactness while untruncated, Clifford points, invariants).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bp_tns as O
+from oracle import statevector as SV
+from paper_2306_14887_amd import lattice as L
+
+from ._state_io import from_flat, message_list, to_flat
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2306_14887_amd import bpki as B
+    c = B.Context()
+    yield c
+    c.close()
+
+
+def _gpu(ctx, lat, theta, depth, chi, **kw):
+    from paper_2306_14887_amd import bpki as B
+    return ctx.solve(B.spec_from_lattice(lat, theta, depth, chi, **kw))
+
+
+def _ora(lat, theta, depth, chi, pauli=()):
+    return O.solve(lat.n_sites, lat.edges, lat.colour, theta, depth, O.Options(chi=chi),
+                   pauli=pauli)
+
+
+@pytest.mark.parametrize("theta", [0.0, math.pi / 8, math.pi / 4, 3 * math.pi / 8, math.pi / 2])
+def test_hexagon_ring_config(ctx, theta):
+    """One heavy hexagon, chi=4, 5 steps, tolerance 1e-12 BP: every <Z_v>(t)."""
+    print(f"[parity] ring theta={theta}", flush=True)
+    r = L.hexagon_ring()
+    g = _gpu(ctx, r, theta, 5, 4)
+    o = _ora(r, theta, 5, 4)
+    assert np.abs(g["z"] - o.z).max() < TOL
+    assert g["status"] == 0
+
+
+def test_tree_exact_vs_statevector(ctx):
+    print("[parity] random tree 14 sites chi=64", flush=True)
+    tr = L.random_tree(14, np.random.default_rng(2))
+    g = _gpu(ctx, tr, 0.9, 6, 64)
+    ref = SV.run(tr.n_sites, tr.edges, 0.9, 6)
+    assert np.abs(g["z"] - ref).max() < 1e-11
+
+
+def test_heavy_hex_29_truncated(ctx):
+    print("[parity] heavy-hex 29q chi=8 8 steps", flush=True)
+    lat = L.heavy_hex(3, 9)
+    for th in (0.3, 0.8):
+        g = _gpu(ctx, lat, th, 8, 8)
+        o = _ora(lat, th, 8, 8)
+        assert np.abs(g["z"] - o.z).max() < TOL
+        assert list(g["bp_iters"][2:]) == o.bp_iters[2:]
+
+
+def test_eagle_small_chi_full_run(ctx):
+    print("[parity] eagle chi=4 6 steps", flush=True)
+    e = L.eagle()
+    g = _gpu(ctx, e, 0.7, 6, 4)
+    o = _ora(e, 0.7, 6, 4)
+    assert np.abs(g["z"] - o.z).max() < TOL
+
+
+def test_pauli_strings(ctx):
+    print("[parity] pauli strings heavy-hex 29q", flush=True)
+    lat = L.heavy_hex(3, 9)
+    ps = L.random_pauli_strings(lat, 8, seed=14887, wmin=3, wmax=9)
+    pl = [(p.sites, p.ops) for p in ps]
+    g = _gpu(ctx, lat, 0.6, 5, 8, pauli=pl)
+    o = _ora(lat, 0.6, 5, 8, pauli=pl)
+    assert np.abs(g["pauli"] - o.pauli).max() < TOL
+
+
+def _session(ctx, lat, theta, depth, chi):
+    from paper_2306_14887_amd import bpki as B
+    return ctx.session(B.spec_from_lattice(lat, theta, depth, chi))
+
+
+def test_bp_sweep_identical_inputs_eagle_chi64(ctx):
+    """One BP sweep from an identical state at the benchmark size (127 q, chi = 64): sampled
+    messages against the oracle's message update computed one by one."""
+    print("[parity] eagle chi=64 BP sweep on identical state", flush=True)
+    e = L.eagle()
+    chi = 64
+    rng = np.random.default_rng(5)
+    net = O.Network(e.n_sites, e.edges, e.colour)
+    # random full-bond state with random PSD unit-trace messages
+    for v in range(net.n):
+        d = len(net.nb[v])
+        net.T[v] = (rng.standard_normal((2,) + (chi,) * d) + 1j * rng.standard_normal((2,) + (chi,) * d)) / chi
+    for k in list(net.M):
+        X = rng.standard_normal((chi, chi)) + 1j * rng.standard_normal((chi, chi))
+        M = X @ X.conj().T
+        net.M[k] = M / np.trace(M)
+    t, m, b = to_flat(net, chi)
+    b[:] = chi
+    s = _session(ctx, e, 0.4, 1, chi)
+    s.set_state(t, m, b)
+    s.bp_sweep()
+    _, m2, _ = s.get_state()
+    got = m2.reshape(-1, chi, chi)
+    idx = {}
+    for ei, (u, v) in enumerate(net.edges):
+        idx[(u, v)] = 2 * ei
+        idx[(v, u)] = 2 * ei + 1
+    keys = list(net.M)
+    pick = [keys[i] for i in rng.choice(len(keys), 24, replace=False)]
+    for (u, v) in pick:
+        ref = net.message(u, v, net.M)
+        assert np.abs(got[idx[(u, v)]] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+def test_observe_identical_state_eagle_chi64(ctx):
+    print("[parity] eagle chi=64 <Z> on identical state", flush=True)
+    e = L.eagle()
+    chi = 64
+    rng = np.random.default_rng(6)
+    net = O.Network(e.n_sites, e.edges, e.colour)
+    for v in range(net.n):
+        d = len(net.nb[v])
+        net.T[v] = (rng.standard_normal((2,) + (chi,) * d) + 1j * rng.standard_normal((2,) + (chi,) * d)) / chi
+    for k in list(net.M):
+        X = rng.standard_normal((chi, chi)) + 1j * rng.standard_normal((chi, chi))
+        M = X @ X.conj().T
+        net.M[k] = M / np.trace(M)
+    t, m, b = to_flat(net, chi)
+    s = _session(ctx, e, 0.4, 1, chi)
+    s.set_state(t, m, b)
+    z = s.observe_z()
+    for v in rng.choice(e.n_sites, 12, replace=False):
+        assert abs(z[v] - net.expect_site(int(v), 3)) < 1e-12
+
+
+def test_eagle_chi64_light_cone_exact(ctx):
+    """Benchmark configuration (127 q, chi=64, FP64), first 5 steps: untruncated, so every
+    sampled <Z_v>(t) equals the exact light-cone value."""
+    print("[parity] eagle chi=64 5 steps vs light cone", flush=True)
+    e = L.eagle()
+    theta = 0.6
+    g = _gpu(ctx, e, theta, 5, 64)
+    for v in [62, 13, 113, 40, 0, 90]:
+        for t in (1, 3, 5):
+            exact = SV.light_cone_z(e.n_sites, e.edges, v, theta, t)
+            assert abs(g["z"][t - 1, v] - exact) < 1e-10, (v, t)
+    assert np.all(np.abs(g["z"]) <= 1 + 1e-12)
+
+
+def test_clifford_points_eagle(ctx):
+    print("[parity] eagle Clifford points", flush=True)
+    e = L.eagle()
+    g0 = _gpu(ctx, e, 0.0, 3, 8)
+    assert np.abs(g0["z"] - 1).max() < 1e-12
+    g1 = _gpu(ctx, e, math.pi / 2, 3, 8)
+    assert np.abs(g1["z"]).max() < 1e-10          # stabilizer value 0, untruncated (8 = 2^3)
+
+
+def test_session_phases_match_solve(ctx):
+    print("[parity] session phases vs solve", flush=True)
+    lat = L.heavy_hex(3, 9)
+    g = _gpu(ctx, lat, 0.5, 4, 8)
+    s = _session(ctx, lat, 0.5, 4, 8)
+    zs = []
+    for _ in range(4):
+        s.apply_rx()
+        for c in range(lat.n_colours()):
+            s.apply_layer(c)
+        s.bp(1000)
+        zs.append(s.observe_z())
+    assert np.abs(np.array(zs) - g["z"]).max() < 1e-13
+
+
+def test_errors_and_edge_cases(ctx):
+    from paper_2306_14887_amd import bpki as B
+    e = L.path(2)
+    g = _gpu(ctx, e, 0.3, 0, 4)               # depth 0: <Z> = 1
+    assert np.all(g["z"] == 1.0)
+    g = _gpu(ctx, e, 0.3, 3, 1)               # chi = 1: product state
+    o = _ora(e, 0.3, 3, 1)
+    assert np.abs(g["z"] - o.z).max() < TOL
+    g = _gpu(ctx, L.heavy_hex(3, 9), 0.9, 3, 8, bp_max_iter=1, bp_tol=0.0)
+    assert g["status"] == 1                   # BP not converged warning
+    with pytest.raises(B.BpkiError):
+        _gpu(ctx, e, 0.3, 2, 0)
