@@ -70,7 +70,8 @@ typedef struct {
 } bpki_problem;
 
 typedef struct {
-  double *z;            /* [(record_every_step ? depth : 1) * n_sites], row t = step t+1       */
+  double *z;            /* [max(1, record_every_step ? depth : 1) * n_sites], row t = step t+1;
+                           depth 0 gives one row of ones (the initial state)                   */
   double *pauli;        /* [n_pauli] or NULL if n_pauli == 0                                    */
   int32_t *bp_iters;    /* optional [depth]: BP sweeps run after each step                      */
   double *bp_residual;  /* optional [depth]: final BP residual of each step                     */
@@ -148,6 +149,12 @@ int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residu
 /* Total device time of the last bpki_session_step, split by phase (milliseconds): rx, gate layers,
  * BP, observables.  Measured with HIP events on the session's stream. */
 int bpki_session_last_timing(const bpki_session *s, double *ms4);
+/* Kernel-level timing of the complex GEMM kernel (every contraction of the method runs in it):
+ * while enabled, each launch on the session's stream is bracketed by HIP events.  read returns
+ * the launch count, the summed kernel time in ms and the summed 8*M*N*K flops of those launches
+ * (complex multiply-adds at 8 real flops).  Enabling resets the counters. */
+int bpki_session_profile(bpki_session *s, int enable);
+int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, double *flops);
 
 #ifdef __cplusplus
 }

@@ -94,6 +94,8 @@ def load(path: str | None = None):
         "bpki_session_observe_pauli": (C.c_int, [vp, dp]),
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_last_timing": (C.c_int, [vp, dp]),
+        "bpki_session_profile": (C.c_int, [vp, C.c_int]),
+        "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp]),
         "bpki_test_gemm": (C.c_int, [vp, C.POINTER(TestGemmDesc), C.c_int, dp, C.c_size_t, dp,
                                      C.c_size_t, dp, C.c_size_t]),
         "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
@@ -114,7 +116,8 @@ def exported_symbols() -> list[str]:
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
             "bpki_session_bp_sweep", "bpki_session_observe_z", "bpki_session_observe_pauli",
-            "bpki_session_step", "bpki_session_last_timing", "bpki_test_gemm",
+            "bpki_session_step", "bpki_session_last_timing", "bpki_session_profile",
+            "bpki_session_profile_read", "bpki_test_gemm",
             "bpki_test_eigh"]
 
 
@@ -388,6 +391,15 @@ class Session:
             C.byref(d)))
         return {"z": z, "bp_iters": it.value, "bp_residual": r.value, "discarded": d.value,
                 "status": rc}
+
+    def profile(self, enable: bool = True):
+        _check(self.lib, self.lib.bpki_session_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
+        _check(self.lib, self.lib.bpki_session_profile_read(self.h, C.byref(n), C.byref(ms),
+                                                            C.byref(fl)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value}
 
     def last_timing(self) -> np.ndarray:
         t = np.zeros(4)

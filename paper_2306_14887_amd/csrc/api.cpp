@@ -223,8 +223,8 @@ extern "C" void bpki_destroy(bpki_ctx *c) {
 static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
                      std::atomic<bool> *cancel) {
   const int n = q.n_sites;
-  const int rows = q.record_every_step ? q.depth : 1;
-  std::vector<double> z((size_t)std::max(rows, 1) * n, 1.0);
+  const int rows = std::max(1, q.record_every_step ? q.depth : 1);
+  std::vector<double> z((size_t)rows * n, 1.0);
   std::vector<int32_t> iters(q.depth, 0);
   std::vector<double> res(q.depth, 0.0), disc(q.depth, 0.0);
   int warn = 0;
@@ -415,6 +415,21 @@ extern "C" int bpki_session_step(bpki_session *s, double *z, int32_t *iters, dou
   return r < s->eng->problem().bp_tol ? 0 : 1;
 }
 
+extern "C" int bpki_session_profile(bpki_session *s, int enable) {
+  if (!s) return fail(-1, "NULL session");
+  s->ctx->be->gemm_profile(enable != 0);
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms,
+                                         double *flops) {
+  if (!s) return fail(-1, "NULL session");
+  long l = 0;
+  s->ctx->be->gemm_profile_read(&l, ms, flops);
+  if (launches) *launches = l;
+  return sess_check(s);
+}
+
 extern "C" int bpki_session_last_timing(const bpki_session *s, double *ms4) {
   if (!s || !ms4) return fail(-1, "NULL argument");
   for (int i = 0; i < 4; ++i) ms4[i] = s->timing[i];
@@ -510,7 +525,7 @@ struct Resident {
 static void finish(bpki_ctx *c, Resident &R, int status) {
   const Problem &q = R.job->q;
   if (status >= 0) {
-    int rows = q.record_every_step ? q.depth : 1;
+    int rows = std::max(1, q.record_every_step ? q.depth : 1);
     bpki_result *r = R.job->r;
     if (r->z) std::memcpy(r->z, R.z.data(), (size_t)rows * q.n_sites * sizeof(double));
     if (r->bp_iters) std::memcpy(r->bp_iters, R.iters.data(), R.iters.size() * sizeof(int32_t));

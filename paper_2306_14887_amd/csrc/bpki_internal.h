@@ -48,6 +48,10 @@ struct Backend {
   // HIP events on the backend's stream: mark slot i; elapsed milliseconds between two marks.
   virtual void timer_mark(int slot) = 0;
   virtual double timer_ms(int a, int b) = 0;
+  // Per-launch GEMM timing (HIP events around every gemm launch while enabled).  read() returns
+  // the number of launches, their summed duration (ms) and summed 8*M*N*K*batch*nprob flops.
+  virtual void gemm_profile(bool enable) = 0;
+  virtual void gemm_profile_read(long *launches, double *ms, double *flops) = 0;
 
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,

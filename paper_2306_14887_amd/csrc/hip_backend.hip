@@ -18,6 +18,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "bpki_internal.h"
 
@@ -123,14 +125,14 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double 
     }
     __syncthreads();
   }
-  // ---- epilogue: D layout of 16x16x4 f64: lane l, reg r -> row 4*(l/16)+r, col l%16 ----
+  // ---- epilogue: D layout of 16x16x4 f64: lane l, reg r -> row l/16 + 4*r, col l%16 ----
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int mg = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        int mg = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
         int ng = n0 + wn + j * 16 + (lane & 15);
         if (mg >= d.M || ng >= d.N) continue;
         double cr = acc[i][j][0][r] - acc[i][j][1][r];
@@ -627,8 +629,46 @@ class HipBackend : public Backend {
     if (nprob <= 0 || d.M <= 0 || d.N <= 0) return;
     int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
     dim3 grid(tiles, d.batch, nprob);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof_) {
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, s_));
+    }
     hipLaunchKernelGGL(gemm_c64_kernel, grid, dim3(256), 0, s_, d, A, B, C);
     HIPCHK(hipGetLastError());
+    if (prof_) {
+      HIPCHK(hipEventRecord(e1, s_));
+      prof_ev_.push_back({e0, e1});
+      prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
+    }
+  }
+  void gemm_profile(bool enable) override {
+    prof_ = enable;
+    if (enable) {
+      drain_profile();
+      prof_launches_ = 0;
+      prof_ms_ = 0;
+      prof_flops_ = 0;
+    }
+  }
+  void gemm_profile_read(long *launches, double *ms, double *flops) override {
+    drain_profile();
+    if (launches) *launches = prof_launches_;
+    if (ms) *ms = prof_ms_;
+    if (flops) *flops = prof_flops_;
+  }
+  void drain_profile() {
+    for (auto &pr : prof_ev_) {
+      HIPCHK(hipEventSynchronize(pr.second));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      prof_ms_ += ms;
+      prof_launches_ += 1;
+      HIPCHK(hipEventDestroy(pr.first));
+      HIPCHK(hipEventDestroy(pr.second));
+    }
+    prof_ev_.clear();
   }
   void eigh(int n, int lda, const double *const *in, double *const *evals, double *const *vecs,
             int nprob) override {
@@ -727,6 +767,10 @@ class HipBackend : public Backend {
   void *gws_ = nullptr;
   size_t gws_bytes_ = 0;
   hipEvent_t ev_[8] = {};
+  bool prof_ = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev_;
+  long prof_launches_ = 0;
+  double prof_ms_ = 0, prof_flops_ = 0;
 };
 
 Backend *make_hip_backend(int device, void *stream, std::string *err) {

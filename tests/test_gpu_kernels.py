@@ -50,7 +50,7 @@ CASES = [
     ("composite", dict(M=64, Mi=8, N=24, Ni=8, K=32, Ki=4,
                        a_mo=300, a_mi=1, a_ko=16, a_ki=2000,
                        b_ko=200, b_ki=1, b_no=10, b_ni=1000,
-                       c_mo=400, c_mi=3, c_no=24, c_ni=1), 3),
+                       c_mo=200, c_mi=24, c_no=8, c_ni=1), 3),
     ("batch_beta_alpha", dict(M=16, N=16, K=128, a_mi=128, a_ki=1, b_ki=16, b_ni=1, c_mi=16,
                               c_ni=1, batch=3, a_b=2048, b_b=2048, c_b=256, beta=1,
                               alpha_re=0.5, alpha_im=-2.0), 2),
