@@ -40,15 +40,37 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // GEMM
 namespace {
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+constexpr int LOADS = (BM * BK) / 256;   // complex elements each thread stages per operand
 }
 
 __device__ __forceinline__ long cidx(int i, int inner, long so, long si) {
   return (long)(i / inner) * so + (long)(i % inner) * si;
 }
 
-__global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double *const *Ap,
-                                                       const double *const *Bp,
-                                                       double *const *Cp) {
+// Offsets of the K part of an operand for a whole K tile starting at k0.  When Ki is a
+// multiple of BK the tile never straddles an outer index, so the division happens once per
+// tile; otherwise per element.
+struct KOff {
+  long base;
+  long si;
+  bool uniform;
+};
+
+__device__ __forceinline__ KOff k_tile(int k0, int Ki, long so, long si) {
+  KOff r;
+  r.uniform = (Ki % BK) == 0;
+  r.base = r.uniform ? (long)(k0 / Ki) * so + (long)(k0 % Ki) * si : 0;
+  r.si = si;
+  return r;
+}
+
+// Grouped complex GEMM.  grid: x = output tiles, y = batch * ksplit, z = problem.  With
+// ksplit > 1 each block sums its K chunk into the partial buffer W (layout
+// [prob][batch][kz][M][N]); gemm_reduce_kernel then combines the chunks in a fixed order.
+__global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const double *const *Ap,
+                                                          const double *const *Bp,
+                                                          double *const *Cp, int ksplit,
+                                                          int kchunk, double2 *W) {
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
@@ -56,15 +78,59 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double 
   const int wave = tid >> 6;
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-  const int bat = blockIdx.y, prob = blockIdx.z;
+  const int bat = blockIdx.y / ksplit, kz = blockIdx.y % ksplit, prob = blockIdx.z;
   const double2 *A = reinterpret_cast<const double2 *>(Ap[prob]) + (long)bat * d.a_b;
   const double2 *B = reinterpret_cast<const double2 *>(Bp[prob]) + (long)bat * d.b_b;
-  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
   const int m0 = tm * BM, n0 = tn * BN;
+  const int kbeg = kz * kchunk, kend = min(d.K, kbeg + kchunk);
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const bool a_mfast = (d.a_mi == 1);
   const bool b_nfast = (d.b_ni == 1);
   const double sa = d.conjA ? -1.0 : 1.0, sb = d.conjB ? -1.0 : 1.0;
+
+  // per-thread staging coordinates and the M / N parts of their offsets (fixed over K)
+  int am[LOADS], ak[LOADS], bn[LOADS], bk[LOADS];
+  long aoff[LOADS], boff[LOADS];
+  bool aok[LOADS], bok[LOADS];
+#pragma unroll
+  for (int it = 0; it < LOADS; ++it) {
+    int e = tid + it * 256;
+    if (a_mfast) { am[it] = e % BM; ak[it] = e / BM; } else { ak[it] = e % BK; am[it] = e / BK; }
+    if (b_nfast) { bn[it] = e % BN; bk[it] = e / BN; } else { bk[it] = e % BK; bn[it] = e / BK; }
+    int mg = m0 + am[it], ng = n0 + bn[it];
+    aok[it] = mg < d.M;
+    bok[it] = ng < d.N;
+    aoff[it] = aok[it] ? cidx(mg, d.Mi, d.a_mo, d.a_mi) : 0;
+    boff[it] = bok[it] ? cidx(ng, d.Ni, d.b_no, d.b_ni) : 0;
+  }
+  double2 ra[LOADS], rb[LOADS];
+  auto fetch = [&](int k0) {
+    KOff ka = k_tile(k0, d.Ki, d.a_ko, d.a_ki), kb = k_tile(k0, d.Ki, d.b_ko, d.b_ki);
+#pragma unroll
+    for (int it = 0; it < LOADS; ++it) {
+      int kga = k0 + ak[it], kgb = k0 + bk[it];
+      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      if (aok[it] && kga < kend) {
+        long o = ka.uniform ? ka.base + (long)ak[it] * ka.si : cidx(kga, d.Ki, d.a_ko, d.a_ki);
+        va = A[aoff[it] + o];
+      }
+      if (bok[it] && kgb < kend) {
+        long o = kb.uniform ? kb.base + (long)bk[it] * kb.si : cidx(kgb, d.Ki, d.b_ko, d.b_ki);
+        vb = B[boff[it] + o];
+      }
+      ra[it] = va;
+      rb[it] = vb;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int it = 0; it < LOADS; ++it) {
+      As[0][ak[it]][am[it]] = ra[it].x;
+      As[1][ak[it]][am[it]] = sa * ra[it].y;
+      Bs[0][bk[it]][bn[it]] = rb[it].x;
+      Bs[1][bk[it]][bn[it]] = sb * rb[it].y;
+    }
+  };
 
   double4_t acc[2][2][4];
 #pragma unroll
@@ -74,34 +140,11 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double 
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[i][j][t] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
-    // ---- stage A tile (BM x BK) ----
-#pragma unroll
-    for (int it = 0; it < (BM * BK) / 256; ++it) {
-      int e = tid + it * 256;
-      int m, k;
-      if (a_mfast) { m = e % BM; k = e / BM; } else { k = e % BK; m = e / BK; }
-      int mg = m0 + m, kg = k0 + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (mg < d.M && kg < d.K)
-        v = A[cidx(mg, d.Mi, d.a_mo, d.a_mi) + cidx(kg, d.Ki, d.a_ko, d.a_ki)];
-      As[0][k][m] = v.x;
-      As[1][k][m] = sa * v.y;
-    }
-    // ---- stage B tile (BK x BN) ----
-#pragma unroll
-    for (int it = 0; it < (BN * BK) / 256; ++it) {
-      int e = tid + it * 256;
-      int n, k;
-      if (b_nfast) { n = e % BN; k = e / BN; } else { k = e % BK; n = e / BK; }
-      int ng = n0 + n, kg = k0 + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (ng < d.N && kg < d.K)
-        v = B[cidx(kg, d.Ki, d.b_ko, d.b_ki) + cidx(ng, d.Ni, d.b_no, d.b_ni)];
-      Bs[0][k][n] = v.x;
-      Bs[1][k][n] = sb * v.y;
-    }
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    stage();
     __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);      // next tile's global loads overlap the MFMAs
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
@@ -126,6 +169,9 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double 
     __syncthreads();
   }
   // ---- epilogue: D layout of 16x16x4 f64: lane l, reg r -> row l/16 + 4*r, col l%16 ----
+  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  double2 *Wp = W ? W + (((size_t)prob * d.batch + bat) * ksplit + kz) * (size_t)d.M * d.N
+                  : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -137,6 +183,10 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double 
         if (mg >= d.M || ng >= d.N) continue;
         double cr = acc[i][j][0][r] - acc[i][j][1][r];
         double ci = acc[i][j][2][r] + acc[i][j][3][r];
+        if (Wp) {
+          Wp[(size_t)mg * d.N + ng] = make_double2(cr, ci);
+          continue;
+        }
         double vr = d.alpha_re * cr - d.alpha_im * ci;
         double vi = d.alpha_re * ci + d.alpha_im * cr;
         long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
@@ -147,6 +197,34 @@ __global__ __launch_bounds__(256) void gemm_c64_kernel(GemmDesc d, const double 
         }
         C[off] = make_double2(vr, vi);
       }
+}
+
+// Sums the K chunks of a split-K GEMM in chunk order and applies alpha / beta.
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *const *Cp,
+                                                          int ksplit, const double2 *W) {
+  const int bat = blockIdx.y, prob = blockIdx.z;
+  const size_t mn = (size_t)d.M * d.N;
+  const double2 *wp = W + ((size_t)prob * d.batch + bat) * ksplit * mn;
+  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < mn;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    double cr = 0, ci = 0;
+    for (int kz = 0; kz < ksplit; ++kz) {
+      double2 v = wp[kz * mn + idx];
+      cr += v.x;
+      ci += v.y;
+    }
+    int mg = (int)(idx / d.N), ng = (int)(idx % d.N);
+    double vr = d.alpha_re * cr - d.alpha_im * ci;
+    double vi = d.alpha_re * ci + d.alpha_im * cr;
+    long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
+    if (d.beta) {
+      double2 o = C[off];
+      vr += o.x;
+      vi += o.y;
+    }
+    C[off] = make_double2(vr, vi);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -574,6 +652,7 @@ class HipBackend : public Backend {
     for (auto &e : ev_)
       if (e) hipEventDestroy(e);
     if (gws_) hipFree(gws_);
+    if (skws_) hipFree(skws_);
     if (own_) hipStreamDestroy(s_);
   }
   void *alloc(size_t bytes) override {
@@ -635,13 +714,51 @@ class HipBackend : public Backend {
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s_));
     }
-    hipLaunchKernelGGL(gemm_c64_kernel, grid, dim3(256), 0, s_, d, A, B, C);
+    // split K when the output alone cannot fill the machine
+    int blocks = tiles * d.batch * nprob;
+    int ksplit = 1, kchunk = d.K;
+    if (blocks < 512 && d.K >= 512) {
+      int want = std::min((512 + blocks - 1) / blocks, d.K / 256);
+      if (want > 1) {
+        kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
+        ksplit = (d.K + kchunk - 1) / kchunk;
+      }
+    }
+    double2 *W = nullptr;
+    if (ksplit > 1) {
+      size_t need = (size_t)nprob * d.batch * ksplit * d.M * d.N * sizeof(double2);
+      W = (double2 *)splitk_ws(need);
+      if (!W) return;
+      grid.y = d.batch * ksplit;
+    }
+    hipLaunchKernelGGL(gemm_c64_kernel, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk, W);
     HIPCHK(hipGetLastError());
     if (prof_) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
       prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
     }
+    if (ksplit > 1) {
+      int bx = std::min(64, (int)((d.M * (size_t)d.N + 255) / 256));
+      hipLaunchKernelGGL(gemm_reduce_kernel, dim3(bx, d.batch, nprob), dim3(256), 0, s_, d, C,
+                         ksplit, (const double2 *)W);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  void *splitk_ws(size_t need) {
+    if (need > skws_bytes_) {
+      hipStreamSynchronize(s_);
+      if (skws_) hipFree(skws_);
+      skws_ = nullptr;
+      skws_bytes_ = 0;
+      if (hipMalloc(&skws_, need) != hipSuccess) {
+        err_ = -4;
+        errmsg_ = "split-K workspace allocation failed";
+        return nullptr;
+      }
+      skws_bytes_ = need;
+    }
+    return skws_;
   }
   void gemm_profile(bool enable) override {
     prof_ = enable;
@@ -767,6 +884,8 @@ class HipBackend : public Backend {
   void *gws_ = nullptr;
   size_t gws_bytes_ = 0;
   hipEvent_t ev_[8] = {};
+  void *skws_ = nullptr;
+  size_t skws_bytes_ = 0;
   bool prof_ = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev_;
   long prof_launches_ = 0;

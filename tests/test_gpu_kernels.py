@@ -55,6 +55,12 @@ CASES = [
                               c_ni=1, batch=3, a_b=2048, b_b=2048, c_b=256, beta=1,
                               alpha_re=0.5, alpha_im=-2.0), 2),
     ("tiny", dict(M=1, N=2, K=3, a_mi=3, a_ki=1, b_ki=2, b_ni=1, c_mi=2, c_ni=1), 1),
+    # long K with few output tiles: split-K path (chunked K, deterministic reduction)
+    ("splitk_composite", dict(M=64, N=48, K=4096, Ki=64, a_ko=64 * 64, a_mi=64, a_ki=1,
+                              b_ko=64 * 48, b_ki=48, b_ni=1, c_mi=48, c_ni=1, beta=1,
+                              alpha_re=-1.5, alpha_im=0.25), 2),
+    ("splitk_odd_inner", dict(M=40, N=24, K=700, Ki=7, a_mi=1, a_ko=40 * 7, a_ki=40,
+                              b_ko=7, b_ki=1, b_ni=700, c_mi=24, c_ni=1, conjB=1), 1),
 ]
 
 
