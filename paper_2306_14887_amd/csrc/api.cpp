@@ -71,7 +71,7 @@ extern "C" int bpki_validate(const bpki_problem *p) {
   if (!p->edges) return fail(-1, "edges is NULL");
   if (!std::isfinite(p->theta_h)) return fail(-1, "theta_h must be finite");
   if (p->depth < 0) return fail(-1, "depth must be >= 0");
-  if (p->chi < 1 || p->chi > 256) return fail(-1, "chi must be in 1..256");
+  if (p->chi < 1 || p->chi > 128) return fail(-1, "chi must be in 1..128");
   if (p->precision != BPKI_FP64 && p->precision != BPKI_FP32)
     return fail(-1, "precision must be BPKI_FP64 or BPKI_FP32");
   if (!std::isfinite(p->bp_tol) || p->bp_tol < 0) return fail(-1, "bp_tol must be finite, >= 0");
@@ -94,6 +94,10 @@ extern "C" int bpki_validate(const bpki_problem *p) {
   }
   for (int v = 0; v < n; ++v)
     if (deg[v] < 1 || deg[v] > 3) return fail(-2, "every site must have degree 1..3");
+  // the truncated SVD of a gate block between two degree-3 sites is a 4chi x 4chi problem
+  for (int e = 0; e < E; ++e)
+    if (deg[p->edges[2 * e]] == 3 && deg[p->edges[2 * e + 1]] == 3 && p->chi > 64)
+      return fail(-1, "chi must be <= 64 when two degree-3 sites share an edge");
   if (p->colour) {
     std::vector<std::set<int>> used(n);
     for (int e = 0; e < E; ++e) {

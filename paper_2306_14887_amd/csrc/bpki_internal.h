@@ -71,6 +71,12 @@ struct Backend {
   // Wsc[c][i] = W[c][i]/sqrt(l_i) for l_i > cut*l_0 (else 0), i < r.
   virtual void gram_factor(int n, int r, const double *const *evals, const double *const *vecs,
                            double *const *R, double *const *Wsc, double cut, int nprob) = 0;
+  // Pivoted Cholesky factor of a Gram matrix G = A^H A (n x n, Hermitian PSD):
+  // G[p][p] = L L^H for a pivot order p, stopping at the first pivot <= cut * max(diag G).
+  // Writes R = L^H P^T (n x n, zero rows beyond the rank) and Wsc = P [L1^{-H}; 0] (n x n), so
+  // that R^H R = G and Q = A Wsc has orthonormal columns.
+  virtual void gram_chol(int n, const double *const *G, double *const *R, double *const *Wsc,
+                         double cut, int nprob) = 0;
   // Theta[(rb,sb)][(rs,ss)] = g(sb,ss) sum_b RB[rb][sb][b] RS[rs][ss][b];  chi = bond extent
   virtual void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
                      double *const *Th, double g_same_re, double g_same_im, double g_diff_re,

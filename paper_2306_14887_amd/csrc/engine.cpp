@@ -50,6 +50,10 @@ struct PtrArena {
 
 inline long ipow(long b, int e) { long r = 1; while (e-- > 0) r *= b; return r; }
 
+// Relative pivot threshold of the Gram-matrix Cholesky: directions of A whose squared weight is
+// below this fraction of the largest are at the FP64 rounding level of the Gram matrix.
+constexpr double kGramCut = 1e-15;
+
 }  // namespace
 
 // Strides of a site tensor's indices: s first, then one per leg.
@@ -806,11 +810,8 @@ double Engine::apply_layer(int colour) {
   // 3. isolate degree-3 endpoints
   if (LP.n_g) {
     run(be_, ar, LP.gram);
-    be_->eigh(2 * chi, 2 * chi, ar.at<const double *const *>(LP.g_in),
-              ar.at<double *const *>(LP.g_ev), ar.at<double *const *>(LP.g_vec), LP.n_g);
-    be_->gram_factor(2 * chi, 2 * chi, ar.at<const double *const *>(LP.g_ev),
-                     ar.at<const double *const *>(LP.g_vec), ar.at<double *const *>(LP.g_R),
-                     ar.at<double *const *>(LP.g_Wsc), 1e-15, LP.n_g);
+    be_->gram_chol(2 * chi, ar.at<const double *const *>(LP.g_in), ar.at<double *const *>(LP.g_R),
+                   ar.at<double *const *>(LP.g_Wsc), kGramCut, LP.n_g);
     run(be_, ar, LP.qform);
   }
   // 4-6. Theta, truncated SVD, new factors

@@ -364,6 +364,290 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
   }
 }
 
+// Jacobi for 64 < n <= 128: the Hermitian matrix is held packed (lower triangle) in LDS and
+// the rotations of every round are logged to global memory; the eigenvector matrix is then
+// rebuilt by replaying the log on blocks of 64 rows held in LDS (rows of V evolve independently
+// under the right-multiplied rotations).
+__device__ __forceinline__ size_t pk_idx(int i, int j) {   // i >= j
+  return (size_t)i * (i + 1) / 2 + j;
+}
+__device__ __forceinline__ double2 pk_get(const double2 *P, int i, int j) {
+  return i >= j ? P[pk_idx(i, j)] : cconj(P[pk_idx(j, i)]);
+}
+__device__ __forceinline__ void pk_set(double2 *P, int i, int j, double2 v) {
+  if (i >= j) P[pk_idx(i, j)] = v;
+  else P[pk_idx(j, i)] = cconj(v);
+}
+
+__global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
+                                                               const double *const *in,
+                                                               double *const *evals,
+                                                               double *const *vecs,
+                                                               double4_t *logbuf,
+                                                               int max_sweeps) {
+  extern __shared__ double2 smem[];
+  __shared__ Rot rot[64];
+  __shared__ int any_rot, nrounds_s;
+  __shared__ double diag_s[128];
+  const int prob = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int np = n + (n & 1);
+  const int h = np / 2;
+  double2 *P = smem;
+  double4_t *lg = logbuf + (size_t)prob * max_sweeps * (np - 1) * h;
+  const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+  for (int idx = tid; idx < np * (np + 1) / 2; idx += nt) {
+    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while ((size_t)i * (i + 1) / 2 > (size_t)idx) --i;
+    while ((size_t)(i + 1) * (i + 2) / 2 <= (size_t)idx) ++i;
+    int j = idx - i * (i + 1) / 2;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n && j < n) {
+      double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
+      v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    }
+    P[idx] = v;
+  }
+  if (tid == 0) nrounds_s = 0;
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  int nrounds = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < h) {
+        int p, q;
+        pair_of(r, tid, np, p, q);
+        double a = P[pk_idx(p, p)].x, dd = P[pk_idx(q, q)].x;
+        double2 b = pk_get(P, p, q);
+        double beta = sqrt(b.x * b.x + b.y * b.y);
+        Rot R;
+        R.p = p; R.q = q;
+        if (beta > 1e-300 && beta > eps * sqrt(fabs(a) * fabs(dd))) {
+          double tau = (dd - a) / (2.0 * beta);
+          double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          double c = 1.0 / sqrt(1.0 + t * t);
+          R.c = c; R.s = t * c;
+          R.wr = b.x / beta; R.wi = -b.y / beta;
+          any_rot = 1;
+        } else {
+          R.c = 1.0; R.s = 0.0; R.wr = 1.0; R.wi = 0.0;
+        }
+        rot[tid] = R;
+        lg[(size_t)nrounds * h + tid] = (double4_t){R.c, R.s, R.wr, R.wi};
+      }
+      __syncthreads();
+      // blocks (I, J) with I >= J cover every unordered element pair once
+      const int nblk = h * (h + 1) / 2;
+      for (int blk = tid; blk < nblk; blk += nt) {
+        int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > blk) --I;
+        while ((I + 1) * (I + 2) / 2 <= blk) ++I;
+        int J = blk - I * (I + 1) / 2;
+        Rot ri = rot[I], rj = rot[J];
+        if (ri.s == 0.0 && rj.s == 0.0) continue;
+        double2 w_j = make_double2(rj.wr, rj.wi), w_i_c = make_double2(ri.wr, -ri.wi);
+        double2 b00 = pk_get(P, ri.p, rj.p), b01 = pk_get(P, ri.p, rj.q);
+        double2 b10 = pk_get(P, ri.q, rj.p), b11 = pk_get(P, ri.q, rj.q);
+        double2 sw = cscale(rj.s, w_j), cw = cscale(rj.c, w_j);
+        double2 t00 = cadd(cscale(rj.c, b00), cscale(-1.0, cmul(sw, b01)));
+        double2 t10 = cadd(cscale(rj.c, b10), cscale(-1.0, cmul(sw, b11)));
+        double2 t01 = cadd(cscale(rj.s, b00), cmul(cw, b01));
+        double2 t11 = cadd(cscale(rj.s, b10), cmul(cw, b11));
+        double2 swc = cscale(ri.s, w_i_c), cwc = cscale(ri.c, w_i_c);
+        double2 n00 = cadd(cscale(ri.c, t00), cscale(-1.0, cmul(swc, t10)));
+        double2 n01 = cadd(cscale(ri.c, t01), cscale(-1.0, cmul(swc, t11)));
+        double2 n10 = cadd(cscale(ri.s, t00), cmul(cwc, t10));
+        double2 n11 = cadd(cscale(ri.s, t01), cmul(cwc, t11));
+        if (I == J) {
+          n00.y = 0.0; n11.y = 0.0;
+          if (ri.s != 0.0) n10 = make_double2(0.0, 0.0);
+          pk_set(P, ri.p, ri.p, n00);
+          pk_set(P, ri.q, ri.q, n11);
+          pk_set(P, ri.q, ri.p, n10);
+        } else {
+          pk_set(P, ri.p, rj.p, n00);
+          pk_set(P, ri.p, rj.q, n01);
+          pk_set(P, ri.q, rj.p, n10);
+          pk_set(P, ri.q, rj.q, n11);
+        }
+      }
+      ++nrounds;
+      __syncthreads();
+    }
+    __syncthreads();
+    int stop = (any_rot == 0);
+    __syncthreads();
+    if (stop) break;
+  }
+  for (int i = tid; i < n; i += nt) diag_s[i] = P[pk_idx(i, i)].x;
+  __threadfence();
+  __syncthreads();
+  // rebuild V by replaying the rotation log on 64-row blocks of V held in LDS
+  double *ev = evals[prob];
+  double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
+  double2 *Vb = smem;
+  for (int r0 = 0; r0 < np; r0 += 64) {
+    const int rows = min(64, np - r0);
+    for (int idx = tid; idx < rows * np; idx += nt) {
+      int rr = idx / np, c = idx % np;
+      Vb[idx] = make_double2((r0 + rr) == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int t = 0; t < nrounds; ++t) {
+      const int rr0 = t % (np - 1);
+      const double4_t *lr = lg + (size_t)t * h;
+      for (int it = tid; it < rows * h; it += nt) {
+        int rr = it / h, J = it % h;
+        double4_t R = lr[J];
+        if (R[1] == 0.0) continue;
+        int p, q;
+        pair_of(rr0, J, np, p, q);
+        double2 w = make_double2(R[2], R[3]);
+        double2 vp = Vb[rr * np + p], vq = Vb[rr * np + q];
+        double2 sw = cscale(R[1], w), cw = cscale(R[0], w);
+        Vb[rr * np + p] = cadd(cscale(R[0], vp), cscale(-1.0, cmul(sw, vq)));
+        Vb[rr * np + q] = cadd(cscale(R[1], vp), cmul(cw, vq));
+      }
+      __syncthreads();
+    }
+    // write the rows of this block, columns permuted into descending eigenvalue order
+    for (int idx = tid; idx < rows * n; idx += nt) {
+      int rr = idx / n, i = idx % n;
+      int row = r0 + rr;
+      if (row >= n) continue;
+      double li = diag_s[i];
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        double lj = diag_s[j];
+        rank += (lj > li) || (lj == li && j < i);
+      }
+      vo[(size_t)row * n + rank] = Vb[rr * np + i];
+      if (row == 0) ev[rank] = li;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pivoted Cholesky factor of a Gram matrix (one workgroup per matrix, work arrays in an
+// L2-resident global area).  Right-looking: pivot = largest remaining diagonal entry (wave
+// reduction), column of L, rank-1 update of the trailing Schur complement; stops at the first
+// pivot <= cut * max diag.  Then X = L1^{-1} by forward substitution (one thread per column).
+__global__ __launch_bounds__(1024) void gram_chol_kernel(int n, const double *const *G,
+                                                         double *const *R, double *const *Wsc,
+                                                         double cut, double2 *ws) {
+  __shared__ int perm[256];
+  __shared__ double dg[256];
+  __shared__ int piv_s, rank_s;
+  __shared__ double gmax_s;
+  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  double2 *W = ws + (size_t)prob * 3 * n * n, *L = W + (size_t)n * n, *X = L + (size_t)n * n;
+  const double2 *g = reinterpret_cast<const double2 *>(G[prob]);
+  for (int idx = tid; idx < n * n; idx += nt) {
+    int i = idx / n, j = idx % n;
+    double2 a = g[(size_t)i * n + j], b = g[(size_t)j * n + i];
+    W[idx] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    L[idx] = make_double2(0.0, 0.0);
+    X[idx] = make_double2(0.0, 0.0);
+  }
+  for (int i = tid; i < n; i += nt) {
+    perm[i] = i;
+    dg[i] = g[(size_t)i * n + i].x;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double m = 0;
+    for (int i = lane; i < n; i += 64) m = fmax(m, dg[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) { gmax_s = m; rank_s = n; }
+  }
+  __syncthreads();
+  const double gmax = gmax_s;
+  for (int k = 0; k < n; ++k) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bj = k;
+      for (int j = k + lane; j < n; j += 64) {
+        double v = dg[perm[j]];
+        if (v > best) { best = v; bj = j; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ob = __shfl_xor(best, o, 64);
+        int oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+      }
+      if (lane == 0) {
+        if (!(best > cut * gmax) || !(gmax > 0)) {
+          rank_s = k;
+          piv_s = -1;
+        } else {
+          int t = perm[k];
+          perm[k] = perm[bj];
+          perm[bj] = t;
+          piv_s = bj;
+        }
+      }
+    }
+    __syncthreads();
+    if (piv_s < 0) break;
+    const int pk = perm[k];
+    const double piv = sqrt(dg[pk]);
+    for (int kk = k + 1 + tid; kk < n; kk += nt) {
+      int i = perm[kk];
+      double2 w = W[(size_t)i * n + pk];
+      L[(size_t)i * n + k] = make_double2(w.x / piv, w.y / piv);
+    }
+    if (tid == 0) L[(size_t)pk * n + k] = make_double2(piv, 0.0);
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int idx = tid; idx < m * m; idx += nt) {
+      int a = k + 1 + idx / m, b = k + 1 + idx % m;
+      int i = perm[a], j = perm[b];
+      double2 li = L[(size_t)i * n + k], lj = L[(size_t)j * n + k];
+      double2 w = W[(size_t)i * n + j];
+      // W[i][j] -= L[i][k] conj(L[j][k])
+      w.x -= li.x * lj.x + li.y * lj.y;
+      w.y -= li.y * lj.x - li.x * lj.y;
+      W[(size_t)i * n + j] = w;
+      if (a == b) dg[i] = w.x;
+    }
+    __syncthreads();
+  }
+  const int r = rank_s;
+  // X = L1^{-1}: L1[i][m] = L[perm[i]][m] (i, m < r), lower triangular
+  for (int j = tid; j < r; j += nt) {
+    for (int i = j; i < r; ++i) {
+      double sr = (i == j) ? 1.0 : 0.0, si = 0.0;
+      const double2 *Li = L + (size_t)perm[i] * n;
+      for (int mm = j; mm < i; ++mm) {
+        double2 a = Li[mm], x = X[(size_t)mm * n + j];
+        sr -= a.x * x.x - a.y * x.y;
+        si -= a.x * x.y + a.y * x.x;
+      }
+      double2 dgl = Li[i];       // real positive pivot
+      X[(size_t)i * n + j] = make_double2(sr / dgl.x, si / dgl.x);
+    }
+  }
+  __syncthreads();
+  double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
+  double2 *Wo = reinterpret_cast<double2 *>(Wsc[prob]);
+  for (int idx = tid; idx < n * n; idx += nt) {
+    int k = idx / n, c = idx % n;
+    double2 l = L[(size_t)c * n + k];
+    Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
+    Wo[idx] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < r * r; idx += nt) {
+    int kk = idx / r, k = idx % r;     // Wsc[perm[kk]][k] = conj(X[k][kk])
+    double2 x = X[(size_t)k * n + kk];
+    Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // small kernels
 
@@ -647,12 +931,16 @@ class HipBackend : public Backend {
     }
     HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_log_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
   }
   ~HipBackend() override {
     for (auto &e : ev_)
       if (e) hipEventDestroy(e);
     if (gws_) hipFree(gws_);
     if (skws_) hipFree(skws_);
+    if (cws_) hipFree(cws_);
+    if (lws_) hipFree(lws_);
     if (own_) hipStreamDestroy(s_);
   }
   void *alloc(size_t bytes) override {
@@ -749,6 +1037,8 @@ class HipBackend : public Backend {
     if (need > skws_bytes_) {
       hipStreamSynchronize(s_);
       if (skws_) hipFree(skws_);
+    if (cws_) hipFree(cws_);
+    if (lws_) hipFree(lws_);
       skws_ = nullptr;
       skws_bytes_ = 0;
       if (hipMalloc(&skws_, need) != hipSuccess) {
@@ -795,6 +1085,24 @@ class HipBackend : public Backend {
       size_t sm = (size_t)2 * np * np * sizeof(double2);
       hipLaunchKernelGGL(eigh_jacobi_kernel<true>, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
                          evals, vecs, (double2 *)nullptr, 60);
+    } else if (np <= 128) {
+      const int sweeps = 24;
+      size_t need = (size_t)nprob * sweeps * (np - 1) * (np / 2) * sizeof(double4_t);
+      if (need > lws_bytes_) {
+        hipStreamSynchronize(s_);
+        if (lws_) hipFree(lws_);
+        lws_ = nullptr;
+        lws_bytes_ = 0;
+        if (hipMalloc(&lws_, need) != hipSuccess) {
+          err_ = -4;
+          errmsg_ = "eigh rotation log allocation failed";
+          return;
+        }
+        lws_bytes_ = need;
+      }
+      size_t sm = std::max((size_t)np * (np + 1) / 2, (size_t)64 * np) * sizeof(double2);
+      hipLaunchKernelGGL(eigh_jacobi_log_kernel, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
+                         evals, vecs, (double4_t *)lws_, sweeps);
     } else {
       size_t need = (size_t)nprob * 2 * np * np * sizeof(double2);
       if (need > gws_bytes_) {
@@ -827,6 +1135,27 @@ class HipBackend : public Backend {
                    double *const *R, double *const *W, double cut, int nprob) override {
     hipLaunchKernelGGL(gram_factor_kernel, dim3(nprob), dim3(256), 0, s_, n, r, ev, vec, R, W,
                        cut);
+    HIPCHK(hipGetLastError());
+  }
+  void gram_chol(int n, const double *const *G, double *const *R, double *const *Wsc, double cut,
+                 int nprob) override {
+    if (nprob <= 0) return;
+    size_t need = (size_t)nprob * 3 * n * n * sizeof(double2);
+    if (need > cws_bytes_) {
+      hipStreamSynchronize(s_);
+      if (cws_) hipFree(cws_);
+    if (lws_) hipFree(lws_);
+      cws_ = nullptr;
+      cws_bytes_ = 0;
+      if (hipMalloc(&cws_, need) != hipSuccess) {
+        err_ = -4;
+        errmsg_ = "Cholesky workspace allocation failed";
+        return;
+      }
+      cws_bytes_ = need;
+    }
+    hipLaunchKernelGGL(gram_chol_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, R, Wsc, cut,
+                       (double2 *)cws_);
     HIPCHK(hipGetLastError());
   }
   void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
@@ -884,6 +1213,10 @@ class HipBackend : public Backend {
   void *gws_ = nullptr;
   size_t gws_bytes_ = 0;
   hipEvent_t ev_[8] = {};
+  void *lws_ = nullptr;
+  size_t lws_bytes_ = 0;
+  void *cws_ = nullptr;
+  size_t cws_bytes_ = 0;
   void *skws_ = nullptr;
   size_t skws_bytes_ = 0;
   bool prof_ = false;
