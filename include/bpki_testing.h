@@ -44,6 +44,12 @@ int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const
 int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *evals,
                    double *vecs);
 
+/* Pivoted Cholesky factor of nprob Hermitian PSD n x n Gram matrices G (n <= 256): R [n][n]
+ * (R^H R = G, zero rows beyond the numerical rank) and Wsc [n][n] (A Wsc has orthonormal columns
+ * when G = A^H A), with pivots stopping at cut * max(diag G). */
+int bpki_test_gram_chol(bpki_ctx *ctx, int n, int nprob, const double *G, double cut, double *R,
+                        double *Wsc);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,7 @@ def load(path: str | None = None):
         "bpki_test_gemm": (C.c_int, [vp, C.POINTER(TestGemmDesc), C.c_int, dp, C.c_size_t, dp,
                                      C.c_size_t, dp, C.c_size_t]),
         "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
+        "bpki_test_gram_chol": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_double, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -118,7 +119,7 @@ def exported_symbols() -> list[str]:
             "bpki_session_bp_sweep", "bpki_session_observe_z", "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_last_timing", "bpki_session_profile",
             "bpki_session_profile_read", "bpki_test_gemm",
-            "bpki_test_eigh"]
+            "bpki_test_eigh", "bpki_test_gram_chol"]
 
 
 def _ptr(a, ct):
@@ -258,6 +259,16 @@ class Context:
             self.h, C.byref(d), nprob, A.ctypes.data_as(dp), A.size // nprob,
             B.ctypes.data_as(dp), B.size // nprob, Cm.ctypes.data_as(dp), Cm.size // nprob))
         return Cm
+
+    def test_gram_chol(self, G: np.ndarray, cut: float = 1e-15):
+        G = np.ascontiguousarray(G, dtype=np.complex128)
+        nprob, n, _ = G.shape
+        R = np.zeros((nprob, n, n), dtype=np.complex128)
+        W = np.zeros((nprob, n, n), dtype=np.complex128)
+        dp = C.POINTER(C.c_double)
+        _check(self.lib, self.lib.bpki_test_gram_chol(self.h, n, nprob, G.ctypes.data_as(dp), cut,
+                                                      R.ctypes.data_as(dp), W.ctypes.data_as(dp)))
+        return R, W
 
     def test_eigh(self, A: np.ndarray):
         A = np.ascontiguousarray(A, dtype=np.complex128)

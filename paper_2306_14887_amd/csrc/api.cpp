@@ -717,3 +717,35 @@ extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, do
   int e = be->check(&msg);
   return e ? fail(e, msg) : 0;
 }
+
+extern "C" int bpki_test_gram_chol(bpki_ctx *c, int n, int nprob, const double *G, double cut,
+                                   double *R, double *Wsc) {
+  if (!c || n < 1 || n > 256 || nprob < 1 || !(cut >= 0)) return fail(-1, "bad argument");
+  Backend *be = c->be.get();
+  std::lock_guard<std::mutex> lk(c->mu);
+  size_t nn = (size_t)n * n;
+  double *dG = (double *)be->alloc(nn * 16 * nprob);
+  double *dR = (double *)be->alloc(nn * 16 * nprob);
+  double *dW = (double *)be->alloc(nn * 16 * nprob);
+  void **ptrs = (void **)be->alloc(3 * nprob * sizeof(void *));
+  if (!dG || !dR || !dW || !ptrs) return fail(-4, "allocation failed");
+  be->h2d(dG, G, nn * 16 * nprob);
+  std::vector<void *> h(3 * nprob);
+  for (int p = 0; p < nprob; ++p) {
+    h[p] = dG + 2 * nn * p;
+    h[nprob + p] = dR + 2 * nn * p;
+    h[2 * nprob + p] = dW + 2 * nn * p;
+  }
+  be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
+  be->gram_chol(n, (const double *const *)ptrs, (double *const *)(ptrs + nprob),
+                (double *const *)(ptrs + 2 * nprob), cut, nprob);
+  be->d2h(R, dR, nn * 16 * nprob);
+  be->d2h(Wsc, dW, nn * 16 * nprob);
+  be->release(dG);
+  be->release(dR);
+  be->release(dW);
+  be->release(ptrs);
+  std::string msg;
+  int e = be->check(&msg);
+  return e ? fail(e, msg) : 0;
+}

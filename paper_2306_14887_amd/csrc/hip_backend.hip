@@ -937,10 +937,10 @@ class HipBackend : public Backend {
   ~HipBackend() override {
     for (auto &e : ev_)
       if (e) hipEventDestroy(e);
-    if (gws_) hipFree(gws_);
-    if (skws_) hipFree(skws_);
-    if (cws_) hipFree(cws_);
-    if (lws_) hipFree(lws_);
+    if (gws_) HIPCHK(hipFree(gws_));
+    if (skws_) HIPCHK(hipFree(skws_));
+    if (cws_) HIPCHK(hipFree(cws_));
+    if (lws_) HIPCHK(hipFree(lws_));
     if (own_) hipStreamDestroy(s_);
   }
   void *alloc(size_t bytes) override {
@@ -955,8 +955,8 @@ class HipBackend : public Backend {
   }
   void release(void *p) override {
     if (p) {
-      hipStreamSynchronize(s_);
-      hipFree(p);
+      HIPCHK(hipStreamSynchronize(s_));
+      HIPCHK(hipFree(p));
     }
   }
   void h2d(void *d, const void *h, size_t b) override {
@@ -978,6 +978,20 @@ class HipBackend : public Backend {
     return err_;
   }
   hipStream_t stream() const { return s_; }
+  void stale_check(const char *where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess && err_ == 0) {
+      err_ = -5;
+      errmsg_ = std::string("pending error before ") + where + ": " + hipGetErrorString(e);
+    }
+  }
+  void launch_check(const char *name) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess && err_ == 0) {
+      err_ = -5;
+      errmsg_ = std::string("launch of ") + name + ": " + hipGetErrorString(e);
+    }
+  }
   void timer_mark(int slot) override {
     if (slot < 0 || slot >= 8) return;
     if (!ev_[slot]) HIPCHK(hipEventCreate(&ev_[slot]));
@@ -1019,8 +1033,9 @@ class HipBackend : public Backend {
       if (!W) return;
       grid.y = d.batch * ksplit;
     }
+    stale_check("gemm_c64_kernel");
     hipLaunchKernelGGL(gemm_c64_kernel, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk, W);
-    HIPCHK(hipGetLastError());
+    launch_check("gemm_c64_kernel");
     if (prof_) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
@@ -1028,17 +1043,16 @@ class HipBackend : public Backend {
     }
     if (ksplit > 1) {
       int bx = std::min(64, (int)((d.M * (size_t)d.N + 255) / 256));
+      stale_check("gemm_reduce_kernel");
       hipLaunchKernelGGL(gemm_reduce_kernel, dim3(bx, d.batch, nprob), dim3(256), 0, s_, d, C,
                          ksplit, (const double2 *)W);
-      HIPCHK(hipGetLastError());
+      launch_check("gemm_reduce_kernel");
     }
   }
   void *splitk_ws(size_t need) {
     if (need > skws_bytes_) {
-      hipStreamSynchronize(s_);
-      if (skws_) hipFree(skws_);
-    if (cws_) hipFree(cws_);
-    if (lws_) hipFree(lws_);
+      HIPCHK(hipStreamSynchronize(s_));
+      if (skws_) HIPCHK(hipFree(skws_));
       skws_ = nullptr;
       skws_bytes_ = 0;
       if (hipMalloc(&skws_, need) != hipSuccess) {
@@ -1083,14 +1097,15 @@ class HipBackend : public Backend {
     int np = n + (n & 1);
     if (np <= 64) {
       size_t sm = (size_t)2 * np * np * sizeof(double2);
+      stale_check("eigh_jacobi_kernel");
       hipLaunchKernelGGL(eigh_jacobi_kernel<true>, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
                          evals, vecs, (double2 *)nullptr, 60);
     } else if (np <= 128) {
       const int sweeps = 24;
       size_t need = (size_t)nprob * sweeps * (np - 1) * (np / 2) * sizeof(double4_t);
       if (need > lws_bytes_) {
-        hipStreamSynchronize(s_);
-        if (lws_) hipFree(lws_);
+        HIPCHK(hipStreamSynchronize(s_));
+        if (lws_) HIPCHK(hipFree(lws_));
         lws_ = nullptr;
         lws_bytes_ = 0;
         if (hipMalloc(&lws_, need) != hipSuccess) {
@@ -1101,13 +1116,14 @@ class HipBackend : public Backend {
         lws_bytes_ = need;
       }
       size_t sm = std::max((size_t)np * (np + 1) / 2, (size_t)64 * np) * sizeof(double2);
+      stale_check("eigh_jacobi_log_kernel");
       hipLaunchKernelGGL(eigh_jacobi_log_kernel, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
                          evals, vecs, (double4_t *)lws_, sweeps);
     } else {
       size_t need = (size_t)nprob * 2 * np * np * sizeof(double2);
       if (need > gws_bytes_) {
-        hipStreamSynchronize(s_);
-        if (gws_) hipFree(gws_);
+        HIPCHK(hipStreamSynchronize(s_));
+        if (gws_) HIPCHK(hipFree(gws_));
         gws_ = nullptr;
         if (hipMalloc(&gws_, need) != hipSuccess) {
           err_ = -4;
@@ -1117,34 +1133,37 @@ class HipBackend : public Backend {
         }
         gws_bytes_ = need;
       }
+      stale_check("eigh_jacobi_kernel");
       hipLaunchKernelGGL(eigh_jacobi_kernel<false>, dim3(nprob), dim3(1024), 0, s_, n, lda, in,
                          evals, vecs, (double2 *)gws_, 60);
     }
-    HIPCHK(hipGetLastError());
+    launch_check("eigh_jacobi_kernel");
   }
   void rx(double *const *t, const int64_t *half, int nprob, double c, double s) override {
+    stale_check("rx_kernel");
     hipLaunchKernelGGL(rx_kernel, dim3(64, nprob), dim3(256), 0, s_, t, half, c, s);
-    HIPCHK(hipGetLastError());
+    launch_check("rx_kernel");
   }
   void msg_sqrt(int n, const double *const *ev, const double *const *vec, double *const *X,
                 double *const *Xp, double cut, int nprob) override {
+    stale_check("msg_sqrt_kernel");
     hipLaunchKernelGGL(msg_sqrt_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, X, Xp, cut);
-    HIPCHK(hipGetLastError());
+    launch_check("msg_sqrt_kernel");
   }
   void gram_factor(int n, int r, const double *const *ev, const double *const *vec,
                    double *const *R, double *const *W, double cut, int nprob) override {
+    stale_check("gram_factor_kernel");
     hipLaunchKernelGGL(gram_factor_kernel, dim3(nprob), dim3(256), 0, s_, n, r, ev, vec, R, W,
                        cut);
-    HIPCHK(hipGetLastError());
+    launch_check("gram_factor_kernel");
   }
   void gram_chol(int n, const double *const *G, double *const *R, double *const *Wsc, double cut,
                  int nprob) override {
     if (nprob <= 0) return;
     size_t need = (size_t)nprob * 3 * n * n * sizeof(double2);
     if (need > cws_bytes_) {
-      hipStreamSynchronize(s_);
-      if (cws_) hipFree(cws_);
-    if (lws_) hipFree(lws_);
+      HIPCHK(hipStreamSynchronize(s_));
+      if (cws_) HIPCHK(hipFree(cws_));
       cws_ = nullptr;
       cws_bytes_ = 0;
       if (hipMalloc(&cws_, need) != hipSuccess) {
@@ -1154,53 +1173,61 @@ class HipBackend : public Backend {
       }
       cws_bytes_ = need;
     }
+    stale_check("gram_chol_kernel");
     hipLaunchKernelGGL(gram_chol_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, R, Wsc, cut,
                        (double2 *)cws_);
-    HIPCHK(hipGetLastError());
+    launch_check("gram_chol_kernel");
   }
   void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
              double *const *Th, double a, double b, double c, double d, int nprob) override {
     int tot = 4 * rB * rS;
     int bx = std::min(1024, (tot + 255) / 256);
+    stale_check("theta_kernel");
     hipLaunchKernelGGL(theta_kernel, dim3(bx, nprob), dim3(256), 0, s_, rB, rS, chi, RB, RS, Th,
                        a, b, c, d);
-    HIPCHK(hipGetLastError());
+    launch_check("theta_kernel");
   }
   void svd_finish(int n, int chi, const double *const *ev, const double *const *vec,
                   double *const *Vs, double *const *S, int *kout, double *disc,
                   double *const *mA, double *const *mB, double cutoff, int nprob) override {
+    stale_check("svd_finish_kernel");
     hipLaunchKernelGGL(svd_finish_kernel, dim3(nprob), dim3(256), 0, s_, n, chi, ev, vec, Vs, S,
                        kout, disc, mA, mB, cutoff);
-    HIPCHK(hipGetLastError());
+    launch_check("svd_finish_kernel");
   }
   void split_sqrt(int rowsB, int rowsS, int n, int chi, const double *const *U,
                   const double *const *V, const double *const *S, double *const *RBn,
                   double *const *RSn, int nprob) override {
     int tot = (rowsB + rowsS) * chi;
     int bx = std::min(1024, (tot + 255) / 256);
+    stale_check("split_sqrt_kernel");
     hipLaunchKernelGGL(split_sqrt_kernel, dim3(bx, nprob), dim3(256), 0, s_, rowsB, rowsS, n,
                        chi, U, V, S, RBn, RSn);
-    HIPCHK(hipGetLastError());
+    launch_check("split_sqrt_kernel");
   }
   void normalize_residual(int chi, double *const *Mn, const double *const *Mo, double *res,
                           int nprob) override {
+    stale_check("normalize_residual_kernel");
     hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(256), 0, s_, chi, Mn, Mo,
                        res);
-    HIPCHK(hipGetLastError());
+    launch_check("normalize_residual_kernel");
   }
   void reduce_max(const double *x, int n, double *out) override {
+    stale_check("reduce_max_kernel");
     hipLaunchKernelGGL(reduce_max_kernel, dim3(1), dim3(256), 0, s_, x, n, out);
-    HIPCHK(hipGetLastError());
+    launch_check("reduce_max_kernel");
   }
   void rho_dot(const double *const *Y, const double *const *T, const int64_t *len, double *rho,
                int nprob) override {
+    stale_check("rho_dot_kernel");
     hipLaunchKernelGGL(rho_dot_kernel, dim3(nprob), dim3(256), 0, s_, Y, T, len, rho);
-    HIPCHK(hipGetLastError());
+    launch_check("rho_dot_kernel");
   }
   void apply_op(const double *const *Tin, double *const *Tout, const int64_t *half,
                 const double *ops, int nprob) override {
+    stale_check("apply_op_kernel");
     hipLaunchKernelGGL(apply_op_kernel, dim3(64, nprob), dim3(256), 0, s_, Tin, Tout, half, ops);
-    HIPCHK(hipGetLastError());
+    launch_check("apply_op_kernel");
   }
 
   int err_ = 0;

@@ -121,3 +121,24 @@ def test_eigh_matches_numpy(ctx, n):
         # eigenvectors: orthonormal and A V = V diag(ev)
         assert np.abs(V[p].conj().T @ V[p] - np.eye(n)).max() < 1e-12 * max(1, n / 16)
         assert np.abs(A[p] @ V[p] - V[p] * ev[p][None, :]).max() < 1e-12 * scale * max(1, n / 16)
+
+
+@pytest.mark.parametrize("n,rank", [(8, 8), (16, 5), (128, 128), (128, 70), (256, 200)])
+def test_gram_chol(ctx, n, rank):
+    """Pivoted Cholesky of A^H A: R^H R = G, and Q = A Wsc is an isometry on the range."""
+    print(f"[gram_chol] n={n} rank={rank}", flush=True)
+    rng = np.random.default_rng(n + rank)
+    nprob = 2
+    A = _rand(rng, nprob, 3 * n, rank) @ (_rand(rng, nprob, rank, n) * np.logspace(0, -4, n)[None, None, :])
+    G = A.conj().transpose(0, 2, 1) @ A
+    R, W = ctx.test_gram_chol(G, 1e-15)
+    for p in range(nprob):
+        scale = np.abs(G[p]).max()
+        assert np.abs(R[p].conj().T @ R[p] - G[p]).max() < 1e-12 * scale
+        Q = A[p] @ W[p]
+        QQ = Q.conj().T @ Q
+        r = int(np.count_nonzero(np.abs(np.diag(QQ)) > 0.5))
+        assert r == rank
+        idx = np.nonzero(np.abs(np.diag(QQ)) > 0.5)[0]
+        assert np.abs(QQ[np.ix_(idx, idx)] - np.eye(r)).max() < 1e-6
+        assert np.abs(Q @ R[p] - A[p]).max() < 1e-8 * np.abs(A[p]).max()
