@@ -242,6 +242,19 @@ __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
+// Sum of one value per thread over the whole block; every thread gets the result.
+__device__ double block_allsum(double v, double *sh /* >= 16 */) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
 // Round-robin pairing (circle method) for np even, m = np-1 odd.
 __device__ __forceinline__ void pair_of(int r, int i, int np, int &p, int &q) {
   int m = np - 1;
@@ -259,6 +272,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
   __shared__ Rot rot[128];
   __shared__ int any_rot;
   __shared__ double diag_s[256];
+  __shared__ double red_s[16];
   const int prob = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int np = n + (n & 1);
@@ -267,6 +281,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
   if (LDS) { A = smem; V = smem + (size_t)np * np; }
   else { A = gws + (size_t)prob * 2 * np * np; V = A + (size_t)np * np; }
   const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+  double fro2 = 0.0;
   for (int idx = tid; idx < np * np; idx += nt) {
     int i = idx / np, j = idx % np;
     double2 v = make_double2(0.0, 0.0);
@@ -276,9 +291,12 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
     }
     A[idx] = v;
     V[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    fro2 += v.x * v.x + v.y * v.y;
   }
   __syncthreads();
   const double eps = 2.220446049250313e-16;
+  // couplings below 0.1 eps ||A||_F are at the rounding level of A and are not rotated
+  const double thr_abs = 0.1 * eps * sqrt(block_allsum(fro2, red_s));
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
     __syncthreads();
@@ -291,7 +309,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
         double beta = sqrt(b.x * b.x + b.y * b.y);
         Rot R;
         R.p = p; R.q = q;
-        if (beta > 1e-300 && beta > eps * sqrt(fabs(a) * fabs(dd))) {
+        if (beta > 1e-300 && beta > thr_abs && beta > eps * sqrt(fabs(a) * fabs(dd))) {
           double tau = (dd - a) / (2.0 * beta);
           double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           double c = 1.0 / sqrt(1.0 + t * t);
@@ -389,6 +407,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
   __shared__ Rot rot[64];
   __shared__ int any_rot, nrounds_s;
   __shared__ double diag_s[128];
+  __shared__ double red_s[16];
   const int prob = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int np = n + (n & 1);
@@ -396,6 +415,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
   double2 *P = smem;
   double4_t *lg = logbuf + (size_t)prob * max_sweeps * (np - 1) * h;
   const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+  double fro2 = 0.0;
   for (int idx = tid; idx < np * (np + 1) / 2; idx += nt) {
     int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
     while ((size_t)i * (i + 1) / 2 > (size_t)idx) --i;
@@ -407,10 +427,23 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
       v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
     }
     P[idx] = v;
+    fro2 += (i == j ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
   }
   if (tid == 0) nrounds_s = 0;
   __syncthreads();
   const double eps = 2.220446049250313e-16;
+  const double thr_abs = 0.1 * eps * sqrt(block_allsum(fro2, red_s));
+  // this thread's 2x2 blocks (I >= J) are the same in every round
+  const int nblk = h * (h + 1) / 2;
+  int bI[3], bJ[3];
+  int nmine = 0;
+  for (int blk = tid; blk < nblk && nmine < 3; blk += nt, ++nmine) {
+    int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > blk) --I;
+    while ((I + 1) * (I + 2) / 2 <= blk) ++I;
+    bI[nmine] = I;
+    bJ[nmine] = blk - I * (I + 1) / 2;
+  }
   int nrounds = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (tid == 0) any_rot = 0;
@@ -424,7 +457,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
         double beta = sqrt(b.x * b.x + b.y * b.y);
         Rot R;
         R.p = p; R.q = q;
-        if (beta > 1e-300 && beta > eps * sqrt(fabs(a) * fabs(dd))) {
+        if (beta > 1e-300 && beta > thr_abs && beta > eps * sqrt(fabs(a) * fabs(dd))) {
           double tau = (dd - a) / (2.0 * beta);
           double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           double c = 1.0 / sqrt(1.0 + t * t);
@@ -439,12 +472,8 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
       }
       __syncthreads();
       // blocks (I, J) with I >= J cover every unordered element pair once
-      const int nblk = h * (h + 1) / 2;
-      for (int blk = tid; blk < nblk; blk += nt) {
-        int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-        while (I * (I + 1) / 2 > blk) --I;
-        while ((I + 1) * (I + 2) / 2 <= blk) ++I;
-        int J = blk - I * (I + 1) / 2;
+      for (int mb = 0; mb < nmine; ++mb) {
+        const int I = bI[mb], J = bJ[mb];
         Rot ri = rot[I], rj = rot[J];
         if (ri.s == 0.0 && rj.s == 0.0) continue;
         double2 w_j = make_double2(rj.wr, rj.wi), w_i_c = make_double2(ri.wr, -ri.wi);
