@@ -402,7 +402,9 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
                                                                double *const *evals,
                                                                double *const *vecs,
                                                                double4_t *logbuf,
-                                                               int max_sweeps) {
+                                                               int max_sweeps,
+                                                               double *meta_diag,
+                                                               int *meta_rounds) {
   extern __shared__ double2 smem[];
   __shared__ Rot rot[64];
   __shared__ int any_rot, nrounds_s;
@@ -476,19 +478,21 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
         const int I = bI[mb], J = bJ[mb];
         Rot ri = rot[I], rj = rot[J];
         if (ri.s == 0.0 && rj.s == 0.0) continue;
-        double2 w_j = make_double2(rj.wr, rj.wi), w_i_c = make_double2(ri.wr, -ri.wi);
         double2 b00 = pk_get(P, ri.p, rj.p), b01 = pk_get(P, ri.p, rj.q);
         double2 b10 = pk_get(P, ri.q, rj.p), b11 = pk_get(P, ri.q, rj.q);
-        double2 sw = cscale(rj.s, w_j), cw = cscale(rj.c, w_j);
-        double2 t00 = cadd(cscale(rj.c, b00), cscale(-1.0, cmul(sw, b01)));
-        double2 t10 = cadd(cscale(rj.c, b10), cscale(-1.0, cmul(sw, b11)));
-        double2 t01 = cadd(cscale(rj.s, b00), cmul(cw, b01));
-        double2 t11 = cadd(cscale(rj.s, b10), cmul(cw, b11));
-        double2 swc = cscale(ri.s, w_i_c), cwc = cscale(ri.c, w_i_c);
-        double2 n00 = cadd(cscale(ri.c, t00), cscale(-1.0, cmul(swc, t10)));
-        double2 n01 = cadd(cscale(ri.c, t01), cscale(-1.0, cmul(swc, t11)));
-        double2 n10 = cadd(cscale(ri.s, t00), cmul(cwc, t10));
-        double2 n11 = cadd(cscale(ri.s, t01), cmul(cwc, t11));
+        // J = diag(1, w) R with R real: apply the phases, then the two real rotations
+        const double2 wj = make_double2(rj.wr, rj.wi), wic = make_double2(ri.wr, -ri.wi);
+        b01 = cmul(b01, wj);
+        b10 = cmul(wic, b10);
+        b11 = cmul(cmul(wic, b11), wj);
+        double2 t00 = make_double2(rj.c * b00.x - rj.s * b01.x, rj.c * b00.y - rj.s * b01.y);
+        double2 t01 = make_double2(rj.s * b00.x + rj.c * b01.x, rj.s * b00.y + rj.c * b01.y);
+        double2 t10 = make_double2(rj.c * b10.x - rj.s * b11.x, rj.c * b10.y - rj.s * b11.y);
+        double2 t11 = make_double2(rj.s * b10.x + rj.c * b11.x, rj.s * b10.y + rj.c * b11.y);
+        double2 n00 = make_double2(ri.c * t00.x - ri.s * t10.x, ri.c * t00.y - ri.s * t10.y);
+        double2 n01 = make_double2(ri.c * t01.x - ri.s * t11.x, ri.c * t01.y - ri.s * t11.y);
+        double2 n10 = make_double2(ri.s * t00.x + ri.c * t10.x, ri.s * t00.y + ri.c * t10.y);
+        double2 n11 = make_double2(ri.s * t01.x + ri.c * t11.x, ri.s * t01.y + ri.c * t11.y);
         if (I == J) {
           n00.y = 0.0; n11.y = 0.0;
           if (ri.s != 0.0) n10 = make_double2(0.0, 0.0);
@@ -510,52 +514,61 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
     __syncthreads();
     if (stop) break;
   }
-  for (int i = tid; i < n; i += nt) diag_s[i] = P[pk_idx(i, i)].x;
-  __threadfence();
+  for (int i = tid; i < np; i += nt) meta_diag[(size_t)prob * np + i] = P[pk_idx(i, i)].x;
+  if (tid == 0) meta_rounds[prob] = nrounds;
+}
+
+// Rebuilds the eigenvectors from the rotation log: rows of V evolve independently under the
+// right-multiplied rotations, so each workgroup replays the whole log on 16 rows held in LDS.
+// grid: x = row blocks of 16, y = problem.  Also sorts into descending eigenvalue order.
+__global__ __launch_bounds__(256) void eigh_replay_kernel(int n, const double4_t *logbuf,
+                                                          int max_sweeps,
+                                                          const double *meta_diag,
+                                                          const int *meta_rounds,
+                                                          double *const *evals,
+                                                          double *const *vecs) {
+  __shared__ double2 Vb[16 * 128];
+  __shared__ double dg[128];
+  const int prob = blockIdx.y, r0 = blockIdx.x * 16;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int np = n + (n & 1), h = np / 2;
+  const double4_t *lg = logbuf + (size_t)prob * max_sweeps * (np - 1) * h;
+  const int nrounds = meta_rounds[prob];
+  const int rows = min(16, np - r0);
+  for (int i = tid; i < np; i += nt) dg[i] = meta_diag[(size_t)prob * np + i];
+  for (int idx = tid; idx < rows * np; idx += nt) {
+    int rr = idx / np, c = idx % np;
+    Vb[idx] = make_double2((r0 + rr) == c ? 1.0 : 0.0, 0.0);
+  }
   __syncthreads();
-  // rebuild V by replaying the rotation log on 64-row blocks of V held in LDS
+  for (int t = 0; t < nrounds; ++t) {
+    const int rr0 = t % (np - 1);
+    const double4_t *lr = lg + (size_t)t * h;
+    for (int it = tid; it < rows * h; it += nt) {
+      int rr = it / h, J = it % h;
+      double4_t R = lr[J];
+      if (R[1] == 0.0) continue;
+      int p, q;
+      pair_of(rr0, J, np, p, q);
+      double2 vp = Vb[rr * np + p];
+      double2 vq = cmul(make_double2(R[2], R[3]), Vb[rr * np + q]);
+      Vb[rr * np + p] = make_double2(R[0] * vp.x - R[1] * vq.x, R[0] * vp.y - R[1] * vq.y);
+      Vb[rr * np + q] = make_double2(R[1] * vp.x + R[0] * vq.x, R[1] * vp.y + R[0] * vq.y);
+    }
+    __syncthreads();
+  }
   double *ev = evals[prob];
   double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
-  double2 *Vb = smem;
-  for (int r0 = 0; r0 < np; r0 += 64) {
-    const int rows = min(64, np - r0);
-    for (int idx = tid; idx < rows * np; idx += nt) {
-      int rr = idx / np, c = idx % np;
-      Vb[idx] = make_double2((r0 + rr) == c ? 1.0 : 0.0, 0.0);
+  for (int i = tid; i < n; i += nt) {
+    double li = dg[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double lj = dg[j];
+      rank += (lj > li) || (lj == li && j < i);
     }
-    __syncthreads();
-    for (int t = 0; t < nrounds; ++t) {
-      const int rr0 = t % (np - 1);
-      const double4_t *lr = lg + (size_t)t * h;
-      for (int it = tid; it < rows * h; it += nt) {
-        int rr = it / h, J = it % h;
-        double4_t R = lr[J];
-        if (R[1] == 0.0) continue;
-        int p, q;
-        pair_of(rr0, J, np, p, q);
-        double2 w = make_double2(R[2], R[3]);
-        double2 vp = Vb[rr * np + p], vq = Vb[rr * np + q];
-        double2 sw = cscale(R[1], w), cw = cscale(R[0], w);
-        Vb[rr * np + p] = cadd(cscale(R[0], vp), cscale(-1.0, cmul(sw, vq)));
-        Vb[rr * np + q] = cadd(cscale(R[1], vp), cmul(cw, vq));
-      }
-      __syncthreads();
-    }
-    // write the rows of this block, columns permuted into descending eigenvalue order
-    for (int idx = tid; idx < rows * n; idx += nt) {
-      int rr = idx / n, i = idx % n;
-      int row = r0 + rr;
-      if (row >= n) continue;
-      double li = diag_s[i];
-      int rank = 0;
-      for (int j = 0; j < n; ++j) {
-        double lj = diag_s[j];
-        rank += (lj > li) || (lj == li && j < i);
-      }
-      vo[(size_t)row * n + rank] = Vb[rr * np + i];
-      if (row == 0) ev[rank] = li;
-    }
-    __syncthreads();
+    for (int rr = 0; rr < rows; ++rr)
+      if (r0 + rr < n) vo[(size_t)(r0 + rr) * n + rank] = Vb[rr * np + i];
+    if (blockIdx.x == 0) ev[rank] = li;
   }
 }
 
@@ -1131,7 +1144,8 @@ class HipBackend : public Backend {
                          evals, vecs, (double2 *)nullptr, 60);
     } else if (np <= 128) {
       const int sweeps = 24;
-      size_t need = (size_t)nprob * sweeps * (np - 1) * (np / 2) * sizeof(double4_t);
+      size_t logb = (size_t)nprob * sweeps * (np - 1) * (np / 2) * sizeof(double4_t);
+      size_t need = logb + (size_t)nprob * np * sizeof(double) + (size_t)nprob * sizeof(int);
       if (need > lws_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
         if (lws_) HIPCHK(hipFree(lws_));
@@ -1146,8 +1160,15 @@ class HipBackend : public Backend {
       }
       size_t sm = std::max((size_t)np * (np + 1) / 2, (size_t)64 * np) * sizeof(double2);
       stale_check("eigh_jacobi_log_kernel");
+      double *mdiag = (double *)((char *)lws_ + logb);
+      int *mrounds = (int *)(mdiag + (size_t)nprob * np);
       hipLaunchKernelGGL(eigh_jacobi_log_kernel, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
-                         evals, vecs, (double4_t *)lws_, sweeps);
+                         evals, vecs, (double4_t *)lws_, sweeps, mdiag, mrounds);
+      launch_check("eigh_jacobi_log_kernel");
+      stale_check("eigh_replay_kernel");
+      hipLaunchKernelGGL(eigh_replay_kernel, dim3((np + 15) / 16, nprob), dim3(256), 0, s_, n,
+                         (const double4_t *)lws_, sweeps, (const double *)mdiag,
+                         (const int *)mrounds, evals, vecs);
     } else {
       size_t need = (size_t)nprob * 2 * np * np * sizeof(double2);
       if (need > gws_bytes_) {
