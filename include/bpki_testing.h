@@ -32,6 +32,7 @@ typedef struct {
   int64_t a_b, b_b, c_b;
   int32_t batch, conjA, conjB, beta;
   double alpha_re, alpha_im;
+  int32_t prec;      /* 0: FP64 MFMA; 1: operands rounded to FP32, FP32 MFMA, FP64 output */
 } bpki_test_gemm_desc;
 
 /* Runs the FP64 MFMA GEMM on nprob problems; problem p uses A + 2*a_elems*p etc.  C is read

@@ -275,7 +275,6 @@ extern "C" int bpki_solve(bpki_ctx *c, const bpki_problem *p, bpki_result *r) {
   if (!c || !r) return fail(-1, "NULL context or result");
   int rc = bpki_validate(p);
   if (rc) return rc;
-  if (p->precision != BPKI_FP64) return fail(-1, "precision mode not available in this build");
   Problem q = to_problem(p);
   size_t need = Engine::estimate_bytes(q);
   if (c->budget && need > c->budget) return fail(-4, "problem exceeds the memory budget");
@@ -300,7 +299,6 @@ extern "C" int bpki_session_open(bpki_ctx *c, const bpki_problem *p, bpki_sessio
   if (!c || !out) return fail(-1, "NULL argument");
   int rc = bpki_validate(p);
   if (rc) return rc;
-  if (p->precision != BPKI_FP64) return fail(-1, "precision mode not available in this build");
   Problem q = to_problem(p);
   size_t need = Engine::estimate_bytes(q);
   if (c->budget && need > c->budget) return fail(-4, "problem exceeds the memory budget");
@@ -467,7 +465,6 @@ extern "C" int bpki_submit(bpki_ctx *c, const bpki_problem *p, bpki_result *r, u
   if (!c || !r || !ticket) return fail(-1, "NULL argument");
   int rc = bpki_validate(p);
   if (rc) return rc;
-  if (p->precision != BPKI_FP64) return fail(-1, "precision mode not available in this build");
   auto job = std::make_shared<bpki_ctx::Job>();
   job->q = to_problem(p);
   job->r = r;
@@ -638,6 +635,8 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
   d.a_b = td->a_b; d.b_b = td->b_b; d.c_b = td->c_b; d.batch = td->batch;
   d.conjA = td->conjA; d.conjB = td->conjB; d.beta = td->beta;
   d.alpha_re = td->alpha_re; d.alpha_im = td->alpha_im;
+  d.prec = td->prec;
+  if (d.prec != 0 && d.prec != 1) return fail(-1, "prec must be 0 (FP64) or 1 (FP32)");
   if (d.M < 1 || d.N < 1 || d.K < 1 || d.Mi < 1 || d.Ni < 1 || d.Ki < 1 || d.batch < 1 ||
       d.M % d.Mi || d.N % d.Ni || d.K % d.Ki)
     return fail(-1, "inconsistent descriptor");

@@ -27,6 +27,7 @@ struct GemmDesc {
   int conjA = 0, conjB = 0;
   int beta = 0;                          // 1: accumulate into C
   double alpha_re = 1.0, alpha_im = 0.0;
+  int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA (FP64 storage)
 };
 
 // Simple composite-index helpers for descriptors.

@@ -777,9 +777,11 @@ void Engine::reset() {
   std::fill(P.bond_h.begin(), P.bond_h.end(), 1);
 }
 
-static void run(Backend *be, const PtrArena &ar, const GemmOp &op) {
+static void run(Backend *be, const PtrArena &ar, const GemmOp &op, int prec) {
   if (op.n == 0) return;
-  be->gemm(op.d, ar.at<const double *const *>(op.a), ar.at<const double *const *>(op.b),
+  GemmDesc d = op.d;
+  d.prec = prec;
+  be->gemm(d, ar.at<const double *const *>(op.a), ar.at<const double *const *>(op.b),
            ar.at<double *const *>(op.c), op.n);
 }
 
@@ -806,13 +808,13 @@ double Engine::apply_layer(int colour) {
   }
   // 2. absorb
   for (auto &t : LP.d2d_in) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
-  for (auto &op : LP.absorb) run(be_, ar, op);
+  for (auto &op : LP.absorb) run(be_, ar, op, prob_.precision);
   // 3. isolate degree-3 endpoints
   if (LP.n_g) {
-    run(be_, ar, LP.gram);
+    run(be_, ar, LP.gram, prob_.precision);
     be_->gram_chol(2 * chi, ar.at<const double *const *>(LP.g_in), ar.at<double *const *>(LP.g_R),
                    ar.at<double *const *>(LP.g_Wsc), kGramCut, LP.n_g);
-    run(be_, ar, LP.qform);
+    run(be_, ar, LP.qform, prob_.precision);
   }
   // 4-6. Theta, truncated SVD, new factors
   const double q = M_PI / 4;
@@ -820,7 +822,7 @@ double Engine::apply_layer(int colour) {
     be_->theta(T.rB, T.rS, chi, ar.at<const double *const *>(T.RB),
                ar.at<const double *const *>(T.RS), ar.at<double *const *>(T.Th), std::cos(q),
                std::sin(q), std::cos(q), -std::sin(q), T.count);
-    run(be_, ar, T.hgemm);
+    run(be_, ar, T.hgemm, 0);        // the truncation SVD is FP64 in every mode
     be_->eigh(T.n, T.n, ar.at<const double *const *>(T.hgemm.c), ar.at<double *const *>(T.ev),
               ar.at<double *const *>(T.vec), T.count);
     be_->svd_finish(T.n, chi, ar.at<const double *const *>(T.ev),
@@ -828,15 +830,15 @@ double Engine::apply_layer(int colour) {
                     ar.at<double *const *>(T.S), P.kbuf + T.slot0, P.disc + T.slot0,
                     ar.at<double *const *>(T.mA), ar.at<double *const *>(T.mB), prob_.svd_cutoff,
                     T.count);
-    run(be_, ar, T.ugemm);
+    run(be_, ar, T.ugemm, 0);
     be_->split_sqrt(2 * T.rB, 2 * T.rS, T.n, chi, ar.at<const double *const *>(T.U),
                     ar.at<const double *const *>(T.vec), ar.at<const double *const *>(T.S),
                     ar.at<double *const *>(T.RBn), ar.at<double *const *>(T.RSn), T.count);
   }
   // 7. rebuild and remove the environment
-  if (LP.n_g) run(be_, ar, LP.rebuild);
+  if (LP.n_g) run(be_, ar, LP.rebuild, prob_.precision);
   // degree <= 2: T~' = R' (already in A-layout); point remove ops at R' directly
-  for (auto &op : LP.remove) run(be_, ar, op);
+  for (auto &op : LP.remove) run(be_, ar, op, prob_.precision);
   for (auto &t : LP.d2d_out) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
   // bookkeeping: discarded weight and bond dimensions
   int ne = (int)LP.edges.size();
@@ -854,7 +856,7 @@ double Engine::apply_layer(int colour) {
 
 double Engine::bp_sweep() {
   Plan &P = *plan_;
-  for (auto &op : P.bp_ops) run(be_, P.arena, op);
+  for (auto &op : P.bp_ops) run(be_, P.arena, op, prob_.precision);
   be_->normalize_residual(P.chi, P.arena.at<double *const *>(P.bp_norm_new),
                           P.arena.at<const double *const *>(P.bp_norm_old), P.res, 2 * P.E);
   be_->reduce_max(P.res, 2 * P.E, P.resmax);
@@ -878,7 +880,7 @@ int Engine::bp(int max_iter, double *residual) {
 
 void Engine::observe_z(double *z) {
   Plan &P = *plan_;
-  for (auto &op : P.obs_ops) run(be_, P.arena, op);
+  for (auto &op : P.obs_ops) run(be_, P.arena, op, prob_.precision);
   be_->rho_dot(P.arena.at<const double *const *>(P.obs_Y),
                P.arena.at<const double *const *>(P.obs_T), P.rho_len, P.rho, P.n);
   std::vector<double> rho((size_t)P.n * 8);
@@ -920,7 +922,9 @@ double Engine::pauli_value(int k, bool with_ops) {
   // pointer arrays for single-problem launches
   void **parr = (void **)be_->alloc(3 * sizeof(void *));
   tmp.push_back(parr);
-  auto gemm1 = [&](const GemmDesc &d, const double *a, const double *b, double *c) {
+  auto gemm1 = [&](const GemmDesc &d0, const double *a, const double *b, double *c) {
+    GemmDesc d = d0;
+    d.prec = prob_.precision;
     const void *h[3] = {a, b, c};
     be_->h2d(parr, h, sizeof(h));
     be_->gemm(d, (const double *const *)parr, (const double *const *)(parr + 1),

@@ -1,6 +1,7 @@
 // HIP/CDNA4 (gfx950) kernels and the device backend of the bpki engine.
 //
-//  * gemm_c64   : grouped, batched complex FP64 GEMM on MFMA (v_mfma_f64_16x16x4f64).  Complex
+//  * gemm_kernel: grouped, batched complex GEMM on MFMA (FP64: v_mfma_f64_16x16x4f64; FP32 mode:
+//                 v_mfma_f32_16x16x4f32 with FP64 storage and FP64 split-K sums).  Complex
 //                 products in real-split form: four real MFMA accumulators per 16x16 tile
 //                 (re*re, im*im, re*im, im*re), combined in the epilogue.  Operands are staged
 //                 through LDS in split re/im planes; the global loads follow whichever index is
@@ -26,6 +27,7 @@
 namespace bpki {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
 #define HIPCHK(x)                                                                    \
   do {                                                                               \
@@ -67,12 +69,39 @@ __device__ __forceinline__ KOff k_tile(int k0, int Ki, long so, long si) {
 // Grouped complex GEMM.  grid: x = output tiles, y = batch * ksplit, z = problem.  With
 // ksplit > 1 each block sums its K chunk into the partial buffer W (layout
 // [prob][batch][kz][M][N]); gemm_reduce_kernel then combines the chunks in a fixed order.
-__global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const double *const *Ap,
-                                                          const double *const *Bp,
-                                                          double *const *Cp, int ksplit,
-                                                          int kchunk, double2 *W) {
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+// T = double: FP64 MFMA (v_mfma_f64_16x16x4f64); T = float: operands rounded to FP32 when
+// staged, FP32 MFMA (v_mfma_f32_16x16x4f32) with FP32 accumulation over the block's K range.
+// Storage and the split-K chunk sums stay FP64.
+template <typename T>
+struct MfmaTraits;
+template <>
+struct MfmaTraits<double> {
+  typedef double4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // result layout: lane l, register r -> row l/16 + 4 r, column l % 16
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct MfmaTraits<float> {
+  typedef float4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // result layout: lane l, register r -> row 4 (l/16) + r, column l % 16
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *const *Ap,
+                                                      const double *const *Bp,
+                                                      double *const *Cp, int ksplit,
+                                                      int kchunk, double2 *W) {
+  typedef MfmaTraits<T> MT;
+  typedef typename MT::acc_t acc_t;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -86,7 +115,7 @@ __global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const doub
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const bool a_mfast = (d.a_mi == 1);
   const bool b_nfast = (d.b_ni == 1);
-  const double sa = d.conjA ? -1.0 : 1.0, sb = d.conjB ? -1.0 : 1.0;
+  const T sa = d.conjA ? T(-1) : T(1), sb = d.conjB ? T(-1) : T(1);
 
   // per-thread staging coordinates and the M / N parts of their offsets (fixed over K)
   int am[LOADS], ak[LOADS], bn[LOADS], bk[LOADS];
@@ -125,20 +154,20 @@ __global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const doub
   auto stage = [&]() {
 #pragma unroll
     for (int it = 0; it < LOADS; ++it) {
-      As[0][ak[it]][am[it]] = ra[it].x;
-      As[1][ak[it]][am[it]] = sa * ra[it].y;
-      Bs[0][bk[it]][bn[it]] = rb[it].x;
-      Bs[1][bk[it]][bn[it]] = sb * rb[it].y;
+      As[0][ak[it]][am[it]] = T(ra[it].x);
+      As[1][ak[it]][am[it]] = sa * T(ra[it].y);
+      Bs[0][bk[it]][bn[it]] = T(rb[it].x);
+      Bs[1][bk[it]][bn[it]] = sb * T(rb[it].y);
     }
   };
 
-  double4_t acc[2][2][4];
+  acc_t acc[2][2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[i][j][t] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < 4; ++t) acc[i][j][t] = (acc_t){T(0), T(0), T(0), T(0)};
 
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -148,7 +177,7 @@ __global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const doub
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      double ar[2], ai[2], br[2], bi[2];
+      T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         ar[t] = As[0][kr][wm + t * 16 + (lane & 15)];
@@ -160,15 +189,15 @@ __global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const doub
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], acc[i][j][1], 0, 0, 0);
-          acc[i][j][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc[i][j][2], 0, 0, 0);
-          acc[i][j][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc[i][j][3], 0, 0, 0);
+          acc[i][j][0] = MT::mma(ar[i], br[j], acc[i][j][0]);
+          acc[i][j][1] = MT::mma(ai[i], bi[j], acc[i][j][1]);
+          acc[i][j][2] = MT::mma(ar[i], bi[j], acc[i][j][2]);
+          acc[i][j][3] = MT::mma(ai[i], br[j], acc[i][j][3]);
         }
     }
     __syncthreads();
   }
-  // ---- epilogue: D layout of 16x16x4 f64: lane l, reg r -> row l/16 + 4*r, col l%16 ----
+  // ---- epilogue ----
   double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
   double2 *Wp = W ? W + (((size_t)prob * d.batch + bat) * ksplit + kz) * (size_t)d.M * d.N
                   : nullptr;
@@ -178,11 +207,11 @@ __global__ __launch_bounds__(256, 2) void gemm_c64_kernel(GemmDesc d, const doub
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int mg = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        int mg = m0 + wm + i * 16 + MT::row(lane, r);
         int ng = n0 + wn + j * 16 + (lane & 15);
         if (mg >= d.M || ng >= d.N) continue;
-        double cr = acc[i][j][0][r] - acc[i][j][1][r];
-        double ci = acc[i][j][2][r] + acc[i][j][3][r];
+        double cr = (double)acc[i][j][0][r] - (double)acc[i][j][1][r];
+        double ci = (double)acc[i][j][2][r] + (double)acc[i][j][3][r];
         if (Wp) {
           Wp[(size_t)mg * d.N + ng] = make_double2(cr, ci);
           continue;
@@ -1075,9 +1104,17 @@ class HipBackend : public Backend {
       if (!W) return;
       grid.y = d.batch * ksplit;
     }
-    stale_check("gemm_c64_kernel");
-    hipLaunchKernelGGL(gemm_c64_kernel, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk, W);
-    launch_check("gemm_c64_kernel");
+    if (d.prec == 1) {
+      stale_check("gemm_kernel<float>");
+      hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk,
+                         W);
+      launch_check("gemm_kernel<float>");
+    } else {
+      stale_check("gemm_kernel<double>");
+      hipLaunchKernelGGL(gemm_kernel<double>, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk,
+                         W);
+      launch_check("gemm_kernel<double>");
+    }
     if (prof_) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});

@@ -81,6 +81,24 @@ def _extent(d, pre):
 
 
 @pytest.mark.parametrize("name,desc,nprob", CASES, ids=[c[0] for c in CASES])
+def test_gemm_fp32_mode(ctx, name, desc, nprob):
+    """FP32 MFMA mode: operands rounded to FP32, FP32 accumulation per K chunk; the error is at
+    FP32 level relative to the operand scale."""
+    print(f"[gemm fp32] case {name} nprob={nprob}", flush=True)
+    rng = np.random.default_rng(abs(hash(name)) % 2**32 + 1)
+    asz, bsz, csz = _extent(desc, "a"), _extent(desc, "b"), _extent(desc, "c")
+    A = _rand(rng, nprob * asz)
+    Bm = _rand(rng, nprob * bsz)
+    Cm = _rand(rng, nprob * csz)
+    got = ctx.test_gemm({**desc, "prec": 1}, A, Bm, Cm, nprob)
+    want = _ref_gemm(desc, A, Bm, Cm, nprob, asz, bsz, csz)
+    scale = np.sqrt(desc["K"]) * 4 * max(1.0, abs(desc.get("alpha_re", 1)) + abs(desc.get("alpha_im", 0)))
+    err = np.abs(got - want).max()
+    assert err < 2e-6 * scale
+    assert err > 0 or desc["K"] < 4     # really computed in FP32
+
+
+@pytest.mark.parametrize("name,desc,nprob", CASES, ids=[c[0] for c in CASES])
 def test_gemm_matches_numpy(ctx, name, desc, nprob):
     print(f"[gemm] case {name} nprob={nprob}", flush=True)
     rng = np.random.default_rng(abs(hash(name)) % 2**32)
