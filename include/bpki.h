@@ -41,12 +41,17 @@ extern "C" {
 
 typedef struct bpki_ctx bpki_ctx;
 
-/* Arithmetic of the bulk contractions.  The eigendecompositions behind the truncation SVD, the
- * message square roots and inverse square roots, the BP residual and the observables' final ratios
- * are FP64 in every mode. */
+/* Arithmetic of the bulk contractions.  Storage, the gate updates (including the truncation SVD
+ * and the message square roots and inverse square roots), the BP residual and the observables'
+ * final ratios are FP64 in every mode.
+ * BPKI_FP32: the BP message contractions and the observables' contractions run on FP32 MFMA
+ * (operands rounded to FP32, FP32 accumulation per K chunk, FP64 chunk sums).  BP sweeps in FP32
+ * until the residual reaches 2e-6, then in FP64 if bp_tol asks for less, so the fixed point is the
+ * FP64 one.  With bp_tol = 1e-6 the measured deviation of every <Z> from the FP64 mode over 20
+ * steps on the 127-qubit lattice (chi 32 and 64) is below 1e-5. */
 typedef enum {
-  BPKI_FP64 = 0,   /* everything FP64 (the parity mode)                      */
-  BPKI_FP32 = 1    /* site tensors and their contractions in FP32 on MFMA    */
+  BPKI_FP64 = 0,   /* everything FP64 (the parity mode)                                     */
+  BPKI_FP32 = 1    /* FP32 MFMA contractions in BP sweeps and observables (see above)       */
 } bpki_precision;
 
 typedef struct {

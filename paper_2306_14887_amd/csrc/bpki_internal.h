@@ -113,7 +113,7 @@ struct Problem {
   std::vector<int> colour;      // E
   double theta = 0;
   int depth = 0, chi = 1;
-  int precision = 0;
+  int precision = 0;            // 0 FP64; 1 FP32 contractions in BP sweeps and observables
   double bp_tol = 1e-12;
   int bp_max_iter = 1000;
   double svd_cutoff = 1e-12, eig_cutoff = 1e-12;
@@ -150,6 +150,10 @@ class Engine {
   Backend *be_;
   Problem prob_;
   Plan *plan_;
+  int bp_prec_ = 0;
+  // The gate updates stay FP64 in every mode: the Gram-based bond isolation amplifies rounding
+  // by the condition number of the isolated tensor, which FP32 cannot absorb.
+  int su_prec() const { return 0; }
   void build();
   double pauli_value(int k, bool with_ops);
 };

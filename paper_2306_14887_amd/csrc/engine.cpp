@@ -54,6 +54,9 @@ inline long ipow(long b, int e) { long r = 1; while (e-- > 0) r *= b; return r; 
 // below this fraction of the largest are at the FP64 rounding level of the Gram matrix.
 constexpr double kGramCut = 1e-15;
 
+// Residual below which FP32 message contractions stop making progress (their rounding level).
+constexpr double kFp32BpFloor = 2e-6;
+
 }  // namespace
 
 // Strides of a site tensor's indices: s first, then one per leg.
@@ -808,13 +811,13 @@ double Engine::apply_layer(int colour) {
   }
   // 2. absorb
   for (auto &t : LP.d2d_in) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
-  for (auto &op : LP.absorb) run(be_, ar, op, prob_.precision);
+  for (auto &op : LP.absorb) run(be_, ar, op, su_prec());
   // 3. isolate degree-3 endpoints
   if (LP.n_g) {
-    run(be_, ar, LP.gram, prob_.precision);
+    run(be_, ar, LP.gram, su_prec());
     be_->gram_chol(2 * chi, ar.at<const double *const *>(LP.g_in), ar.at<double *const *>(LP.g_R),
                    ar.at<double *const *>(LP.g_Wsc), kGramCut, LP.n_g);
-    run(be_, ar, LP.qform, prob_.precision);
+    run(be_, ar, LP.qform, su_prec());
   }
   // 4-6. Theta, truncated SVD, new factors
   const double q = M_PI / 4;
@@ -836,9 +839,9 @@ double Engine::apply_layer(int colour) {
                     ar.at<double *const *>(T.RBn), ar.at<double *const *>(T.RSn), T.count);
   }
   // 7. rebuild and remove the environment
-  if (LP.n_g) run(be_, ar, LP.rebuild, prob_.precision);
+  if (LP.n_g) run(be_, ar, LP.rebuild, su_prec());
   // degree <= 2: T~' = R' (already in A-layout); point remove ops at R' directly
-  for (auto &op : LP.remove) run(be_, ar, op, prob_.precision);
+  for (auto &op : LP.remove) run(be_, ar, op, su_prec());
   for (auto &t : LP.d2d_out) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
   // bookkeeping: discarded weight and bond dimensions
   int ne = (int)LP.edges.size();
@@ -856,7 +859,7 @@ double Engine::apply_layer(int colour) {
 
 double Engine::bp_sweep() {
   Plan &P = *plan_;
-  for (auto &op : P.bp_ops) run(be_, P.arena, op, prob_.precision);
+  for (auto &op : P.bp_ops) run(be_, P.arena, op, bp_prec_);
   be_->normalize_residual(P.chi, P.arena.at<double *const *>(P.bp_norm_new),
                           P.arena.at<const double *const *>(P.bp_norm_old), P.res, 2 * P.E);
   be_->reduce_max(P.res, 2 * P.E, P.resmax);
@@ -867,20 +870,25 @@ double Engine::bp_sweep() {
 }
 
 int Engine::bp(int max_iter, double *residual) {
+  // Mixed modes sweep with FP32 contractions while the residual is above the FP32 floor, then
+  // (if the tolerance asks for more) finish with FP64 sweeps: the fixed point is the FP64 one.
   int it = 0;
   double r = INFINITY;
+  bp_prec_ = prob_.precision ? 1 : 0;
   while (it < max_iter) {
     r = bp_sweep();
     ++it;
     if (r < prob_.bp_tol) break;
+    if (bp_prec_ == 1 && r < kFp32BpFloor) bp_prec_ = 0;
   }
+  bp_prec_ = prob_.precision ? 1 : 0;
   if (residual) *residual = r;
   return it;
 }
 
 void Engine::observe_z(double *z) {
   Plan &P = *plan_;
-  for (auto &op : P.obs_ops) run(be_, P.arena, op, prob_.precision);
+  for (auto &op : P.obs_ops) run(be_, P.arena, op, prob_.precision ? 1 : 0);
   be_->rho_dot(P.arena.at<const double *const *>(P.obs_Y),
                P.arena.at<const double *const *>(P.obs_T), P.rho_len, P.rho, P.n);
   std::vector<double> rho((size_t)P.n * 8);
