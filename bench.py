@@ -84,6 +84,91 @@ def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict
     }
 
 
+def serving_bench(n: int, slots: int) -> dict:
+    """Serving workload: ``n`` requests from the seeded serving stream (lattices (3,9), (5,11),
+    (7,15); theta ~ U[0, pi/2]; depth ~ U{1..20}; chi ~ U{8,16,32,64}).  First every request is
+    solved one at a time in plain FP64 (the comparator); then the same requests are served in
+    mixed precision (FP32 BP contractions, BP tolerance 1e-6) with Poisson arrivals at the measured
+    sequential FP64 solve rate.  Reports solves/s, p50/p99 latency (finish - arrival) and the
+    largest |<Z>| deviation of a served result from its FP64 solve."""
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    reqs = L.serving_requests(n, seed=0, rate=1.0)
+    lats = {}
+    specs64, specsmx = [], []
+    for r in reqs:
+        key = (r.rows, r.row_len)
+        if key not in lats:
+            lats[key] = L.heavy_hex(*key)
+        specs64.append(bpki.spec_from_lattice(lats[key], r.theta, r.depth, r.chi))
+        specsmx.append(bpki.spec_from_lattice(lats[key], r.theta, r.depth, r.chi,
+                                              precision=bpki.BPKI_FP32, bp_tol=1e-6))
+    ref = []
+    with bpki.Context(0) as ctx:
+        t0 = time.perf_counter()
+        lat_seq = []
+        for s in specs64:
+            a = time.perf_counter()
+            ref.append(ctx.solve(s)["z"])
+            lat_seq.append(time.perf_counter() - a)
+        t_seq = time.perf_counter() - t0
+    rate = n / t_seq
+    gaps = np.array([r.arrival for r in reqs])
+    arrivals = gaps / gaps[-1] * (n / rate) if n > 1 else gaps * 0
+    with bpki.Context(0) as ctx:
+        ctx.serving_config(slots)
+        tickets = [None] * n
+        t0 = time.perf_counter()
+        for i, s in enumerate(specsmx):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            tickets[i] = ctx.submit(s)
+        while not all(t.poll() for t in tickets):
+            time.sleep(0.0005)
+        times = np.array([t.times() for t in tickets])
+        outs = [t.wait() for t in tickets]
+    lat = times[:, 2] - times[:, 0]
+    makespan = times[:, 2].max() - times[:, 0].min()
+    err = max(float(np.abs(o["z"] - z).max()) for o, z in zip(outs, ref))
+    return {
+        "requests": n, "slots": slots,
+        "served_mixed_solves_per_s": n / makespan,
+        "served_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "served_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "sequential_fp64_solves_per_s": rate,
+        "sequential_fp64_p50_ms": 1e3 * float(np.percentile(lat_seq, 50)),
+        "sequential_fp64_p99_ms": 1e3 * float(np.percentile(lat_seq, 99)),
+        "arrival_rate_per_s": rate,
+        "max_abs_dz_vs_fp64": err,
+    }
+
+
+def mixed_window(lat, theta, chi, warmup, steps) -> dict:
+    """The same steps in mixed precision (FP32 BP contractions, BP tolerance 1e-6)."""
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+
+    with bpki.Context(0) as ctx:
+        sess = ctx.session(bpki.spec_from_lattice(lat, theta, warmup + steps, chi,
+                                                  precision=bpki.BPKI_FP32, bp_tol=1e-6))
+        for _ in range(warmup):
+            sess.step(observe=True)
+        iters = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            iters.append(sess.step(observe=True)["bp_iters"])
+        wall = time.perf_counter() - t0
+        sess.close()
+    return {"value": steps / wall, "unit": "Floquet steps/s", "ms_per_step": 1e3 * wall / steps,
+            "bp_sweeps_per_step": float(np.mean(iters)), "bp_tol": 1e-6,
+            "dtype": "c64 contractions in BP (FP64 storage, gates, eigh, residual)"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +176,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving", type=int, default=48,
+                    help="requests in the serving measurement (0 = skip; 256 = full stream)")
+    ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-request "
@@ -173,6 +261,11 @@ def main() -> int:
             "traffic": None,
         },
     }
+    out["mixed"] = mixed_window(lat, theta, chi, args.warmup, args.steps)
+    print("mixed-precision window done", file=sys.stderr, flush=True)
+    if args.serving > 0:
+        out["serving"] = serving_bench(args.serving, args.slots)
+        print("serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, chi, theta, float(np.mean(iters)))
     print(json.dumps(out), flush=True)

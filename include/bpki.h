@@ -108,13 +108,17 @@ int bpki_estimate_bytes(const bpki_problem *p, size_t *bytes);
 int bpki_solve(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
 
 /* ---- Serving: continuous batching -----------------------------------------------------------
- * bpki_submit queues a problem (deep copy) and returns at once with a ticket.  A worker thread of
- * the context admits queued problems while their bpki_estimate_bytes fits the memory budget,
- * interleaves the Floquet steps of all resident problems on the device (requests start and finish
- * at different times) and writes each result into its caller-owned buffers, which must stay valid
- * until bpki_wait returns or bpki_poll reports done.  A problem that can never fit the budget is
- * rejected with -4 by bpki_submit.  The result of a problem does not depend on what else is
- * resident. */
+ * bpki_submit queues a problem (deep copy) and returns at once with a ticket.  The context runs a
+ * fixed number of serving slots, each a worker thread with its own HIP stream; a free slot takes
+ * the oldest queued problem whose bpki_estimate_bytes fits the memory budget next to the resident
+ * ones (arrival order; a problem larger than the budget's free part waits until memory frees up),
+ * so problems that arrive while others run start as slots and memory free up, and the kernels of
+ * all resident problems run concurrently on the device.  Results go into caller-owned buffers,
+ * which must stay valid until bpki_wait returns or bpki_poll reports done.  A problem that can
+ * never fit the budget is rejected with -4 by bpki_submit.  The result of a problem does not
+ * depend on what else is resident (private workspaces, deterministic reductions). */
+/* Number of serving slots (1..64, default 8); only before the first bpki_submit. */
+int bpki_serving_config(bpki_ctx *ctx, int slots);
 int bpki_submit(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r, uint64_t *ticket);
 /* *done = 1 when finished; returns the problem's status (0/+1/negative) once done, else 0. */
 int bpki_poll(bpki_ctx *ctx, uint64_t ticket, int *done);
@@ -122,6 +126,9 @@ int bpki_poll(bpki_ctx *ctx, uint64_t ticket, int *done);
 int bpki_wait(bpki_ctx *ctx, uint64_t ticket);
 /* Cancels a queued or running problem; its bpki_wait returns -6. */
 int bpki_cancel(bpki_ctx *ctx, uint64_t ticket);
+/* Host steady-clock times (seconds) of a ticket: submitted, started on a slot, finished (0 if not
+ * yet).  Valid until bpki_wait forgets the ticket. */
+int bpki_ticket_times(bpki_ctx *ctx, uint64_t ticket, double *times3);
 
 /* ---- Sessions: step-by-step access to one resident state -----------------------------------
  * A session holds one problem's tensors and messages on the device.  It exposes each phase of a

@@ -81,6 +81,8 @@ def load(path: str | None = None):
         "bpki_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int)]),
         "bpki_wait": (C.c_int, [vp, C.c_uint64]),
         "bpki_cancel": (C.c_int, [vp, C.c_uint64]),
+        "bpki_serving_config": (C.c_int, [vp, C.c_int]),
+        "bpki_ticket_times": (C.c_int, [vp, C.c_uint64, dp]),
         "bpki_session_open": (C.c_int, [vp, P, C.POINTER(vp)]),
         "bpki_session_close": (None, [vp]),
         "bpki_session_sizes": (C.c_int, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
@@ -113,7 +115,8 @@ def load(path: str | None = None):
 def exported_symbols() -> list[str]:
     return ["bpki_problem_defaults", "bpki_create", "bpki_destroy", "bpki_last_error",
             "bpki_validate", "bpki_estimate_bytes", "bpki_solve", "bpki_submit", "bpki_poll",
-            "bpki_wait", "bpki_cancel", "bpki_session_open", "bpki_session_close",
+            "bpki_wait", "bpki_cancel", "bpki_serving_config", "bpki_ticket_times",
+            "bpki_session_open", "bpki_session_close",
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
             "bpki_session_bp_sweep", "bpki_session_observe_z", "bpki_session_observe_pauli",
@@ -237,6 +240,9 @@ class Context:
         _check(self.lib, self.lib.bpki_submit(self.h, C.byref(p), C.byref(r), C.byref(t)))
         return Ticket(self, int(t.value), out, r, keep)
 
+    def serving_config(self, slots: int):
+        _check(self.lib, self.lib.bpki_serving_config(self.h, slots))
+
     def session(self, spec: ProblemSpec) -> "Session":
         return Session(self, spec)
 
@@ -318,6 +324,13 @@ class Ticket:
 
     def cancel(self):
         _check(self.ctx.lib, self.ctx.lib.bpki_cancel(self.ctx.h, self.t))
+
+    def times(self):
+        """(submitted, started, finished) host steady-clock seconds."""
+        t = np.zeros(3)
+        _check(self.ctx.lib, self.ctx.lib.bpki_ticket_times(self.ctx.h, self.t,
+                                                            _ptr(t, C.c_double)))
+        return t
 
 
 class Session:

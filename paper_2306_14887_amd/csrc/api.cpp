@@ -195,9 +195,13 @@ struct bpki_ctx {
   struct Job;
   std::map<uint64_t, std::shared_ptr<Job>> jobs;
   std::deque<std::shared_ptr<Job>> queue;
-  std::thread worker;
+  int n_slots = 8;
+  std::vector<std::unique_ptr<Backend>> slot_be;
+  std::vector<std::thread> slot_threads;
   std::condition_variable cv, done_cv;
   bool stop = false;
+  size_t used = 0;
+  int running = 0;
   uint64_t next_ticket = 1;
 };
 
@@ -439,7 +443,12 @@ extern "C" int bpki_session_last_timing(const bpki_session *s, double *ms4) {
 }
 
 // ------------------------------------------------------------------------------------------
-// serving (continuous batching): see serve.cpp
+// serving: concurrent slots.  Each slot is a worker thread with its own HIP stream and backend;
+// a slot takes the oldest queued request whose memory estimate fits the budget next to what is
+// resident, runs it to completion on its stream and writes the result into the caller's buffers.
+// Requests that arrive while others run are admitted as slots and memory free up, and the
+// kernels of different slots run concurrently on the device.  A request's arithmetic does not
+// depend on the other slots (same kernels, deterministic reductions, private workspaces).
 struct bpki_ctx::Job {
   uint64_t ticket = 0;
   Problem q;
@@ -448,7 +457,12 @@ struct bpki_ctx::Job {
   bool done = false;
   int status = 0;
   size_t bytes = 0;
+  double t_submit = 0, t_start = 0, t_done = 0;
 };
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 static void serving_shutdown(bpki_ctx *c) {
   {
@@ -456,10 +470,83 @@ static void serving_shutdown(bpki_ctx *c) {
     c->stop = true;
   }
   c->cv.notify_all();
-  if (c->worker.joinable()) c->worker.join();
+  for (auto &t : c->slot_threads)
+    if (t.joinable()) t.join();
+  c->slot_threads.clear();
+  c->slot_be.clear();
 }
 
-static void worker_loop(bpki_ctx *c);
+static void slot_loop(bpki_ctx *c, int slot) {
+  Backend *be = c->slot_be[slot].get();
+  for (;;) {
+    std::shared_ptr<bpki_ctx::Job> job;
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv.wait(lk, [&] {
+        if (c->stop) return true;
+        if (c->queue.empty()) return false;
+        auto &h = c->queue.front();
+        return h->cancel.load() || c->budget == 0 || c->running == 0 ||
+               c->used + h->bytes <= c->budget;
+      });
+      if (c->stop && c->queue.empty()) return;
+      if (c->queue.empty()) continue;
+      job = c->queue.front();
+      c->queue.pop_front();
+      if (job->cancel) {
+        job->status = -6;
+        job->done = true;
+        job->t_done = now_s();
+        c->done_cv.notify_all();
+        continue;
+      }
+      c->used += job->bytes;
+      c->running += 1;
+      job->t_start = now_s();
+    }
+    int status;
+    {
+      std::string msg;
+      if (be->check(&msg)) {
+        status = -5;
+      } else {
+        std::unique_ptr<Engine> eng(new Engine(be, job->q));
+        if (be->check(&msg)) status = -4;
+        else status = run_solve(be, *eng, job->q, job->r, &job->cancel);
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->used -= job->bytes;
+      c->running -= 1;
+      job->status = status;
+      job->done = true;
+      job->t_done = now_s();
+    }
+    c->done_cv.notify_all();
+    c->cv.notify_all();
+  }
+}
+
+static int start_slots(bpki_ctx *c) {
+  if (!c->slot_threads.empty()) return 0;
+  for (int i = 0; i < c->n_slots; ++i) {
+    std::string err;
+    Backend *be = make_hip_backend(c->device, nullptr, &err);
+    if (!be) return fail(-5, "serving slot: " + err);
+    c->slot_be.emplace_back(be);
+  }
+  for (int i = 0; i < c->n_slots; ++i) c->slot_threads.emplace_back(slot_loop, c, i);
+  return 0;
+}
+
+extern "C" int bpki_serving_config(bpki_ctx *c, int slots) {
+  if (!c || slots < 1 || slots > 64) return fail(-1, "slots must be in 1..64");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->slot_threads.empty()) return fail(-1, "serving already started");
+  c->n_slots = slots;
+  return 0;
+}
 
 extern "C" int bpki_submit(bpki_ctx *c, const bpki_problem *p, bpki_result *r, uint64_t *ticket) {
   if (!c || !r || !ticket) return fail(-1, "NULL argument");
@@ -471,10 +558,11 @@ extern "C" int bpki_submit(bpki_ctx *c, const bpki_problem *p, bpki_result *r, u
   job->bytes = Engine::estimate_bytes(job->q);
   if (c->budget && job->bytes > c->budget) return fail(-4, "problem can never fit the budget");
   std::lock_guard<std::mutex> lk(c->mu);
+  if (int e = start_slots(c)) return e;
   job->ticket = c->next_ticket++;
+  job->t_submit = now_s();
   c->jobs[job->ticket] = job;
   c->queue.push_back(job);
-  if (!c->worker.joinable()) c->worker = std::thread(worker_loop, c);
   c->cv.notify_all();
   *ticket = job->ticket;
   return 0;
@@ -489,6 +577,17 @@ extern "C" int bpki_poll(bpki_ctx *c, uint64_t t, int *done) {
   return it->second->done ? it->second->status : 0;
 }
 
+extern "C" int bpki_ticket_times(bpki_ctx *c, uint64_t t, double *times3) {
+  if (!c || !times3) return fail(-1, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->jobs.find(t);
+  if (it == c->jobs.end()) return fail(-7, "unknown ticket");
+  times3[0] = it->second->t_submit;
+  times3[1] = it->second->t_start;
+  times3[2] = it->second->t_done;
+  return 0;
+}
+
 extern "C" int bpki_wait(bpki_ctx *c, uint64_t t) {
   if (!c) return fail(-1, "NULL context");
   std::unique_lock<std::mutex> lk(c->mu);
@@ -497,7 +596,7 @@ extern "C" int bpki_wait(bpki_ctx *c, uint64_t t) {
   auto job = it->second;
   c->done_cv.wait(lk, [&] { return job->done; });
   c->jobs.erase(t);
-  if (job->status < 0) g_err = "request failed";
+  if (job->status < 0) g_err = job->status == -6 ? "cancelled" : "request failed";
   return job->status;
 }
 
@@ -509,115 +608,6 @@ extern "C" int bpki_cancel(bpki_ctx *c, uint64_t t) {
   it->second->cancel = true;
   c->cv.notify_all();
   return 0;
-}
-
-// Worker: admits queued jobs while they fit the budget and interleaves their Floquet steps.
-struct Resident {
-  std::shared_ptr<bpki_ctx::Job> job;
-  std::unique_ptr<Engine> eng;
-  std::vector<int> colours;
-  int t = 0;
-  std::vector<double> z;
-  std::vector<int32_t> iters;
-  std::vector<double> res, disc;
-  int warn = 0;
-};
-
-static void finish(bpki_ctx *c, Resident &R, int status) {
-  const Problem &q = R.job->q;
-  if (status >= 0) {
-    int rows = std::max(1, q.record_every_step ? q.depth : 1);
-    bpki_result *r = R.job->r;
-    if (r->z) std::memcpy(r->z, R.z.data(), (size_t)rows * q.n_sites * sizeof(double));
-    if (r->bp_iters) std::memcpy(r->bp_iters, R.iters.data(), R.iters.size() * sizeof(int32_t));
-    if (r->bp_residual) std::memcpy(r->bp_residual, R.res.data(), R.res.size() * sizeof(double));
-    if (r->discarded) std::memcpy(r->discarded, R.disc.data(), R.disc.size() * sizeof(double));
-    if (r->pauli && q.pauli_offsets.size() > 1) R.eng->observe_pauli(r->pauli);
-    status = R.warn;
-  }
-  std::lock_guard<std::mutex> lk(c->mu);
-  R.job->status = status;
-  R.job->done = true;
-  c->done_cv.notify_all();
-}
-
-static void worker_loop(bpki_ctx *c) {
-  std::vector<Resident> live;
-  size_t used = 0;
-  for (;;) {
-    {
-      std::unique_lock<std::mutex> lk(c->mu);
-      c->cv.wait(lk, [&] { return c->stop || !c->queue.empty() || !live.empty(); });
-      if (c->stop && live.empty()) return;
-      // admission by memory footprint, in arrival order
-      while (!c->queue.empty()) {
-        auto job = c->queue.front();
-        if (job->cancel) {
-          c->queue.pop_front();
-          job->status = -6;
-          job->done = true;
-          c->done_cv.notify_all();
-          continue;
-        }
-        if (c->budget && used + job->bytes > c->budget && !live.empty()) break;
-        c->queue.pop_front();
-        lk.unlock();
-        Resident R;
-        R.job = job;
-        R.eng.reset(new Engine(c->be.get(), job->q));
-        R.colours.assign(job->q.colour.begin(), job->q.colour.end());
-        std::sort(R.colours.begin(), R.colours.end());
-        R.colours.erase(std::unique(R.colours.begin(), R.colours.end()), R.colours.end());
-        int rows = job->q.record_every_step ? job->q.depth : 1;
-        R.z.assign((size_t)std::max(rows, 1) * job->q.n_sites, 1.0);
-        R.iters.assign(job->q.depth, 0);
-        R.res.assign(job->q.depth, 0.0);
-        R.disc.assign(job->q.depth, 0.0);
-        used += job->bytes;
-        live.push_back(std::move(R));
-        lk.lock();
-      }
-    }
-    // one Floquet step of every resident request (round robin)
-    for (size_t i = 0; i < live.size();) {
-      Resident &R = live[i];
-      const Problem &q = R.job->q;
-      bool drop = false;
-      if (R.job->cancel) {
-        finish(c, R, -6);
-        drop = true;
-      } else if (R.t >= q.depth) {
-        finish(c, R, 0);
-        drop = true;
-      } else {
-        R.eng->apply_rx();
-        double d = 0;
-        for (int col : R.colours) d += R.eng->apply_layer(col);
-        double rr = 0;
-        R.iters[R.t] = R.eng->bp(q.bp_max_iter, &rr);
-        R.res[R.t] = rr;
-        R.disc[R.t] = d;
-        if (!(rr < q.bp_tol)) R.warn = 1;
-        if (q.record_every_step || R.t == q.depth - 1)
-          R.eng->observe_z(&R.z[(size_t)(q.record_every_step ? R.t : 0) * q.n_sites]);
-        R.t++;
-        std::string msg;
-        if (c->be->check(&msg)) {
-          finish(c, R, -5);
-          drop = true;
-        } else if (R.t >= q.depth) {
-          finish(c, R, 0);
-          drop = true;
-        }
-      }
-      if (drop) {
-        used -= R.job->bytes;
-        live.erase(live.begin() + i);
-      } else {
-        ++i;
-      }
-    }
-  }
 }
 
 // ------------------------------------------------------------------------------------------
