@@ -91,6 +91,9 @@ void bpki_problem_defaults(bpki_problem *p);
  * destroyed by the library) or NULL for a stream owned by the context.  `mem_budget_bytes` caps the
  * device memory the context may hold (0 = no cap).  Returns 0 or a negative code. */
 int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t mem_budget_bytes);
+/* Cancels unfinished tickets, stops the serving slots and releases the context.  Sessions
+ * still open keep the context's device resources alive; it is freed when the last one is closed.
+ * No call other than bpki_session_* on those open sessions may use `ctx` afterwards. */
 void bpki_destroy(bpki_ctx *ctx);
 
 /* Message of the last error on this thread (never NULL). */

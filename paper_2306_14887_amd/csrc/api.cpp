@@ -203,6 +203,10 @@ struct bpki_ctx {
   size_t used = 0;
   int running = 0;
   uint64_t next_ticket = 1;
+  // sessions run on `be`: the context is deleted when it has been destroyed and the last of its
+  // sessions is closed, whichever comes second
+  int open_sessions = 0;
+  bool destroyed = false;
 };
 
 extern "C" int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t budget) {
@@ -224,7 +228,13 @@ static void serving_shutdown(bpki_ctx *c);
 extern "C" void bpki_destroy(bpki_ctx *c) {
   if (!c) return;
   serving_shutdown(c);
-  delete c;
+  bool last;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->destroyed = true;
+    last = c->open_sessions == 0;
+  }
+  if (last) delete c;
 }
 
 // One whole solve on an engine; outputs written only on success.
@@ -317,11 +327,25 @@ extern "C" int bpki_session_open(bpki_ctx *c, const bpki_problem *p, bpki_sessio
   s->colours.assign(q.colour.begin(), q.colour.end());
   std::sort(s->colours.begin(), s->colours.end());
   s->colours.erase(std::unique(s->colours.begin(), s->colours.end()), s->colours.end());
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    ++c->open_sessions;
+  }
   *out = s;
   return 0;
 }
 
-extern "C" void bpki_session_close(bpki_session *s) { delete s; }
+extern "C" void bpki_session_close(bpki_session *s) {
+  if (!s) return;
+  bpki_ctx *c = s->ctx;
+  delete s;  // releases the session's device memory through c->be
+  bool last;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    last = --c->open_sessions == 0 && c->destroyed;
+  }
+  if (last) delete c;
+}
 
 static int sess_check(bpki_session *s) {
   std::string msg;
@@ -468,6 +492,7 @@ static void serving_shutdown(bpki_ctx *c) {
   {
     std::lock_guard<std::mutex> lk(c->mu);
     c->stop = true;
+    for (auto &kv : c->jobs) kv.second->cancel = true;
   }
   c->cv.notify_all();
   for (auto &t : c->slot_threads)

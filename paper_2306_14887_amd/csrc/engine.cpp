@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <set>
 #include <functional>
 #include <stdexcept>
 #include <tuple>
@@ -102,6 +103,13 @@ struct LayerPlan {
     int slot0 = 0;                  // first edge slot of this type (k / disc arrays)
   };
   std::vector<Type> types;
+  // all Theta^H Theta of one size share one eigensolver launch (each matrix gets one workgroup,
+  // so a launch costs the same for 3 or 50 matrices)
+  struct EighGroup {
+    int n = 0, count = 0;
+    size_t in = 0, ev = 0, vec = 0;
+  };
+  std::vector<EighGroup> eig_groups;
   GemmOp rebuild;                   // deg-3 endpoints: Tt = Q R'
   std::vector<GemmOp> remove;       // grouped
   std::vector<std::pair<size_t, size_t>> copies_in, copies_out;  // deg-1 (dst, src, bytes) as ptr
@@ -136,9 +144,13 @@ struct Plan {
   size_t ws_elems = 0, bpws_elems = 0;
   PtrArena arena;
   std::vector<LayerPlan> layers;
-  // BP
-  std::vector<GemmOp> bp_ops;
-  size_t bp_norm_new = 0, bp_norm_old = 0;
+  // BP: one group of launches per vertex class of the sweep schedule
+  struct BpClass {
+    std::vector<GemmOp> ops;
+    size_t norm_new = 0, norm_old = 0;
+    int nmsg = 0, res_off = 0;
+  };
+  std::vector<BpClass> bp_classes;
   // observables
   std::vector<GemmOp> obs_ops;
   size_t obs_Y = 0, obs_T = 0;
@@ -557,6 +569,8 @@ void Engine::build() {
       types[{LP.eps[w.ep[0]].r, LP.eps[w.ep[1]].r}].push_back(q);
     }
     LP.types.clear();
+    LP.eig_groups.clear();
+    std::map<int, std::vector<const void *>> g_in, g_ev, g_vec;
     for (auto &t : types) {
       LayerPlan::Type T;
       T.rB = t.first.first;
@@ -610,7 +624,21 @@ void Engine::build() {
         T.hgemm.a = T.Th; T.hgemm.b = T.Th; T.hgemm.c = hoff;
         T.ugemm.a = T.Th; T.ugemm.b = T.Vs; T.ugemm.c = T.U;
       }
+      g_in[T.n].insert(g_in[T.n].end(), H.begin(), H.end());
+      g_ev[T.n].insert(g_ev[T.n].end(), ev.begin(), ev.end());
+      g_vec[T.n].insert(g_vec[T.n].end(), vec.begin(), vec.end());
       LP.types.push_back(T);
+    }
+    for (auto &g : g_in) {
+      LayerPlan::EighGroup G;
+      G.n = g.first;
+      G.count = (int)g.second.size();
+      if (real) {
+        G.in = P.arena.add(g.second);
+        G.ev = P.arena.add(g_ev[g.first]);
+        G.vec = P.arena.add(g_vec[g.first]);
+      }
+      LP.eig_groups.push_back(G);
     }
   };
 
@@ -666,63 +694,107 @@ void Engine::build() {
       op.a = P.arena.add(a); op.b = P.arena.add(b); op.c = P.arena.add(c);
       ops.push_back(op);
     };
-    // degree 3 sites: Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
-    //                 Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
+    // Sweep schedule: vertex classes (the two sides of a bipartite graph, else a greedy proper
+    // vertex colouring).  The messages sent by one class are recomputed together and normalised
+    // before the next class; a site reads the message of a neighbour whose class has already
+    // been updated in this sweep from the new buffer, otherwise from the current one.
+    std::vector<int> cls(P.n, -1);
+    bool bip = true;
+    for (int s0 = 0; s0 < P.n; ++s0) {
+      if (cls[s0] >= 0) continue;
+      cls[s0] = 0;
+      std::vector<int> queue{s0};
+      for (size_t qi = 0; qi < queue.size(); ++qi) {
+        int x = queue[qi];
+        for (int y : P.nb[x]) {
+          if (cls[y] < 0) { cls[y] = 1 - cls[x]; queue.push_back(y); }
+          else if (cls[y] == cls[x]) bip = false;
+        }
+      }
+    }
+    if (!bip) {
+      std::fill(cls.begin(), cls.end(), -1);
+      for (int v = 0; v < P.n; ++v) {
+        std::set<int> used;
+        for (int u : P.nb[v]) if (cls[u] >= 0) used.insert(cls[u]);
+        int c = 0;
+        while (used.count(c)) ++c;
+        cls[v] = c;
+      }
+    }
+    const int ncls = P.n ? *std::max_element(cls.begin(), cls.end()) + 1 : 0;
     Layout L3 = t_layout(3, chi), L2 = t_layout(2, chi), L1 = t_layout(1, chi);
-    {
-      std::vector<const void *> a[10], b[10], c[10];
-      for (int v = 0; v < P.n; ++v) {
-        if (P.deg[v] != 3) continue;
-        const auto &y = sws[v].y;
-        auto push = [&](int k, const void *aa, const void *bb, const void *cc) {
-          a[k].push_back(aa); b[k].push_back(bb); c[k].push_back(cc);
-        };
-        push(0, Tp(v), Mp(P.in_msg[v][2]), B(y[0]));        // Y2
-        push(1, B(y[0]), Mp(P.in_msg[v][1]), B(y[1]));      // Y21
-        push(2, B(y[0]), Mp(P.in_msg[v][0]), B(y[2]));      // Y20
-        push(3, Tp(v), Mp(P.in_msg[v][1]), B(y[3]));        // Y1
-        push(4, B(y[3]), Mp(P.in_msg[v][0]), B(y[4]));      // Y10
-        push(5, B(y[1]), Tp(v), Mnp(P.out_msg[v][0]));
-        push(6, B(y[2]), Tp(v), Mnp(P.out_msg[v][1]));
-        push(7, B(y[4]), Tp(v), Mnp(P.out_msg[v][2]));
+    int res_off = 0;
+    for (int c = 0; c < ncls; ++c) {
+      Plan::BpClass C;
+      auto in = [&](int v, int i) { return cls[P.nb[v][i]] < c ? Mnp(P.in_msg[v][i]) : Mp(P.in_msg[v][i]); };
+      // degree 3: Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
+      //           Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
+      {
+        std::vector<const void *> a[8], b[8], cc[8];
+        for (int v = 0; v < P.n; ++v) {
+          if (P.deg[v] != 3 || cls[v] != c) continue;
+          const auto &y = sws[v].y;
+          auto push = [&](int k, const void *aa, const void *bb, const void *c3) {
+            a[k].push_back(aa); b[k].push_back(bb); cc[k].push_back(c3);
+          };
+          push(0, Tp(v), in(v, 2), B(y[0]));
+          push(1, B(y[0]), in(v, 1), B(y[1]));
+          push(2, B(y[0]), in(v, 0), B(y[2]));
+          push(3, Tp(v), in(v, 1), B(y[3]));
+          push(4, B(y[3]), in(v, 0), B(y[4]));
+          push(5, B(y[1]), Tp(v), Mnp(P.out_msg[v][0]));
+          push(6, B(y[2]), Tp(v), Mnp(P.out_msg[v][1]));
+          push(7, B(y[4]), Tp(v), Mnp(P.out_msg[v][2]));
+        }
+        add_op(C.ops, leg_desc(3, 2, L3, L3, chi), a[0], b[0], cc[0]);
+        add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[1], b[1], cc[1]);
+        add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[2], b[2], cc[2]);
+        add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[3], b[3], cc[3]);
+        add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[4], b[4], cc[4]);
+        add_op(C.ops, close_desc(3, 0, L3, chi), a[5], b[5], cc[5]);
+        add_op(C.ops, close_desc(3, 1, L3, chi), a[6], b[6], cc[6]);
+        add_op(C.ops, close_desc(3, 2, L3, chi), a[7], b[7], cc[7]);
       }
-      add_op(P.bp_ops, leg_desc(3, 2, L3, L3, chi), a[0], b[0], c[0]);
-      add_op(P.bp_ops, leg_desc(3, 1, L3, L3, chi), a[1], b[1], c[1]);
-      add_op(P.bp_ops, leg_desc(3, 0, L3, L3, chi), a[2], b[2], c[2]);
-      add_op(P.bp_ops, leg_desc(3, 1, L3, L3, chi), a[3], b[3], c[3]);
-      add_op(P.bp_ops, leg_desc(3, 0, L3, L3, chi), a[4], b[4], c[4]);
-      add_op(P.bp_ops, close_desc(3, 0, L3, chi), a[5], b[5], c[5]);
-      add_op(P.bp_ops, close_desc(3, 1, L3, chi), a[6], b[6], c[6]);
-      add_op(P.bp_ops, close_desc(3, 2, L3, chi), a[7], b[7], c[7]);
-    }
-    {
-      std::vector<const void *> a[4], b[4], c[4];
-      for (int v = 0; v < P.n; ++v) {
-        if (P.deg[v] != 2) continue;
-        const auto &y = sws[v].y;
-        a[0].push_back(Tp(v)); b[0].push_back(Mp(P.in_msg[v][1])); c[0].push_back(B(y[0]));
-        a[1].push_back(Tp(v)); b[1].push_back(Mp(P.in_msg[v][0])); c[1].push_back(B(y[1]));
-        a[2].push_back(B(y[0])); b[2].push_back(Tp(v)); c[2].push_back(Mnp(P.out_msg[v][0]));
-        a[3].push_back(B(y[1])); b[3].push_back(Tp(v)); c[3].push_back(Mnp(P.out_msg[v][1]));
+      {
+        std::vector<const void *> a[4], b[4], cc[4];
+        for (int v = 0; v < P.n; ++v) {
+          if (P.deg[v] != 2 || cls[v] != c) continue;
+          const auto &y = sws[v].y;
+          a[0].push_back(Tp(v)); b[0].push_back(in(v, 1)); cc[0].push_back(B(y[0]));
+          a[1].push_back(Tp(v)); b[1].push_back(in(v, 0)); cc[1].push_back(B(y[1]));
+          a[2].push_back(B(y[0])); b[2].push_back(Tp(v)); cc[2].push_back(Mnp(P.out_msg[v][0]));
+          a[3].push_back(B(y[1])); b[3].push_back(Tp(v)); cc[3].push_back(Mnp(P.out_msg[v][1]));
+        }
+        add_op(C.ops, leg_desc(2, 1, L2, L2, chi), a[0], b[0], cc[0]);
+        add_op(C.ops, leg_desc(2, 0, L2, L2, chi), a[1], b[1], cc[1]);
+        add_op(C.ops, close_desc(2, 0, L2, chi), a[2], b[2], cc[2]);
+        add_op(C.ops, close_desc(2, 1, L2, chi), a[3], b[3], cc[3]);
       }
-      add_op(P.bp_ops, leg_desc(2, 1, L2, L2, chi), a[0], b[0], c[0]);
-      add_op(P.bp_ops, leg_desc(2, 0, L2, L2, chi), a[1], b[1], c[1]);
-      add_op(P.bp_ops, close_desc(2, 0, L2, chi), a[2], b[2], c[2]);
-      add_op(P.bp_ops, close_desc(2, 1, L2, chi), a[3], b[3], c[3]);
-    }
-    {
-      std::vector<const void *> a, b, c;
-      for (int v = 0; v < P.n; ++v) {
-        if (P.deg[v] != 1) continue;
-        a.push_back(Tp(v)); b.push_back(Tp(v)); c.push_back(Mnp(P.out_msg[v][0]));
+      {
+        std::vector<const void *> a, b, cc;
+        for (int v = 0; v < P.n; ++v) {
+          if (P.deg[v] != 1 || cls[v] != c) continue;
+          a.push_back(Tp(v)); b.push_back(Tp(v)); cc.push_back(Mnp(P.out_msg[v][0]));
+        }
+        add_op(C.ops, close_desc(1, 0, L1, chi), a, b, cc);
       }
-      add_op(P.bp_ops, close_desc(1, 0, L1, chi), a, b, c);
-    }
-    {
       std::vector<const void *> nn, no;
-      for (int m = 0; m < 2 * P.E; ++m) { nn.push_back(Mnp(m)); no.push_back(Mp(m)); }
-      P.bp_norm_new = P.arena.add(nn);
-      P.bp_norm_old = P.arena.add(no);
+      for (int v = 0; v < P.n; ++v) {
+        if (cls[v] != c) continue;
+        for (int i = 0; i < P.deg[v]; ++i) {
+          nn.push_back(Mnp(P.out_msg[v][i]));
+          no.push_back(Mp(P.out_msg[v][i]));
+        }
+      }
+      C.nmsg = (int)nn.size();
+      C.res_off = res_off;
+      res_off += C.nmsg;
+      if (C.nmsg) {
+        C.norm_new = P.arena.add(nn);
+        C.norm_old = P.arena.add(no);
+      }
+      P.bp_classes.push_back(C);
     }
     // observables: Y = T x0 M0 x1 M1 x2 M2 (T-order), rho = sum Y conj(T)
     {
@@ -826,8 +898,11 @@ double Engine::apply_layer(int colour) {
                ar.at<const double *const *>(T.RS), ar.at<double *const *>(T.Th), std::cos(q),
                std::sin(q), std::cos(q), -std::sin(q), T.count);
     run(be_, ar, T.hgemm, 0);        // the truncation SVD is FP64 in every mode
-    be_->eigh(T.n, T.n, ar.at<const double *const *>(T.hgemm.c), ar.at<double *const *>(T.ev),
-              ar.at<double *const *>(T.vec), T.count);
+  }
+  for (auto &G : LP.eig_groups)
+    be_->eigh(G.n, G.n, ar.at<const double *const *>(G.in), ar.at<double *const *>(G.ev),
+              ar.at<double *const *>(G.vec), G.count);
+  for (auto &T : LP.types) {
     be_->svd_finish(T.n, chi, ar.at<const double *const *>(T.ev),
                     ar.at<const double *const *>(T.vec), ar.at<double *const *>(T.Vs),
                     ar.at<double *const *>(T.S), P.kbuf + T.slot0, P.disc + T.slot0,
@@ -859,9 +934,13 @@ double Engine::apply_layer(int colour) {
 
 double Engine::bp_sweep() {
   Plan &P = *plan_;
-  for (auto &op : P.bp_ops) run(be_, P.arena, op, bp_prec_);
-  be_->normalize_residual(P.chi, P.arena.at<double *const *>(P.bp_norm_new),
-                          P.arena.at<const double *const *>(P.bp_norm_old), P.res, 2 * P.E);
+  for (auto &C : P.bp_classes) {
+    for (auto &op : C.ops) run(be_, P.arena, op, bp_prec_);
+    if (C.nmsg)
+      be_->normalize_residual(P.chi, P.arena.at<double *const *>(C.norm_new),
+                              P.arena.at<const double *const *>(C.norm_old), P.res + C.res_off,
+                              C.nmsg);
+  }
   be_->reduce_max(P.res, 2 * P.E, P.resmax);
   be_->d2d(P.M, P.Mn, message_elems() * 16);
   double r = 0;

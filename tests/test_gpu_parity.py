@@ -138,8 +138,18 @@ def test_bp_sweep_identical_inputs_eagle_chi64(ctx):
         idx[(v, u)] = 2 * ei + 1
     keys = list(net.M)
     pick = [keys[i] for i in rng.choice(len(keys), 24, replace=False)]
+    # the sweep updates the two sides of the (bipartite) lattice in turn: a class-1 site reads
+    # the messages its class-0 neighbours sent earlier in the same sweep
+    cls = net.vertex_classes()
+    assert max(cls) == 1
+    assert {cls[u] for (u, _) in pick} == {0, 1}
     for (u, v) in pick:
-        ref = net.message(u, v, net.M)
+        Min = dict(net.M)
+        if cls[u] == 1:
+            for w in net.nb[u]:
+                if w != v:
+                    Min[(w, u)] = net.message(w, u, net.M)
+        ref = net.message(u, v, Min)
         assert np.abs(got[idx[(u, v)]] - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
 
 
@@ -214,3 +224,19 @@ def test_errors_and_edge_cases(ctx):
     assert g["status"] == 1                   # BP not converged warning
     with pytest.raises(B.BpkiError):
         _gpu(ctx, e, 0.3, 2, 0)
+
+
+def test_session_outlives_destroyed_context():
+    """A session keeps working after its context is destroyed; the context's device resources
+    are released when the session closes."""
+    from paper_2306_14887_amd import bpki as B
+    print("[parity] session after context destroy", flush=True)
+    lat = L.heavy_hex(3, 9)
+    c = B.Context()
+    ref = c.solve(B.spec_from_lattice(lat, 0.5, 2, 8))
+    s = c.session(B.spec_from_lattice(lat, 0.5, 2, 8))
+    c.close()
+    for _ in range(2):
+        s.step()
+    assert np.abs(s.observe_z() - ref["z"][-1]).max() < 1e-13
+    s.close()
