@@ -182,6 +182,20 @@ def mixed_window(lat, theta, chi, warmup, steps) -> dict:
             "dtype": "c64 contractions in BP (FP64 storage, gates, eigh, residual)"}
 
 
+def copy_probe(mib: int) -> int:
+    """8 launches of torch's device copy kernel, each reading and writing ``mib`` MiB."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(8):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_per_launch": n * 8, "launches": 8}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,7 +206,13 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=48,
                     help="requests in the serving measurement (0 = skip; 256 = full stream)")
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision window")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 8 plain device-to-device copies of MIB MiB and exit "
+                         "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
+    if args.copy_probe > 0:
+        return copy_probe(args.copy_probe)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-request "
               "work does not span devices in this build.", file=sys.stderr)
@@ -274,8 +294,9 @@ def main() -> int:
             "traffic": None,
         },
     }
-    out["mixed"] = mixed_window(lat, theta, chi, args.warmup, args.steps)
-    print("mixed-precision window done", file=sys.stderr, flush=True)
+    if not args.no_mixed:
+        out["mixed"] = mixed_window(lat, theta, chi, args.warmup, args.steps)
+        print("mixed-precision window done", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.slots)
         print("serving done", file=sys.stderr, flush=True)

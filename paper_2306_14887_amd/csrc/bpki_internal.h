@@ -57,7 +57,8 @@ struct Backend {
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,
                     double *const *C, int nprob) = 0;
-  // Batched Hermitian eigendecomposition (FP64, cyclic Jacobi).  in[p]: n x n (lda), read only.
+  // Batched Hermitian eigendecomposition (FP64).  in[p]: n x n (lda), read only; its Hermitian
+  // part is used.
   // evals[p]: n reals, descending; vecs[p]: n x n, column i = eigenvector i (ld = n).
   virtual void eigh(int n, int lda, const double *const *in, double *const *evals,
                     double *const *vecs, int nprob) = 0;

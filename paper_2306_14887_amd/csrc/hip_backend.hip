@@ -6,10 +6,11 @@
 //                 (re*re, im*im, re*im, im*re), combined in the epilogue.  Operands are staged
 //                 through LDS in split re/im planes; the global loads follow whichever index is
 //                 unit-stride so they coalesce for every leg ordering of the site tensors.
-//  * eigh_jacobi: batched Hermitian eigendecomposition, FP64 cyclic Jacobi with the parallel
-//                 round-robin ordering (n/2 disjoint rotations per round, all 2x2 block updates
-//                 of a round in parallel).  Matrix and eigenvectors live in LDS up to n = 64,
-//                 otherwise in a global (L2-resident) work area.
+//  * eigh: batched Hermitian eigendecomposition in FP64.  n <= 64 and n > 128: cyclic Jacobi
+//          with the parallel round-robin ordering (n/2 disjoint rotations per round, all 2x2
+//          block updates of a round in parallel; LDS up to n = 64, else a global work area).
+//          64 < n <= 128: Householder tridiagonalisation and implicit QL, one workgroup per
+//          matrix, then a column-parallel back-transformation.
 //  * small kernels for the X rotations, message square roots, Gram factor, the gate block,
 //    truncation, BP normalisation/residual and the site density matrices.
 #include <hip/hip_runtime.h>
@@ -411,193 +412,651 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
   }
 }
 
-// Jacobi for 64 < n <= 128: the Hermitian matrix is held packed (lower triangle) in LDS and
-// the rotations of every round are logged to global memory; the eigenvector matrix is then
-// rebuilt by replaying the log on blocks of 64 rows held in LDS (rows of V evolve independently
-// under the right-multiplied rotations).
-__device__ __forceinline__ size_t pk_idx(int i, int j) {   // i >= j
+// Packed lower-triangle index (i >= j).
+__device__ __forceinline__ size_t pk_idx(int i, int j) {
   return (size_t)i * (i + 1) / 2 + j;
 }
-__device__ __forceinline__ double2 pk_get(const double2 *P, int i, int j) {
-  return i >= j ? P[pk_idx(i, j)] : cconj(P[pk_idx(j, i)]);
-}
-__device__ __forceinline__ void pk_set(double2 *P, int i, int j, double2 v) {
-  if (i >= j) P[pk_idx(i, j)] = v;
-  else P[pk_idx(j, i)] = cconj(v);
+
+// ------------------------------------------------------------------------------------------
+// Hermitian eigensolver for 64 < n <= 128 in two kernels.
+//
+// eigh_tridiag_dc_kernel (one workgroup of 512 threads per matrix):
+//  1. Householder reduction to real symmetric tridiagonal form, A = Q T Q^H with
+//     Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^H (v_k(k+1) = 1, zero above).  Each
+//     reflector maps column k below the diagonal onto beta e_1 with beta real, so T is real.
+//     The trailing block is updated as A <- A - v w^H - w v^H with x = tau A v and
+//     w = x - (1/2) Re(conj(tau) v^H x) v.  The matrix is held packed (lower triangle) in LDS;
+//     reflectors go to the workspace.
+//  2. Divide and conquer on T (Cuppen's rank-one tearing; eigenvectors by the Gu-Eisenstat
+//     construction).  The index range is cut into the binary tree of ranges
+//     [floor(q n / 2^D), floor((q+1) n / 2^D)); the couplings beta at the seven cuts of the top
+//     three levels are torn off (T = diag(T_1 .. T_8) + sum |beta| u u^T with
+//     u = e_{k-1} + sign(beta) e_k and the two diagonal entries lowered by |beta|).  The eight
+//     leaves (8..16 entries) are diagonalised by cyclic Jacobi, one wave each, and merged back
+//     pairwise by the whole workgroup.  A merge of two solved halves with eigenvectors
+//     Q = diag(Q1, Q2) solves D + rho z z^T (z = Q^T u / sqrt 2, rho = 2|beta|):
+//       - deflation: components with rho |z_i| <= tol keep (d_i, q_i); pairs of eigenvalues
+//         closer than tol are rotated so that one z component vanishes
+//         (tol = 8 eps max(|d|_max, rho));
+//       - each remaining root of f = 1 + rho sum z_i^2 / (d_i - lambda) is bracketed between
+//         consecutive poles and computed in the variable tau = lambda - d_o from the nearer
+//         pole d_o (so that every difference d_i - lambda is formed accurately) by a
+//         safeguarded rational iteration: the pole sums on either side of the root are
+//         replaced by one-pole models matched in value and slope (as in Bunch, Nielsen and
+//         Sorensen, 1978), with bisection whenever the model's root leaves the bracket;
+//       - z is recomputed from the roots (Loewner's formula) so that the eigenvectors
+//         v_j = (zhat_i / (d_i - lambda_j))_i are numerically orthogonal; the new eigenvector
+//         matrix is Q_K V.
+// eigh_backtransform_kernel (grid: 16-column blocks x matrices): V = Q Z by applying
+// H_{n-2}, ..., H_0 to each column block in LDS; sorts into descending eigenvalue order.
+//
+// Workspace per matrix (doubles): reflectors n*n complex (column k = v_k), tau n complex,
+// Z n*n real (column-major; during the merges it holds the coefficient vectors V), eigenvalues
+// n, and an n*n staging area for the merges.
+__host__ __device__ __forceinline__ size_t tql_ws_doubles(int n) {
+  return (size_t)4 * n * n + (size_t)3 * n;
 }
 
-__global__ __launch_bounds__(1024) void eigh_jacobi_log_kernel(int n, int lda,
-                                                               const double *const *in,
-                                                               double *const *evals,
-                                                               double *const *vecs,
-                                                               double4_t *logbuf,
-                                                               int max_sweeps,
-                                                               double *meta_diag,
-                                                               int *meta_rounds) {
-  extern __shared__ double2 smem[];
-  __shared__ Rot rot[64];
-  __shared__ int any_rot, nrounds_s;
-  __shared__ double diag_s[128];
-  __shared__ double red_s[16];
-  const int prob = blockIdx.x;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int np = n + (n & 1);
-  const int h = np / 2;
-  double2 *P = smem;
-  double4_t *lg = logbuf + (size_t)prob * max_sweeps * (np - 1) * h;
-  const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
-  double fro2 = 0.0;
-  for (int idx = tid; idx < np * (np + 1) / 2; idx += nt) {
-    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while ((size_t)i * (i + 1) / 2 > (size_t)idx) --i;
-    while ((size_t)(i + 1) * (i + 2) / 2 <= (size_t)idx) ++i;
-    int j = idx - i * (i + 1) / 2;
-    double2 v = make_double2(0.0, 0.0);
-    if (i < n && j < n) {
-      double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
-      v = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-    }
-    P[idx] = v;
-    fro2 += (i == j ? 1.0 : 2.0) * (v.x * v.x + v.y * v.y);
-  }
-  if (tid == 0) nrounds_s = 0;
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Scratch of one merge (LDS), indexed by position in the merged range.
+struct DcScratch {
+  double *z, *dd, *zK, *dK, *tau, *dorg, *zh, *lam, *rc, *rs, *red;
+  int *perm, *K, *defl, *ra, *rb, *cnt;
+};
+
+__device__ double block_max512(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < 8; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// Merges the solved ranges [lo, k) and [k, hi) coupled by beta (all 512 threads).
+// d: eigenvalues (LDS), Z: eigenvectors (LDS, column-major, leading dimension n);
+// Vg, Wg: n x n global staging areas of this matrix.
+__device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, double *Z,
+                         const DcScratch &S, double *Vg, double *Wg) {
   const double eps = 2.220446049250313e-16;
-  const double thr_abs = 0.1 * eps * sqrt(block_allsum(fro2, red_s));
-  // this thread's 2x2 blocks (I >= J) are the same in every round
-  const int nblk = h * (h + 1) / 2;
-  int bI[3], bJ[3];
-  int nmine = 0;
-  for (int blk = tid; blk < nblk && nmine < 3; blk += nt, ++nmine) {
-    int I = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > blk) --I;
-    while ((I + 1) * (I + 2) / 2 <= blk) ++I;
-    bI[nmine] = I;
-    bJ[nmine] = blk - I * (I + 1) / 2;
+  const int tid = threadIdx.x;
+  constexpr int NT = 512;
+  const int s = hi - lo;
+  const double rho = 2.0 * fabs(beta);
+  const double sg = beta >= 0.0 ? 1.0 : -1.0;
+  // z = (last row of Q1, sign(beta) first row of Q2) / sqrt 2
+  double dmax = 0.0;
+  for (int t = tid; t < s; t += NT) {
+    const int i = lo + t;
+    S.z[t] = (i < k ? Z[(size_t)i * n + k - 1] : sg * Z[(size_t)i * n + k]) * 0.70710678118654752440;
+    S.dd[t] = d[i];
+    dmax = fmax(dmax, fabs(d[i]));
   }
-  int nrounds = 0;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) any_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < np - 1; ++r) {
-      if (tid < h) {
-        int p, q;
-        pair_of(r, tid, np, p, q);
-        double a = P[pk_idx(p, p)].x, dd = P[pk_idx(q, q)].x;
-        double2 b = pk_get(P, p, q);
-        double beta = sqrt(b.x * b.x + b.y * b.y);
-        Rot R;
-        R.p = p; R.q = q;
-        if (beta > 1e-300 && beta > thr_abs && beta > eps * sqrt(fabs(a) * fabs(dd))) {
-          double tau = (dd - a) / (2.0 * beta);
-          double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          double c = 1.0 / sqrt(1.0 + t * t);
-          R.c = c; R.s = t * c;
-          R.wr = b.x / beta; R.wi = -b.y / beta;
-          any_rot = 1;
-        } else {
-          R.c = 1.0; R.s = 0.0; R.wr = 1.0; R.wi = 0.0;
-        }
-        rot[tid] = R;
-        lg[(size_t)nrounds * h + tid] = (double4_t){R.c, R.s, R.wr, R.wi};
-      }
-      __syncthreads();
-      // blocks (I, J) with I >= J cover every unordered element pair once
-      for (int mb = 0; mb < nmine; ++mb) {
-        const int I = bI[mb], J = bJ[mb];
-        Rot ri = rot[I], rj = rot[J];
-        if (ri.s == 0.0 && rj.s == 0.0) continue;
-        double2 b00 = pk_get(P, ri.p, rj.p), b01 = pk_get(P, ri.p, rj.q);
-        double2 b10 = pk_get(P, ri.q, rj.p), b11 = pk_get(P, ri.q, rj.q);
-        // J = diag(1, w) R with R real: apply the phases, then the two real rotations
-        const double2 wj = make_double2(rj.wr, rj.wi), wic = make_double2(ri.wr, -ri.wi);
-        b01 = cmul(b01, wj);
-        b10 = cmul(wic, b10);
-        b11 = cmul(cmul(wic, b11), wj);
-        double2 t00 = make_double2(rj.c * b00.x - rj.s * b01.x, rj.c * b00.y - rj.s * b01.y);
-        double2 t01 = make_double2(rj.s * b00.x + rj.c * b01.x, rj.s * b00.y + rj.c * b01.y);
-        double2 t10 = make_double2(rj.c * b10.x - rj.s * b11.x, rj.c * b10.y - rj.s * b11.y);
-        double2 t11 = make_double2(rj.s * b10.x + rj.c * b11.x, rj.s * b10.y + rj.c * b11.y);
-        double2 n00 = make_double2(ri.c * t00.x - ri.s * t10.x, ri.c * t00.y - ri.s * t10.y);
-        double2 n01 = make_double2(ri.c * t01.x - ri.s * t11.x, ri.c * t01.y - ri.s * t11.y);
-        double2 n10 = make_double2(ri.s * t00.x + ri.c * t10.x, ri.s * t00.y + ri.c * t10.y);
-        double2 n11 = make_double2(ri.s * t01.x + ri.c * t11.x, ri.s * t01.y + ri.c * t11.y);
-        if (I == J) {
-          n00.y = 0.0; n11.y = 0.0;
-          if (ri.s != 0.0) n10 = make_double2(0.0, 0.0);
-          pk_set(P, ri.p, ri.p, n00);
-          pk_set(P, ri.q, ri.q, n11);
-          pk_set(P, ri.q, ri.p, n10);
-        } else {
-          pk_set(P, ri.p, rj.p, n00);
-          pk_set(P, ri.p, rj.q, n01);
-          pk_set(P, ri.q, rj.p, n10);
-          pk_set(P, ri.q, rj.q, n11);
-        }
-      }
-      ++nrounds;
-      __syncthreads();
+  dmax = block_max512(dmax, S.red);
+  const double tol = 8.0 * eps * fmax(dmax, rho);
+  // ascending order of dd (ties by position)
+  for (int t = tid; t < s; t += NT) {
+    const double v = S.dd[t];
+    int r = 0;
+    for (int u = 0; u < s; ++u) {
+      const double w = S.dd[u];
+      r += (w < v) || (w == v && u < t);
     }
-    __syncthreads();
-    int stop = (any_rot == 0);
-    __syncthreads();
-    if (stop) break;
-  }
-  for (int i = tid; i < np; i += nt) meta_diag[(size_t)prob * np + i] = P[pk_idx(i, i)].x;
-  if (tid == 0) meta_rounds[prob] = nrounds;
-}
-
-// Rebuilds the eigenvectors from the rotation log: rows of V evolve independently under the
-// right-multiplied rotations, so each workgroup replays the whole log on 16 rows held in LDS.
-// grid: x = row blocks of 16, y = problem.  Also sorts into descending eigenvalue order.
-__global__ __launch_bounds__(256) void eigh_replay_kernel(int n, const double4_t *logbuf,
-                                                          int max_sweeps,
-                                                          const double *meta_diag,
-                                                          const int *meta_rounds,
-                                                          double *const *evals,
-                                                          double *const *vecs) {
-  __shared__ double2 Vb[16 * 128];
-  __shared__ double dg[128];
-  const int prob = blockIdx.y, r0 = blockIdx.x * 16;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int np = n + (n & 1), h = np / 2;
-  const double4_t *lg = logbuf + (size_t)prob * max_sweeps * (np - 1) * h;
-  const int nrounds = meta_rounds[prob];
-  const int rows = min(16, np - r0);
-  for (int i = tid; i < np; i += nt) dg[i] = meta_diag[(size_t)prob * np + i];
-  for (int idx = tid; idx < rows * np; idx += nt) {
-    int rr = idx / np, c = idx % np;
-    Vb[idx] = make_double2((r0 + rr) == c ? 1.0 : 0.0, 0.0);
+    S.perm[r] = t;
+    S.zK[r] = S.z[t];      // sorted copies for the scan
   }
   __syncthreads();
-  for (int t = 0; t < nrounds; ++t) {
-    const int rr0 = t % (np - 1);
-    const double4_t *lr = lg + (size_t)t * h;
-    for (int it = tid; it < rows * h; it += nt) {
-      int rr = it / h, J = it % h;
-      double4_t R = lr[J];
-      if (R[1] == 0.0) continue;
-      int p, q;
-      pair_of(rr0, J, np, p, q);
-      double2 vp = Vb[rr * np + p];
-      double2 vq = cmul(make_double2(R[2], R[3]), Vb[rr * np + q]);
-      Vb[rr * np + p] = make_double2(R[0] * vp.x - R[1] * vq.x, R[0] * vp.y - R[1] * vq.y);
-      Vb[rr * np + q] = make_double2(R[1] * vp.x + R[0] * vq.x, R[1] * vp.y + R[0] * vq.y);
+  // deflation scan in ascending order (one thread)
+  if (tid == 0) {
+    int nk = 0, nd = 0, nr = 0, prev = -1;
+    for (int r = 0; r < s; ++r) {
+      const int t = S.perm[r];
+      const double zt = S.zK[r];
+      if (rho * fabs(zt) <= tol) {
+        S.defl[nd++] = t;
+        continue;
+      }
+      if (prev >= 0 && fabs(S.dd[t] - S.dd[prev]) <= tol) {
+        const double zp = S.z[prev];
+        const double rr = sqrt(zp * zp + zt * zt);
+        const double c = zt / rr, sn = zp / rr;
+        const double dp = S.dd[prev], dt = S.dd[t];
+        S.dd[prev] = c * c * dp + sn * sn * dt;
+        S.dd[t] = sn * sn * dp + c * c * dt;
+        S.z[prev] = 0.0;
+        S.z[t] = rr;
+        S.ra[nr] = prev;
+        S.rb[nr] = t;
+        S.rc[nr] = c;
+        S.rs[nr] = sn;
+        ++nr;
+        S.defl[nd++] = prev;
+        prev = t;
+        continue;
+      }
+      if (prev >= 0) S.K[nk++] = prev;
+      prev = t;
+    }
+    if (prev >= 0) S.K[nk++] = prev;
+    S.cnt[0] = nk;
+    S.cnt[1] = nd;
+    S.cnt[2] = nr;
+  }
+  __syncthreads();
+  const int nk = S.cnt[0], nr = S.cnt[2];
+  // the deflation rotations act on the columns of Q; each row evolves independently
+  for (int r = lo + tid; r < hi; r += NT)
+    for (int q = 0; q < nr; ++q) {
+      const size_t ca = (size_t)(lo + S.ra[q]) * n + r, cb = (size_t)(lo + S.rb[q]) * n + r;
+      const double c = S.rc[q], sn = S.rs[q];
+      const double qa = Z[ca], qb = Z[cb];
+      Z[ca] = c * qa - sn * qb;
+      Z[cb] = sn * qa + c * qb;
+    }
+  __syncthreads();
+  // gather: kept columns of Q (in ascending eigenvalue order), then the deflated ones, to Wg;
+  // kept z and d contiguous
+  for (int idx = tid; idx < s * s; idx += NT) {
+    const int c = idx / s, r = lo + idx % s;
+    const int col = c < nk ? S.K[c] : S.defl[c - nk];
+    Wg[(size_t)(lo + c) * n + r] = Z[(size_t)(lo + col) * n + r];
+  }
+  for (int c = tid; c < nk; c += NT) {
+    S.zK[c] = S.z[S.K[c]];
+    S.dK[c] = S.dd[S.K[c]];
+  }
+  __syncthreads();
+  // secular roots: four lanes per root, each summing a quarter of the terms
+  {
+    const int q4 = tid & 3;
+    const double *zK = S.zK, *dK = S.dK;
+    for (int j = tid >> 2; j < nk; j += NT / 4) {
+      double zs = 0.0;
+      for (int t = q4; t < nk; t += 4) zs += zK[t] * zK[t];
+      zs += __shfl_xor(zs, 1, 64);
+      zs += __shfl_xor(zs, 2, 64);
+      const double dj = dK[j];
+      int o = j;
+      double a, b;
+      if (j + 1 < nk) {
+        const double half = 0.5 * (dK[j + 1] - dj);
+        double f = 0.0;
+        for (int t = q4; t < nk; t += 4) f += zK[t] * zK[t] / ((dK[t] - dj) - half);
+        f += __shfl_xor(f, 1, 64);
+        f += __shfl_xor(f, 2, 64);
+        f = 1.0 + rho * f;
+        if (f >= 0.0) { a = 0.0; b = half; }
+        else { o = j + 1; a = -half; b = 0.0; }
+      } else {
+        a = 0.0;
+        b = rho * zs;
+      }
+      // Safeguarded rational iteration: near tau, the poles at or left of d_j (psi) and right
+      // of it (phi) are modelled as p + q/(dL - x) and r + s/(dR - x), matched in value and
+      // slope; the model's root (a quadratic) is taken when it lies inside the bracket [a, b],
+      // else the bracket midpoint.  Stops when f vanishes to rounding or the bracket closes.
+      const double dorg = dK[o];
+      const bool hasR = j + 1 < nk;
+      const double dL = dK[j] - dorg, dR = hasR ? dK[j + 1] - dorg : 0.0;
+      double tau = 0.5 * (a + b);
+      for (int it = 0; it < 96; ++it) {
+        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+        for (int t = q4; t < nk; t += 4) {
+          const double r = 1.0 / ((dK[t] - dorg) - tau);
+          const double w = zK[t] * zK[t] * r;
+          if (t <= j) {
+            psi += w;
+            dpsi += w * r;
+          } else {
+            phi += w;
+            dphi += w * r;
+          }
+        }
+        psi += __shfl_xor(psi, 1, 64);
+        dpsi += __shfl_xor(dpsi, 1, 64);
+        phi += __shfl_xor(phi, 1, 64);
+        dphi += __shfl_xor(dphi, 1, 64);
+        psi += __shfl_xor(psi, 2, 64);
+        dpsi += __shfl_xor(dpsi, 2, 64);
+        phi += __shfl_xor(phi, 2, 64);
+        dphi += __shfl_xor(dphi, 2, 64);
+        psi *= rho;
+        dpsi *= rho;
+        phi *= rho;
+        dphi *= rho;
+        const double f = 1.0 + psi + phi;
+        if (fabs(f) <= eps * (1.0 + fabs(psi) + phi)) break;
+        if (f > 0.0) b = tau;
+        else a = tau;
+        if (!(b - a > 4.0 * eps * fmax(fabs(a), fabs(b)))) break;
+        const double hL = dL - tau;
+        const double Qm = dpsi * hL * hL, Pm = psi - dpsi * hL;
+        double x = 0.5 * (a + b);
+        if (hasR) {
+          const double hR = dR - tau;
+          const double Sm = dphi * hR * hR, Rm = phi - dphi * hR;
+          const double C = 1.0 + Pm + Rm;
+          const double B = C * (dL + dR) + Qm + Sm, Dq = C * dL * dR + Qm * dR + Sm * dL;
+          const double disc = B * B - 4.0 * C * Dq;
+          if (C != 0.0 && disc >= 0.0) {
+            const double sq = sqrt(disc), den = B >= 0.0 ? B + sq : B - sq;
+            const double u1 = den / (2.0 * C);
+            const double u2 = den != 0.0 ? 2.0 * Dq / den : u1;
+            if (u1 > a && u1 < b) x = u1;
+            else if (u2 > a && u2 < b) x = u2;
+          }
+        } else {
+          const double C = 1.0 + Pm + phi;
+          if (C > 0.0) {
+            const double u = dL + Qm / C;
+            if (u > a && u < b) x = u;
+          }
+        }
+        if (x == tau) break;
+        tau = x;
+      }
+      if (q4 == 0) {
+        S.dorg[j] = dorg;
+        S.tau[j] = tau;
+      }
+    }
+  }
+  __syncthreads();
+  // zhat_t^2 = (lambda_{nk-1} - d_t)/rho * prod_{j<t} (lambda_j - d_t)/(d_j - d_t)
+  //            * prod_{t<=j<nk-1} (lambda_j - d_t)/(d_{j+1} - d_t)      (d = kept, ascending)
+  for (int t = tid >> 2; t < nk; t += NT / 4) {
+    const int q4 = tid & 3;
+    const double dt = S.dK[t];
+    double prod = q4 == 0 ? (S.tau[nk - 1] - (dt - S.dorg[nk - 1])) / rho : 1.0;
+    for (int j = q4; j < t; j += 4) prod *= (S.tau[j] - (dt - S.dorg[j])) / (S.dK[j] - dt);
+    for (int j = t + q4; j < nk - 1; j += 4) prod *= (S.tau[j] - (dt - S.dorg[j])) / (S.dK[j + 1] - dt);
+    prod *= __shfl_xor(prod, 1, 64);
+    prod *= __shfl_xor(prod, 2, 64);
+    if (q4 == 0) S.zh[t] = copysign(sqrt(fmax(prod, 0.0)), S.zK[t]);
+  }
+  __syncthreads();
+  // coefficient vectors v_j (unnormalised; the norms are taken in the product below), column j
+  // at Vg[(lo + j) n + lo ..]
+  for (int idx = tid; idx < nk * nk; idx += NT) {
+    const int j = idx / nk, t = idx % nk;
+    Vg[(size_t)(lo + j) * n + lo + t] = S.zh[t] / ((S.dK[t] - S.dorg[j]) - S.tau[j]);
+  }
+  for (int j = tid; j < nk; j += NT) S.lam[j] = S.dorg[j] + S.tau[j];
+  __syncthreads();
+  // new eigenvectors Q_K V (4 x 4 register tiles), then the deflated columns
+  {
+    const int tr = (s + 3) >> 2, tc = (nk + 3) >> 2;
+    for (int tile = tid; tile < tr * tc; tile += NT) {
+      const int r0 = lo + (tile % tr) * 4, j0 = (tile / tr) * 4;
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      const double *vcol[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) vcol[v] = Vg + (size_t)(lo + min(j0 + v, nk - 1)) * n + lo;
+      double nrm[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int t = 0; t < nk; ++t) {
+        const double *wcol = Wg + (size_t)(lo + t) * n;
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = r0 + u < hi ? wcol[r0 + u] : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          b[v] = vcol[v][t];
+          nrm[v] += b[v] * b[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double inv = 1.0 / sqrt(nrm[v]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + v < nk && r0 + u < hi) Z[(size_t)(lo + j0 + v) * n + r0 + u] = acc[u][v] * inv;
+      }
+    }
+    for (int idx = tid; idx < s * (s - nk); idx += NT) {
+      const int j = nk + idx / s, r = lo + idx % s;
+      Z[(size_t)(lo + j) * n + r] = Wg[(size_t)(lo + j) * n + r];
+    }
+    for (int j = tid; j < s; j += NT) d[lo + j] = j < nk ? S.lam[j] : S.dd[S.defl[j - nk]];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int dc_bound(int q, int n, int depth) {
+  return (int)(((long)q * n) >> depth);
+}
+
+__global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
+                                                              const double *const *in,
+                                                              double *ws) {
+  extern __shared__ double2 smem[];
+  __shared__ double d_s[128], e_s[128];
+  // phase-local scratch: reflector vectors (stage 1), leaf matrices (leaves), merge arrays
+  __shared__ __attribute__((aligned(16))) double sbuf[1664];
+  __shared__ double2 tau_sh;
+  double2 *v_s = reinterpret_cast<double2 *>(sbuf), *w_s = v_s + 128;
+  const int prob = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nw = blockDim.x >> 6;
+  double *base = ws + (size_t)prob * tql_ws_doubles(n);
+  double2 *hh = reinterpret_cast<double2 *>(base);
+  double2 *tau_g = hh + (size_t)n * n;
+  double *Zg = reinterpret_cast<double *>(tau_g + n);
+  double *dg = Zg + (size_t)n * n;
+  double *Wg = dg + n;
+  double2 *P = smem;
+  const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+
+  // Hermitian part of the input, lower triangle packed by rows
+  for (int i = wave; i < n; i += nw)
+    for (int j = lane; j <= i; j += 64) {
+      double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
+      P[pk_idx(i, j)] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+    }
+  __syncthreads();
+
+  // ---- 1. tridiagonal reduction ----
+  for (int k = 0; k + 1 < n; ++k) {
+    const int m = n - 1 - k;          // length of the column below the diagonal
+    if (wave == 0) {
+      double sq = 0.0;
+      for (int i = 1 + lane; i < m; i += 64) {
+        double2 x = P[pk_idx(k + 1 + i, k)];
+        sq += x.x * x.x + x.y * x.y;
+      }
+      sq = wave_sum(sq);
+      const double2 alpha = P[pk_idx(k + 1, k)];
+      double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+      double beta = alpha.x;
+      if (sq > 0.0 || alpha.y != 0.0) {
+        beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sq), alpha.x);
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
+        const double dn = den.x * den.x + den.y * den.y;
+        scale = make_double2(den.x / dn, -den.y / dn);
+      }
+      for (int i = lane; i < m; i += 64) {
+        double2 vi = i == 0 ? make_double2(1.0, 0.0) : cmul(P[pk_idx(k + 1 + i, k)], scale);
+        v_s[i] = vi;
+        hh[(size_t)k * n + k + 1 + i] = vi;
+      }
+      if (lane == 0) {
+        tau_sh = tau;
+        tau_g[k] = tau;
+        e_s[k] = beta;
+        d_s[k] = P[pk_idx(k, k)].x;
+      }
+    }
+    __syncthreads();
+    const double2 tau = tau_sh;
+    if (tau.x == 0.0 && tau.y == 0.0) continue;   // H_k = I (uniform over the block)
+    // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): 4 threads per row
+    {
+      const int r = tid >> 2, q = tid & 3;
+      double2 acc = make_double2(0.0, 0.0);
+      if (r < m) {
+        const int gi = k + 1 + r;
+        for (int c = q; c < m; c += 4) {
+          const int gj = k + 1 + c;
+          const double2 a = gj <= gi ? P[pk_idx(gi, gj)] : cconj(P[pk_idx(gj, gi)]);
+          const double2 vc = v_s[c];
+          acc.x += a.x * vc.x - a.y * vc.y;
+          acc.y += a.x * vc.y + a.y * vc.x;
+        }
+      }
+      acc.x += __shfl_xor(acc.x, 1, 64);
+      acc.y += __shfl_xor(acc.y, 1, 64);
+      acc.x += __shfl_xor(acc.x, 2, 64);
+      acc.y += __shfl_xor(acc.y, 2, 64);
+      if (r < m && q == 0) w_s[r] = cmul(tau, acc);
+    }
+    __syncthreads();
+    // w = x + a v with a = -(1/2) Re(conj(tau) v^H x)
+    if (wave == 0) {
+      double dr = 0.0, di = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        const double2 vi = v_s[i], xi = w_s[i];
+        dr += vi.x * xi.x + vi.y * xi.y;
+        di += vi.x * xi.y - vi.y * xi.x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double a = -0.5 * (tau.x * dr + tau.y * di);
+      for (int i = lane; i < m; i += 64) {
+        const double2 vi = v_s[i];
+        w_s[i] = make_double2(w_s[i].x + a * vi.x, w_s[i].y + a * vi.y);
+      }
+    }
+    __syncthreads();
+    // S <- S - v w^H - w v^H on the lower triangle
+    for (int rr = wave; rr < m; rr += nw) {
+      const int gi = k + 1 + rr;
+      const double2 vi = v_s[rr], wi = w_s[rr];
+      for (int c = lane; c <= rr; c += 64) {
+        const double2 vc = v_s[c], wc = w_s[c];
+        double2 &a = P[pk_idx(gi, k + 1 + c)];
+        double ur = vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
+        double ui = vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
+        a = make_double2(a.x - ur, c == rr ? 0.0 : a.y - ui);
+      }
     }
     __syncthreads();
   }
+  if (tid == 0) {
+    d_s[n - 1] = P[pk_idx(n - 1, n - 1)].x;
+    e_s[n - 1] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- 2. divide and conquer on (d, e) ----
+  // Z = I (column-major, in the LDS that held the matrix); tear the couplings at the seven
+  // split points of the top three levels
+  double *Z = reinterpret_cast<double *>(smem);
+  for (int idx = tid; idx < n * n; idx += blockDim.x) Z[idx] = (idx % (n + 1)) == 0 ? 1.0 : 0.0;
+  __syncthreads();
+  if (tid == 0)
+    for (int D = 0; D < 3; ++D)
+      for (int q = 0; q < (1 << D); ++q) {
+        const int k = dc_bound(2 * q + 1, n, D + 1);
+        if (k <= 0 || k >= n) continue;
+        const double r = fabs(e_s[k - 1]);
+        d_s[k - 1] -= r;
+        d_s[k] -= r;
+      }
+  __syncthreads();
+  // leaves: the eight ranges of depth 3 (8..16 entries), cyclic Jacobi by one wave each on the
+  // packed 16 x 16 tridiagonal block (padding indices have no coupling and never rotate)
+  {
+    const double eps = 2.220446049250313e-16;
+    const int lo = dc_bound(wave, n, 3), m = dc_bound(wave + 1, n, 3) - lo;
+    double *A = sbuf + wave * 136;
+    double *rcs = sbuf + 1088 + wave * 16;          // c[8], s[8]
+    auto at = [&](int i, int j) -> double & { return i >= j ? A[pk_idx(i, j)] : A[pk_idx(j, i)]; };
+    for (int idx = lane; idx < 136; idx += 64) A[idx] = 0.0;
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    double fro2 = 0.0;
+    if (lane < m) {
+      A[pk_idx(lane, lane)] = d_s[lo + lane];
+      fro2 = d_s[lo + lane] * d_s[lo + lane];
+      if (lane + 1 < m) {
+        A[pk_idx(lane + 1, lane)] = e_s[lo + lane];
+        fro2 += 2.0 * e_s[lo + lane] * e_s[lo + lane];
+      }
+    }
+    const double thr_abs = 0.5 * eps * sqrt(wave_sum(fro2));
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      bool rotated = false;
+      for (int r = 0; r < 15; ++r) {
+        if (lane < 8) {
+          int p, q;
+          pair_of(r, lane, 16, p, q);
+          double c = 1.0, sn = 0.0;
+          if (p < m && q < m) {
+            const double app = at(p, p), aqq = at(q, q), apq = at(p, q);
+            if (fabs(apq) > thr_abs && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
+              const double tau = (aqq - app) / (2.0 * apq);
+              const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              c = 1.0 / sqrt(1.0 + t * t);
+              sn = t * c;
+              rotated = true;
+            }
+          }
+          rcs[lane] = c;
+          rcs[8 + lane] = sn;
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        {
+          const int I = lane >> 3, J = lane & 7;
+          const double ci = rcs[I], si = rcs[8 + I], cj = rcs[J], sj = rcs[8 + J];
+          if (I >= J && (si != 0.0 || sj != 0.0)) {
+            int pi, qi, pj, qj;
+            pair_of(r, I, 16, pi, qi);
+            pair_of(r, J, 16, pj, qj);
+            const double b00 = at(pi, pj), b01 = at(pi, qj), b10 = at(qi, pj), b11 = at(qi, qj);
+            const double t00 = cj * b00 - sj * b01, t01 = sj * b00 + cj * b01;
+            const double t10 = cj * b10 - sj * b11, t11 = sj * b10 + cj * b11;
+            const double n00 = ci * t00 - si * t10, n01 = ci * t01 - si * t11;
+            const double n10 = si * t00 + ci * t10, n11 = si * t01 + ci * t11;
+            if (I == J) {
+              at(pi, pi) = n00;
+              at(qi, qi) = n11;
+              at(qi, pi) = si != 0.0 ? 0.0 : n10;
+            } else {
+              at(pi, pj) = n00;
+              at(pi, qj) = n01;
+              at(qi, pj) = n10;
+              at(qi, qj) = n11;
+            }
+          }
+        }
+        for (int it = lane; it < 128; it += 64) {
+          const int row = it >> 3, J = it & 7;
+          const double c = rcs[J], sn = rcs[8 + J];
+          if (sn != 0.0 && row < m) {
+            int p, q;
+            pair_of(r, J, 16, p, q);
+            double &vp = Z[(size_t)(lo + p) * n + lo + row], &vq = Z[(size_t)(lo + q) * n + lo + row];
+            const double a = vp, b = vq;
+            vp = c * a - sn * b;
+            vq = sn * a + c * b;
+          }
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (__ballot(rotated) == 0) break;
+    }
+    if (lane < m) d_s[lo + lane] = A[pk_idx(lane, lane)];
+  }
+  __syncthreads();
+  // merges of the top three levels by the whole workgroup
+  {
+    DcScratch S;
+    S.z = sbuf; S.dd = sbuf + 128; S.zK = sbuf + 256; S.dK = sbuf + 384; S.tau = sbuf + 512;
+    S.dorg = sbuf + 640; S.zh = sbuf + 768; S.lam = sbuf + 896; S.rc = sbuf + 1024;
+    S.rs = sbuf + 1152;
+    int *ib = reinterpret_cast<int *>(sbuf + 1280);
+    S.perm = ib; S.K = ib + 128; S.defl = ib + 256; S.ra = ib + 384; S.rb = ib + 512;
+    S.cnt = ib + 640;
+    S.red = sbuf + 1608;
+    for (int D = 2; D >= 0; --D)
+      for (int q = 0; q < (1 << D); ++q) {
+        const int lo = dc_bound(q, n, D), hi = dc_bound(q + 1, n, D);
+        const int k = dc_bound(2 * q + 1, n, D + 1);
+        if (lo < k && k < hi) dc_merge(n, lo, k, hi, e_s[k - 1], d_s, Z, S, Zg, Wg);
+      }
+  }
+  for (int idx = tid; idx < n * n; idx += blockDim.x) Zg[idx] = Z[idx];
+  for (int i = tid; i < n; i += blockDim.x) dg[i] = d_s[i];
+}
+
+__global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const double *ws,
+                                                                 double *const *evals,
+                                                                 double *const *vecs) {
+  constexpr int CB = 16;
+  __shared__ double2 Vb[128 * CB];
+  __shared__ double2 vk[128];
+  __shared__ double2 part[4][CB];
+  __shared__ double2 wk[CB];
+  __shared__ double dsh[128];
+  const int prob = blockIdx.y, c0 = blockIdx.x * CB;
+  const int tid = threadIdx.x;
+  const double *base = ws + (size_t)prob * tql_ws_doubles(n);
+  const double2 *hh = reinterpret_cast<const double2 *>(base);
+  const double2 *tau_g = hh + (size_t)n * n;
+  const double *Zg = reinterpret_cast<const double *>(tau_g + n);
+  const double *dg = Zg + (size_t)n * n;
+  const int cols = min(CB, n - c0);
+  for (int idx = tid; idx < n * CB; idx += 256) {
+    const int r = idx / CB, c = idx % CB;
+    Vb[idx] = make_double2(c < cols ? Zg[(size_t)(c0 + c) * n + r] : 0.0, 0.0);
+  }
+  for (int i = tid; i < n; i += 256) dsh[i] = dg[i];
+  __syncthreads();
+  const int c = tid & (CB - 1), part_id = tid >> 4;   // 16 row groups per column
+  for (int k = n - 2; k >= 0; --k) {
+    const double2 tau = tau_g[k];
+    if (tau.x == 0.0 && tau.y == 0.0) continue;
+    const int m = n - 1 - k;
+    for (int i = tid; i < m; i += 256) vk[i] = hh[(size_t)k * n + k + 1 + i];
+    __syncthreads();
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = part_id; i < m; i += 16) {
+      const double2 v = vk[i], x = Vb[(k + 1 + i) * CB + c];
+      acc.x += v.x * x.x + v.y * x.y;      // conj(v) x
+      acc.y += v.x * x.y - v.y * x.x;
+    }
+    acc.x += __shfl_xor(acc.x, 16, 64);
+    acc.y += __shfl_xor(acc.y, 16, 64);
+    acc.x += __shfl_xor(acc.x, 32, 64);
+    acc.y += __shfl_xor(acc.y, 32, 64);
+    if ((tid & 63) < CB) part[tid >> 6][c] = acc;
+    __syncthreads();
+    if (tid < CB) {
+      double2 t = make_double2(part[0][tid].x + part[1][tid].x + part[2][tid].x + part[3][tid].x,
+                               part[0][tid].y + part[1][tid].y + part[2][tid].y + part[3][tid].y);
+      wk[tid] = cmul(tau, t);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < m * CB; idx += 256) {
+      const int i = idx / CB, cc = idx % CB;
+      const double2 u = cmul(vk[i], wk[cc]);
+      double2 &x = Vb[(k + 1 + i) * CB + cc];
+      x = make_double2(x.x - u.x, x.y - u.y);
+    }
+    __syncthreads();
+  }
+  // descending order (rank sort, ties by index) and output
   double *ev = evals[prob];
   double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
-  for (int i = tid; i < n; i += nt) {
-    double li = dg[i];
+  for (int cc = 0; cc < cols; ++cc) {
+    const int j = c0 + cc;
+    const double lj = dsh[j];
     int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      double lj = dg[j];
-      rank += (lj > li) || (lj == li && j < i);
+    for (int i = 0; i < n; ++i) {
+      const double li = dsh[i];
+      rank += (li > lj) || (li == lj && i < j);
     }
-    for (int rr = 0; rr < rows; ++rr)
-      if (r0 + rr < n) vo[(size_t)(r0 + rr) * n + rank] = Vb[rr * np + i];
-    if (blockIdx.x == 0) ev[rank] = li;
+    for (int r = tid; r < n; r += 256) vo[(size_t)r * n + rank] = Vb[r * CB + cc];
+    if (tid == 0) ev[rank] = lj;
   }
 }
 
@@ -1002,8 +1461,8 @@ class HipBackend : public Backend {
     }
     HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
-    HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_log_kernel,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_dc_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
   }
   ~HipBackend() override {
     for (auto &e : ev_)
@@ -1179,10 +1638,8 @@ class HipBackend : public Backend {
       stale_check("eigh_jacobi_kernel");
       hipLaunchKernelGGL(eigh_jacobi_kernel<true>, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
                          evals, vecs, (double2 *)nullptr, 60);
-    } else if (np <= 128) {
-      const int sweeps = 24;
-      size_t logb = (size_t)nprob * sweeps * (np - 1) * (np / 2) * sizeof(double4_t);
-      size_t need = logb + (size_t)nprob * np * sizeof(double) + (size_t)nprob * sizeof(int);
+    } else if (n <= 128) {
+      size_t need = (size_t)nprob * tql_ws_doubles(n) * sizeof(double);
       if (need > lws_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
         if (lws_) HIPCHK(hipFree(lws_));
@@ -1190,22 +1647,19 @@ class HipBackend : public Backend {
         lws_bytes_ = 0;
         if (hipMalloc(&lws_, need) != hipSuccess) {
           err_ = -4;
-          errmsg_ = "eigh rotation log allocation failed";
+          errmsg_ = "eigh workspace allocation failed";
           return;
         }
         lws_bytes_ = need;
       }
-      size_t sm = std::max((size_t)np * (np + 1) / 2, (size_t)64 * np) * sizeof(double2);
-      stale_check("eigh_jacobi_log_kernel");
-      double *mdiag = (double *)((char *)lws_ + logb);
-      int *mrounds = (int *)(mdiag + (size_t)nprob * np);
-      hipLaunchKernelGGL(eigh_jacobi_log_kernel, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
-                         evals, vecs, (double4_t *)lws_, sweeps, mdiag, mrounds);
-      launch_check("eigh_jacobi_log_kernel");
-      stale_check("eigh_replay_kernel");
-      hipLaunchKernelGGL(eigh_replay_kernel, dim3((np + 15) / 16, nprob), dim3(256), 0, s_, n,
-                         (const double4_t *)lws_, sweeps, (const double *)mdiag,
-                         (const int *)mrounds, evals, vecs);
+      size_t sm = std::max((size_t)n * (n + 1) / 2 * sizeof(double2), (size_t)n * n * sizeof(double));
+      stale_check("eigh_tridiag_dc_kernel");
+      hipLaunchKernelGGL(eigh_tridiag_dc_kernel, dim3(nprob), dim3(512), sm, s_, n, lda, in,
+                         (double *)lws_);
+      launch_check("eigh_tridiag_dc_kernel");
+      stale_check("eigh_backtransform_kernel");
+      hipLaunchKernelGGL(eigh_backtransform_kernel, dim3((n + 15) / 16, nprob), dim3(256), 0, s_,
+                         n, (const double *)lws_, evals, vecs);
     } else {
       size_t need = (size_t)nprob * 2 * np * np * sizeof(double2);
       if (need > gws_bytes_) {

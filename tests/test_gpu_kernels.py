@@ -120,20 +120,31 @@ def test_gemm_rejects_out_of_bounds_descriptor(ctx):
         ctx.test_gemm(d, A, np.zeros(64 * 64, complex), np.zeros(64 * 64, complex))
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 63, 64, 65, 128, 200])
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 63, 64, 65, 97, 127, 128, 200])
 def test_eigh_matches_numpy(ctx, n):
     print(f"[eigh] n={n}", flush=True)
     rng = np.random.default_rng(n)
-    nprob = 3
+    nprob = 6
     X = _rand(rng, nprob, n, n)
     A = X + X.conj().transpose(0, 2, 1)
-    # one PSD, rank-deficient problem with a wide spectrum (as in the Gram matrices)
+    # a PSD, rank-deficient problem with a wide spectrum (as in the Gram matrices)
     Y = _rand(rng, n, max(1, n // 3)) * np.logspace(0, -6, max(1, n // 3))[None, :]
     A[1] = Y @ Y.conj().T
+    # degenerate spectra: zero, identity, two repeated eigenvalues in a random basis
+    A[2] = 0.0
+    A[3] = np.eye(n)
+    U, _ = np.linalg.qr(_rand(rng, n, n))
+    lam = np.where(np.arange(n) < n // 2, 1.0, -0.5)
+    A[4] = (U * lam[None, :]) @ U.conj().T
+    # a Theta^H Theta-like matrix: rank n/2, singular values from 1 down to 1e-6
+    k = max(1, n // 2)
+    Y = _rand(rng, 2 * n, k) * np.logspace(0, -6, k)[None, :]
+    Y = Y @ _rand(rng, k, n)
+    A[5] = Y.conj().T @ Y
     ev, V = ctx.test_eigh(A)
     for p in range(nprob):
         ref = np.sort(np.linalg.eigvalsh(A[p]))[::-1]
-        scale = np.abs(ref).max()
+        scale = max(np.abs(ref).max(), 1e-300)
         assert np.abs(ev[p] - ref).max() < 1e-13 * scale * max(1, n / 16)
         assert np.all(np.diff(ev[p]) <= 1e-15 * scale)
         # eigenvectors: orthonormal and A V = V diag(ev)
