@@ -2,8 +2,9 @@
 //
 //  * gemm_kernel: grouped, batched complex GEMM on MFMA (FP64: v_mfma_f64_16x16x4f64; FP32 mode:
 //                 v_mfma_f32_16x16x4f32 with FP64 storage and FP64 split-K sums).  Complex
-//                 products in real-split form: four real MFMA accumulators per 16x16 tile
-//                 (re*re, im*im, re*im, im*re), combined in the epilogue.  Operands are staged
+//                 products by the 3M method: three real MFMA accumulators per 16x16 tile,
+//                 P1 = sum re*re, P2 = sum im*im, P3 = sum (re+im)*(re+im), combined in the
+//                 epilogue as re = P1 - P2, im = P3 - P1 - P2.  Operands are staged
 //                 through LDS in split re/im planes; the global loads follow whichever index is
 //                 unit-stride so they coalesce for every leg ordering of the site tensors.
 //  * eigh: batched Hermitian eigendecomposition in FP64.  n <= 64 and n > 128: cyclic Jacobi
@@ -162,13 +163,13 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
     }
   };
 
-  acc_t acc[2][2][4];
+  acc_t acc[2][2][3];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[i][j][t] = (acc_t){T(0), T(0), T(0), T(0)};
+      for (int t = 0; t < 3; ++t) acc[i][j][t] = (acc_t){T(0), T(0), T(0), T(0)};
 
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
@@ -186,14 +187,19 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         br[t] = Bs[0][kr][wn + t * 16 + (lane & 15)];
         bi[t] = Bs[1][kr][wn + t * 16 + (lane & 15)];
       }
+      T as[2], bs[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        as[t] = ar[t] + ai[t];
+        bs[t] = br[t] + bi[t];
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc[i][j][0] = MT::mma(ar[i], br[j], acc[i][j][0]);
           acc[i][j][1] = MT::mma(ai[i], bi[j], acc[i][j][1]);
-          acc[i][j][2] = MT::mma(ar[i], bi[j], acc[i][j][2]);
-          acc[i][j][3] = MT::mma(ai[i], br[j], acc[i][j][3]);
+          acc[i][j][2] = MT::mma(as[i], bs[j], acc[i][j][2]);
         }
     }
     __syncthreads();
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         int ng = n0 + wn + j * 16 + (lane & 15);
         if (mg >= d.M || ng >= d.N) continue;
         double cr = (double)acc[i][j][0][r] - (double)acc[i][j][1][r];
-        double ci = (double)acc[i][j][2][r] + (double)acc[i][j][3][r];
+        double ci = (double)acc[i][j][2][r] - (double)acc[i][j][0][r] - (double)acc[i][j][1][r];
         if (Wp) {
           Wp[(size_t)mg * d.N + ng] = make_double2(cr, ci);
           continue;
@@ -1549,8 +1555,8 @@ class HipBackend : public Backend {
     // split K when the output alone cannot fill the machine
     int blocks = tiles * d.batch * nprob;
     int ksplit = 1, kchunk = d.K;
-    if (blocks < 512 && d.K >= 512) {
-      int want = std::min((512 + blocks - 1) / blocks, d.K / 256);
+    if (blocks < 1024 && d.K >= 512) {
+      int want = std::min((1024 + blocks - 1) / blocks, d.K / 256);
       if (want > 1) {
         kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
         ksplit = (d.K + kchunk - 1) / kchunk;

@@ -1,6 +1,8 @@
 """Device primitives against independent host computations (numpy): the complex FP64 MFMA
 GEMM with composite strides, conjugation, batches and grouped problems, and the batched FP64
-Hermitian Jacobi eigensolver."""
+Hermitian eigensolver (Jacobi, and Householder + divide and conquer for 64 < n <= 128)."""
+import zlib
+
 import numpy as np
 import pytest
 
@@ -85,7 +87,7 @@ def test_gemm_fp32_mode(ctx, name, desc, nprob):
     """FP32 MFMA mode: operands rounded to FP32, FP32 accumulation per K chunk; the error is at
     FP32 level relative to the operand scale."""
     print(f"[gemm fp32] case {name} nprob={nprob}", flush=True)
-    rng = np.random.default_rng(abs(hash(name)) % 2**32 + 1)
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 1)
     asz, bsz, csz = _extent(desc, "a"), _extent(desc, "b"), _extent(desc, "c")
     A = _rand(rng, nprob * asz)
     Bm = _rand(rng, nprob * bsz)
@@ -101,7 +103,7 @@ def test_gemm_fp32_mode(ctx, name, desc, nprob):
 @pytest.mark.parametrize("name,desc,nprob", CASES, ids=[c[0] for c in CASES])
 def test_gemm_matches_numpy(ctx, name, desc, nprob):
     print(f"[gemm] case {name} nprob={nprob}", flush=True)
-    rng = np.random.default_rng(abs(hash(name)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
     asz, bsz, csz = _extent(desc, "a"), _extent(desc, "b"), _extent(desc, "c")
     A = _rand(rng, nprob * asz)
     Bm = _rand(rng, nprob * bsz)
