@@ -208,6 +208,20 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
   double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
   double2 *Wp = W ? W + (((size_t)prob * d.batch + bat) * ksplit + kz) * (size_t)d.M * d.N
                   : nullptr;
+  // output offsets: 8 distinct rows and 2 distinct columns per thread
+  long roff[2][4], coff[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mg = m0 + wm + i * 16 + MT::row(lane, r);
+      roff[i][r] = (!Wp && mg < d.M) ? cidx(mg, d.Mi, d.c_mo, d.c_mi) : 0;
+    }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int ng = n0 + wn + j * 16 + (lane & 15);
+    coff[j] = (!Wp && ng < d.N) ? cidx(ng, d.Ni, d.c_no, d.c_ni) : 0;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -225,7 +239,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         }
         double vr = d.alpha_re * cr - d.alpha_im * ci;
         double vi = d.alpha_re * ci + d.alpha_im * cr;
-        long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
+        long off = roff[i][r] + coff[j];
         if (d.beta) {
           double2 o = C[off];
           vr += o.x;
