@@ -7,11 +7,11 @@
 //                 epilogue as re = P1 - P2, im = P3 - P1 - P2.  Operands are staged
 //                 through LDS in split re/im planes; the global loads follow whichever index is
 //                 unit-stride so they coalesce for every leg ordering of the site tensors.
-//  * eigh: batched Hermitian eigendecomposition in FP64.  n <= 64 and n > 128: cyclic Jacobi
+//  * eigh: batched Hermitian eigendecomposition in FP64.  n < 32 and n > 128: cyclic Jacobi
 //          with the parallel round-robin ordering (n/2 disjoint rotations per round, all 2x2
-//          block updates of a round in parallel; LDS up to n = 64, else a global work area).
-//          64 < n <= 128: Householder tridiagonalisation and implicit QL, one workgroup per
-//          matrix, then a column-parallel back-transformation.
+//          block updates of a round in parallel; LDS for n < 32, else a global work area).
+//          32 <= n <= 128: Householder tridiagonalisation and divide and conquer, one
+//          workgroup per matrix, then a column-parallel back-transformation.
 //  * small kernels for the X rotations, message square roots, Gram factor, the gate block,
 //    truncation, BP normalisation/residual and the site density matrices.
 #include <hip/hip_runtime.h>
@@ -438,7 +438,7 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Hermitian eigensolver for 64 < n <= 128 in two kernels.
+// Hermitian eigensolver for 32 <= n <= 128 in two kernels.
 //
 // eigh_tridiag_dc_kernel (one workgroup of 512 threads per matrix):
 //  1. Householder reduction to real symmetric tridiagonal form, A = Q T Q^H with
@@ -1167,21 +1167,28 @@ __global__ __launch_bounds__(1024) void gram_chol_kernel(int n, const double *co
     __syncthreads();
   }
   const int r = rank_s;
-  // X = L1^{-1}: L1[i][m] = L[perm[i]][m] (i, m < r), lower triangular
-  for (int j = tid; j < r; j += nt) {
-    for (int i = j; i < r; ++i) {
-      double sr = (i == j) ? 1.0 : 0.0, si = 0.0;
-      const double2 *Li = L + (size_t)perm[i] * n;
-      for (int mm = j; mm < i; ++mm) {
-        double2 a = Li[mm], x = X[(size_t)mm * n + j];
-        sr -= a.x * x.x - a.y * x.y;
-        si -= a.x * x.y + a.y * x.x;
+  // X = L1^{-1}: L1[i][m] = L[perm[i]][m] (i, m < r), lower triangular.  Forward substitution
+  // row by row, X[i][j] = (delta_ij - sum_{j<=m<i} L1[i][m] X[m][j]) / L1[i][i], with all
+  // columns j <= i of a row at once, eight threads per column splitting the sum.
+  for (int i = 0; i < r; ++i) {
+    const double2 *Li = L + (size_t)perm[i] * n;
+    const double inv = 1.0 / Li[i].x;      // real positive pivot
+    const int q = tid & 7;
+    for (int j = tid >> 3; j <= i; j += nt >> 3) {
+      double sr = 0.0, si = 0.0;
+      for (int mm = j + q; mm < i; mm += 8) {
+        const double2 a = Li[mm], x = X[(size_t)mm * n + j];
+        sr += a.x * x.x - a.y * x.y;
+        si += a.x * x.y + a.y * x.x;
       }
-      double2 dgl = Li[i];       // real positive pivot
-      X[(size_t)i * n + j] = make_double2(sr / dgl.x, si / dgl.x);
+      for (int o = 1; o < 8; o <<= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+      }
+      if (q == 0) X[(size_t)i * n + j] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
     }
+    __syncthreads();
   }
-  __syncthreads();
   double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
   double2 *Wo = reinterpret_cast<double2 *>(Wsc[prob]);
   for (int idx = tid; idx < n * n; idx += nt) {
@@ -1653,7 +1660,7 @@ class HipBackend : public Backend {
             int nprob) override {
     if (nprob <= 0) return;
     int np = n + (n & 1);
-    if (np <= 64) {
+    if (n < 32) {
       size_t sm = (size_t)2 * np * np * sizeof(double2);
       stale_check("eigh_jacobi_kernel");
       hipLaunchKernelGGL(eigh_jacobi_kernel<true>, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
