@@ -10,7 +10,16 @@ next --steps steps are timed, so the default run is steps 7..20 of the 20-step c
 The JSON line also carries:
   roofline     : the complex GEMM kernel (every contraction of the step runs in it), algorithmic
                  flops 8*M*N*K per launch over its HIP-event-timed launch durations, against the
-                 MI355X FP64 peak (78.6 TFLOP/s dense).
+                 MI355X FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the
+                 committed rocprofv3 counter summary (null once the kernel source has changed);
+                 achievable = measured roofs on this GPU (MFMA chains without memory traffic, a
+                 1 GiB copy); frac_of_achievable_mfma compares the algorithmic rate with the
+                 measured FP64 MFMA rate x 4/3 (the 3M complex product issues 3/4 of the
+                 algorithmic real flops).
+  mixed        : the same window in mixed precision, with max / median |<Z>| difference to FP64.
+  theta_batch  : the eight theta_h values of the workload (20 steps each) solved together, one
+                 serving slot each: aggregate Floquet steps/s.
+  serving      : the seeded request stream (see serving_bench).
   cpu_baseline : the FP64 oracle on this host's cores on a bounded sample of the same workload
                  (one gate layer, one BP sweep and one <Z> sweep on a seeded random chi = 64
                  state), converted to Floquet steps/s with the BP sweep count measured here.
@@ -28,6 +37,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_hbm_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2306_14887_amd", "csrc", "hip_backend.hip")
+
+
+def gemm_traffic():
+    """HBM bytes per GEMM launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when
+    the GEMM kernel source has changed since those counters were taken (its hash is recorded)."""
+    import hashlib
+    try:
+        src = open(GEMM_SOURCE).read()
+        a = src.index("constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;")
+        b = src.index("// Twelve independent MFMA accumulation chains per wave")
+        h = hashlib.sha256(src[a:b].encode()).hexdigest()
+        rec = {}
+        for line in open(TRAFFIC_PROFILE):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+        if rec.get("kernel_source_sha256") != h:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def _cores() -> int:
@@ -74,8 +106,17 @@ def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict
         net.expect_site(v, 3)
     t_obs = time.perf_counter() - t0
     t_step = lat.n_edges * t_gate + bp_sweeps_per_step * t_sweep + t_obs
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": 1.0 / t_step, "unit": "Floquet steps/s", "cores": _cores(), "kind": "oracle",
+        "cpu": model,
         "sample": (f"FP64 numpy oracle on a seeded random chi={chi} state of the 127-qubit "
                    f"lattice: one gate layer ({n_layer0} gates, {t_layer0:.1f} s), one BP sweep "
                    f"({t_sweep:.1f} s), <Z> on all sites ({t_obs:.1f} s); step time = "
@@ -171,15 +212,61 @@ def mixed_window(lat, theta, chi, warmup, steps) -> dict:
                                                   precision=bpki.BPKI_FP32, bp_tol=MIXED_TOL))
         for _ in range(warmup):
             sess.step(observe=True)
-        iters = []
+        iters, zs = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
-            iters.append(sess.step(observe=True)["bp_iters"])
+            r = sess.step(observe=True)
+            iters.append(r["bp_iters"])
+            zs.append(r["z"])
         wall = time.perf_counter() - t0
         sess.close()
     return {"value": steps / wall, "unit": "Floquet steps/s", "ms_per_step": 1e3 * wall / steps,
             "bp_sweeps_per_step": float(np.mean(iters)), "bp_tol": MIXED_TOL,
-            "dtype": "c64 contractions in BP (FP64 storage, gates, eigh, residual)"}
+            "dtype": "c64 contractions in BP (FP64 storage, gates, eigh, residual)",
+            "_z": np.array(zs)}
+
+
+def achievable_peaks(ctx) -> dict:
+    """Micro-benchmarks of the two roofs on this GPU: independent MFMA chains with no memory
+    traffic (the library's probe) and a 1 GiB device-to-device copy (read + write)."""
+    out = {"mfma_f64_tflops": ctx.test_mfma_rate(0, 1024, 2000),
+           "mfma_f32_tflops": ctx.test_mfma_rate(1, 1024, 2000)}
+    try:
+        import torch
+        n = (1 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(8):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        out["hbm_copy_gbps"] = 8 * 2 * n * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+    except Exception:
+        out["hbm_copy_gbps"] = None
+    return out
+
+
+def theta_batch(lat, chi: int, depth: int) -> dict:
+    """The eight theta_h values of the workload solved together (one serving slot each): the
+    aggregate Floquet steps/s of the batch (8 * depth / makespan)."""
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    thetas = L.theta_draw(8, 2306)
+    with bpki.Context(0) as ctx:
+        ctx.serving_config(len(thetas))
+        t0 = time.perf_counter()
+        tickets = [ctx.submit(bpki.spec_from_lattice(lat, float(t), depth, chi)) for t in thetas]
+        outs = [t.wait() for t in tickets]
+        wall = time.perf_counter() - t0
+    return {"thetas": len(thetas), "depth": depth, "chi": chi, "precision": "fp64",
+            "aggregate_steps_per_s": len(thetas) * depth / wall, "makespan_s": wall,
+            "bp_sweeps_per_step": float(sum(sum(o["bp_iters"]) for o in outs)) / (len(thetas) * depth)}
 
 
 def copy_probe(mib: int) -> int:
@@ -207,6 +294,8 @@ def main() -> int:
                     help="requests in the serving measurement (0 = skip; 256 = full stream)")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision window")
+    ap.add_argument("--theta-batch", type=int, default=1,
+                    help="1: also solve the eight theta_h values together (aggregate steps/s)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 8 plain device-to-device copies of MIB MiB and exit "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -242,12 +331,13 @@ def main() -> int:
     if have_torch:
         torch.cuda.synchronize()
     sess.profile(True)
-    iters = []
+    iters, zsteps = [], []
     phase = np.zeros(4)
     t0 = time.perf_counter()
     for t in range(args.steps):
         r = sess.step(observe=True)
         iters.append(r["bp_iters"])
+        zsteps.append(r["z"])
         phase += sess.last_timing()
         print(f"step {t + 1}/{args.steps}: bp sweeps {r['bp_iters']}", file=sys.stderr,
               flush=True)
@@ -258,6 +348,7 @@ def main() -> int:
     sess.profile(False)
     z = r["z"]
     sess.close()
+    peaks = achievable_peaks(ctx)
     ctx.close()
 
     steps_per_s = args.steps / wall
@@ -287,16 +378,26 @@ def main() -> int:
             "mean_z_last_step": float(np.mean(z)),
         },
         "roofline": {
-            "bound": "mfma", "kernel": "gemm_c64_kernel",
+            "bound": "mfma", "kernel": "gemm_kernel<double>",
             "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "launches": prof["launches"], "avg_launch_ms": avg_ms,
-            "traffic": None,
+            "traffic": gemm_traffic(), "traffic_unit": "bytes per launch (HBM, calibrated)",
+            "achievable": peaks,
+            "frac_of_achievable_mfma": (achieved / (peaks["mfma_f64_tflops"] * 4.0 / 3.0)
+                                        if peaks["mfma_f64_tflops"] else None),
         },
     }
     if not args.no_mixed:
-        out["mixed"] = mixed_window(lat, theta, chi, args.warmup, args.steps)
+        mixed = mixed_window(lat, theta, chi, args.warmup, args.steps)
+        dz = np.abs(mixed.pop("_z") - np.array(zsteps))
+        mixed["abs_dz_vs_fp64_max"] = float(dz.max())
+        mixed["abs_dz_vs_fp64_median"] = float(np.median(dz))
+        out["mixed"] = mixed
         print("mixed-precision window done", file=sys.stderr, flush=True)
+    if args.theta_batch:
+        out["theta_batch"] = theta_batch(lat, chi, args.warmup + args.steps)
+        print("theta batch done", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.slots)
         print("serving done", file=sys.stderr, flush=True)

@@ -1,7 +1,8 @@
 /*
- * Test hooks of libbpki: the two device primitives every phase of the method is built from,
- * exposed so that each can be checked element by element against an independent host
- * computation.  Not needed to run simulations (see bpki.h).
+ * Test hooks of libbpki: the device primitives every phase of the method is built from, exposed
+ * so that each can be checked element by element against an independent host computation, and
+ * the MFMA throughput probe that calibrates the roofline.  Not needed to run simulations (see
+ * bpki.h).
  *
  * Buffers are host memory holding complex128 values as (re, im) pairs.  The library copies them
  * to the device, runs the primitive on the context's stream and copies the result back.
@@ -40,7 +41,8 @@ typedef struct {
 int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const double *A,
                    size_t a_elems, const double *B, size_t b_elems, double *C, size_t c_elems);
 
-/* Batched Hermitian eigendecomposition (FP64 Jacobi) of nprob n x n matrices (n <= 256):
+/* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32 and n > 128, Householder
+ * tridiagonalisation + divide and conquer otherwise) of nprob n x n matrices (n <= 256):
  * evals [nprob][n] descending, vecs [nprob][n][n] with column i the eigenvector of evals[i]. */
 int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *evals,
                    double *vecs);
@@ -50,6 +52,12 @@ int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *eva
  * when G = A^H A), with pivots stopping at cut * max(diag G). */
 int bpki_test_gram_chol(bpki_ctx *ctx, int n, int nprob, const double *G, double cut, double *R,
                         double *Wsc);
+
+/* Achievable MFMA rate on the context's stream: `blocks` workgroups of four waves each run `iters`
+ * iterations of twelve independent 16x16x4 MFMA accumulation chains (precision BPKI_FP64:
+ * v_mfma_f64_16x16x4f64; BPKI_FP32: v_mfma_f32_16x16x4f32), no memory traffic.  *tflops receives
+ * 2048 * 12 * iters * 4 * blocks / elapsed time of the second of two launches. */
+int bpki_test_mfma_rate(bpki_ctx *ctx, int precision, int blocks, int iters, double *tflops);
 
 #ifdef __cplusplus
 }

@@ -102,6 +102,7 @@ def load(path: str | None = None):
                                      C.c_size_t, dp, C.c_size_t]),
         "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
         "bpki_test_gram_chol": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_double, dp, dp]),
+        "bpki_test_mfma_rate": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -122,7 +123,7 @@ def exported_symbols() -> list[str]:
             "bpki_session_bp_sweep", "bpki_session_observe_z", "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_last_timing", "bpki_session_profile",
             "bpki_session_profile_read", "bpki_test_gemm",
-            "bpki_test_eigh", "bpki_test_gram_chol"]
+            "bpki_test_eigh", "bpki_test_gram_chol", "bpki_test_mfma_rate"]
 
 
 def _ptr(a, ct):
@@ -275,6 +276,13 @@ class Context:
         _check(self.lib, self.lib.bpki_test_gram_chol(self.h, n, nprob, G.ctypes.data_as(dp), cut,
                                                       R.ctypes.data_as(dp), W.ctypes.data_as(dp)))
         return R, W
+
+    def test_mfma_rate(self, precision: int = 0, blocks: int = 1024, iters: int = 2000) -> float:
+        """Achievable MFMA TFLOP/s (FP64 for precision 0, FP32 for 1) with no memory traffic."""
+        out = C.c_double()
+        _check(self.lib, self.lib.bpki_test_mfma_rate(self.h, precision, blocks, iters,
+                                                      C.byref(out)))
+        return out.value
 
     def test_eigh(self, A: np.ndarray):
         A = np.ascontiguousarray(A, dtype=np.complex128)

@@ -732,6 +732,18 @@ extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, do
   return e ? fail(e, msg) : 0;
 }
 
+extern "C" int bpki_test_mfma_rate(bpki_ctx *c, int precision, int blocks, int iters,
+                                   double *tflops) {
+  if (!c || !tflops || (precision != BPKI_FP64 && precision != BPKI_FP32) || blocks < 1 ||
+      blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+    return fail(-1, "bad argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  *tflops = c->be->mfma_rate(precision, blocks, iters);
+  std::string msg;
+  if (int e = c->be->check(&msg)) return fail(e, "device error: " + msg);
+  return 0;
+}
+
 extern "C" int bpki_test_gram_chol(bpki_ctx *c, int n, int nprob, const double *G, double cut,
                                    double *R, double *Wsc) {
   if (!c || n < 1 || n > 256 || nprob < 1 || !(cut >= 0)) return fail(-1, "bad argument");

@@ -97,6 +97,9 @@ struct Backend {
   virtual void normalize_residual(int chi, double *const *Mnew, const double *const *Mold,
                                   double *res, int nprob) = 0;
   virtual void reduce_max(const double *x, int n, double *out) = 0;
+  // Throughput of a loop of independent 16x16x4 MFMAs (no memory traffic) on this stream, in
+  // TFLOP/s: prec 0 = FP64, 1 = FP32; `blocks` workgroups of four waves, `iters` iterations.
+  virtual double mfma_rate(int prec, int blocks, int iters) = 0;
   // rho[p][s][s'] = sum_i Y[p][s][i] conj(T[p][s'][i]) over i < len[p]; out 4 complex per p.
   virtual void rho_dot(const double *const *Y, const double *const *T, const int64_t *len,
                        double *rho, int nprob) = 0;

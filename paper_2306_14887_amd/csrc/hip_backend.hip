@@ -249,6 +249,25 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
       }
 }
 
+// Twelve independent MFMA accumulation chains per wave, no memory traffic: the achievable MFMA
+// rate that bounds gemm_kernel.  The final comparison keeps the chains live.
+template <typename T>
+__global__ __launch_bounds__(256) void mfma_rate_kernel(int iters, double *out) {
+  typedef MfmaTraits<T> MT;
+  typedef typename MT::acc_t acc_t;
+  acc_t acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = (acc_t){T(0), T(0), T(0), T(0)};
+  const T a = T(threadIdx.x) * T(1e-3), b = T(blockIdx.x) * T(1e-3);
+  for (int it = 0; it < iters; ++it)
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = MT::mma(a, b, acc[i]);
+  double sum = 0.0;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) sum += (double)acc[i][0] + (double)acc[i][1] + (double)acc[i][2] + (double)acc[i][3];
+  if (sum == -1.0) out[0] = sum;
+}
+
 // Sums the K chunks of a split-K GEMM in chunk order and applies alpha / beta.
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *const *Cp,
                                                           int ksplit, const double2 *W) {
@@ -1779,6 +1798,31 @@ class HipBackend : public Backend {
     hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(256), 0, s_, chi, Mn, Mo,
                        res);
     launch_check("normalize_residual_kernel");
+  }
+  double mfma_rate(int prec, int blocks, int iters) override {
+    if (blocks < 1 || iters < 1) return 0.0;
+    double *out = (double *)alloc(sizeof(double));
+    if (!out) return 0.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {      // the first launch warms the clocks up
+      HIPCHK(hipEventRecord(e0, s_));
+      if (prec == 1)
+        hipLaunchKernelGGL(mfma_rate_kernel<float>, dim3(blocks), dim3(256), 0, s_, iters, out);
+      else
+        hipLaunchKernelGGL(mfma_rate_kernel<double>, dim3(blocks), dim3(256), 0, s_, iters, out);
+      launch_check("mfma_rate_kernel");
+      HIPCHK(hipEventRecord(e1, s_));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    release(out);
+    const double flops = 2048.0 * 12 * (double)iters * (double)blocks * 4;
+    return ms > 0.0f ? flops / (ms * 1e-3) / 1e12 : 0.0;
   }
   void reduce_max(const double *x, int n, double *out) override {
     stale_check("reduce_max_kernel");

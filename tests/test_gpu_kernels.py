@@ -173,3 +173,18 @@ def test_gram_chol(ctx, n, rank):
         idx = np.nonzero(np.abs(np.diag(QQ)) > 0.5)[0]
         assert np.abs(QQ[np.ix_(idx, idx)] - np.eye(r)).max() < 1e-6
         assert np.abs(Q @ R[p] - A[p]).max() < 1e-8 * np.abs(A[p]).max()
+
+
+def test_mfma_rate_probe(ctx):
+    """The MFMA throughput probe returns a rate between a tenth of and the nominal dense peak
+    (FP64 78.6, FP32 157.3 TFLOP/s) and rejects bad arguments."""
+    from paper_2306_14887_amd import bpki as B
+    print("[mfma rate]", flush=True)
+    r64 = ctx.test_mfma_rate(0, blocks=512, iters=500)
+    r32 = ctx.test_mfma_rate(1, blocks=512, iters=500)
+    assert 7.86 < r64 <= 78.6 * 1.02
+    assert 15.7 < r32 <= 157.3 * 1.02
+    with pytest.raises(B.BpkiError):
+        ctx.test_mfma_rate(2)
+    with pytest.raises(B.BpkiError):
+        ctx.test_mfma_rate(0, blocks=0)
