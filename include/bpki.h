@@ -168,11 +168,15 @@ int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residu
  * BP, observables.  Measured with HIP events on the session's stream. */
 int bpki_session_last_timing(const bpki_session *s, double *ms4);
 /* Kernel-level timing of the complex GEMM kernel (every contraction of the method runs in it):
- * while enabled, each launch on the session's stream is bracketed by HIP events.  read returns
- * the launch count, the summed kernel time in ms and the summed 8*M*N*K flops of those launches
- * (complex multiply-adds at 8 real flops).  Enabling resets the counters. */
-int bpki_session_profile(bpki_session *s, int enable);
-int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, double *flops);
+ * with stride k >= 1, every k-th launch on the session's stream is bracketed by HIP events (each
+ * event pair costs a few microseconds of stream time, so a stride above 1 keeps the measurement
+ * from slowing the run it measures); stride 0 turns it off.  read returns the bracketed launch
+ * count, the summed kernel time in ms and the summed 8*M*N*K flops of those launches (complex
+ * multiply-adds at 8 real flops), and optionally the count of all launches since enabling.
+ * Enabling resets the counters. */
+int bpki_session_profile(bpki_session *s, int stride);
+int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, double *flops,
+                              int64_t *all_launches);
 
 #ifdef __cplusplus
 }

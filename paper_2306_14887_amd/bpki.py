@@ -97,7 +97,8 @@ def load(path: str | None = None):
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_last_timing": (C.c_int, [vp, dp]),
         "bpki_session_profile": (C.c_int, [vp, C.c_int]),
-        "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp]),
+        "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp,
+                                                 C.POINTER(C.c_int64)]),
         "bpki_test_gemm": (C.c_int, [vp, C.POINTER(TestGemmDesc), C.c_int, dp, C.c_size_t, dp,
                                      C.c_size_t, dp, C.c_size_t]),
         "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
@@ -424,14 +425,16 @@ class Session:
         return {"z": z, "bp_iters": it.value, "bp_residual": r.value, "discarded": d.value,
                 "status": rc}
 
-    def profile(self, enable: bool = True):
-        _check(self.lib, self.lib.bpki_session_profile(self.h, 1 if enable else 0))
+    def profile(self, enable: bool = True, stride: int = 1):
+        """Bracket every `stride`-th GEMM launch with HIP events (off when enable is False)."""
+        _check(self.lib, self.lib.bpki_session_profile(self.h, stride if enable else 0))
 
     def profile_read(self):
-        n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
+        n, ms, fl, a = C.c_int64(), C.c_double(), C.c_double(), C.c_int64()
         _check(self.lib, self.lib.bpki_session_profile_read(self.h, C.byref(n), C.byref(ms),
-                                                            C.byref(fl)))
-        return {"launches": n.value, "ms": ms.value, "flops": fl.value}
+                                                            C.byref(fl), C.byref(a)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value,
+                "all_launches": a.value}
 
     def last_timing(self) -> np.ndarray:
         t = np.zeros(4)

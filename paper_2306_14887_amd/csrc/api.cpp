@@ -445,18 +445,20 @@ extern "C" int bpki_session_step(bpki_session *s, double *z, int32_t *iters, dou
   return r < s->eng->problem().bp_tol ? 0 : 1;
 }
 
-extern "C" int bpki_session_profile(bpki_session *s, int enable) {
+extern "C" int bpki_session_profile(bpki_session *s, int stride) {
   if (!s) return fail(-1, "NULL session");
-  s->ctx->be->gemm_profile(enable != 0);
+  if (stride < 0) return fail(-1, "stride must be >= 0");
+  s->ctx->be->gemm_profile(stride);
   return sess_check(s);
 }
 
 extern "C" int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms,
-                                         double *flops) {
+                                         double *flops, int64_t *all_launches) {
   if (!s) return fail(-1, "NULL session");
-  long l = 0;
-  s->ctx->be->gemm_profile_read(&l, ms, flops);
+  long l = 0, a = 0;
+  s->ctx->be->gemm_profile_read(&l, &a, ms, flops);
   if (launches) *launches = l;
+  if (all_launches) *all_launches = a;
   return sess_check(s);
 }
 

@@ -51,8 +51,10 @@ struct Backend {
   virtual double timer_ms(int a, int b) = 0;
   // Per-launch GEMM timing (HIP events around every gemm launch while enabled).  read() returns
   // the number of launches, their summed duration (ms) and summed 8*M*N*K*batch*nprob flops.
-  virtual void gemm_profile(bool enable) = 0;
-  virtual void gemm_profile_read(long *launches, double *ms, double *flops) = 0;
+  // GEMM timing: stride 0 = off, k >= 1 = bracket every k-th launch with HIP events (all
+  // launches are counted).  read: bracketed launches, all launches, their ms and 8MNK flops.
+  virtual void gemm_profile(int stride) = 0;
+  virtual void gemm_profile_read(long *sampled, long *all, double *ms, double *flops) = 0;
 
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,

@@ -1587,7 +1587,8 @@ class HipBackend : public Backend {
     int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
     dim3 grid(tiles, d.batch, nprob);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof_) {
+    const bool rec = prof_stride_ > 0 && (prof_all_++ % prof_stride_) == 0;
+    if (rec) {
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s_));
@@ -1620,7 +1621,7 @@ class HipBackend : public Backend {
                          W);
       launch_check("gemm_kernel<double>");
     }
-    if (prof_) {
+    if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
       prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
@@ -1648,18 +1649,20 @@ class HipBackend : public Backend {
     }
     return skws_;
   }
-  void gemm_profile(bool enable) override {
-    prof_ = enable;
-    if (enable) {
+  void gemm_profile(int stride) override {
+    prof_stride_ = stride > 0 ? stride : 0;
+    if (prof_stride_) {
       drain_profile();
       prof_launches_ = 0;
+      prof_all_ = 0;
       prof_ms_ = 0;
       prof_flops_ = 0;
     }
   }
-  void gemm_profile_read(long *launches, double *ms, double *flops) override {
+  void gemm_profile_read(long *sampled, long *all, double *ms, double *flops) override {
     drain_profile();
-    if (launches) *launches = prof_launches_;
+    if (sampled) *sampled = prof_launches_;
+    if (all) *all = prof_all_;
     if (ms) *ms = prof_ms_;
     if (flops) *flops = prof_flops_;
   }
@@ -1858,9 +1861,9 @@ class HipBackend : public Backend {
   size_t cws_bytes_ = 0;
   void *skws_ = nullptr;
   size_t skws_bytes_ = 0;
-  bool prof_ = false;
+  int prof_stride_ = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev_;
-  long prof_launches_ = 0;
+  long prof_launches_ = 0, prof_all_ = 0;
   double prof_ms_ = 0, prof_flops_ = 0;
 };
 
