@@ -1224,6 +1224,144 @@ __global__ __launch_bounds__(1024) void gram_chol_kernel(int n, const double *co
   }
 }
 
+// The same factorisation for n <= 128 with the Gram matrix packed (lower triangle, physical
+// indices) in LDS: pivoting permutes logical indices only, each rank-one update touches the
+// remaining triangle, and X = L1^{-1} is formed in the LDS that held G.  L goes to the workspace.
+__global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double *const *G,
+                                                             double *const *R,
+                                                             double *const *Wsc, double cut,
+                                                             double2 *ws) {
+  extern __shared__ double2 smem[];
+  __shared__ int perm[128];
+  __shared__ double dg[128];
+  __shared__ double2 lk[128];
+  __shared__ int piv_s, rank_s;
+  __shared__ double gmax_s;
+  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  double2 *L = ws + (size_t)prob * n * n;
+  double2 *P = smem;
+  const double2 *g = reinterpret_cast<const double2 *>(G[prob]);
+  for (int i = wave; i < n; i += nw)
+    for (int j = lane; j <= i; j += 64) {
+      const double2 a = g[(size_t)i * n + j], b = g[(size_t)j * n + i];
+      P[pk_idx(i, j)] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+    }
+  for (int idx = tid; idx < n * n; idx += nt) L[idx] = make_double2(0.0, 0.0);
+  for (int i = tid; i < n; i += nt) {
+    perm[i] = i;
+    dg[i] = g[(size_t)i * n + i].x;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double m = 0;
+    for (int i = lane; i < n; i += 64) m = fmax(m, dg[i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) {
+      gmax_s = m;
+      rank_s = n;
+    }
+  }
+  __syncthreads();
+  const double gmax = gmax_s;
+  for (int k = 0; k < n; ++k) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bj = k;
+      for (int j = k + lane; j < n; j += 64) {
+        const double v = dg[perm[j]];
+        if (v > best) { best = v; bj = j; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+      }
+      if (lane == 0) {
+        if (!(best > cut * gmax) || !(gmax > 0)) {
+          rank_s = k;
+          piv_s = -1;
+        } else {
+          const int t = perm[k];
+          perm[k] = perm[bj];
+          perm[bj] = t;
+          piv_s = bj;
+        }
+      }
+    }
+    __syncthreads();
+    if (piv_s < 0) break;
+    const int pkk = perm[k];
+    const double piv = sqrt(dg[pkk]);
+    for (int kk = k + 1 + tid; kk < n; kk += nt) {
+      const int i = perm[kk];
+      const double2 w = i >= pkk ? P[pk_idx(i, pkk)] : cconj(P[pk_idx(pkk, i)]);
+      const double2 l = make_double2(w.x / piv, w.y / piv);
+      L[(size_t)i * n + k] = l;
+      lk[i] = l;
+    }
+    if (tid == 0) L[(size_t)pkk * n + k] = make_double2(piv, 0.0);
+    __syncthreads();
+    // W[i][j] -= L[i][k] conj(L[j][k]) over the remaining logical pairs (row >= col)
+    const int m = n - k - 1;
+    for (int row = wave; row < m; row += nw) {
+      const int i = perm[k + 1 + row];
+      const double2 li = lk[i];
+      for (int col = lane; col <= row; col += 64) {
+        const int j = perm[k + 1 + col];
+        const double2 lj = lk[j];
+        if (i >= j) {
+          double2 &w = P[pk_idx(i, j)];
+          w = make_double2(w.x - (li.x * lj.x + li.y * lj.y), w.y - (li.y * lj.x - li.x * lj.y));
+          if (i == j) dg[i] = w.x;
+        } else {
+          double2 &w = P[pk_idx(j, i)];
+          w = make_double2(w.x - (lj.x * li.x + lj.y * li.y), w.y - (lj.y * li.x - lj.x * li.y));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int r = rank_s;
+  __syncthreads();
+  // X = L1^{-1} (L1[i][m] = L[perm[i]][m], i, m < r), rows in turn, X packed in LDS
+  double2 *X = P;
+  for (int i = 0; i < r; ++i) {
+    const double2 *Li = L + (size_t)perm[i] * n;
+    const double inv = 1.0 / Li[i].x;
+    const int q = tid & 7;
+    for (int j = tid >> 3; j <= i; j += nt >> 3) {
+      double sr = 0.0, si = 0.0;
+      for (int mm = j + q; mm < i; mm += 8) {
+        const double2 a = Li[mm], x = X[pk_idx(mm, j)];
+        sr += a.x * x.x - a.y * x.y;
+        si += a.x * x.y + a.y * x.x;
+      }
+      for (int o = 1; o < 8; o <<= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+      }
+      if (q == 0) X[pk_idx(i, j)] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
+    }
+    __syncthreads();
+  }
+  double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
+  double2 *Wo = reinterpret_cast<double2 *>(Wsc[prob]);
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int k = idx / n, c = idx % n;
+    const double2 l = L[(size_t)c * n + k];
+    Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
+    Wo[idx] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < r * r; idx += nt) {
+    const int kk = idx / r, k = idx % r;     // Wsc[perm[kk]][k] = conj(X[k][kk]), kk <= k
+    if (kk > k) continue;
+    const double2 x = X[pk_idx(k, kk)];
+    Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // small kernels
 
@@ -1507,6 +1645,8 @@ class HipBackend : public Backend {
     }
     HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel<true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
+    HIPCHK(hipFuncSetAttribute((const void *)gram_chol_lds_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
     HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_dc_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
   }
@@ -1763,10 +1903,18 @@ class HipBackend : public Backend {
       }
       cws_bytes_ = need;
     }
-    stale_check("gram_chol_kernel");
-    hipLaunchKernelGGL(gram_chol_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, R, Wsc, cut,
-                       (double2 *)cws_);
-    launch_check("gram_chol_kernel");
+    if (n <= 128) {
+      stale_check("gram_chol_lds_kernel");
+      hipLaunchKernelGGL(gram_chol_lds_kernel, dim3(nprob), dim3(1024),
+                         (size_t)n * (n + 1) / 2 * sizeof(double2), s_, n, G, R, Wsc, cut,
+                         (double2 *)cws_);
+      launch_check("gram_chol_lds_kernel");
+    } else {
+      stale_check("gram_chol_kernel");
+      hipLaunchKernelGGL(gram_chol_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, R, Wsc, cut,
+                         (double2 *)cws_);
+      launch_check("gram_chol_kernel");
+    }
   }
   void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
              double *const *Th, double a, double b, double c, double d, int nprob) override {
