@@ -843,18 +843,23 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
     __syncthreads();
     const double2 tau = tau_sh;
     if (tau.x == 0.0 && tau.y == 0.0) continue;   // H_k = I (uniform over the block)
-    // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): 4 threads per row
+    // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): 4 threads per row;
+    // row gi of S is row gi of the packed triangle up to the diagonal, then column gi
     {
       const int r = tid >> 2, q = tid & 3;
       double2 acc = make_double2(0.0, 0.0);
       if (r < m) {
         const int gi = k + 1 + r;
-        for (int c = q; c < m; c += 4) {
-          const int gj = k + 1 + c;
-          const double2 a = gj <= gi ? P[pk_idx(gi, gj)] : cconj(P[pk_idx(gj, gi)]);
-          const double2 vc = v_s[c];
+        const double2 *prow = P + pk_idx(gi, k + 1);
+        for (int c = q; c <= r; c += 4) {
+          const double2 a = prow[c], vc = v_s[c];
           acc.x += a.x * vc.x - a.y * vc.y;
           acc.y += a.x * vc.y + a.y * vc.x;
+        }
+        for (int c = r + 1 + q; c < m; c += 4) {
+          const double2 a = P[pk_idx(k + 1 + c, gi)], vc = v_s[c];   // conj(a) vc
+          acc.x += a.x * vc.x + a.y * vc.y;
+          acc.y += a.x * vc.y - a.y * vc.x;
         }
       }
       acc.x += __shfl_xor(acc.x, 1, 64);
@@ -864,33 +869,29 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
       if (r < m && q == 0) w_s[r] = cmul(tau, acc);
     }
     __syncthreads();
-    // w = x + a v with a = -(1/2) Re(conj(tau) v^H x)
-    if (wave == 0) {
-      double dr = 0.0, di = 0.0;
-      for (int i = lane; i < m; i += 64) {
-        const double2 vi = v_s[i], xi = w_s[i];
-        dr += vi.x * xi.x + vi.y * xi.y;
-        di += vi.x * xi.y - vi.y * xi.x;
-      }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      const double a = -0.5 * (tau.x * dr + tau.y * di);
-      for (int i = lane; i < m; i += 64) {
-        const double2 vi = v_s[i];
-        w_s[i] = make_double2(w_s[i].x + a * vi.x, w_s[i].y + a * vi.y);
-      }
+    // every wave forms a = -(1/2) Re(conj(tau) v^H x) itself (x is in w_s); then
+    // S <- S - v w^H - w v^H on the lower triangle with w = x + a v formed on the fly
+    double dr = 0.0, di = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double2 vi = v_s[i], xi = w_s[i];
+      dr += vi.x * xi.x + vi.y * xi.y;
+      di += vi.x * xi.y - vi.y * xi.x;
     }
-    __syncthreads();
-    // S <- S - v w^H - w v^H on the lower triangle
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double aw = -0.5 * (tau.x * dr + tau.y * di);
     for (int rr = wave; rr < m; rr += nw) {
       const int gi = k + 1 + rr;
-      const double2 vi = v_s[rr], wi = w_s[rr];
+      const double2 vi = v_s[rr], xi = w_s[rr];
+      const double2 wi = make_double2(xi.x + aw * vi.x, xi.y + aw * vi.y);
+      double2 *prow = P + pk_idx(gi, k + 1);
       for (int c = lane; c <= rr; c += 64) {
-        const double2 vc = v_s[c], wc = w_s[c];
-        double2 &a = P[pk_idx(gi, k + 1 + c)];
-        double ur = vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
-        double ui = vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
-        a = make_double2(a.x - ur, c == rr ? 0.0 : a.y - ui);
+        const double2 vc = v_s[c], xc = w_s[c];
+        const double2 wc = make_double2(xc.x + aw * vc.x, xc.y + aw * vc.y);
+        const double2 a = prow[c];
+        const double ur = vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
+        const double ui = vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
+        prow[c] = make_double2(a.x - ur, c == rr ? 0.0 : a.y - ui);
       }
     }
     __syncthreads();
