@@ -1423,27 +1423,17 @@ __global__ void gram_factor_kernel(int n, int r, const double *const *evals,
   }
 }
 
-__global__ void theta_kernel(int rB, int rS, int chi, const double *const *RB,
-                             const double *const *RS, double *const *Th, double gsr, double gsi,
-                             double gdr, double gdi) {
-  const double2 *a = reinterpret_cast<const double2 *>(RB[blockIdx.y]);
-  const double2 *b = reinterpret_cast<const double2 *>(RS[blockIdx.y]);
+// Theta <- g(s_B, s_S) Theta in place, rows (r_B, s_B), columns (r_S, s_S).
+__global__ void theta_phase_kernel(int rB, int rS, double *const *Th, double gsr, double gsi,
+                                   double gdr, double gdi) {
   double2 *t = reinterpret_cast<double2 *>(Th[blockIdx.y]);
-  int rows = 2 * rB, cols = 2 * rS;
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < rows * cols;
-       idx += gridDim.x * blockDim.x) {
-    int row = idx / cols, col = idx % cols;
-    int rb = row >> 1, sbv = row & 1, rs = col >> 1, ss = col & 1;
-    const double2 *pa = a + ((size_t)rb * 2 + sbv) * chi;
-    const double2 *pb = b + ((size_t)rs * 2 + ss) * chi;
-    double re = 0, im = 0;
-    for (int k = 0; k < chi; ++k) {
-      double2 x = pa[k], y = pb[k];
-      re += x.x * y.x - x.y * y.y;
-      im += x.x * y.y + x.y * y.x;
-    }
-    double gr = (sbv == ss) ? gsr : gdr, gi = (sbv == ss) ? gsi : gdi;
-    t[idx] = make_double2(gr * re - gi * im, gr * im + gi * re);
+  const int cols = 2 * rS, tot = 2 * rB * cols;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += gridDim.x * blockDim.x) {
+    const int row = idx / cols, col = idx - row * cols;
+    const bool same = (row & 1) == (col & 1);
+    const double gr = same ? gsr : gdr, gi = same ? gsi : gdi;
+    const double2 v = t[idx];
+    t[idx] = make_double2(gr * v.x - gi * v.y, gr * v.y + gi * v.x);
   }
 }
 
@@ -1919,12 +1909,20 @@ class HipBackend : public Backend {
   }
   void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
              double *const *Th, double a, double b, double c, double d, int nprob) override {
+    // Theta[(rb,sb)][(rs,ss)] = sum_k RB[rb][sb][k] RS[rs][ss][k] on the MFMA GEMM (rows of RB
+    // and RS are contiguous runs of chi), then the gate phases elementwise
+    GemmDesc gd;
+    gd.M = 2 * rB; gd.Mi = gd.M; gd.a_mi = chi;
+    gd.N = 2 * rS; gd.Ni = gd.N; gd.b_ni = chi;
+    gd.K = chi; gd.Ki = chi; gd.a_ki = 1; gd.b_ki = 1;
+    gd.c_mi = gd.N; gd.c_ni = 1;
+    gemm(gd, RB, RS, Th, nprob);
     int tot = 4 * rB * rS;
     int bx = std::min(1024, (tot + 255) / 256);
-    stale_check("theta_kernel");
-    hipLaunchKernelGGL(theta_kernel, dim3(bx, nprob), dim3(256), 0, s_, rB, rS, chi, RB, RS, Th,
-                       a, b, c, d);
-    launch_check("theta_kernel");
+    stale_check("theta_phase_kernel");
+    hipLaunchKernelGGL(theta_phase_kernel, dim3(bx, nprob), dim3(256), 0, s_, rB, rS, Th, a, b, c,
+                       d);
+    launch_check("theta_phase_kernel");
   }
   void svd_finish(int n, int chi, const double *const *ev, const double *const *vec,
                   double *const *Vs, double *const *S, int *kout, double *disc,
