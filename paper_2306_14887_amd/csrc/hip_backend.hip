@@ -1378,25 +1378,37 @@ __global__ void rx_kernel(double *const *T, const int64_t *half, double c, doubl
   }
 }
 
-__global__ void msg_sqrt_kernel(int n, const double *const *evals, const double *const *vecs,
-                                double *const *X, double *const *Xp, double cut) {
+// X = W f(l) W^H and Xp = W g(l) W^H with f = sqrt(max(l, 0)) and g = 1/sqrt(l) above the cutoff
+// (0 below); f and g are formed once per message in LDS.  n <= 128.
+__global__ __launch_bounds__(256) void msg_sqrt_kernel(int n, const double *const *evals,
+                                                       const double *const *vecs,
+                                                       double *const *X, double *const *Xp,
+                                                       double cut) {
+  __shared__ double fs[128], gs[128];
   const double *l = evals[blockIdx.x];
   const double2 *W = reinterpret_cast<const double2 *>(vecs[blockIdx.x]);
   double2 *x = reinterpret_cast<double2 *>(X[blockIdx.x]);
   double2 *xp = reinterpret_cast<double2 *>(Xp[blockIdx.x]);
-  double lmax = l[0] > 0 ? l[0] : 0.0;
+  const double lmax = l[0] > 0 ? l[0] : 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double lk = l[k];
+    fs[k] = lk > 0 ? sqrt(lk) : 0.0;
+    gs[k] = (lk > cut * lmax && lk > 0) ? 1.0 / sqrt(lk) : 0.0;
+  }
+  __syncthreads();
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    int i = idx / n, j = idx % n;
+    const int i = idx / n, j = idx % n;
+    const double2 *wi = W + (size_t)i * n, *wj = W + (size_t)j * n;
     double sr = 0, si = 0, pr = 0, pi = 0;
     for (int k = 0; k < n; ++k) {
-      double lk = l[k];
-      double f = lk > 0 ? sqrt(lk) : 0.0;
-      double g = (lk > cut * lmax && lk > 0) ? 1.0 / sqrt(lk) : 0.0;
-      double2 a = W[(size_t)i * n + k], b = W[(size_t)j * n + k];
+      const double2 a = wi[k], b = wj[k];
       // a * conj(b)
-      double re = a.x * b.x + a.y * b.y, im = a.y * b.x - a.x * b.y;
-      sr += f * re; si += f * im;
-      pr += g * re; pi += g * im;
+      const double re = a.x * b.x + a.y * b.y, im = a.y * b.x - a.x * b.y;
+      const double f = fs[k], g = gs[k];
+      sr += f * re;
+      si += f * im;
+      pr += g * re;
+      pi += g * im;
     }
     x[idx] = make_double2(sr, si);
     xp[idx] = make_double2(pr, pi);
@@ -1582,17 +1594,21 @@ __global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n,
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// rho[p][s][s'] = sum_i Y_p[s][i] conj(T_p[s'][i]): RHO_CHUNKS workgroups per problem each sum a
+// strided part into partial[p][chunk][8]; rho_sum_kernel adds the chunks in a fixed order.
+constexpr int RHO_CHUNKS = 64;
 __global__ __launch_bounds__(256) void rho_dot_kernel(const double *const *Y,
                                                       const double *const *T, const int64_t *len,
-                                                      double *rho) {
+                                                      double *partial) {
   __shared__ double sh[8];
-  const int p = blockIdx.x;
+  const int p = blockIdx.y;
   const double2 *y = reinterpret_cast<const double2 *>(Y[p]);
   const double2 *t = reinterpret_cast<const double2 *>(T[p]);
-  int64_t L = len[p];
+  const int64_t L = len[p];
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t i = threadIdx.x; i < L; i += blockDim.x) {
-    double2 y0 = y[i], y1 = y[L + i], t0 = t[i], t1 = t[L + i];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 y0 = y[i], y1 = y[L + i], t0 = t[i], t1 = t[L + i];
     // y_s * conj(t_s')
     acc[0] += y0.x * t0.x + y0.y * t0.y; acc[1] += y0.y * t0.x - y0.x * t0.y;
     acc[2] += y0.x * t1.x + y0.y * t1.y; acc[3] += y0.y * t1.x - y0.x * t1.y;
@@ -1600,9 +1616,18 @@ __global__ __launch_bounds__(256) void rho_dot_kernel(const double *const *Y,
     acc[6] += y1.x * t1.x + y1.y * t1.y; acc[7] += y1.y * t1.x - y1.x * t1.y;
   }
   for (int k = 0; k < 8; ++k) {
-    double s = block_sum<256>(acc[k], sh);
-    if (threadIdx.x == 0) rho[(size_t)p * 8 + k] = s;
+    const double s = block_sum<256>(acc[k], sh);
+    if (threadIdx.x == 0) partial[((size_t)p * gridDim.x + blockIdx.x) * 8 + k] = s;
   }
+}
+
+__global__ void rho_sum_kernel(const double *partial, int chunks, int nprob, double *rho) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nprob * 8) return;
+  const int p = idx / 8, k = idx % 8;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += partial[((size_t)p * chunks + c) * 8 + k];
+  rho[idx] = s;
 }
 
 __global__ void apply_op_kernel(const double *const *Tin, double *const *Tout,
@@ -1648,6 +1673,7 @@ class HipBackend : public Backend {
     if (skws_) HIPCHK(hipFree(skws_));
     if (cws_) HIPCHK(hipFree(cws_));
     if (lws_) HIPCHK(hipFree(lws_));
+    if (rws_) HIPCHK(hipFree(rws_));
     if (own_) hipStreamDestroy(s_);
   }
   void *alloc(size_t bytes) override {
@@ -1981,9 +2007,27 @@ class HipBackend : public Backend {
   }
   void rho_dot(const double *const *Y, const double *const *T, const int64_t *len, double *rho,
                int nprob) override {
+    if (nprob <= 0) return;
+    const size_t need = (size_t)nprob * RHO_CHUNKS * 8 * sizeof(double);
+    if (need > rws_bytes_) {
+      HIPCHK(hipStreamSynchronize(s_));
+      if (rws_) HIPCHK(hipFree(rws_));
+      rws_ = nullptr;
+      rws_bytes_ = 0;
+      if (hipMalloc(&rws_, need) != hipSuccess) {
+        err_ = -4;
+        errmsg_ = "observable workspace allocation failed";
+        return;
+      }
+      rws_bytes_ = need;
+    }
     stale_check("rho_dot_kernel");
-    hipLaunchKernelGGL(rho_dot_kernel, dim3(nprob), dim3(256), 0, s_, Y, T, len, rho);
+    hipLaunchKernelGGL(rho_dot_kernel, dim3(RHO_CHUNKS, nprob), dim3(256), 0, s_, Y, T, len,
+                       (double *)rws_);
     launch_check("rho_dot_kernel");
+    hipLaunchKernelGGL(rho_sum_kernel, dim3((nprob * 8 + 255) / 256), dim3(256), 0, s_,
+                       (const double *)rws_, RHO_CHUNKS, nprob, rho);
+    launch_check("rho_sum_kernel");
   }
   void apply_op(const double *const *Tin, double *const *Tout, const int64_t *half,
                 const double *ops, int nprob) override {
@@ -2004,6 +2048,8 @@ class HipBackend : public Backend {
   hipEvent_t ev_[8] = {};
   void *lws_ = nullptr;
   size_t lws_bytes_ = 0;
+  void *rws_ = nullptr;
+  size_t rws_bytes_ = 0;
   void *cws_ = nullptr;
   size_t cws_bytes_ = 0;
   void *skws_ = nullptr;
