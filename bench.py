@@ -17,6 +17,7 @@ The JSON line also carries:
                  measured FP64 MFMA rate x 4/3 (the 3M complex product issues 3/4 of the
                  algorithmic real flops).
   mixed        : the same window in mixed precision, with max / median |<Z>| difference to FP64.
+  chi128       : the same workload at chi = 128, steps 8..10 (FP64).
   theta_batch  : the eight theta_h values of the workload (20 steps each) solved together, one
                  serving slot each: aggregate Floquet steps/s.
   serving      : the seeded request stream (see serving_bench).
@@ -273,6 +274,32 @@ def theta_batch(lat, chi: int, depth: int) -> dict:
             "bp_sweeps_per_step": float(sum(sum(o["bp_iters"]) for o in outs)) / (len(thetas) * depth)}
 
 
+def chi128_window(lat, theta: float, warmup: int = 7, steps: int = 3) -> dict:
+    """The same workload at chi = 128 (bonds saturate after 7 steps): FP64 steps/s over `steps`
+    steps after `warmup`."""
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+
+    with bpki.Context(0) as ctx:
+        sess = ctx.session(bpki.spec_from_lattice(lat, theta, warmup + steps, 128))
+        for _ in range(warmup):
+            sess.step(observe=True)
+        iters = []
+        phase = np.zeros(4)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            iters.append(sess.step(observe=True)["bp_iters"])
+            phase += sess.last_timing()
+        wall = time.perf_counter() - t0
+        sess.close()
+    return {"chi": 128, "value": steps / wall, "unit": "Floquet steps/s",
+            "ms_per_step": 1e3 * wall / steps, "steps_timed": f"{warmup + 1}..{warmup + steps}",
+            "bp_sweeps_per_step": float(np.mean(iters)),
+            "phase_ms_per_step": {k: float(v / steps) for k, v in
+                                  zip(("rx", "gate_layers", "bp", "observe"), phase)}}
+
+
 def copy_probe(mib: int) -> int:
     """8 launches of torch's device copy kernel, each reading and writing ``mib`` MiB."""
     import torch
@@ -298,6 +325,8 @@ def main() -> int:
                     help="requests in the serving measurement (0 = skip; 256 = full stream)")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision window")
+    ap.add_argument("--chi128", type=int, default=1,
+                    help="1: also time steps 8..10 of the workload at chi = 128")
     ap.add_argument("--theta-batch", type=int, default=1,
                     help="1: also solve the eight theta_h values together (aggregate steps/s)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -400,6 +429,9 @@ def main() -> int:
         mixed["abs_dz_vs_fp64_median"] = float(np.median(dz))
         out["mixed"] = mixed
         print("mixed-precision window done", file=sys.stderr, flush=True)
+    if args.chi128:
+        out["chi128"] = chi128_window(lat, theta)
+        print("chi=128 window done", file=sys.stderr, flush=True)
     if args.theta_batch:
         out["theta_batch"] = theta_batch(lat, chi, args.warmup + args.steps)
         print("theta batch done", file=sys.stderr, flush=True)

@@ -188,6 +188,21 @@ def test_eagle_chi64_light_cone_exact(ctx):
     assert np.all(np.abs(g["z"]) <= 1 + 1e-12)
 
 
+def test_eagle_chi128_light_cone_exact(ctx):
+    """chi = 128 on the 127-qubit lattice (allowed: no two degree-3 sites share an edge; the
+    truncation eigenproblems have n = 2 chi = 256 and the Gram matrices n = 256): 4 untruncated
+    steps against exact light-cone values."""
+    print("[parity] eagle chi=128 4 steps vs light cone", flush=True)
+    e = L.eagle()
+    theta = 0.45
+    g = _gpu(ctx, e, theta, 4, 128)
+    for v in [62, 13, 0]:
+        for t in (2, 4):
+            exact = SV.light_cone_z(e.n_sites, e.edges, v, theta, t)
+            assert abs(g["z"][t - 1, v] - exact) < 1e-10, (v, t)
+    assert np.all(np.abs(g["z"]) <= 1 + 1e-12)
+
+
 def test_clifford_points_eagle(ctx):
     print("[parity] eagle Clifford points", flush=True)
     e = L.eagle()
