@@ -41,7 +41,7 @@ typedef struct {
 int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const double *A,
                    size_t a_elems, const double *B, size_t b_elems, double *C, size_t c_elems);
 
-/* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32 and n > 128, Householder
+/* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32, Householder
  * tridiagonalisation + divide and conquer otherwise) of nprob n x n matrices (n <= 256):
  * evals [nprob][n] descending, vecs [nprob][n][n] with column i the eigenvector of evals[i]. */
 int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *evals,

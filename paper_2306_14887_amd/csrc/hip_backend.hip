@@ -7,11 +7,11 @@
 //                 epilogue as re = P1 - P2, im = P3 - P1 - P2.  Operands are staged
 //                 through LDS in split re/im planes; the global loads follow whichever index is
 //                 unit-stride so they coalesce for every leg ordering of the site tensors.
-//  * eigh: batched Hermitian eigendecomposition in FP64.  n < 32 and n > 128: cyclic Jacobi
-//          with the parallel round-robin ordering (n/2 disjoint rotations per round, all 2x2
-//          block updates of a round in parallel; LDS for n < 32, else a global work area).
-//          32 <= n <= 128: Householder tridiagonalisation and divide and conquer, one
-//          workgroup per matrix, then a column-parallel back-transformation.
+//  * eigh: batched Hermitian eigendecomposition in FP64.  n < 32: cyclic Jacobi in LDS with
+//          the parallel round-robin ordering (n/2 disjoint rotations per round, all 2x2 block
+//          updates of a round in parallel).  32 <= n <= 256: Householder tridiagonalisation
+//          and divide and conquer, one workgroup per matrix (matrix in LDS up to n = 128, in
+//          an L2-resident work area above), then a column-parallel back-transformation.
 //  * small kernels for the X rotations, message square roots, Gram factor, the gate block,
 //    truncation, BP normalisation/residual and the site density matrices.
 #include <hip/hip_runtime.h>
@@ -331,12 +331,10 @@ __device__ __forceinline__ void pair_of(int r, int i, int np, int &p, int &q) {
   else { p = (r + i) % m; q = (r - i + m) % m; }
 }
 
-template <bool LDS>
 __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
                                                            const double *const *in,
                                                            double *const *evals,
-                                                           double *const *vecs, double2 *gws,
-                                                           int max_sweeps) {
+                                                           double *const *vecs, int max_sweeps) {
   extern __shared__ double2 smem[];
   __shared__ Rot rot[128];
   __shared__ int any_rot;
@@ -346,9 +344,7 @@ __global__ __launch_bounds__(1024) void eigh_jacobi_kernel(int n, int lda,
   const int tid = threadIdx.x, nt = blockDim.x;
   const int np = n + (n & 1);
   const int h = np / 2;
-  double2 *A, *V;
-  if (LDS) { A = smem; V = smem + (size_t)np * np; }
-  else { A = gws + (size_t)prob * 2 * np * np; V = A + (size_t)np * np; }
+  double2 *A = smem, *V = smem + (size_t)np * np;
   const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
   double fro2 = 0.0;
   for (int idx = tid; idx < np * np; idx += nt) {
@@ -457,22 +453,22 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Hermitian eigensolver for 32 <= n <= 128 in two kernels.
+// Hermitian eigensolver for 32 <= n <= 256 in two kernels.
 //
 // eigh_tridiag_dc_kernel (one workgroup of 512 threads per matrix):
 //  1. Householder reduction to real symmetric tridiagonal form, A = Q T Q^H with
 //     Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^H (v_k(k+1) = 1, zero above).  Each
 //     reflector maps column k below the diagonal onto beta e_1 with beta real, so T is real.
 //     The trailing block is updated as A <- A - v w^H - w v^H with x = tau A v and
-//     w = x - (1/2) Re(conj(tau) v^H x) v.  The matrix is held packed (lower triangle) in LDS;
-//     reflectors go to the workspace.
+//     w = x - (1/2) Re(conj(tau) v^H x) v.  Only the lower triangle is kept (packed in LDS for
+//     n <= 128, row-major in the workspace above); reflectors go to the workspace.
 //  2. Divide and conquer on T (Cuppen's rank-one tearing; eigenvectors by the Gu-Eisenstat
 //     construction).  The index range is cut into the binary tree of ranges
-//     [floor(q n / 2^D), floor((q+1) n / 2^D)); the couplings beta at the seven cuts of the top
-//     three levels are torn off (T = diag(T_1 .. T_8) + sum |beta| u u^T with
-//     u = e_{k-1} + sign(beta) e_k and the two diagonal entries lowered by |beta|).  The eight
-//     leaves (8..16 entries) are diagonalised by cyclic Jacobi, one wave each, and merged back
-//     pairwise by the whole workgroup.  A merge of two solved halves with eigenvectors
+//     [floor(q n / 2^D), floor((q+1) n / 2^D)); the couplings beta at the cuts above the
+//     leaves (depth 3 for n <= 128, depth 4 above) are torn off (T = diag(T_1 .. T_L) +
+//     sum |beta| u u^T with u = e_{k-1} + sign(beta) e_k and the two diagonal entries lowered
+//     by |beta|).  The leaves (8..16 entries) are diagonalised by cyclic Jacobi, one wave
+//     each, and merged back pairwise by the whole workgroup.  A merge of two solved halves with eigenvectors
 //     Q = diag(Q1, Q2) solves D + rho z z^T (z = Q^T u / sqrt 2, rho = 2|beta|):
 //       - deflation: components with rho |z_i| <= tol keep (d_i, q_i); pairs of eigenvalues
 //         closer than tol are rotated so that one z component vanishes
@@ -490,10 +486,12 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 // H_{n-2}, ..., H_0 to each column block in LDS; sorts into descending eigenvalue order.
 //
 // Workspace per matrix (doubles): reflectors n*n complex (column k = v_k), tau n complex,
-// Z n*n real (column-major; during the merges it holds the coefficient vectors V), eigenvalues
-// n, and an n*n staging area for the merges.
+// Z n*n real (column-major), eigenvalues n, an n*n staging area for the merges, and for
+// n > 128 an n*n complex area that holds the matrix during the reduction (its lower triangle,
+// row-major) and the merge coefficient vectors V afterwards.  For n <= 128 the matrix and Z
+// live in LDS and Z's global area holds V during the merges.
 __host__ __device__ __forceinline__ size_t tql_ws_doubles(int n) {
-  return (size_t)4 * n * n + (size_t)3 * n;
+  return (size_t)(n > 128 ? 6 : 4) * n * n + (size_t)3 * n;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -519,7 +517,7 @@ __device__ double block_max512(double v, double *red) {
 }
 
 // Merges the solved ranges [lo, k) and [k, hi) coupled by beta (all 512 threads).
-// d: eigenvalues (LDS), Z: eigenvectors (LDS, column-major, leading dimension n);
+// d: eigenvalues (LDS), Z: eigenvectors (column-major, leading dimension n; LDS or global);
 // Vg, Wg: n x n global staging areas of this matrix.
 __device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, double *Z,
                          const DcScratch &S, double *Vg, double *Wg) {
@@ -779,32 +777,44 @@ __device__ __forceinline__ int dc_bound(int q, int n, int depth) {
   return (int)(((long)q * n) >> depth);
 }
 
+// NMAX = 128: matrix (packed lower triangle) and Z in LDS, leaves at depth 3.
+// NMAX = 256: matrix (lower triangle of a row-major n x n array) and Z in this matrix's
+// workspace, which stays in L2; leaves at depth 4.  Both use 512 threads.
+template <int NMAX>
 __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
                                                               const double *const *in,
                                                               double *ws) {
+  constexpr bool BIG = NMAX > 128;
+  constexpr int LD = BIG ? 4 : 3;               // depth of the leaves
   extern __shared__ double2 smem[];
-  __shared__ double d_s[128], e_s[128];
-  // phase-local scratch: reflector vectors (stage 1), leaf matrices (leaves), merge arrays
-  __shared__ __attribute__((aligned(16))) double sbuf[1664];
+  __shared__ double d_s[NMAX], e_s[NMAX];
+  // phase-local scratch: reduction vectors (stage 1), leaf matrices (leaves), merge arrays
+  __shared__ __attribute__((aligned(16))) double sbuf[13 * NMAX];
   __shared__ double2 tau_sh;
-  double2 *v_s = reinterpret_cast<double2 *>(sbuf), *w_s = v_s + 128;
+  double2 *v_s = reinterpret_cast<double2 *>(sbuf), *w_s = v_s + NMAX;
+  double2 *x1_s = w_s + NMAX, *x2_s = x1_s + NMAX;   // BIG: row part, two column partials
   const int prob = blockIdx.x;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int nw = blockDim.x >> 6;
+  constexpr int nw = 8;
   double *base = ws + (size_t)prob * tql_ws_doubles(n);
   double2 *hh = reinterpret_cast<double2 *>(base);
   double2 *tau_g = hh + (size_t)n * n;
   double *Zg = reinterpret_cast<double *>(tau_g + n);
   double *dg = Zg + (size_t)n * n;
   double *Wg = dg + n;
-  double2 *P = smem;
+  double2 *Pg = reinterpret_cast<double2 *>(Wg + (size_t)n * n);
   const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+  // element (i, j), i >= j, of the matrix being reduced
+  auto pel = [&](int i, int j) -> double2 & {
+    if constexpr (BIG) return Pg[(size_t)i * n + j];
+    else return smem[pk_idx(i, j)];
+  };
 
-  // Hermitian part of the input, lower triangle packed by rows
+  // Hermitian part of the input, lower triangle
   for (int i = wave; i < n; i += nw)
     for (int j = lane; j <= i; j += 64) {
       double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
-      P[pk_idx(i, j)] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+      pel(i, j) = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
     }
   __syncthreads();
 
@@ -814,11 +824,11 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
     if (wave == 0) {
       double sq = 0.0;
       for (int i = 1 + lane; i < m; i += 64) {
-        double2 x = P[pk_idx(k + 1 + i, k)];
+        double2 x = pel(k + 1 + i, k);
         sq += x.x * x.x + x.y * x.y;
       }
       sq = wave_sum(sq);
-      const double2 alpha = P[pk_idx(k + 1, k)];
+      const double2 alpha = pel(k + 1, k);
       double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
       double beta = alpha.x;
       if (sq > 0.0 || alpha.y != 0.0) {
@@ -829,7 +839,7 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
         scale = make_double2(den.x / dn, -den.y / dn);
       }
       for (int i = lane; i < m; i += 64) {
-        double2 vi = i == 0 ? make_double2(1.0, 0.0) : cmul(P[pk_idx(k + 1 + i, k)], scale);
+        double2 vi = i == 0 ? make_double2(1.0, 0.0) : cmul(pel(k + 1 + i, k), scale);
         v_s[i] = vi;
         hh[(size_t)k * n + k + 1 + i] = vi;
       }
@@ -837,27 +847,27 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
         tau_sh = tau;
         tau_g[k] = tau;
         e_s[k] = beta;
-        d_s[k] = P[pk_idx(k, k)].x;
+        d_s[k] = pel(k, k).x;
       }
     }
     __syncthreads();
     const double2 tau = tau_sh;
     if (tau.x == 0.0 && tau.y == 0.0) continue;   // H_k = I (uniform over the block)
-    // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): 4 threads per row;
-    // row gi of S is row gi of the packed triangle up to the diagonal, then column gi
-    {
+    if constexpr (!BIG) {
+      // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): 4 threads per row;
+      // row gi of S is row gi of the packed triangle up to the diagonal, then column gi
       const int r = tid >> 2, q = tid & 3;
       double2 acc = make_double2(0.0, 0.0);
       if (r < m) {
         const int gi = k + 1 + r;
-        const double2 *prow = P + pk_idx(gi, k + 1);
+        const double2 *prow = smem + pk_idx(gi, k + 1);
         for (int c = q; c <= r; c += 4) {
           const double2 a = prow[c], vc = v_s[c];
           acc.x += a.x * vc.x - a.y * vc.y;
           acc.y += a.x * vc.y + a.y * vc.x;
         }
         for (int c = r + 1 + q; c < m; c += 4) {
-          const double2 a = P[pk_idx(k + 1 + c, gi)], vc = v_s[c];   // conj(a) vc
+          const double2 a = smem[pk_idx(k + 1 + c, gi)], vc = v_s[c];   // conj(a) vc
           acc.x += a.x * vc.x + a.y * vc.y;
           acc.y += a.x * vc.y - a.y * vc.x;
         }
@@ -867,49 +877,110 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
       acc.x += __shfl_xor(acc.x, 2, 64);
       acc.y += __shfl_xor(acc.y, 2, 64);
       if (r < m && q == 0) w_s[r] = cmul(tau, acc);
+    } else {
+      // S v from the lower triangle in two coalesced passes: the row part (diagonal included)
+      // with 16 lanes per row, and the strictly upper part as conj(S)^T v with one lane per
+      // column and the rows split in two halves by parity
+      const double2 *S0 = Pg + (size_t)(k + 1) * n + k + 1;
+      {
+        const int q = tid & 15;
+        for (int r = tid >> 4; r < m; r += 32) {
+          const double2 *prow = S0 + (size_t)r * n;
+          double2 acc = make_double2(0.0, 0.0);
+          for (int c = q; c <= r; c += 16) {
+            const double2 a = prow[c], vc = v_s[c];
+            acc.x += a.x * vc.x - a.y * vc.y;
+            acc.y += a.x * vc.y + a.y * vc.x;
+          }
+#pragma unroll
+          for (int o = 1; o < 16; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+          }
+          if (q == 0) x1_s[r] = acc;
+        }
+      }
+      {
+        const int c = tid & 255, half = tid >> 8, c0 = c & ~63;
+        if (c0 < m) {
+          double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+          for (int r = c0 + 1 + half; r < m; r += 2) {
+            if (r > c) {
+              const double2 a = S0[(size_t)r * n + c], vr = v_s[r];   // conj(a) v_r
+              acc.x += a.x * vr.x + a.y * vr.y;
+              acc.y += a.x * vr.y - a.y * vr.x;
+            }
+          }
+          if (c < m) x2_s[half * NMAX + c] = acc;
+        }
+      }
     }
     __syncthreads();
-    // every wave forms a = -(1/2) Re(conj(tau) v^H x) itself (x is in w_s); then
-    // S <- S - v w^H - w v^H on the lower triangle with w = x + a v formed on the fly
+    // every wave forms a = -(1/2) Re(conj(tau) v^H x) itself; then S <- S - v w^H - w v^H on
+    // the lower triangle with w = x + a v formed on the fly
+    auto xval = [&](int i) -> double2 {
+      if constexpr (BIG) {
+        const double2 t = x1_s[i], u = x2_s[i], w = x2_s[NMAX + i];
+        return cmul(tau, make_double2(t.x + u.x + w.x, t.y + u.y + w.y));
+      } else {
+        return w_s[i];
+      }
+    };
     double dr = 0.0, di = 0.0;
     for (int i = lane; i < m; i += 64) {
-      const double2 vi = v_s[i], xi = w_s[i];
+      const double2 vi = v_s[i], xi = xval(i);
       dr += vi.x * xi.x + vi.y * xi.y;
       di += vi.x * xi.y - vi.y * xi.x;
     }
     dr = wave_sum(dr);
     di = wave_sum(di);
     const double aw = -0.5 * (tau.x * dr + tau.y * di);
+    // w at this lane's columns (c = lane + 64 t)
+    double2 wl[NMAX / 64];
+#pragma unroll
+    for (int t = 0; t < NMAX / 64; ++t) {
+      const int c = lane + 64 * t;
+      if (c < m) {
+        const double2 vc = v_s[c], xc = xval(c);
+        wl[t] = make_double2(xc.x + aw * vc.x, xc.y + aw * vc.y);
+      } else {
+        wl[t] = make_double2(0.0, 0.0);
+      }
+    }
     for (int rr = wave; rr < m; rr += nw) {
       const int gi = k + 1 + rr;
-      const double2 vi = v_s[rr], xi = w_s[rr];
+      const double2 vi = v_s[rr], xi = xval(rr);
       const double2 wi = make_double2(xi.x + aw * vi.x, xi.y + aw * vi.y);
-      double2 *prow = P + pk_idx(gi, k + 1);
-      for (int c = lane; c <= rr; c += 64) {
-        const double2 vc = v_s[c], xc = w_s[c];
-        const double2 wc = make_double2(xc.x + aw * vc.x, xc.y + aw * vc.y);
-        const double2 a = prow[c];
-        const double ur = vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
-        const double ui = vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
-        prow[c] = make_double2(a.x - ur, c == rr ? 0.0 : a.y - ui);
+      double2 *prow = &pel(gi, k + 1);
+#pragma unroll
+      for (int t = 0; t < NMAX / 64; ++t) {
+        const int c = lane + 64 * t;
+        if (c <= rr) {
+          const double2 vc = v_s[c], wc = wl[t];
+          const double2 a = prow[c];
+          const double ur = vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
+          const double ui = vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
+          prow[c] = make_double2(a.x - ur, c == rr ? 0.0 : a.y - ui);
+        }
       }
     }
     __syncthreads();
   }
   if (tid == 0) {
-    d_s[n - 1] = P[pk_idx(n - 1, n - 1)].x;
+    d_s[n - 1] = pel(n - 1, n - 1).x;
     e_s[n - 1] = 0.0;
   }
   __syncthreads();
 
   // ---- 2. divide and conquer on (d, e) ----
-  // Z = I (column-major, in the LDS that held the matrix); tear the couplings at the seven
-  // split points of the top three levels
-  double *Z = reinterpret_cast<double *>(smem);
+  // Z = I (column-major); tear the couplings at the split points above the leaves
+  double *Z = BIG ? Zg : reinterpret_cast<double *>(smem);
+  double *Vg = BIG ? reinterpret_cast<double *>(Pg) : Zg;
   for (int idx = tid; idx < n * n; idx += blockDim.x) Z[idx] = (idx % (n + 1)) == 0 ? 1.0 : 0.0;
   __syncthreads();
   if (tid == 0)
-    for (int D = 0; D < 3; ++D)
+    for (int D = 0; D < LD; ++D)
       for (int q = 0; q < (1 << D); ++q) {
         const int k = dc_bound(2 * q + 1, n, D + 1);
         if (k <= 0 || k >= n) continue;
@@ -918,11 +989,11 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
         d_s[k] -= r;
       }
   __syncthreads();
-  // leaves: the eight ranges of depth 3 (8..16 entries), cyclic Jacobi by one wave each on the
+  // leaves: the ranges of depth LD (8..16 entries), cyclic Jacobi by one wave each on the
   // packed 16 x 16 tridiagonal block (padding indices have no coupling and never rotate)
-  {
+  for (int leaf = wave; leaf < (1 << LD); leaf += nw) {
     const double eps = 2.220446049250313e-16;
-    const int lo = dc_bound(wave, n, 3), m = dc_bound(wave + 1, n, 3) - lo;
+    const int lo = dc_bound(leaf, n, LD), m = dc_bound(leaf + 1, n, LD) - lo;
     double *A = sbuf + wave * 136;
     double *rcs = sbuf + 1088 + wave * 16;          // c[8], s[8]
     auto at = [&](int i, int j) -> double & { return i >= j ? A[pk_idx(i, j)] : A[pk_idx(j, i)]; };
@@ -1005,38 +1076,42 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
       if (__ballot(rotated) == 0) break;
     }
     if (lane < m) d_s[lo + lane] = A[pk_idx(lane, lane)];
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // merges of the top three levels by the whole workgroup
+  // merges of the levels above the leaves by the whole workgroup
   {
     DcScratch S;
-    S.z = sbuf; S.dd = sbuf + 128; S.zK = sbuf + 256; S.dK = sbuf + 384; S.tau = sbuf + 512;
-    S.dorg = sbuf + 640; S.zh = sbuf + 768; S.lam = sbuf + 896; S.rc = sbuf + 1024;
-    S.rs = sbuf + 1152;
-    int *ib = reinterpret_cast<int *>(sbuf + 1280);
-    S.perm = ib; S.K = ib + 128; S.defl = ib + 256; S.ra = ib + 384; S.rb = ib + 512;
-    S.cnt = ib + 640;
-    S.red = sbuf + 1608;
-    for (int D = 2; D >= 0; --D)
+    S.z = sbuf; S.dd = sbuf + NMAX; S.zK = sbuf + 2 * NMAX; S.dK = sbuf + 3 * NMAX;
+    S.tau = sbuf + 4 * NMAX; S.dorg = sbuf + 5 * NMAX; S.zh = sbuf + 6 * NMAX;
+    S.lam = sbuf + 7 * NMAX; S.rc = sbuf + 8 * NMAX; S.rs = sbuf + 9 * NMAX;
+    int *ib = reinterpret_cast<int *>(sbuf + 10 * NMAX);
+    S.perm = ib; S.K = ib + NMAX; S.defl = ib + 2 * NMAX; S.ra = ib + 3 * NMAX;
+    S.rb = ib + 4 * NMAX; S.cnt = ib + 5 * NMAX;
+    S.red = sbuf + 10 * NMAX + 5 * NMAX / 2 + 8;
+    for (int D = LD - 1; D >= 0; --D)
       for (int q = 0; q < (1 << D); ++q) {
         const int lo = dc_bound(q, n, D), hi = dc_bound(q + 1, n, D);
         const int k = dc_bound(2 * q + 1, n, D + 1);
-        if (lo < k && k < hi) dc_merge(n, lo, k, hi, e_s[k - 1], d_s, Z, S, Zg, Wg);
+        if (lo < k && k < hi) dc_merge(n, lo, k, hi, e_s[k - 1], d_s, Z, S, Vg, Wg);
       }
   }
-  for (int idx = tid; idx < n * n; idx += blockDim.x) Zg[idx] = Z[idx];
+  if constexpr (!BIG)
+    for (int idx = tid; idx < n * n; idx += blockDim.x) Zg[idx] = Z[idx];
   for (int i = tid; i < n; i += blockDim.x) dg[i] = d_s[i];
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const double *ws,
                                                                  double *const *evals,
                                                                  double *const *vecs) {
   constexpr int CB = 16;
-  __shared__ double2 Vb[128 * CB];
-  __shared__ double2 vk[128];
+  __shared__ double2 Vb[NMAX * CB];
+  __shared__ double2 vk[NMAX];
   __shared__ double2 part[4][CB];
   __shared__ double2 wk[CB];
-  __shared__ double dsh[128];
+  __shared__ double dsh[NMAX];
   const int prob = blockIdx.y, c0 = blockIdx.x * CB;
   const int tid = threadIdx.x;
   const double *base = ws + (size_t)prob * tql_ws_doubles(n);
@@ -1659,17 +1734,16 @@ class HipBackend : public Backend {
       HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
       own_ = true;
     }
-    HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel<true>,
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
     HIPCHK(hipFuncSetAttribute((const void *)gram_chol_lds_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
-    HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_dc_kernel,
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_dc_kernel<128>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
   }
   ~HipBackend() override {
     for (auto &e : ev_)
       if (e) hipEventDestroy(e);
-    if (gws_) HIPCHK(hipFree(gws_));
     if (skws_) HIPCHK(hipFree(skws_));
     if (cws_) HIPCHK(hipFree(cws_));
     if (lws_) HIPCHK(hipFree(lws_));
@@ -1838,13 +1912,19 @@ class HipBackend : public Backend {
   void eigh(int n, int lda, const double *const *in, double *const *evals, double *const *vecs,
             int nprob) override {
     if (nprob <= 0) return;
+    if (n < 1 || n > 256) {
+      err_ = -1;
+      errmsg_ = "eigh: n must be in 1..256";
+      return;
+    }
     int np = n + (n & 1);
     if (n < 32) {
       size_t sm = (size_t)2 * np * np * sizeof(double2);
       stale_check("eigh_jacobi_kernel");
-      hipLaunchKernelGGL(eigh_jacobi_kernel<true>, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
-                         evals, vecs, (double2 *)nullptr, 60);
-    } else if (n <= 128) {
+      hipLaunchKernelGGL(eigh_jacobi_kernel, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
+                         evals, vecs, 60);
+    } else {
+      // n <= 256 (the callers' limit)
       size_t need = (size_t)nprob * tql_ws_doubles(n) * sizeof(double);
       if (need > lws_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
@@ -1858,33 +1938,25 @@ class HipBackend : public Backend {
         }
         lws_bytes_ = need;
       }
-      size_t sm = std::max((size_t)n * (n + 1) / 2 * sizeof(double2), (size_t)n * n * sizeof(double));
       stale_check("eigh_tridiag_dc_kernel");
-      hipLaunchKernelGGL(eigh_tridiag_dc_kernel, dim3(nprob), dim3(512), sm, s_, n, lda, in,
-                         (double *)lws_);
+      if (n <= 128) {
+        size_t sm = std::max((size_t)n * (n + 1) / 2 * sizeof(double2), (size_t)n * n * sizeof(double));
+        hipLaunchKernelGGL(eigh_tridiag_dc_kernel<128>, dim3(nprob), dim3(512), sm, s_, n, lda,
+                           in, (double *)lws_);
+      } else {
+        hipLaunchKernelGGL(eigh_tridiag_dc_kernel<256>, dim3(nprob), dim3(512), 0, s_, n, lda,
+                           in, (double *)lws_);
+      }
       launch_check("eigh_tridiag_dc_kernel");
       stale_check("eigh_backtransform_kernel");
-      hipLaunchKernelGGL(eigh_backtransform_kernel, dim3((n + 15) / 16, nprob), dim3(256), 0, s_,
-                         n, (const double *)lws_, evals, vecs);
-    } else {
-      size_t need = (size_t)nprob * 2 * np * np * sizeof(double2);
-      if (need > gws_bytes_) {
-        HIPCHK(hipStreamSynchronize(s_));
-        if (gws_) HIPCHK(hipFree(gws_));
-        gws_ = nullptr;
-        if (hipMalloc(&gws_, need) != hipSuccess) {
-          err_ = -4;
-          errmsg_ = "eigh workspace allocation failed";
-          gws_bytes_ = 0;
-          return;
-        }
-        gws_bytes_ = need;
-      }
-      stale_check("eigh_jacobi_kernel");
-      hipLaunchKernelGGL(eigh_jacobi_kernel<false>, dim3(nprob), dim3(1024), 0, s_, n, lda, in,
-                         evals, vecs, (double2 *)gws_, 60);
+      if (n <= 128)
+        hipLaunchKernelGGL(eigh_backtransform_kernel<128>, dim3((n + 15) / 16, nprob), dim3(256),
+                           0, s_, n, (const double *)lws_, evals, vecs);
+      else
+        hipLaunchKernelGGL(eigh_backtransform_kernel<256>, dim3((n + 15) / 16, nprob), dim3(256),
+                           0, s_, n, (const double *)lws_, evals, vecs);
     }
-    launch_check("eigh_jacobi_kernel");
+    launch_check("eigh");
   }
   void rx(double *const *t, const int64_t *half, int nprob, double c, double s) override {
     stale_check("rx_kernel");
@@ -2043,8 +2115,6 @@ class HipBackend : public Backend {
   int dev_;
   hipStream_t s_;
   bool own_;
-  void *gws_ = nullptr;
-  size_t gws_bytes_ = 0;
   hipEvent_t ev_[8] = {};
   void *lws_ = nullptr;
   size_t lws_bytes_ = 0;

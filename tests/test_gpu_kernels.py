@@ -122,7 +122,7 @@ def test_gemm_rejects_out_of_bounds_descriptor(ctx):
         ctx.test_gemm(d, A, np.zeros(64 * 64, complex), np.zeros(64 * 64, complex))
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 31, 32, 40, 63, 64, 65, 97, 127, 128, 200])
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 31, 32, 40, 63, 64, 65, 97, 127, 128, 129, 200, 256])
 def test_eigh_matches_numpy(ctx, n):
     print(f"[eigh] n={n}", flush=True)
     rng = np.random.default_rng(n)
