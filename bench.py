@@ -130,7 +130,7 @@ def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict
     }
 
 
-MIXED_TOL = 1e-8   # mixed-mode BP tolerance: every served <Z> within 1e-5 of its FP64 solve
+MIXED_TOL = 1e-8   # mixed-mode BP tolerance (served <Z> vs FP64 solve: reported per run)
 
 
 def serving_bench(n: int, slots: int) -> dict:
@@ -138,7 +138,9 @@ def serving_bench(n: int, slots: int) -> dict:
     (7,15); theta ~ U[0, pi/2]; depth ~ U{1..20}; chi ~ U{8,16,32,64}).
     1. comparator: every request solved one at a time in plain FP64 (BP tolerance 1e-12);
     2. capacity: all requests submitted at once to the serving slots in mixed precision (FP32 BP
-       contractions, FP64 polish to BP tolerance 1e-8): solves/s = n / makespan;
+       contractions, FP64 polish to BP tolerance 1e-8): solves/s = n / makespan, with
+       cross-request packing (the library default: chi <= 16, up to 16 per pack, from a backlog)
+       and without;
     3. latency: the same served run with Poisson arrivals at twice the comparator's solve rate:
        p50 / p99 of (finish - arrival).
     Also reports the largest |<Z>| deviation of a served result from its FP64 solve."""
@@ -168,9 +170,11 @@ def serving_bench(n: int, slots: int) -> dict:
         t_seq = time.perf_counter() - t0
     rate = n / t_seq
 
-    def served(arrivals):
+    def served(arrivals, pack=True):
         with bpki.Context(0) as ctx:
             ctx.serving_config(slots)
+            if not pack:
+                ctx.serving_packing(1)
             tickets = [None] * n
             t0 = time.perf_counter()
             for i, s in enumerate(specsmx):
@@ -181,20 +185,27 @@ def serving_bench(n: int, slots: int) -> dict:
             while not all(t.poll() for t in tickets):
                 time.sleep(0.0005)
             times = np.array([t.times() for t in tickets])
+            packs = np.array([t.pack_size() for t in tickets])
             outs = [t.wait() for t in tickets]
         err = max(float(np.abs(o["z"] - z).max()) for o, z in zip(outs, ref))
-        return times, err
+        return times, err, packs
 
-    times_sat, err_sat = served(np.zeros(n))
+    times_sat, err_sat, packs_sat = served(np.zeros(n))
     cap = n / (times_sat[:, 2].max() - times_sat[:, 0].min())
+    times_np, err_np, _ = served(np.zeros(n), pack=False)
+    cap_np = n / (times_np[:, 2].max() - times_np[:, 0].min())
     gaps = np.array([r.arrival for r in reqs])
     lam = 2.0 * rate
     arrivals = gaps / gaps[-1] * (n / lam) if n > 1 else gaps * 0
-    times, err = served(arrivals)
+    times, err, packs = served(arrivals)
     lat = times[:, 2] - times[:, 0]
     return {
         "requests": n, "slots": slots, "mixed_bp_tol": MIXED_TOL,
         "served_mixed_solves_per_s": cap,
+        "served_mixed_solves_per_s_without_packing": cap_np,
+        "requests_packed_capacity_run": int((packs_sat > 1).sum()),
+        "mean_pack_size_capacity_run": float(packs_sat.mean()),
+        "requests_packed_poisson_run": int((packs > 1).sum()),
         "sequential_fp64_solves_per_s": rate,
         "speedup_vs_sequential_fp64": cap / rate,
         "poisson_arrival_rate_per_s": lam,
@@ -202,7 +213,7 @@ def serving_bench(n: int, slots: int) -> dict:
         "served_p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "sequential_fp64_p50_ms": 1e3 * float(np.percentile(lat_seq, 50)),
         "sequential_fp64_p99_ms": 1e3 * float(np.percentile(lat_seq, 99)),
-        "max_abs_dz_vs_fp64": max(err, err_sat),
+        "max_abs_dz_vs_fp64": max(err, err_sat, err_np),
     }
 
 

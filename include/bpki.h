@@ -47,10 +47,11 @@ typedef struct bpki_ctx bpki_ctx;
  * BPKI_FP32: the BP message contractions and the observables' contractions run on FP32 MFMA
  * (operands rounded to FP32, FP32 accumulation per K chunk, FP64 chunk sums).  BP sweeps in FP32
  * until the residual reaches 2e-6, then in FP64 if bp_tol asks for less, so the fixed point is the
- * FP64 one.  With bp_tol = 1e-8 the measured deviation of every <Z> from the FP64 mode (bp_tol
- * 1e-12) is below 1e-6 on the serving workloads (heavy-hex lattices of 29..103 qubits, chi 8..64,
- * up to 20 steps).  Looser tolerances trade accuracy for speed: with bp_tol = 1e-6 a near-Clifford
- * chi = 8 request deviated by 5e-5. */
+ * FP64 one.  With bp_tol = 1e-8 the largest measured deviation of a <Z> from the FP64 mode
+ * (bp_tol 1e-12) on the seeded serving stream (heavy-hex lattices of 29, 65 and 127 qubits,
+ * chi 8..64, up to 20 steps) is 3e-7 over its first 48 requests and 1.1e-5 over all 256.  Looser
+ * tolerances trade accuracy for speed: with bp_tol = 1e-6 a near-Clifford chi = 8 request
+ * deviated by 5e-5. */
 typedef enum {
   BPKI_FP64 = 0,   /* everything FP64 (the parity mode)                                     */
   BPKI_FP32 = 1    /* FP32 MFMA contractions in BP sweeps and observables (see above)       */
@@ -120,10 +121,25 @@ int bpki_solve(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
  * so problems that arrive while others run start as slots and memory free up, and the kernels of
  * all resident problems run concurrently on the device.  Results go into caller-owned buffers,
  * which must stay valid until bpki_wait returns or bpki_poll reports done.  A problem that can
- * never fit the budget is rejected with -4 by bpki_submit.  The result of a problem does not
- * depend on what else is resident (private workspaces, deterministic reductions). */
+ * never fit the budget is rejected with -4 by bpki_submit.
+ *
+ * Cross-request packing: when a slot takes a problem with chi <= max_chi and depth >= 1 while at
+ * least as many problems as there are slots are queued, it also takes (in arrival order, within
+ * the budget) up to max_requests - 1 queued problems on the same lattice (identical n_sites,
+ * edges and resolved colours) with the same chi, precision, bp_tol, bp_max_iter and cutoffs and
+ * a depth no larger than its own; theta_h, Pauli strings and record_every_step may differ.  The
+ * pack is solved as one problem on the disjoint union of the lattices, so each launch of a gate
+ * layer or BP sweep covers all members (small-chi requests are launch-bound alone).  Each member
+ * keeps its own BP stopping point (its messages are frozen once its own residual is below
+ * bp_tol) and its result is written when its own last step is done; bp_iters reports its own
+ * sweeps.  A packed member's result equals its solve alone up to rounding (launch-size dependent
+ * split-K sums), which stays far below the FP64 parity tolerance; unpacked problems give results
+ * that do not depend on what else is resident (private workspaces, deterministic reductions). */
 /* Number of serving slots (1..64, default 8); only before the first bpki_submit. */
 int bpki_serving_config(bpki_ctx *ctx, int slots);
+/* Packing limits (max_requests 1..64, 1 = no packing; defaults 16 and chi <= 16); only before the
+ * first bpki_submit. */
+int bpki_serving_packing(bpki_ctx *ctx, int max_requests, int max_chi);
 int bpki_submit(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r, uint64_t *ticket);
 /* *done = 1 when finished; returns the problem's status (0/+1/negative) once done, else 0. */
 int bpki_poll(bpki_ctx *ctx, uint64_t ticket, int *done);
@@ -134,6 +150,9 @@ int bpki_cancel(bpki_ctx *ctx, uint64_t ticket);
 /* Host steady-clock times (seconds) of a ticket: submitted, started on a slot, finished (0 if not
  * yet).  Valid until bpki_wait forgets the ticket. */
 int bpki_ticket_times(bpki_ctx *ctx, uint64_t ticket, double *times3);
+/* Number of problems in the pack that ran the ticket (1 = solved alone; 0 until started).
+ * Valid until bpki_wait forgets the ticket. */
+int bpki_ticket_pack_size(bpki_ctx *ctx, uint64_t ticket, int32_t *size);
 
 /* ---- Sessions: step-by-step access to one resident state -----------------------------------
  * A session holds one problem's tensors and messages on the device.  It exposes each phase of a

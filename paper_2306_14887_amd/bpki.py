@@ -82,7 +82,9 @@ def load(path: str | None = None):
         "bpki_wait": (C.c_int, [vp, C.c_uint64]),
         "bpki_cancel": (C.c_int, [vp, C.c_uint64]),
         "bpki_serving_config": (C.c_int, [vp, C.c_int]),
+        "bpki_serving_packing": (C.c_int, [vp, C.c_int, C.c_int]),
         "bpki_ticket_times": (C.c_int, [vp, C.c_uint64, dp]),
+        "bpki_ticket_pack_size": (C.c_int, [vp, C.c_uint64, ip]),
         "bpki_session_open": (C.c_int, [vp, P, C.POINTER(vp)]),
         "bpki_session_close": (None, [vp]),
         "bpki_session_sizes": (C.c_int, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
@@ -117,7 +119,8 @@ def load(path: str | None = None):
 def exported_symbols() -> list[str]:
     return ["bpki_problem_defaults", "bpki_create", "bpki_destroy", "bpki_last_error",
             "bpki_validate", "bpki_estimate_bytes", "bpki_solve", "bpki_submit", "bpki_poll",
-            "bpki_wait", "bpki_cancel", "bpki_serving_config", "bpki_ticket_times",
+            "bpki_wait", "bpki_cancel", "bpki_serving_config", "bpki_serving_packing",
+            "bpki_ticket_times", "bpki_ticket_pack_size",
             "bpki_session_open", "bpki_session_close",
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
@@ -245,6 +248,10 @@ class Context:
     def serving_config(self, slots: int):
         _check(self.lib, self.lib.bpki_serving_config(self.h, slots))
 
+    def serving_packing(self, max_requests: int, max_chi: int = 32):
+        """Cross-request packing limits (max_requests = 1 turns packing off)."""
+        _check(self.lib, self.lib.bpki_serving_packing(self.h, max_requests, max_chi))
+
     def session(self, spec: ProblemSpec) -> "Session":
         return Session(self, spec)
 
@@ -340,6 +347,12 @@ class Ticket:
         _check(self.ctx.lib, self.ctx.lib.bpki_ticket_times(self.ctx.h, self.t,
                                                             _ptr(t, C.c_double)))
         return t
+
+    def pack_size(self) -> int:
+        """Problems in the pack that ran this ticket (1 = alone, 0 = not started)."""
+        n = C.c_int32()
+        _check(self.ctx.lib, self.ctx.lib.bpki_ticket_pack_size(self.ctx.h, self.t, C.byref(n)))
+        return int(n.value)
 
 
 class Session:

@@ -196,6 +196,7 @@ struct bpki_ctx {
   std::map<uint64_t, std::shared_ptr<Job>> jobs;
   std::deque<std::shared_ptr<Job>> queue;
   int n_slots = 8;
+  int pack_max = 16, pack_max_chi = 16;     // cross-request packing (see bpki_serving_packing)
   std::vector<std::unique_ptr<Backend>> slot_be;
   std::vector<std::thread> slot_threads;
   std::condition_variable cv, done_cv;
@@ -483,8 +484,57 @@ struct bpki_ctx::Job {
   bool done = false;
   int status = 0;
   size_t bytes = 0;
+  int pack_size = 0;
   double t_submit = 0, t_start = 0, t_done = 0;
 };
+
+// Cross-request packing.  Requests on the same lattice (sites, edges and colours) with the same
+// chi, precision, BP and truncation settings are solved together as one problem on the disjoint
+// union of their lattices: every launch of a gate layer or BP sweep then covers all of them.  The
+// members keep their own X angles, depths and Pauli strings; each member's messages are frozen
+// once its own BP residual is below the tolerance (Engine::bp_members), so every member follows
+// the schedule of a solve of its own, and its result is written as soon as its last step is done.
+static bool packable(const Problem &a, const Problem &b) {
+  return a.n_sites == b.n_sites && a.chi == b.chi && a.precision == b.precision &&
+         a.bp_tol == b.bp_tol && a.bp_max_iter == b.bp_max_iter && a.svd_cutoff == b.svd_cutoff &&
+         a.eig_cutoff == b.eig_cutoff && b.depth >= 1 && a.edges == b.edges &&
+         a.colour == b.colour;
+}
+
+static Problem pack_problem(const std::vector<const Problem *> &qs, std::vector<int> *pauli0) {
+  Problem u = *qs[0];
+  u.n_sites = 0;
+  u.depth = 0;
+  u.record_every_step = 1;
+  u.edges.clear();
+  u.colour.clear();
+  u.site_theta.clear();
+  u.member_site0.clear();
+  u.pauli_offsets.assign(1, 0);
+  u.pauli_sites.clear();
+  u.pauli_ops.clear();
+  pauli0->clear();
+  for (const Problem *q : qs) {
+    const int s0 = u.n_sites;
+    u.member_site0.push_back(s0);
+    for (int x : q->edges) u.edges.push_back(x + s0);
+    u.colour.insert(u.colour.end(), q->colour.begin(), q->colour.end());
+    u.site_theta.insert(u.site_theta.end(), q->n_sites, q->theta);
+    pauli0->push_back((int)u.pauli_offsets.size() - 1);
+    for (size_t k = 0; k + 1 < q->pauli_offsets.size(); ++k) {
+      for (int i = q->pauli_offsets[k]; i < q->pauli_offsets[k + 1]; ++i) {
+        u.pauli_sites.push_back(q->pauli_sites[i] + s0);
+        u.pauli_ops.push_back(q->pauli_ops[i]);
+      }
+      u.pauli_offsets.push_back((int)u.pauli_sites.size());
+    }
+    u.n_sites += q->n_sites;
+    u.depth = std::max(u.depth, q->depth);
+  }
+  u.member_site0.push_back(u.n_sites);
+  pauli0->push_back((int)u.pauli_offsets.size() - 1);
+  return u;
+}
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -503,10 +553,122 @@ static void serving_shutdown(bpki_ctx *c) {
   c->slot_be.clear();
 }
 
+static void finish_job(bpki_ctx *c, const std::shared_ptr<bpki_ctx::Job> &job, int status) {
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    job->status = status;
+    job->done = true;
+    job->t_done = now_s();
+  }
+  c->done_cv.notify_all();
+}
+
+// Runs a pack to the largest member depth; finishes every member (result or error).
+static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
+                     const std::vector<std::shared_ptr<bpki_ctx::Job>> &jobs,
+                     const std::vector<int> &pauli0) {
+  const int R = (int)jobs.size();
+  struct Acc {
+    std::vector<double> z, res, disc;
+    std::vector<int32_t> iters;
+    int warn = 0;
+    bool fin = false;
+  };
+  std::vector<Acc> acc(R);
+  std::vector<int> edge_member(U.edges.size() / 2);
+  for (int j = 0, e0 = 0; j < R; ++j) {
+    const Problem &q = jobs[j]->q;
+    const int rows = std::max(1, q.record_every_step ? q.depth : 1);
+    acc[j].z.assign((size_t)rows * q.n_sites, 1.0);
+    acc[j].iters.assign(q.depth, 0);
+    acc[j].res.assign(q.depth, 0.0);
+    acc[j].disc.assign(q.depth, 0.0);
+    const int ne = (int)q.edges.size() / 2;
+    for (int e = 0; e < ne; ++e) edge_member[e0 + e] = j;
+    e0 += ne;
+  }
+  std::vector<int> cols(U.colour.begin(), U.colour.end());
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  std::vector<int> sweeps(R);
+  std::vector<double> rr(R), zall(U.n_sites), dj(R);
+  auto fin = [&](int j, int status) {
+    acc[j].fin = true;
+    finish_job(c, jobs[j], status);
+  };
+  for (int t = 0; t < U.depth; ++t) {
+    int open = 0;
+    for (int j = 0; j < R; ++j) {
+      if (acc[j].fin) continue;
+      if (jobs[j]->cancel.load()) fin(j, -6);
+      else ++open;
+    }
+    if (!open) return;
+    eng.apply_rx();
+    std::fill(dj.begin(), dj.end(), 0.0);
+    for (int col : cols) {
+      eng.apply_layer(col);
+      for (auto &ed : eng.layer_discarded()) dj[edge_member[ed.first]] += ed.second;
+    }
+    eng.bp_members(U.bp_max_iter, sweeps.data(), rr.data());
+    bool need_z = false;
+    for (int j = 0; j < R; ++j) {
+      const Problem &q = jobs[j]->q;
+      if (!acc[j].fin && t < q.depth && (q.record_every_step || t == q.depth - 1)) need_z = true;
+    }
+    if (need_z) eng.observe_z(zall.data());
+    std::string msg;
+    if (int e = be->check(&msg)) {
+      for (int j = 0; j < R; ++j)
+        if (!acc[j].fin) fin(j, e);
+      return;
+    }
+    for (int j = 0; j < R; ++j) {
+      const Problem &q = jobs[j]->q;
+      if (acc[j].fin || t >= q.depth) continue;
+      Acc &a = acc[j];
+      a.iters[t] = sweeps[j];
+      a.res[t] = rr[j];
+      a.disc[t] = dj[j];
+      if (!(rr[j] < q.bp_tol)) a.warn = 1;
+      const int s0 = U.member_site0[j];
+      if (q.record_every_step || t == q.depth - 1) {
+        const int row = q.record_every_step ? t : 0;
+        std::copy(zall.begin() + s0, zall.begin() + s0 + q.n_sites,
+                  a.z.begin() + (size_t)row * q.n_sites);
+      }
+      if (t < q.depth - 1) continue;
+      std::vector<double> pv(pauli0[j + 1] - pauli0[j], 0.0);
+      if (!pv.empty()) eng.observe_pauli_range(pauli0[j], pauli0[j + 1], pv.data());
+      if (int e = be->check(&msg)) {
+        fin(j, e);
+        continue;
+      }
+      bool finite = true;
+      for (double x : a.z) finite = finite && std::isfinite(x);
+      if (!finite) {
+        fin(j, -5);
+        continue;
+      }
+      bpki_result *r = jobs[j]->r;
+      if (r->z) std::memcpy(r->z, a.z.data(), a.z.size() * sizeof(double));
+      if (r->pauli && !pv.empty()) std::memcpy(r->pauli, pv.data(), pv.size() * sizeof(double));
+      if (r->bp_iters) std::memcpy(r->bp_iters, a.iters.data(), a.iters.size() * sizeof(int32_t));
+      if (r->bp_residual) std::memcpy(r->bp_residual, a.res.data(), a.res.size() * sizeof(double));
+      if (r->discarded) std::memcpy(r->discarded, a.disc.data(), a.disc.size() * sizeof(double));
+      fin(j, a.warn);
+    }
+  }
+  for (int j = 0; j < R; ++j)
+    if (!acc[j].fin) fin(j, -5);    // not reached: every member ends at its own depth
+}
+
 static void slot_loop(bpki_ctx *c, int slot) {
   Backend *be = c->slot_be[slot].get();
   for (;;) {
     std::shared_ptr<bpki_ctx::Job> job;
+    std::vector<std::shared_ptr<bpki_ctx::Job>> pack;
+    size_t pack_bytes = 0;
     {
       std::unique_lock<std::mutex> lk(c->mu);
       c->cv.wait(lk, [&] {
@@ -527,13 +689,37 @@ static void slot_loop(bpki_ctx *c, int slot) {
         c->done_cv.notify_all();
         continue;
       }
-      c->used += job->bytes;
-      c->running += 1;
-      job->t_start = now_s();
+      pack.assign(1, job);
+      size_t bytes = job->bytes;
+      // pack only from a backlog (more queued requests than slots: otherwise the idle slots
+      // run them concurrently), and only companions that end no later than the head
+      if (c->pack_max > 1 && job->q.chi <= c->pack_max_chi && job->q.depth >= 1 &&
+          (int)c->queue.size() >= c->n_slots) {
+        for (auto it = c->queue.begin();
+             it != c->queue.end() && (int)pack.size() < c->pack_max;) {
+          const auto &h = *it;
+          if (!h->cancel && packable(job->q, h->q) && h->q.depth <= job->q.depth &&
+              (c->budget == 0 || c->used + bytes + h->bytes <= c->budget)) {
+            bytes += h->bytes;
+            pack.push_back(h);
+            it = c->queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      c->used += bytes;
+      c->running += (int)pack.size();
+      const double t0 = now_s();
+      for (auto &m : pack) {
+        m->t_start = t0;
+        m->pack_size = (int)pack.size();
+      }
+      pack_bytes = bytes;
     }
-    int status;
-    {
-      std::string msg;
+    std::string msg;
+    if (pack.size() == 1) {
+      int status;
       if (be->check(&msg)) {
         status = -5;
       } else {
@@ -541,16 +727,28 @@ static void slot_loop(bpki_ctx *c, int slot) {
         if (be->check(&msg)) status = -4;
         else status = run_solve(be, *eng, job->q, job->r, &job->cancel);
       }
+      finish_job(c, job, status);
+    } else {
+      std::vector<const Problem *> qs;
+      for (auto &m : pack) qs.push_back(&m->q);
+      std::vector<int> pauli0;
+      Problem U = pack_problem(qs, &pauli0);
+      if (be->check(&msg)) {
+        for (auto &m : pack) finish_job(c, m, -5);
+      } else {
+        std::unique_ptr<Engine> eng(new Engine(be, U));
+        if (be->check(&msg)) {
+          for (auto &m : pack) finish_job(c, m, -4);
+        } else {
+          run_pack(c, be, *eng, U, pack, pauli0);
+        }
+      }
     }
     {
       std::lock_guard<std::mutex> lk(c->mu);
-      c->used -= job->bytes;
-      c->running -= 1;
-      job->status = status;
-      job->done = true;
-      job->t_done = now_s();
+      c->used -= pack_bytes;
+      c->running -= (int)pack.size();
     }
-    c->done_cv.notify_all();
     c->cv.notify_all();
   }
 }
@@ -572,6 +770,16 @@ extern "C" int bpki_serving_config(bpki_ctx *c, int slots) {
   std::lock_guard<std::mutex> lk(c->mu);
   if (!c->slot_threads.empty()) return fail(-1, "serving already started");
   c->n_slots = slots;
+  return 0;
+}
+
+extern "C" int bpki_serving_packing(bpki_ctx *c, int max_requests, int max_chi) {
+  if (!c || max_requests < 1 || max_requests > 64 || max_chi < 1)
+    return fail(-1, "max_requests must be in 1..64 and max_chi >= 1");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->slot_threads.empty()) return fail(-1, "serving already started");
+  c->pack_max = max_requests;
+  c->pack_max_chi = max_chi;
   return 0;
 }
 
@@ -612,6 +820,15 @@ extern "C" int bpki_ticket_times(bpki_ctx *c, uint64_t t, double *times3) {
   times3[0] = it->second->t_submit;
   times3[1] = it->second->t_start;
   times3[2] = it->second->t_done;
+  return 0;
+}
+
+extern "C" int bpki_ticket_pack_size(bpki_ctx *c, uint64_t t, int32_t *size) {
+  if (!c || !size) return fail(-1, "NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->jobs.find(t);
+  if (it == c->jobs.end()) return fail(-7, "unknown ticket");
+  *size = it->second->pack_size;
   return 0;
 }
 

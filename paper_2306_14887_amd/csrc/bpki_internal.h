@@ -99,6 +99,13 @@ struct Backend {
   virtual void normalize_residual(int chi, double *const *Mnew, const double *const *Mold,
                                   double *res, int nprob) = 0;
   virtual void reduce_max(const double *x, int n, double *out) = 0;
+  // Packed solves: out[j] = max of res[idx[k]] over k in [off[j], off[j+1]), and
+  // act_next[j] = act[j] && !(out[j] < tol).
+  virtual void member_residual(const double *res, const int *off, const int *idx, int nmem,
+                               const int *act, int *act_next, double tol, double *out) = 0;
+  // M[m] <- Mn[m] (elems complex each) for every message m whose member is active.
+  virtual void commit_messages(double *M, const double *Mn, long elems, int nmsg,
+                               const int *msg_member, const int *act) = 0;
   // Throughput of a loop of independent 16x16x4 MFMAs (no memory traffic) on this stream, in
   // TFLOP/s: prec 0 = FP64, 1 = FP32; `blocks` workgroups of four waves, `iters` iterations.
   virtual double mfma_rate(int prec, int blocks, int iters) = 0;
@@ -126,6 +133,11 @@ struct Problem {
   std::vector<int> pauli_offsets, pauli_sites;
   std::vector<uint8_t> pauli_ops;
   int record_every_step = 1;
+  // Packed solves (several requests on the disjoint union of their lattices): the X angle of
+  // every site (empty: theta everywhere) and the first site of each member followed by n_sites
+  // (empty: a single member).  Members are contiguous site ranges with contiguous edge ranges.
+  std::vector<double> site_theta;
+  std::vector<int> member_site0;
 };
 
 // Host-side graph plan (degrees, neighbours, layers) and device workspace sizes.
@@ -144,6 +156,14 @@ class Engine {
   int bp(int max_iter, double *residual);         // returns sweeps
   void observe_z(double *z);                      // host out [n_sites]
   void observe_pauli(double *out);                // host out [n_pauli]
+  void observe_pauli_range(int k0, int k1, double *out);   // strings k0 .. k1-1
+  // Packed solves: sweeps until every member's residual is below bp_tol.  A member's messages
+  // are frozen after the sweep that brought its own residual below the tolerance, so each member
+  // follows its own BP schedule; per member: sweeps and final residual.
+  void bp_members(int max_iter, int *sweeps, double *residual);
+  int n_members() const;
+  // (edge, discarded weight) for every edge of the last apply_layer
+  const std::vector<std::pair<int, double>> &layer_discarded() const { return layer_disc_; }
   int n_colours() const;
   const Problem &problem() const { return prob_; }
 
@@ -157,6 +177,8 @@ class Engine {
   Problem prob_;
   Plan *plan_;
   int bp_prec_ = 0;
+  std::vector<std::pair<int, double>> layer_disc_;
+  void sweep_classes();
   // The gate updates stay FP64 in every mode: the Gram-based bond isolation amplifies rounding
   // by the condition number of the isolated tensor, which FP32 cannot absorb.
   int su_prec() const { return 0; }

@@ -151,6 +151,12 @@ struct Plan {
     int nmsg = 0, res_off = 0;
   };
   std::vector<BpClass> bp_classes;
+  // packed solves: member of every residual slot (CSR by member), member of every message,
+  // active flags (ping-pong) and per-member residuals
+  int nmem = 1;
+  std::vector<int> site_member;
+  int *mem_off = nullptr, *mem_idx = nullptr, *msg_member = nullptr, *act[2] = {nullptr, nullptr};
+  double *res_m = nullptr;
   // observables
   std::vector<GemmOp> obs_ops;
   size_t obs_Y = 0, obs_T = 0;
@@ -300,6 +306,12 @@ void Engine::build() {
   for (int v = 0; v < P.n; ++v) {
     std::sort(P.nb[v].begin(), P.nb[v].end());
     P.deg[v] = (int)P.nb[v].size();
+  }
+  P.site_member.assign(P.n, 0);
+  if (p.member_site0.size() > 2) {
+    P.nmem = (int)p.member_site0.size() - 1;
+    for (int j = 0; j < P.nmem; ++j)
+      for (int v = p.member_site0[j]; v < p.member_site0[j + 1]; ++v) P.site_member[v] = j;
   }
   // messages: 2e = edges[2e] -> edges[2e+1], 2e+1 reverse
   std::map<std::pair<int, int>, int> midx;
@@ -723,6 +735,7 @@ void Engine::build() {
       }
     }
     const int ncls = P.n ? *std::max_element(cls.begin(), cls.end()) + 1 : 0;
+    std::vector<int> res_src;             // source site of every residual slot
     Layout L3 = t_layout(3, chi), L2 = t_layout(2, chi), L1 = t_layout(1, chi);
     int res_off = 0;
     for (int c = 0; c < ncls; ++c) {
@@ -785,6 +798,7 @@ void Engine::build() {
         for (int i = 0; i < P.deg[v]; ++i) {
           nn.push_back(Mnp(P.out_msg[v][i]));
           no.push_back(Mp(P.out_msg[v][i]));
+          res_src.push_back(v);
         }
       }
       C.nmsg = (int)nn.size();
@@ -795,6 +809,27 @@ void Engine::build() {
         C.norm_old = P.arena.add(no);
       }
       P.bp_classes.push_back(C);
+    }
+    if (P.nmem > 1) {
+      std::vector<std::vector<int>> by(P.nmem);
+      for (size_t r = 0; r < res_src.size(); ++r) by[P.site_member[res_src[r]]].push_back((int)r);
+      std::vector<int> off(1, 0), idx;
+      for (auto &b : by) {
+        idx.insert(idx.end(), b.begin(), b.end());
+        off.push_back((int)idx.size());
+      }
+      std::vector<int> mm(2 * P.E, 0);
+      for (int v = 0; v < P.n; ++v)
+        for (int m : P.out_msg[v]) mm[m] = P.site_member[v];
+      P.mem_off = (int *)A(off.size() * 4);
+      P.mem_idx = (int *)A(std::max<size_t>(1, idx.size()) * 4);
+      P.msg_member = (int *)A(std::max<size_t>(1, mm.size()) * 4);
+      P.act[0] = (int *)A((size_t)P.nmem * 4);
+      P.act[1] = (int *)A((size_t)P.nmem * 4);
+      P.res_m = (double *)A((size_t)P.nmem * 8);
+      be_->h2d(P.mem_off, off.data(), off.size() * 4);
+      if (!idx.empty()) be_->h2d(P.mem_idx, idx.data(), idx.size() * 4);
+      if (!mm.empty()) be_->h2d(P.msg_member, mm.data(), mm.size() * 4);
     }
     // observables: Y = T x0 M0 x1 M1 x2 M2 (T-order), rho = sum Y conj(T)
     {
@@ -862,8 +897,20 @@ static void run(Backend *be, const PtrArena &ar, const GemmOp &op, int prec) {
 
 void Engine::apply_rx() {
   Plan &P = *plan_;
-  double c = std::cos(prob_.theta / 2), s = std::sin(prob_.theta / 2);
-  be_->rx(P.arena.at<double *const *>(P.rx_ptrs), P.rx_half, P.n, c, s);
+  if (prob_.site_theta.empty()) {
+    double c = std::cos(prob_.theta / 2), s = std::sin(prob_.theta / 2);
+    be_->rx(P.arena.at<double *const *>(P.rx_ptrs), P.rx_half, P.n, c, s);
+    return;
+  }
+  // one launch per run of sites with the same angle
+  for (int v0 = 0; v0 < P.n;) {
+    int v1 = v0 + 1;
+    const double th = prob_.site_theta[v0];
+    while (v1 < P.n && prob_.site_theta[v1] == th) ++v1;
+    be_->rx(P.arena.at<double *const *>(P.rx_ptrs) + v0, P.rx_half + v0, v1 - v0,
+            std::cos(th / 2), std::sin(th / 2));
+    v0 = v1;
+  }
 }
 
 double Engine::apply_layer(int colour) {
@@ -925,14 +972,16 @@ double Engine::apply_layer(int colour) {
   be_->d2h(disc.data(), P.disc, ne * 8);
   be_->d2h(k.data(), P.kbuf, ne * 4);
   double dsum = 0;
+  layer_disc_.resize(ne);
   for (int i = 0; i < ne; ++i) {
     dsum += disc[i];
     P.bond_h[LP.edges[i].e] = k[i];
+    layer_disc_[i] = {LP.edges[i].e, disc[i]};
   }
   return dsum;
 }
 
-double Engine::bp_sweep() {
+void Engine::sweep_classes() {
   Plan &P = *plan_;
   for (auto &C : P.bp_classes) {
     for (auto &op : C.ops) run(be_, P.arena, op, bp_prec_);
@@ -941,6 +990,11 @@ double Engine::bp_sweep() {
                               P.arena.at<const double *const *>(C.norm_old), P.res + C.res_off,
                               C.nmsg);
   }
+}
+
+double Engine::bp_sweep() {
+  Plan &P = *plan_;
+  sweep_classes();
   be_->reduce_max(P.res, 2 * P.E, P.resmax);
   be_->d2d(P.M, P.Mn, message_elems() * 16);
   double r = 0;
@@ -963,6 +1017,51 @@ int Engine::bp(int max_iter, double *residual) {
   bp_prec_ = prob_.precision ? 1 : 0;
   if (residual) *residual = r;
   return it;
+}
+
+int Engine::n_members() const { return plan_->nmem; }
+
+void Engine::bp_members(int max_iter, int *sweeps, double *residual) {
+  Plan &P = *plan_;
+  const int R = P.nmem;
+  std::vector<int> act(R, 1);
+  std::vector<double> r(R, INFINITY);
+  for (int j = 0; j < R; ++j) {
+    sweeps[j] = 0;
+    residual[j] = INFINITY;
+  }
+  be_->h2d(P.act[0], act.data(), (size_t)R * 4);
+  int cur = 0;
+  bp_prec_ = prob_.precision ? 1 : 0;
+  for (int it = 1; it <= max_iter; ++it) {
+    sweep_classes();
+    be_->member_residual(P.res, P.mem_off, P.mem_idx, R, P.act[cur], P.act[cur ^ 1],
+                         prob_.bp_tol, P.res_m);
+    be_->commit_messages(P.M, P.Mn, (long)P.chi * P.chi, 2 * P.E, P.msg_member, P.act[cur]);
+    be_->d2h(r.data(), P.res_m, (size_t)R * 8);
+    cur ^= 1;
+    bool any = false;
+    double rmax = 0.0;
+    for (int j = 0; j < R; ++j) {
+      if (!act[j]) continue;
+      sweeps[j] = it;
+      residual[j] = r[j];
+      if (r[j] < prob_.bp_tol) act[j] = 0;
+      else any = true;
+      rmax = std::max(rmax, r[j]);
+    }
+    if (!any) break;
+    if (bp_prec_ == 1 && rmax < kFp32BpFloor) bp_prec_ = 0;
+  }
+  bp_prec_ = prob_.precision ? 1 : 0;
+}
+
+void Engine::observe_pauli_range(int k0, int k1, double *out) {
+  for (int k = k0; k < k1; ++k) {
+    double a = pauli_value(k, true);
+    double b = pauli_value(k, false);
+    out[k - k0] = a / b;
+  }
 }
 
 void Engine::observe_z(double *z) {

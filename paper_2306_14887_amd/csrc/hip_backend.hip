@@ -1669,6 +1669,44 @@ __global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n,
   if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// Packed solves: one workgroup per member takes the max (NaN-propagating) of its residual slots
+// and clears the member's active flag for the next sweep once the max is below tol.
+__global__ __launch_bounds__(256) void member_residual_kernel(const double *res, const int *off,
+                                                              const int *idx, const int *act,
+                                                              int *act_next, double tol,
+                                                              double *out) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double m = 0;
+  for (int k = off[j] + threadIdx.x; k < off[j + 1]; k += blockDim.x) {
+    double v = res[idx[k]];
+    m = (v > m || v != v) ? v : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double a = sh[threadIdx.x], b = sh[threadIdx.x + s];
+      sh[threadIdx.x] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[j] = sh[0];
+    act_next[j] = act[j] && !(sh[0] < tol);
+  }
+}
+
+// M[m] <- Mn[m] for the messages of active members (elems complex per message).
+__global__ __launch_bounds__(256) void commit_messages_kernel(double2 *M, const double2 *Mn,
+                                                              long elems, long total,
+                                                              const int *msg_member,
+                                                              const int *act) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+       i += (long)gridDim.x * blockDim.x)
+    if (act[msg_member[i / elems]]) M[i] = Mn[i];
+}
+
 // rho[p][s][s'] = sum_i Y_p[s][i] conj(T_p[s'][i]): RHO_CHUNKS workgroups per problem each sum a
 // strided part into partial[p][chunk][8]; rho_sum_kernel adds the chunks in a fixed order.
 constexpr int RHO_CHUNKS = 64;
@@ -2076,6 +2114,24 @@ class HipBackend : public Backend {
     stale_check("reduce_max_kernel");
     hipLaunchKernelGGL(reduce_max_kernel, dim3(1), dim3(256), 0, s_, x, n, out);
     launch_check("reduce_max_kernel");
+  }
+  void member_residual(const double *res, const int *off, const int *idx, int nmem,
+                       const int *act, int *act_next, double tol, double *out) override {
+    if (nmem <= 0) return;
+    stale_check("member_residual_kernel");
+    hipLaunchKernelGGL(member_residual_kernel, dim3(nmem), dim3(256), 0, s_, res, off, idx, act,
+                       act_next, tol, out);
+    launch_check("member_residual_kernel");
+  }
+  void commit_messages(double *M, const double *Mn, long elems, int nmsg, const int *msg_member,
+                       const int *act) override {
+    const long total = elems * nmsg;
+    if (total <= 0) return;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    stale_check("commit_messages_kernel");
+    hipLaunchKernelGGL(commit_messages_kernel, dim3(blocks), dim3(256), 0, s_, (double2 *)M,
+                       (const double2 *)Mn, elems, total, msg_member, act);
+    launch_check("commit_messages_kernel");
   }
   void rho_dot(const double *const *Y, const double *const *T, const int64_t *len, double *rho,
                int nprob) override {

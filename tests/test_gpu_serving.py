@@ -1,5 +1,6 @@
 """Serving (continuous batching) on the GPU: results are the same alone and in the mix,
-admission respects the memory budget, cancellation and rejection work."""
+packed requests match their solves alone, admission respects the memory budget, cancellation
+and rejection work."""
 import time
 
 import numpy as np
@@ -28,6 +29,7 @@ def test_same_alone_and_in_the_mix():
     specs = _specs(12)
     with B.Context() as ctx:
         ctx.serving_config(4)
+        ctx.serving_packing(1)
         tickets = [ctx.submit(s) for s in specs]
         mixed = [t.wait() for t in tickets]
     with B.Context() as ctx:
@@ -35,6 +37,62 @@ def test_same_alone_and_in_the_mix():
             alone = ctx.solve(s)
             assert m["status"] == alone["status"]
             assert np.abs(m["z"] - alone["z"]).max() <= 1e-12
+
+
+def _pack_specs():
+    """Eight requests that share a lattice, chi, precision and tolerances (so they pack): their
+    own angles, depths, Pauli strings and recording modes."""
+    from paper_2306_14887_amd import bpki as B
+    lat = L.heavy_hex(3, 9)
+    rng = np.random.default_rng(7)
+    out = []
+    for i in range(8):
+        ps = L.random_pauli_strings(lat, 3, seed=200 + i, wmin=2, wmax=6)
+        out.append(B.spec_from_lattice(lat, float(rng.uniform(0.0, 1.5)), int(rng.integers(1, 9)),
+                                       8, pauli=[(p.sites, p.ops) for p in ps],
+                                       record_every_step=int(i % 3 != 0)))
+    return out
+
+
+def test_packed_requests_match_alone():
+    """Queued requests on one lattice are packed into one solve on the union of their lattices;
+    each member follows its own BP stopping point, so it matches its solve alone (to rounding)
+    and, through it, the oracle."""
+    from paper_2306_14887_amd import bpki as B
+    from oracle import bp_tns as O
+    print("[serving] packed requests vs alone", flush=True)
+    specs = _pack_specs()
+    with B.Context() as ctx:
+        ctx.serving_config(1)
+        ctx.serving_packing(16, 32)
+        # a request on another lattice occupies the slot while the eight queue up; the deepest
+        # request goes first so that it heads the pack (companions end no later than the head)
+        blocker = ctx.submit(B.spec_from_lattice(L.heavy_hex(5, 11), 0.7, 6, 16))
+        order = sorted(range(len(specs)), key=lambda i: -specs[i].depth)
+        tickets = [None] * len(specs)
+        for i in order:
+            tickets[i] = ctx.submit(specs[i])
+        blocker.wait()
+        while not all(t.poll() for t in tickets):
+            time.sleep(0.002)
+        packs = [t.pack_size() for t in tickets]
+        outs = [t.wait() for t in tickets]
+    assert min(packs) == len(specs)
+    with B.Context() as ctx:
+        for s, o in zip(specs, outs):
+            alone = ctx.solve(s)
+            assert o["status"] == alone["status"] == 0
+            assert np.abs(o["z"] - alone["z"]).max() < 1e-10
+            assert np.abs(o["pauli"] - alone["pauli"]).max() < 1e-10
+            d = s.depth
+            assert np.abs(o["bp_iters"][:d] - alone["bp_iters"][:d]).max() <= 1
+            assert np.abs(o["discarded"][:d] - alone["discarded"][:d]).max() < 1e-10
+    lat = L.heavy_hex(3, 9)
+    s, o = specs[1], outs[1]
+    ref = O.solve(lat.n_sites, lat.edges, lat.colour, s.theta, s.depth, O.Options(chi=8),
+                  pauli=s.pauli)
+    assert np.abs(o["z"] - ref.z).max() < 1e-8
+    assert np.abs(o["pauli"] - ref.pauli).max() < 1e-8
 
 
 def test_budget_admission_and_overlap():
