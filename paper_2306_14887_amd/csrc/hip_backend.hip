@@ -1772,6 +1772,16 @@ class HipBackend : public Backend {
       HIPCHK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
       own_ = true;
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        cus > 0)
+      resident_ = 2 * cus;
+    else
+      (void)hipGetLastError();
+    if (hipHostMalloc(&pin_, kPinBytes, hipHostMallocDefault) != hipSuccess) {
+      pin_ = nullptr;            // small reads then take the staged path
+      (void)hipGetLastError();
+    }
     HIPCHK(hipFuncSetAttribute((const void *)eigh_jacobi_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
     HIPCHK(hipFuncSetAttribute((const void *)gram_chol_lds_kernel,
@@ -1786,6 +1796,7 @@ class HipBackend : public Backend {
     if (cws_) HIPCHK(hipFree(cws_));
     if (lws_) HIPCHK(hipFree(lws_));
     if (rws_) HIPCHK(hipFree(rws_));
+    if (pin_) HIPCHK(hipHostFree(pin_));
     if (own_) hipStreamDestroy(s_);
   }
   void *alloc(size_t bytes) override {
@@ -1808,7 +1819,22 @@ class HipBackend : public Backend {
     if (b) HIPCHK(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s_));
     HIPCHK(hipStreamSynchronize(s_));
   }
+  // Small reads (residuals, bond dimensions, site densities) go through a pinned buffer and a
+  // polling wait on the stream: the host resumes as soon as the stream drains, which shortens
+  // the bubble between BP sweeps.
   void d2h(void *h, const void *d, size_t b) override {
+    if (b && b <= kPinBytes && pin_) {
+      HIPCHK(hipMemcpyAsync(pin_, d, b, hipMemcpyDeviceToHost, s_));
+      hipError_t e;
+      while ((e = hipStreamQuery(s_)) == hipErrorNotReady) {
+      }
+      // a not-ready answer of the query may linger as the last error: clear it
+      const hipError_t le = hipGetLastError();
+      if (e != hipSuccess) HIPCHK(e);
+      if (le != hipSuccess && le != hipErrorNotReady) HIPCHK(le);
+      std::memcpy(h, pin_, b);
+      return;
+    }
     if (b) HIPCHK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s_));
     HIPCHK(hipStreamSynchronize(s_));
   }
@@ -1862,11 +1888,13 @@ class HipBackend : public Backend {
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s_));
     }
-    // split K when the output alone cannot fill the machine
+    // split K when the output alone cannot fill the machine: as many chunks as keep the grid
+    // within one round of resident workgroups (two per CU; a partial second round measured
+    // slower than fewer, longer chunks)
     int blocks = tiles * d.batch * nprob;
     int ksplit = 1, kchunk = d.K;
-    if (blocks < 1024 && d.K >= 512) {
-      int want = std::min((1024 + blocks - 1) / blocks, d.K / 256);
+    if (blocks < resident_ && d.K >= 512) {
+      int want = std::min(resident_ / blocks, d.K / 256);
       if (want > 1) {
         kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
         ksplit = (d.K + kchunk - 1) / kchunk;
@@ -2176,6 +2204,9 @@ class HipBackend : public Backend {
   size_t lws_bytes_ = 0;
   void *rws_ = nullptr;
   size_t rws_bytes_ = 0;
+  static constexpr size_t kPinBytes = 16384;
+  int resident_ = 512;             // gemm_kernel workgroups resident at once (2 per CU)
+  void *pin_ = nullptr;
   void *cws_ = nullptr;
   size_t cws_bytes_ = 0;
   void *skws_ = nullptr;
