@@ -1311,6 +1311,7 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
   __shared__ int perm[128];
   __shared__ double dg[128];
   __shared__ double2 lk[128];
+  __shared__ double2 lrow_s[2 * 128];
   __shared__ int piv_s, rank_s;
   __shared__ double gmax_s;
   const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -1400,10 +1401,17 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
   }
   const int r = rank_s;
   __syncthreads();
-  // X = L1^{-1} (L1[i][m] = L[perm[i]][m], i, m < r), rows in turn, X packed in LDS
+  // X = L1^{-1} (L1[i][m] = L[perm[i]][m], i, m < r), rows in turn, X packed in LDS.  Row i of
+  // L1 is staged in LDS (double buffered: row i+1 is fetched while row i is solved).
   double2 *X = P;
+  double2(*lrow)[128] = reinterpret_cast<double2(*)[128]>(lrow_s);
+  if (r > 0 && tid == 0) lrow[0][0] = L[(size_t)perm[0] * n];
+  __syncthreads();
   for (int i = 0; i < r; ++i) {
-    const double2 *Li = L + (size_t)perm[i] * n;
+    const double2 *Li = lrow[i & 1];
+    const bool fetch = i + 1 < r && tid <= i + 1;
+    double2 nxt = make_double2(0.0, 0.0);
+    if (fetch) nxt = L[(size_t)perm[i + 1] * n + tid];
     const double inv = 1.0 / Li[i].x;
     const int q = tid & 7;
     for (int j = tid >> 3; j <= i; j += nt >> 3) {
@@ -1419,6 +1427,7 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
       }
       if (q == 0) X[pk_idx(i, j)] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
     }
+    if (fetch) lrow[(i + 1) & 1][tid] = nxt;
     __syncthreads();
   }
   double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
@@ -1638,6 +1647,7 @@ __global__ __launch_bounds__(256) void normalize_residual_kernel(int chi, double
   double den = trr * trr + tri * tri;
   double ir = trr / den, ii = -tri / den;   // 1/tr
   double acc = 0;
+#pragma unroll 8
   for (int idx = threadIdx.x; idx < chi * chi; idx += blockDim.x) {
     double2 v = m[idx];
     double2 w = make_double2(v.x * ir - v.y * ii, v.x * ii + v.y * ir);
