@@ -48,13 +48,17 @@ GEMM_SOURCE = os.path.join(ROOT, "paper_2306_14887_amd", "csrc", "hip_backend.hi
 
 def gemm_traffic():
     """HBM bytes per GEMM launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when
-    the GEMM kernel source has changed since those counters were taken (its hash is recorded)."""
+    the GEMM kernel or its launch code has changed since those counters were taken (their hash is
+    recorded)."""
     import hashlib
     try:
         src = open(GEMM_SOURCE).read()
+        # the kernel and its launch configuration (tiling, split-K choice)
         a = src.index("constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;")
         b = src.index("// Twelve independent MFMA accumulation chains per wave")
-        h = hashlib.sha256(src[a:b].encode()).hexdigest()
+        c = src.index("  void gemm(const GemmDesc &d, const double *const *A")
+        e = src.index("  void *splitk_ws(size_t need) {")
+        h = hashlib.sha256((src[a:b] + src[c:e]).encode()).hexdigest()
         rec = {}
         for line in open(TRAFFIC_PROFILE):
             if ":" in line:
