@@ -249,6 +249,128 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
       }
 }
 
+// Streaming complex GEMM for K <= 64 and N <= 64 (single-stride K and N): C = A B with the whole
+// B (K x N) resident in LDS and the rows of A streamed through registers.  The leg contractions
+// of the site tensors (K = N = chi) have this shape: M = chi^2 rows per (site, s), so the tiled
+// kernel's short K loop (64 / 16 steps per tile) would leave the loads of a tile exposed.  Each
+// wave owns strips of 16 rows: the A fragments of a strip (16 rows x 64 k) are loaded straight into
+// the MFMA operand layout in two halves of K, the next strip's half being in flight while the other
+// half is multiplied, and the 16 x 64 output strip goes from the accumulators to C.  3M complex
+// products as in gemm_kernel.  TR: the MFMA computes the transposed strip (B^T A^T), so that a
+// lane's outputs share one row of C and the stores run along M (used when M is C's unit-stride
+// index).  grid: x = workgroups per (batch, problem), y = batch, z = problem.
+constexpr int SK_MAX = 64;
+template <typename T, bool TR>
+__global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const double *const *Ap,
+                                                             const double *const *Bp,
+                                                             double *const *Cp) {
+  typedef MfmaTraits<T> MT;
+  typedef typename MT::acc_t acc_t;
+  __shared__ T Bs[2][SK_MAX][SK_MAX + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bat = blockIdx.y, prob = blockIdx.z;
+  const double2 *A = reinterpret_cast<const double2 *>(Ap[prob]) + (long)bat * d.a_b;
+  const double2 *B = reinterpret_cast<const double2 *>(Bp[prob]) + (long)bat * d.b_b;
+  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  const T sa = d.conjA ? T(-1) : T(1), sb = d.conjB ? T(-1) : T(1);
+  // B into LDS, zero outside K x N
+  for (int idx = tid; idx < SK_MAX * SK_MAX; idx += 256) {
+    const int k = idx / SK_MAX, n = idx % SK_MAX;
+    double2 v = make_double2(0.0, 0.0);
+    if (k < d.K && n < d.N) v = B[(long)k * d.b_ki + (long)n * d.b_ni];
+    Bs[0][k][n] = T(v.x);
+    Bs[1][k][n] = sb * T(v.y);
+  }
+  __syncthreads();
+  const int ksteps = (d.K + 3) >> 2;            // 1 .. 16
+  const int ntiles = (d.N + 15) >> 4;           // 1 .. 4
+  const int strips = (d.M + 15) >> 4;
+  const int stride = gridDim.x * 4;
+  const int r16 = lane & 15, kq = lane >> 4;
+  // A fragment of k-step j for this lane: row (strip * 16 + r16), k = 4 j + kq
+  auto row_off = [&](int s) -> long {
+    const int m = s * 16 + r16;
+    return m < d.M ? cidx(m, d.Mi, d.a_mo, d.a_mi) : -1;
+  };
+  auto load_half = [&](long ro, int h, double2 (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 4 * (8 * h + q) + kq;
+      v[q] = (ro >= 0 && k < d.K) ? A[ro + (long)k * d.a_ki] : make_double2(0.0, 0.0);
+    }
+  };
+  acc_t acc[4][3];
+  auto mma_half = [&](int h, const double2 (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = 8 * h + q;
+      if (j >= ksteps) break;
+      const int k = 4 * j + kq;
+      const T ar = T(v[q].x), ai = sa * T(v[q].y), as = ar + ai;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= ntiles) break;
+        const T br = Bs[0][k][16 * t + r16], bi = Bs[1][k][16 * t + r16], bs = br + bi;
+        if constexpr (TR) {
+          acc[t][0] = MT::mma(br, ar, acc[t][0]);
+          acc[t][1] = MT::mma(bi, ai, acc[t][1]);
+          acc[t][2] = MT::mma(bs, as, acc[t][2]);
+        } else {
+          acc[t][0] = MT::mma(ar, br, acc[t][0]);
+          acc[t][1] = MT::mma(ai, bi, acc[t][1]);
+          acc[t][2] = MT::mma(as, bs, acc[t][2]);
+        }
+      }
+    }
+  };
+  int s = blockIdx.x * 4 + wave;
+  double2 lo[8], hi[8];
+  long ro = s < strips ? row_off(s) : -1;
+  if (s < strips) {
+    load_half(ro, 0, lo);
+    load_half(ro, 1, hi);
+  }
+  for (; s < strips; s += stride) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[t][c] = (acc_t){T(0), T(0), T(0), T(0)};
+    const int sn = s + stride;
+    const long ron = sn < strips ? row_off(sn) : -1;
+    mma_half(0, lo);
+    if (sn < strips) load_half(ron, 0, lo);     // the next strip's first half is in flight ...
+    mma_half(1, hi);                              // ... while this strip's second half is used
+    if (sn < strips) load_half(ron, 1, hi);
+    // output strip: lane holds rows MT::row(lane, r) and column 16 t + r16 of each n-tile
+    // (TR: row s * 16 + r16 and columns 16 t + MT::row(lane, r))
+    const int mt = s * 16 + r16;
+    const long cot = (TR && mt < d.M) ? cidx(mt, d.Mi, d.c_mo, d.c_mi) : 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = TR ? mt : s * 16 + MT::row(lane, r);
+      if (m >= d.M) continue;
+      const long co = TR ? cot : cidx(m, d.Mi, d.c_mo, d.c_mi);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int n = 16 * t + (TR ? MT::row(lane, r) : r16);
+        if (t >= ntiles || n >= d.N) continue;
+        const double cr = (double)acc[t][0][r] - (double)acc[t][1][r];
+        const double ci = (double)acc[t][2][r] - (double)acc[t][0][r] - (double)acc[t][1][r];
+        double vr = d.alpha_re * cr - d.alpha_im * ci;
+        double vi = d.alpha_re * ci + d.alpha_im * cr;
+        const long off = co + (long)n * d.c_ni;
+        if (d.beta) {
+          const double2 o = C[off];
+          vr += o.x;
+          vi += o.y;
+        }
+        C[off] = make_double2(vr, vi);
+      }
+    }
+    ro = ron;
+  }
+}
+
 // Twelve independent MFMA accumulation chains per wave, no memory traffic: the achievable MFMA
 // rate that bounds gemm_kernel.  The final comparison keeps the chains live.
 template <typename T>
@@ -1897,6 +2019,28 @@ class HipBackend : public Backend {
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s_));
+    }
+    // K and N within 64 (one stride each): B resident in LDS, rows of A streamed
+    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 64) {
+      const int strips = (d.M + 15) / 16;
+      const int per = std::max(1, resident_ / std::max(1, d.batch * nprob));
+      dim3 g(std::max(1, std::min(per, (strips + 3) / 4)), d.batch, nprob);
+      const bool tr = d.c_mi == 1 && d.c_ni != 1;     // C is unit-stride along M
+      stale_check("gemm_stream_kernel");
+      if (d.prec == 1) {
+        if (tr) hipLaunchKernelGGL((gemm_stream_kernel<float, true>), g, dim3(256), 0, s_, d, A, B, C);
+        else hipLaunchKernelGGL((gemm_stream_kernel<float, false>), g, dim3(256), 0, s_, d, A, B, C);
+      } else {
+        if (tr) hipLaunchKernelGGL((gemm_stream_kernel<double, true>), g, dim3(256), 0, s_, d, A, B, C);
+        else hipLaunchKernelGGL((gemm_stream_kernel<double, false>), g, dim3(256), 0, s_, d, A, B, C);
+      }
+      launch_check("gemm_stream_kernel");
+      if (rec) {
+        HIPCHK(hipEventRecord(e1, s_));
+        prof_ev_.push_back({e0, e1});
+        prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
+      }
+      return;
     }
     // split K when the output alone cannot fill the machine: as many chunks as keep the grid
     // within one round of resident workgroups (two per CU; a partial second round measured

@@ -1,6 +1,7 @@
 """Device primitives against independent host computations (numpy): the complex FP64 MFMA
-GEMM with composite strides, conjugation, batches and grouped problems, and the batched FP64
-Hermitian eigensolver (Jacobi, and Householder + divide and conquer for 64 < n <= 128)."""
+GEMMs (tiled with composite strides and split K; streaming for K, N <= 64) with conjugation,
+batches and grouped problems, the batched FP64 Hermitian eigensolver (Jacobi below n = 32,
+Householder + divide and conquer up to n = 256) and the pivoted Cholesky factor."""
 import zlib
 
 import numpy as np
@@ -63,6 +64,23 @@ CASES = [
                               alpha_re=-1.5, alpha_im=0.25), 2),
     ("splitk_odd_inner", dict(M=40, N=24, K=700, Ki=7, a_mi=1, a_ko=40 * 7, a_ki=40,
                               b_ko=7, b_ki=1, b_ni=700, c_mi=24, c_ni=1, conjB=1), 1),
+    # K, N <= 64 with one stride each and M >= 64: the streaming kernel (B resident in LDS)
+    # middle leg of a degree-3 tensor [s][a][b][c] at chi = 22 (K, N not multiples of 16 or 4)
+    ("stream_leg_mid", dict(M=22 * 22, Mi=22, N=22, K=22, a_mo=22 * 22, a_mi=1, a_ki=22,
+                            b_ki=22, b_ni=1, c_mo=22 * 22, c_mi=1, c_ni=22,
+                            batch=2, a_b=22 ** 3, b_b=0, c_b=22 ** 3), 3),
+    # last leg at chi = 64 (K unit-stride), accumulate with a complex alpha
+    ("stream_leg_last_beta", dict(M=64 * 64, Mi=64, N=64, K=64, a_mo=64 * 64, a_mi=64, a_ki=1,
+                                  b_ki=64, b_ni=1, c_mo=64 * 64, c_mi=64, c_ni=1,
+                                  batch=2, a_b=64 ** 3, b_b=0, c_b=64 ** 3, beta=1,
+                                  alpha_re=0.75, alpha_im=-0.5), 2),
+    # ragged M (not a multiple of the 16-row strip), conjugated operands, N < K
+    ("stream_ragged_conj", dict(M=1000, N=37, K=61, a_mi=61, a_ki=1, b_ki=1, b_ni=61,
+                                c_mi=37, c_ni=1, conjA=1, conjB=1), 2),
+    # C unit-stride along M (the transposed-strip variant), ragged M, accumulate
+    ("stream_mfast_out", dict(M=1000, N=50, K=64, a_mi=1, a_ki=1000, b_ki=50, b_ni=1,
+                              c_mi=1, c_ni=1000, conjB=1, beta=1, alpha_re=-0.5,
+                              alpha_im=1.25), 2),
 ]
 
 
