@@ -8,8 +8,10 @@ The first --warmup steps (default 6: bonds saturate at chi = 64 after 6 steps) a
 next --steps steps are timed, so the default run is steps 7..20 of the 20-step circuit.
 
 The JSON line also carries:
-  roofline     : the complex GEMM kernel (every contraction of the step runs in it), algorithmic
-                 flops 8*M*N*K per launch over its HIP-event-timed launch durations, against the
+  roofline     : the complex GEMM kernels (every contraction of the step runs in them: the tiled
+                 gemm_kernel, and gemm_stream_kernel for the leg contractions with K, N <= 64),
+                 algorithmic flops 8*M*N*K per launch over the HIP-event-timed launch durations
+                 (every 7th launch of the timed window), against the
                  MI355X FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the
                  committed rocprofv3 counter summary (null once the kernel source has changed);
                  achievable = measured roofs on this GPU (MFMA chains without memory traffic, a
@@ -426,7 +428,7 @@ def main() -> int:
             "mean_z_last_step": float(np.mean(z)),
         },
         "roofline": {
-            "bound": "mfma", "kernel": "gemm_kernel<double>",
+            "bound": "mfma", "kernel": "gemm_kernel<double> + gemm_stream_kernel<double>",
             "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
             "launches": prof["launches"], "launches_in_window": prof["all_launches"],

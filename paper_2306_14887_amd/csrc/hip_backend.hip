@@ -2020,8 +2020,9 @@ class HipBackend : public Backend {
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s_));
     }
-    // K and N within 64 (one stride each): B resident in LDS, rows of A streamed
-    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 64) {
+    // K and N within 64 (one stride each) and enough rows to amortise loading B (at least 16
+    // strips): B resident in LDS, rows of A streamed
+    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 256) {
       const int strips = (d.M + 15) / 16;
       const int per = std::max(1, resident_ / std::max(1, d.batch * nprob));
       dim3 g(std::max(1, std::min(per, (strips + 3) / 4)), d.batch, nprob);

@@ -64,7 +64,7 @@ CASES = [
                               alpha_re=-1.5, alpha_im=0.25), 2),
     ("splitk_odd_inner", dict(M=40, N=24, K=700, Ki=7, a_mi=1, a_ko=40 * 7, a_ki=40,
                               b_ko=7, b_ki=1, b_ni=700, c_mi=24, c_ni=1, conjB=1), 1),
-    # K, N <= 64 with one stride each and M >= 64: the streaming kernel (B resident in LDS)
+    # K, N <= 64 with one stride each and M >= 256: the streaming kernel (B resident in LDS)
     # middle leg of a degree-3 tensor [s][a][b][c] at chi = 22 (K, N not multiples of 16 or 4)
     ("stream_leg_mid", dict(M=22 * 22, Mi=22, N=22, K=22, a_mo=22 * 22, a_mi=1, a_ki=22,
                             b_ki=22, b_ni=1, c_mo=22 * 22, c_mi=1, c_ni=22,
