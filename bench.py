@@ -20,6 +20,8 @@ The JSON line also carries:
                  algorithmic real flops).
   mixed        : the same window in mixed precision, with max / median |<Z>| difference to FP64.
   chi128       : the same workload at chi = 128, steps 8..10 (FP64).
+  weight10     : the paper's weight-10 observable after 5 steps at the eight theta_h, measured by
+                 the extended time evolution (5 steps, then 5 steps of U(pi/2)^dagger, <Z_13>).
   theta_batch  : the eight theta_h values of the workload (20 steps each) solved together, one
                  serving slot each: aggregate Floquet steps/s.
   serving      : the seeded request stream (see serving_bench).
@@ -276,6 +278,30 @@ def achievable_peaks(ctx) -> dict:
     return out
 
 
+def weight10(lat, chi: int) -> dict:
+    """The paper's weight-10 observable X13,29,31 Y9,30 Z8,12,17,28,32 after 5 steps, by the
+    extended time evolution: it equals U^5(pi/2) Z_13 U^5(pi/2)^dagger (with phase +1), so it is
+    <Z_13> after 5 steps at theta_h and 5 steps of U(pi/2)^dagger.  One 10-step solve per seeded
+    theta_h (FP64, chi as given)."""
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    vals, secs = [], []
+    with bpki.Context(0) as ctx:
+        for th in L.theta_draw():
+            t0 = time.perf_counter()
+            r = ctx.solve(bpki.spec_from_lattice(lat, th, 5, chi, clifford_steps=5,
+                                                 record_every_step=False))
+            secs.append(time.perf_counter() - t0)
+            vals.append(float(r["z"][-1][13]))
+    return {"observable": "X13,29,31 Y9,30 Z8,12,17,28,32 after 5 steps", "chi": chi,
+            "steps": "5 + 5 (extended time evolution)",
+            "theta_h": [float(t) for t in L.theta_draw()], "value": vals,
+            "seconds_per_solve_mean": float(np.mean(secs))}
+
+
 def theta_batch(lat, chi: int, depth: int) -> dict:
     """The eight theta_h values of the workload solved together (one serving slot each): the
     aggregate Floquet steps/s of the batch (8 * depth / makespan)."""
@@ -347,6 +373,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision window")
     ap.add_argument("--chi128", type=int, default=1,
                     help="1: also time steps 8..10 of the workload at chi = 128")
+    ap.add_argument("--weight10", type=int, default=1,
+                    help="1: also the weight-10 observable at the 8 theta_h (extended evolution)")
     ap.add_argument("--theta-batch", type=int, default=1,
                     help="1: also solve the eight theta_h values together (aggregate steps/s)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -452,6 +480,9 @@ def main() -> int:
     if args.chi128:
         out["chi128"] = chi128_window(lat, theta)
         print("chi=128 window done", file=sys.stderr, flush=True)
+    if args.weight10:
+        out["weight10"] = weight10(lat, chi)
+        print("weight-10 observable done", file=sys.stderr, flush=True)
     if args.theta_batch:
         out["theta_batch"] = theta_batch(lat, chi, args.warmup + args.steps)
         print("theta batch done", file=sys.stderr, flush=True)

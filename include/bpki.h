@@ -75,16 +75,23 @@ typedef struct {
   const int32_t *pauli_offsets;/* [n_pauli+1] CSR offsets into pauli_sites / pauli_ops         */
   const int32_t *pauli_sites;  /* [pauli_offsets[n_pauli]]                                     */
   const uint8_t *pauli_ops;    /* [pauli_offsets[n_pauli]]  1=X 2=Y 3=Z                        */
-  int32_t record_every_step;   /* 1: z holds steps 1..depth; 0: final step only                */
+  int32_t record_every_step;   /* 1: z holds steps 1..depth (+ clifford_steps); 0: final only   */
+  int32_t clifford_steps;      /* n' >= 0 steps of U(pi/2)^dagger after the depth steps (the
+                                  paper's extended time evolution, "Measuring expectation values":
+                                  <Z_i> after them equals the expectation of the Pauli string
+                                  U^n'(pi/2) Z_i U^n'(pi/2)^dagger in the state after depth steps).
+                                  Each such step applies the gate layers in descending colour with
+                                  exp(-i pi/4 ZZ), then exp(+i pi/4 X) on every site, then BP.     */
 } bpki_problem;
 
+/* Below, S = depth + clifford_steps is the number of steps run. */
 typedef struct {
-  double *z;            /* [max(1, record_every_step ? depth : 1) * n_sites], row t = step t+1;
-                           depth 0 gives one row of ones (the initial state)                   */
-  double *pauli;        /* [n_pauli] or NULL if n_pauli == 0                                    */
-  int32_t *bp_iters;    /* optional [depth]: BP sweeps run after each step                      */
-  double *bp_residual;  /* optional [depth]: final BP residual of each step                     */
-  double *discarded;    /* optional [depth]: sum over the step's gates of the discarded weight  */
+  double *z;            /* [max(1, record_every_step ? S : 1) * n_sites], row t = step t+1;
+                           S = 0 gives one row of ones (the initial state)                     */
+  double *pauli;        /* [n_pauli] or NULL if n_pauli == 0 (measured after the last step)     */
+  int32_t *bp_iters;    /* optional [S]: BP sweeps run after each step                          */
+  double *bp_residual;  /* optional [S]: final BP residual of each step                         */
+  double *discarded;    /* optional [S]: sum over the step's gates of the discarded weight      */
 } bpki_result;
 
 /* Fill *p with the defaults (tolerances 1e-12, 1000 sweeps, FP64, record every step). */
@@ -183,10 +190,14 @@ int bpki_session_observe_pauli(bpki_session *s, double *pauli);
 /* One whole Floquet step: X rotations, all gate layers, BP, then z (may be NULL). */
 int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residual,
                       double *discarded);
+/* One step of U(pi/2)^dagger (see clifford_steps): gate layers in descending colour with
+ * exp(-i pi/4 ZZ), X rotations by -pi/2, BP, then z (may be NULL). */
+int bpki_session_clifford_inverse_step(bpki_session *s, double *z, int32_t *iters,
+                                       double *residual, double *discarded);
 /* Total device time of the last bpki_session_step, split by phase (milliseconds): rx, gate layers,
  * BP, observables.  Measured with HIP events on the session's stream. */
 int bpki_session_last_timing(const bpki_session *s, double *ms4);
-/* Kernel-level timing of the complex GEMM kernel (every contraction of the method runs in it):
+/* Kernel-level timing of the complex GEMM kernels (every contraction of the method runs in them):
  * with stride k >= 1, every k-th launch on the session's stream is bracketed by HIP events (each
  * event pair costs a few microseconds of stream time, so a stride above 1 keeps the measurement
  * from slowing the run it measures); stride 0 turns it off.  read returns the bracketed launch

@@ -30,8 +30,11 @@ What it computes (arXiv 2306.14887, Tindall, Fishman, Stoudenmire, Sels):
 
 Readings where the paper is silent (all mirrored by the HIP path):
   message normalisation: unit trace; singular values: unit 2-norm;
-  BP schedule: synchronous sweeps, warm-started from the current messages, residual =
+  BP schedule: sweeps by vertex class (the two sides of a bipartite lattice, else a greedy
+  vertex colouring; see Network.bp_sweep), warm-started from the current messages, residual =
   max over directed edges of the Frobenius norm of the change, stop when < tol;
+  extended time evolution (U(pi/2)^dagger steps): gates exp(-i pi/4 ZZ) in descending
+  colour, then X rotations by -pi/2;
   truncation: keep min(chi, #{sigma_i > eps_svd * sigma_1}) singular values;
   message square roots: eigenvalues clipped at 0; inverse square roots keep eigenvalues
   > eps_eig * lambda_max; gate layers: ascending colour of a proper edge colouring.
@@ -350,33 +353,48 @@ class Result:
 
 
 def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
-          pauli=(), record_every_step: bool = True, net: Network | None = None) -> Result:
+          pauli=(), record_every_step: bool = True, net: Network | None = None,
+          clifford_steps: int = 0) -> Result:
     """Run ``depth`` Floquet steps and measure (Eq. "State"; Methods).
 
     Each step: exact X rotations, then the simple-update gate layers in ascending
     colour, then BP to convergence, then <Z_v> for every site.
+    ``clifford_steps`` further steps apply U(pi/2)^dagger (the extended time evolution of
+    "Measuring expectation values"): since U = (ZZ gates)(X rotations), its adjoint applies
+    the gates exp(-i pi/4 ZZ) first (descending colour, the forward order mirrored), then the
+    X rotations by -pi/2; BP and <Z_v> follow as after a forward step.
     ``pauli`` is a sequence of (sites, ops) evaluated after the final step.
     """
     if net is None:
         net = Network(n_sites, edges, colour)
     colours = sorted(set(int(c) for c in net.colour.tolist()))
+    inv = Options(chi=opt.chi, bp_tol=opt.bp_tol, bp_max_iter=opt.bp_max_iter,
+                  svd_cutoff=opt.svd_cutoff, eig_cutoff=opt.eig_cutoff, zz_sign=-opt.zz_sign)
+    steps = depth + clifford_steps
     zs, iters, resid, disc = [], [], [], []
     converged = True
-    for _t in range(depth):
-        net.apply_rx(theta)
+    for _t in range(steps):
         dsum = 0.0
-        for c in colours:
-            for e, (u, v) in enumerate(net.edges):
-                if int(net.colour[e]) == c:
-                    dsum += net.simple_update(u, v, opt)
+        if _t < depth:
+            net.apply_rx(theta)
+            for c in colours:
+                for e, (u, v) in enumerate(net.edges):
+                    if int(net.colour[e]) == c:
+                        dsum += net.simple_update(u, v, opt)
+        else:
+            for c in reversed(colours):
+                for e, (u, v) in enumerate(net.edges):
+                    if int(net.colour[e]) == c:
+                        dsum += net.simple_update(u, v, inv)
+            net.apply_rx(-math.pi / 2)
         it, res = net.bp(opt.bp_tol, opt.bp_max_iter)
         converged &= res < opt.bp_tol
         iters.append(it)
         resid.append(res)
         disc.append(dsum)
-        if record_every_step or _t == depth - 1:
+        if record_every_step or _t == steps - 1:
             zs.append([net.expect_site(v, 3) for v in range(net.n)])
-    if depth == 0:
+    if steps == 0:
         zs.append([1.0] * net.n)
     pv = np.array([net.expect_pauli(s, o) for s, o in pauli], dtype=float)
     return Result(np.array(zs, dtype=float), pv, iters, resid, disc, converged)

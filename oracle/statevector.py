@@ -58,6 +58,11 @@ class StateVector:
         self.apply_rx(theta)
         self.apply_zz()
 
+    def clifford_inverse_step(self) -> None:
+        """One step of U(pi/2)^dagger = (RX layer at -pi/2)(ZZ layer)^dagger."""
+        self.psi = self.psi * np.conj(self.zz_phase)
+        self.apply_rx(-math.pi / 2)
+
     def expect_z(self) -> np.ndarray:
         p = np.abs(self.psi) ** 2
         return self.z.astype(float) @ p

@@ -33,7 +33,7 @@ class _Problem(C.Structure):
         ("svd_cutoff", C.c_double), ("eig_cutoff", C.c_double),
         ("n_pauli", C.c_int32), ("pauli_offsets", C.POINTER(C.c_int32)),
         ("pauli_sites", C.POINTER(C.c_int32)), ("pauli_ops", C.POINTER(C.c_uint8)),
-        ("record_every_step", C.c_int32),
+        ("record_every_step", C.c_int32), ("clifford_steps", C.c_int32),
     ]
 
 
@@ -97,6 +97,7 @@ def load(path: str | None = None):
         "bpki_session_observe_z": (C.c_int, [vp, dp]),
         "bpki_session_observe_pauli": (C.c_int, [vp, dp]),
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
+        "bpki_session_clifford_inverse_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_last_timing": (C.c_int, [vp, dp]),
         "bpki_session_profile": (C.c_int, [vp, C.c_int]),
         "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp,
@@ -125,7 +126,8 @@ def exported_symbols() -> list[str]:
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
             "bpki_session_bp_sweep", "bpki_session_observe_z", "bpki_session_observe_pauli",
-            "bpki_session_step", "bpki_session_last_timing", "bpki_session_profile",
+            "bpki_session_step", "bpki_session_clifford_inverse_step",
+            "bpki_session_last_timing", "bpki_session_profile",
             "bpki_session_profile_read", "bpki_test_gemm",
             "bpki_test_eigh", "bpki_test_gram_chol", "bpki_test_mfma_rate"]
 
@@ -156,6 +158,7 @@ class ProblemSpec:
     eig_cutoff: float = 1e-12
     pauli: tuple = ()
     record_every_step: bool = True
+    clifford_steps: int = 0         # steps of U(pi/2)^dagger after the depth steps
 
     def to_c(self):
         keep = {}
@@ -178,6 +181,7 @@ class ProblemSpec:
         p.svd_cutoff = float(self.svd_cutoff)
         p.eig_cutoff = float(self.eig_cutoff)
         p.record_every_step = 1 if self.record_every_step else 0
+        p.clifford_steps = int(self.clifford_steps)
         if self.pauli:
             offs, sites, ops = [0], [], []
             for s, o in self.pauli:
@@ -304,13 +308,14 @@ class Context:
 
 
 def _alloc_result(spec: ProblemSpec) -> dict:
-    rows = spec.depth if spec.record_every_step else 1
+    steps = spec.depth + spec.clifford_steps
+    rows = steps if spec.record_every_step else 1
     return {
         "z": np.full((max(rows, 1), spec.n_sites), np.nan),
         "pauli": np.zeros(len(spec.pauli)),
-        "bp_iters": np.zeros(max(spec.depth, 1), dtype=np.int32),
-        "bp_residual": np.zeros(max(spec.depth, 1)),
-        "discarded": np.zeros(max(spec.depth, 1)),
+        "bp_iters": np.zeros(max(steps, 1), dtype=np.int32),
+        "bp_residual": np.zeros(max(steps, 1)),
+        "discarded": np.zeros(max(steps, 1)),
     }
 
 
@@ -433,6 +438,17 @@ class Session:
         z = np.zeros(self.spec.n_sites) if observe else None
         it, r, d = C.c_int32(), C.c_double(), C.c_double()
         rc = _check(self.lib, self.lib.bpki_session_step(
+            self.h, _ptr(z, C.c_double) if observe else None, C.byref(it), C.byref(r),
+            C.byref(d)))
+        return {"z": z, "bp_iters": it.value, "bp_residual": r.value, "discarded": d.value,
+                "status": rc}
+
+    def clifford_inverse_step(self, observe: bool = True):
+        """One step of U(pi/2)^dagger (gates with exp(-i pi/4 ZZ) in descending colour, X
+        rotations by -pi/2), BP, then <Z> if observe."""
+        z = np.zeros(self.spec.n_sites) if observe else None
+        it, r, d = C.c_int32(), C.c_double(), C.c_double()
+        rc = _check(self.lib, self.lib.bpki_session_clifford_inverse_step(
             self.h, _ptr(z, C.c_double) if observe else None, C.byref(it), C.byref(r),
             C.byref(d)))
         return {"z": z, "bp_iters": it.value, "bp_residual": r.value, "discarded": d.value,

@@ -81,6 +81,7 @@ extern "C" int bpki_validate(const bpki_problem *p) {
     return fail(-1, "cutoffs must be finite and >= 0");
   if (p->record_every_step != 0 && p->record_every_step != 1)
     return fail(-1, "record_every_step must be 0 or 1");
+  if (p->clifford_steps < 0) return fail(-1, "clifford_steps must be >= 0");
   const int n = p->n_sites, E = p->n_edges;
   std::vector<int> deg(n, 0);
   std::set<std::pair<int, int>> seen;
@@ -165,6 +166,7 @@ static Problem to_problem(const bpki_problem *p) {
   q.svd_cutoff = p->svd_cutoff;
   q.eig_cutoff = p->eig_cutoff;
   q.record_every_step = p->record_every_step;
+  q.clifford_steps = p->clifford_steps;
   if (p->n_pauli > 0) {
     q.pauli_offsets.assign(p->pauli_offsets, p->pauli_offsets + p->n_pauli + 1);
     int tot = p->pauli_offsets[p->n_pauli];
@@ -239,31 +241,48 @@ extern "C" void bpki_destroy(bpki_ctx *c) {
 }
 
 // One whole solve on an engine; outputs written only on success.
+// Steps of U(pi/2)^dagger (the extended time evolution of "Measuring expectation values"):
+// U = (ZZ gates)(X rotations) gives U^dagger = (X rotations by -theta)(gates exp(-i pi/4 ZZ)),
+// so the gates come first (descending colour, mirroring the forward step), then the rotations.
+static double clifford_inverse_step(Engine &eng, const std::vector<int> &cols) {
+  double d = 0;
+  for (auto it = cols.rbegin(); it != cols.rend(); ++it) d += eng.apply_layer(*it, -1);
+  eng.apply_rx_angle(-M_PI / 2);
+  return d;
+}
+
+static std::vector<int> sorted_colours(const Problem &q) {
+  std::vector<int> cs(q.colour.begin(), q.colour.end());
+  std::sort(cs.begin(), cs.end());
+  cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+  return cs;
+}
+
 static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
                      std::atomic<bool> *cancel) {
   const int n = q.n_sites;
-  const int rows = std::max(1, q.record_every_step ? q.depth : 1);
+  const int steps = q.depth + q.clifford_steps;
+  const int rows = std::max(1, q.record_every_step ? steps : 1);
   std::vector<double> z((size_t)rows * n, 1.0);
-  std::vector<int32_t> iters(q.depth, 0);
-  std::vector<double> res(q.depth, 0.0), disc(q.depth, 0.0);
+  std::vector<int32_t> iters(steps, 0);
+  std::vector<double> res(steps, 0.0), disc(steps, 0.0);
+  const std::vector<int> cols = sorted_colours(q);
   int warn = 0;
-  for (int t = 0; t < q.depth; ++t) {
+  for (int t = 0; t < steps; ++t) {
     if (cancel && cancel->load()) return fail(-6, "cancelled");
-    eng.apply_rx();
     double d = 0;
-    for (int c : [&] {
-           std::vector<int> cs(q.colour.begin(), q.colour.end());
-           std::sort(cs.begin(), cs.end());
-           cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
-           return cs;
-         }())
-      d += eng.apply_layer(c);
+    if (t < q.depth) {
+      eng.apply_rx();
+      for (int c : cols) d += eng.apply_layer(c);
+    } else {
+      d = clifford_inverse_step(eng, cols);
+    }
     double rr = 0;
     iters[t] = eng.bp(q.bp_max_iter, &rr);
     res[t] = rr;
     disc[t] = d;
     if (!(rr < q.bp_tol)) warn = 1;
-    if (q.record_every_step || t == q.depth - 1) {
+    if (q.record_every_step || t == steps - 1) {
       int row = q.record_every_step ? t : 0;
       eng.observe_z(&z[(size_t)row * n]);
     }
@@ -446,6 +465,31 @@ extern "C" int bpki_session_step(bpki_session *s, double *z, int32_t *iters, dou
   return r < s->eng->problem().bp_tol ? 0 : 1;
 }
 
+extern "C" int bpki_session_clifford_inverse_step(bpki_session *s, double *z, int32_t *iters,
+                                                  double *res, double *disc) {
+  if (!s) return fail(-1, "NULL session");
+  Backend *be = s->ctx->be.get();
+  be->timer_mark(0);
+  be->timer_mark(1);
+  const double d = clifford_inverse_step(*s->eng, s->colours);
+  be->timer_mark(2);
+  double r = 0;
+  int it = s->eng->bp(s->eng->problem().bp_max_iter, &r);
+  be->timer_mark(3);
+  if (z) s->eng->observe_z(z);
+  be->timer_mark(4);
+  s->timing[0] = be->timer_ms(0, 1);
+  s->timing[1] = be->timer_ms(1, 2);
+  s->timing[2] = be->timer_ms(2, 3);
+  s->timing[3] = z ? be->timer_ms(3, 4) : 0.0;
+  if (iters) *iters = it;
+  if (res) *res = r;
+  if (disc) *disc = d;
+  int e = sess_check(s);
+  if (e) return e;
+  return r < s->eng->problem().bp_tol ? 0 : 1;
+}
+
 extern "C" int bpki_session_profile(bpki_session *s, int stride) {
   if (!s) return fail(-1, "NULL session");
   if (stride < 0) return fail(-1, "stride must be >= 0");
@@ -497,8 +541,8 @@ struct bpki_ctx::Job {
 static bool packable(const Problem &a, const Problem &b) {
   return a.n_sites == b.n_sites && a.chi == b.chi && a.precision == b.precision &&
          a.bp_tol == b.bp_tol && a.bp_max_iter == b.bp_max_iter && a.svd_cutoff == b.svd_cutoff &&
-         a.eig_cutoff == b.eig_cutoff && b.depth >= 1 && a.edges == b.edges &&
-         a.colour == b.colour;
+         a.eig_cutoff == b.eig_cutoff && b.depth >= 1 && a.clifford_steps == 0 &&
+         b.clifford_steps == 0 && a.edges == b.edges && a.colour == b.colour;
 }
 
 static Problem pack_problem(const std::vector<const Problem *> &qs, std::vector<int> *pauli0) {
@@ -694,6 +738,7 @@ static void slot_loop(bpki_ctx *c, int slot) {
       // pack only from a backlog (more queued requests than slots: otherwise the idle slots
       // run them concurrently), and only companions that end no later than the head
       if (c->pack_max > 1 && job->q.chi <= c->pack_max_chi && job->q.depth >= 1 &&
+          job->q.clifford_steps == 0 &&
           (int)c->queue.size() >= c->n_slots) {
         for (auto it = c->queue.begin();
              it != c->queue.end() && (int)pack.size() < c->pack_max;) {

@@ -133,6 +133,7 @@ struct Problem {
   std::vector<int> pauli_offsets, pauli_sites;
   std::vector<uint8_t> pauli_ops;
   int record_every_step = 1;
+  int clifford_steps = 0;       // steps of U(pi/2)^dagger after the depth steps at theta
   // Packed solves (several requests on the disjoint union of their lattices): the X angle of
   // every site (empty: theta everywhere) and the first site of each member followed by n_sites
   // (empty: a single member).  Members are contiguous site ranges with contiguous edge ranges.
@@ -151,7 +152,9 @@ class Engine {
 
   void reset();                                   // |0...0>, messages [[1]]
   void apply_rx();
-  double apply_layer(int colour);                 // returns discarded weight of the layer
+  void apply_rx_angle(double theta);              // the same X angle on every site
+  // zz_sign = -1 applies exp(-i pi/4 ZZ), the gates of U(pi/2)^dagger; returns discarded weight
+  double apply_layer(int colour, int zz_sign = 1);
   double bp_sweep();                              // returns residual
   int bp(int max_iter, double *residual);         // returns sweeps
   void observe_z(double *z);                      // host out [n_sites]

@@ -913,7 +913,13 @@ void Engine::apply_rx() {
   }
 }
 
-double Engine::apply_layer(int colour) {
+void Engine::apply_rx_angle(double theta) {
+  Plan &P = *plan_;
+  be_->rx(P.arena.at<double *const *>(P.rx_ptrs), P.rx_half, P.n, std::cos(theta / 2),
+          std::sin(theta / 2));
+}
+
+double Engine::apply_layer(int colour, int zz_sign) {
   Plan &P = *plan_;
   auto it = std::find(P.layer_colours.begin(), P.layer_colours.end(), colour);
   if (it == P.layer_colours.end()) return 0.0;
@@ -943,7 +949,7 @@ double Engine::apply_layer(int colour) {
   for (auto &T : LP.types) {
     be_->theta(T.rB, T.rS, chi, ar.at<const double *const *>(T.RB),
                ar.at<const double *const *>(T.RS), ar.at<double *const *>(T.Th), std::cos(q),
-               std::sin(q), std::cos(q), -std::sin(q), T.count);
+               zz_sign * std::sin(q), std::cos(q), -zz_sign * std::sin(q), T.count);
     run(be_, ar, T.hgemm, 0);        // the truncation SVD is FP64 in every mode
   }
   for (auto &G : LP.eig_groups)

@@ -255,3 +255,48 @@ def test_session_outlives_destroyed_context():
         s.step()
     assert np.abs(s.observe_z() - ref["z"][-1]).max() < 1e-13
     s.close()
+
+
+def test_extended_time_evolution_vs_oracle(ctx):
+    """Steps of U(pi/2)^dagger after the forward steps (clifford_steps): truncated heavy-hex
+    29 q at chi = 8, every <Z_v> row against the oracle; Pauli strings after the last step."""
+    print("[parity] extended time evolution heavy-hex 29q chi=8", flush=True)
+    lat = L.heavy_hex(3, 9)
+    ps = L.random_pauli_strings(lat, 4, seed=77, wmin=3, wmax=7)
+    pl = [(p.sites, p.ops) for p in ps]
+    g = _gpu(ctx, lat, 0.55, 3, 8, clifford_steps=2, pauli=pl)
+    o = O.solve(lat.n_sites, lat.edges, lat.colour, 0.55, 3, O.Options(chi=8), pauli=pl,
+                clifford_steps=2)
+    assert g["z"].shape == (5, lat.n_sites)
+    assert np.abs(g["z"] - o.z).max() < TOL
+    assert np.abs(g["pauli"] - o.pauli).max() < TOL
+    # the stopping sweep sits where the residual crosses 1e-12 slowly; rounding differences
+    # between the two sides shift it by up to two sweeps here (observed: 2 at one step)
+    d = np.abs(np.array(g["bp_iters"]) - np.array(o.bp_iters))
+    assert d.max() <= 2, (list(g["bp_iters"]), list(o.bp_iters))
+
+
+def test_extended_time_evolution_tree_exact(ctx):
+    """On a tree without truncation the extended evolution is exact: state vector."""
+    print("[parity] extended time evolution tree vs state vector", flush=True)
+    tr = L.random_tree(14, np.random.default_rng(8))
+    g = _gpu(ctx, tr, 0.8, 2, 64, clifford_steps=3)
+    sv = SV.StateVector(tr.n_sites, tr.edges)
+    ref = []
+    for _ in range(2):
+        sv.step(0.8)
+        ref.append(sv.expect_z())
+    for _ in range(3):
+        sv.clifford_inverse_step()
+        ref.append(sv.expect_z())
+    assert np.abs(g["z"] - np.array(ref)).max() < 1e-11
+
+
+def test_session_clifford_inverse_step_matches_solve(ctx):
+    print("[parity] session inverse steps vs solve", flush=True)
+    lat = L.heavy_hex(3, 9)
+    g = _gpu(ctx, lat, 0.5, 2, 8, clifford_steps=2)
+    s = _session(ctx, lat, 0.5, 2, 8)
+    zs = [s.step()["z"] for _ in range(2)] + [s.clifford_inverse_step()["z"] for _ in range(2)]
+    s.close()
+    assert np.abs(np.array(zs) - g["z"]).max() < 1e-13
