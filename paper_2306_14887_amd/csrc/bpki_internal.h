@@ -43,7 +43,6 @@ struct Backend {
   virtual void h2d(void *dst, const void *src, size_t bytes) = 0;
   virtual void d2h(void *dst, const void *src, size_t bytes) = 0;
   virtual void d2d(void *dst, const void *src, size_t bytes) = 0;
-  virtual void zero(void *dst, size_t bytes) = 0;
   virtual void sync() = 0;
   virtual int check(std::string *msg) = 0;          // 0 or negative error code
   // HIP events on the backend's stream: mark slot i; elapsed milliseconds between two marks.
@@ -71,10 +70,6 @@ struct Backend {
   // X = W f(l) W^H with f = sqrt(max(l,0)) and Xp with f = 1/sqrt(l) for l > cut*l_max else 0.
   virtual void msg_sqrt(int n, const double *const *evals, const double *const *vecs,
                         double *const *X, double *const *Xp, double cut, int nprob) = 0;
-  // From eigh(G) of the Gram matrix G = A^H A (n x n): R[i][c] = sqrt(l_i) conj(W[c][i]),
-  // Wsc[c][i] = W[c][i]/sqrt(l_i) for l_i > cut*l_0 (else 0), i < r.
-  virtual void gram_factor(int n, int r, const double *const *evals, const double *const *vecs,
-                           double *const *R, double *const *Wsc, double cut, int nprob) = 0;
   // Pivoted Cholesky factor of a Gram matrix G = A^H A (n x n, Hermitian PSD):
   // G[p][p] = L L^H for a pivot order p, stopping at the first pivot <= cut * max(diag G).
   // Writes R = L^H P^T (n x n, zero rows beyond the rank) and Wsc = P [L1^{-H}; 0] (n x n), so

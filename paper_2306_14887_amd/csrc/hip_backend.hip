@@ -1621,26 +1621,6 @@ __global__ __launch_bounds__(256) void msg_sqrt_kernel(int n, const double *cons
   }
 }
 
-__global__ void gram_factor_kernel(int n, int r, const double *const *evals,
-                                   const double *const *vecs, double *const *R,
-                                   double *const *Wsc, double cut) {
-  const double *l = evals[blockIdx.x];
-  const double2 *W = reinterpret_cast<const double2 *>(vecs[blockIdx.x]);
-  double2 *Ro = reinterpret_cast<double2 *>(R[blockIdx.x]);
-  double2 *Wo = reinterpret_cast<double2 *>(Wsc[blockIdx.x]);
-  double l0 = l[0] > 0 ? l[0] : 0.0;
-  for (int idx = threadIdx.x; idx < r * n; idx += blockDim.x) {
-    int i = idx / n, c = idx % n;    // R[i][c]
-    double li = l[i];
-    bool keep = li > cut * l0 && li > 0;
-    double sq = keep ? sqrt(li) : 0.0;
-    double2 w = W[(size_t)c * n + i];
-    Ro[idx] = make_double2(sq * w.x, -sq * w.y);
-    double is = keep ? 1.0 / sq : 0.0;
-    Wo[(size_t)c * r + i] = make_double2(is * w.x, is * w.y);
-  }
-}
-
 // Theta <- g(s_B, s_S) Theta in place, rows (r_B, s_B), columns (r_S, s_S).
 __global__ void theta_phase_kernel(int rB, int rS, double *const *Th, double gsr, double gsi,
                                    double gdr, double gdi) {
@@ -1973,7 +1953,6 @@ class HipBackend : public Backend {
   void d2d(void *d, const void *s, size_t b) override {
     if (b) HIPCHK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, s_));
   }
-  void zero(void *d, size_t b) override { if (b) HIPCHK(hipMemsetAsync(d, 0, b, s_)); }
   void sync() override { HIPCHK(hipStreamSynchronize(s_)); }
   int check(std::string *msg) override {
     HIPCHK(hipGetLastError());
@@ -2189,13 +2168,6 @@ class HipBackend : public Backend {
     stale_check("msg_sqrt_kernel");
     hipLaunchKernelGGL(msg_sqrt_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, X, Xp, cut);
     launch_check("msg_sqrt_kernel");
-  }
-  void gram_factor(int n, int r, const double *const *ev, const double *const *vec,
-                   double *const *R, double *const *W, double cut, int nprob) override {
-    stale_check("gram_factor_kernel");
-    hipLaunchKernelGGL(gram_factor_kernel, dim3(nprob), dim3(256), 0, s_, n, r, ev, vec, R, W,
-                       cut);
-    launch_check("gram_factor_kernel");
   }
   void gram_chol(int n, const double *const *G, double *const *R, double *const *Wsc, double cut,
                  int nprob) override {
