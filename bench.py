@@ -10,7 +10,8 @@ next --steps steps are timed, so the default run is steps 7..20 of the 20-step c
 The JSON line also carries:
   roofline     : the complex GEMM kernels (every contraction of the step runs in them: the tiled
                  gemm_kernel, and gemm_stream_kernel for the leg contractions with K, N <= 64),
-                 algorithmic flops 8*M*N*K per launch over the HIP-event-timed launch durations
+                 algorithmic flops 8*M*N*K per launch (8*K*M(M+1)/2 for the Hermitian outputs,
+                 whose upper triangle is a mirror) over the HIP-event-timed launch durations
                  (every 7th launch of the timed window), against the
                  MI355X FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the
                  committed rocprofv3 counter summary (null once the kernel source has changed);

@@ -202,7 +202,8 @@ int bpki_session_last_timing(const bpki_session *s, double *ms4);
  * event pair costs a few microseconds of stream time, so a stride above 1 keeps the measurement
  * from slowing the run it measures); stride 0 turns it off.  read returns the bracketed launch
  * count, the summed kernel time in ms and the summed 8*M*N*K flops of those launches (complex
- * multiply-adds at 8 real flops), and optionally the count of all launches since enabling.
+ * multiply-adds at 8 real flops; 8*K*M(M+1)/2 for a Hermitian output, of which only the lower
+ * triangle is computed), and optionally the count of all launches since enabling.
  * Enabling resets the counters. */
 int bpki_session_profile(bpki_session *s, int stride);
 int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, double *flops,

@@ -34,6 +34,10 @@ typedef struct {
   int32_t batch, conjA, conjB, beta;
   double alpha_re, alpha_im;
   int32_t prec;      /* 0: FP64 MFMA; 1: operands rounded to FP32, FP32 MFMA, FP64 output */
+  int32_t herm;      /* 1: the caller guarantees C = A B is Hermitian (M == N, Mi == M, Ni == N,
+                        alpha_im == 0, beta == 0): the lower triangle is computed, the diagonal
+                        stored real, the upper triangle written as its conjugate mirror
+                        (exactly Hermitian output) */
 } bpki_test_gemm_desc;
 
 /* Runs the FP64 MFMA GEMM on nprob problems; problem p uses A + 2*a_elems*p etc.  C is read

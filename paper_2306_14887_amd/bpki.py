@@ -51,7 +51,8 @@ class TestGemmDesc(C.Structure):
                                          "b_ni", "c_mo", "c_mi", "c_no", "c_ni", "a_b", "b_b",
                                          "c_b")] + \
                [(n, C.c_int32) for n in ("batch", "conjA", "conjB", "beta")] + \
-               [("alpha_re", C.c_double), ("alpha_im", C.c_double), ("prec", C.c_int32)]
+               [("alpha_re", C.c_double), ("alpha_im", C.c_double), ("prec", C.c_int32),
+                ("herm", C.c_int32)]
 
 
 _lib = None
@@ -263,7 +264,7 @@ class Context:
     def test_gemm(self, desc: dict, A, B, Cm, nprob: int = 1):
         d = TestGemmDesc()
         defaults = dict(Mi=None, Ni=None, Ki=None, batch=1, conjA=0, conjB=0, beta=0,
-                        alpha_re=1.0, alpha_im=0.0, prec=0)
+                        alpha_re=1.0, alpha_im=0.0, prec=0, herm=0)
         full = {**defaults, **desc}
         for k in ("M", "N", "K"):
             if full.get(k + "i") is None:

@@ -915,7 +915,10 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
   d.conjA = td->conjA; d.conjB = td->conjB; d.beta = td->beta;
   d.alpha_re = td->alpha_re; d.alpha_im = td->alpha_im;
   d.prec = td->prec;
+  d.herm = td->herm;
   if (d.prec != 0 && d.prec != 1) return fail(-1, "prec must be 0 (FP64) or 1 (FP32)");
+  if (d.herm && (d.M != d.N || d.Mi != d.M || d.Ni != d.N || d.alpha_im != 0 || d.beta))
+    return fail(-1, "herm needs M == N, single-stride M and N, real alpha and beta = 0");
   if (d.M < 1 || d.N < 1 || d.K < 1 || d.Mi < 1 || d.Ni < 1 || d.Ki < 1 || d.batch < 1 ||
       d.M % d.Mi || d.N % d.Ni || d.K % d.Ki)
     return fail(-1, "inconsistent descriptor");

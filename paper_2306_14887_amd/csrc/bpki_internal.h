@@ -28,6 +28,10 @@ struct GemmDesc {
   int beta = 0;                          // 1: accumulate into C
   double alpha_re = 1.0, alpha_im = 0.0;
   int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA (FP64 storage)
+  // 1: C = A B is Hermitian (M == N, single-stride M and N, real alpha, beta = 0): only the
+  // lower triangle is computed, the diagonal is stored real and the upper triangle is written
+  // as the conjugate mirror
+  int herm = 0;
 };
 
 // Simple composite-index helpers for descriptors.

@@ -556,6 +556,7 @@ void Engine::build() {
       g.K = (int)c2; g.Ki = (int)c2; g.a_ki = 2 * chi; g.b_ki = 2 * chi;
       g.N = 2 * chi; g.Ni = 2 * chi; g.b_ni = 1;
       g.c_mi = 2 * chi; g.c_ni = 1;
+      g.herm = 1;                       // Hermitian: lower triangle, conjugate mirror
       LP.gram.d = g;
       GemmDesc qd;                      // Q = A Wsc : [env][2chi] x [2chi][2chi]
       qd.M = (int)c2; qd.Mi = (int)c2; qd.a_mi = 2 * chi; qd.c_mi = 2 * chi;
@@ -616,6 +617,7 @@ void Engine::build() {
       hd.M = T.n; hd.Mi = T.n; hd.a_mi = 1; hd.conjA = 1;
       hd.K = 2 * T.rB; hd.Ki = 2 * T.rB; hd.a_ki = T.n; hd.b_ki = T.n;
       hd.N = T.n; hd.Ni = T.n; hd.b_ni = 1; hd.c_mi = T.n; hd.c_ni = 1;
+      hd.herm = 1;                      // Theta^H Theta is Hermitian
       T.hgemm.d = hd;
       GemmDesc ud;                      // U = Theta Vs : [2rB][n] x [n][chi]
       ud.M = 2 * T.rB; ud.Mi = 2 * T.rB; ud.a_mi = T.n; ud.c_mi = chi;
@@ -737,6 +739,13 @@ void Engine::build() {
     const int ncls = P.n ? *std::max_element(cls.begin(), cls.end()) + 1 : 0;
     std::vector<int> res_src;             // source site of every residual slot
     Layout L3 = t_layout(3, chi), L2 = t_layout(2, chi), L1 = t_layout(1, chi);
+    // a closing contraction sum T (prod M) conj(T) with Hermitian messages is Hermitian: only its
+    // lower triangle is computed (messages stay exactly Hermitian)
+    auto hclose = [&](int deg, int leg, const Layout &L) {
+      GemmDesc d = close_desc(deg, leg, L, chi);
+      d.herm = 1;
+      return d;
+    };
     int res_off = 0;
     for (int c = 0; c < ncls; ++c) {
       Plan::BpClass C;
@@ -765,9 +774,9 @@ void Engine::build() {
         add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[2], b[2], cc[2]);
         add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[3], b[3], cc[3]);
         add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[4], b[4], cc[4]);
-        add_op(C.ops, close_desc(3, 0, L3, chi), a[5], b[5], cc[5]);
-        add_op(C.ops, close_desc(3, 1, L3, chi), a[6], b[6], cc[6]);
-        add_op(C.ops, close_desc(3, 2, L3, chi), a[7], b[7], cc[7]);
+        add_op(C.ops, hclose(3, 0, L3), a[5], b[5], cc[5]);
+        add_op(C.ops, hclose(3, 1, L3), a[6], b[6], cc[6]);
+        add_op(C.ops, hclose(3, 2, L3), a[7], b[7], cc[7]);
       }
       {
         std::vector<const void *> a[4], b[4], cc[4];
@@ -781,8 +790,8 @@ void Engine::build() {
         }
         add_op(C.ops, leg_desc(2, 1, L2, L2, chi), a[0], b[0], cc[0]);
         add_op(C.ops, leg_desc(2, 0, L2, L2, chi), a[1], b[1], cc[1]);
-        add_op(C.ops, close_desc(2, 0, L2, chi), a[2], b[2], cc[2]);
-        add_op(C.ops, close_desc(2, 1, L2, chi), a[3], b[3], cc[3]);
+        add_op(C.ops, hclose(2, 0, L2), a[2], b[2], cc[2]);
+        add_op(C.ops, hclose(2, 1, L2), a[3], b[3], cc[3]);
       }
       {
         std::vector<const void *> a, b, cc;
@@ -790,7 +799,7 @@ void Engine::build() {
           if (P.deg[v] != 1 || cls[v] != c) continue;
           a.push_back(Tp(v)); b.push_back(Tp(v)); cc.push_back(Mnp(P.out_msg[v][0]));
         }
-        add_op(C.ops, close_desc(1, 0, L1, chi), a, b, cc);
+        add_op(C.ops, hclose(1, 0, L1), a, b, cc);
       }
       std::vector<const void *> nn, no;
       for (int v = 0; v < P.n; ++v) {

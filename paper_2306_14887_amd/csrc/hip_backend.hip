@@ -95,7 +95,7 @@ struct MfmaTraits<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T>
+template <typename T, bool HERM>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *const *Ap,
                                                       const double *const *Bp,
                                                       double *const *Cp, int ksplit,
@@ -109,6 +109,21 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
   const int wave = tid >> 6;
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+  // Hermitian output: tiles above the diagonal are left to the mirror writes of their transposes;
+  // a diagonal tile computes its ten 16x16 blocks on or below the diagonal, three or two per wave
+  // (block b of wave w is number w + 4 b in the order (0,0) (1,0) (1,1) (2,0) (2,1) ...)
+  if (HERM && tm < tn) return;
+  const bool dtile = HERM && tm == tn;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);     // wave-uniform: scalar registers
+  const int nblk = wv < 2 ? 3 : 2;
+  int dbi[3], dbj[3];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int q = wv + 4 * b;
+    const int bi = q < 1 ? 0 : q < 3 ? 1 : q < 6 ? 2 : 3;
+    dbi[b] = bi;
+    dbj[b] = min(q - bi * (bi + 1) / 2, bi);
+  }
   const int bat = blockIdx.y / ksplit, kz = blockIdx.y % ksplit, prob = blockIdx.z;
   const double2 *A = reinterpret_cast<const double2 *>(Ap[prob]) + (long)bat * d.a_b;
   const double2 *B = reinterpret_cast<const double2 *>(Bp[prob]) + (long)bat * d.b_b;
@@ -172,6 +187,30 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
       for (int t = 0; t < 3; ++t) acc[i][j][t] = (acc_t){T(0), T(0), T(0), T(0)};
 
   if (kbeg < kend) fetch(kbeg);
+  if (HERM && dtile) {
+    // blocks 0, 1, 2 of the wave accumulate in acc[0][0], acc[0][1], acc[1][0]
+    auto block = [&](int kr, int bi, int bj, acc_t(&a3)[3]) {
+      const int ra = 16 * bi + (lane & 15), cb = 16 * bj + (lane & 15);
+      const T ar = As[0][kr][ra], ai = As[1][kr][ra], br = Bs[0][kr][cb], bi_ = Bs[1][kr][cb];
+      const T as = ar + ai, bs = br + bi_;
+      a3[0] = MT::mma(ar, br, a3[0]);
+      a3[1] = MT::mma(ai, bi_, a3[1]);
+      a3[2] = MT::mma(as, bs, a3[2]);
+    };
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      stage();
+      __syncthreads();
+      if (k0 + BK < kend) fetch(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        block(kr, dbi[0], dbj[0], acc[0][0]);
+        block(kr, dbi[1], dbj[1], acc[0][1]);
+        if (nblk > 2) block(kr, dbi[2], dbj[2], acc[1][0]);
+      }
+      __syncthreads();
+    }
+  } else
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     stage();
     __syncthreads();
@@ -208,6 +247,43 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
   double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
   double2 *Wp = W ? W + (((size_t)prob * d.batch + bat) * ksplit + kz) * (size_t)d.M * d.N
                   : nullptr;
+  if constexpr (HERM) {
+    // element (mg, ng) with mg >= ng, and its conjugate at (ng, mg) (single strides, real alpha,
+    // no accumulation); split K: the partial sum only, mirrored by the reduction
+    auto put = [&](int mg, int ng, double cr, double ci) {
+      if (mg >= d.M || ng >= d.N || mg < ng) return;
+      if (Wp) {
+        Wp[(size_t)mg * d.N + ng] = make_double2(cr, ci);
+        return;
+      }
+      const double vr = d.alpha_re * cr, vi = mg == ng ? 0.0 : d.alpha_re * ci;
+      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = make_double2(vr, vi);
+      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = make_double2(vr, -vi);
+    };
+    if (dtile) {
+      auto put_block = [&](int bi, int bj, const acc_t(&a3)[3]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          put(m0 + 16 * bi + MT::row(lane, r), n0 + 16 * bj + (lane & 15),
+              (double)a3[0][r] - (double)a3[1][r],
+              (double)a3[2][r] - (double)a3[0][r] - (double)a3[1][r]);
+      };
+      put_block(dbi[0], dbj[0], acc[0][0]);
+      put_block(dbi[1], dbj[1], acc[0][1]);
+      if (nblk > 2) put_block(dbi[2], dbj[2], acc[1][0]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            put(m0 + wm + i * 16 + MT::row(lane, r), n0 + wn + j * 16 + (lane & 15),
+                (double)acc[i][j][0][r] - (double)acc[i][j][1][r],
+                (double)acc[i][j][2][r] - (double)acc[i][j][0][r] - (double)acc[i][j][1][r]);
+    }
+    return;
+  }
   // output offsets: 8 distinct rows and 2 distinct columns per thread
   long roff[2][4], coff[2];
 #pragma unroll
@@ -399,13 +475,20 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
   double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < mn;
        idx += (size_t)gridDim.x * blockDim.x) {
+    int mg = (int)(idx / d.N), ng = (int)(idx % d.N);
+    if (d.herm && mg < ng) continue;              // written as the mirror of (ng, mg)
     double cr = 0, ci = 0;
     for (int kz = 0; kz < ksplit; ++kz) {
       double2 v = wp[kz * mn + idx];
       cr += v.x;
       ci += v.y;
     }
-    int mg = (int)(idx / d.N), ng = (int)(idx % d.N);
+    if (d.herm) {
+      const double vr = d.alpha_re * cr, vi = mg == ng ? 0.0 : d.alpha_re * ci;
+      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = make_double2(vr, vi);
+      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = make_double2(vr, -vi);
+      continue;
+    }
     double vr = d.alpha_re * cr - d.alpha_im * ci;
     double vi = d.alpha_re * ci + d.alpha_im * cr;
     long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
@@ -2001,7 +2084,7 @@ class HipBackend : public Backend {
     }
     // K and N within 64 (one stride each) and enough rows to amortise loading B (at least 16
     // strips): B resident in LDS, rows of A streamed
-    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 256) {
+    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 256 && !d.herm) {
       const int strips = (d.M + 15) / 16;
       const int per = std::max(1, resident_ / std::max(1, d.batch * nprob));
       dim3 g(std::max(1, std::min(per, (strips + 3) / 4)), d.batch, nprob);
@@ -2043,19 +2126,29 @@ class HipBackend : public Backend {
     }
     if (d.prec == 1) {
       stale_check("gemm_kernel<float>");
-      hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk,
-                         W);
+      if (d.herm)
+        hipLaunchKernelGGL((gemm_kernel<float, true>), grid, dim3(256), 0, s_, d, A, B, C, ksplit,
+                           kchunk, W);
+      else
+        hipLaunchKernelGGL((gemm_kernel<float, false>), grid, dim3(256), 0, s_, d, A, B, C, ksplit,
+                           kchunk, W);
       launch_check("gemm_kernel<float>");
     } else {
       stale_check("gemm_kernel<double>");
-      hipLaunchKernelGGL(gemm_kernel<double>, grid, dim3(256), 0, s_, d, A, B, C, ksplit, kchunk,
-                         W);
+      if (d.herm)
+        hipLaunchKernelGGL((gemm_kernel<double, true>), grid, dim3(256), 0, s_, d, A, B, C, ksplit,
+                           kchunk, W);
+      else
+        hipLaunchKernelGGL((gemm_kernel<double, false>), grid, dim3(256), 0, s_, d, A, B, C, ksplit,
+                           kchunk, W);
       launch_check("gemm_kernel<double>");
     }
     if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
-      prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
+      // algorithmic work: the distinct entries (a Hermitian output has M (M + 1) / 2)
+      const double outs = d.herm ? 0.5 * d.M * (d.M + 1.0) : (double)d.M * d.N;
+      prof_flops_ += 8.0 * outs * (double)d.K * d.batch * nprob;
     }
     if (ksplit > 1) {
       int bx = std::min(64, (int)((d.M * (size_t)d.N + 255) / 256));

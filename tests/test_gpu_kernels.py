@@ -132,6 +132,47 @@ def test_gemm_matches_numpy(ctx, name, desc, nprob):
     assert np.abs(got - want).max() < 1e-13 * scale
 
 
+HERM_CASES = [
+    # one diagonal tile (the BP closings: 64 x 64 output, K = 2 chi^2 split)
+    ("herm_64_splitk", 64, 4096, 2, 0),
+    # several tiles: diagonal, lower and (skipped) upper tiles, ragged edge, no split
+    ("herm_200", 200, 96, 2, 0),
+    ("herm_200_fp32", 200, 96, 1, 1),
+    ("herm_128_splitk_fp32", 128, 2048, 2, 1),
+]
+
+
+@pytest.mark.parametrize("name,n,k,nprob,prec", HERM_CASES, ids=[c[0] for c in HERM_CASES])
+def test_gemm_hermitian_output(ctx, name, n, k, nprob, prec):
+    """herm = 1: C = A A^H computed on the lower triangle and mirrored; equals the full
+    product and is exactly Hermitian."""
+    print(f"[gemm herm] case {name}", flush=True)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    # A [n][k] row-major; B = A^H read from the same data: B[kk][j] = conj(A[j][kk])
+    d = dict(M=n, N=n, K=k, a_mi=k, a_ki=1, b_ki=1, b_ni=k, c_mi=n, c_ni=1, conjB=1,
+             alpha_re=0.75, herm=1, prec=prec)
+    A = _rand(rng, nprob * n * k)
+    Cm = _rand(rng, nprob * n * n)
+    got = ctx.test_gemm(d, A, A, Cm, nprob).reshape(nprob, n, n)
+    for p in range(nprob):
+        a = A[p * n * k:(p + 1) * n * k].reshape(n, k)
+        want = 0.75 * (a @ a.conj().T)
+        if prec:
+            # FP32 products: relative to the largest entry (the diagonal sums k positive terms)
+            assert np.abs(got[p] - want).max() < 1e-6 * np.abs(want).max()
+        else:
+            assert np.abs(got[p] - want).max() < 1e-13 * np.sqrt(k) * 4
+        assert np.array_equal(got[p], got[p].conj().T)
+
+
+def test_gemm_herm_rejects_invalid_descriptor(ctx):
+    from paper_2306_14887_amd.bpki import BpkiError
+    d = dict(M=64, N=32, K=64, a_mi=64, a_ki=1, b_ki=32, b_ni=1, c_mi=32, c_ni=1, herm=1)
+    with pytest.raises(BpkiError):
+        ctx.test_gemm(d, np.zeros(64 * 64, complex), np.zeros(64 * 32, complex),
+                      np.zeros(64 * 32, complex))
+
+
 def test_gemm_rejects_out_of_bounds_descriptor(ctx):
     from paper_2306_14887_amd.bpki import BpkiError
     d = dict(M=64, N=64, K=64, a_mi=64, a_ki=1, b_ki=64, b_ni=1, c_mi=64, c_ni=1)
