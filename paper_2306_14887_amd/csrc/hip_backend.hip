@@ -658,23 +658,25 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Hermitian eigensolver for 32 <= n <= 256 in two kernels.
+// Hermitian eigensolver for 32 <= n <= 256 in three kernels, one workgroup per matrix each.
 //
-// eigh_tridiag_dc_kernel (one workgroup of 512 threads per matrix):
-//  1. Householder reduction to real symmetric tridiagonal form, A = Q T Q^H with
+//  1. eigh_tridiag_kernel (1024 threads): Householder reduction to real symmetric
+//     tridiagonal form, A = Q T Q^H with
 //     Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^H (v_k(k+1) = 1, zero above).  Each
 //     reflector maps column k below the diagonal onto beta e_1 with beta real, so T is real.
 //     The trailing block is updated as A <- A - v w^H - w v^H with x = tau A v and
 //     w = x - (1/2) Re(conj(tau) v^H x) v.  Only the lower triangle is kept (packed in LDS for
 //     n <= 128, row-major in the workspace above); reflectors go to the workspace.
-//  2. Divide and conquer on T (Cuppen's rank-one tearing; eigenvectors by the Gu-Eisenstat
-//     construction).  The index range is cut into the binary tree of ranges
-//     [floor(q n / 2^D), floor((q+1) n / 2^D)); the couplings beta at the cuts above the
-//     leaves (depth 3 for n <= 128, depth 4 above) are torn off (T = diag(T_1 .. T_L) +
-//     sum |beta| u u^T with u = e_{k-1} + sign(beta) e_k and the two diagonal entries lowered
-//     by |beta|).  The leaves (8..16 entries) are diagonalised by cyclic Jacobi, one wave
-//     each, and merged back pairwise by the whole workgroup.  A merge of two solved halves with eigenvectors
-//     Q = diag(Q1, Q2) solves D + rho z z^T (z = Q^T u / sqrt 2, rho = 2|beta|):
+//     The diagonal d and off-diagonal e go to the workspace (eigenvalue and staging areas).
+//  2. eigh_dc_kernel (512 threads): divide and conquer on T (Cuppen's rank-one tearing;
+//     eigenvectors by the Gu-Eisenstat construction).  The index range is cut into the binary
+//     tree of ranges [floor(q n / 2^D), floor((q+1) n / 2^D)); the couplings beta at the cuts
+//     above the leaves (depth 3 for n <= 128, depth 4 above) are torn off (T = diag(T_1 ..
+//     T_L) + sum |beta| u u^T with u = e_{k-1} + sign(beta) e_k and the two diagonal entries
+//     lowered by |beta|).  The leaves (8..16 entries) are diagonalised by cyclic Jacobi, one
+//     wave each, and merged back pairwise by the whole workgroup.  A merge of two solved
+//     halves with eigenvectors Q = diag(Q1, Q2) solves D + rho z z^T (z = Q^T u / sqrt 2,
+//     rho = 2|beta|):
 //       - deflation: components with rho |z_i| <= tol keep (d_i, q_i); pairs of eigenvalues
 //         closer than tol are rotated so that one z component vanishes
 //         (tol = 8 eps max(|d|_max, rho));
@@ -687,8 +689,8 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 //       - z is recomputed from the roots (Loewner's formula) so that the eigenvectors
 //         v_j = (zhat_i / (d_i - lambda_j))_i are numerically orthogonal; the new eigenvector
 //         matrix is Q_K V.
-// eigh_backtransform_kernel (grid: 16-column blocks x matrices): V = Q Z by applying
-// H_{n-2}, ..., H_0 to each column block in LDS; sorts into descending eigenvalue order.
+//  3. eigh_backtransform_kernel (grid: 16-column blocks x matrices): V = Q Z by applying
+//     H_{n-2}, ..., H_0 to each column block in LDS; sorts into descending eigenvalue order.
 //
 // Workspace per matrix (doubles): reflectors n*n complex (column k = v_k), tau n complex,
 // Z n*n real (column-major), eigenvalues n, an n*n staging area for the merges, and for
@@ -982,25 +984,25 @@ __device__ __forceinline__ int dc_bound(int q, int n, int depth) {
   return (int)(((long)q * n) >> depth);
 }
 
-// NMAX = 128: matrix (packed lower triangle) and Z in LDS, leaves at depth 3.
-// NMAX = 256: matrix (lower triangle of a row-major n x n array) and Z in this matrix's
-// workspace, which stays in L2; leaves at depth 4.  Both use 512 threads.
-template <int NMAX>
-__global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
-                                                              const double *const *in,
-                                                              double *ws) {
+// eigh_tridiag_kernel: stage 1 (Householder reduction), NT threads per matrix; writes the
+// reflectors and tau, d to the eigenvalue area and e to the staging area of the workspace.
+// NMAX = 128: matrix packed (lower triangle) in LDS.  NMAX = 256: lower triangle of a row-major
+// n x n array in this matrix's workspace, which stays in L2.
+template <int NMAX, int NT>
+__global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const double *const *in,
+                                                          double *ws) {
   constexpr bool BIG = NMAX > 128;
-  constexpr int LD = BIG ? 4 : 3;               // depth of the leaves
+  constexpr int HALVES = NT / 256;              // BIG: row slabs of the column pass
+  constexpr int TPR = NT / 128;                 // !BIG: threads per row of the matvec
   extern __shared__ double2 smem[];
   __shared__ double d_s[NMAX], e_s[NMAX];
-  // phase-local scratch: reduction vectors (stage 1), leaf matrices (leaves), merge arrays
-  __shared__ __attribute__((aligned(16))) double sbuf[13 * NMAX];
+  __shared__ __attribute__((aligned(16))) double sbuf[(6 + 2 * HALVES) * NMAX];
   __shared__ double2 tau_sh;
   double2 *v_s = reinterpret_cast<double2 *>(sbuf), *w_s = v_s + NMAX;
-  double2 *x1_s = w_s + NMAX, *x2_s = x1_s + NMAX;   // BIG: row part, two column partials
+  double2 *x1_s = w_s + NMAX, *x2_s = x1_s + NMAX;   // BIG: row part, HALVES column partials
   const int prob = blockIdx.x;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  constexpr int nw = 8;
+  constexpr int nw = NT / 64;
   double *base = ws + (size_t)prob * tql_ws_doubles(n);
   double2 *hh = reinterpret_cast<double2 *>(base);
   double2 *tau_g = hh + (size_t)n * n;
@@ -1059,37 +1061,38 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
     const double2 tau = tau_sh;
     if (tau.x == 0.0 && tau.y == 0.0) continue;   // H_k = I (uniform over the block)
     if constexpr (!BIG) {
-      // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): 4 threads per row;
+      // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): TPR threads per row;
       // row gi of S is row gi of the packed triangle up to the diagonal, then column gi
-      const int r = tid >> 2, q = tid & 3;
+      const int r = tid / TPR, q = tid % TPR;
       double2 acc = make_double2(0.0, 0.0);
       if (r < m) {
         const int gi = k + 1 + r;
         const double2 *prow = smem + pk_idx(gi, k + 1);
-        for (int c = q; c <= r; c += 4) {
+        for (int c = q; c <= r; c += TPR) {
           const double2 a = prow[c], vc = v_s[c];
           acc.x += a.x * vc.x - a.y * vc.y;
           acc.y += a.x * vc.y + a.y * vc.x;
         }
-        for (int c = r + 1 + q; c < m; c += 4) {
+        for (int c = r + 1 + q; c < m; c += TPR) {
           const double2 a = smem[pk_idx(k + 1 + c, gi)], vc = v_s[c];   // conj(a) vc
           acc.x += a.x * vc.x + a.y * vc.y;
           acc.y += a.x * vc.y - a.y * vc.x;
         }
       }
-      acc.x += __shfl_xor(acc.x, 1, 64);
-      acc.y += __shfl_xor(acc.y, 1, 64);
-      acc.x += __shfl_xor(acc.x, 2, 64);
-      acc.y += __shfl_xor(acc.y, 2, 64);
+#pragma unroll
+      for (int o = 1; o < TPR; o <<= 1) {
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+      }
       if (r < m && q == 0) w_s[r] = cmul(tau, acc);
     } else {
       // S v from the lower triangle in two coalesced passes: the row part (diagonal included)
       // with 16 lanes per row, and the strictly upper part as conj(S)^T v with one lane per
-      // column and the rows split in two halves by parity
+      // column and the rows split in HALVES slabs by residue
       const double2 *S0 = Pg + (size_t)(k + 1) * n + k + 1;
       {
         const int q = tid & 15;
-        for (int r = tid >> 4; r < m; r += 32) {
+        for (int r = tid >> 4; r < m; r += NT / 16) {
           const double2 *prow = S0 + (size_t)r * n;
           double2 acc = make_double2(0.0, 0.0);
           for (int c = q; c <= r; c += 16) {
@@ -1110,7 +1113,7 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
         if (c0 < m) {
           double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
-          for (int r = c0 + 1 + half; r < m; r += 2) {
+          for (int r = c0 + 1 + half; r < m; r += HALVES) {
             if (r > c) {
               const double2 a = S0[(size_t)r * n + c], vr = v_s[r];   // conj(a) v_r
               acc.x += a.x * vr.x + a.y * vr.y;
@@ -1126,8 +1129,14 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
     // the lower triangle with w = x + a v formed on the fly
     auto xval = [&](int i) -> double2 {
       if constexpr (BIG) {
-        const double2 t = x1_s[i], u = x2_s[i], w = x2_s[NMAX + i];
-        return cmul(tau, make_double2(t.x + u.x + w.x, t.y + u.y + w.y));
+        double2 t = x1_s[i];
+#pragma unroll
+        for (int h = 0; h < HALVES; ++h) {
+          const double2 u = x2_s[h * NMAX + i];
+          t.x += u.x;
+          t.y += u.y;
+        }
+        return cmul(tau, t);
       } else {
         return w_s[i];
       }
@@ -1175,6 +1184,38 @@ __global__ __launch_bounds__(512) void eigh_tridiag_dc_kernel(int n, int lda,
   if (tid == 0) {
     d_s[n - 1] = pel(n - 1, n - 1).x;
     e_s[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += NT) {
+    dg[i] = d_s[i];
+    Wg[i] = e_s[i];
+  }
+}
+
+// eigh_dc_kernel: stage 2 (divide and conquer on the tridiagonal d, e left by
+// eigh_tridiag_kernel), 512 threads per matrix.  NMAX = 128: Z in LDS, leaves at depth 3.
+// NMAX = 256: Z in the workspace, leaves at depth 4.
+template <int NMAX>
+__global__ __launch_bounds__(512) void eigh_dc_kernel(int n, double *ws) {
+  constexpr bool BIG = NMAX > 128;
+  constexpr int LD = BIG ? 4 : 3;               // depth of the leaves
+  extern __shared__ double2 smem[];
+  __shared__ double d_s[NMAX], e_s[NMAX];
+  // phase-local scratch: leaf matrices (leaves), merge arrays
+  __shared__ __attribute__((aligned(16))) double sbuf[13 * NMAX];
+  const int prob = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int nw = 8;
+  double *base = ws + (size_t)prob * tql_ws_doubles(n);
+  double2 *hh = reinterpret_cast<double2 *>(base);
+  double2 *tau_g = hh + (size_t)n * n;
+  double *Zg = reinterpret_cast<double *>(tau_g + n);
+  double *dg = Zg + (size_t)n * n;
+  double *Wg = dg + n;
+  double2 *Pg = reinterpret_cast<double2 *>(Wg + (size_t)n * n);
+  for (int i = tid; i < n; i += 512) {
+    d_s[i] = dg[i];
+    e_s[i] = Wg[i];
   }
   __syncthreads();
 
@@ -1981,7 +2022,9 @@ class HipBackend : public Backend {
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
     HIPCHK(hipFuncSetAttribute((const void *)gram_chol_lds_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
-    HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_dc_kernel<128>,
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_kernel<128, 1024>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
+    HIPCHK(hipFuncSetAttribute((const void *)eigh_dc_kernel<128>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
   }
   ~HipBackend() override {
@@ -2231,16 +2274,22 @@ class HipBackend : public Backend {
         }
         lws_bytes_ = need;
       }
-      stale_check("eigh_tridiag_dc_kernel");
+      stale_check("eigh_tridiag_kernel");
       if (n <= 128) {
-        size_t sm = std::max((size_t)n * (n + 1) / 2 * sizeof(double2), (size_t)n * n * sizeof(double));
-        hipLaunchKernelGGL(eigh_tridiag_dc_kernel<128>, dim3(nprob), dim3(512), sm, s_, n, lda,
-                           in, (double *)lws_);
+        hipLaunchKernelGGL((eigh_tridiag_kernel<128, 1024>), dim3(nprob), dim3(1024),
+                           (size_t)n * (n + 1) / 2 * sizeof(double2), s_, n, lda, in,
+                           (double *)lws_);
+        launch_check("eigh_tridiag_kernel");
+        hipLaunchKernelGGL(eigh_dc_kernel<128>, dim3(nprob), dim3(512),
+                           (size_t)n * n * sizeof(double), s_, n, (double *)lws_);
       } else {
-        hipLaunchKernelGGL(eigh_tridiag_dc_kernel<256>, dim3(nprob), dim3(512), 0, s_, n, lda,
-                           in, (double *)lws_);
+        hipLaunchKernelGGL((eigh_tridiag_kernel<256, 1024>), dim3(nprob), dim3(1024), 0, s_, n,
+                           lda, in, (double *)lws_);
+        launch_check("eigh_tridiag_kernel");
+        hipLaunchKernelGGL(eigh_dc_kernel<256>, dim3(nprob), dim3(512), 0, s_, n,
+                           (double *)lws_);
       }
-      launch_check("eigh_tridiag_dc_kernel");
+      launch_check("eigh_dc_kernel");
       stale_check("eigh_backtransform_kernel");
       if (n <= 128)
         hipLaunchKernelGGL(eigh_backtransform_kernel<128>, dim3((n + 15) / 16, nprob), dim3(256),
