@@ -1852,10 +1852,10 @@ __device__ double block_sum(double v, double *sh) {
   return r;   // valid on thread 0
 }
 
-__global__ __launch_bounds__(256) void normalize_residual_kernel(int chi, double *const *Mn,
+__global__ __launch_bounds__(1024) void normalize_residual_kernel(int chi, double *const *Mn,
                                                                  const double *const *Mo,
                                                                  double *res) {
-  __shared__ double sh[8];
+  __shared__ double sh[16];
   __shared__ double trr, tri;
   const int p = blockIdx.x;
   double2 *m = reinterpret_cast<double2 *>(Mn[p]);
@@ -1866,8 +1866,8 @@ __global__ __launch_bounds__(256) void normalize_residual_kernel(int chi, double
     tr += v.x;
     ti += v.y;
   }
-  double a = block_sum<256>(tr, sh);
-  double b = block_sum<256>(ti, sh);
+  double a = block_sum<1024>(tr, sh);
+  double b = block_sum<1024>(ti, sh);
   if (threadIdx.x == 0) { trr = a; tri = b; }
   __syncthreads();
   double den = trr * trr + tri * tri;
@@ -1882,7 +1882,7 @@ __global__ __launch_bounds__(256) void normalize_residual_kernel(int chi, double
     double dx = w.x - q.x, dy = w.y - q.y;
     acc += dx * dx + dy * dy;
   }
-  double s = block_sum<256>(acc, sh);
+  double s = block_sum<1024>(acc, sh);
   if (threadIdx.x == 0) res[p] = (trr > 0 && isfinite(s)) ? sqrt(s) : INFINITY;
 }
 
@@ -2148,13 +2148,13 @@ class HipBackend : public Backend {
       }
       return;
     }
-    // split K when the output alone cannot fill the machine: as many chunks as keep the grid
-    // within one round of resident workgroups (two per CU; a partial second round measured
-    // slower than fewer, longer chunks)
+    // split K when the output alone cannot fill the machine: as many chunks (of at least 32) as
+    // keep the grid within one round of resident workgroups (two per CU; a partial second round
+    // measured slower than fewer, longer chunks)
     int blocks = tiles * d.batch * nprob;
     int ksplit = 1, kchunk = d.K;
-    if (blocks < resident_ && d.K >= 512) {
-      int want = std::min(resident_ / blocks, d.K / 256);
+    if (blocks < resident_ && d.K >= 128) {
+      int want = std::min(resident_ / blocks, d.K / 32);
       if (want > 1) {
         kchunk = ((d.K + want - 1) / want + BK - 1) / BK * BK;
         ksplit = (d.K + kchunk - 1) / kchunk;
@@ -2378,7 +2378,7 @@ class HipBackend : public Backend {
   void normalize_residual(int chi, double *const *Mn, const double *const *Mo, double *res,
                           int nprob) override {
     stale_check("normalize_residual_kernel");
-    hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(256), 0, s_, chi, Mn, Mo,
+    hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(1024), 0, s_, chi, Mn, Mo,
                        res);
     launch_check("normalize_residual_kernel");
   }
