@@ -753,26 +753,36 @@ __device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, d
       r += (w < v) || (w == v && u < t);
     }
     S.perm[r] = t;
-    S.zK[r] = S.z[t];      // sorted copies for the scan
+    S.zK[r] = S.z[t];      // sorted copies for the scan (dK is free until the gather below)
+    S.dK[r] = v;
   }
   __syncthreads();
-  // deflation scan in ascending order (one thread)
+  // deflation scan in ascending order (one thread).  The last kept entry's d and z live in
+  // registers and the sorted copies are read one entry ahead, so no iteration waits on a load
+  // that depends on the previous one.
   if (tid == 0) {
     int nk = 0, nd = 0, nr = 0, prev = -1;
+    double zp = 0.0, dp = 0.0;
+    int tn = S.perm[0];
+    double zn = S.zK[0], dn = S.dK[0];
     for (int r = 0; r < s; ++r) {
-      const int t = S.perm[r];
-      const double zt = S.zK[r];
+      const int t = tn;
+      const double zt = zn, dt = dn;
+      if (r + 1 < s) {
+        tn = S.perm[r + 1];
+        zn = S.zK[r + 1];
+        dn = S.dK[r + 1];
+      }
       if (rho * fabs(zt) <= tol) {
         S.defl[nd++] = t;
         continue;
       }
-      if (prev >= 0 && fabs(S.dd[t] - S.dd[prev]) <= tol) {
-        const double zp = S.z[prev];
+      if (prev >= 0 && fabs(dt - dp) <= tol) {
         const double rr = sqrt(zp * zp + zt * zt);
         const double c = zt / rr, sn = zp / rr;
-        const double dp = S.dd[prev], dt = S.dd[t];
+        const double dtn = sn * sn * dp + c * c * dt;
         S.dd[prev] = c * c * dp + sn * sn * dt;
-        S.dd[t] = sn * sn * dp + c * c * dt;
+        S.dd[t] = dtn;
         S.z[prev] = 0.0;
         S.z[t] = rr;
         S.ra[nr] = prev;
@@ -782,10 +792,14 @@ __device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, d
         ++nr;
         S.defl[nd++] = prev;
         prev = t;
+        zp = rr;
+        dp = dtn;
         continue;
       }
       if (prev >= 0) S.K[nk++] = prev;
       prev = t;
+      zp = zt;
+      dp = dt;
     }
     if (prev >= 0) S.K[nk++] = prev;
     S.cnt[0] = nk;
