@@ -27,6 +27,11 @@ What it computes (arXiv 2306.14887, Tindall, Fishman, Stoudenmire, Sels):
 * Single-site expectation values use the rank-one BP environment (Eq. "SingleSIte");
   Pauli strings on a cluster whose induced subgraph is a tree are contracted exactly
   inside the cluster with BP messages on the cut legs.
+* Bond entanglement entropy (Eq. "EntanglementEntropy"): the Schmidt weights of an edge
+  are the spectrum of the two messages that meet on it (Network.bond_spectrum).
+* The infinite lattice ("Dynamics of the infinite heavy-hex lattice", Fig. 4) is its
+  periodic unit cell given as a graph: BP on the 5-site quotient graph is BP on the
+  infinite lattice with translation-invariant messages, so nothing here is specific to it.
 
 Readings where the paper is silent (all mirrored by the HIP path):
   message normalisation: unit trace; singular values: unit 2-norm;
@@ -37,7 +42,9 @@ Readings where the paper is silent (all mirrored by the HIP path):
   colour, then X rotations by -pi/2;
   truncation: keep min(chi, #{sigma_i > eps_svd * sigma_1}) singular values;
   message square roots: eigenvalues clipped at 0; inverse square roots keep eigenvalues
-  > eps_eig * lambda_max; gate layers: ascending colour of a proper edge colouring.
+  > eps_eig * lambda_max; gate layers: ascending colour of a proper edge colouring;
+  entropy: s = -sum_i p_i log2 p_i with the minus sign the printed formula lacks, over the
+  chi weights of one bond (not chi^2), normalised to sum 1.
 
 Conventions: the legs of the tensor of site v are (physical, then neighbours in
 ascending site id).  A message M[a_ket, a_bra] carries the ket index first.
@@ -341,6 +348,31 @@ class Network:
 
         return float((value(True) / value(False)).real)
 
+    def bond_spectrum(self, v: int, w: int) -> np.ndarray:
+        """Schmidt weights p_i = lambda_i^2 of the bond (v, w) under the BP approximation,
+        descending, unit sum (the bond tensor spectrum of Eq. "EntanglementEntropy").
+
+        Cutting the edge splits the BP-contracted norm into the two messages that meet on it:
+        <psi|psi> = sum_{a,a'} M_{v->w}[a, a'] M_{w->v}[a, a'] = Tr(M_{v->w} M_{w->v}^T), and in
+        the Vidal gauge both messages are the diagonal bond matrix, so the squared bond
+        weights are the eigenvalues of M_{v->w} M_{w->v}^T (real and >= 0 for the positive
+        semidefinite messages: rounding below zero is clipped).  Exact on a tree without
+        truncation.
+        """
+        P = self.M[(v, w)] @ self.M[(w, v)].T
+        lam = np.clip(np.linalg.eigvals(P).real, 0.0, None)
+        s = lam.sum()
+        if not s > 0.0:
+            raise FloatingPointError(f"bond ({v}, {w}): zero norm")
+        return np.sort(lam / s)[::-1]
+
+    def bond_entropy(self, v: int, w: int) -> float:
+        """s = -sum_i p_i log2 p_i over the Schmidt weights of the bond (Eq.
+        "EntanglementEntropy", read with the minus sign and the sum over the chi weights)."""
+        p = self.bond_spectrum(v, w)
+        p = p[p > 0.0]
+        return float(-np.sum(p * np.log2(p)))
+
 
 @dataclass
 class Result:
@@ -350,11 +382,12 @@ class Result:
     bp_residual: list = field(default_factory=list)
     discarded: list = field(default_factory=list)
     converged: bool = True
+    entropy: np.ndarray | None = None   # [rows, n_edges] bond entropies (bits) when asked for
 
 
 def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
           pauli=(), record_every_step: bool = True, net: Network | None = None,
-          clifford_steps: int = 0) -> Result:
+          clifford_steps: int = 0, entropy: bool = False) -> Result:
     """Run ``depth`` Floquet steps and measure (Eq. "State"; Methods).
 
     Each step: exact X rotations, then the simple-update gate layers in ascending
@@ -364,6 +397,8 @@ def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
     the gates exp(-i pi/4 ZZ) first (descending colour, the forward order mirrored), then the
     X rotations by -pi/2; BP and <Z_v> follow as after a forward step.
     ``pauli`` is a sequence of (sites, ops) evaluated after the final step.
+    ``entropy``: also record the bond entropy of every edge (``Network.bond_entropy``) on
+    the same steps as <Z_v>.
     """
     if net is None:
         net = Network(n_sites, edges, colour)
@@ -371,7 +406,7 @@ def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
     inv = Options(chi=opt.chi, bp_tol=opt.bp_tol, bp_max_iter=opt.bp_max_iter,
                   svd_cutoff=opt.svd_cutoff, eig_cutoff=opt.eig_cutoff, zz_sign=-opt.zz_sign)
     steps = depth + clifford_steps
-    zs, iters, resid, disc = [], [], [], []
+    zs, iters, resid, disc, ents = [], [], [], [], []
     converged = True
     for _t in range(steps):
         dsum = 0.0
@@ -394,7 +429,11 @@ def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
         disc.append(dsum)
         if record_every_step or _t == steps - 1:
             zs.append([net.expect_site(v, 3) for v in range(net.n)])
+            if entropy:
+                ents.append([net.bond_entropy(u, v) for u, v in net.edges])
     if steps == 0:
         zs.append([1.0] * net.n)
+        ents.append([0.0] * len(net.edges))
     pv = np.array([net.expect_pauli(s, o) for s, o in pauli], dtype=float)
-    return Result(np.array(zs, dtype=float), pv, iters, resid, disc, converged)
+    return Result(np.array(zs, dtype=float), pv, iters, resid, disc, converged,
+                  np.array(ents, dtype=float) if entropy else None)

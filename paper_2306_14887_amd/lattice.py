@@ -185,6 +185,61 @@ def path(n: int) -> Lattice:
 
 
 # ---------------------------------------------------------------------------
+# The infinite heavy-hex lattice: periodic cells
+# ---------------------------------------------------------------------------
+
+# Sites of one cell: the two degree-3 sites A, B of the underlying hexagonal lattice and one
+# bridge C_d on each of its three bond directions d.
+CELL_SITES = ("A", "B", "C0", "C1", "C2")
+# Bridge C_d of cell r joins A(r) to B(r + shift[d]) (hexagonal lattice in brick-wall form).
+_CELL_SHIFT = ((0, 0), (1, 0), (0, 1))
+
+
+def heavy_hex_torus(l1: int, l2: int, derangement=(1, 2, 0)) -> Lattice:
+    """Periodic heavy-hex lattice of l1 x l2 cells (5 sites, 6 edges per cell).
+
+    Site 5 * (x * l2 + y) + k is CELL_SITES[k] of cell (x, y).  Edge A(r)-C_d(r) has colour d
+    and edge C_d(r)-B(r + shift_d) colour derangement[d]: every site then sees distinct
+    colours (the A legs by construction, the B legs because ``derangement`` is a bijection,
+    the bridges because it has no fixed point), and the colouring is the same in every cell,
+    so the gate layers commute with translations.  With l1 = l2 = 1 this is the paper's
+    5-site unit cell ("Dynamics of the infinite heavy-hex lattice", Fig. 4): the quotient
+    graph of the infinite lattice, a theta graph (A and B joined through the three bridges).
+    BP on a quotient graph is BP on the infinite lattice restricted to translation-invariant
+    messages, and a gate layer on it is the layer on every translate at once.
+    """
+    if l1 < 1 or l2 < 1:
+        raise ValueError("need at least one cell in each direction")
+    dr = tuple(int(c) for c in derangement)
+    if sorted(dr) != [0, 1, 2] or any(dr[d] == d for d in range(3)):
+        raise ValueError("derangement must be a fixed-point-free permutation of (0, 1, 2)")
+
+    def site(x: int, y: int, k: int) -> int:
+        return 5 * ((x % l1) * l2 + (y % l2)) + k
+
+    edges, colour = [], []
+    coords = {}
+    for x in range(l1):
+        for y in range(l2):
+            for k in range(5):
+                coords[site(x, y, k)] = (x, y, CELL_SITES[k])
+            for d in range(3):
+                sx, sy = _CELL_SHIFT[d]
+                edges.append((site(x, y, 0), site(x, y, 2 + d)))
+                colour.append(d)
+                edges.append((site(x, y, 2 + d), site(x + sx, y + sy, 1)))
+                colour.append(dr[d])
+    name = "hhx_cell5" if l1 == l2 == 1 else f"hhx_torus{l1}x{l2}"
+    return Lattice(5 * l1 * l2, np.array(edges, dtype=np.int32),
+                   np.array(colour, dtype=np.int32), name=name, coords=coords)
+
+
+def infinite_cell(derangement=(1, 2, 0)) -> Lattice:
+    """The 5-site periodic unit cell of the infinite heavy-hex lattice (sites A, B, C0..C2)."""
+    return heavy_hex_torus(1, 1, derangement)
+
+
+# ---------------------------------------------------------------------------
 # Pauli strings on connected clusters
 # ---------------------------------------------------------------------------
 

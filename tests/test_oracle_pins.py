@@ -278,3 +278,145 @@ def test_oracle_extended_evolution_exact_on_a_tree():
         ref.append(sv.expect_z())
     assert res.z.shape == (5, tr.n_sites)
     assert np.abs(res.z - np.array(ref)).max() < 1e-11
+
+
+# --- bond entanglement entropy and the infinite lattice --------------------------------------
+
+def _schmidt_weights(psi, n, left):
+    """Squared singular values of the state vector across the cut (left sites | the rest)."""
+    L = sorted(left)
+    R = [q for q in range(n) if q not in left]
+    m = np.transpose(psi.reshape((2,) * n), L + R).reshape(2 ** len(L), -1)
+    return np.sort(np.linalg.svd(m, compute_uv=False) ** 2)[::-1]
+
+
+def _side(n, edges, e):
+    """Sites on the first endpoint's side of edge e of a tree (or of a tree-like ball)."""
+    u, v = (int(x) for x in edges[e])
+    nb = [[] for _ in range(n)]
+    for k, (a, b) in enumerate(np.asarray(edges).tolist()):
+        if k != e:
+            nb[a].append(b)
+            nb[b].append(a)
+    seen, st = {u}, [u]
+    while st:
+        x = st.pop()
+        for y in nb[x]:
+            if y not in seen:
+                seen.add(y)
+                st.append(y)
+    assert v not in seen
+    return seen
+
+
+def _pad_cmp(p, q):
+    k = max(len(p), len(q))
+    return np.abs(np.pad(p, (0, k - len(p))) - np.pad(q, (0, k - len(q)))).max()
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_bond_spectrum_exact_on_trees(seed):
+    """On a tree without truncation the BP bond spectrum is the Schmidt spectrum of the state
+    across the edge, at every step (entropies) and in full (final step)."""
+    rng = np.random.default_rng(seed)
+    tr = L.random_tree(10, rng)
+    th = float(rng.uniform(0.2, 1.4))
+    net = O.Network(tr.n_sites, tr.edges, tr.colour)
+    r = O.solve(tr.n_sites, tr.edges, tr.colour, th, 3, O.Options(chi=16), net=net, entropy=True)
+    sv = SV.StateVector(tr.n_sites, tr.edges)
+    for t in range(3):
+        sv.step(th)
+        for e in range(tr.n_edges):
+            p = _schmidt_weights(sv.psi, tr.n_sites, _side(tr.n_sites, tr.edges, e))
+            p = p[p > 0]
+            assert abs(r.entropy[t, e] - float(-np.sum(p * np.log2(p)))) < 1e-10, (t, e)
+    wants = [_schmidt_weights(sv.psi, tr.n_sites, _side(tr.n_sites, tr.edges, e))
+             for e in range(tr.n_edges)]
+    for e, (u, v) in enumerate(tr.edges.tolist()):
+        assert _pad_cmp(net.bond_spectrum(u, v), wants[e]) < 1e-12
+        assert _pad_cmp(net.bond_spectrum(v, u), wants[e]) < 1e-12
+    # the spectrum is gauge invariant: insert G G^-1 (random, complex) on every bond, let BP
+    # find the new messages (complex Hermitian now, no longer diagonal) and compare again
+    for u, v in tr.edges.tolist():
+        d = net.bond_dim(u, v)
+        G = np.eye(d) + 0.3 * (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+        net.T[u] = O.absorb(net.T[u], net.axis(u, v), G)
+        net.T[v] = O.absorb(net.T[v], net.axis(v, u), np.linalg.inv(G).T)
+    for key, m in net.M.items():
+        net.M[key] = np.eye(m.shape[0], dtype=complex) / m.shape[0]
+    net.bp(1e-13, 200)
+    assert max(np.abs(m - np.diag(np.diag(m))).max() for m in net.M.values()) > 1e-3
+    for e, (u, v) in enumerate(tr.edges.tolist()):
+        assert _pad_cmp(net.bond_spectrum(u, v), wants[e]) < 1e-11
+
+
+def test_bond_entropy_closed_forms():
+    """A product state has zero entropy on every bond; at the Clifford point one step makes
+    each bond of a 2-site chain a maximally entangled pair (1 bit)."""
+    e = L.eagle()
+    r = O.solve(e.n_sites, e.edges, e.colour, 0.0, 2, O.Options(chi=4), entropy=True)
+    assert np.abs(r.entropy).max() < 1e-12
+    pth = L.path(2)
+    r = O.solve(2, pth.edges, pth.colour, math.pi / 2, 1, O.Options(chi=4), entropy=True)
+    assert abs(r.entropy[0, 0] - 1.0) < 1e-12
+
+
+def test_infinite_cell_exact_while_light_cone_is_a_tree():
+    """BP on the 5-site periodic cell gives the exact infinite-lattice <Z> as long as the
+    backward light cone (radius t-1) is a tree of the infinite lattice (t <= 6) and chi does
+    not truncate: compared with the state vector of that ball cut out of a 4 x 4 torus."""
+    cell = L.infinite_cell()
+    th = 0.83
+    r = _solve(cell, th, 4, 16)
+    big = L.heavy_hex_torus(4, 4)
+    for t in range(1, 5):
+        want = [SV.light_cone_z(big.n_sites, big.edges, k, th, t) for k in range(5)]
+        assert np.abs(r.z[t - 1] - want).max() < 1e-11, t
+    # cell symmetry: A ~ B and the three bridges
+    assert np.abs(r.z[:, 0] - r.z[:, 1]).max() < 1e-11
+    assert np.abs(r.z[:, 2:] - r.z[:, 2:3]).max() < 1e-11
+
+
+def test_infinite_cell_bond_spectrum_vs_light_cone():
+    """The cell's BP bond spectrum equals the exact Schmidt spectrum across the edge on the
+    infinite lattice, computed from the ball of radius t-1 around the edge (a tree)."""
+    cell = L.infinite_cell()
+    th = 0.61
+    net = O.Network(cell.n_sites, cell.edges, cell.colour)
+    O.solve(cell.n_sites, cell.edges, cell.colour, th, 3, O.Options(chi=8), net=net)
+    big = L.heavy_hex_torus(4, 4)
+    for e in range(cell.n_edges):           # edge e of cell (0, 0) is edge e of the torus
+        u, v = (int(x) for x in big.edges[e])
+        sub = sorted(set(SV.ball(big.n_sites, big.edges, u, 2)) |
+                     set(SV.ball(big.n_sites, big.edges, v, 2)))
+        idx = {q: i for i, q in enumerate(sub)}
+        es = [(idx[a], idx[b]) for a, b in big.edges.tolist() if a in idx and b in idx]
+        assert len(es) == len(sub) - 1                      # a tree
+        sv = SV.StateVector(len(sub), np.array(es))
+        for _ in range(3):
+            sv.step(th)
+        e_sub = es.index((idx[u], idx[v]))
+        want = _schmidt_weights(sv.psi, len(sub), _side(len(sub), np.array(es), e_sub))
+        cu, cv = (int(x) for x in cell.edges[e])
+        assert _pad_cmp(net.bond_spectrum(cu, cv), want) < 1e-12, e
+
+
+def test_infinite_cell_equals_its_supercell_with_truncation():
+    """A 2 x 2 supercell covers the cell: with truncation (chi = 4) and BP to tolerance, every
+    copy of a cell site has the cell's <Z> and every copy of a cell edge the cell's entropy."""
+    cell, sup = L.infinite_cell(), L.heavy_hex_torus(2, 2)
+    th = 0.9
+    rc = O.solve(cell.n_sites, cell.edges, cell.colour, th, 5, O.Options(chi=4), entropy=True)
+    rs = O.solve(sup.n_sites, sup.edges, sup.colour, th, 5, O.Options(chi=4), entropy=True)
+    assert max(rc.discarded) > 1e-6                         # truncation is active
+    for c in range(4):
+        assert np.abs(rs.z[:, 5 * c:5 * c + 5] - rc.z).max() < 1e-10
+        assert np.abs(rs.entropy[:, 6 * c:6 * c + 6] - rc.entropy).max() < 1e-10
+
+
+def test_infinite_cell_colourings_agree_untruncated():
+    """The two derangements colour the bridges' B legs differently; without truncation the
+    state is the same, so <Z> agrees to rounding."""
+    a = _solve(L.infinite_cell((1, 2, 0)), 0.7, 4, 16)
+    b = _solve(L.infinite_cell((2, 0, 1)), 0.7, 4, 16)
+    assert np.abs(a.z - b.z).max() < 1e-11
