@@ -19,6 +19,10 @@
  *     ascending colour.  NULL asks the library for the greedy colouring over the edge list sorted by
  *     (min, max) endpoint (smallest colour free at both ends).
  *   - Pauli ops: 1 = X, 2 = Y, 3 = Z.  A string's sites must induce a tree in the lattice.
+ *   - A periodic lattice is passed as its quotient graph (one cell with the periodic edges
+ *     closed on itself; it must stay a simple graph): BP on it is BP on the infinite lattice with
+ *     translation-invariant messages ("Dynamics of the infinite heavy-hex lattice", Fig. 4: the
+ *     5-site heavy-hex cell is a theta graph, two degree-3 sites joined through three bridges).
  *   - All observables are real doubles.
  *
  * Return codes
@@ -92,6 +96,14 @@ typedef struct {
   int32_t *bp_iters;    /* optional [S]: BP sweeps run after each step                          */
   double *bp_residual;  /* optional [S]: final BP residual of each step                         */
   double *discarded;    /* optional [S]: sum over the step's gates of the discarded weight      */
+  double *bond_entropy; /* optional [max(1, record_every_step ? S : 1) * n_edges]: on the steps
+                           z is recorded, the entanglement entropy of every edge in bits,
+                           s_e = -sum_i p_i log2 p_i (Eq. "EntanglementEntropy", read with the
+                           minus sign and the sum over the chi weights of one bond), where the
+                           Schmidt weights p_i are the eigenvalues of M_{u->v}^{1/2} M_{v->u}^T
+                           M_{u->v}^{1/2} normalised to unit sum (the BP norm across the edge is
+                           Tr(M_{u->v} M_{v->u}^T)); exact on trees without truncation.  FP64
+                           in every precision mode.  S = 0 gives one row of zeros.           */
 } bpki_result;
 
 /* Fill *p with the defaults (tolerances 1e-12, 1000 sweeps, FP64, record every step). */
@@ -186,6 +198,9 @@ int bpki_session_apply_layer(bpki_session *s, int32_t colour, double *discarded)
 int bpki_session_bp(bpki_session *s, int32_t max_iter, int32_t *iters, double *residual);
 int bpki_session_bp_sweep(bpki_session *s, double *residual);
 int bpki_session_observe_z(bpki_session *s, double *z);
+/* entropy [n_edges] (host): bond entropies of the current state and messages, as
+ * bpki_result.bond_entropy. */
+int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy);
 int bpki_session_observe_pauli(bpki_session *s, double *pauli);
 /* One whole Floquet step: X rotations, all gate layers, BP, then z (may be NULL). */
 int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residual,

@@ -41,7 +41,7 @@ class _Result(C.Structure):
     _fields_ = [
         ("z", C.POINTER(C.c_double)), ("pauli", C.POINTER(C.c_double)),
         ("bp_iters", C.POINTER(C.c_int32)), ("bp_residual", C.POINTER(C.c_double)),
-        ("discarded", C.POINTER(C.c_double)),
+        ("discarded", C.POINTER(C.c_double)), ("bond_entropy", C.POINTER(C.c_double)),
     ]
 
 
@@ -96,6 +96,7 @@ def load(path: str | None = None):
         "bpki_session_bp": (C.c_int, [vp, C.c_int32, ip, dp]),
         "bpki_session_bp_sweep": (C.c_int, [vp, dp]),
         "bpki_session_observe_z": (C.c_int, [vp, dp]),
+        "bpki_session_observe_bond_entropy": (C.c_int, [vp, dp]),
         "bpki_session_observe_pauli": (C.c_int, [vp, dp]),
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_clifford_inverse_step": (C.c_int, [vp, dp, ip, dp, dp]),
@@ -126,7 +127,8 @@ def exported_symbols() -> list[str]:
             "bpki_session_open", "bpki_session_close",
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
-            "bpki_session_bp_sweep", "bpki_session_observe_z", "bpki_session_observe_pauli",
+            "bpki_session_bp_sweep", "bpki_session_observe_z",
+            "bpki_session_observe_bond_entropy", "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_clifford_inverse_step",
             "bpki_session_last_timing", "bpki_session_profile",
             "bpki_session_profile_read", "bpki_test_gemm",
@@ -160,6 +162,7 @@ class ProblemSpec:
     pauli: tuple = ()
     record_every_step: bool = True
     clifford_steps: int = 0         # steps of U(pi/2)^dagger after the depth steps
+    bond_entropy: bool = False      # also return the entropy of every edge (result side)
 
     def to_c(self):
         keep = {}
@@ -317,6 +320,8 @@ def _alloc_result(spec: ProblemSpec) -> dict:
         "bp_iters": np.zeros(max(steps, 1), dtype=np.int32),
         "bp_residual": np.zeros(max(steps, 1)),
         "discarded": np.zeros(max(steps, 1)),
+        "bond_entropy": (np.full((max(rows, 1), int(np.asarray(spec.edges).size // 2)), np.nan)
+                         if spec.bond_entropy else None),
     }
 
 
@@ -327,6 +332,8 @@ def _result_struct(out: dict) -> _Result:
     r.bp_iters = _ptr(out["bp_iters"], C.c_int32)
     r.bp_residual = _ptr(out["bp_residual"], C.c_double)
     r.discarded = _ptr(out["discarded"], C.c_double)
+    if out.get("bond_entropy") is not None:
+        r.bond_entropy = _ptr(out["bond_entropy"], C.c_double)
     return r
 
 
@@ -428,6 +435,12 @@ class Session:
         z = np.zeros(self.spec.n_sites)
         _check(self.lib, self.lib.bpki_session_observe_z(self.h, _ptr(z, C.c_double)))
         return z
+
+    def observe_bond_entropy(self) -> np.ndarray:
+        """Entropy (bits) of the Schmidt weights of every edge, in edge order."""
+        e = np.zeros(int(np.asarray(self.spec.edges).size // 2))
+        _check(self.lib, self.lib.bpki_session_observe_bond_entropy(self.h, _ptr(e, C.c_double)))
+        return e
 
     def observe_pauli(self) -> np.ndarray:
         out = np.zeros(len(self.spec.pauli))

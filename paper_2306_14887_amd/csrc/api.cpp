@@ -264,6 +264,8 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
   const int steps = q.depth + q.clifford_steps;
   const int rows = std::max(1, q.record_every_step ? steps : 1);
   std::vector<double> z((size_t)rows * n, 1.0);
+  const int ne = (int)q.edges.size() / 2;
+  std::vector<double> ent(r->bond_entropy ? (size_t)rows * ne : 0, 0.0);
   std::vector<int32_t> iters(steps, 0);
   std::vector<double> res(steps, 0.0), disc(steps, 0.0);
   const std::vector<int> cols = sorted_colours(q);
@@ -285,6 +287,7 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
     if (q.record_every_step || t == steps - 1) {
       int row = q.record_every_step ? t : 0;
       eng.observe_z(&z[(size_t)row * n]);
+      if (!ent.empty()) eng.observe_entropy(&ent[(size_t)row * ne]);
     }
     std::string msg;
     int e = be->check(&msg);
@@ -297,7 +300,10 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
   if (e) return fail(e, "device error: " + msg);
   for (double x : z)
     if (!std::isfinite(x)) return fail(-5, "non-finite observable (numerical breakdown)");
+  for (double x : ent)
+    if (!std::isfinite(x)) return fail(-5, "non-finite bond entropy (numerical breakdown)");
   if (r->z) std::memcpy(r->z, z.data(), (size_t)rows * n * sizeof(double));
+  if (!ent.empty()) std::memcpy(r->bond_entropy, ent.data(), ent.size() * sizeof(double));
   if (r->pauli && !pv.empty()) std::memcpy(r->pauli, pv.data(), pv.size() * sizeof(double));
   if (r->bp_iters) std::memcpy(r->bp_iters, iters.data(), iters.size() * sizeof(int32_t));
   if (r->bp_residual) std::memcpy(r->bp_residual, res.data(), res.size() * sizeof(double));
@@ -427,6 +433,12 @@ extern "C" int bpki_session_bp_sweep(bpki_session *s, double *res) {
 extern "C" int bpki_session_observe_z(bpki_session *s, double *z) {
   if (!s || !z) return fail(-1, "NULL argument");
   s->eng->observe_z(z);
+  return sess_check(s);
+}
+
+extern "C" int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy) {
+  if (!s || !entropy) return fail(-1, "NULL argument");
+  s->eng->observe_entropy(entropy);
   return sess_check(s);
 }
 
@@ -613,29 +625,35 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
                      const std::vector<int> &pauli0) {
   const int R = (int)jobs.size();
   struct Acc {
-    std::vector<double> z, res, disc;
+    std::vector<double> z, ent, res, disc;
     std::vector<int32_t> iters;
     int warn = 0;
     bool fin = false;
   };
   std::vector<Acc> acc(R);
-  std::vector<int> edge_member(U.edges.size() / 2);
+  std::vector<int> edge_member(U.edges.size() / 2), edge0(R + 1, 0);
+  bool any_ent = false;
   for (int j = 0, e0 = 0; j < R; ++j) {
     const Problem &q = jobs[j]->q;
     const int rows = std::max(1, q.record_every_step ? q.depth : 1);
     acc[j].z.assign((size_t)rows * q.n_sites, 1.0);
+    if (jobs[j]->r->bond_entropy) {
+      acc[j].ent.assign((size_t)rows * (q.edges.size() / 2), 0.0);
+      any_ent = true;
+    }
     acc[j].iters.assign(q.depth, 0);
     acc[j].res.assign(q.depth, 0.0);
     acc[j].disc.assign(q.depth, 0.0);
     const int ne = (int)q.edges.size() / 2;
     for (int e = 0; e < ne; ++e) edge_member[e0 + e] = j;
     e0 += ne;
+    edge0[j + 1] = e0;
   }
   std::vector<int> cols(U.colour.begin(), U.colour.end());
   std::sort(cols.begin(), cols.end());
   cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
   std::vector<int> sweeps(R);
-  std::vector<double> rr(R), zall(U.n_sites), dj(R);
+  std::vector<double> rr(R), zall(U.n_sites), dj(R), eall(any_ent ? U.edges.size() / 2 : 0);
   auto fin = [&](int j, int status) {
     acc[j].fin = true;
     finish_job(c, jobs[j], status);
@@ -655,12 +673,16 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
       for (auto &ed : eng.layer_discarded()) dj[edge_member[ed.first]] += ed.second;
     }
     eng.bp_members(U.bp_max_iter, sweeps.data(), rr.data());
-    bool need_z = false;
+    bool need_z = false, need_e = false;
     for (int j = 0; j < R; ++j) {
       const Problem &q = jobs[j]->q;
-      if (!acc[j].fin && t < q.depth && (q.record_every_step || t == q.depth - 1)) need_z = true;
+      if (!acc[j].fin && t < q.depth && (q.record_every_step || t == q.depth - 1)) {
+        need_z = true;
+        need_e = need_e || !acc[j].ent.empty();
+      }
     }
     if (need_z) eng.observe_z(zall.data());
+    if (need_e) eng.observe_entropy(eall.data());
     std::string msg;
     if (int e = be->check(&msg)) {
       for (int j = 0; j < R; ++j)
@@ -680,6 +702,11 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
         const int row = q.record_every_step ? t : 0;
         std::copy(zall.begin() + s0, zall.begin() + s0 + q.n_sites,
                   a.z.begin() + (size_t)row * q.n_sites);
+        if (!a.ent.empty()) {
+          const int ne = edge0[j + 1] - edge0[j];
+          std::copy(eall.begin() + edge0[j], eall.begin() + edge0[j + 1],
+                    a.ent.begin() + (size_t)row * ne);
+        }
       }
       if (t < q.depth - 1) continue;
       std::vector<double> pv(pauli0[j + 1] - pauli0[j], 0.0);
@@ -690,12 +717,14 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
       }
       bool finite = true;
       for (double x : a.z) finite = finite && std::isfinite(x);
+      for (double x : a.ent) finite = finite && std::isfinite(x);
       if (!finite) {
         fin(j, -5);
         continue;
       }
       bpki_result *r = jobs[j]->r;
       if (r->z) std::memcpy(r->z, a.z.data(), a.z.size() * sizeof(double));
+      if (!a.ent.empty()) std::memcpy(r->bond_entropy, a.ent.data(), a.ent.size() * sizeof(double));
       if (r->pauli && !pv.empty()) std::memcpy(r->pauli, pv.data(), pv.size() * sizeof(double));
       if (r->bp_iters) std::memcpy(r->bp_iters, a.iters.data(), a.iters.size() * sizeof(int32_t));
       if (r->bp_residual) std::memcpy(r->bp_residual, a.res.data(), a.res.size() * sizeof(double));

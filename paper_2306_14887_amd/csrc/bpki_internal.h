@@ -74,6 +74,9 @@ struct Backend {
   // X = W f(l) W^H with f = sqrt(max(l,0)) and Xp with f = 1/sqrt(l) for l > cut*l_max else 0.
   virtual void msg_sqrt(int n, const double *const *evals, const double *const *vecs,
                         double *const *X, double *const *Xp, double cut, int nprob) = 0;
+  // Entropy -sum p log2 p of the Schmidt weights p = max(evals, 0) / sum (n per problem); out
+  // [nprob] device, NaN for an all-zero spectrum.
+  virtual void bond_entropy(int n, const double *const *evals, double *out, int nprob) = 0;
   // Pivoted Cholesky factor of a Gram matrix G = A^H A (n x n, Hermitian PSD):
   // G[p][p] = L L^H for a pivot order p, stopping at the first pivot <= cut * max(diag G).
   // Writes R = L^H P^T (n x n, zero rows beyond the rank) and Wsc = P [L1^{-H}; 0] (n x n), so
@@ -159,6 +162,7 @@ class Engine {
   void observe_z(double *z);                      // host out [n_sites]
   void observe_pauli(double *out);                // host out [n_pauli]
   void observe_pauli_range(int k0, int k1, double *out);   // strings k0 .. k1-1
+  void observe_entropy(double *out);              // host out [n_edges]: bond entropies (bits)
   // Packed solves: sweeps until every member's residual is below bp_tol.  A member's messages
   // are frozen after the sweep that brought its own residual below the tolerance, so each member
   // follows its own BP schedule; per member: sweeps and final residual.

@@ -160,6 +160,10 @@ struct Plan {
   // observables
   std::vector<GemmOp> obs_ops;
   size_t obs_Y = 0, obs_T = 0;
+  // bond entropies: X = sqrt(M_{u->v}), Y = X M_{v->u}^T, B = Y X, eigenvalues of B
+  size_t ent_m = 0, ent_ev = 0, ent_vec = 0, ent_X = 0, ent_Y = 0, ent_B = 0;
+  GemmOp ent_xm, ent_b;
+  double *ent_out = nullptr;       // [E]
   int max_layer_edges = 0;
   std::vector<void *> allocs;
 };
@@ -673,11 +677,51 @@ void Engine::build() {
     layer_build(LP, nullptr, b, false);
     ws_max = std::max(ws_max, b.top);
   }
+  // the bond-entropy observable borrows the SU workspace (idle while observing)
+  Bump eb;
+  std::vector<size_t> e_ev(P.E), e_vec(P.E), e_X(P.E), e_Y(P.E), e_B(P.E);
+  for (int e = 0; e < P.E; ++e) {
+    e_ev[e] = eb.take(chi);
+    e_vec[e] = eb.take(c2);
+    e_X[e] = eb.take(c2);
+    e_Y[e] = eb.take(c2);
+    e_B[e] = eb.take(c2);
+  }
+  ws_max = std::max(ws_max, eb.top);
   P.ws_elems = ws_max;
   P.ws = (double *)A(ws_max * 16);
   for (auto &LP : P.layers) {
     Bump b;
     layer_build(LP, P.ws, b, true);
+  }
+  if (P.E) {
+    auto W = [&](size_t off) { return (const void *)(P.ws + 2 * off); };
+    std::vector<const void *> m, mt, ev, vec, X, Y, B;
+    for (int e = 0; e < P.E; ++e) {
+      m.push_back(Mp(2 * e));
+      mt.push_back(Mp(2 * e + 1));
+      ev.push_back(W(e_ev[e]));
+      vec.push_back(W(e_vec[e]));
+      X.push_back(W(e_X[e]));
+      Y.push_back(W(e_Y[e]));
+      B.push_back(W(e_B[e]));
+    }
+    P.ent_m = P.arena.add(m); P.ent_ev = P.arena.add(ev); P.ent_vec = P.arena.add(vec);
+    P.ent_X = P.arena.add(X); P.ent_Y = P.arena.add(Y); P.ent_B = P.arena.add(B);
+    GemmDesc d;
+    d.M = d.N = d.K = d.Mi = d.Ni = d.Ki = chi;
+    d.a_mi = chi; d.a_ki = 1;
+    d.b_ki = 1; d.b_ni = chi;          // B[k][n] = M_{v->u}[n][k]
+    d.c_mi = chi; d.c_ni = 1;
+    P.ent_xm.d = d;
+    P.ent_xm.n = P.E;
+    P.ent_xm.a = P.ent_X; P.ent_xm.b = P.arena.add(mt); P.ent_xm.c = P.ent_Y;
+    d.b_ki = chi; d.b_ni = 1;
+    d.herm = 1;                        // X M^T X with Hermitian X and M
+    P.ent_b.d = d;
+    P.ent_b.n = P.E;
+    P.ent_b.a = P.ent_Y; P.ent_b.b = P.ent_X; P.ent_b.c = P.ent_B;
+    P.ent_out = (double *)A((size_t)P.E * 8);
   }
 
   // ---- BP plan ----
@@ -1093,6 +1137,28 @@ void Engine::observe_z(double *z) {
     double den = dr * dr + di * di;
     z[v] = (nr * dr + ni * di) / den;
   }
+}
+
+// Bond entanglement entropy of every edge (Eq. "EntanglementEntropy"): with the BP norm across
+// the edge equal to Tr(M_{u->v} M_{v->u}^T), the Schmidt weights are the eigenvalues of the
+// Hermitian X M_{v->u}^T X, X = M_{u->v}^{1/2}, normalised to unit sum.  FP64 in every mode.
+void Engine::observe_entropy(double *out) {
+  Plan &P = *plan_;
+  if (!P.E) return;
+  const PtrArena &ar = P.arena;
+  const int chi = P.chi;
+  be_->eigh(chi, chi, ar.at<const double *const *>(P.ent_m), ar.at<double *const *>(P.ent_ev),
+            ar.at<double *const *>(P.ent_vec), P.E);
+  // the pseudo-inverse root lands in the Y buffer and is overwritten by the product below
+  be_->msg_sqrt(chi, ar.at<const double *const *>(P.ent_ev), ar.at<const double *const *>(P.ent_vec),
+                ar.at<double *const *>(P.ent_X), ar.at<double *const *>(P.ent_Y),
+                prob_.eig_cutoff, P.E);
+  run(be_, ar, P.ent_xm, 0);
+  run(be_, ar, P.ent_b, 0);
+  be_->eigh(chi, chi, ar.at<const double *const *>(P.ent_B), ar.at<double *const *>(P.ent_ev),
+            ar.at<double *const *>(P.ent_vec), P.E);
+  be_->bond_entropy(chi, ar.at<const double *const *>(P.ent_ev), P.ent_out, P.E);
+  be_->d2h(out, P.ent_out, (size_t)P.E * 8);
 }
 
 void Engine::observe_pauli(double *out) {

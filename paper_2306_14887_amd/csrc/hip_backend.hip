@@ -1900,6 +1900,29 @@ __global__ __launch_bounds__(1024) void normalize_residual_kernel(int chi, doubl
   if (threadIdx.x == 0) res[p] = (trr > 0 && isfinite(s)) ? sqrt(s) : INFINITY;
 }
 
+// Bond entanglement entropy (Eq. "EntanglementEntropy", with the minus sign and the sum over the
+// chi weights of one bond): the eigenvalues of the bond matrix X M^T X, clipped at zero and
+// normalised to unit sum, give the Schmidt weights p; s = -sum p log2 p.  One workgroup per bond.
+__global__ __launch_bounds__(256) void bond_entropy_kernel(int n, const double *const *evals,
+                                                           double *out) {
+  __shared__ double sh[4];
+  __shared__ double tot;
+  const double *l = evals[blockIdx.x];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += fmax(l[i], 0.0);
+  const double t = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) tot = t;
+  __syncthreads();
+  const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+  acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double q = fmax(l[i], 0.0) * inv;
+    if (q > 0.0) acc -= q * log2(q);
+  }
+  const double e = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot > 0.0 && isfinite(e) ? e : NAN;
+}
+
 __global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n, double *out) {
   __shared__ double sh[256];
   double m = 0;
@@ -2420,6 +2443,12 @@ class HipBackend : public Backend {
     release(out);
     const double flops = 2048.0 * 12 * (double)iters * (double)blocks * 4;
     return ms > 0.0f ? flops / (ms * 1e-3) / 1e12 : 0.0;
+  }
+  void bond_entropy(int n, const double *const *evals, double *out, int nprob) override {
+    if (nprob <= 0) return;
+    stale_check("bond_entropy_kernel");
+    hipLaunchKernelGGL(bond_entropy_kernel, dim3(nprob), dim3(256), 0, s_, n, evals, out);
+    launch_check("bond_entropy_kernel");
   }
   void reduce_max(const double *x, int n, double *out) override {
     stale_check("reduce_max_kernel");

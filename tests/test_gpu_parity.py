@@ -18,6 +18,10 @@ from ._state_io import from_flat, message_list, to_flat
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-8
+# Bond entropies: s = -sum p log2 p moves by sum |dp_i| (|log2 p_i| + 1/ln 2); with the
+# Schmidt weights p_i matching to the 1e-8 of the observables and log2(1/p_i) <= ~40 for the
+# weights that matter, 1e-7 bounds the difference (observed: ~1e-12).
+ENT_TOL = 1e-7
 
 
 @pytest.fixture(scope="module")
@@ -89,9 +93,10 @@ def test_heavy_hex_29_truncated(ctx):
 def test_eagle_small_chi_full_run(ctx):
     print("[parity] eagle chi=4 6 steps", flush=True)
     e = L.eagle()
-    g = _gpu(ctx, e, 0.7, 6, 4)
-    o = _ora(e, 0.7, 6, 4)
+    g = _gpu(ctx, e, 0.7, 6, 4, bond_entropy=True)
+    o = O.solve(e.n_sites, e.edges, e.colour, 0.7, 6, O.Options(chi=4), entropy=True)
     assert np.abs(g["z"] - o.z).max() < TOL
+    assert np.abs(g["bond_entropy"] - o.entropy).max() < ENT_TOL
 
 
 def test_pauli_strings(ctx):
@@ -172,6 +177,10 @@ def test_observe_identical_state_eagle_chi64(ctx):
     z = s.observe_z()
     for v in rng.choice(e.n_sites, 12, replace=False):
         assert abs(z[v] - net.expect_site(int(v), 3)) < 1e-12
+    # bond entropies of the same state (complex, full-rank messages): every edge
+    ent = s.observe_bond_entropy()
+    want = np.array([net.bond_entropy(u, v) for u, v in net.edges])
+    assert np.abs(ent - want).max() < 1e-10
 
 
 def test_eagle_chi64_light_cone_exact(ctx):
@@ -300,3 +309,105 @@ def test_session_clifford_inverse_step_matches_solve(ctx):
     zs = [s.step()["z"] for _ in range(2)] + [s.clifford_inverse_step()["z"] for _ in range(2)]
     s.close()
     assert np.abs(np.array(zs) - g["z"]).max() < 1e-13
+
+
+# --- bond entropy and the infinite lattice ----------------------------------------------------
+
+@pytest.mark.parametrize("chi,theta", [(8, math.pi / 8), (16, 3 * math.pi / 8), (8, 0.9)])
+def test_infinite_cell_vs_oracle(ctx, chi, theta):
+    """The 5-site periodic cell of the infinite heavy-hex lattice with truncation: every <Z> and
+    every bond entropy at every step."""
+    print(f"[parity] infinite cell chi={chi} theta={theta}", flush=True)
+    cell = L.infinite_cell()
+    g = _gpu(ctx, cell, theta, 10, chi, bond_entropy=True)
+    o = O.solve(cell.n_sites, cell.edges, cell.colour, theta, 10, O.Options(chi=chi),
+                entropy=True)
+    assert max(o.discarded) > 1e-8                       # truncation is active
+    assert g["status"] == 0
+    assert np.abs(g["z"] - o.z).max() < TOL
+    assert np.abs(g["bond_entropy"] - o.entropy).max() < ENT_TOL
+
+
+def test_infinite_cell_exact_light_cone(ctx):
+    """Untruncated cell (chi = 32, 5 steps) against exact infinite-lattice values from the
+    state vector of the backward light cone cut out of a 4 x 4 torus; bond spectra at step 4
+    (chi = 16) against the exact Schmidt weights across the edge."""
+    print("[parity] infinite cell vs light cone", flush=True)
+    cell, big = L.infinite_cell(), L.heavy_hex_torus(4, 4)
+    th = 0.77
+    g = _gpu(ctx, cell, th, 5, 32)
+    for t in (1, 3, 5):
+        want = [SV.light_cone_z(big.n_sites, big.edges, k, th, t) for k in range(5)]
+        assert np.abs(g["z"][t - 1] - want).max() < 1e-10, t
+    g = _gpu(ctx, cell, th, 4, 16, bond_entropy=True)
+    for e in range(cell.n_edges):
+        u, v = (int(x) for x in big.edges[e])
+        sub = sorted(set(SV.ball(big.n_sites, big.edges, u, 3)) |
+                     set(SV.ball(big.n_sites, big.edges, v, 3)))
+        idx = {q: i for i, q in enumerate(sub)}
+        es = [(idx[a], idx[b]) for a, b in big.edges.tolist() if a in idx and b in idx]
+        sv = SV.StateVector(len(sub), np.array(es))
+        for _ in range(4):
+            sv.step(th)
+        left = _tree_side(len(sub), es, es.index((idx[u], idx[v])))
+        p = _schmidt(sv.psi, len(sub), left)
+        p = p[p > 0]
+        assert abs(g["bond_entropy"][-1, e] + np.sum(p * np.log2(p))) < 1e-10, e
+
+
+def test_bond_entropy_tree_exact(ctx):
+    """On a tree without truncation the entropies are the exact entanglement entropies of the
+    state across each edge (state vector), at every step."""
+    print("[parity] bond entropy on a tree vs state vector", flush=True)
+    rng = np.random.default_rng(11)
+    tr = L.random_tree(12, rng)
+    th = 1.1
+    g = _gpu(ctx, tr, th, 3, 16, bond_entropy=True)
+    sv = SV.StateVector(tr.n_sites, tr.edges)
+    es = [tuple(x) for x in tr.edges.tolist()]
+    for t in range(3):
+        sv.step(th)
+        for e in range(tr.n_edges):
+            p = _schmidt(sv.psi, tr.n_sites, _tree_side(tr.n_sites, es, e))
+            p = p[p > 0]
+            assert abs(g["bond_entropy"][t, e] + np.sum(p * np.log2(p))) < 1e-10, (t, e)
+
+
+def test_session_bond_entropy_matches_solve(ctx):
+    print("[parity] session bond entropy vs solve", flush=True)
+    cell = L.infinite_cell()
+    g = _gpu(ctx, cell, 0.5, 3, 8, bond_entropy=True)
+    s = _session(ctx, cell, 0.5, 3, 8)
+    rows = []
+    for _ in range(3):
+        s.step()
+        rows.append(s.observe_bond_entropy())
+    s.close()
+    assert np.abs(np.array(rows) - g["bond_entropy"]).max() < 1e-13
+    g0 = _gpu(ctx, cell, 0.5, 0, 8, bond_entropy=True)
+    assert g0["bond_entropy"].shape == (1, 6) and np.all(g0["bond_entropy"] == 0.0)
+
+
+def _schmidt(psi, n, left):
+    L_ = sorted(left)
+    R_ = [q for q in range(n) if q not in left]
+    m = np.transpose(psi.reshape((2,) * n), L_ + R_).reshape(2 ** len(L_), -1)
+    return np.linalg.svd(m, compute_uv=False) ** 2
+
+
+def _tree_side(n, edges, e):
+    u, v = edges[e]
+    nb = [[] for _ in range(n)]
+    for k, (a, b) in enumerate(edges):
+        if k != e:
+            nb[a].append(b)
+            nb[b].append(a)
+    seen, st = {u}, [u]
+    while st:
+        x = st.pop()
+        for y in nb[x]:
+            if y not in seen:
+                seen.add(y)
+                st.append(y)
+    assert v not in seen
+    return seen

@@ -50,7 +50,8 @@ def _pack_specs():
         ps = L.random_pauli_strings(lat, 3, seed=200 + i, wmin=2, wmax=6)
         out.append(B.spec_from_lattice(lat, float(rng.uniform(0.0, 1.5)), int(rng.integers(1, 9)),
                                        8, pauli=[(p.sites, p.ops) for p in ps],
-                                       record_every_step=int(i % 3 != 0)))
+                                       record_every_step=int(i % 3 != 0),
+                                       bond_entropy=i % 2 == 0))
     return out
 
 
@@ -87,6 +88,8 @@ def test_packed_requests_match_alone():
             d = s.depth
             assert np.abs(o["bp_iters"][:d] - alone["bp_iters"][:d]).max() <= 1
             assert np.abs(o["discarded"][:d] - alone["discarded"][:d]).max() < 1e-10
+            if s.bond_entropy:
+                assert np.abs(o["bond_entropy"] - alone["bond_entropy"]).max() < 1e-10
     lat = L.heavy_hex(3, 9)
     s, o = specs[1], outs[1]
     ref = O.solve(lat.n_sites, lat.edges, lat.colour, s.theta, s.depth, O.Options(chi=8),
