@@ -347,6 +347,50 @@ def chi128_window(lat, theta: float, warmup: int = 7, steps: int = 3) -> dict:
                                   zip(("rx", "gate_layers", "bp", "observe"), phase)}}
 
 
+def infinite_lattice(chi: int, depth: int = 30) -> dict:
+    """The thermodynamic limit ("Dynamics of the infinite heavy-hex lattice", Fig. 4): the 5-site
+    periodic cell (degree-3 sites A, B and three bridges) at theta_h in {pi/8, pi/4, 3pi/8},
+    `depth` Floquet steps, FP64 (BP tolerance 1e-12) and mixed precision (FP32 MFMA BP, 1e-8):
+    <Z> per sublattice per step, the bond entropies after the last step and the time per step."""
+    import math
+
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    cell = L.infinite_cell()
+    thetas = [math.pi / 8, math.pi / 4, 3 * math.pi / 8]
+    runs, zs = [], {}
+    with bpki.Context(0) as ctx:
+        for prec, tol, name in ((bpki.BPKI_FP64, 1e-12, "fp64"), (bpki.BPKI_FP32, 1e-8, "mixed")):
+            for th in thetas:
+                t0 = time.perf_counter()
+                r = ctx.solve(bpki.spec_from_lattice(cell, th, depth, chi, precision=prec,
+                                                     bp_tol=tol, bond_entropy=True))
+                wall = time.perf_counter() - t0
+                z = r["z"]
+                zs[(name, th)] = z
+                runs.append({
+                    "theta_h": th, "precision": name, "status": int(r["status"]),
+                    "ms_per_step": 1e3 * wall / depth,
+                    "bp_sweeps_per_step": float(np.mean(r["bp_iters"][:depth])),
+                    "z_A": [round(float(x), 6) for x in z[:, 0]],
+                    "z_B": [round(float(x), 6) for x in z[:, 1]],
+                    "z_bridges": [round(float(x), 6) for x in z[:, 2:].mean(axis=1)],
+                    "bond_entropy_last_step": [round(float(x), 6)
+                                               for x in r["bond_entropy"][-1]],
+                })
+                print(f"infinite cell {name} theta={th:.4f}: {1e3 * wall / depth:.1f} ms/step",
+                      file=sys.stderr, flush=True)
+    for run in runs:
+        if run["precision"] == "mixed":
+            dz = np.abs(zs[("mixed", run["theta_h"])] - zs[("fp64", run["theta_h"])])
+            run["abs_dz_vs_fp64_max"] = float(dz.max())
+    return {"lattice": "heavy-hex 5-site periodic cell (edges A-C_d colour d, C_d-B colour "
+                       "(d+1) mod 3)", "chi": chi, "steps": depth, "runs": runs}
+
+
 def copy_probe(mib: int) -> int:
     """8 launches of torch's device copy kernel, each reading and writing ``mib`` MiB."""
     import torch
@@ -378,6 +422,9 @@ def main() -> int:
                     help="1: also the weight-10 observable at the 8 theta_h (extended evolution)")
     ap.add_argument("--theta-batch", type=int, default=1,
                     help="1: also solve the eight theta_h values together (aggregate steps/s)")
+    ap.add_argument("--infinite", type=int, default=128, metavar="CHI",
+                    help="bond dimension of the infinite-lattice section (5-site periodic cell, "
+                         "3 theta_h x 30 steps, FP64 and mixed; 0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 8 plain device-to-device copies of MIB MiB and exit "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -487,6 +534,9 @@ def main() -> int:
     if args.theta_batch:
         out["theta_batch"] = theta_batch(lat, chi, args.warmup + args.steps)
         print("theta batch done", file=sys.stderr, flush=True)
+    if args.infinite > 0:
+        out["infinite_lattice"] = infinite_lattice(args.infinite)
+        print("infinite lattice done", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.slots)
         print("serving done", file=sys.stderr, flush=True)
