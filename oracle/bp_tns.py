@@ -29,6 +29,8 @@ What it computes (arXiv 2306.14887, Tindall, Fishman, Stoudenmire, Sels):
   inside the cluster with BP messages on the cut legs.
 * Bond entanglement entropy (Eq. "EntanglementEntropy"): the Schmidt weights of an edge
   are the spectrum of the two messages that meet on it (Network.bond_spectrum).
+* The explicit Vidal gauge (Methods, "The Vidal gauge"): the gauge transformation built from
+  the messages (Network.vidal_gauge), equivalent to the message form in exact arithmetic.
 * The infinite lattice ("Dynamics of the infinite heavy-hex lattice", Fig. 4) is its
   periodic unit cell given as a graph: BP on the 5-site quotient graph is BP on the
   infinite lattice with translation-invariant messages, so nothing here is specific to it.
@@ -365,6 +367,41 @@ class Network:
         if not s > 0.0:
             raise FloatingPointError(f"bond ({v}, {w}): zero norm")
         return np.sort(lam / s)[::-1]
+
+    def vidal_gauge(self, cutoff: float = 1e-12) -> dict:
+        """Bring the state into the symmetric Vidal gauge with the BP messages (Methods, "The
+        Vidal gauge": the messages define the gauge transformation that makes every grouping of
+        Eq. "IsometryPropertyDefinition" an isometry, Eq. "IsometryDefinition").
+
+        For an edge (u, v) let X = M_{u->v}^{1/2}, Y = M_{v->u}^{1/2}.  The state across the
+        edge is L R^T with Gram matrices L^H L = M_{u->v}^T and R^H R = M_{v->u}^T, so
+        L = Q_L X^T and R = Q_R Y^T with isometric Q's, and the SVD X^T Y = U S V^H gives the
+        Schmidt form (Q_L U) S (Q_R conj V)^T.  Inserting the identity X^{T+} U S V^H Y^{+}
+        (on the supports) on the bond and splitting S symmetrically, leg u->v of T_u absorbs
+        P_u = X^{T+} U S^{1/2} and leg v->u of T_v absorbs P_v = Y^{T+} conj(V) S^{1/2}.  S is
+        normalised to unit 2-norm (the state changes by a positive factor) and singular values
+        <= cutoff * s_1 are dropped.  The new messages are the BP fixed point diag(S) (unit
+        trace).  Returns {(u, v): S} in edge order.
+        """
+        lam, P = {}, {}
+        for u, v in self.edges:
+            X, Xp = msg_sqrt(self.M[(u, v)], cutoff)
+            Y, Yp = msg_sqrt(self.M[(v, u)], cutoff)
+            U, sv, Vh = np.linalg.svd(X.T @ Y)
+            keep = sv > cutoff * sv[0]
+            U, sv, Vh = U[:, keep], sv[keep], Vh[keep, :]
+            sv = sv / np.linalg.norm(sv)
+            lam[(u, v)] = sv
+            P[(u, v)] = Xp.T @ (U * np.sqrt(sv)[None, :])
+            P[(v, u)] = Yp.T @ (Vh.T * np.sqrt(sv)[None, :])
+        for v in range(self.n):
+            for u in self.nb[v]:
+                self.T[v] = absorb(self.T[v], self.axis(v, u), P[(v, u)])
+        for (u, v), sv in lam.items():
+            D = np.diag(sv / sv.sum()).astype(complex)
+            self.M[(u, v)] = D
+            self.M[(v, u)] = D.copy()
+        return lam
 
     def bond_entropy(self, v: int, w: int) -> float:
         """s = -sum_i p_i log2 p_i over the Schmidt weights of the bond (Eq.

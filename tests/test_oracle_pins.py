@@ -420,3 +420,87 @@ def test_infinite_cell_colourings_agree_untruncated():
     a = _solve(L.infinite_cell((1, 2, 0)), 0.7, 4, 16)
     b = _solve(L.infinite_cell((2, 0, 1)), 0.7, 4, 16)
     assert np.abs(a.z - b.z).max() < 1e-11
+
+
+# --- explicit Vidal gauge ------------------------------------------------------------------------
+
+def _contract_tree(net):
+    """Whole state vector of a (small) tensor network by one einsum over all bonds."""
+    letters = "abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ"
+    el = {}
+    for k, (u, v) in enumerate(net.edges):
+        el[(u, v)] = el[(v, u)] = letters[k]
+    phys = [letters[len(net.edges) + v] for v in range(net.n)]
+    subs = [phys[v] + "".join(el[(v, u)] for u in net.nb[v]) for v in range(net.n)]
+    psi = np.einsum(",".join(subs) + "->" + "".join(phys), *net.T, optimize=True).reshape(-1)
+    return psi / np.linalg.norm(psi)
+
+
+def _isometry_error(net, lam):
+    """Eq. "IsometryDefinition": Gamma_v (T_v with S^{-1/2} removed from every leg), with S^2 on
+    all legs but one, contracted with its conjugate is proportional to the identity on that
+    leg.  Returns the largest deviation after dividing out the proportionality factor."""
+    S = {}
+    for (u, v), s in lam.items():
+        S[(u, v)] = S[(v, u)] = s
+    err = 0.0
+    for v in range(net.n):
+        G = net.T[v]
+        for u in net.nb[v]:
+            G = O.absorb(G, net.axis(v, u), np.diag(1.0 / np.sqrt(S[(v, u)])))
+        for u in net.nb[v]:
+            Y = G
+            for w in net.nb[v]:
+                if w != u:
+                    Y = O.absorb(Y, net.axis(v, w), np.diag(S[(v, w)] ** 2).astype(complex))
+            ax = net.axis(v, u)
+            others = [a for a in range(G.ndim) if a != ax]
+            I = np.tensordot(Y, G.conj(), axes=(others, others))
+            c = np.trace(I) / I.shape[0]
+            err = max(err, float(np.abs(I / c - np.eye(I.shape[0])).max()))
+    return err
+
+
+def test_vidal_gauge_on_a_tree_keeps_the_state():
+    """On a tree the transform leaves the (normalised) state vector unchanged, its bond weights
+    are the Schmidt coefficients (S^2 = bond spectrum), every grouping is an isometry and the
+    diagonal messages are a BP fixed point."""
+    rng = np.random.default_rng(3)
+    tr = L.random_tree(8, rng)
+    net = O.Network(tr.n_sites, tr.edges, tr.colour)
+    O.solve(tr.n_sites, tr.edges, tr.colour, 0.9, 3, O.Options(chi=8), net=net)
+    # a random complex gauge first, so that the transform has work to do
+    for u, v in tr.edges.tolist():
+        d = net.bond_dim(u, v)
+        G = np.eye(d) + 0.3 * (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+        net.T[u] = O.absorb(net.T[u], net.axis(u, v), G)
+        net.T[v] = O.absorb(net.T[v], net.axis(v, u), np.linalg.inv(G).T)
+    for key, m in net.M.items():
+        net.M[key] = np.eye(m.shape[0], dtype=complex) / m.shape[0]
+    net.bp(1e-14, 200)
+    psi0 = _contract_tree(net)
+    spec = {e: net.bond_spectrum(*e) for e in net.edges}
+    lam = net.vidal_gauge()
+    assert np.abs(_contract_tree(net) - psi0).max() < 1e-12
+    for e, s in lam.items():
+        assert np.abs(s ** 2 - spec[e][:len(s)]).max() < 1e-12
+        assert spec[e][len(s):].sum() < 1e-20
+    assert _isometry_error(net, lam) < 1e-10
+    assert net.bp_sweep() < 1e-12
+
+
+def test_vidal_gauge_on_the_infinite_cell():
+    """On the loopy cell with truncation (BP converged): <Z> is unchanged, S^2 is the bond
+    spectrum, and the transformed state satisfies the isometries and the BP fixed point."""
+    cell = L.infinite_cell()
+    net = O.Network(cell.n_sites, cell.edges, cell.colour)
+    O.solve(cell.n_sites, cell.edges, cell.colour, 1.2, 8, O.Options(chi=16), net=net)
+    z0 = np.array([net.expect_site(v, 3) for v in range(net.n)])
+    spec = {e: net.bond_spectrum(*e) for e in net.edges}
+    lam = net.vidal_gauge()
+    z1 = np.array([net.expect_site(v, 3) for v in range(net.n)])
+    assert np.abs(z1 - z0).max() < 1e-12
+    for e, s in lam.items():
+        assert np.abs(s ** 2 - spec[e][:len(s)]).max() < 1e-12
+    assert _isometry_error(net, lam) < 1e-10
+    assert net.bp_sweep() < 1e-10
