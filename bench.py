@@ -387,8 +387,30 @@ def infinite_lattice(chi: int, depth: int = 30) -> dict:
         if run["precision"] == "mixed":
             dz = np.abs(zs[("mixed", run["theta_h"])] - zs[("fp64", run["theta_h"])])
             run["abs_dz_vs_fp64_max"] = float(dz.max())
+    # the three FP64 runs packed into one problem on the union of three cells (serving path):
+    # a small request on the same lattice holds the one slot while the three queue up
+    with bpki.Context(0) as ctx:
+        ctx.serving_config(1)
+        ctx.serving_packing(len(thetas), chi)
+        hold = ctx.submit(bpki.spec_from_lattice(cell, 0.1, 1, 2))
+        tickets = [ctx.submit(bpki.spec_from_lattice(cell, th, depth, chi, bond_entropy=True))
+                   for th in thetas]
+        hold.wait()
+        while not all(t.poll() for t in tickets):
+            time.sleep(0.002)
+        times = np.array([t.times() for t in tickets])      # a ticket is released by wait()
+        packs = [t.pack_size() for t in tickets]
+        outs = [t.wait() for t in tickets]
+    span = float(times[:, 2].max() - times[:, 1].min())
+    packed = {"pack_sizes": packs, "aggregate_steps_per_s": len(thetas) * depth / span,
+              "makespan_s": span,
+              "sequential_steps_per_s": len(thetas) * depth / (1e-3 * depth * sum(
+                  r["ms_per_step"] for r in runs if r["precision"] == "fp64")),
+              "abs_dz_vs_alone_max": float(max(np.abs(o["z"] - zs[("fp64", th)]).max()
+                                               for o, th in zip(outs, thetas)))}
     return {"lattice": "heavy-hex 5-site periodic cell (edges A-C_d colour d, C_d-B colour "
-                       "(d+1) mod 3)", "chi": chi, "steps": depth, "runs": runs}
+                       "(d+1) mod 3)", "chi": chi, "steps": depth, "runs": runs,
+            "fp64_packed": packed}
 
 
 def copy_probe(mib: int) -> int:

@@ -201,6 +201,19 @@ int bpki_session_observe_z(bpki_session *s, double *z);
 /* entropy [n_edges] (host): bond entropies of the current state and messages, as
  * bpki_result.bond_entropy. */
 int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy);
+/* Explicit symmetric Vidal gauge from the current messages (Methods, "The Vidal gauge"), in
+ * place.  For every edge (u, v) with X_u = M_{u->v}^{1/2}, X_v = M_{v->u}^{1/2} and the SVD
+ * X_u^T X_v = U S V^H, leg u->v of T_u absorbs X_u^{T+} U S^{1/2} and leg v->u of T_v absorbs
+ * X_v^{T+} conj(V) S^{1/2}: the identity (on the supports of the messages) is inserted on every
+ * bond, so the state changes only by a positive factor; each site tensor with S^{-1/2} removed
+ * from its legs (Gamma_v) then forms, with S on its other legs, the isometries of Eqs.
+ * "IsometryPropertyDefinition" and "IsometryDefinition", and diag(S)/sum(S) on both directions
+ * (written as the new messages) is a BP fixed point.  S is normalised to unit 2-norm; singular
+ * values <= svd_cutoff * s_1 are dropped (bond dimensions shrink accordingly).  Computed from the
+ * eigenpairs of C^H C in FP64 in every mode.  lambda: [n_edges][chi] host, S descending and
+ * zero-padded, or NULL.  Equivalent to the message form in exact arithmetic (a conditioning
+ * safeguard and the paper's stated representation). */
+int bpki_session_vidal_gauge(bpki_session *s, double *lambda);
 int bpki_session_observe_pauli(bpki_session *s, double *pauli);
 /* One whole Floquet step: X rotations, all gate layers, BP, then z (may be NULL). */
 int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residual,

@@ -97,6 +97,7 @@ def load(path: str | None = None):
         "bpki_session_bp_sweep": (C.c_int, [vp, dp]),
         "bpki_session_observe_z": (C.c_int, [vp, dp]),
         "bpki_session_observe_bond_entropy": (C.c_int, [vp, dp]),
+        "bpki_session_vidal_gauge": (C.c_int, [vp, dp]),
         "bpki_session_observe_pauli": (C.c_int, [vp, dp]),
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_clifford_inverse_step": (C.c_int, [vp, dp, ip, dp, dp]),
@@ -128,7 +129,8 @@ def exported_symbols() -> list[str]:
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
             "bpki_session_bp_sweep", "bpki_session_observe_z",
-            "bpki_session_observe_bond_entropy", "bpki_session_observe_pauli",
+            "bpki_session_observe_bond_entropy", "bpki_session_vidal_gauge",
+            "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_clifford_inverse_step",
             "bpki_session_last_timing", "bpki_session_profile",
             "bpki_session_profile_read", "bpki_test_gemm",
@@ -441,6 +443,13 @@ class Session:
         e = np.zeros(int(np.asarray(self.spec.edges).size // 2))
         _check(self.lib, self.lib.bpki_session_observe_bond_entropy(self.h, _ptr(e, C.c_double)))
         return e
+
+    def vidal_gauge(self) -> np.ndarray:
+        """Transform the state in place into the symmetric Vidal gauge; returns the bond weights
+        S [n_edges, chi] (descending, unit 2-norm, zero-padded)."""
+        lam = np.zeros((int(np.asarray(self.spec.edges).size // 2), int(self.spec.chi)))
+        _check(self.lib, self.lib.bpki_session_vidal_gauge(self.h, _ptr(lam, C.c_double)))
+        return lam
 
     def observe_pauli(self) -> np.ndarray:
         out = np.zeros(len(self.spec.pauli))

@@ -436,6 +436,12 @@ extern "C" int bpki_session_observe_z(bpki_session *s, double *z) {
   return sess_check(s);
 }
 
+extern "C" int bpki_session_vidal_gauge(bpki_session *s, double *lambda) {
+  if (!s) return fail(-1, "NULL session");
+  s->eng->vidal_gauge(lambda);
+  return sess_check(s);
+}
+
 extern "C" int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy) {
   if (!s || !entropy) return fail(-1, "NULL argument");
   s->eng->observe_entropy(entropy);

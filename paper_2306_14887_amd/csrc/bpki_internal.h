@@ -77,6 +77,13 @@ struct Backend {
   // Entropy -sum p log2 p of the Schmidt weights p = max(evals, 0) / sum (n per problem); out
   // [nprob] device, NaN for an all-zero spectrum.
   virtual void bond_entropy(int n, const double *const *evals, double *out, int nprob) = 0;
+  // Symmetric Vidal gauge factors of nprob edges from the eigenpairs of C^H C (C = X^T Y):
+  // D1 = V diag(s^{1/2} / lambda), D2 = conj(V) diag(s^{1/2}) (s = lambda above cut * lambda_1,
+  // unit 2-norm), both messages of the edge set to diag(s) / sum(s); lam [nprob][n] = s,
+  // kept [nprob] (device).
+  virtual void vidal_svd(int n, const double *const *evals, const double *const *vecs,
+                         double *const *D1, double *const *D2, double *const *Mu,
+                         double *const *Mv, double *lam, int *kept, double cut, int nprob) = 0;
   // Pivoted Cholesky factor of a Gram matrix G = A^H A (n x n, Hermitian PSD):
   // G[p][p] = L L^H for a pivot order p, stopping at the first pivot <= cut * max(diag G).
   // Writes R = L^H P^T (n x n, zero rows beyond the rank) and Wsc = P [L1^{-H}; 0] (n x n), so
@@ -163,6 +170,7 @@ class Engine {
   void observe_pauli(double *out);                // host out [n_pauli]
   void observe_pauli_range(int k0, int k1, double *out);   // strings k0 .. k1-1
   void observe_entropy(double *out);              // host out [n_edges]: bond entropies (bits)
+  void vidal_gauge(double *lambda);               // in place; host out [n_edges][chi] or NULL
   // Packed solves: sweeps until every member's residual is below bp_tol.  A member's messages
   // are frozen after the sweep that brought its own residual below the tolerance, so each member
   // follows its own BP schedule; per member: sweeps and final residual.

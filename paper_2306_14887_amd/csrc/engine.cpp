@@ -164,6 +164,16 @@ struct Plan {
   size_t ent_m = 0, ent_ev = 0, ent_vec = 0, ent_X = 0, ent_Y = 0, ent_B = 0;
   GemmOp ent_xm, ent_b;
   double *ent_out = nullptr;       // [E]
+  // explicit Vidal gauge: square roots of all 2E messages, C = X_u^T X_v, eigh(C^H C), the gauge
+  // factors P_u = X_u^{T+} C D1, P_v = X_v^{T+} D2, then every leg absorbs its factor
+  size_t vg_m = 0, vg_ev = 0, vg_vec = 0, vg_X = 0, vg_Xp = 0, vg_ev3 = 0, vg_vec3 = 0,
+         vg_D1 = 0, vg_D2 = 0, vg_Mu = 0, vg_Mv = 0;
+  GemmOp vg_c, vg_h, vg_t1, vg_pu, vg_pv;
+  std::vector<GemmOp> vg_ops;
+  std::vector<std::pair<double *, const double *>> vg_copy;   // degree-1 sites: result -> T
+  std::vector<size_t> vg_copy_len;
+  double *vg_lam = nullptr;        // [E][chi]
+  int *vg_kept = nullptr;          // [E]
   int max_layer_edges = 0;
   std::vector<void *> allocs;
 };
@@ -688,6 +698,25 @@ void Engine::build() {
     e_B[e] = eb.take(c2);
   }
   ws_max = std::max(ws_max, eb.top);
+  // the Vidal gauge transform also borrows it (from offset 0: never live with the above)
+  Bump vb;
+  std::vector<size_t> v_ev(2 * P.E), v_vec(2 * P.E), v_X(2 * P.E), v_Xp(2 * P.E), v_C(P.E),
+      v_H(P.E), v_ev3(P.E), v_vec3(P.E), v_D1(P.E), v_D2(P.E);
+  for (int m = 0; m < 2 * P.E; ++m) {
+    v_ev[m] = vb.take(chi);
+    v_vec[m] = vb.take(c2);
+    v_X[m] = vb.take(c2);
+    v_Xp[m] = vb.take(c2);
+  }
+  for (int e = 0; e < P.E; ++e) {
+    v_C[e] = vb.take(c2);
+    v_H[e] = vb.take(c2);
+    v_ev3[e] = vb.take(chi);
+    v_vec3[e] = vb.take(c2);
+    v_D1[e] = vb.take(c2);
+    v_D2[e] = vb.take(c2);
+  }
+  ws_max = std::max(ws_max, vb.top);
   P.ws_elems = ws_max;
   P.ws = (double *)A(ws_max * 16);
   for (auto &LP : P.layers) {
@@ -722,6 +751,63 @@ void Engine::build() {
     P.ent_b.n = P.E;
     P.ent_b.a = P.ent_Y; P.ent_b.b = P.ent_X; P.ent_b.c = P.ent_B;
     P.ent_out = (double *)A((size_t)P.E * 8);
+
+    // Vidal gauge: square roots of every message (index m = 2e: u -> v, 2e + 1: v -> u)
+    std::vector<const void *> am, aev, avec, aX, aXp;
+    for (int m2 = 0; m2 < 2 * P.E; ++m2) {
+      am.push_back(Mp(m2));
+      aev.push_back(W(v_ev[m2]));
+      avec.push_back(W(v_vec[m2]));
+      aX.push_back(W(v_X[m2]));
+      aXp.push_back(W(v_Xp[m2]));
+    }
+    P.vg_m = P.arena.add(am); P.vg_ev = P.arena.add(aev); P.vg_vec = P.arena.add(avec);
+    P.vg_X = P.arena.add(aX); P.vg_Xp = P.arena.add(aXp);
+    std::vector<const void *> xu, xv, xpu, xpv, cc, hh, ev3, vec3, d1, d2, mu, mv, pu, pv;
+    for (int e = 0; e < P.E; ++e) {
+      xu.push_back(W(v_X[2 * e]));
+      xv.push_back(W(v_X[2 * e + 1]));
+      xpu.push_back(W(v_Xp[2 * e]));
+      xpv.push_back(W(v_Xp[2 * e + 1]));
+      cc.push_back(W(v_C[e]));
+      hh.push_back(W(v_H[e]));
+      ev3.push_back(W(v_ev3[e]));
+      vec3.push_back(W(v_vec3[e]));
+      d1.push_back(W(v_D1[e]));
+      d2.push_back(W(v_D2[e]));
+      mu.push_back(Mp(2 * e));
+      mv.push_back(Mp(2 * e + 1));
+      pu.push_back(W(v_vec[2 * e]));        // the message eigenvectors are spent by then
+      pv.push_back(W(v_vec[2 * e + 1]));
+    }
+    GemmDesc tn;                            // C[m][n] = sum_k A[k][m] B[k][n]
+    tn.M = tn.N = tn.K = tn.Mi = tn.Ni = tn.Ki = chi;
+    tn.a_mi = 1; tn.a_ki = chi;
+    tn.b_ki = chi; tn.b_ni = 1;
+    tn.c_mi = chi; tn.c_ni = 1;
+    GemmDesc nn = tn;                       // C = A B
+    nn.a_mi = chi; nn.a_ki = 1;
+    auto op = [&](const GemmDesc &d, const std::vector<const void *> &a,
+                  const std::vector<const void *> &b, const std::vector<const void *> &c) {
+      GemmOp o;
+      o.d = d;
+      o.n = P.E;
+      o.a = P.arena.add(a); o.b = P.arena.add(b); o.c = P.arena.add(c);
+      return o;
+    };
+    P.vg_c = op(tn, xu, xv, cc);            // C = X_u^T X_v
+    GemmDesc hd = tn;
+    hd.conjA = 1;
+    hd.herm = 1;
+    P.vg_h = op(hd, cc, cc, hh);            // C^H C
+    P.vg_ev3 = P.arena.add(ev3); P.vg_vec3 = P.arena.add(vec3);
+    P.vg_D1 = P.arena.add(d1); P.vg_D2 = P.arena.add(d2);
+    P.vg_Mu = P.arena.add(mu); P.vg_Mv = P.arena.add(mv);
+    P.vg_t1 = op(nn, cc, d1, hh);           // C D1 = U S^{1/2} (into the spent C^H C)
+    P.vg_pu = op(tn, xpu, hh, pu);          // P_u = X_u^{T+} U S^{1/2}
+    P.vg_pv = op(tn, xpv, d2, pv);          // P_v = X_v^{T+} conj(V) S^{1/2}
+    P.vg_lam = (double *)A((size_t)P.E * chi * 8);
+    P.vg_kept = (int *)A((size_t)P.E * 4);
   }
 
   // ---- BP plan ----
@@ -909,6 +995,33 @@ void Engine::build() {
       }
       P.obs_Y = P.arena.add(ry);
       P.obs_T = P.arena.add(rt);
+      // Vidal gauge factors on every leg: T x0 P0 x1 P1 x2 P2, the last product written back
+      // into T (degree 1: through a buffer and a copy)
+      if (P.E) {
+        auto Wv = [&](size_t off) { return (const void *)(P.ws + 2 * off); };
+        std::vector<const void *> va[3][3], vb2[3][3], vc[3][3];
+        for (int v = 0; v < P.n; ++v) {
+          const int d = P.deg[v];
+          const void *cur = Tp(v);
+          for (int l = 0; l < d; ++l) {
+            const int m = P.in_msg[v][l], e = m / 2;
+            // m odd: the message comes from edges[2e+1], so v = edges[2e] holds P_u
+            const void *f = Wv(v_vec[(m & 1) ? 2 * e : 2 * e + 1]);
+            const void *dst = l == d - 1 && d > 1 ? Tp(v) : d == 1 ? B(obs1[v]) : B(sws[v].y[l]);
+            va[d - 1][l].push_back(cur); vb2[d - 1][l].push_back(f); vc[d - 1][l].push_back(dst);
+            cur = dst;
+          }
+          if (d == 1) {
+            P.vg_copy.push_back({P.T + 2 * P.toff[v], (const double *)B(obs1[v])});
+            P.vg_copy_len.push_back((size_t)P.tsize[v] * 16);   // complex entries
+          }
+        }
+        for (int d = 1; d <= 3; ++d) {
+          Layout L = t_layout(d, chi);
+          for (int l = 0; l < d; ++l) add_op(P.vg_ops, leg_desc(d, l, L, L, chi), va[d - 1][l],
+                                             vb2[d - 1][l], vc[d - 1][l]);
+        }
+      }
       P.rho_len = (int64_t *)A(lens.size() * 8);
       be_->h2d(P.rho_len, lens.data(), lens.size() * 8);
     }
@@ -1159,6 +1272,42 @@ void Engine::observe_entropy(double *out) {
             ar.at<double *const *>(P.ent_vec), P.E);
   be_->bond_entropy(chi, ar.at<const double *const *>(P.ent_ev), P.ent_out, P.E);
   be_->d2h(out, P.ent_out, (size_t)P.E * 8);
+}
+
+// Explicit symmetric Vidal gauge from the BP messages (Methods, "The Vidal gauge"): for every
+// edge (u, v), X_u = M_{u->v}^{1/2}, X_v = M_{v->u}^{1/2}, C = X_u^T X_v = U S V^H; leg u->v of T_u
+// absorbs P_u = X_u^{T+} U S^{1/2} and leg v->u of T_v absorbs P_v = X_v^{T+} conj(V) S^{1/2},
+// which inserts the identity (on the supports) on the bond and makes every grouping of a site
+// tensor with the bond weights of its other legs an isometry.  S is normalised to unit 2-norm,
+// values <= svd_cutoff * s_1 are dropped, and the messages become the fixed point diag(S)/sum S.
+void Engine::vidal_gauge(double *lambda) {
+  Plan &P = *plan_;
+  if (!P.E) return;
+  const PtrArena &ar = P.arena;
+  const int chi = P.chi;
+  be_->eigh(chi, chi, ar.at<const double *const *>(P.vg_m), ar.at<double *const *>(P.vg_ev),
+            ar.at<double *const *>(P.vg_vec), 2 * P.E);
+  be_->msg_sqrt(chi, ar.at<const double *const *>(P.vg_ev), ar.at<const double *const *>(P.vg_vec),
+                ar.at<double *const *>(P.vg_X), ar.at<double *const *>(P.vg_Xp),
+                prob_.eig_cutoff, 2 * P.E);
+  run(be_, ar, P.vg_c, 0);
+  run(be_, ar, P.vg_h, 0);
+  be_->eigh(chi, chi, ar.at<const double *const *>(P.vg_h.c), ar.at<double *const *>(P.vg_ev3),
+            ar.at<double *const *>(P.vg_vec3), P.E);
+  be_->vidal_svd(chi, ar.at<const double *const *>(P.vg_ev3),
+                 ar.at<const double *const *>(P.vg_vec3), ar.at<double *const *>(P.vg_D1),
+                 ar.at<double *const *>(P.vg_D2), ar.at<double *const *>(P.vg_Mu),
+                 ar.at<double *const *>(P.vg_Mv), P.vg_lam, P.vg_kept, prob_.svd_cutoff, P.E);
+  run(be_, ar, P.vg_t1, 0);
+  run(be_, ar, P.vg_pu, 0);
+  run(be_, ar, P.vg_pv, 0);
+  for (auto &o : P.vg_ops) run(be_, ar, o, 0);
+  for (size_t i = 0; i < P.vg_copy.size(); ++i)
+    be_->d2d(P.vg_copy[i].first, P.vg_copy[i].second, P.vg_copy_len[i]);
+  std::vector<int> k(P.E);
+  be_->d2h(k.data(), P.vg_kept, (size_t)P.E * 4);
+  for (int e = 0; e < P.E; ++e) P.bond_h[e] = std::min(P.bond_h[e], k[e]);
+  if (lambda) be_->d2h(lambda, P.vg_lam, (size_t)P.E * chi * 8);
 }
 
 void Engine::observe_pauli(double *out) {

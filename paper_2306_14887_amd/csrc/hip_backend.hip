@@ -1923,6 +1923,67 @@ __global__ __launch_bounds__(256) void bond_entropy_kernel(int n, const double *
   if (threadIdx.x == 0) out[blockIdx.x] = tot > 0.0 && isfinite(e) ? e : NAN;
 }
 
+// Symmetric Vidal gauge (Methods, "The Vidal gauge"), one workgroup per edge (u, v) with
+// C = X^T Y, X and Y the square roots of the two messages on the edge.  From the eigenpairs
+// (l_i descending, columns of V) of C^H C the singular values are lambda_i = sqrt(l_i); those
+// above cut * lambda_1 are kept and normalised to unit 2-norm (s_i), the rest dropped.  Writes
+// D1 = V diag(s_i^{1/2} / lambda_i) (so C D1 = U S^{1/2}), D2 = conj(V) diag(s_i^{1/2}), the
+// BP fixed point diag(s) / sum(s) into both messages of the edge, s (zero-padded) and the kept
+// count.  n <= 256.
+__global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *const *evals,
+                                                        const double *const *vecs,
+                                                        double *const *D1, double *const *D2,
+                                                        double *const *Mu, double *const *Mv,
+                                                        double *lam, int *kept, double cut) {
+  __shared__ double sv[256], f1[256], f2[256];
+  __shared__ double sh[4];
+  __shared__ double nrm_s, sum_s, cnt_s;
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const double *l = evals[e];
+  const double l0 = sqrt(fmax(l[0], 0.0));
+  double acc = 0.0, cnt = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double li = sqrt(fmax(l[i], 0.0));
+    const bool keep = li > 0.0 && li > cut * l0;
+    sv[i] = keep ? li : 0.0;
+    acc += keep ? li * li : 0.0;
+    cnt += keep ? 1.0 : 0.0;
+  }
+  const double t = block_sum<256>(acc, sh);
+  const double c = block_sum<256>(cnt, sh);
+  if (tid == 0) {
+    nrm_s = sqrt(t);
+    cnt_s = c;
+  }
+  __syncthreads();
+  const double inv = nrm_s > 0.0 ? 1.0 / nrm_s : 0.0;
+  acc = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double si = sv[i] * inv;
+    f1[i] = si > 0.0 ? sqrt(si) / sv[i] : 0.0;
+    f2[i] = sqrt(si);
+    lam[(size_t)e * n + i] = si;
+    acc += si;
+  }
+  const double ss = block_sum<256>(acc, sh);
+  if (tid == 0) sum_s = ss;
+  __syncthreads();
+  const double isum = sum_s > 0.0 ? 1.0 / sum_s : 0.0;
+  const double2 *V = reinterpret_cast<const double2 *>(vecs[e]);
+  double2 *d1 = reinterpret_cast<double2 *>(D1[e]), *d2 = reinterpret_cast<double2 *>(D2[e]);
+  double2 *mu = reinterpret_cast<double2 *>(Mu[e]), *mv = reinterpret_cast<double2 *>(Mv[e]);
+  for (int idx = tid; idx < n * n; idx += 256) {
+    const int r = idx / n, q = idx % n;
+    const double2 w = V[idx];                  // component r of eigenvector q
+    d1[idx] = make_double2(w.x * f1[q], w.y * f1[q]);
+    d2[idx] = make_double2(w.x * f2[q], -w.y * f2[q]);
+    const double2 m = make_double2(r == q ? sv[q] * inv * isum : 0.0, 0.0);
+    mu[idx] = m;
+    mv[idx] = m;
+  }
+  if (tid == 0) kept[e] = (int)cnt_s;
+}
+
 __global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n, double *out) {
   __shared__ double sh[256];
   double m = 0;
@@ -2449,6 +2510,15 @@ class HipBackend : public Backend {
     stale_check("bond_entropy_kernel");
     hipLaunchKernelGGL(bond_entropy_kernel, dim3(nprob), dim3(256), 0, s_, n, evals, out);
     launch_check("bond_entropy_kernel");
+  }
+  void vidal_svd(int n, const double *const *evals, const double *const *vecs, double *const *D1,
+                 double *const *D2, double *const *Mu, double *const *Mv, double *lam, int *kept,
+                 double cut, int nprob) override {
+    if (nprob <= 0) return;
+    stale_check("vidal_svd_kernel");
+    hipLaunchKernelGGL(vidal_svd_kernel, dim3(nprob), dim3(256), 0, s_, n, evals, vecs, D1, D2,
+                       Mu, Mv, lam, kept, cut);
+    launch_check("vidal_svd_kernel");
   }
   void reduce_max(const double *x, int n, double *out) override {
     stale_check("reduce_max_kernel");

@@ -56,3 +56,40 @@ def message_list(net: "O.Network", chi: int):
             pad[:M.shape[0], :M.shape[1]] = M
             out.append(pad)
     return out
+
+
+def contract_network(net):
+    """Whole state vector of a (small) tensor network by one einsum over all bonds."""
+    letters = "abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ"
+    el = {}
+    for k, (u, v) in enumerate(net.edges):
+        el[(u, v)] = el[(v, u)] = letters[k]
+    phys = [letters[len(net.edges) + v] for v in range(net.n)]
+    subs = [phys[v] + "".join(el[(v, u)] for u in net.nb[v]) for v in range(net.n)]
+    psi = np.einsum(",".join(subs) + "->" + "".join(phys), *net.T, optimize=True).reshape(-1)
+    return psi / np.linalg.norm(psi)
+
+
+def isometry_error(net, lam):
+    """Eq. "IsometryDefinition": Gamma_v (T_v with S^{-1/2} removed from every leg), with S^2 on
+    all legs but one, contracted with its conjugate is proportional to the identity on that
+    leg.  Returns the largest deviation after dividing out the proportionality factor."""
+    S = {}
+    for (u, v), s in lam.items():
+        S[(u, v)] = S[(v, u)] = s
+    err = 0.0
+    for v in range(net.n):
+        G = net.T[v]
+        for u in net.nb[v]:
+            G = O.absorb(G, net.axis(v, u), np.diag(1.0 / np.sqrt(S[(v, u)])))
+        for u in net.nb[v]:
+            Y = G
+            for w in net.nb[v]:
+                if w != u:
+                    Y = O.absorb(Y, net.axis(v, w), np.diag(S[(v, w)] ** 2).astype(complex))
+            ax = net.axis(v, u)
+            others = [a for a in range(G.ndim) if a != ax]
+            I = np.tensordot(Y, G.conj(), axes=(others, others))
+            c = np.trace(I) / I.shape[0]
+            err = max(err, float(np.abs(I / c - np.eye(I.shape[0])).max()))
+    return err

@@ -411,3 +411,78 @@ def _tree_side(n, edges, e):
                 st.append(y)
     assert v not in seen
     return seen
+
+
+# --- explicit Vidal gauge ------------------------------------------------------------------------
+
+def test_vidal_gauge_identical_state_vs_oracle(ctx):
+    """The same converged, truncated state (infinite cell, chi = 16) transformed on both sides:
+    bond weights to 1e-10, <Z> unchanged, the result a BP fixed point whose groupings are
+    isometries."""
+    from ._state_io import isometry_error
+    print("[parity] Vidal gauge on an identical state", flush=True)
+    cell, chi = L.infinite_cell(), 16
+    net = O.Network(cell.n_sites, cell.edges, cell.colour)
+    O.solve(cell.n_sites, cell.edges, cell.colour, 1.2, 8, O.Options(chi=chi), net=net)
+    zo = np.array([net.expect_site(v, 3) for v in range(net.n)])
+    t, m, b = to_flat(net, chi)
+    s = _session(ctx, cell, 1.2, 8, chi)
+    s.set_state(t, m, b)
+    z0 = s.observe_z()
+    lam_g = s.vidal_gauge()
+    z1 = s.observe_z()
+    lam_o = net.vidal_gauge()
+    for e, (u, v) in enumerate(net.edges):
+        k = len(lam_o[(u, v)])
+        assert np.abs(lam_g[e, :k] - lam_o[(u, v)]).max() < 1e-10
+        assert np.all(lam_g[e, k:] == 0.0)
+    assert np.abs(z0 - zo).max() < 1e-12
+    assert np.abs(z1 - zo).max() < 1e-10
+    t2, m2, b2 = s.get_state()
+    g = from_flat(O.Network(cell.n_sites, cell.edges, cell.colour), chi, t2, m2, b2)
+    lam = {(u, v): lam_g[e, :int(b2[e])] for e, (u, v) in enumerate(net.edges)}
+    assert isometry_error(g, lam) < 1e-8
+    assert s.bp_sweep() < 1e-9
+    s.close()
+
+
+def test_vidal_gauge_keeps_the_state_on_a_tree(ctx):
+    """Untruncated tree: the transformed network contracts to the same state vector, which is the
+    circuit's (state vector simulation)."""
+    from ._state_io import contract_network
+    print("[parity] Vidal gauge on a tree", flush=True)
+    tr = L.random_tree(9, np.random.default_rng(21))
+    chi = 8
+    s = _session(ctx, tr, 0.9, 3, chi)
+    for _ in range(3):
+        s.step()
+    nets = []
+    for transform in (False, True):
+        if transform:
+            s.vidal_gauge()
+        t, m, b = s.get_state()
+        nets.append(from_flat(O.Network(tr.n_sites, tr.edges, tr.colour), chi, t, m, b))
+    s.close()
+    psi0, psi1 = contract_network(nets[0]), contract_network(nets[1])
+    assert np.abs(psi1 - psi0).max() < 1e-12
+    sv = SV.StateVector(tr.n_sites, tr.edges)
+    for _ in range(3):
+        sv.step(0.9)
+    assert abs(abs(np.vdot(sv.psi, psi0)) - 1.0) < 1e-12
+
+
+def test_vidal_gauge_mid_evolution_vs_oracle(ctx):
+    """Transforming in the middle of a truncated run changes nothing beyond rounding: 4 steps,
+    Vidal gauge, 3 more steps against 7 straight steps and against the oracle."""
+    print("[parity] Vidal gauge mid-evolution", flush=True)
+    lat = L.heavy_hex(3, 9)
+    ref = _gpu(ctx, lat, 0.8, 7, 6)
+    s = _session(ctx, lat, 0.8, 7, 6)
+    for _ in range(4):
+        s.step()
+    s.vidal_gauge()
+    zs = [s.step()["z"] for _ in range(3)]
+    s.close()
+    o = _ora(lat, 0.8, 7, 6)
+    assert np.abs(np.array(zs) - ref["z"][4:]).max() < 1e-8
+    assert np.abs(np.array(zs) - o.z[4:]).max() < 1e-8

@@ -16,6 +16,8 @@ from oracle import clifford as C
 from oracle import statevector as SV
 from paper_2306_14887_amd import lattice as L
 
+from ._state_io import contract_network, isometry_error
+
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -424,43 +426,6 @@ def test_infinite_cell_colourings_agree_untruncated():
 
 # --- explicit Vidal gauge ------------------------------------------------------------------------
 
-def _contract_tree(net):
-    """Whole state vector of a (small) tensor network by one einsum over all bonds."""
-    letters = "abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ"
-    el = {}
-    for k, (u, v) in enumerate(net.edges):
-        el[(u, v)] = el[(v, u)] = letters[k]
-    phys = [letters[len(net.edges) + v] for v in range(net.n)]
-    subs = [phys[v] + "".join(el[(v, u)] for u in net.nb[v]) for v in range(net.n)]
-    psi = np.einsum(",".join(subs) + "->" + "".join(phys), *net.T, optimize=True).reshape(-1)
-    return psi / np.linalg.norm(psi)
-
-
-def _isometry_error(net, lam):
-    """Eq. "IsometryDefinition": Gamma_v (T_v with S^{-1/2} removed from every leg), with S^2 on
-    all legs but one, contracted with its conjugate is proportional to the identity on that
-    leg.  Returns the largest deviation after dividing out the proportionality factor."""
-    S = {}
-    for (u, v), s in lam.items():
-        S[(u, v)] = S[(v, u)] = s
-    err = 0.0
-    for v in range(net.n):
-        G = net.T[v]
-        for u in net.nb[v]:
-            G = O.absorb(G, net.axis(v, u), np.diag(1.0 / np.sqrt(S[(v, u)])))
-        for u in net.nb[v]:
-            Y = G
-            for w in net.nb[v]:
-                if w != u:
-                    Y = O.absorb(Y, net.axis(v, w), np.diag(S[(v, w)] ** 2).astype(complex))
-            ax = net.axis(v, u)
-            others = [a for a in range(G.ndim) if a != ax]
-            I = np.tensordot(Y, G.conj(), axes=(others, others))
-            c = np.trace(I) / I.shape[0]
-            err = max(err, float(np.abs(I / c - np.eye(I.shape[0])).max()))
-    return err
-
-
 def test_vidal_gauge_on_a_tree_keeps_the_state():
     """On a tree the transform leaves the (normalised) state vector unchanged, its bond weights
     are the Schmidt coefficients (S^2 = bond spectrum), every grouping is an isometry and the
@@ -478,14 +443,14 @@ def test_vidal_gauge_on_a_tree_keeps_the_state():
     for key, m in net.M.items():
         net.M[key] = np.eye(m.shape[0], dtype=complex) / m.shape[0]
     net.bp(1e-14, 200)
-    psi0 = _contract_tree(net)
+    psi0 = contract_network(net)
     spec = {e: net.bond_spectrum(*e) for e in net.edges}
     lam = net.vidal_gauge()
-    assert np.abs(_contract_tree(net) - psi0).max() < 1e-12
+    assert np.abs(contract_network(net) - psi0).max() < 1e-12
     for e, s in lam.items():
         assert np.abs(s ** 2 - spec[e][:len(s)]).max() < 1e-12
         assert spec[e][len(s):].sum() < 1e-20
-    assert _isometry_error(net, lam) < 1e-10
+    assert isometry_error(net, lam) < 1e-10
     assert net.bp_sweep() < 1e-12
 
 
@@ -502,5 +467,20 @@ def test_vidal_gauge_on_the_infinite_cell():
     assert np.abs(z1 - z0).max() < 1e-12
     for e, s in lam.items():
         assert np.abs(s ** 2 - spec[e][:len(s)]).max() < 1e-12
-    assert _isometry_error(net, lam) < 1e-10
+    assert isometry_error(net, lam) < 1e-10
     assert net.bp_sweep() < 1e-10
+
+
+def test_vidal_gauge_mid_evolution_changes_nothing():
+    """Evolution continued from the Vidal gauge equals evolution in the message form (the
+    Methods state their equivalence): 4 steps, transform, 3 more steps vs 7 steps straight,
+    with truncation on the 29-qubit heavy-hex lattice."""
+    lat = L.heavy_hex(3, 9)
+    opt = O.Options(chi=6)
+    ref = O.solve(lat.n_sites, lat.edges, lat.colour, 0.8, 7, opt)
+    net = O.Network(lat.n_sites, lat.edges, lat.colour)
+    O.solve(lat.n_sites, lat.edges, lat.colour, 0.8, 4, opt, net=net)
+    net.vidal_gauge()
+    r = O.solve(lat.n_sites, lat.edges, lat.colour, 0.8, 3, opt, net=net)
+    assert max(ref.discarded) > 1e-6
+    assert np.abs(r.z - ref.z[4:]).max() < 1e-9
