@@ -31,6 +31,8 @@ What it computes (arXiv 2306.14887, Tindall, Fishman, Stoudenmire, Sels):
   are the spectrum of the two messages that meet on it (Network.bond_spectrum).
 * The explicit Vidal gauge (Methods, "The Vidal gauge"): the gauge transformation built from
   the messages (Network.vidal_gauge), equivalent to the message form in exact arithmetic.
+* The BP error estimate (Eq. "BPErrorEstimate"): the index of separability of the exactly
+  contracted edge environment in the symmetric gauge (Network.bp_error; small networks).
 * The infinite lattice ("Dynamics of the infinite heavy-hex lattice", Fig. 4) is its
   periodic unit cell given as a graph: BP on the 5-site quotient graph is BP on the
   infinite lattice with translation-invariant messages, so nothing here is specific to it.
@@ -402,6 +404,64 @@ class Network:
             self.M[(u, v)] = D
             self.M[(v, u)] = D.copy()
         return lam
+
+    def edge_environment(self, u: int, v: int) -> np.ndarray:
+        """The norm network <psi|psi> with edge (u, v) cut and everything else contracted exactly
+        (Methods, "Estimating the error of BP for general tensor networks", Fig.
+        "EdgeEnvironment"): a (d*d) x (d*d) matrix, rows the (ket, bra) pair of the cut on u's
+        side, columns on v's side, d the bond dimension.  Small networks only: every site first
+        becomes its norm tensor N_w = sum_s T_w[s] (x) conj(T_w[s]) (one leg of dimension d_e^2
+        per neighbour), then pairs of tensors are contracted greedily (smallest result first).
+        """
+        tensors = []
+        for w in range(self.n):
+            T = self.T[w]
+            k = T.ndim - 1
+            N = np.tensordot(T, T.conj(), axes=([0], [0]))          # legs ket..., bra...
+            perm = [x for i in range(k) for x in (i, k + i)]          # (ket_i, bra_i) adjacent
+            N = np.transpose(N, perm).reshape([T.shape[1 + i] ** 2 for i in range(k)])
+            labels = []
+            for x in self.nb[w]:
+                if {w, x} == {u, v}:
+                    labels.append(("cut", w))
+                else:
+                    labels.append(("bond", min(w, x), max(w, x)))
+            tensors.append((N, labels))
+        while len(tensors) > 1:
+            best = None
+            for i in range(len(tensors)):
+                for j in range(i + 1, len(tensors)):
+                    li, lj = tensors[i][1], tensors[j][1]
+                    common = [x for x in li if x in lj]
+                    if not common:
+                        continue
+                    size = 1
+                    for t_, l_ in ((tensors[i][0], li), (tensors[j][0], lj)):
+                        for dim, lab in zip(t_.shape, l_):
+                            if lab not in common:
+                                size *= dim
+                    if best is None or size < best[0]:
+                        best = (size, i, j, common)
+            if best is None:                       # disconnected pieces: outer product
+                best = (0, 0, 1, [])
+            _, i, j, common = best
+            (A, la), (B, lb) = tensors[i], tensors[j]
+            C = np.tensordot(A, B, axes=([la.index(x) for x in common], [lb.index(x) for x in common]))
+            lc = [x for x in la if x not in common] + [x for x in lb if x not in common]
+            tensors = [t for k_, t in enumerate(tensors) if k_ not in (i, j)] + [(C, lc)]
+        E, labels = tensors[0]
+        E = np.transpose(E, [labels.index(("cut", u)), labels.index(("cut", v))])
+        return E
+
+    def bp_error(self, u: int, v: int, cutoff: float = 1e-12):
+        """BP error estimate on edge (u, v) (Eq. "BPErrorEstimate"): 1 - sqrt(l_1^2 / sum l_i^2)
+        over the singular values l_i of the edge environment, taken in the symmetric gauge (the
+        state is first brought into it with vidal_gauge, which the paper prescribes for
+        consistency).  Returns (error, singular values normalised to unit 2-norm)."""
+        self.vidal_gauge(cutoff)
+        sv = np.linalg.svd(self.edge_environment(u, v), compute_uv=False)
+        sv = sv / np.linalg.norm(sv)
+        return float(1.0 - math.sqrt(sv[0] ** 2)), sv
 
     def bond_entropy(self, v: int, w: int) -> float:
         """s = -sum_i p_i log2 p_i over the Schmidt weights of the bond (Eq.

@@ -58,7 +58,7 @@ def message_list(net: "O.Network", chi: int):
     return out
 
 
-def contract_network(net):
+def contract_network(net, normalise=True):
     """Whole state vector of a (small) tensor network by one einsum over all bonds."""
     letters = "abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ"
     el = {}
@@ -67,7 +67,7 @@ def contract_network(net):
     phys = [letters[len(net.edges) + v] for v in range(net.n)]
     subs = [phys[v] + "".join(el[(v, u)] for u in net.nb[v]) for v in range(net.n)]
     psi = np.einsum(",".join(subs) + "->" + "".join(phys), *net.T, optimize=True).reshape(-1)
-    return psi / np.linalg.norm(psi)
+    return psi / np.linalg.norm(psi) if normalise else psi
 
 
 def isometry_error(net, lam):

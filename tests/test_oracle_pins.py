@@ -484,3 +484,99 @@ def test_vidal_gauge_mid_evolution_changes_nothing():
     r = O.solve(lat.n_sites, lat.edges, lat.colour, 0.8, 3, opt, net=net)
     assert max(ref.discarded) > 1e-6
     assert np.abs(r.z - ref.z[4:]).max() < 1e-9
+
+
+# --- BP error estimate ---------------------------------------------------------------------------
+
+def _open_cut_states(net, u, v):
+    """psi[a, b, s_0..s_{n-1}]: the network contracted over every bond but (u, v), whose two
+    halves stay open (a on u's side, b on v's side)."""
+    letters = "abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ"
+    el = {}
+    k = 2
+    for x, y in net.edges:
+        if {x, y} == {u, v}:
+            el[(u, v)], el[(v, u)] = letters[0], letters[1]
+        else:
+            el[(x, y)] = el[(y, x)] = letters[k]
+            k += 1
+    phys = [letters[k + w] for w in range(net.n)]
+    subs = [phys[w] + "".join(el[(w, x)] for x in net.nb[w]) for w in range(net.n)]
+    return np.einsum(",".join(subs) + "->ab" + "".join(phys), *net.T, optimize=True)
+
+
+def test_edge_environment_against_open_cut_states():
+    """On the 12-ring (a loop) the edge environment equals the overlaps of the states with the
+    cut bond left open, E[(a,a'),(b,b')] = <psi_{a'b'}|psi_{ab}>, computed through the full
+    physical state instead of the norm network; its trace is the norm."""
+    r = L.hexagon_ring()
+    net = O.Network(r.n_sites, r.edges, r.colour)
+    O.solve(r.n_sites, r.edges, r.colour, 1.1, 4, O.Options(chi=8), net=net)
+    rng = np.random.default_rng(12)
+    for x, y in net.edges:                  # a complex gauge: E is then complex, not Hermitian
+        d = net.bond_dim(x, y)
+        G = np.eye(d) + 0.3 * (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+        net.T[x] = O.absorb(net.T[x], net.axis(x, y), G)
+        net.T[y] = O.absorb(net.T[y], net.axis(y, x), np.linalg.inv(G).T)
+    u, v = net.edges[3]
+    E = net.edge_environment(u, v)
+    psi = _open_cut_states(net, u, v)
+    d = psi.shape[0]
+    flat = psi.reshape(d, d, -1)
+    want = np.einsum("abx,cdx->acbd", flat, flat.conj()).reshape(d * d, d * d)
+    assert np.abs(want.imag).max() > 1e-3 * np.abs(want).max()
+    assert np.abs(E - want).max() < 1e-12 * np.abs(want).max()
+    full = contract_network(net, normalise=False)
+    assert abs(np.trace(E) - np.vdot(full, full)) < 1e-12 * abs(np.trace(E))
+    # the estimate (Eq. "BPErrorEstimate") in the symmetric gauge, from the open-cut states
+    for key, m in net.M.items():
+        net.M[key] = np.eye(m.shape[0], dtype=complex) / m.shape[0]
+    net.bp(1e-14, 500)
+    err, sv = net.bp_error(u, v)
+    psi = _open_cut_states(net, u, v)
+    d = psi.shape[0]
+    flat = psi.reshape(d, d, -1)
+    s = np.linalg.svd(np.einsum("abx,cdx->acbd", flat, flat.conj()).reshape(d * d, d * d),
+                      compute_uv=False)
+    assert abs(err - (1.0 - math.sqrt(s[0] ** 2 / np.sum(s ** 2)))) < 1e-12
+    assert np.abs(sv - s / np.linalg.norm(s)).max() < 1e-12
+
+
+def test_bp_error_zero_on_trees_and_product_states_and_gauge_invariant():
+    """A tree's edge environment is rank one (cutting an edge disconnects the norm network), so
+    the estimate vanishes; so it does for a product state on a loop; and it does not depend on
+    the gauge the state was in before the symmetric gauge is fixed."""
+    rng = np.random.default_rng(8)
+    tr = L.random_tree(9, rng)
+    net = O.Network(tr.n_sites, tr.edges, tr.colour)
+    O.solve(tr.n_sites, tr.edges, tr.colour, 0.8, 3, O.Options(chi=8), net=net)
+    for e in net.edges:
+        assert net.bp_error(*e)[0] < 1e-13
+    r = L.hexagon_ring()
+    net = O.Network(r.n_sites, r.edges, r.colour)
+    O.solve(r.n_sites, r.edges, r.colour, 0.0, 3, O.Options(chi=4), net=net)
+    assert net.bp_error(*net.edges[0])[0] < 1e-13
+    O.solve(r.n_sites, r.edges, r.colour, 1.2, 5, O.Options(chi=4), net=net)
+    e0, s0 = net.bp_error(*net.edges[5])
+    assert e0 > 1e-4                                   # the loop correlations are visible
+    for x, y in net.edges:
+        d = net.bond_dim(x, y)
+        G = np.eye(d) + 0.3 * (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+        net.T[x] = O.absorb(net.T[x], net.axis(x, y), G)
+        net.T[y] = O.absorb(net.T[y], net.axis(y, x), np.linalg.inv(G).T)
+    for key, m in net.M.items():
+        net.M[key] = np.eye(m.shape[0], dtype=complex) / m.shape[0]
+    net.bp(1e-14, 500)
+    e1, s1 = net.bp_error(*net.edges[5])
+    assert abs(e1 - e0) < 1e-10 and np.abs(s1 - s0).max() < 1e-9
+
+
+def test_bp_error_vanishes_until_the_light_cone_wraps_the_loop():
+    """Untruncated rings: with the light cone (radius t) shorter than the loop the estimate is
+    zero to rounding; on a ring short enough for it to wrap it is not."""
+    for n, want_zero in ((6, False), (8, True), (10, True)):
+        rg = L.ring(n)
+        net = O.Network(rg.n_sites, rg.edges, rg.colour)
+        O.solve(rg.n_sites, rg.edges, rg.colour, 0.6, 4, O.Options(chi=16), net=net)
+        err = net.bp_error(*net.edges[0])[0]
+        assert (err < 1e-12) if want_zero else (err > 1e-6), (n, err)
