@@ -413,6 +413,36 @@ def infinite_lattice(chi: int, depth: int = 30) -> dict:
             "fp64_packed": packed}
 
 
+def bp_error_ring(steps: int = 5, chi: int = 4) -> dict:
+    """The BP error estimate (Eq. "BPErrorEstimate") on one heavy hexagon (the 12-qubit ring, the
+    paper's smallest loop): after each of `steps` Floquet steps at theta_h in {0, pi/8, pi/4,
+    3pi/8, pi/2}, the estimate on every edge (FP64, chi as given); reports the mean and the
+    largest over the edges, per step."""
+    import math
+
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    ring = L.hexagon_ring()
+    out = []
+    t0 = time.perf_counter()
+    with bpki.Context(0) as ctx:
+        for th in (0.0, math.pi / 8, math.pi / 4, 3 * math.pi / 8, math.pi / 2):
+            sess = ctx.session(bpki.spec_from_lattice(ring, th, steps, chi))
+            mean, worst = [], []
+            for _ in range(steps):
+                sess.step(observe=False)
+                errs = [sess.bp_error(e)[0] for e in range(ring.n_edges)]
+                mean.append(float(np.mean(errs)))
+                worst.append(float(np.max(errs)))
+            sess.close()
+            out.append({"theta_h": th, "mean_per_step": mean, "max_per_step": worst})
+    return {"lattice": "12-qubit heavy hexagon (ring)", "chi": chi, "steps": steps,
+            "runs": out, "seconds": time.perf_counter() - t0}
+
+
 def copy_probe(mib: int) -> int:
     """8 launches of torch's device copy kernel, each reading and writing ``mib`` MiB."""
     import torch
@@ -447,6 +477,8 @@ def main() -> int:
     ap.add_argument("--infinite", type=int, default=128, metavar="CHI",
                     help="bond dimension of the infinite-lattice section (5-site periodic cell, "
                          "3 theta_h x 30 steps, FP64 and mixed; 0 = skip)")
+    ap.add_argument("--bp-error", type=int, default=1,
+                    help="1: also the BP error estimate on the 12-qubit ring (5 theta_h, 5 steps)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 8 plain device-to-device copies of MIB MiB and exit "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -556,6 +588,9 @@ def main() -> int:
     if args.theta_batch:
         out["theta_batch"] = theta_batch(lat, chi, args.warmup + args.steps)
         print("theta batch done", file=sys.stderr, flush=True)
+    if args.bp_error:
+        out["bp_error_ring"] = bp_error_ring()
+        print("BP error estimate done", file=sys.stderr, flush=True)
     if args.infinite > 0:
         out["infinite_lattice"] = infinite_lattice(args.infinite)
         print("infinite lattice done", file=sys.stderr, flush=True)

@@ -214,6 +214,16 @@ int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy);
  * zero-padded, or NULL.  Equivalent to the message form in exact arithmetic (a conditioning
  * safeguard and the paper's stated representation). */
 int bpki_session_vidal_gauge(bpki_session *s, double *lambda);
+/* BP error estimate on edge `edge` (Methods, "Estimating the error of BP for general tensor
+ * networks", Eq. "BPErrorEstimate"): the state is first brought into the symmetric gauge (as
+ * bpki_session_vidal_gauge, left so afterwards), the norm network is cut along the edge and the
+ * rest contracted exactly into the chi^2 x chi^2 edge environment E, and
+ * error = 1 - sqrt(s_1^2 / sum_i s_i^2) over the singular values s_i of E (0 when the environment
+ * is rank one, as BP assumes).  Built for ring lattices (every site of degree 2, connected: the
+ * contraction is the chain of the sites' norm transfer matrices) with chi <= 16; other graphs or
+ * larger chi return -1.  spectrum: [chi^2] host, s_i / ||s|| descending, or NULL.  Allocates
+ * its work buffers (n + 4 matrices of chi^4 complex) for the call. */
+int bpki_session_bp_error(bpki_session *s, int32_t edge, double *error, double *spectrum);
 int bpki_session_observe_pauli(bpki_session *s, double *pauli);
 /* One whole Floquet step: X rotations, all gate layers, BP, then z (may be NULL). */
 int bpki_session_step(bpki_session *s, double *z, int32_t *iters, double *residual,

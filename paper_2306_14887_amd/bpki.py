@@ -98,6 +98,7 @@ def load(path: str | None = None):
         "bpki_session_observe_z": (C.c_int, [vp, dp]),
         "bpki_session_observe_bond_entropy": (C.c_int, [vp, dp]),
         "bpki_session_vidal_gauge": (C.c_int, [vp, dp]),
+        "bpki_session_bp_error": (C.c_int, [vp, C.c_int32, dp, dp]),
         "bpki_session_observe_pauli": (C.c_int, [vp, dp]),
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_clifford_inverse_step": (C.c_int, [vp, dp, ip, dp, dp]),
@@ -130,6 +131,7 @@ def exported_symbols() -> list[str]:
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
             "bpki_session_bp_sweep", "bpki_session_observe_z",
             "bpki_session_observe_bond_entropy", "bpki_session_vidal_gauge",
+            "bpki_session_bp_error",
             "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_clifford_inverse_step",
             "bpki_session_last_timing", "bpki_session_profile",
@@ -450,6 +452,15 @@ class Session:
         lam = np.zeros((int(np.asarray(self.spec.edges).size // 2), int(self.spec.chi)))
         _check(self.lib, self.lib.bpki_session_vidal_gauge(self.h, _ptr(lam, C.c_double)))
         return lam
+
+    def bp_error(self, edge: int):
+        """BP error estimate on `edge` of a ring lattice (chi <= 16); leaves the state in the
+        symmetric gauge.  Returns (error, singular values of the edge environment, unit norm)."""
+        err = C.c_double()
+        sp = np.zeros(int(self.spec.chi) ** 2)
+        _check(self.lib, self.lib.bpki_session_bp_error(self.h, int(edge), C.byref(err),
+                                                        _ptr(sp, C.c_double)))
+        return err.value, sp
 
     def observe_pauli(self) -> np.ndarray:
         out = np.zeros(len(self.spec.pauli))

@@ -81,6 +81,9 @@ struct Backend {
   // D1 = V diag(s^{1/2} / lambda), D2 = conj(V) diag(s^{1/2}) (s = lambda above cut * lambda_1,
   // unit 2-norm), both messages of the edge set to diag(s) / sum(s); lam [nprob][n] = s,
   // kept [nprob] (device).
+  // Norm transfer matrices of degree-2 sites, F [chi^2][chi^2] per problem (flip: legs swapped).
+  virtual void transfer(int chi, const double *const *T, const int *flip, double *const *F,
+                        int nprob) = 0;
   virtual void vidal_svd(int n, const double *const *evals, const double *const *vecs,
                          double *const *D1, double *const *D2, double *const *Mu,
                          double *const *Mv, double *lam, int *kept, double cut, int nprob) = 0;
@@ -171,6 +174,9 @@ class Engine {
   void observe_pauli_range(int k0, int k1, double *out);   // strings k0 .. k1-1
   void observe_entropy(double *out);              // host out [n_edges]: bond entropies (bits)
   void vidal_gauge(double *lambda);               // in place; host out [n_edges][chi] or NULL
+  bool is_ring() const;                           // connected, every site of degree 2
+  // BP error estimate on edge e of a ring (symmetric gauge first); spectrum [chi^2] or NULL
+  double bp_error(int e, double *spectrum);
   // Packed solves: sweeps until every member's residual is below bp_tol.  A member's messages
   // are frozen after the sweep that brought its own residual below the tolerance, so each member
   // follows its own BP schedule; per member: sweeps and final residual.

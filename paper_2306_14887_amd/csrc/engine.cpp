@@ -1310,6 +1310,109 @@ void Engine::vidal_gauge(double *lambda) {
   if (lambda) be_->d2h(lambda, P.vg_lam, (size_t)P.E * chi * 8);
 }
 
+bool Engine::is_ring() const {
+  const Plan &P = *plan_;
+  if (P.n < 3 || P.E != P.n) return false;
+  for (int v = 0; v < P.n; ++v)
+    if (P.deg[v] != 2) return false;
+  int prev = -1, cur = 0, steps = 0;
+  do {
+    const int next = P.nb[cur][0] != prev ? P.nb[cur][0] : P.nb[cur][1];
+    prev = cur;
+    cur = next;
+    ++steps;
+  } while (cur != 0 && steps <= P.n);
+  return steps == P.n;
+}
+
+// BP error estimate (Eq. "BPErrorEstimate") on edge e = (u, v) of a ring, in the symmetric gauge
+// (vidal_gauge first).  Cutting the edge leaves an open chain of norm transfer matrices: walking
+// from v away from u around to u, E = F_v ... F_u (chi^2 x chi^2: v's side of the cut as rows,
+// u's as columns).  The singular values come from eigh(E^H E); the estimate is
+// 1 - sqrt(s_1^2 / sum s_i^2).  Work buffers are allocated for the call (chi^2 <= 256).
+double Engine::bp_error(int e, double *spectrum) {
+  Plan &P = *plan_;
+  vidal_gauge(nullptr);
+  const int chi = P.chi, n = P.n, c2 = chi * chi;
+  const size_t c4 = (size_t)c2 * c2;
+  const int u = prob_.edges[2 * e], v = prob_.edges[2 * e + 1];
+  // walk: w_0 = v (coming from u), ..., w_{n-1} = u
+  std::vector<int> walk{v}, flip;
+  std::vector<int> from{u};
+  while ((int)walk.size() < n) {
+    const int w = walk.back(), pw = from.back();
+    const int nx = P.nb[w][0] != pw ? P.nb[w][0] : P.nb[w][1];
+    from.push_back(w);
+    walk.push_back(nx);
+  }
+  // buffers: n transfer matrices, two chain products, E^H E, eigenpairs; pointer arrays
+  const size_t mat = c4 * 16;
+  const size_t nptr = 5 * (size_t)n + 8;
+  char *buf = (char *)be_->alloc(mat * (n + 4) + (size_t)c2 * 8 + nptr * sizeof(void *) +
+                                 (size_t)n * 4);
+  if (!buf) return NAN;
+  auto M_ = [&](int i) { return (double *)(buf + mat * i); };
+  double *R0 = M_(n), *R1 = M_(n + 1), *H = M_(n + 2), *V = M_(n + 3);
+  double *ev = (double *)(buf + mat * (n + 4));
+  const void **pp = (const void **)((char *)ev + (size_t)c2 * 8);
+  int *fl = (int *)((char *)pp + nptr * sizeof(void *));
+  std::vector<const void *> ptrs;
+  std::vector<int> flips;
+  for (int k = 0; k < n; ++k) {
+    const int w = walk[k];
+    ptrs.push_back(P.T + 2 * P.toff[w]);
+    flips.push_back(P.nb[w][0] != from[k] ? 1 : 0);     // incoming leg is T's leg 1
+  }
+  for (int k = 0; k < n; ++k) ptrs.push_back(M_(k));
+  // chain: R_1 = F_0 F_1, R_k = R_{k-1} F_k (ping-pong), then E^H E, then eigh in/out
+  const size_t chain0 = ptrs.size();
+  double *prev = M_(0);
+  for (int k = 1; k < n; ++k) {
+    double *out = (k & 1) ? R0 : R1;
+    ptrs.push_back(prev);
+    ptrs.push_back(M_(k));
+    ptrs.push_back(out);
+    prev = out;
+  }
+  const size_t herm0 = ptrs.size();
+  ptrs.push_back(prev);
+  ptrs.push_back(prev);
+  ptrs.push_back(H);
+  ptrs.push_back(H);
+  ptrs.push_back(ev);
+  ptrs.push_back(V);
+  be_->h2d(pp, ptrs.data(), ptrs.size() * sizeof(void *));
+  be_->h2d(fl, flips.data(), flips.size() * 4);
+  auto at = [&](size_t i) { return (const double *const *)(pp + i); };
+  auto atw = [&](size_t i) { return (double *const *)(pp + i); };
+  be_->transfer(chi, at(0), fl, atw(n), n);
+  GemmDesc d;
+  d.M = d.N = d.K = d.Mi = d.Ni = d.Ki = c2;
+  d.a_mi = c2; d.a_ki = 1;
+  d.b_ki = c2; d.b_ni = 1;
+  d.c_mi = c2; d.c_ni = 1;
+  for (int k = 1; k < n; ++k) {
+    const size_t o = chain0 + 3 * (size_t)(k - 1);
+    be_->gemm(d, at(o), at(o + 1), atw(o + 2), 1);
+  }
+  GemmDesc h = d;                        // E^H E
+  h.a_mi = 1; h.a_ki = c2;
+  h.conjA = 1;
+  h.herm = 1;
+  be_->gemm(h, at(herm0), at(herm0 + 1), atw(herm0 + 2), 1);
+  be_->eigh(c2, c2, at(herm0 + 3), atw(herm0 + 4), atw(herm0 + 5), 1);
+  std::vector<double> l(c2);
+  be_->d2h(l.data(), ev, (size_t)c2 * 8);
+  be_->release(buf);
+  double tot = 0.0;
+  for (double x : l) tot += std::max(x, 0.0);
+  const double l1 = std::max(l[0], 0.0);
+  if (spectrum)
+    for (int i = 0; i < c2; ++i)
+      spectrum[i] = tot > 0 ? std::sqrt(std::max(l[i], 0.0) / tot) : 0.0;
+  return tot > 0 ? 1.0 - std::sqrt(l1 / tot) : NAN;
+}
+
 void Engine::observe_pauli(double *out) {
   int np = (int)prob_.pauli_offsets.size() - 1;
   for (int k = 0; k < np; ++k) {

@@ -486,3 +486,51 @@ def test_vidal_gauge_mid_evolution_vs_oracle(ctx):
     o = _ora(lat, 0.8, 7, 6)
     assert np.abs(np.array(zs) - ref["z"][4:]).max() < 1e-8
     assert np.abs(np.array(zs) - o.z[4:]).max() < 1e-8
+
+
+# --- BP error estimate ------------------------------------------------------------------------
+
+@pytest.mark.parametrize("theta,chi", [(math.pi / 4, 4), (3 * math.pi / 8, 4), (1.2, 8)])
+def test_bp_error_ring_vs_oracle(ctx, theta, chi):
+    """The 12-ring after 5 truncated steps, the same state on both sides: the estimate on every
+    edge to 1e-12 and the singular values of the edge environment (the small ones come from
+    eigh(E^H E), whose absolute accuracy is ~1e-16 s_1^2 / s_i) to 1e-7."""
+    import copy
+    print(f"[parity] BP error on the 12-ring theta={theta} chi={chi}", flush=True)
+    r = L.hexagon_ring()
+    net = O.Network(r.n_sites, r.edges, r.colour)
+    O.solve(r.n_sites, r.edges, r.colour, theta, 5, O.Options(chi=chi), net=net)
+    t, m, b = to_flat(net, chi)
+    s = _session(ctx, r, theta, 5, chi)
+    s.set_state(t, m, b)
+    for e in range(0, r.n_edges, 3):
+        err_g, sp_g = s.bp_error(e)
+        err_o, sp_o = copy.deepcopy(net).bp_error(*net.edges[e])
+        assert err_o > 1e-6
+        assert abs(err_g - err_o) < 1e-12, (e, err_g, err_o)
+        k = len(sp_o)
+        assert np.abs(sp_g[:k] - sp_o).max() < 1e-7
+        assert np.all(np.abs(sp_g[k:]) < 1e-7)
+    s.close()
+
+
+def test_bp_error_edge_cases(ctx):
+    from paper_2306_14887_amd import bpki as B
+    print("[parity] BP error edge cases", flush=True)
+    r = L.hexagon_ring()
+    s = _session(ctx, r, 0.0, 3, 4)
+    for _ in range(3):
+        s.step()
+    err, sp = s.bp_error(0)                      # product state: rank-one environment
+    assert err < 1e-13 and abs(sp[0] - 1.0) < 1e-13
+    with pytest.raises(B.BpkiError):
+        s.bp_error(99)
+    s.close()
+    s = _session(ctx, L.eagle(), 0.3, 1, 4)      # not a ring
+    with pytest.raises(B.BpkiError):
+        s.bp_error(0)
+    s.close()
+    s = _session(ctx, r, 0.3, 1, 32)             # chi^2 > 256
+    with pytest.raises(B.BpkiError):
+        s.bp_error(0)
+    s.close()
