@@ -379,11 +379,13 @@ class Network:
         edge is L R^T with Gram matrices L^H L = M_{u->v}^T and R^H R = M_{v->u}^T, so
         L = Q_L X^T and R = Q_R Y^T with isometric Q's, and the SVD X^T Y = U S V^H gives the
         Schmidt form (Q_L U) S (Q_R conj V)^T.  Inserting the identity X^{T+} U S V^H Y^{+}
-        (on the supports) on the bond and splitting S symmetrically, leg u->v of T_u absorbs
-        P_u = X^{T+} U S^{1/2} and leg v->u of T_v absorbs P_v = Y^{T+} conj(V) S^{1/2}.  S is
-        normalised to unit 2-norm (the state changes by a positive factor) and singular values
-        <= cutoff * s_1 are dropped.  The new messages are the BP fixed point diag(S) (unit
-        trace).  Returns {(u, v): S} in edge order.
+        (on the supports, up to a positive factor) on the bond and splitting S symmetrically,
+        leg u->v of T_u absorbs P_u = X^{T+} U W and leg v->u of T_v absorbs
+        P_v = Y^{T+} conj(V) W with W = (S / sum S)^{1/2}, the root of the new unit-trace message:
+        a state already in this gauge then gets P = 1 (the transform is idempotent and keeps the
+        tensors' scale).  S is normalised to unit 2-norm and singular values <= cutoff * s_1 are
+        dropped.  The new messages are the BP fixed point diag(S) / sum S.  Returns
+        {(u, v): S} in edge order.
         """
         lam, P = {}, {}
         for u, v in self.edges:
@@ -394,8 +396,9 @@ class Network:
             U, sv, Vh = U[:, keep], sv[keep], Vh[keep, :]
             sv = sv / np.linalg.norm(sv)
             lam[(u, v)] = sv
-            P[(u, v)] = Xp.T @ (U * np.sqrt(sv)[None, :])
-            P[(v, u)] = Yp.T @ (Vh.T * np.sqrt(sv)[None, :])
+            w = np.sqrt(sv / sv.sum())
+            P[(u, v)] = Xp.T @ (U * w[None, :])
+            P[(v, u)] = Yp.T @ (Vh.T * w[None, :])
         for v in range(self.n):
             for u in self.nb[v]:
                 self.T[v] = absorb(self.T[v], self.axis(v, u), P[(v, u)])

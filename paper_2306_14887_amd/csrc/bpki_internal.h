@@ -81,9 +81,10 @@ struct Backend {
   // D1 = V diag(s^{1/2} / lambda), D2 = conj(V) diag(s^{1/2}) (s = lambda above cut * lambda_1,
   // unit 2-norm), both messages of the edge set to diag(s) / sum(s); lam [nprob][n] = s,
   // kept [nprob] (device).
-  // Norm transfer matrices of degree-2 sites, F [chi^2][chi^2] per problem (flip: legs swapped).
-  virtual void transfer(int chi, const double *const *T, const int *flip, double *const *F,
-                        int nprob) = 0;
+  // Norm transfer matrices of degree-2 sites, F [chi^2][chi^2] per problem (flip: legs swapped),
+  // each multiplied by scale[p] (device).
+  virtual void transfer(int chi, const double *const *T, const int *flip, const double *scale,
+                        double *const *F, int nprob) = 0;
   virtual void vidal_svd(int n, const double *const *evals, const double *const *vecs,
                          double *const *D1, double *const *D2, double *const *Mu,
                          double *const *Mv, double *lam, int *kept, double cut, int nprob) = 0;

@@ -1349,19 +1349,27 @@ double Engine::bp_error(int e, double *spectrum) {
   const size_t mat = c4 * 16;
   const size_t nptr = 5 * (size_t)n + 8;
   char *buf = (char *)be_->alloc(mat * (n + 4) + (size_t)c2 * 8 + nptr * sizeof(void *) +
-                                 (size_t)n * 4);
+                                 (size_t)n * 12);
   if (!buf) return NAN;
   auto M_ = [&](int i) { return (double *)(buf + mat * i); };
   double *R0 = M_(n), *R1 = M_(n + 1), *H = M_(n + 2), *V = M_(n + 3);
   double *ev = (double *)(buf + mat * (n + 4));
   const void **pp = (const void **)((char *)ev + (size_t)c2 * 8);
-  int *fl = (int *)((char *)pp + nptr * sizeof(void *));
+  double *sc = (double *)((char *)pp + nptr * sizeof(void *));
+  int *fl = (int *)(sc + n);
   std::vector<const void *> ptrs;
   std::vector<int> flips;
+  // each transfer matrix is divided by ||T_w||^2 (positive factors leave the estimate unchanged
+  // and keep the product of n of them in range)
+  std::vector<double> scales(n), th((size_t)2 * P.tsize[walk[0]]);
   for (int k = 0; k < n; ++k) {
     const int w = walk[k];
     ptrs.push_back(P.T + 2 * P.toff[w]);
     flips.push_back(P.nb[w][0] != from[k] ? 1 : 0);     // incoming leg is T's leg 1
+    be_->d2h(th.data(), P.T + 2 * P.toff[w], (size_t)P.tsize[w] * 16);
+    double nrm2 = 0.0;
+    for (double x : th) nrm2 += x * x;
+    scales[k] = nrm2 > 0.0 ? 1.0 / nrm2 : 1.0;
   }
   for (int k = 0; k < n; ++k) ptrs.push_back(M_(k));
   // chain: R_1 = F_0 F_1, R_k = R_{k-1} F_k (ping-pong), then E^H E, then eigh in/out
@@ -1383,9 +1391,10 @@ double Engine::bp_error(int e, double *spectrum) {
   ptrs.push_back(V);
   be_->h2d(pp, ptrs.data(), ptrs.size() * sizeof(void *));
   be_->h2d(fl, flips.data(), flips.size() * 4);
+  be_->h2d(sc, scales.data(), scales.size() * 8);
   auto at = [&](size_t i) { return (const double *const *)(pp + i); };
   auto atw = [&](size_t i) { return (double *const *)(pp + i); };
-  be_->transfer(chi, at(0), fl, atw(n), n);
+  be_->transfer(chi, at(0), fl, sc, atw(n), n);
   GemmDesc d;
   d.M = d.N = d.K = d.Mi = d.Ni = d.Ki = c2;
   d.a_mi = c2; d.a_ki = 1;

@@ -1926,10 +1926,10 @@ __global__ __launch_bounds__(256) void bond_entropy_kernel(int n, const double *
 // Symmetric Vidal gauge (Methods, "The Vidal gauge"), one workgroup per edge (u, v) with
 // C = X^T Y, X and Y the square roots of the two messages on the edge.  From the eigenpairs
 // (l_i descending, columns of V) of C^H C the singular values are lambda_i = sqrt(l_i); those
-// above cut * lambda_1 are kept and normalised to unit 2-norm (s_i), the rest dropped.  Writes
-// D1 = V diag(s_i^{1/2} / lambda_i) (so C D1 = U S^{1/2}), D2 = conj(V) diag(s_i^{1/2}), the
-// BP fixed point diag(s) / sum(s) into both messages of the edge, s (zero-padded) and the kept
-// count.  n <= 256.
+// above cut * lambda_1 are kept and normalised to unit 2-norm (s_i), the rest dropped.  With
+// w_i = (s_i / sum s)^{1/2}, writes D1 = V diag(w_i / lambda_i) (so C D1 = U W),
+// D2 = conj(V) diag(w_i), the BP fixed point diag(s) / sum(s) into both messages of the edge,
+// s (zero-padded) and the kept count.  n <= 256.
 __global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *const *evals,
                                                         const double *const *vecs,
                                                         double *const *D1, double *const *D2,
@@ -1960,8 +1960,6 @@ __global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *con
   acc = 0.0;
   for (int i = tid; i < n; i += 256) {
     const double si = sv[i] * inv;
-    f1[i] = si > 0.0 ? sqrt(si) / sv[i] : 0.0;
-    f2[i] = sqrt(si);
     lam[(size_t)e * n + i] = si;
     acc += si;
   }
@@ -1969,6 +1967,14 @@ __global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *con
   if (tid == 0) sum_s = ss;
   __syncthreads();
   const double isum = sum_s > 0.0 ? 1.0 / sum_s : 0.0;
+  // W = (S / sum S)^{1/2}, the root of the new unit-trace message: a state already in this gauge
+  // gets P = 1 (idempotent, scale kept)
+  for (int i = tid; i < n; i += 256) {
+    const double wi = sqrt(sv[i] * inv * isum);
+    f1[i] = sv[i] > 0.0 ? wi / sv[i] : 0.0;
+    f2[i] = wi;
+  }
+  __syncthreads();
   const double2 *V = reinterpret_cast<const double2 *>(vecs[e]);
   double2 *d1 = reinterpret_cast<double2 *>(D1[e]), *d2 = reinterpret_cast<double2 *>(D2[e]);
   double2 *mu = reinterpret_cast<double2 *>(Mu[e]), *mv = reinterpret_cast<double2 *>(Mv[e]);
@@ -1986,10 +1992,12 @@ __global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *con
 
 // Norm transfer matrix of a degree-2 site (Methods, "Estimating the error of BP for general
 // tensor networks"): F[(a a'), (b b')] = sum_s T[s][a][b] conj(T[s][a'][b']), a the leg towards the
-// previous site of a walk around a ring and b towards the next (flip: they are T's legs 1 and 0).
+// previous site of a walk around a ring and b towards the next (flip: they are T's legs 1 and 0),
+// times scale[p] (the caller's 1 / ||T||^2 keeps long products in range).
 // Grid (ceil(chi^4 / 256), nprob).
 __global__ __launch_bounds__(256) void transfer_kernel(int chi, const double *const *T,
-                                                       const int *flip, double *const *F) {
+                                                       const int *flip, const double *scale,
+                                                       double *const *F) {
   const int p = blockIdx.y;
   const long c2 = (long)chi * chi, c4 = c2 * c2;
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -2006,7 +2014,7 @@ __global__ __launch_bounds__(256) void transfer_kernel(int chi, const double *co
     re += x.x * y.x + x.y * y.y;           // x * conj(y)
     im += x.y * y.x - x.x * y.y;
   }
-  reinterpret_cast<double2 *>(F[p])[idx] = make_double2(re, im);
+  reinterpret_cast<double2 *>(F[p])[idx] = make_double2(re * scale[p], im * scale[p]);
 }
 
 __global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n, double *out) {
@@ -2545,13 +2553,13 @@ class HipBackend : public Backend {
                        Mu, Mv, lam, kept, cut);
     launch_check("vidal_svd_kernel");
   }
-  void transfer(int chi, const double *const *T, const int *flip, double *const *F,
-                int nprob) override {
+  void transfer(int chi, const double *const *T, const int *flip, const double *scale,
+                double *const *F, int nprob) override {
     if (nprob <= 0) return;
     const long c4 = (long)chi * chi * chi * chi;
     stale_check("transfer_kernel");
     hipLaunchKernelGGL(transfer_kernel, dim3((unsigned)((c4 + 255) / 256), nprob), dim3(256), 0,
-                       s_, chi, T, flip, F);
+                       s_, chi, T, flip, scale, F);
     launch_check("transfer_kernel");
   }
   void reduce_max(const double *x, int n, double *out) override {

@@ -534,3 +534,26 @@ def test_bp_error_edge_cases(ctx):
     with pytest.raises(B.BpkiError):
         s.bp_error(0)
     s.close()
+
+
+def test_vidal_gauge_repeated_keeps_scale_and_bp_error(ctx):
+    """Regression: at the Clifford point every bond spectrum is flat; twelve transforms in a row
+    keep the tensors (idempotence) and the BP error of the untruncated 2-step state stays 0 on
+    every edge (a growing scale once overflowed the eigensolver's norm)."""
+    from ._state_io import from_flat
+    print("[parity] repeated Vidal gauge at the Clifford point", flush=True)
+    r = L.hexagon_ring()
+    s = _session(ctx, r, math.pi / 2, 2, 4)
+    for _ in range(2):
+        s.step()
+    s.vidal_gauge()
+    t1, _, _ = s.get_state()
+    for _ in range(11):
+        s.vidal_gauge()
+    t12, _, _ = s.get_state()
+    n1 = np.linalg.norm(t1.reshape(r.n_sites, -1), axis=1)
+    n12 = np.linalg.norm(t12.reshape(r.n_sites, -1), axis=1)
+    assert np.abs(n12 / n1 - 1.0).max() < 1e-10
+    errs = [s.bp_error(e)[0] for e in range(r.n_edges)]
+    s.close()
+    assert max(errs) < 1e-12, errs

@@ -580,3 +580,24 @@ def test_bp_error_vanishes_until_the_light_cone_wraps_the_loop():
         O.solve(rg.n_sites, rg.edges, rg.colour, 0.6, 4, O.Options(chi=16), net=net)
         err = net.bp_error(*net.edges[0])[0]
         assert (err < 1e-12) if want_zero else (err > 1e-6), (n, err)
+
+
+@pytest.mark.parametrize("theta", [math.pi / 2, 1.1])
+def test_vidal_gauge_is_idempotent(theta):
+    """On a state already in the symmetric gauge every gauge factor is unitary (the identity up
+    to the SVD's freedom within degenerate singular values and its phases), so a repeated
+    transform keeps every tensor's norm, the messages and the state.  (The Clifford point has
+    flat spectra, where that freedom is largest.)"""
+    import copy
+    r = L.hexagon_ring()
+    net = O.Network(r.n_sites, r.edges, r.colour)
+    O.solve(r.n_sites, r.edges, r.colour, theta, 2, O.Options(chi=4), net=net)
+    net.vidal_gauge()
+    before = copy.deepcopy(net)
+    for _ in range(3):
+        net.vidal_gauge()
+    for v in range(net.n):
+        assert abs(np.linalg.norm(net.T[v]) / np.linalg.norm(before.T[v]) - 1.0) < 1e-12
+    for k in net.M:
+        assert np.abs(net.M[k] - before.M[k]).max() < 1e-13
+    assert abs(abs(np.vdot(contract_network(net), contract_network(before))) - 1.0) < 1e-12
