@@ -107,6 +107,36 @@ def msg_sqrt(M: np.ndarray, eps_eig: float):
     return X, Xp
 
 
+def contract_greedy(tensors):
+    """Contract a list of (array, labels) over all shared labels, pairwise, always taking the
+    pair whose result is smallest (pieces without shared labels are joined by outer products).
+    Returns a one-element list.  Plain and exact; for the small networks of the diagnostics."""
+    tensors = list(tensors)
+    while len(tensors) > 1:
+        best = None
+        for i in range(len(tensors)):
+            for j in range(i + 1, len(tensors)):
+                li, lj = tensors[i][1], tensors[j][1]
+                common = [x for x in li if x in lj]
+                if not common:
+                    continue
+                size = 1
+                for t_, l_ in ((tensors[i][0], li), (tensors[j][0], lj)):
+                    for dim, lab in zip(t_.shape, l_):
+                        if lab not in common:
+                            size *= dim
+                if best is None or size < best[0]:
+                    best = (size, i, j, common)
+        if best is None:                       # disconnected pieces: outer product
+            best = (0, 0, 1, [])
+        _, i, j, common = best
+        (A, la), (B, lb) = tensors[i], tensors[j]
+        C = np.tensordot(A, B, axes=([la.index(x) for x in common], [lb.index(x) for x in common]))
+        lc = [x for x in la if x not in common] + [x for x in lb if x not in common]
+        tensors = [t for k_, t in enumerate(tensors) if k_ not in (i, j)] + [(C, lc)]
+    return tensors
+
+
 @dataclass
 class Options:
     chi: int
@@ -320,6 +350,39 @@ class Network:
         val = np.trace(PAULI[op] @ rho) / np.trace(rho)
         return float(val.real)
 
+    def expect_pauli_cluster(self, sites, ops) -> float:
+        """<P> of a Pauli string on any connected cluster, loops included: the cluster's norm
+        network (operators on the ket, every leg leaving the cluster closed with its incoming BP
+        message) is contracted exactly, Re(<P>_BP / <I>_BP).  On a tree cluster this is
+        expect_pauli; a cluster that is the whole lattice is the exact expectation in the state.
+        """
+        sites = [int(x) for x in sites]
+        opmap = {x: int(o) for x, o in zip(sites, ops)}
+        cset = set(sites)
+
+        def value(with_ops: bool) -> complex:
+            tensors = []
+            for w in sites:
+                O = PAULI[opmap[w]] if with_ops else PAULI[0]
+                Y = np.tensordot(O, self.T[w], axes=([1], [0]))
+                out_legs = []
+                for i, x in enumerate(self.nb[w]):
+                    if x in cset:
+                        out_legs.append(1 + i)
+                    else:
+                        Y = absorb(Y, 1 + i, self.M[(x, w)])
+                closed = [a for a in range(Y.ndim) if a not in out_legs]   # physical + cut legs
+                N = np.tensordot(Y, self.T[w].conj(), axes=(closed, closed))
+                k = len(out_legs)
+                perm = [q for i in range(k) for q in (i, k + i)]
+                dims = [self.T[w].shape[a] ** 2 for a in out_legs]
+                N = np.transpose(N, perm).reshape(dims) if k else N
+                labels = [(min(w, self.nb[w][a - 1]), max(w, self.nb[w][a - 1])) for a in out_legs]
+                tensors.append((N, labels))
+            return complex(np.asarray(contract_greedy(tensors)[0][0]))
+
+        return float((value(True) / value(False)).real)
+
     def expect_pauli(self, sites, ops) -> float:
         """<P> of a Pauli string on a cluster whose induced subgraph is a tree.
 
@@ -430,28 +493,7 @@ class Network:
                 else:
                     labels.append(("bond", min(w, x), max(w, x)))
             tensors.append((N, labels))
-        while len(tensors) > 1:
-            best = None
-            for i in range(len(tensors)):
-                for j in range(i + 1, len(tensors)):
-                    li, lj = tensors[i][1], tensors[j][1]
-                    common = [x for x in li if x in lj]
-                    if not common:
-                        continue
-                    size = 1
-                    for t_, l_ in ((tensors[i][0], li), (tensors[j][0], lj)):
-                        for dim, lab in zip(t_.shape, l_):
-                            if lab not in common:
-                                size *= dim
-                    if best is None or size < best[0]:
-                        best = (size, i, j, common)
-            if best is None:                       # disconnected pieces: outer product
-                best = (0, 0, 1, [])
-            _, i, j, common = best
-            (A, la), (B, lb) = tensors[i], tensors[j]
-            C = np.tensordot(A, B, axes=([la.index(x) for x in common], [lb.index(x) for x in common]))
-            lc = [x for x in la if x not in common] + [x for x in lb if x not in common]
-            tensors = [t for k_, t in enumerate(tensors) if k_ not in (i, j)] + [(C, lc)]
+        tensors = contract_greedy(tensors)
         E, labels = tensors[0]
         E = np.transpose(E, [labels.index(("cut", u)), labels.index(("cut", v))])
         return E

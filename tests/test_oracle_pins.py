@@ -601,3 +601,43 @@ def test_vidal_gauge_is_idempotent(theta):
     for k in net.M:
         assert np.abs(net.M[k] - before.M[k]).max() < 1e-13
     assert abs(abs(np.vdot(contract_network(net), contract_network(before))) - 1.0) < 1e-12
+
+
+# --- Pauli strings on clusters with a loop -------------------------------------------------------
+
+def _ring_with_pendants():
+    """The 12-qubit heavy hexagon with one extra qubit on sites 0 and 6 (14 sites, one loop)."""
+    r = L.hexagon_ring()
+    edges = np.vstack([r.edges, [[0, 12], [6, 13]]]).astype(np.int32)
+    return L.Lattice(14, edges, L.greedy_colouring(14, edges), name="ring12p2")
+
+
+def test_cluster_contraction_equals_tree_path_on_trees():
+    lat = L.heavy_hex(3, 9)
+    net = O.Network(lat.n_sites, lat.edges, lat.colour)
+    O.solve(lat.n_sites, lat.edges, lat.colour, 0.7, 4, O.Options(chi=8), net=net)
+    for p in L.random_pauli_strings(lat, 6, seed=3, wmin=3, wmax=9):
+        a = net.expect_pauli(p.sites, p.ops)
+        b = net.expect_pauli_cluster(p.sites, p.ops)
+        assert abs(a - b) < 1e-12
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.2])
+def test_loop_cluster_covering_the_lattice_is_exact(theta):
+    """A cluster that is the whole lattice cuts nothing, so its value is the exact expectation:
+    strings on all 14 sites of the ring with two pendants (a loop plus branches), untruncated,
+    against the state vector."""
+    lat = _ring_with_pendants()
+    net = O.Network(lat.n_sites, lat.edges, lat.colour)
+    O.solve(lat.n_sites, lat.edges, lat.colour, theta, 3, O.Options(chi=16), net=net)
+    sv = SV.StateVector(lat.n_sites, lat.edges)
+    for _ in range(3):
+        sv.step(theta)
+    rng = np.random.default_rng(int(theta * 10))
+    for _ in range(4):
+        ops = [int(x) for x in rng.integers(0, 4, lat.n_sites)]
+        ops[int(rng.integers(12))] = int(rng.integers(1, 4))
+        sites = list(range(lat.n_sites))
+        want = sv.expect_pauli([s for s, o in zip(sites, ops) if o], [o for o in ops if o])
+        got = net.expect_pauli_cluster(sites, [o for o in ops])
+        assert abs(got - want) < 1e-11, (ops, got, want)
