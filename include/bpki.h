@@ -11,14 +11,19 @@
  *   gauge, truncating every bond to at most chi (Methods, "The simple update procedure"), regauges
  *   with BP (Methods, "Belief propagation on a tensor network state",
  *   Eq. "MessageTensorSelfConsistency") and reads expectation values off the converged messages
- *   (Eq. "SingleSIte"; Pauli strings on tree clusters are contracted exactly inside the cluster).
+ *   (Eq. "SingleSIte"; a Pauli string's cluster is contracted exactly inside, BP messages closing
+ *   the legs that leave it).
  *
  * Conventions shared by all entry points
  *   - Sites are 0-based; an edge is an unordered pair (u, v), u != v.  Every site has degree 1..3.
  *   - colour[e] is a proper edge colouring (edges that share a site differ).  Gate layers run in
  *     ascending colour.  NULL asks the library for the greedy colouring over the edge list sorted by
  *     (min, max) endpoint (smallest colour free at both ends).
- *   - Pauli ops: 1 = X, 2 = Y, 3 = Z.  A string's sites must induce a tree in the lattice.
+ *   - Pauli ops: 1 = X, 2 = Y, 3 = Z.  A string's sites must induce a connected subgraph that is a
+ *     tree or has exactly one loop.  A loop cluster (chi <= 64) is contracted as the trace of the
+ *     product of its loop sites' chi^2 x chi^2 norm transfer matrices (branches folded in first):
+ *     O(m chi^6) for a loop of m sites, with three chi^4-complex work matrices allocated per string;
+ *     a cluster that is the whole lattice gives the exact expectation in the state.
  *   - A periodic lattice is passed as its quotient graph (one cell with the periodic edges
  *     closed on itself; it must stay a simple graph): BP on it is BP on the infinite lattice with
  *     translation-invariant messages ("Dynamics of the infinite heavy-hex lattice", Fig. 4: the
@@ -122,7 +127,7 @@ void bpki_destroy(bpki_ctx *ctx);
 const char *bpki_last_error(void);
 
 /* Host-only checks (no device needed): ranges, graph (self loops, duplicates, degree 1..3),
- * colouring, Pauli strings (valid ops, distinct sites, tree clusters). */
+ * colouring, Pauli strings (valid ops, distinct sites, clusters with at most one loop). */
 int bpki_validate(const bpki_problem *p);
 
 /* Device bytes a solve of *p holds: site tensors (sum_v 2*chi^deg complex), messages

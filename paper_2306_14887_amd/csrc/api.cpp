@@ -125,7 +125,7 @@ extern "C" int bpki_validate(const bpki_problem *p) {
         if (!s.insert(q).second) return fail(-1, "repeated site in a Pauli string");
         if (p->pauli_ops[i] < 1 || p->pauli_ops[i] > 3) return fail(-1, "Pauli op must be 1..3");
       }
-      // induced subgraph must be a tree: connected with |S|-1 edges
+      // induced subgraph: connected with |S| - 1 edges (a tree) or |S| edges (one loop)
       int m = 0;
       std::map<int, std::vector<int>> adj;
       for (int ed = 0; ed < E; ++ed) {
@@ -136,7 +136,10 @@ extern "C" int bpki_validate(const bpki_problem *p) {
           adj[v].push_back(u);
         }
       }
-      if (m != (int)s.size() - 1) return fail(-1, "Pauli cluster does not induce a tree");
+      if (m != (int)s.size() - 1 && m != (int)s.size())
+        return fail(-1, "Pauli cluster must induce a tree or a graph with one loop");
+      if (m == (int)s.size() && p->chi > 64)
+        return fail(-1, "a Pauli cluster with a loop needs chi <= 64");
       std::set<int> vis;
       std::vector<int> st{*s.begin()};
       while (!st.empty()) {

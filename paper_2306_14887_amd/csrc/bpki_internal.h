@@ -81,6 +81,8 @@ struct Backend {
   // D1 = V diag(s^{1/2} / lambda), D2 = conj(V) diag(s^{1/2}) (s = lambda above cut * lambda_1,
   // unit 2-norm), both messages of the edge set to diag(s) / sum(s); lam [nprob][n] = s,
   // kept [nprob] (device).
+  // out[0..1] = trace of the n x n complex matrix R (device).
+  virtual void trace(const double *R, int n, double *out) = 0;
   // Norm transfer matrices of degree-2 sites, F [chi^2][chi^2] per problem (flip: legs swapped),
   // each multiplied by scale[p] (device).
   virtual void transfer(int chi, const double *const *T, const int *flip, const double *scale,

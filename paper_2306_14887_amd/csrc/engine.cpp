@@ -1506,7 +1506,116 @@ double Engine::pauli_value(int k, bool with_ops) {
     result = r[0] + r[6];       // Re(rho00 + rho11); imaginary part ~ 0 for Hermitian ops
     return nullptr;
   };
-  env(sites[0], -1);
+  // a tree cluster: contract towards its first site
+  std::set<int> cs(sites.begin(), sites.end());
+  int inner = 0;
+  for (int v : sites)
+    for (int u : P.nb[v]) inner += cs.count(u) ? 1 : 0;
+  inner /= 2;
+  if (inner == (int)sites.size() - 1) {
+    env(sites[0], -1);
+    be_->sync();
+    for (void *q : tmp) be_->release(q);
+    return result;
+  }
+  // a cluster with one loop: the branches hanging off the loop are contracted into
+  // environments as above; every loop site becomes its norm transfer matrix
+  // F[(a a'), (b b')] = sum T'[s][a][b][x] conj(T[s][a'][b'][x]) (a: leg to the previous loop
+  // site, b: to the next, x: the remaining leg, already closed with its environment, T' the
+  // operator applied to the ket), scaled by 1 / ||T||^2; the value is Tr(F_0 F_1 ... F_{m-1}).
+  std::map<int, int> cdeg;
+  for (int v : sites)
+    for (int u : P.nb[v]) cdeg[v] += cs.count(u) ? 1 : 0;
+  std::set<int> cyc = cs;
+  std::vector<int> leaves;
+  for (int v : sites)
+    if (cdeg[v] == 1) leaves.push_back(v);
+  while (!leaves.empty()) {
+    const int v = leaves.back();
+    leaves.pop_back();
+    cyc.erase(v);
+    for (int u : P.nb[v])
+      if (cyc.count(u) && --cdeg[u] == 1) leaves.push_back(u);
+  }
+  std::vector<int> loop{*cyc.begin()};
+  for (int prev = -1;;) {
+    const int w = loop.back();
+    int nx = -1;
+    for (int u : P.nb[w])
+      if (cyc.count(u) && u != prev && (nx < 0 || u < nx)) nx = u;
+    if (nx < 0 || loop.size() > cyc.size()) {      // not a single loop (rejected on input)
+      for (void *q : tmp) be_->release(q);
+      return NAN;
+    }
+    if (nx == loop.front() && loop.size() > 2) break;
+    prev = w;
+    loop.push_back(nx);
+  }
+  const int m = (int)loop.size();
+  const size_t c4 = (size_t)c2 * c2;
+  double *F = alloc(c4), *Ra = alloc(c4), *Rb = alloc(c4), *acc = nullptr;
+  std::vector<double> th;
+  for (int k = 0; k < m; ++k) {
+    const int v = loop[k], pv = loop[(k + m - 1) % m], nx = loop[(k + 1) % m];
+    const int d = P.deg[v];
+    Layout L = t_layout(d, chi);
+    const double *Tv = P.T + 2 * P.toff[v];
+    double *cur = alloc((size_t)P.tsize[v]);
+    const int o = with_ops ? op[v] : 0;
+    be_->h2d(opbuf, PM[o], sizeof(PM[o]));
+    int64_t half = P.tsize[v] / 2;
+    be_->h2d(hbuf, &half, 8);
+    const void *pp[2] = {Tv, cur};
+    be_->h2d(parr, pp, sizeof(pp));
+    be_->apply_op((const double *const *)parr, (double *const *)(parr + 1), hbuf, opbuf, 1);
+    int lp = -1, ln = -1, lx = -1;
+    for (int i = 0; i < d; ++i) {
+      const int u = P.nb[v][i];
+      if (u == pv) { lp = i; continue; }
+      if (u == nx) { ln = i; continue; }
+      lx = i;
+      const double *E = cs.count(u) ? env(u, v) : P.M + 2 * (size_t)P.in_msg[v][i] * c2;
+      double *nxt = alloc((size_t)P.tsize[v]);
+      gemm1(leg_desc(d, i, L, L, chi), cur, E, nxt);
+      cur = nxt;
+    }
+    th.resize((size_t)2 * P.tsize[v]);
+    be_->d2h(th.data(), Tv, (size_t)P.tsize[v] * 16);
+    double nrm2 = 0.0;
+    for (double x : th) nrm2 += x * x;
+    GemmDesc g;
+    g.M = (int)c2; g.Mi = chi; g.a_mo = L.leg[lp]; g.a_mi = L.leg[ln];
+    g.N = (int)c2; g.Ni = chi; g.b_no = L.leg[lp]; g.b_ni = L.leg[ln];
+    g.c_mo = c2 * chi; g.c_mi = chi; g.c_no = c2; g.c_ni = 1;
+    g.conjB = 1;
+    if (lx < 0) {                      // K = s
+      g.K = 2; g.Ki = 2; g.a_ki = L.s; g.b_ki = L.s;
+    } else {                           // K = (s, x)
+      g.K = 2 * chi; g.Ki = chi;
+      g.a_ko = L.s; g.a_ki = L.leg[lx];
+      g.b_ko = L.s; g.b_ki = L.leg[lx];
+    }
+    g.alpha_re = nrm2 > 0.0 ? 1.0 / nrm2 : 1.0;
+    double *dst = k == 0 ? Ra : F;
+    gemm1(g, cur, Tv, dst);
+    if (k > 0) {
+      double *out = acc == Ra ? Rb : Ra;
+      GemmDesc c;
+      c.M = c.N = c.K = c.Mi = c.Ni = c.Ki = (int)c2;
+      c.a_mi = c2; c.a_ki = 1;
+      c.b_ki = c2; c.b_ni = 1;
+      c.c_mi = c2; c.c_ni = 1;
+      gemm1(c, acc, F, out);
+      acc = out;
+    } else {
+      acc = Ra;
+    }
+  }
+  double *tr = alloc(1);
+  be_->trace(acc, (int)c2, tr);
+  double t2[2];
+  be_->d2h(t2, tr, sizeof(t2));
+  result = t2[0];
   be_->sync();
   for (void *q : tmp) be_->release(q);
   return result;

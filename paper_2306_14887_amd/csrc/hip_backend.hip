@@ -2017,6 +2017,24 @@ __global__ __launch_bounds__(256) void transfer_kernel(int chi, const double *co
   reinterpret_cast<double2 *>(F[p])[idx] = make_double2(re * scale[p], im * scale[p]);
 }
 
+// Trace of an n x n complex matrix: out = (Re, Im).  One workgroup.
+__global__ __launch_bounds__(256) void trace_kernel(const double *R, int n, double *out) {
+  __shared__ double sh[4];
+  const double2 *r = reinterpret_cast<const double2 *>(R);
+  double re = 0.0, im = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double2 v = r[(size_t)i * n + i];
+    re += v.x;
+    im += v.y;
+  }
+  const double a = block_sum<256>(re, sh);
+  const double b = block_sum<256>(im, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
 __global__ __launch_bounds__(256) void reduce_max_kernel(const double *x, int n, double *out) {
   __shared__ double sh[256];
   double m = 0;
@@ -2561,6 +2579,11 @@ class HipBackend : public Backend {
     hipLaunchKernelGGL(transfer_kernel, dim3((unsigned)((c4 + 255) / 256), nprob), dim3(256), 0,
                        s_, chi, T, flip, scale, F);
     launch_check("transfer_kernel");
+  }
+  void trace(const double *R, int n, double *out) override {
+    stale_check("trace_kernel");
+    hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, s_, R, n, out);
+    launch_check("trace_kernel");
   }
   void reduce_max(const double *x, int n, double *out) override {
     stale_check("reduce_max_kernel");

@@ -69,11 +69,14 @@ def test_validate_error_codes():
     assert _validate(_spec(iso)) == -2                      # isolated site
     col = L.Lattice(3, np.array([[0, 1], [1, 2]], np.int32), np.array([0, 0], np.int32))
     assert _validate(_spec(col)) == -3                      # improper colouring
-    # Pauli strings: op range, repeated site, non-tree cluster
+    # Pauli strings: op range, repeated site, clusters with more than one loop, loops at chi > 64
     r = L.hexagon_ring()
     assert _validate(_spec(r, pauli=[([0, 1], [1, 4])])) == -1
     assert _validate(_spec(r, pauli=[([0, 0], [1, 1])])) == -1
-    assert _validate(_spec(r, pauli=[(list(range(12)), [3] * 12)])) == -1   # the whole ring
+    assert _validate(_spec(r, pauli=[(list(range(12)), [3] * 12)])) == 0    # one loop
+    assert _validate(_spec(r, chi=128, pauli=[(list(range(12)), [3] * 12)])) == -1
+    hh = L.heavy_hex(3, 9)                                                    # two loops
+    assert _validate(_spec(hh, pauli=[(list(range(hh.n_sites)), [3] * hh.n_sites)])) == -1
     assert _validate(_spec(r, pauli=[([0, 5], [3, 3])])) == -1               # disconnected
     assert _validate(_spec(r, pauli=[([0, 1, 2], [1, 2, 3])])) == 0
 

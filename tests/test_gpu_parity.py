@@ -557,3 +557,91 @@ def test_vidal_gauge_repeated_keeps_scale_and_bp_error(ctx):
     errs = [s.bp_error(e)[0] for e in range(r.n_edges)]
     s.close()
     assert max(errs) < 1e-12, errs
+
+
+# --- Pauli strings on clusters with a loop ---------------------------------------------------------
+
+def _ring_with_pendants():
+    r = L.hexagon_ring()
+    edges = np.vstack([r.edges, [[0, 12], [6, 13]]]).astype(np.int32)
+    return L.Lattice(14, edges, L.greedy_colouring(14, edges), name="ring12p2")
+
+
+def _hexagon_with_branches(lat, extra):
+    """A shortest cycle through a degree-3 site (a heavy hexagon) plus `extra` frontier sites."""
+    from collections import deque
+    nb = lat.neighbours()
+    root = int(np.nonzero(lat.degrees() == 3)[0][0])
+    best = None
+    for first in nb[root]:
+        # shortest path from `first` back to root avoiding the edge (root, first)
+        prev = {first: None}
+        dq = deque([first])
+        while dq:
+            x = dq.popleft()
+            for y in nb[x]:
+                if (x == first and y == root) or y in prev:
+                    continue
+                prev[y] = x
+                dq.append(y)
+        if root in prev:
+            path, x = [], root
+            while x is not None:
+                path.append(x)
+                x = prev[x]
+            if best is None or len(path) < len(best):
+                best = path
+    cyc = sorted(set(best))
+    out = list(cyc)
+    for x in cyc:
+        for y in nb[x]:
+            if len(out) < len(cyc) + extra and y not in out:
+                out.append(y)
+    return out
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.2])
+def test_loop_cluster_whole_lattice_exact(ctx, theta):
+    """Strings on all 14 sites of the ring with two pendants (a loop plus branches): nothing is
+    cut, so the value is the exact expectation; untruncated against the state vector."""
+    print(f"[parity] loop cluster = whole lattice theta={theta}", flush=True)
+    lat = _ring_with_pendants()
+    rng = np.random.default_rng(31)
+    strings = [(list(range(14)), [int(x) for x in rng.integers(1, 4, 14)]) for _ in range(3)]
+    g = _gpu(ctx, lat, theta, 3, 16, pauli=strings)
+    sv = SV.StateVector(lat.n_sites, lat.edges)
+    for _ in range(3):
+        sv.step(theta)
+    want = [sv.expect_pauli(s, o) for s, o in strings]
+    assert np.abs(g["pauli"] - want).max() < 1e-10
+
+
+def test_loop_cluster_vs_oracle_truncated(ctx):
+    """Heavy hexagon clusters (12-site loop, plus up to three branch sites) on the 29-qubit
+    lattice after truncated steps: BP messages on the cut legs, against the oracle's exact
+    contraction of the cluster."""
+    print("[parity] loop clusters on heavy-hex 29 vs oracle", flush=True)
+    lat = L.heavy_hex(3, 9)
+    rng = np.random.default_rng(32)
+    strings = []
+    for extra in (0, 1, 3):
+        sites = _hexagon_with_branches(lat, extra)
+        strings.append((sites, [int(x) for x in rng.integers(1, 4, len(sites))]))
+    g = _gpu(ctx, lat, 0.7, 5, 8, pauli=strings)
+    net = O.Network(lat.n_sites, lat.edges, lat.colour)
+    o = O.solve(lat.n_sites, lat.edges, lat.colour, 0.7, 5, O.Options(chi=8), net=net)
+    assert max(o.discarded) > 1e-8
+    want = [net.expect_pauli_cluster(s, op) for s, op in strings]
+    assert np.abs(g["pauli"] - want).max() < TOL
+    assert np.abs(g["z"] - o.z).max() < TOL
+
+
+def test_loop_cluster_validation(ctx):
+    from paper_2306_14887_amd import bpki as B
+    lat = L.heavy_hex(3, 9)
+    sites = _hexagon_with_branches(lat, 0)
+    with pytest.raises(B.BpkiError):                       # chi > 64 with a loop
+        _gpu(ctx, lat, 0.7, 1, 128, pauli=[(sites, [3] * len(sites))])
+    both = sorted(set(range(lat.n_sites)))                   # the whole lattice: two loops
+    with pytest.raises(B.BpkiError):
+        _gpu(ctx, lat, 0.7, 1, 4, pauli=[(both, [3] * len(both))])
