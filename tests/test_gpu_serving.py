@@ -143,3 +143,40 @@ def test_cancel_and_reject():
         with pytest.raises(B.BpkiError) as ex:
             ctx.submit(B.spec_from_lattice(e, 0.9, 2, 8))
         assert ex.value.code == -4
+
+
+def test_memory_estimate_bounds_the_device_footprint():
+    """The admission estimate (bpki_estimate_bytes) bounds what a solve really holds on the device:
+    the drop in free device memory (hipMemGetInfo) after opening a session and running two steps
+    with every observable, workspaces included."""
+    import ctypes as C
+
+    from paper_2306_14887_amd import bpki as B
+    print("[serving] memory estimate vs device footprint", flush=True)
+    hip = C.CDLL("libamdhip64.so")
+    free, total = C.c_size_t(), C.c_size_t()
+
+    def free_bytes():
+        assert hip.hipMemGetInfo(C.byref(free), C.byref(total)) == 0
+        return free.value
+
+    lib = B.load()
+    cases = [(L.eagle(), 32), (L.heavy_hex(5, 11), 64), (L.infinite_cell(), 128),
+             (L.hexagon_ring(), 16)]
+    for lat, chi in cases:                   # a fresh context each: its workspaces start empty
+        spec = B.spec_from_lattice(lat, 0.7, 2, chi, bond_entropy=True)
+        p, keep = spec.to_c()
+        est = C.c_size_t()
+        assert lib.bpki_estimate_bytes(p, C.byref(est)) == 0
+        with B.Context() as ctx:
+            f0 = free_bytes()
+            s = ctx.session(spec)
+            s.step()
+            s.step()
+            s.observe_bond_entropy()
+            s.vidal_gauge()
+            used = f0 - free_bytes()
+            s.close()
+        print(f"  {lat.name} chi={chi}: estimate {est.value / 2**20:.0f} MiB, "
+              f"used {used / 2**20:.0f} MiB", flush=True)
+        assert used <= est.value, (lat.name, chi, used, est.value)
