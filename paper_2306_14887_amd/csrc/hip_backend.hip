@@ -1560,6 +1560,188 @@ __global__ __launch_bounds__(1024) void gram_chol_kernel(int n, const double *co
   }
 }
 
+// Blocked pivoted Cholesky of the Gram matrices for n > 128 (the factorisation of the kernel
+// above, reorganised so that most of the work runs on the GEMM): between launches the workspace
+// holds, per matrix, the trailing matrix W, the factor L (row = original index, column = pivot
+// order) and X, and the meta block {rank, done, gmax, dg[n], perm[n]} (dg: diagonal of the
+// trailing matrix; 16-byte aligned blocks).  chol_init_kernel sets them up; per panel of CHOL_NB columns
+// chol_panel_kernel (one workgroup per matrix) picks the pivots and computes the columns with the
+// in-panel corrections, and a GEMM applies W -= L_panel L_panel^H; chol_finish_kernel forms
+// L1^{-1} and the outputs exactly as the single-kernel version.
+constexpr int CHOL_NB = 16;
+__host__ __device__ inline size_t chol_meta_bytes(int n) { return (16 + (size_t)n * 12 + 15) & ~size_t(15); }
+
+__global__ __launch_bounds__(1024) void chol_init_kernel(int n, const double *const *G,
+                                                         double2 *ws, char *meta) {
+  __shared__ double red[16];
+  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  double2 *W = ws + (size_t)prob * 3 * n * n, *L = W + (size_t)n * n, *X = L + (size_t)n * n;
+  char *mb = meta + (size_t)prob * chol_meta_bytes(n);
+  double *dg = reinterpret_cast<double *>(mb + 16);
+  int *perm = reinterpret_cast<int *>(mb + 16 + (size_t)n * 8);
+  const double2 *g = reinterpret_cast<const double2 *>(G[prob]);
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx / n, j = idx % n;
+    const double2 x = g[(size_t)i * n + j], y = g[(size_t)j * n + i];
+    W[idx] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    L[idx] = make_double2(0.0, 0.0);
+    X[idx] = make_double2(0.0, 0.0);
+  }
+  double m = 0.0;
+  for (int i = tid; i < n; i += nt) {
+    perm[i] = i;
+    const double d = g[(size_t)i * n + i].x;
+    dg[i] = d;
+    m = fmax(m, d);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double gm = 0.0;
+    for (int w = 0; w < nt / 64; ++w) gm = fmax(gm, red[w]);
+    reinterpret_cast<int *>(mb)[0] = n;         // rank
+    reinterpret_cast<int *>(mb)[1] = 0;         // done
+    reinterpret_cast<double *>(mb)[1] = gm;     // gmax
+  }
+}
+
+__global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int k0, double cut, double2 *ws,
+                                                          char *meta) {
+  extern __shared__ double2 lp[];                // [n][CHOL_NB + 1] (padded rows)
+  __shared__ int perm_s[256];
+  __shared__ double dg_s[256];
+  __shared__ int stop_s;
+  constexpr int LD = CHOL_NB + 1;
+  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  char *mb = meta + (size_t)prob * chol_meta_bytes(n);
+  if (reinterpret_cast<const int *>(mb)[1]) return;          // rank reached in an earlier panel
+  const double gmax = reinterpret_cast<const double *>(mb)[1];
+  double *dg = reinterpret_cast<double *>(mb + 16);
+  int *perm = reinterpret_cast<int *>(mb + 16 + (size_t)n * 8);
+  const double2 *W = ws + (size_t)prob * 3 * n * n;
+  double2 *L = const_cast<double2 *>(W) + (size_t)n * n;
+  for (int i = tid; i < n; i += nt) {
+    perm_s[i] = perm[i];
+    dg_s[i] = dg[i];
+  }
+  for (int idx = tid; idx < n * LD; idx += nt) lp[idx] = make_double2(0.0, 0.0);
+  if (tid == 0) stop_s = 0;
+  __syncthreads();
+  int j = 0;
+  for (; j < CHOL_NB && k0 + j < n; ++j) {
+    const int k = k0 + j;
+    if (wave == 0) {
+      double best = -1.0;
+      int bj = k;
+      for (int q = k + lane; q < n; q += 64) {
+        const double v = dg_s[perm_s[q]];
+        if (v > best) { best = v; bj = q; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+      }
+      if (lane == 0) {
+        if (!(best > cut * gmax) || !(gmax > 0)) {
+          stop_s = 1;
+        } else {
+          const int t = perm_s[k];
+          perm_s[k] = perm_s[bj];
+          perm_s[bj] = t;
+        }
+      }
+    }
+    __syncthreads();
+    if (stop_s) break;
+    const int pk = perm_s[k];
+    const double piv = sqrt(dg_s[pk]);
+    const double ipiv = 1.0 / piv;
+    for (int q = k + 1 + tid; q < n; q += nt) {
+      const int i = perm_s[q];
+      double2 v = W[(size_t)i * n + pk];
+      for (int c = 0; c < j; ++c) {
+        const double2 a = lp[i * LD + c], b = lp[pk * LD + c];
+        // v -= a conj(b)
+        v.x -= a.x * b.x + a.y * b.y;
+        v.y -= a.y * b.x - a.x * b.y;
+      }
+      lp[i * LD + j] = make_double2(v.x * ipiv, v.y * ipiv);
+    }
+    if (tid == 0) lp[pk * LD + j] = make_double2(piv, 0.0);
+    __syncthreads();
+    for (int q = k + 1 + tid; q < n; q += nt) {
+      const int i = perm_s[q];
+      const double2 l = lp[i * LD + j];
+      dg_s[i] -= l.x * l.x + l.y * l.y;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * CHOL_NB; idx += nt) {
+    const int i = idx / CHOL_NB, c = idx % CHOL_NB;
+    if (c < j) L[(size_t)i * n + k0 + c] = lp[i * LD + c];
+  }
+  for (int i = tid; i < n; i += nt) {
+    perm[i] = perm_s[i];
+    dg[i] = dg_s[i];
+  }
+  if (tid == 0 && stop_s) {
+    reinterpret_cast<int *>(mb)[0] = k0 + j;
+    reinterpret_cast<int *>(mb)[1] = 1;
+  }
+}
+
+__global__ __launch_bounds__(1024) void chol_finish_kernel(int n, double *const *R,
+                                                           double *const *Wsc, double2 *ws,
+                                                           const char *meta) {
+  __shared__ int perm[256];
+  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  double2 *L = ws + (size_t)prob * 3 * n * n + (size_t)n * n, *X = L + (size_t)n * n;
+  const char *mb = meta + (size_t)prob * chol_meta_bytes(n);
+  const int rank_s = reinterpret_cast<const int *>(mb)[0];
+  for (int i = tid; i < n; i += nt) perm[i] = reinterpret_cast<const int *>(mb + 16 + (size_t)n * 8)[i];
+  __syncthreads();
+  const int r = rank_s;
+  // X = L1^{-1}: L1[i][m] = L[perm[i]][m] (i, m < r), lower triangular.  Forward substitution
+  // row by row, X[i][j] = (delta_ij - sum_{j<=m<i} L1[i][m] X[m][j]) / L1[i][i], with all
+  // columns j <= i of a row at once, eight threads per column splitting the sum.
+  for (int i = 0; i < r; ++i) {
+    const double2 *Li = L + (size_t)perm[i] * n;
+    const double inv = 1.0 / Li[i].x;      // real positive pivot
+    const int q = tid & 7;
+    for (int j = tid >> 3; j <= i; j += nt >> 3) {
+      double sr = 0.0, si = 0.0;
+      for (int mm = j + q; mm < i; mm += 8) {
+        const double2 a = Li[mm], x = X[(size_t)mm * n + j];
+        sr += a.x * x.x - a.y * x.y;
+        si += a.x * x.y + a.y * x.x;
+      }
+      for (int o = 1; o < 8; o <<= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+      }
+      if (q == 0) X[(size_t)i * n + j] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
+    }
+    __syncthreads();
+  }
+  double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
+  double2 *Wo = reinterpret_cast<double2 *>(Wsc[prob]);
+  for (int idx = tid; idx < n * n; idx += nt) {
+    int k = idx / n, c = idx % n;
+    double2 l = L[(size_t)c * n + k];
+    Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
+    Wo[idx] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < r * r; idx += nt) {
+    int kk = idx / r, k = idx % r;     // Wsc[perm[kk]][k] = conj(X[k][kk])
+    double2 x = X[(size_t)k * n + kk];
+    Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
+  }
+}
+
 // The same factorisation for n <= 128 with the Gram matrix packed (lower triangle, physical
 // indices) in LDS: pivoting permutes logical indices only, each rank-one update touches the
 // remaining triangle, and X = L1^{-1} is formed in the LDS that held G.  L goes to the workspace.
@@ -2171,6 +2353,9 @@ class HipBackend : public Backend {
                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
     HIPCHK(hipFuncSetAttribute((const void *)gram_chol_lds_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
+    HIPCHK(hipFuncSetAttribute((const void *)chol_panel_kernel,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               256 * (CHOL_NB + 1) * (int)sizeof(double2)));
     HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_kernel<128, 1024>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
     HIPCHK(hipFuncSetAttribute((const void *)eigh_dc_kernel<128>,
@@ -2181,6 +2366,7 @@ class HipBackend : public Backend {
       if (e) hipEventDestroy(e);
     if (skws_) HIPCHK(hipFree(skws_));
     if (cws_) HIPCHK(hipFree(cws_));
+    if (cmeta_) HIPCHK(hipFree(cmeta_));
     if (lws_) HIPCHK(hipFree(lws_));
     if (rws_) HIPCHK(hipFree(rws_));
     if (pin_) HIPCHK(hipHostFree(pin_));
@@ -2483,10 +2669,62 @@ class HipBackend : public Backend {
                          (double2 *)cws_);
       launch_check("gram_chol_lds_kernel");
     } else {
-      stale_check("gram_chol_kernel");
-      hipLaunchKernelGGL(gram_chol_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, R, Wsc, cut,
-                         (double2 *)cws_);
-      launch_check("gram_chol_kernel");
+      // blocked: meta blocks and the panel GEMMs' pointer arrays (W, L at the panel's column)
+      const size_t mbytes = (size_t)nprob * chol_meta_bytes(n);
+      const int npan = (n + CHOL_NB - 1) / CHOL_NB;
+      const size_t pbytes = (size_t)npan * 3 * nprob * sizeof(void *);
+      const size_t moff = (mbytes + 15) & ~size_t(15);
+      if (moff + pbytes > cmeta_bytes_) {
+        HIPCHK(hipStreamSynchronize(s_));
+        if (cmeta_) HIPCHK(hipFree(cmeta_));
+        cmeta_ = nullptr;
+        cmeta_bytes_ = 0;
+        if (hipMalloc(&cmeta_, moff + pbytes) != hipSuccess) {
+          err_ = -4;
+          errmsg_ = "Cholesky workspace allocation failed";
+          return;
+        }
+        cmeta_bytes_ = moff + pbytes;
+      }
+      char *meta = (char *)cmeta_;
+      void **cp = (void **)(meta + moff);
+      std::vector<void *> hp((size_t)npan * 3 * nprob);
+      double2 *base = (double2 *)cws_;
+      for (int pn = 0; pn < npan; ++pn)
+        for (int q = 0; q < nprob; ++q) {
+          double2 *W = base + (size_t)q * 3 * n * n;
+          hp[((size_t)pn * 3 + 0) * nprob + q] = W + (size_t)n * n + pn * CHOL_NB;   // L panel
+          hp[((size_t)pn * 3 + 1) * nprob + q] = W + (size_t)n * n + pn * CHOL_NB;
+          hp[((size_t)pn * 3 + 2) * nprob + q] = W;
+        }
+      h2d(cp, hp.data(), hp.size() * sizeof(void *));
+      stale_check("chol_init_kernel");
+      hipLaunchKernelGGL(chol_init_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, base, meta);
+      launch_check("chol_init_kernel");
+      GemmDesc up;                       // W -= L_panel L_panel^H
+      up.M = up.Mi = n; up.N = up.Ni = n;
+      up.a_mi = n; up.a_ki = 1;
+      up.b_ki = 1; up.b_ni = n; up.conjB = 1;
+      up.c_mi = n; up.c_ni = 1;
+      up.beta = 1; up.alpha_re = -1.0;
+      const size_t lds = (size_t)n * (CHOL_NB + 1) * sizeof(double2);
+      for (int pn = 0; pn < npan; ++pn) {
+        const int k0 = pn * CHOL_NB;
+        stale_check("chol_panel_kernel");
+        hipLaunchKernelGGL(chol_panel_kernel, dim3(nprob), dim3(1024), lds, s_, n, k0, cut, base,
+                           meta);
+        launch_check("chol_panel_kernel");
+        if (k0 + CHOL_NB < n) {
+          up.K = up.Ki = CHOL_NB;
+          gemm(up, (const double *const *)(cp + (size_t)pn * 3 * nprob),
+               (const double *const *)(cp + ((size_t)pn * 3 + 1) * nprob),
+               (double *const *)(cp + ((size_t)pn * 3 + 2) * nprob), nprob);
+        }
+      }
+      stale_check("chol_finish_kernel");
+      hipLaunchKernelGGL(chol_finish_kernel, dim3(nprob), dim3(1024), 0, s_, n, R, Wsc, base,
+                         (const char *)meta);
+      launch_check("chol_finish_kernel");
     }
   }
   void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
@@ -2656,6 +2894,8 @@ class HipBackend : public Backend {
   void *pin_ = nullptr;
   void *cws_ = nullptr;
   size_t cws_bytes_ = 0;
+  void *cmeta_ = nullptr;            // blocked Cholesky: meta blocks + panel pointer arrays
+  size_t cmeta_bytes_ = 0;
   void *skws_ = nullptr;
   size_t skws_bytes_ = 0;
   int prof_stride_ = 0;

@@ -213,7 +213,8 @@ def test_eigh_matches_numpy(ctx, n):
         assert np.abs(A[p] @ V[p] - V[p] * ev[p][None, :]).max() < 1e-12 * scale * max(1, n / 16)
 
 
-@pytest.mark.parametrize("n,rank", [(8, 8), (16, 5), (128, 128), (128, 70), (256, 200)])
+@pytest.mark.parametrize("n,rank", [(8, 8), (16, 5), (128, 128), (128, 70), (130, 129), (160, 100),
+                                    (200, 200), (256, 200), (256, 256)])
 def test_gram_chol(ctx, n, rank):
     """Pivoted Cholesky of A^H A: R^H R = G, and Q = A Wsc is an isometry on the range."""
     print(f"[gram_chol] n={n} rank={rank}", flush=True)
