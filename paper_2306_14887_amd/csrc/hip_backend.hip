@@ -1436,146 +1436,30 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const do
 }
 
 // ------------------------------------------------------------------------------------------
-// Pivoted Cholesky factor of a Gram matrix (one workgroup per matrix, work arrays in an
-// L2-resident global area).  Right-looking: pivot = largest remaining diagonal entry (wave
-// reduction), column of L, rank-1 update of the trailing Schur complement; stops at the first
-// pivot <= cut * max diag.  Then X = L1^{-1} by forward substitution (one thread per column).
-__global__ __launch_bounds__(1024) void gram_chol_kernel(int n, const double *const *G,
-                                                         double *const *R, double *const *Wsc,
-                                                         double cut, double2 *ws) {
-  __shared__ int perm[256];
-  __shared__ double dg[256];
-  __shared__ int piv_s, rank_s;
-  __shared__ double gmax_s;
-  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  double2 *W = ws + (size_t)prob * 3 * n * n, *L = W + (size_t)n * n, *X = L + (size_t)n * n;
-  const double2 *g = reinterpret_cast<const double2 *>(G[prob]);
-  for (int idx = tid; idx < n * n; idx += nt) {
-    int i = idx / n, j = idx % n;
-    double2 a = g[(size_t)i * n + j], b = g[(size_t)j * n + i];
-    W[idx] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-    L[idx] = make_double2(0.0, 0.0);
-    X[idx] = make_double2(0.0, 0.0);
-  }
-  for (int i = tid; i < n; i += nt) {
-    perm[i] = i;
-    dg[i] = g[(size_t)i * n + i].x;
-  }
-  __syncthreads();
-  if (wave == 0) {
-    double m = 0;
-    for (int i = lane; i < n; i += 64) m = fmax(m, dg[i]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if (lane == 0) { gmax_s = m; rank_s = n; }
-  }
-  __syncthreads();
-  const double gmax = gmax_s;
-  for (int k = 0; k < n; ++k) {
-    if (wave == 0) {
-      double best = -1.0;
-      int bj = k;
-      for (int j = k + lane; j < n; j += 64) {
-        double v = dg[perm[j]];
-        if (v > best) { best = v; bj = j; }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        double ob = __shfl_xor(best, o, 64);
-        int oj = __shfl_xor(bj, o, 64);
-        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
-      }
-      if (lane == 0) {
-        if (!(best > cut * gmax) || !(gmax > 0)) {
-          rank_s = k;
-          piv_s = -1;
-        } else {
-          int t = perm[k];
-          perm[k] = perm[bj];
-          perm[bj] = t;
-          piv_s = bj;
-        }
-      }
-    }
-    __syncthreads();
-    if (piv_s < 0) break;
-    const int pk = perm[k];
-    const double piv = sqrt(dg[pk]);
-    for (int kk = k + 1 + tid; kk < n; kk += nt) {
-      int i = perm[kk];
-      double2 w = W[(size_t)i * n + pk];
-      L[(size_t)i * n + k] = make_double2(w.x / piv, w.y / piv);
-    }
-    if (tid == 0) L[(size_t)pk * n + k] = make_double2(piv, 0.0);
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = tid; idx < m * m; idx += nt) {
-      int a = k + 1 + idx / m, b = k + 1 + idx % m;
-      int i = perm[a], j = perm[b];
-      double2 li = L[(size_t)i * n + k], lj = L[(size_t)j * n + k];
-      double2 w = W[(size_t)i * n + j];
-      // W[i][j] -= L[i][k] conj(L[j][k])
-      w.x -= li.x * lj.x + li.y * lj.y;
-      w.y -= li.y * lj.x - li.x * lj.y;
-      W[(size_t)i * n + j] = w;
-      if (a == b) dg[i] = w.x;
-    }
-    __syncthreads();
-  }
-  const int r = rank_s;
-  // X = L1^{-1}: L1[i][m] = L[perm[i]][m] (i, m < r), lower triangular.  Forward substitution
-  // row by row, X[i][j] = (delta_ij - sum_{j<=m<i} L1[i][m] X[m][j]) / L1[i][i], with all
-  // columns j <= i of a row at once, eight threads per column splitting the sum.
-  for (int i = 0; i < r; ++i) {
-    const double2 *Li = L + (size_t)perm[i] * n;
-    const double inv = 1.0 / Li[i].x;      // real positive pivot
-    const int q = tid & 7;
-    for (int j = tid >> 3; j <= i; j += nt >> 3) {
-      double sr = 0.0, si = 0.0;
-      for (int mm = j + q; mm < i; mm += 8) {
-        const double2 a = Li[mm], x = X[(size_t)mm * n + j];
-        sr += a.x * x.x - a.y * x.y;
-        si += a.x * x.y + a.y * x.x;
-      }
-      for (int o = 1; o < 8; o <<= 1) {
-        sr += __shfl_xor(sr, o, 64);
-        si += __shfl_xor(si, o, 64);
-      }
-      if (q == 0) X[(size_t)i * n + j] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
-    }
-    __syncthreads();
-  }
-  double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
-  double2 *Wo = reinterpret_cast<double2 *>(Wsc[prob]);
-  for (int idx = tid; idx < n * n; idx += nt) {
-    int k = idx / n, c = idx % n;
-    double2 l = L[(size_t)c * n + k];
-    Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
-    Wo[idx] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int idx = tid; idx < r * r; idx += nt) {
-    int kk = idx / r, k = idx % r;     // Wsc[perm[kk]][k] = conj(X[k][kk])
-    double2 x = X[(size_t)k * n + kk];
-    Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
-  }
-}
-
-// Blocked pivoted Cholesky of the Gram matrices for n > 128 (the factorisation of the kernel
-// above, reorganised so that most of the work runs on the GEMM): between launches the workspace
+// Pivoted Cholesky factor of a Gram matrix G = A^H A: pivot = largest remaining diagonal entry,
+// column of L, update of the trailing Schur complement; stops at the first pivot <= cut * max
+// diag.  Then X = L1^{-1}, R = L^H P^T and Wsc = P [L1^{-H}; 0].
+//
+// For n > 128 it is blocked so that most of the work runs on the GEMM: between launches the workspace
 // holds, per matrix, the trailing matrix W, the factor L (row = original index, column = pivot
 // order) and X, and the meta block {rank, done, gmax, dg[n], perm[n]} (dg: diagonal of the
 // trailing matrix; 16-byte aligned blocks).  chol_init_kernel sets them up; per panel of CHOL_NB columns
 // chol_panel_kernel (one workgroup per matrix) picks the pivots and computes the columns with the
-// in-panel corrections, and a GEMM applies W -= L_panel L_panel^H; chol_finish_kernel forms
-// L1^{-1} and the outputs exactly as the single-kernel version.
+// in-panel corrections, and a GEMM applies W -= L_panel L_panel^H.  Then L1^{-1} by blocks: the
+// diagonal blocks' inverses (chol_diag_inv_kernel), and for each block row I in turn
+// Y = L1[I, :I] X[:I, :I] and X[I, :I] = -X[I, I] Y on the GEMM; chol_out_kernel writes R and Wsc.
 constexpr int CHOL_NB = 16;
 __host__ __device__ inline size_t chol_meta_bytes(int n) { return (16 + (size_t)n * 12 + 15) & ~size_t(15); }
+// per-matrix workspace of the blocked path: W (later L1), L, X (n x n each) and Y (CHOL_NB x n)
+__host__ __device__ inline size_t chol_stride(int n) {
+  return 3 * (size_t)n * n + (size_t)CHOL_NB * n;
+}
 
 __global__ __launch_bounds__(1024) void chol_init_kernel(int n, const double *const *G,
                                                          double2 *ws, char *meta) {
   __shared__ double red[16];
   const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  double2 *W = ws + (size_t)prob * 3 * n * n, *L = W + (size_t)n * n, *X = L + (size_t)n * n;
+  double2 *W = ws + (size_t)prob * chol_stride(n), *L = W + (size_t)n * n, *X = L + (size_t)n * n;
   char *mb = meta + (size_t)prob * chol_meta_bytes(n);
   double *dg = reinterpret_cast<double *>(mb + 16);
   int *perm = reinterpret_cast<int *>(mb + 16 + (size_t)n * 8);
@@ -1620,7 +1504,7 @@ __global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int k0, double 
   const double gmax = reinterpret_cast<const double *>(mb)[1];
   double *dg = reinterpret_cast<double *>(mb + 16);
   int *perm = reinterpret_cast<int *>(mb + 16 + (size_t)n * 8);
-  const double2 *W = ws + (size_t)prob * 3 * n * n;
+  const double2 *W = ws + (size_t)prob * chol_stride(n);
   double2 *L = const_cast<double2 *>(W) + (size_t)n * n;
   for (int i = tid; i < n; i += nt) {
     perm_s[i] = perm[i];
@@ -1693,51 +1577,74 @@ __global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int k0, double 
   }
 }
 
-__global__ __launch_bounds__(1024) void chol_finish_kernel(int n, double *const *R,
-                                                           double *const *Wsc, double2 *ws,
-                                                           const char *meta) {
+// L1 (pivot order, rows of L permuted; identity rows beyond the rank so that L1 is invertible and
+// its leading rank x rank block is the factor's) into the W area; X cleared.
+__global__ __launch_bounds__(1024) void chol_l1_kernel(int n, double2 *ws, const char *meta) {
   __shared__ int perm[256];
   const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  double2 *L = ws + (size_t)prob * 3 * n * n + (size_t)n * n, *X = L + (size_t)n * n;
+  double2 *L1 = ws + (size_t)prob * chol_stride(n), *L = L1 + (size_t)n * n, *X = L + (size_t)n * n;
   const char *mb = meta + (size_t)prob * chol_meta_bytes(n);
-  const int rank_s = reinterpret_cast<const int *>(mb)[0];
+  const int r = reinterpret_cast<const int *>(mb)[0];
   for (int i = tid; i < n; i += nt) perm[i] = reinterpret_cast<const int *>(mb + 16 + (size_t)n * 8)[i];
   __syncthreads();
-  const int r = rank_s;
-  // X = L1^{-1}: L1[i][m] = L[perm[i]][m] (i, m < r), lower triangular.  Forward substitution
-  // row by row, X[i][j] = (delta_ij - sum_{j<=m<i} L1[i][m] X[m][j]) / L1[i][i], with all
-  // columns j <= i of a row at once, eight threads per column splitting the sum.
-  for (int i = 0; i < r; ++i) {
-    const double2 *Li = L + (size_t)perm[i] * n;
-    const double inv = 1.0 / Li[i].x;      // real positive pivot
-    const int q = tid & 7;
-    for (int j = tid >> 3; j <= i; j += nt >> 3) {
-      double sr = 0.0, si = 0.0;
-      for (int mm = j + q; mm < i; mm += 8) {
-        const double2 a = Li[mm], x = X[(size_t)mm * n + j];
-        sr += a.x * x.x - a.y * x.y;
-        si += a.x * x.y + a.y * x.x;
-      }
-      for (int o = 1; o < 8; o <<= 1) {
-        sr += __shfl_xor(sr, o, 64);
-        si += __shfl_xor(si, o, 64);
-      }
-      if (q == 0) X[(size_t)i * n + j] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
-    }
-    __syncthreads();
+  for (int idx = tid; idx < n * n; idx += nt) {
+    const int i = idx / n, m = idx % n;
+    L1[idx] = i < r ? L[(size_t)perm[i] * n + m] : make_double2(i == m ? 1.0 : 0.0, 0.0);
+    X[idx] = make_double2(0.0, 0.0);
   }
+}
+
+// Inverses of the CHOL_NB x CHOL_NB diagonal blocks of L1 into X (real positive diagonal): lane j
+// solves column j by forward substitution.  Grid (blocks, nprob), one wave.
+__global__ __launch_bounds__(64) void chol_diag_inv_kernel(int n, double2 *ws) {
+  __shared__ double2 ls[CHOL_NB][CHOL_NB + 1], xs[CHOL_NB][CHOL_NB + 1];
+  const int blk = blockIdx.x, prob = blockIdx.y, lane = threadIdx.x;
+  const int i0 = blk * CHOL_NB, b = min(CHOL_NB, n - i0);
+  double2 *L1 = ws + (size_t)prob * chol_stride(n), *X = L1 + 2 * (size_t)n * n;
+  for (int idx = lane; idx < b * b; idx += 64) {
+    const int i = idx / b, m = idx % b;
+    ls[i][m] = L1[(size_t)(i0 + i) * n + i0 + m];
+  }
+  __syncthreads();
+  if (lane < b) {
+    const int j = lane;
+    for (int i = j; i < b; ++i) {
+      double sr = i == j ? 1.0 : 0.0, si = 0.0;
+      for (int m = j; m < i; ++m) {
+        const double2 a = ls[i][m], x = xs[m][j];
+        sr -= a.x * x.x - a.y * x.y;
+        si -= a.x * x.y + a.y * x.x;
+      }
+      const double inv = 1.0 / ls[i][i].x;
+      xs[i][j] = make_double2(sr * inv, si * inv);
+    }
+    for (int i = j; i < b; ++i) X[(size_t)(i0 + i) * n + i0 + j] = xs[i][j];
+  }
+}
+
+// Outputs from L, X = L1^{-1} and the pivot order: R = L^H P^T (rows beyond the rank zero) and
+// Wsc[perm[kk]][k] = conj(X[k][kk]) for k, kk < rank.
+__global__ __launch_bounds__(1024) void chol_out_kernel(int n, double *const *R, double *const *Wsc,
+                                                        const double2 *ws, const char *meta) {
+  __shared__ int perm[256];
+  const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const double2 *L = ws + (size_t)prob * chol_stride(n) + (size_t)n * n, *X = L + (size_t)n * n;
+  const char *mb = meta + (size_t)prob * chol_meta_bytes(n);
+  const int r = reinterpret_cast<const int *>(mb)[0];
+  for (int i = tid; i < n; i += nt) perm[i] = reinterpret_cast<const int *>(mb + 16 + (size_t)n * 8)[i];
+  __syncthreads();
   double2 *Ro = reinterpret_cast<double2 *>(R[prob]);
   double2 *Wo = reinterpret_cast<double2 *>(Wsc[prob]);
   for (int idx = tid; idx < n * n; idx += nt) {
-    int k = idx / n, c = idx % n;
-    double2 l = L[(size_t)c * n + k];
+    const int k = idx / n, c = idx % n;
+    const double2 l = L[(size_t)c * n + k];
     Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
     Wo[idx] = make_double2(0.0, 0.0);
   }
   __syncthreads();
   for (int idx = tid; idx < r * r; idx += nt) {
-    int kk = idx / r, k = idx % r;     // Wsc[perm[kk]][k] = conj(X[k][kk])
-    double2 x = X[(size_t)k * n + kk];
+    const int kk = idx / r, k = idx % r;
+    const double2 x = X[(size_t)k * n + kk];
     Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
   }
 }
@@ -2649,7 +2556,7 @@ class HipBackend : public Backend {
   void gram_chol(int n, const double *const *G, double *const *R, double *const *Wsc, double cut,
                  int nprob) override {
     if (nprob <= 0) return;
-    size_t need = (size_t)nprob * 3 * n * n * sizeof(double2);
+    size_t need = (size_t)nprob * (n <= 128 ? 3 * (size_t)n * n : chol_stride(n)) * sizeof(double2);
     if (need > cws_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
       if (cws_) HIPCHK(hipFree(cws_));
@@ -2669,10 +2576,12 @@ class HipBackend : public Backend {
                          (double2 *)cws_);
       launch_check("gram_chol_lds_kernel");
     } else {
-      // blocked: meta blocks and the panel GEMMs' pointer arrays (W, L at the panel's column)
+      // blocked: meta blocks and the GEMMs' pointer arrays (panel updates, then the block rows of
+      // the triangular inverse)
       const size_t mbytes = (size_t)nprob * chol_meta_bytes(n);
       const int npan = (n + CHOL_NB - 1) / CHOL_NB;
-      const size_t pbytes = (size_t)npan * 3 * nprob * sizeof(void *);
+      const size_t nptr = ((size_t)npan * 3 + (size_t)(npan - 1) * 6) * nprob;
+      const size_t pbytes = nptr * sizeof(void *);
       const size_t moff = (mbytes + 15) & ~size_t(15);
       if (moff + pbytes > cmeta_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
@@ -2688,21 +2597,38 @@ class HipBackend : public Backend {
       }
       char *meta = (char *)cmeta_;
       void **cp = (void **)(meta + moff);
-      std::vector<void *> hp((size_t)npan * 3 * nprob);
+      std::vector<void *> hp(nptr);
       double2 *base = (double2 *)cws_;
-      for (int pn = 0; pn < npan; ++pn)
-        for (int q = 0; q < nprob; ++q) {
-          double2 *W = base + (size_t)q * 3 * n * n;
-          hp[((size_t)pn * 3 + 0) * nprob + q] = W + (size_t)n * n + pn * CHOL_NB;   // L panel
-          hp[((size_t)pn * 3 + 1) * nprob + q] = W + (size_t)n * n + pn * CHOL_NB;
-          hp[((size_t)pn * 3 + 2) * nprob + q] = W;
+      const size_t nn = (size_t)n * n;
+      auto slot = [&](size_t gemm, int which, int q) -> void *& {
+        return hp[(gemm * 3 + which) * nprob + q];
+      };
+      for (int q = 0; q < nprob; ++q) {
+        double2 *W = base + (size_t)q * chol_stride(n), *L = W + nn, *X = L + nn, *Y = X + nn;
+        for (int pn = 0; pn < npan; ++pn) {                   // W -= L_panel L_panel^H
+          slot(pn, 0, q) = L + pn * CHOL_NB;
+          slot(pn, 1, q) = L + pn * CHOL_NB;
+          slot(pn, 2, q) = W;
         }
-      h2d(cp, hp.data(), hp.size() * sizeof(void *));
+        for (int I = 1; I < npan; ++I) {                      // W now holds L1
+          const size_t g = npan + 2 * (size_t)(I - 1);
+          const size_t i0 = (size_t)I * CHOL_NB;
+          slot(g, 0, q) = W + i0 * n;                         // Y = L1[I, :I] X[:I, :I]
+          slot(g, 1, q) = X;
+          slot(g, 2, q) = Y;
+          slot(g + 1, 0, q) = X + i0 * n + i0;                // X[I, :I] = -X[I, I] Y
+          slot(g + 1, 1, q) = Y;
+          slot(g + 1, 2, q) = X + i0 * n;
+        }
+      }
+      h2d(cp, hp.data(), pbytes);
+      auto ptrs = [&](size_t gemm, int which) { return cp + (gemm * 3 + which) * nprob; };
       stale_check("chol_init_kernel");
       hipLaunchKernelGGL(chol_init_kernel, dim3(nprob), dim3(1024), 0, s_, n, G, base, meta);
       launch_check("chol_init_kernel");
       GemmDesc up;                       // W -= L_panel L_panel^H
       up.M = up.Mi = n; up.N = up.Ni = n;
+      up.K = up.Ki = CHOL_NB;
       up.a_mi = n; up.a_ki = 1;
       up.b_ki = 1; up.b_ni = n; up.conjB = 1;
       up.c_mi = n; up.c_ni = 1;
@@ -2714,17 +2640,37 @@ class HipBackend : public Backend {
         hipLaunchKernelGGL(chol_panel_kernel, dim3(nprob), dim3(1024), lds, s_, n, k0, cut, base,
                            meta);
         launch_check("chol_panel_kernel");
-        if (k0 + CHOL_NB < n) {
-          up.K = up.Ki = CHOL_NB;
-          gemm(up, (const double *const *)(cp + (size_t)pn * 3 * nprob),
-               (const double *const *)(cp + ((size_t)pn * 3 + 1) * nprob),
-               (double *const *)(cp + ((size_t)pn * 3 + 2) * nprob), nprob);
-        }
+        if (k0 + CHOL_NB < n)
+          gemm(up, (const double *const *)ptrs(pn, 0), (const double *const *)ptrs(pn, 1),
+               (double *const *)ptrs(pn, 2), nprob);
       }
-      stale_check("chol_finish_kernel");
-      hipLaunchKernelGGL(chol_finish_kernel, dim3(nprob), dim3(1024), 0, s_, n, R, Wsc, base,
+      stale_check("chol_l1_kernel");
+      hipLaunchKernelGGL(chol_l1_kernel, dim3(nprob), dim3(1024), 0, s_, n, base,
                          (const char *)meta);
-      launch_check("chol_finish_kernel");
+      launch_check("chol_l1_kernel");
+      stale_check("chol_diag_inv_kernel");
+      hipLaunchKernelGGL(chol_diag_inv_kernel, dim3(npan, nprob), dim3(64), 0, s_, n, base);
+      launch_check("chol_diag_inv_kernel");
+      for (int I = 1; I < npan; ++I) {
+        const size_t g = npan + 2 * (size_t)(I - 1);
+        const int i0 = I * CHOL_NB, b = std::min(CHOL_NB, n - i0);
+        GemmDesc y;                      // Y (b x i0) = L1[i0.., :i0] X[:i0, :i0]
+        y.M = y.Mi = b; y.N = y.Ni = i0; y.K = y.Ki = i0;
+        y.a_mi = n; y.a_ki = 1;
+        y.b_ki = n; y.b_ni = 1;
+        y.c_mi = n; y.c_ni = 1;
+        gemm(y, (const double *const *)ptrs(g, 0), (const double *const *)ptrs(g, 1),
+             (double *const *)ptrs(g, 2), nprob);
+        GemmDesc x = y;                  // X[i0.., :i0] = -X[i0.., i0..] Y
+        x.K = x.Ki = b;
+        x.alpha_re = -1.0;
+        gemm(x, (const double *const *)ptrs(g + 1, 0), (const double *const *)ptrs(g + 1, 1),
+             (double *const *)ptrs(g + 1, 2), nprob);
+      }
+      stale_check("chol_out_kernel");
+      hipLaunchKernelGGL(chol_out_kernel, dim3(nprob), dim3(1024), 0, s_, n, R, Wsc,
+                         (const double2 *)base, (const char *)meta);
+      launch_check("chol_out_kernel");
     }
   }
   void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
