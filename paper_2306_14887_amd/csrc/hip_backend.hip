@@ -1989,6 +1989,36 @@ __global__ __launch_bounds__(1024) void normalize_residual_kernel(int chi, doubl
   if (threadIdx.x == 0) res[p] = (trr > 0 && isfinite(s)) ? sqrt(s) : INFINITY;
 }
 
+// For n > 64 the two products of msg_sqrt_kernel run on the GEMM: this kernel forms
+// Wf = W diag(f) and Wg = W diag(g) (f, g as above) into a work area (2 n^2 per message, message p
+// at ws + 2 p n^2) and the pointer arrays of the three operands; then X = Wf W^H, Xp = Wg W^H.
+__global__ __launch_bounds__(256) void sqrt_scale_kernel(int n, const double *const *evals,
+                                                         const double *const *vecs, double cut,
+                                                         double2 *ws, double **pf, double **pg) {
+  __shared__ double fs[256], gs[256];
+  const int p = blockIdx.x;
+  const double *l = evals[p];
+  const double2 *W = reinterpret_cast<const double2 *>(vecs[p]);
+  double2 *wf = ws + (size_t)p * 2 * n * n, *wg = wf + (size_t)n * n;
+  const double lmax = l[0] > 0 ? l[0] : 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double lk = l[k];
+    fs[k] = lk > 0 ? sqrt(lk) : 0.0;
+    gs[k] = (lk > cut * lmax && lk > 0) ? 1.0 / sqrt(lk) : 0.0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int k = idx % n;
+    const double2 w = W[idx];
+    wf[idx] = make_double2(w.x * fs[k], w.y * fs[k]);
+    wg[idx] = make_double2(w.x * gs[k], w.y * gs[k]);
+  }
+  if (threadIdx.x == 0) {
+    pf[p] = reinterpret_cast<double *>(wf);
+    pg[p] = reinterpret_cast<double *>(wg);
+  }
+}
+
 // Bond entanglement entropy (Eq. "EntanglementEntropy", with the minus sign and the sum over the
 // chi weights of one bond): the eigenvalues of the bond matrix X M^T X, clipped at zero and
 // normalised to unit sum, give the Schmidt weights p; s = -sum p log2 p.  One workgroup per bond.
@@ -2274,6 +2304,7 @@ class HipBackend : public Backend {
     if (skws_) HIPCHK(hipFree(skws_));
     if (cws_) HIPCHK(hipFree(cws_));
     if (cmeta_) HIPCHK(hipFree(cmeta_));
+    if (sqws_) HIPCHK(hipFree(sqws_));
     if (lws_) HIPCHK(hipFree(lws_));
     if (rws_) HIPCHK(hipFree(rws_));
     if (pin_) HIPCHK(hipHostFree(pin_));
@@ -2549,9 +2580,40 @@ class HipBackend : public Backend {
   }
   void msg_sqrt(int n, const double *const *ev, const double *const *vec, double *const *X,
                 double *const *Xp, double cut, int nprob) override {
-    stale_check("msg_sqrt_kernel");
-    hipLaunchKernelGGL(msg_sqrt_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, X, Xp, cut);
-    launch_check("msg_sqrt_kernel");
+    if (nprob <= 0) return;
+    if (n <= 64) {
+      stale_check("msg_sqrt_kernel");
+      hipLaunchKernelGGL(msg_sqrt_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, X, Xp, cut);
+      launch_check("msg_sqrt_kernel");
+      return;
+    }
+    const size_t need = (size_t)nprob * 2 * n * n * sizeof(double2) + 2 * nprob * sizeof(void *);
+    if (need > sqws_bytes_) {
+      HIPCHK(hipStreamSynchronize(s_));
+      if (sqws_) HIPCHK(hipFree(sqws_));
+      sqws_ = nullptr;
+      sqws_bytes_ = 0;
+      if (hipMalloc(&sqws_, need) != hipSuccess) {
+        err_ = -4;
+        errmsg_ = "message square-root workspace allocation failed";
+        return;
+      }
+      sqws_bytes_ = need;
+    }
+    double2 *w = (double2 *)sqws_;
+    double **pf = (double **)(w + (size_t)nprob * 2 * n * n), **pg = pf + nprob;
+    stale_check("sqrt_scale_kernel");
+    hipLaunchKernelGGL(sqrt_scale_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, cut, w, pf,
+                       pg);
+    launch_check("sqrt_scale_kernel");
+    GemmDesc d;                          // X = (W diag f) W^H, Hermitian
+    d.M = d.Mi = n; d.N = d.Ni = n; d.K = d.Ki = n;
+    d.a_mi = n; d.a_ki = 1;
+    d.b_ki = 1; d.b_ni = n; d.conjB = 1;
+    d.c_mi = n; d.c_ni = 1;
+    d.herm = 1;
+    gemm(d, (const double *const *)pf, vec, X, nprob);
+    gemm(d, (const double *const *)pg, vec, Xp, nprob);
   }
   void gram_chol(int n, const double *const *G, double *const *R, double *const *Wsc, double cut,
                  int nprob) override {
@@ -2842,6 +2904,8 @@ class HipBackend : public Backend {
   size_t cws_bytes_ = 0;
   void *cmeta_ = nullptr;            // blocked Cholesky: meta blocks + panel pointer arrays
   size_t cmeta_bytes_ = 0;
+  void *sqws_ = nullptr;             // message square roots on the GEMM: scaled vectors, pointers
+  size_t sqws_bytes_ = 0;
   void *skws_ = nullptr;
   size_t skws_bytes_ = 0;
   int prof_stride_ = 0;

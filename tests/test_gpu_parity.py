@@ -645,3 +645,15 @@ def test_loop_cluster_validation(ctx):
     both = sorted(set(range(lat.n_sites)))                   # the whole lattice: two loops
     with pytest.raises(B.BpkiError):
         _gpu(ctx, lat, 0.7, 1, 4, pauli=[(both, [3] * len(both))])
+
+
+def test_infinite_cell_chi80_vs_oracle(ctx):
+    """chi = 80 (message roots on the GEMM, n = 80; Gram factorisations blocked, n = 160) on the
+    infinite-lattice cell with truncation from step 7: <Z> and entropies against the oracle."""
+    print("[parity] infinite cell chi=80", flush=True)
+    cell = L.infinite_cell()
+    g = _gpu(ctx, cell, 1.0, 8, 80, bond_entropy=True)
+    o = O.solve(cell.n_sites, cell.edges, cell.colour, 1.0, 8, O.Options(chi=80), entropy=True)
+    assert max(o.discarded) > 1e-6
+    assert np.abs(g["z"] - o.z).max() < TOL
+    assert np.abs(g["bond_entropy"] - o.entropy).max() < ENT_TOL
