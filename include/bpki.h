@@ -73,8 +73,8 @@ typedef struct {
   const int32_t *colour;       /* [n_edges] or NULL (greedy colouring, see above)               */
   double theta_h;              /* X rotation angle: exp(-i theta_h X / 2)                       */
   int32_t depth;               /* Floquet steps, >= 0                                          */
-  int32_t chi;                 /* maximum bond dimension, 1..128 (1..64 if two degree-3 sites
-                                  share an edge)                                               */
+  int32_t chi;                 /* maximum bond dimension, 1..256 (1..128 if two degree-3 sites
+                                  share an edge: the truncation eigenproblems have n <= 512)    */
   int32_t precision;           /* bpki_precision                                               */
   double bp_tol;               /* BP stops when max ||M'-M||_F < bp_tol   (e.g. 1e-12)         */
   int32_t bp_max_iter;         /* e.g. 1000                                                     */

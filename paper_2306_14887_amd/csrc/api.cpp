@@ -71,7 +71,7 @@ extern "C" int bpki_validate(const bpki_problem *p) {
   if (!p->edges) return fail(-1, "edges is NULL");
   if (!std::isfinite(p->theta_h)) return fail(-1, "theta_h must be finite");
   if (p->depth < 0) return fail(-1, "depth must be >= 0");
-  if (p->chi < 1 || p->chi > 128) return fail(-1, "chi must be in 1..128");
+  if (p->chi < 1 || p->chi > 256) return fail(-1, "chi must be in 1..256");
   if (p->precision != BPKI_FP64 && p->precision != BPKI_FP32)
     return fail(-1, "precision must be BPKI_FP64 or BPKI_FP32");
   if (!std::isfinite(p->bp_tol) || p->bp_tol < 0) return fail(-1, "bp_tol must be finite, >= 0");
@@ -97,8 +97,8 @@ extern "C" int bpki_validate(const bpki_problem *p) {
     if (deg[v] < 1 || deg[v] > 3) return fail(-2, "every site must have degree 1..3");
   // the truncated SVD of a gate block between two degree-3 sites is a 4chi x 4chi problem
   for (int e = 0; e < E; ++e)
-    if (deg[p->edges[2 * e]] == 3 && deg[p->edges[2 * e + 1]] == 3 && p->chi > 64)
-      return fail(-1, "chi must be <= 64 when two degree-3 sites share an edge");
+    if (deg[p->edges[2 * e]] == 3 && deg[p->edges[2 * e + 1]] == 3 && p->chi > 128)
+      return fail(-1, "chi must be <= 128 when two degree-3 sites share an edge");
   if (p->colour) {
     std::vector<std::set<int>> used(n);
     for (int e = 0; e < E; ++e) {
@@ -1022,7 +1022,7 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
 
 extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, double *evals,
                               double *vecs) {
-  if (!c || n < 1 || n > 256 || nprob < 1) return fail(-1, "bad argument");
+  if (!c || n < 1 || n > 512 || nprob < 1) return fail(-1, "bad argument");
   Backend *be = c->be.get();
   std::lock_guard<std::mutex> lk(c->mu);
   size_t nn = (size_t)n * n;
@@ -1066,7 +1066,7 @@ extern "C" int bpki_test_mfma_rate(bpki_ctx *c, int precision, int blocks, int i
 
 extern "C" int bpki_test_gram_chol(bpki_ctx *c, int n, int nprob, const double *G, double cut,
                                    double *R, double *Wsc) {
-  if (!c || n < 1 || n > 256 || nprob < 1 || !(cut >= 0)) return fail(-1, "bad argument");
+  if (!c || n < 1 || n > 512 || nprob < 1 || !(cut >= 0)) return fail(-1, "bad argument");
   Backend *be = c->be.get();
   std::lock_guard<std::mutex> lk(c->mu);
   size_t nn = (size_t)n * n;

@@ -1000,8 +1000,8 @@ __device__ __forceinline__ int dc_bound(int q, int n, int depth) {
 
 // eigh_tridiag_kernel: stage 1 (Householder reduction), NT threads per matrix; writes the
 // reflectors and tau, d to the eigenvalue area and e to the staging area of the workspace.
-// NMAX = 128: matrix packed (lower triangle) in LDS.  NMAX = 256: lower triangle of a row-major
-// n x n array in this matrix's workspace, which stays in L2.
+// NMAX = 128: matrix packed (lower triangle) in LDS.  NMAX = 256, 512: lower triangle of a
+// row-major n x n array in this matrix's workspace (in L2 up to n = 256).
 template <int NMAX, int NT>
 __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const double *const *in,
                                                           double *ws) {
@@ -1122,8 +1122,8 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
           if (q == 0) x1_s[r] = acc;
         }
       }
-      {
-        const int c = tid & 255, half = tid >> 8, c0 = c & ~63;
+      for (int c = tid & 255; c < NMAX; c += 256) {
+        const int half = tid >> 8, c0 = c & ~63;
         if (c0 < m) {
           double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
@@ -1208,11 +1208,11 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
 
 // eigh_dc_kernel: stage 2 (divide and conquer on the tridiagonal d, e left by
 // eigh_tridiag_kernel), 512 threads per matrix.  NMAX = 128: Z in LDS, leaves at depth 3.
-// NMAX = 256: Z in the workspace, leaves at depth 4.
+// NMAX = 256 (512): Z in the workspace, leaves at depth 4 (5).
 template <int NMAX>
 __global__ __launch_bounds__(512) void eigh_dc_kernel(int n, double *ws) {
   constexpr bool BIG = NMAX > 128;
-  constexpr int LD = BIG ? 4 : 3;               // depth of the leaves
+  constexpr int LD = NMAX > 256 ? 5 : BIG ? 4 : 3;   // depth of the leaves (8..16 entries)
   extern __shared__ double2 smem[];
   __shared__ double d_s[NMAX], e_s[NMAX];
   // phase-local scratch: leaf matrices (leaves), merge arrays
@@ -1366,7 +1366,7 @@ template <int NMAX>
 __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const double *ws,
                                                                  double *const *evals,
                                                                  double *const *vecs) {
-  constexpr int CB = 16;
+  constexpr int CB = NMAX > 256 ? 4 : 16;          // eigenvector columns per workgroup
   __shared__ double2 Vb[NMAX * CB];
   __shared__ double2 vk[NMAX];
   __shared__ double2 part[4][CB];
@@ -1386,7 +1386,8 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const do
   }
   for (int i = tid; i < n; i += 256) dsh[i] = dg[i];
   __syncthreads();
-  const int c = tid & (CB - 1), part_id = tid >> 4;   // 16 row groups per column
+  constexpr int RG = 256 / CB;                        // row groups per column
+  const int c = tid & (CB - 1), part_id = tid / CB;
   for (int k = n - 2; k >= 0; --k) {
     const double2 tau = tau_g[k];
     if (tau.x == 0.0 && tau.y == 0.0) continue;
@@ -1394,15 +1395,16 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const do
     for (int i = tid; i < m; i += 256) vk[i] = hh[(size_t)k * n + k + 1 + i];
     __syncthreads();
     double2 acc = make_double2(0.0, 0.0);
-    for (int i = part_id; i < m; i += 16) {
+    for (int i = part_id; i < m; i += RG) {
       const double2 v = vk[i], x = Vb[(k + 1 + i) * CB + c];
       acc.x += v.x * x.x + v.y * x.y;      // conj(v) x
       acc.y += v.x * x.y - v.y * x.x;
     }
-    acc.x += __shfl_xor(acc.x, 16, 64);
-    acc.y += __shfl_xor(acc.y, 16, 64);
-    acc.x += __shfl_xor(acc.x, 32, 64);
-    acc.y += __shfl_xor(acc.y, 32, 64);
+#pragma unroll
+    for (int o = CB; o < 64; o <<= 1) {    // the wave's lanes of this column
+      acc.x += __shfl_xor(acc.x, o, 64);
+      acc.y += __shfl_xor(acc.y, o, 64);
+    }
     if ((tid & 63) < CB) part[tid >> 6][c] = acc;
     __syncthreads();
     if (tid < CB) {
@@ -1493,8 +1495,8 @@ __global__ __launch_bounds__(1024) void chol_init_kernel(int n, const double *co
 __global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int k0, double cut, double2 *ws,
                                                           char *meta) {
   extern __shared__ double2 lp[];                // [n][CHOL_NB + 1] (padded rows)
-  __shared__ int perm_s[256];
-  __shared__ double dg_s[256];
+  __shared__ int perm_s[512];
+  __shared__ double dg_s[512];
   __shared__ int stop_s;
   constexpr int LD = CHOL_NB + 1;
   const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -1580,7 +1582,7 @@ __global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int k0, double 
 // L1 (pivot order, rows of L permuted; identity rows beyond the rank so that L1 is invertible and
 // its leading rank x rank block is the factor's) into the W area; X cleared.
 __global__ __launch_bounds__(1024) void chol_l1_kernel(int n, double2 *ws, const char *meta) {
-  __shared__ int perm[256];
+  __shared__ int perm[512];
   const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   double2 *L1 = ws + (size_t)prob * chol_stride(n), *L = L1 + (size_t)n * n, *X = L + (size_t)n * n;
   const char *mb = meta + (size_t)prob * chol_meta_bytes(n);
@@ -1626,7 +1628,7 @@ __global__ __launch_bounds__(64) void chol_diag_inv_kernel(int n, double2 *ws) {
 // Wsc[perm[kk]][k] = conj(X[k][kk]) for k, kk < rank.
 __global__ __launch_bounds__(1024) void chol_out_kernel(int n, double *const *R, double *const *Wsc,
                                                         const double2 *ws, const char *meta) {
-  __shared__ int perm[256];
+  __shared__ int perm[512];
   const int prob = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const double2 *L = ws + (size_t)prob * chol_stride(n) + (size_t)n * n, *X = L + (size_t)n * n;
   const char *mb = meta + (size_t)prob * chol_meta_bytes(n);
@@ -2292,7 +2294,7 @@ class HipBackend : public Backend {
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
     HIPCHK(hipFuncSetAttribute((const void *)chol_panel_kernel,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                               256 * (CHOL_NB + 1) * (int)sizeof(double2)));
+                               512 * (CHOL_NB + 1) * (int)sizeof(double2)));
     HIPCHK(hipFuncSetAttribute((const void *)eigh_tridiag_kernel<128, 1024>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 132096));
     HIPCHK(hipFuncSetAttribute((const void *)eigh_dc_kernel<128>,
@@ -2521,9 +2523,9 @@ class HipBackend : public Backend {
   void eigh(int n, int lda, const double *const *in, double *const *evals, double *const *vecs,
             int nprob) override {
     if (nprob <= 0) return;
-    if (n < 1 || n > 256) {
+    if (n < 1 || n > 512) {
       err_ = -1;
-      errmsg_ = "eigh: n must be in 1..256";
+      errmsg_ = "eigh: n must be in 1..512";
       return;
     }
     int np = n + (n & 1);
@@ -2533,7 +2535,7 @@ class HipBackend : public Backend {
       hipLaunchKernelGGL(eigh_jacobi_kernel, dim3(nprob), dim3(1024), sm, s_, n, lda, in,
                          evals, vecs, 60);
     } else {
-      // n <= 256 (the callers' limit)
+      // n <= 512 (the callers' limit)
       size_t need = (size_t)nprob * tql_ws_doubles(n) * sizeof(double);
       if (need > lws_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
@@ -2555,11 +2557,17 @@ class HipBackend : public Backend {
         launch_check("eigh_tridiag_kernel");
         hipLaunchKernelGGL(eigh_dc_kernel<128>, dim3(nprob), dim3(512),
                            (size_t)n * n * sizeof(double), s_, n, (double *)lws_);
-      } else {
+      } else if (n <= 256) {
         hipLaunchKernelGGL((eigh_tridiag_kernel<256, 1024>), dim3(nprob), dim3(1024), 0, s_, n,
                            lda, in, (double *)lws_);
         launch_check("eigh_tridiag_kernel");
         hipLaunchKernelGGL(eigh_dc_kernel<256>, dim3(nprob), dim3(512), 0, s_, n,
+                           (double *)lws_);
+      } else {
+        hipLaunchKernelGGL((eigh_tridiag_kernel<512, 1024>), dim3(nprob), dim3(1024), 0, s_, n,
+                           lda, in, (double *)lws_);
+        launch_check("eigh_tridiag_kernel");
+        hipLaunchKernelGGL(eigh_dc_kernel<512>, dim3(nprob), dim3(512), 0, s_, n,
                            (double *)lws_);
       }
       launch_check("eigh_dc_kernel");
@@ -2567,8 +2575,11 @@ class HipBackend : public Backend {
       if (n <= 128)
         hipLaunchKernelGGL(eigh_backtransform_kernel<128>, dim3((n + 15) / 16, nprob), dim3(256),
                            0, s_, n, (const double *)lws_, evals, vecs);
-      else
+      else if (n <= 256)
         hipLaunchKernelGGL(eigh_backtransform_kernel<256>, dim3((n + 15) / 16, nprob), dim3(256),
+                           0, s_, n, (const double *)lws_, evals, vecs);
+      else
+        hipLaunchKernelGGL(eigh_backtransform_kernel<512>, dim3((n + 3) / 4, nprob), dim3(256),
                            0, s_, n, (const double *)lws_, evals, vecs);
     }
     launch_check("eigh");

@@ -55,6 +55,12 @@ def test_validate_accepts_lattices():
 def test_validate_error_codes():
     e = L.eagle()
     assert _validate(_spec(e, chi=0)) == -1
+    assert _validate(_spec(e, chi=257)) == -1
+    assert _validate(_spec(e, chi=256)) == 0                # no two degree-3 sites adjacent
+    h = L.Lattice(6, np.array([[0, 1], [0, 2], [0, 3], [1, 4], [1, 5]], dtype=np.int32),
+                  np.array([0, 1, 2, 1, 2], dtype=np.int32))
+    assert _validate(_spec(h, chi=128)) == 0                 # degree-3 pair: 4 chi <= 512
+    assert _validate(_spec(h, chi=129)) == -1
     assert _validate(_spec(e, depth=-1)) == -1
     assert _validate(_spec(e, theta=float("nan"))) == -1
     assert _validate(_spec(e, bp_max_iter=0)) == -1

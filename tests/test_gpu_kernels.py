@@ -181,7 +181,8 @@ def test_gemm_rejects_out_of_bounds_descriptor(ctx):
         ctx.test_gemm(d, A, np.zeros(64 * 64, complex), np.zeros(64 * 64, complex))
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 31, 32, 40, 63, 64, 65, 97, 127, 128, 129, 200, 256])
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 31, 32, 40, 63, 64, 65, 97, 127, 128, 129, 200, 256,
+                               257, 300, 512])
 def test_eigh_matches_numpy(ctx, n):
     print(f"[eigh] n={n}", flush=True)
     rng = np.random.default_rng(n)
@@ -214,7 +215,8 @@ def test_eigh_matches_numpy(ctx, n):
 
 
 @pytest.mark.parametrize("n,rank", [(8, 8), (16, 5), (128, 128), (128, 70), (130, 129), (160, 100),
-                                    (200, 200), (256, 200), (256, 256)])
+                                    (200, 200), (256, 200), (256, 256), (384, 300),
+                                    (512, 512)])
 def test_gram_chol(ctx, n, rank):
     """Pivoted Cholesky of A^H A: R^H R = G, and Q = A Wsc is an isometry on the range."""
     print(f"[gram_chol] n={n} rank={rank}", flush=True)

@@ -657,3 +657,18 @@ def test_infinite_cell_chi80_vs_oracle(ctx):
     assert max(o.discarded) > 1e-6
     assert np.abs(g["z"] - o.z).max() < TOL
     assert np.abs(g["bond_entropy"] - o.entropy).max() < ENT_TOL
+
+
+def test_degree3_pair_chi72_tree_exact(ctx):
+    """Two adjacent degree-3 sites (an H-shaped tree) at chi = 72: the gate on their edge has a
+    4 chi = 288 truncation eigenproblem (the n > 256 eigensolver), the Gram factorisations
+    n = 144 (blocked) and the message roots n = 72 (GEMM); untruncated, so every <Z>(t) is the
+    state vector's, and the oracle agrees."""
+    print("[parity] H tree chi=72 (n = 288 eigensolver)", flush=True)
+    h = L.Lattice(6, np.array([[0, 1], [0, 2], [0, 3], [1, 4], [1, 5]], dtype=np.int32),
+                  np.array([0, 1, 2, 1, 2], dtype=np.int32), name="H6")
+    g = _gpu(ctx, h, 0.8, 4, 72)
+    want = SV.run(h.n_sites, h.edges, 0.8, 4)
+    assert np.abs(g["z"] - want).max() < 1e-10
+    o = _ora(h, 0.8, 4, 72)
+    assert np.abs(g["z"] - o.z).max() < TOL
