@@ -413,6 +413,52 @@ def infinite_lattice(chi: int, depth: int = 30) -> dict:
             "fp64_packed": packed}
 
 
+def infinite_lattice_chi256(depth: int) -> dict:
+    """The periodic heavy-hex cell at chi = 256 (the largest bond dimension of the thermodynamic-limit
+    workload; truncation eigenproblems of n = 512): theta_h = pi/4, `depth` Floquet steps, FP64
+    (BP tolerance 1e-12) and mixed precision (1e-8): <Z> per sublattice per step, the bond
+    entropies after the last step and the time per step over the saturated steps (9..depth)."""
+    import math
+
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    cell = L.infinite_cell()
+    th = math.pi / 4
+    runs, zs = [], {}
+    with bpki.Context(0) as ctx:
+        for prec, tol, name in ((bpki.BPKI_FP64, 1e-12, "fp64"), (bpki.BPKI_FP32, 1e-8, "mixed")):
+            sess = ctx.session(bpki.spec_from_lattice(cell, th, depth, 256, precision=prec,
+                                                      bp_tol=tol))
+            z, iters, sat = [], [], []
+            for t in range(depth):
+                t0 = time.perf_counter()
+                r = sess.step()
+                dt = time.perf_counter() - t0
+                if t >= 8:
+                    sat.append(dt)
+                z.append(r["z"])
+                iters.append(r["bp_iters"])
+            ent = sess.observe_bond_entropy()
+            sess.close()
+            z = np.array(z)
+            zs[name] = z
+            runs.append({
+                "precision": name, "ms_per_step_saturated": 1e3 * float(np.mean(sat)) if sat else None,
+                "bp_sweeps_per_step": float(np.mean(iters)),
+                "z_A": [round(float(x), 6) for x in z[:, 0]],
+                "z_B": [round(float(x), 6) for x in z[:, 1]],
+                "z_bridges": [round(float(x), 6) for x in z[:, 2:].mean(axis=1)],
+                "bond_entropy_last_step": [round(float(x), 6) for x in ent],
+            })
+            print(f"infinite cell chi=256 {name}: {runs[-1]['ms_per_step_saturated']:.1f} ms/step",
+                  file=sys.stderr, flush=True)
+    runs[1]["abs_dz_vs_fp64_max"] = float(np.abs(zs["mixed"] - zs["fp64"]).max())
+    return {"chi": 256, "theta_h": th, "steps": depth, "runs": runs}
+
+
 def bp_error_ring(steps: int = 5, chi: int = 4) -> dict:
     """The BP error estimate (Eq. "BPErrorEstimate") on one heavy hexagon (the 12-qubit ring, the
     paper's smallest loop): after each of `steps` Floquet steps at theta_h in {0, pi/8, pi/4,
@@ -477,6 +523,9 @@ def main() -> int:
     ap.add_argument("--infinite", type=int, default=128, metavar="CHI",
                     help="bond dimension of the infinite-lattice section (5-site periodic cell, "
                          "3 theta_h x 30 steps, FP64 and mixed; 0 = skip)")
+    ap.add_argument("--infinite256", type=int, default=30, metavar="STEPS",
+                    help="steps of the infinite-lattice cell at chi = 256 (theta_h = pi/4, FP64 and "
+                         "mixed; 0 = skip)")
     ap.add_argument("--bp-error", type=int, default=1,
                     help="1: also the BP error estimate on the 12-qubit ring (5 theta_h, 5 steps)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -594,6 +643,9 @@ def main() -> int:
     if args.infinite > 0:
         out["infinite_lattice"] = infinite_lattice(args.infinite)
         print("infinite lattice done", file=sys.stderr, flush=True)
+    if args.infinite256 > 0:
+        out["infinite_lattice_chi256"] = infinite_lattice_chi256(args.infinite256)
+        print("infinite lattice chi=256 done", file=sys.stderr, flush=True)
     if args.serving > 0:
         out["serving"] = serving_bench(args.serving, args.slots)
         print("serving done", file=sys.stderr, flush=True)

@@ -46,12 +46,12 @@ int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const
                    size_t a_elems, const double *B, size_t b_elems, double *C, size_t c_elems);
 
 /* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32, Householder
- * tridiagonalisation + divide and conquer otherwise) of nprob n x n matrices (n <= 256):
+ * tridiagonalisation + divide and conquer otherwise) of nprob n x n matrices (n <= 512):
  * evals [nprob][n] descending, vecs [nprob][n][n] with column i the eigenvector of evals[i]. */
 int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *evals,
                    double *vecs);
 
-/* Pivoted Cholesky factor of nprob Hermitian PSD n x n Gram matrices G (n <= 256): R [n][n]
+/* Pivoted Cholesky factor of nprob Hermitian PSD n x n Gram matrices G (n <= 512): R [n][n]
  * (R^H R = G, zero rows beyond the numerical rank) and Wsc [n][n] (A Wsc has orthonormal columns
  * when G = A^H A), with pivots stopping at cut * max(diag G). */
 int bpki_test_gram_chol(bpki_ctx *ctx, int n, int nprob, const double *G, double cut, double *R,
