@@ -162,7 +162,7 @@ def test_memory_estimate_bounds_the_device_footprint():
 
     lib = B.load()
     cases = [(L.eagle(), 32), (L.heavy_hex(5, 11), 64), (L.infinite_cell(), 128),
-             (L.hexagon_ring(), 16)]
+             (L.infinite_cell(), 256), (L.hexagon_ring(), 16)]
     for lat, chi in cases:                   # a fresh context each: its workspaces start empty
         spec = B.spec_from_lattice(lat, 0.7, 2, chi, bond_entropy=True)
         p, keep = spec.to_c()
