@@ -695,10 +695,16 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 // Workspace per matrix (doubles): reflectors n*n complex (column k = v_k), tau n complex,
 // Z n*n real (column-major), eigenvalues n, an n*n staging area for the merges, and for
 // n > 128 an n*n complex area that holds the matrix during the reduction (its lower triangle,
-// row-major) and the merge coefficient vectors V afterwards.  For n <= 128 the matrix and Z
-// live in LDS and Z's global area holds V during the merges.
+// row-major) and the merge coefficient vectors V afterwards, then for n > 256 the blocked
+// reduction's panel vectors [V | W] (n x 2 TRD_NB complex, row-major).  For n <= 128 the matrix and Z live in LDS
+// and Z's global area holds V during the merges.
+constexpr int TRD_NB = 32;
 __host__ __device__ __forceinline__ size_t tql_ws_doubles(int n) {
-  return (size_t)(n > 128 ? 6 : 4) * n * n + (size_t)3 * n;
+  return (size_t)(n > 128 ? 6 : 4) * n * n + (size_t)3 * n +
+         (n > 256 ? (size_t)4 * n * TRD_NB : 0);
+}
+__host__ __device__ __forceinline__ size_t trd_panel_offset(int n) {   // doubles, for n > 256
+  return (size_t)6 * n * n + (size_t)3 * n;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -1000,8 +1006,8 @@ __device__ __forceinline__ int dc_bound(int q, int n, int depth) {
 
 // eigh_tridiag_kernel: stage 1 (Householder reduction), NT threads per matrix; writes the
 // reflectors and tau, d to the eigenvalue area and e to the staging area of the workspace.
-// NMAX = 128: matrix packed (lower triangle) in LDS.  NMAX = 256, 512: lower triangle of a
-// row-major n x n array in this matrix's workspace (in L2 up to n = 256).
+// NMAX = 128: matrix packed (lower triangle) in LDS.  NMAX = 256: lower triangle of a row-major
+// n x n array in this matrix's workspace, which stays in L2 (n > 256: eigh_trd_panel_kernel).
 template <int NMAX, int NT>
 __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const double *const *in,
                                                           double *ws) {
@@ -1204,6 +1210,196 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
     dg[i] = d_s[i];
     Wg[i] = e_s[i];
   }
+}
+
+// Blocked Householder reduction for n > 256 (the reduction of eigh_tridiag_kernel, reorganised as in
+// LAPACK's panel form): a panel of TRD_NB reflectors is generated by one workgroup per matrix
+// without touching the stored matrix A_st, whose true trailing part is
+// A_st - V W^H - W V^H for the panel's reflector vectors V and w-vectors W so far; the column a
+// reflector is taken from and every product S v are corrected on the fly.  After the panel two
+// GEMMs apply A_st -= V W^H + W V^H.  The single-workgroup memory traffic per reflector drops from
+// four passes over the trailing triangle (two reads for S v, read and write for the rank-2
+// update) to two.  Outputs as eigh_tridiag_kernel: reflectors and tau, d to the eigenvalue area
+// and e to the staging area.
+template <int NMAX, int NT>
+__global__ __launch_bounds__(NT) void eigh_trd_panel_kernel(int n, int lda, const double *const *in,
+                                                            double *ws, int k0) {
+  constexpr int HALVES = NT / 256;
+  __shared__ __attribute__((aligned(16))) double sbuf[(6 + 2 * HALVES) * NMAX];
+  __shared__ double2 pq_s[2 * TRD_NB];
+  __shared__ double2 tau_sh;
+  double2 *v_s = reinterpret_cast<double2 *>(sbuf), *a_s = v_s + NMAX;
+  double2 *x1_s = a_s + NMAX, *x2_s = x1_s + NMAX;
+  const int prob = blockIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int nw = NT / 64;
+  double *base = ws + (size_t)prob * tql_ws_doubles(n);
+  double2 *hh = reinterpret_cast<double2 *>(base);
+  double2 *tau_g = hh + (size_t)n * n;
+  double *Zg = reinterpret_cast<double *>(tau_g + n);
+  double *dg = Zg + (size_t)n * n;
+  double *Wg = dg + n;
+  double2 *Pg = reinterpret_cast<double2 *>(Wg + (size_t)n * n);
+  double2 *U = reinterpret_cast<double2 *>(base + trd_panel_offset(n));   // [n][2 TRD_NB]
+  constexpr int UL = 2 * TRD_NB;
+  if (k0 == 0) {
+    const double2 *src = reinterpret_cast<const double2 *>(in[prob]);
+    for (int i = wave; i < n; i += nw)
+      for (int j = lane; j <= i; j += 64) {
+        const double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
+        Pg[(size_t)i * n + j] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+      }
+  }
+  for (int idx = tid; idx < n * UL; idx += NT) U[idx] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const int kend = min(n - 1, k0 + TRD_NB);
+  for (int k = k0; k < kend; ++k) {
+    const int j = k - k0, m = n - 1 - k;
+    // 1. column k of the true matrix, rows k..n-1: A_st[i][k] - sum_c V[i][c] conj(W[k][c]) +
+    //    W[i][c] conj(V[k][c])
+    for (int i = k + tid; i < n; i += NT) {
+      double2 a = Pg[(size_t)i * n + k];
+      for (int c = 0; c < j; ++c) {
+        const double2 vi = U[(size_t)i * UL + c], wi = U[(size_t)i * UL + TRD_NB + c];
+        const double2 vk = U[(size_t)k * UL + c], wk = U[(size_t)k * UL + TRD_NB + c];
+        // vi conj(wk) + wi conj(vk)
+        a.x -= vi.x * wk.x + vi.y * wk.y + wi.x * vk.x + wi.y * vk.y;
+        a.y -= vi.y * wk.x - vi.x * wk.y + wi.y * vk.x - wi.x * vk.y;
+      }
+      a_s[i - k] = a;
+    }
+    __syncthreads();
+    // 2. the reflector (wave 0), as in eigh_tridiag_kernel
+    if (wave == 0) {
+      double sq = 0.0;
+      for (int i = 2 + lane; i <= m; i += 64) {
+        const double2 x = a_s[i];
+        sq += x.x * x.x + x.y * x.y;
+      }
+      sq = wave_sum(sq);
+      const double2 alpha = a_s[1];
+      double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+      double beta = alpha.x;
+      if (sq > 0.0 || alpha.y != 0.0) {
+        beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sq), alpha.x);
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
+        const double dn = den.x * den.x + den.y * den.y;
+        scale = make_double2(den.x / dn, -den.y / dn);
+      }
+      for (int i = lane; i < m; i += 64) {
+        const double2 vi = i == 0 ? make_double2(1.0, 0.0) : cmul(a_s[1 + i], scale);
+        v_s[i] = vi;
+        hh[(size_t)k * n + k + 1 + i] = vi;
+        U[(size_t)(k + 1 + i) * UL + j] = vi;
+      }
+      if (lane == 0) {
+        tau_sh = tau;
+        tau_g[k] = tau;
+        Wg[k] = beta;
+        dg[k] = a_s[0].x;
+      }
+    }
+    __syncthreads();
+    const double2 tau = tau_sh;
+    if (tau.x == 0.0 && tau.y == 0.0) continue;   // H_k = I: w = 0 (U's column stays 0)
+    // 3. S v over the stored trailing block (two coalesced passes as in eigh_tridiag_kernel) and
+    //    the panel scalars p_c = W_c^H v, q_c = V_c^H v (rows k+1..n-1)
+    const double2 *S0 = Pg + (size_t)(k + 1) * n + k + 1;
+    {
+      const int q = tid & 15;
+      for (int r = tid >> 4; r < m; r += NT / 16) {
+        const double2 *prow = S0 + (size_t)r * n;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int c = q; c <= r; c += 16) {
+          const double2 a = prow[c], vc = v_s[c];
+          acc.x += a.x * vc.x - a.y * vc.y;
+          acc.y += a.x * vc.y + a.y * vc.x;
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          acc.x += __shfl_xor(acc.x, o, 64);
+          acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (q == 0) x1_s[r] = acc;
+      }
+    }
+    for (int c = tid & 255; c < NMAX; c += 256) {
+      const int half = tid >> 8, c0 = c & ~63;
+      if (c0 < m) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int r = c0 + 1 + half; r < m; r += HALVES) {
+          if (r > c) {
+            const double2 a = S0[(size_t)r * n + c], vr = v_s[r];   // conj(a) v_r
+            acc.x += a.x * vr.x + a.y * vr.y;
+            acc.y += a.x * vr.y - a.y * vr.x;
+          }
+        }
+        if (c < m) x2_s[half * NMAX + c] = acc;
+      }
+    }
+    for (int c = wave; c < 2 * j; c += nw) {      // c < j: p_c (W column), else q_{c-j} (V)
+      const int col = c < j ? TRD_NB + c : c - j;
+      double pr = 0.0, pi = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        const double2 u = U[(size_t)(k + 1 + i) * UL + col], vi = v_s[i];   // conj(u) v
+        pr += u.x * vi.x + u.y * vi.y;
+        pi += u.x * vi.y - u.y * vi.x;
+      }
+      pr = wave_sum(pr);
+      pi = wave_sum(pi);
+      if (lane == 0) pq_s[c] = make_double2(pr, pi);
+    }
+    __syncthreads();
+    // x_i = tau (S v - sum_c V[i][c] p_c + W[i][c] q_c)
+    for (int i = tid; i < m; i += NT) {
+      double2 t = x1_s[i];
+#pragma unroll
+      for (int h = 0; h < HALVES; ++h) {
+        const double2 u = x2_s[h * NMAX + i];
+        t.x += u.x;
+        t.y += u.y;
+      }
+      for (int c = 0; c < j; ++c) {
+        const double2 vi = U[(size_t)(k + 1 + i) * UL + c], wi = U[(size_t)(k + 1 + i) * UL + TRD_NB + c];
+        const double2 p = pq_s[c], q = pq_s[j + c];
+        t.x -= vi.x * p.x - vi.y * p.y + wi.x * q.x - wi.y * q.y;
+        t.y -= vi.x * p.y + vi.y * p.x + wi.x * q.y + wi.y * q.x;
+      }
+      x1_s[i] = cmul(tau, t);
+    }
+    __syncthreads();
+    // 4. w = x + a v with a = -(1/2) Re(conj(tau) v^H x) (every wave forms a itself)
+    double dr = 0.0, di = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double2 vi = v_s[i], xi = x1_s[i];
+      dr += vi.x * xi.x + vi.y * xi.y;
+      di += vi.x * xi.y - vi.y * xi.x;
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double aw = -0.5 * (tau.x * dr + tau.y * di);
+    for (int i = tid; i < m; i += NT) {
+      const double2 vi = v_s[i], xi = x1_s[i];
+      U[(size_t)(k + 1 + i) * UL + TRD_NB + j] = make_double2(xi.x + aw * vi.x, xi.y + aw * vi.y);
+    }
+    __syncthreads();
+  }
+}
+
+// Last diagonal entry after the final panel update (d[n-1]; e[n-1] = 0).  One thread per matrix.
+__global__ void eigh_trd_last_kernel(int n, double *ws, int nprob) {
+  const int prob = blockIdx.x * blockDim.x + threadIdx.x;
+  if (prob >= nprob) return;
+  double *base = ws + (size_t)prob * tql_ws_doubles(n);
+  double2 *tau_g = reinterpret_cast<double2 *>(base) + (size_t)n * n;
+  double *Zg = reinterpret_cast<double *>(tau_g + n);
+  double *dg = Zg + (size_t)n * n;
+  double *Wg = dg + n;
+  const double2 *Pg = reinterpret_cast<const double2 *>(Wg + (size_t)n * n);
+  dg[n - 1] = Pg[(size_t)(n - 1) * n + n - 1].x;
+  Wg[n - 1] = 0.0;
 }
 
 // eigh_dc_kernel: stage 2 (divide and conquer on the tridiagonal d, e left by
@@ -2307,6 +2503,7 @@ class HipBackend : public Backend {
     if (cws_) HIPCHK(hipFree(cws_));
     if (cmeta_) HIPCHK(hipFree(cmeta_));
     if (sqws_) HIPCHK(hipFree(sqws_));
+    if (tptr_) HIPCHK(hipFree(tptr_));
     if (lws_) HIPCHK(hipFree(lws_));
     if (rws_) HIPCHK(hipFree(rws_));
     if (pin_) HIPCHK(hipHostFree(pin_));
@@ -2520,6 +2717,57 @@ class HipBackend : public Backend {
     }
     prof_ev_.clear();
   }
+  // Blocked Householder reduction (n > 256): panels of TRD_NB reflectors, each followed by the
+  // two GEMMs A_st -= V W^H + W V^H on every matrix, then the last diagonal entry.
+  void trd_blocked(int n, int lda, const double *const *in, int nprob) {
+    const size_t need = (size_t)6 * nprob * sizeof(void *);
+    if (need > tptr_bytes_) {
+      HIPCHK(hipStreamSynchronize(s_));
+      if (tptr_) HIPCHK(hipFree(tptr_));
+      tptr_ = nullptr;
+      tptr_bytes_ = 0;
+      if (hipMalloc(&tptr_, need) != hipSuccess) {
+        err_ = -4;
+        errmsg_ = "eigh pointer table allocation failed";
+        return;
+      }
+      tptr_bytes_ = need;
+    }
+    std::vector<void *> hp((size_t)6 * nprob);
+    for (int q = 0; q < nprob; ++q) {
+      double *base = (double *)lws_ + (size_t)q * tql_ws_doubles(n);
+      double2 *U = (double2 *)(base + trd_panel_offset(n));
+      double2 *P = (double2 *)(base + (size_t)4 * n * n + (size_t)3 * n);   // the stored matrix
+      hp[0 * nprob + q] = U;                // V W^H: A = V, B = W
+      hp[1 * nprob + q] = U + TRD_NB;
+      hp[2 * nprob + q] = P;
+      hp[3 * nprob + q] = U + TRD_NB;       // W V^H: A = W, B = V
+      hp[4 * nprob + q] = U;
+      hp[5 * nprob + q] = P;
+    }
+    h2d(tptr_, hp.data(), need);
+    void **tp = (void **)tptr_;
+    GemmDesc d;
+    d.M = d.Mi = n; d.N = d.Ni = n; d.K = d.Ki = TRD_NB;
+    d.a_mi = 2 * TRD_NB; d.a_ki = 1;
+    d.b_ki = 1; d.b_ni = 2 * TRD_NB; d.conjB = 1;
+    d.c_mi = n; d.c_ni = 1;
+    d.beta = 1; d.alpha_re = -1.0;
+    for (int k0 = 0; k0 < n - 1; k0 += TRD_NB) {
+      stale_check("eigh_trd_panel_kernel");
+      hipLaunchKernelGGL((eigh_trd_panel_kernel<512, 1024>), dim3(nprob), dim3(1024), 0, s_, n,
+                         lda, in, (double *)lws_, k0);
+      launch_check("eigh_trd_panel_kernel");
+      gemm(d, (const double *const *)tp, (const double *const *)(tp + nprob),
+           (double *const *)(tp + 2 * nprob), nprob);
+      gemm(d, (const double *const *)(tp + 3 * nprob), (const double *const *)(tp + 4 * nprob),
+           (double *const *)(tp + 5 * nprob), nprob);
+    }
+    stale_check("eigh_trd_last_kernel");
+    hipLaunchKernelGGL(eigh_trd_last_kernel, dim3((nprob + 63) / 64), dim3(64), 0, s_, n,
+                       (double *)lws_, nprob);
+    launch_check("eigh_trd_last_kernel");
+  }
   void eigh(int n, int lda, const double *const *in, double *const *evals, double *const *vecs,
             int nprob) override {
     if (nprob <= 0) return;
@@ -2564,9 +2812,10 @@ class HipBackend : public Backend {
         hipLaunchKernelGGL(eigh_dc_kernel<256>, dim3(nprob), dim3(512), 0, s_, n,
                            (double *)lws_);
       } else {
-        hipLaunchKernelGGL((eigh_tridiag_kernel<512, 1024>), dim3(nprob), dim3(1024), 0, s_, n,
-                           lda, in, (double *)lws_);
-        launch_check("eigh_tridiag_kernel");
+        // n > 256: the blocked reduction (at n = 256 the single kernel is as fast: ~50 matrices
+        // per launch keep enough workgroups busy, and the panels' extra launches cost more)
+        trd_blocked(n, lda, in, nprob);
+        if (err_) return;
         hipLaunchKernelGGL(eigh_dc_kernel<512>, dim3(nprob), dim3(512), 0, s_, n,
                            (double *)lws_);
       }
@@ -2917,6 +3166,8 @@ class HipBackend : public Backend {
   size_t cmeta_bytes_ = 0;
   void *sqws_ = nullptr;             // message square roots on the GEMM: scaled vectors, pointers
   size_t sqws_bytes_ = 0;
+  void *tptr_ = nullptr;             // blocked tridiagonalisation: GEMM pointer table
+  size_t tptr_bytes_ = 0;
   void *skws_ = nullptr;
   size_t skws_bytes_ = 0;
   int prof_stride_ = 0;
