@@ -123,3 +123,15 @@ def test_create_without_device_fails_loudly():
     rc = lib.bpki_create(C.byref(h), 0, None, 0)
     assert rc == -5
     assert b"HIP" in lib.bpki_last_error() or b"device" in lib.bpki_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus N > 1 exits with status 2 and says why, before any
+    device work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
