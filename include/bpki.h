@@ -208,10 +208,12 @@ int bpki_session_observe_z(bpki_session *s, double *z);
 int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy);
 /* Explicit symmetric Vidal gauge from the current messages (Methods, "The Vidal gauge"), in
  * place.  For every edge (u, v) with X_u = M_{u->v}^{1/2}, X_v = M_{v->u}^{1/2} and the SVD
- * X_u^T X_v = U S V^H, leg u->v of T_u absorbs X_u^{T+} U S^{1/2} and leg v->u of T_v absorbs
- * X_v^{T+} conj(V) S^{1/2}: the identity (on the supports of the messages) is inserted on every
- * bond, so the state changes only by a positive factor; each site tensor with S^{-1/2} removed
- * from its legs (Gamma_v) then forms, with S on its other legs, the isometries of Eqs.
+ * X_u^T X_v = U S V^H, leg u->v of T_u absorbs X_u^{T+} U W and leg v->u of T_v absorbs
+ * X_v^{T+} conj(V) W with W = (S / sum S)^{1/2}: the identity (on the supports of the messages,
+ * up to a positive factor) is inserted on every bond, so the state changes only by a positive
+ * factor, and a state already in this gauge is left as it is (the transform is idempotent up to
+ * the SVD's unitary freedom); each site tensor with W^{-1} removed from its legs (Gamma_v, up to
+ * scale) then forms, with S on its other legs, the isometries of Eqs.
  * "IsometryPropertyDefinition" and "IsometryDefinition", and diag(S)/sum(S) on both directions
  * (written as the new messages) is a BP fixed point.  S is normalised to unit 2-norm; singular
  * values <= svd_cutoff * s_1 are dropped (bond dimensions shrink accordingly).  Computed from the
