@@ -312,6 +312,7 @@ def theta_batch(lat, chi: int, depth: int) -> dict:
     thetas = L.theta_draw(8, 2306)
     with bpki.Context(0) as ctx:
         ctx.serving_config(len(thetas))
+        ctx.serving_packing(1)
         t0 = time.perf_counter()
         tickets = [ctx.submit(bpki.spec_from_lattice(lat, float(t), depth, chi)) for t in thetas]
         outs = [t.wait() for t in tickets]
@@ -319,6 +320,40 @@ def theta_batch(lat, chi: int, depth: int) -> dict:
     return {"thetas": len(thetas), "depth": depth, "chi": chi, "precision": "fp64",
             "aggregate_steps_per_s": len(thetas) * depth / wall, "makespan_s": wall,
             "bp_sweeps_per_step": float(sum(sum(o["bp_iters"]) for o in outs)) / (len(thetas) * depth)}
+
+
+def precision_form(lat, chi: int, depth: int) -> dict:
+    """The precision form of the workload: the eight seeded theta_h values (one serving slot
+    each), with the 64 seeded Pauli strings (weight 3..17, tree clusters, X/Y/Z uniform) measured
+    after the last step, in FP64 and in mixed precision (FP32 BP contractions, BP tolerance 1e-8):
+    the absolute error of every <Z_v>(t) and every string of the mixed run against the FP64 run,
+    and the wall time of each batch (steps and strings)."""
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    thetas = L.theta_draw(8, 2306)
+    strings = [(p.sites, p.ops) for p in L.random_pauli_strings(lat, 64, seed=14887)]
+    res = {}
+    for name, prec, tol in (("fp64", bpki.BPKI_FP64, 1e-12), ("mixed", bpki.BPKI_FP32, MIXED_TOL)):
+        with bpki.Context(0) as ctx:
+            ctx.serving_config(len(thetas))
+            ctx.serving_packing(1)
+            t0 = time.perf_counter()
+            tickets = [ctx.submit(bpki.spec_from_lattice(lat, float(t), depth, chi, precision=prec,
+                                                         bp_tol=tol, pauli=strings))
+                       for t in thetas]
+            outs = [t.wait() for t in tickets]
+            res[name] = (outs, time.perf_counter() - t0)
+    (o64, w64), (o32, w32) = res["fp64"], res["mixed"]
+    dz = np.abs(np.array([o["z"] for o in o32]) - np.array([o["z"] for o in o64]))
+    dp = np.abs(np.array([o["pauli"] for o in o32]) - np.array([o["pauli"] for o in o64]))
+    return {"thetas": len(thetas), "depth": depth, "chi": chi, "pauli_strings": len(strings),
+            "fp64_batch_s": w64, "mixed_batch_s": w32,
+            "abs_dz_max": float(dz.max()), "abs_dz_median": float(np.median(dz)),
+            "abs_dpauli_max": float(dp.max()), "abs_dpauli_median": float(np.median(dp)),
+            "pauli_abs_max_fp64": float(np.abs(np.array([o["pauli"] for o in o64])).max())}
 
 
 def chi128_window(lat, theta: float, warmup: int = 7, steps: int = 3) -> dict:
@@ -523,6 +558,8 @@ def main() -> int:
     ap.add_argument("--infinite", type=int, default=128, metavar="CHI",
                     help="bond dimension of the infinite-lattice section (5-site periodic cell, "
                          "3 theta_h x 30 steps, FP64 and mixed; 0 = skip)")
+    ap.add_argument("--precision-form", type=int, default=1,
+                    help="1: also the 8 theta_h with 64 Pauli strings each, FP64 vs mixed errors")
     ap.add_argument("--infinite256", type=int, default=30, metavar="STEPS",
                     help="steps of the infinite-lattice cell at chi = 256 (theta_h = pi/4, FP64 and "
                          "mixed; 0 = skip)")
@@ -637,6 +674,9 @@ def main() -> int:
     if args.theta_batch:
         out["theta_batch"] = theta_batch(lat, chi, args.warmup + args.steps)
         print("theta batch done", file=sys.stderr, flush=True)
+    if args.precision_form:
+        out["precision_form"] = precision_form(lat, chi, args.warmup + args.steps)
+        print("precision form done", file=sys.stderr, flush=True)
     if args.bp_error:
         out["bp_error_ring"] = bp_error_ring()
         print("BP error estimate done", file=sys.stderr, flush=True)
