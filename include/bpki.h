@@ -123,6 +123,24 @@ int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t mem_budget_
  * No call other than bpki_session_* on those open sessions may use `ctx` afterwards. */
 void bpki_destroy(bpki_ctx *ctx);
 
+/* The caller's device allocator (a framework's caching allocator, a pool) in place of hipMalloc
+ * and hipFree for every device buffer of the context: site tensors, messages and workspaces of its
+ * solves, sessions and serving slots.
+ *   alloc(bytes, stream, user): device memory for use on `stream` (the hipStream_t of the library
+ *     that will use it), aligned to 256 bytes, or NULL when there is none (the call that needed it
+ *     then fails with -4; a pointer not so aligned goes back to `free` and the call fails with -5).
+ *   free(ptr, stream, user): called once the library's work on `stream` has completed, so the
+ *     memory may be reused at once; from the host thread that released the buffer (the caller's,
+ *     or a serving slot's worker).  Neither callback may call into the library.
+ * Both callbacks or neither (NULL, NULL: hipMalloc and hipFree).  Only before the context has
+ * taken device memory (no solve, session, submit or test call yet): -1 otherwise.  `user` and the
+ * callbacks must stay valid until bpki_destroy has returned and the last session is closed.
+ * A failed allocation, like a device error, is sticky: later calls on the context (or on that
+ * serving slot) fail too. */
+typedef void *(*bpki_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*bpki_free_fn)(void *ptr, void *stream, void *user);
+int bpki_set_allocator(bpki_ctx *ctx, bpki_alloc_fn alloc, bpki_free_fn free, void *user);
+
 /* Message of the last error on this thread (never NULL). */
 const char *bpki_last_error(void);
 

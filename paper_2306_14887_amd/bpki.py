@@ -58,6 +58,11 @@ class TestGemmDesc(C.Structure):
 _lib = None
 
 
+# bpki_alloc_fn / bpki_free_fn: (bytes, stream, user) -> device pointer; (ptr, stream, user)
+AllocFn = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FreeFn = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
 def load(path: str | None = None):
     """Load libbpki.so (once).  Raises if it has not been built."""
     global _lib
@@ -74,6 +79,7 @@ def load(path: str | None = None):
         "bpki_problem_defaults": (None, [P]),
         "bpki_create": (C.c_int, [C.POINTER(vp), C.c_int, vp, C.c_size_t]),
         "bpki_destroy": (None, [vp]),
+        "bpki_set_allocator": (C.c_int, [vp, AllocFn, FreeFn, vp]),
         "bpki_last_error": (C.c_char_p, []),
         "bpki_validate": (C.c_int, [P]),
         "bpki_estimate_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
@@ -125,7 +131,7 @@ def exported_symbols() -> list[str]:
     return ["bpki_problem_defaults", "bpki_create", "bpki_destroy", "bpki_last_error",
             "bpki_validate", "bpki_estimate_bytes", "bpki_solve", "bpki_submit", "bpki_poll",
             "bpki_wait", "bpki_cancel", "bpki_serving_config", "bpki_serving_packing",
-            "bpki_ticket_times", "bpki_ticket_pack_size",
+            "bpki_ticket_times", "bpki_ticket_pack_size", "bpki_set_allocator",
             "bpki_session_open", "bpki_session_close",
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
             "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
@@ -210,6 +216,23 @@ def spec_from_lattice(lat, theta, depth, chi, **kw) -> ProblemSpec:
     return ProblemSpec(lat.n_sites, lat.edges, lat.colour, theta, depth, chi, **kw)
 
 
+def torch_allocator(device: int = 0):
+    """(alloc, free) for Context.set_allocator that take the memory from torch's caching allocator,
+    on the library's stream (torch then reuses a returned block in that stream's order only)."""
+    import torch
+
+    def alloc(nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(nbytes, device, stream or 0)
+        except torch.OutOfMemoryError:
+            return None
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
+
+
 class Context:
     """A device context (HIP device, stream, memory budget)."""
 
@@ -221,6 +244,19 @@ class Context:
                                               C.c_void_p(stream) if stream else None,
                                               mem_budget))
         self.h = h
+
+    def set_allocator(self, alloc, free):
+        """Take the context's device memory from alloc(nbytes, stream) -> pointer (int, or None
+        when there is none) and give it back with free(ptr, stream); streams are hipStream_t
+        handles as ints (None for the null stream).  Before the first solve, session or submit.
+        The callbacks run on the library's threads (serving slots included).  (None, None) keeps
+        hipMalloc and hipFree."""
+        if alloc is None and free is None:
+            self._alloc_cb, self._free_cb = AllocFn(), FreeFn()       # NULL function pointers
+        else:
+            self._alloc_cb = AllocFn(lambda n, stream, user: alloc(n, stream))
+            self._free_cb = FreeFn(lambda p, stream, user: free(p, stream))
+        _check(self.lib, self.lib.bpki_set_allocator(self.h, self._alloc_cb, self._free_cb, None))
 
     def close(self):
         if self.h:

@@ -213,6 +213,10 @@ struct bpki_ctx {
   // sessions is closed, whichever comes second
   int open_sessions = 0;
   bool destroyed = false;
+  // caller's device allocator (bpki_set_allocator), also given to the serving slots' backends
+  bpki_alloc_fn ualloc = nullptr;
+  bpki_free_fn ufree = nullptr;
+  void *uuser = nullptr;
 };
 
 extern "C" int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t budget) {
@@ -226,6 +230,19 @@ extern "C" int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t 
   c->budget = budget;
   c->be.reset(be);
   *out = c;
+  return 0;
+}
+
+extern "C" int bpki_set_allocator(bpki_ctx *c, bpki_alloc_fn alloc, bpki_free_fn free, void *user) {
+  if (!c) return fail(-1, "ctx is NULL");
+  if (!alloc != !free) return fail(-1, "give both alloc and free, or neither");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->slot_threads.empty() || c->open_sessions || c->be->set_allocator(alloc, free, user))
+    return fail(-1, "the context already holds device memory: set the allocator before the first "
+                    "solve, session or submit");
+  c->ualloc = alloc;
+  c->ufree = free;
+  c->uuser = user;
   return 0;
 }
 
@@ -857,6 +874,7 @@ static int start_slots(bpki_ctx *c) {
     std::string err;
     Backend *be = make_hip_backend(c->device, nullptr, &err);
     if (!be) return fail(-5, "serving slot: " + err);
+    be->set_allocator(c->ualloc, c->ufree, c->uuser);      // a fresh backend takes it
     c->slot_be.emplace_back(be);
   }
   for (int i = 0; i < c->n_slots; ++i) c->slot_threads.emplace_back(slot_loop, c, i);

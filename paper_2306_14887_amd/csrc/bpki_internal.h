@@ -39,9 +39,15 @@ inline void set_simple_m(GemmDesc &d, int M, long sa, long sc) { d.M = M; d.Mi =
 
 enum class Prec : int { F64 = 0, F32 = 1 };
 
+// A caller's device allocator: memory for use on `stream`, and its return once that stream is idle.
+typedef void *(*DevAlloc)(size_t bytes, void *stream, void *user);
+typedef void (*DevFree)(void *ptr, void *stream, void *user);
+
 // Small device kernels used by the engine (implemented in hip_backend.hip).
 struct Backend {
   virtual ~Backend() {}
+  // Route every device allocation of this backend through (a, f); -1 once it holds device memory.
+  virtual int set_allocator(DevAlloc a, DevFree f, void *user) = 0;
   virtual void *alloc(size_t bytes) = 0;          // zero-initialised
   virtual void release(void *p) = 0;
   virtual void h2d(void *dst, const void *src, size_t bytes) = 0;

@@ -2499,21 +2499,53 @@ class HipBackend : public Backend {
   ~HipBackend() override {
     for (auto &e : ev_)
       if (e) hipEventDestroy(e);
-    if (skws_) HIPCHK(hipFree(skws_));
-    if (cws_) HIPCHK(hipFree(cws_));
-    if (cmeta_) HIPCHK(hipFree(cmeta_));
-    if (sqws_) HIPCHK(hipFree(sqws_));
-    if (tptr_) HIPCHK(hipFree(tptr_));
-    if (lws_) HIPCHK(hipFree(lws_));
-    if (rws_) HIPCHK(hipFree(rws_));
+    if (skws_) HIPCHK(dfree(skws_));
+    if (cws_) HIPCHK(dfree(cws_));
+    if (cmeta_) HIPCHK(dfree(cmeta_));
+    if (sqws_) HIPCHK(dfree(sqws_));
+    if (tptr_) HIPCHK(dfree(tptr_));
+    if (lws_) HIPCHK(dfree(lws_));
+    if (rws_) HIPCHK(dfree(rws_));
     if (pin_) HIPCHK(hipHostFree(pin_));
     if (own_) hipStreamDestroy(s_);
   }
+  int set_allocator(DevAlloc a, DevFree f, void *user) override {
+    if (touched_ || !a != !f) return -1;
+    ua_ = a;
+    uf_ = f;
+    uu_ = user;
+    return 0;
+  }
+  // Device memory from hipMalloc, or from the caller's allocator: asked for memory used on this
+  // backend's stream, which must come 256-byte aligned as hipMalloc's does (correctness needs the
+  // 16 bytes of a complex double; the rest keeps a tile row's loads within whole cache lines).
+  hipError_t dmalloc(void **p, size_t bytes) {
+    touched_ = true;
+    if (!ua_) return hipMalloc(p, bytes);
+    *p = ua_(bytes, (void *)s_, uu_);
+    if (*p && ((uintptr_t)*p & 255)) {
+      uf_(*p, (void *)s_, uu_);
+      *p = nullptr;
+      if (err_ == 0) {
+        err_ = -5;
+        errmsg_ = "the device allocator returned memory not aligned to 256 bytes";
+      }
+    }
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  // The caller's free runs after this stream has drained: the allocator may hand the memory to
+  // other work at once.
+  hipError_t dfree(void *p) {
+    if (!uf_) return hipFree(p);
+    hipError_t e = hipStreamSynchronize(s_);
+    uf_(p, (void *)s_, uu_);
+    return e;
+  }
   void *alloc(size_t bytes) override {
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = dmalloc(&p, bytes);
     if (e != hipSuccess) {
-      if (err_ == 0) { err_ = -4; errmsg_ = "hipMalloc failed (out of device memory)"; }
+      if (err_ == 0) { err_ = -4; errmsg_ = "device allocation failed (out of device memory)"; }
       return nullptr;
     }
     HIPCHK(hipMemsetAsync(p, 0, bytes, s_));
@@ -2522,10 +2554,12 @@ class HipBackend : public Backend {
   void release(void *p) override {
     if (p) {
       HIPCHK(hipStreamSynchronize(s_));
-      HIPCHK(hipFree(p));
+      HIPCHK(dfree(p));
     }
   }
+  // After an error (a failed allocation leaves null buffers behind) no copy is issued.
   void h2d(void *d, const void *h, size_t b) override {
+    if (err_) return;
     if (b) HIPCHK(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s_));
     HIPCHK(hipStreamSynchronize(s_));
   }
@@ -2533,6 +2567,7 @@ class HipBackend : public Backend {
   // polling wait on the stream: the host resumes as soon as the stream drains, which shortens
   // the bubble between BP sweeps.
   void d2h(void *h, const void *d, size_t b) override {
+    if (err_) return;
     if (b && b <= kPinBytes && pin_) {
       HIPCHK(hipMemcpyAsync(pin_, d, b, hipMemcpyDeviceToHost, s_));
       hipError_t e;
@@ -2549,6 +2584,7 @@ class HipBackend : public Backend {
     HIPCHK(hipStreamSynchronize(s_));
   }
   void d2d(void *d, const void *s, size_t b) override {
+    if (err_) return;
     if (b) HIPCHK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, s_));
   }
   void sync() override { HIPCHK(hipStreamSynchronize(s_)); }
@@ -2676,10 +2712,10 @@ class HipBackend : public Backend {
   void *splitk_ws(size_t need) {
     if (need > skws_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
-      if (skws_) HIPCHK(hipFree(skws_));
+      if (skws_) HIPCHK(dfree(skws_));
       skws_ = nullptr;
       skws_bytes_ = 0;
-      if (hipMalloc(&skws_, need) != hipSuccess) {
+      if (dmalloc(&skws_, need) != hipSuccess) {
         err_ = -4;
         errmsg_ = "split-K workspace allocation failed";
         return nullptr;
@@ -2723,10 +2759,10 @@ class HipBackend : public Backend {
     const size_t need = (size_t)6 * nprob * sizeof(void *);
     if (need > tptr_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
-      if (tptr_) HIPCHK(hipFree(tptr_));
+      if (tptr_) HIPCHK(dfree(tptr_));
       tptr_ = nullptr;
       tptr_bytes_ = 0;
-      if (hipMalloc(&tptr_, need) != hipSuccess) {
+      if (dmalloc(&tptr_, need) != hipSuccess) {
         err_ = -4;
         errmsg_ = "eigh pointer table allocation failed";
         return;
@@ -2787,10 +2823,10 @@ class HipBackend : public Backend {
       size_t need = (size_t)nprob * tql_ws_doubles(n) * sizeof(double);
       if (need > lws_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
-        if (lws_) HIPCHK(hipFree(lws_));
+        if (lws_) HIPCHK(dfree(lws_));
         lws_ = nullptr;
         lws_bytes_ = 0;
-        if (hipMalloc(&lws_, need) != hipSuccess) {
+        if (dmalloc(&lws_, need) != hipSuccess) {
           err_ = -4;
           errmsg_ = "eigh workspace allocation failed";
           return;
@@ -2850,10 +2886,10 @@ class HipBackend : public Backend {
     const size_t need = (size_t)nprob * 2 * n * n * sizeof(double2) + 2 * nprob * sizeof(void *);
     if (need > sqws_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
-      if (sqws_) HIPCHK(hipFree(sqws_));
+      if (sqws_) HIPCHK(dfree(sqws_));
       sqws_ = nullptr;
       sqws_bytes_ = 0;
-      if (hipMalloc(&sqws_, need) != hipSuccess) {
+      if (dmalloc(&sqws_, need) != hipSuccess) {
         err_ = -4;
         errmsg_ = "message square-root workspace allocation failed";
         return;
@@ -2881,10 +2917,10 @@ class HipBackend : public Backend {
     size_t need = (size_t)nprob * (n <= 128 ? 3 * (size_t)n * n : chol_stride(n)) * sizeof(double2);
     if (need > cws_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
-      if (cws_) HIPCHK(hipFree(cws_));
+      if (cws_) HIPCHK(dfree(cws_));
       cws_ = nullptr;
       cws_bytes_ = 0;
-      if (hipMalloc(&cws_, need) != hipSuccess) {
+      if (dmalloc(&cws_, need) != hipSuccess) {
         err_ = -4;
         errmsg_ = "Cholesky workspace allocation failed";
         return;
@@ -2907,10 +2943,10 @@ class HipBackend : public Backend {
       const size_t moff = (mbytes + 15) & ~size_t(15);
       if (moff + pbytes > cmeta_bytes_) {
         HIPCHK(hipStreamSynchronize(s_));
-        if (cmeta_) HIPCHK(hipFree(cmeta_));
+        if (cmeta_) HIPCHK(dfree(cmeta_));
         cmeta_ = nullptr;
         cmeta_bytes_ = 0;
-        if (hipMalloc(&cmeta_, moff + pbytes) != hipSuccess) {
+        if (dmalloc(&cmeta_, moff + pbytes) != hipSuccess) {
           err_ = -4;
           errmsg_ = "Cholesky workspace allocation failed";
           return;
@@ -3120,10 +3156,10 @@ class HipBackend : public Backend {
     const size_t need = (size_t)nprob * RHO_CHUNKS * 8 * sizeof(double);
     if (need > rws_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
-      if (rws_) HIPCHK(hipFree(rws_));
+      if (rws_) HIPCHK(dfree(rws_));
       rws_ = nullptr;
       rws_bytes_ = 0;
-      if (hipMalloc(&rws_, need) != hipSuccess) {
+      if (dmalloc(&rws_, need) != hipSuccess) {
         err_ = -4;
         errmsg_ = "observable workspace allocation failed";
         return;
@@ -3169,6 +3205,10 @@ class HipBackend : public Backend {
   void *tptr_ = nullptr;             // blocked tridiagonalisation: GEMM pointer table
   size_t tptr_bytes_ = 0;
   void *skws_ = nullptr;
+  DevAlloc ua_ = nullptr;            // caller's allocator (null: hipMalloc / hipFree)
+  DevFree uf_ = nullptr;
+  void *uu_ = nullptr;
+  bool touched_ = false;             // device memory has been taken (the allocator is then fixed)
   size_t skws_bytes_ = 0;
   int prof_stride_ = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev_;
