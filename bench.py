@@ -131,9 +131,18 @@ def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict
                 break
     except OSError:
         pass
+    blas = "unknown BLAS"
+    try:
+        import threadpoolctl
+        info = [i for i in threadpoolctl.threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas = ", ".join(f"{i.get('internal_api')} {i.get('version')} "
+                             f"({i.get('num_threads')} threads)" for i in info)
+    except Exception:
+        pass
     return {
         "value": 1.0 / t_step, "unit": "Floquet steps/s", "cores": _cores(), "kind": "oracle",
-        "cpu": model,
+        "cpu": model, "blas": blas,
         "sample": (f"FP64 numpy oracle on a seeded random chi={chi} state of the 127-qubit "
                    f"lattice: the X rotations and all three gate layers ({lat.n_edges} gates, "
                    f"{t_gates:.1f} s), {n_sample_sweeps} BP sweeps ({t_sweep:.1f} s each), <Z> on "
