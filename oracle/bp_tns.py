@@ -44,7 +44,8 @@ Readings where the paper is silent (all mirrored by the HIP path):
   max over directed edges of the Frobenius norm of the change, stop when < tol;
   extended time evolution (U(pi/2)^dagger steps): gates exp(-i pi/4 ZZ) in descending
   colour, then X rotations by -pi/2;
-  truncation: keep min(chi, #{sigma_i > eps_svd * sigma_1}) singular values;
+  truncation: keep min(chi, #{sigma_i^2 > eps_svd * sigma_1^2}) singular values (the cutoff
+  acts on the Schmidt weights sigma^2, which is what an FP64 Gram-matrix eigensolver resolves);
   message square roots: eigenvalues clipped at 0; inverse square roots keep eigenvalues
   > eps_eig * lambda_max; gate layers: ascending colour of a proper edge colouring;
   entropy: s = -sum_i p_i log2 p_i with the minus sign the printed formula lacks, over the
@@ -145,6 +146,10 @@ class Options:
     svd_cutoff: float = 1e-12
     eig_cutoff: float = 1e-12
     zz_sign: float = 1.0            # +1: exp(+i pi/4 ZZ) as printed in Eq. "Propagator"
+    # BP to convergence before every gate (the costly "most accurate" schedule the Methods
+    # mention; the default regauges once per Floquet step).  Tests only: on a tree it makes
+    # every truncation the optimal one of the current state across that edge.
+    regauge_every_gate: bool = False
 
 
 class Network:
@@ -242,10 +247,19 @@ class Network:
         U, sig, Vh = np.linalg.svd(mat, full_matrices=False)
         if sig.size == 0 or sig[0] <= 0.0:
             raise FloatingPointError("simple update: zero two-site block")
-        k = int(min(opt.chi, np.count_nonzero(sig > opt.svd_cutoff * sig[0])))
-        total = float(np.sum(sig ** 2))
-        discarded = float(np.sum(sig[k:] ** 2)) / total
+        # truncation to at most chi: the Schmidt weights are p_i = sigma_i^2; weights below
+        # svd_cutoff * p_1 are dropped as numerically zero
+        p = sig ** 2
+        above = int(np.count_nonzero(p > opt.svd_cutoff * p[0]))
+        k = min(opt.chi, above)
+        discarded = float(np.sum(p[k:])) / float(np.sum(p))
         S = sig[:k] / np.linalg.norm(sig[:k])
+        # diagnostics of the cut: when chi (not the cutoff) sets k, the gap between the last
+        # kept and the first dropped singular value relative to sigma_1 (a near-zero gap makes
+        # the kept subspace ill-determined)
+        self.last_kept = k
+        self.last_cut_gap = float((sig[k - 1] - sig[k]) / sig[0]) if above > k else math.inf
+        self.last_S = S
         sq = np.sqrt(S)
         Rv_new = (U[:, :k] * sq[None, :]).reshape(rv, 2, k)
         Rw_new = (sq[:, None] * Vh[:k, :]).reshape(k, rw, 2).transpose(1, 2, 0)
@@ -446,8 +460,8 @@ class Network:
         leg u->v of T_u absorbs P_u = X^{T+} U W and leg v->u of T_v absorbs
         P_v = Y^{T+} conj(V) W with W = (S / sum S)^{1/2}, the root of the new unit-trace message:
         a state already in this gauge then gets P = 1 (the transform is idempotent and keeps the
-        tensors' scale).  S is normalised to unit 2-norm and singular values <= cutoff * s_1 are
-        dropped.  The new messages are the BP fixed point diag(S) / sum S.  Returns
+        tensors' scale).  S is normalised to unit 2-norm and singular values whose Schmidt weight
+        s_i^2 is <= cutoff * s_1^2 are dropped.  The new messages are the BP fixed point diag(S) / sum S.  Returns
         {(u, v): S} in edge order.
         """
         lam, P = {}, {}
@@ -455,7 +469,7 @@ class Network:
             X, Xp = msg_sqrt(self.M[(u, v)], cutoff)
             Y, Yp = msg_sqrt(self.M[(v, u)], cutoff)
             U, sv, Vh = np.linalg.svd(X.T @ Y)
-            keep = sv > cutoff * sv[0]
+            keep = sv ** 2 > cutoff * sv[0] ** 2          # Schmidt weights, as in the truncation
             U, sv, Vh = U[:, keep], sv[keep], Vh[keep, :]
             sv = sv / np.linalg.norm(sv)
             lam[(u, v)] = sv
@@ -516,6 +530,11 @@ class Network:
         return float(-np.sum(p * np.log2(p)))
 
 
+# A chi-limited cut whose gap (sigma_chi - sigma_{chi+1}) / sigma_1 is below this is counted as
+# near-degenerate: rounding can then move the kept subspace.
+DEGENERATE_GAP = 1e-10
+
+
 @dataclass
 class Result:
     z: np.ndarray                       # [depth, n_sites] (or [1, n_sites])
@@ -525,6 +544,9 @@ class Result:
     discarded: list = field(default_factory=list)
     converged: bool = True
     entropy: np.ndarray | None = None   # [rows, n_edges] bond entropies (bits) when asked for
+    bond_dims: np.ndarray | None = None  # [rows, n_edges] bond dimension of every edge
+    min_cut_gap: list = field(default_factory=list)      # per step, min over chi-limited cuts
+    degenerate_cuts: list = field(default_factory=list)  # per step, cuts with gap < DEGENERATE_GAP
 
 
 def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
@@ -548,34 +570,48 @@ def solve(n_sites: int, edges, colour, theta: float, depth: int, opt: Options,
     inv = Options(chi=opt.chi, bp_tol=opt.bp_tol, bp_max_iter=opt.bp_max_iter,
                   svd_cutoff=opt.svd_cutoff, eig_cutoff=opt.eig_cutoff, zz_sign=-opt.zz_sign)
     steps = depth + clifford_steps
-    zs, iters, resid, disc, ents = [], [], [], [], []
+    zs, iters, resid, disc, ents, dims, gaps, degen = [], [], [], [], [], [], [], []
     converged = True
     for _t in range(steps):
-        dsum = 0.0
+        dsum, gmin, ndeg = 0.0, math.inf, 0
+
+        def gate(u, v, o):
+            nonlocal dsum, gmin, ndeg
+            if opt.regauge_every_gate:
+                net.bp(opt.bp_tol, opt.bp_max_iter)
+            dsum += net.simple_update(u, v, o)
+            gmin = min(gmin, net.last_cut_gap)
+            ndeg += net.last_cut_gap < DEGENERATE_GAP
+
         if _t < depth:
             net.apply_rx(theta)
             for c in colours:
                 for e, (u, v) in enumerate(net.edges):
                     if int(net.colour[e]) == c:
-                        dsum += net.simple_update(u, v, opt)
+                        gate(u, v, opt)
         else:
             for c in reversed(colours):
                 for e, (u, v) in enumerate(net.edges):
                     if int(net.colour[e]) == c:
-                        dsum += net.simple_update(u, v, inv)
+                        gate(u, v, inv)
             net.apply_rx(-math.pi / 2)
         it, res = net.bp(opt.bp_tol, opt.bp_max_iter)
         converged &= res < opt.bp_tol
         iters.append(it)
         resid.append(res)
         disc.append(dsum)
+        gaps.append(gmin)
+        degen.append(ndeg)
         if record_every_step or _t == steps - 1:
             zs.append([net.expect_site(v, 3) for v in range(net.n)])
+            dims.append([net.bond_dim(u, v) for u, v in net.edges])
             if entropy:
                 ents.append([net.bond_entropy(u, v) for u, v in net.edges])
     if steps == 0:
         zs.append([1.0] * net.n)
+        dims.append([1] * len(net.edges))
         ents.append([0.0] * len(net.edges))
     pv = np.array([net.expect_pauli(s, o) for s, o in pauli], dtype=float)
     return Result(np.array(zs, dtype=float), pv, iters, resid, disc, converged,
-                  np.array(ents, dtype=float) if entropy else None)
+                  np.array(ents, dtype=float) if entropy else None,
+                  np.array(dims, dtype=np.int64), gaps, degen)

@@ -69,12 +69,19 @@ def test_bp_exact_on_trees(seed, n):
 @pytest.mark.parametrize("theta", [math.pi / 8, math.pi / 4, 3 * math.pi / 8])
 def test_hexagon_ring_exact_before_light_cone_wraps(theta):
     """One heavy hexagon (12-ring): exact while the light cone has not gone round the
-    loop (paper: perfect agreement with the state vector for the first steps)."""
+    loop (paper: perfect agreement with the state vector for the first steps).  The only
+    departure is the svd_cutoff, which drops Schmidt weights below 1e-12 of the largest: a
+    truncation with discarded weight eps moves a one-site <Z> by at most 2 eps at that gate (the
+    operator acts on one side of the cut, so the kept and dropped parts do not interfere), and
+    the test allows twice the discarded weight accumulated up to each step."""
     r = L.hexagon_ring()
     res = _solve(r, theta, 6, 64)
     ref = SV.run(r.n_sites, r.edges, theta, 6)
-    assert np.abs(res.z - ref).max() < 1e-11
-    assert res.bp_iters == [1] * 6          # messages set by the gates are already fixed
+    allow = 1e-13 + 2.0 * np.cumsum(res.discarded)
+    assert np.all(np.abs(res.z - ref).max(axis=1) < allow)
+    # where no gate discarded anything, the messages set by the gates are already the fixed point
+    for it, d in zip(res.bp_iters, res.discarded):
+        assert d > 1e-20 or it == 1
 
 
 def test_hexagon_ring_chi4_config():
@@ -334,9 +341,11 @@ def test_bond_spectrum_exact_on_trees(seed):
             assert abs(r.entropy[t, e] - float(-np.sum(p * np.log2(p)))) < 1e-10, (t, e)
     wants = [_schmidt_weights(sv.psi, tr.n_sites, _side(tr.n_sites, tr.edges, e))
              for e in range(tr.n_edges)]
+    # weights below svd_cutoff (1e-12) times the largest are dropped by the truncation rule, and
+    # the rest renormalised: the spectra agree to twice the cutoff
     for e, (u, v) in enumerate(tr.edges.tolist()):
-        assert _pad_cmp(net.bond_spectrum(u, v), wants[e]) < 1e-12
-        assert _pad_cmp(net.bond_spectrum(v, u), wants[e]) < 1e-12
+        assert _pad_cmp(net.bond_spectrum(u, v), wants[e]) < 2e-12
+        assert _pad_cmp(net.bond_spectrum(v, u), wants[e]) < 2e-12
     # the spectrum is gauge invariant: insert G G^-1 (random, complex) on every bond, let BP
     # find the new messages (complex Hermitian now, no longer diagonal) and compare again
     for u, v in tr.edges.tolist():
