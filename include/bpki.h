@@ -78,7 +78,9 @@ typedef struct {
   int32_t precision;           /* bpki_precision                                               */
   double bp_tol;               /* BP stops when max ||M'-M||_F < bp_tol   (e.g. 1e-12)         */
   int32_t bp_max_iter;         /* e.g. 1000                                                     */
-  double svd_cutoff;           /* keep sigma_i > svd_cutoff * sigma_1     (e.g. 1e-12)         */
+  double svd_cutoff;           /* truncation keeps min(chi, #{sigma_i^2 > svd_cutoff*sigma_1^2})
+                                  singular values: the cutoff acts on the Schmidt weights
+                                  (e.g. 1e-12), which FP64 eigenvalues of Theta^H Theta resolve  */
   double eig_cutoff;           /* inverse square roots keep lambda > eig_cutoff * lambda_max    */
   int32_t n_pauli;             /* Pauli strings measured after the final step                  */
   const int32_t *pauli_offsets;/* [n_pauli+1] CSR offsets into pauli_sites / pauli_ops         */
@@ -109,6 +111,14 @@ typedef struct {
                            M_{u->v}^{1/2} normalised to unit sum (the BP norm across the edge is
                            Tr(M_{u->v} M_{v->u}^T)); exact on trees without truncation.  FP64
                            in every precision mode.  S = 0 gives one row of zeros.           */
+  /* Truncation diagnostics ("The simple update procedure": each gate keeps at most chi values). */
+  int32_t *bond_dims;   /* optional [max(1, record_every_step ? S : 1) * n_edges]: the bond
+                           dimension of every edge on the steps z is recorded (ones for S = 0) */
+  double *min_cut_gap;  /* optional [S]: smallest (sigma_chi - sigma_{chi+1}) / sigma_1 over the
+                           step's gates whose bond chi (not svd_cutoff) limited; +inf if none */
+  int32_t *degenerate_cuts; /* optional [S]: number of the step's gates with such a gap below
+                           1e-10 (near-degenerate cuts: rounding can move the kept subspace,
+                           so runs that differ only in rounding may part there)               */
 } bpki_result;
 
 /* Fill *p with the defaults (tolerances 1e-12, 1000 sweeps, FP64, record every step). */
@@ -157,11 +167,12 @@ int bpki_solve(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
 
 /* ---- Serving: continuous batching -----------------------------------------------------------
  * bpki_submit queues a problem (deep copy) and returns at once with a ticket.  The context runs a
- * fixed number of serving slots, each a worker thread with its own HIP stream; a free slot takes
- * the oldest queued problem whose bpki_estimate_bytes fits the memory budget next to the resident
- * ones (arrival order; a problem larger than the budget's free part waits until memory frees up),
- * so problems that arrive while others run start as slots and memory free up, and the kernels of
- * all resident problems run concurrently on the device.  Results go into caller-owned buffers,
+ * fixed number of serving slots, each a worker thread with its own HIP stream.  Admission is in
+ * strict arrival order: a free slot takes the problem at the head of the queue once its
+ * bpki_estimate_bytes fits the memory budget next to the resident ones (a head that does not fit
+ * waits, and the problems behind it with it, until memory frees up; a problem alone on the device
+ * is always admitted), so problems that arrive while others run start as slots and memory free
+ * up, and the kernels of all resident problems run concurrently on the device.  Results go into caller-owned buffers,
  * which must stay valid until bpki_wait returns or bpki_poll reports done.  A problem that can
  * never fit the budget is rejected with -4 by bpki_submit.
  *
@@ -218,6 +229,10 @@ int bpki_session_set_state(bpki_session *s, const double *tensors, const double 
 /* Phases of one Floquet step (paper: "State ansatz" and Methods). */
 int bpki_session_apply_rx(bpki_session *s);
 int bpki_session_apply_layer(bpki_session *s, int32_t colour, double *discarded);
+/* Per edge [n_edges] (host; each may be NULL), for the edges the last apply_layer (or step)
+ * updated: kept bond dimension, discarded weight and cut gap (as bpki_result.min_cut_gap, +inf
+ * when svd_cutoff set the bond); -1 / NaN for the other edges. */
+int bpki_session_layer_cuts(bpki_session *s, int32_t *kept, double *discarded, double *gap);
 int bpki_session_bp(bpki_session *s, int32_t max_iter, int32_t *iters, double *residual);
 int bpki_session_bp_sweep(bpki_session *s, double *residual);
 int bpki_session_observe_z(bpki_session *s, double *z);
@@ -234,7 +249,7 @@ int bpki_session_observe_bond_entropy(bpki_session *s, double *entropy);
  * scale) then forms, with S on its other legs, the isometries of Eqs.
  * "IsometryPropertyDefinition" and "IsometryDefinition", and diag(S)/sum(S) on both directions
  * (written as the new messages) is a BP fixed point.  S is normalised to unit 2-norm; singular
- * values <= svd_cutoff * s_1 are dropped (bond dimensions shrink accordingly).  Computed from the
+ * values with s_i^2 <= svd_cutoff * s_1^2 are dropped (bond dimensions shrink accordingly).  Computed from the
  * eigenpairs of C^H C in FP64 in every mode.  lambda: [n_edges][chi] host, S descending and
  * zero-padded, or NULL.  Equivalent to the message form in exact arithmetic (a conditioning
  * safeguard and the paper's stated representation). */

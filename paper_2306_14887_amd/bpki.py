@@ -42,6 +42,8 @@ class _Result(C.Structure):
         ("z", C.POINTER(C.c_double)), ("pauli", C.POINTER(C.c_double)),
         ("bp_iters", C.POINTER(C.c_int32)), ("bp_residual", C.POINTER(C.c_double)),
         ("discarded", C.POINTER(C.c_double)), ("bond_entropy", C.POINTER(C.c_double)),
+        ("bond_dims", C.POINTER(C.c_int32)), ("min_cut_gap", C.POINTER(C.c_double)),
+        ("degenerate_cuts", C.POINTER(C.c_int32)),
     ]
 
 
@@ -99,6 +101,7 @@ def load(path: str | None = None):
         "bpki_session_set_state": (C.c_int, [vp, dp, dp, ip]),
         "bpki_session_apply_rx": (C.c_int, [vp]),
         "bpki_session_apply_layer": (C.c_int, [vp, C.c_int32, dp]),
+        "bpki_session_layer_cuts": (C.c_int, [vp, ip, dp, dp]),
         "bpki_session_bp": (C.c_int, [vp, C.c_int32, ip, dp]),
         "bpki_session_bp_sweep": (C.c_int, [vp, dp]),
         "bpki_session_observe_z": (C.c_int, [vp, dp]),
@@ -134,7 +137,8 @@ def exported_symbols() -> list[str]:
             "bpki_ticket_times", "bpki_ticket_pack_size", "bpki_set_allocator",
             "bpki_session_open", "bpki_session_close",
             "bpki_session_sizes", "bpki_session_get_state", "bpki_session_set_state",
-            "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_bp",
+            "bpki_session_apply_rx", "bpki_session_apply_layer", "bpki_session_layer_cuts",
+            "bpki_session_bp",
             "bpki_session_bp_sweep", "bpki_session_observe_z",
             "bpki_session_observe_bond_entropy", "bpki_session_vidal_gauge",
             "bpki_session_bp_error",
@@ -362,6 +366,10 @@ def _alloc_result(spec: ProblemSpec) -> dict:
         "discarded": np.zeros(max(steps, 1)),
         "bond_entropy": (np.full((max(rows, 1), int(np.asarray(spec.edges).size // 2)), np.nan)
                          if spec.bond_entropy else None),
+        "bond_dims": np.zeros((max(rows, 1), int(np.asarray(spec.edges).size // 2)),
+                              dtype=np.int32),
+        "min_cut_gap": np.zeros(max(steps, 1)),
+        "degenerate_cuts": np.zeros(max(steps, 1), dtype=np.int32),
     }
 
 
@@ -374,6 +382,9 @@ def _result_struct(out: dict) -> _Result:
     r.discarded = _ptr(out["discarded"], C.c_double)
     if out.get("bond_entropy") is not None:
         r.bond_entropy = _ptr(out["bond_entropy"], C.c_double)
+    r.bond_dims = _ptr(out["bond_dims"], C.c_int32)
+    r.min_cut_gap = _ptr(out["min_cut_gap"], C.c_double)
+    r.degenerate_cuts = _ptr(out["degenerate_cuts"], C.c_int32)
     return r
 
 
@@ -459,6 +470,16 @@ class Session:
         d = C.c_double()
         _check(self.lib, self.lib.bpki_session_apply_layer(self.h, colour, C.byref(d)))
         return d.value
+
+    def layer_cuts(self):
+        """Per edge, for the edges the last layer updated: (kept bond dimension, discarded
+        weight, cut gap); -1 / NaN elsewhere."""
+        ne = int(np.asarray(self.spec.edges).size // 2)
+        k, d, g = np.zeros(ne, dtype=np.int32), np.zeros(ne), np.zeros(ne)
+        _check(self.lib, self.lib.bpki_session_layer_cuts(self.h, _ptr(k, C.c_int32),
+                                                          _ptr(d, C.c_double),
+                                                          _ptr(g, C.c_double)))
+        return k, d, g
 
     def bp(self, max_iter: int = 1000):
         it, r = C.c_int32(), C.c_double()

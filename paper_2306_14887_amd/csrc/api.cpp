@@ -22,6 +22,10 @@ using namespace bpki;
 
 static thread_local std::string g_err;
 
+// A chi-limited cut whose gap (sigma_chi - sigma_{chi+1}) / sigma_1 is below this is reported as
+// near-degenerate: there the kept subspace moves with rounding.
+static constexpr double kDegenerateGap = 1e-10;
+
 static int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
@@ -278,6 +282,20 @@ static std::vector<int> sorted_colours(const Problem &q) {
   return cs;
 }
 
+// Cut diagnostics of one step: the smallest gap of a chi-limited cut and the number of cuts whose
+// gap is below kDegenerateGap, accumulated over the step's layers for the edges [e0, e1).
+struct StepCuts {
+  double gap = INFINITY;
+  int degenerate = 0;
+  void add(const std::vector<Engine::Cut> &cuts, int e0 = 0, int e1 = 1 << 30) {
+    for (const auto &c : cuts) {
+      if (c.e < e0 || c.e >= e1) continue;
+      gap = std::min(gap, c.gap);
+      degenerate += c.gap < kDegenerateGap;
+    }
+  }
+};
+
 static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
                      std::atomic<bool> *cancel) {
   const int n = q.n_sites;
@@ -286,28 +304,39 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
   std::vector<double> z((size_t)rows * n, 1.0);
   const int ne = (int)q.edges.size() / 2;
   std::vector<double> ent(r->bond_entropy ? (size_t)rows * ne : 0, 0.0);
-  std::vector<int32_t> iters(steps, 0);
-  std::vector<double> res(steps, 0.0), disc(steps, 0.0);
+  std::vector<int32_t> iters(steps, 0), ndeg(steps, 0), bdim((size_t)rows * ne, 1);
+  std::vector<double> res(steps, 0.0), disc(steps, 0.0), gap(steps, INFINITY);
   const std::vector<int> cols = sorted_colours(q);
   int warn = 0;
   for (int t = 0; t < steps; ++t) {
     if (cancel && cancel->load()) return fail(-6, "cancelled");
     double d = 0;
+    StepCuts sc;
     if (t < q.depth) {
       eng.apply_rx();
-      for (int c : cols) d += eng.apply_layer(c);
+      for (int c : cols) {
+        d += eng.apply_layer(c);
+        sc.add(eng.layer_cuts());
+      }
     } else {
-      d = clifford_inverse_step(eng, cols);
+      for (auto it = cols.rbegin(); it != cols.rend(); ++it) {
+        d += eng.apply_layer(*it, -1);
+        sc.add(eng.layer_cuts());
+      }
+      eng.apply_rx_angle(-M_PI / 2);
     }
     double rr = 0;
     iters[t] = eng.bp(q.bp_max_iter, &rr);
     res[t] = rr;
     disc[t] = d;
+    gap[t] = sc.gap;
+    ndeg[t] = sc.degenerate;
     if (!(rr < q.bp_tol)) warn = 1;
     if (q.record_every_step || t == steps - 1) {
       int row = q.record_every_step ? t : 0;
       eng.observe_z(&z[(size_t)row * n]);
       if (!ent.empty()) eng.observe_entropy(&ent[(size_t)row * ne]);
+      std::copy(eng.bond_dims().begin(), eng.bond_dims().end(), bdim.begin() + (size_t)row * ne);
     }
     std::string msg;
     int e = be->check(&msg);
@@ -328,6 +357,10 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
   if (r->bp_iters) std::memcpy(r->bp_iters, iters.data(), iters.size() * sizeof(int32_t));
   if (r->bp_residual) std::memcpy(r->bp_residual, res.data(), res.size() * sizeof(double));
   if (r->discarded) std::memcpy(r->discarded, disc.data(), disc.size() * sizeof(double));
+  if (r->bond_dims) std::memcpy(r->bond_dims, bdim.data(), bdim.size() * sizeof(int32_t));
+  if (r->min_cut_gap) std::memcpy(r->min_cut_gap, gap.data(), gap.size() * sizeof(double));
+  if (r->degenerate_cuts)
+    std::memcpy(r->degenerate_cuts, ndeg.data(), ndeg.size() * sizeof(int32_t));
   return warn;
 }
 
@@ -430,6 +463,23 @@ extern "C" int bpki_session_apply_layer(bpki_session *s, int32_t colour, double 
   double d = s->eng->apply_layer(colour);
   if (disc) *disc = d;
   return sess_check(s);
+}
+
+extern "C" int bpki_session_layer_cuts(bpki_session *s, int32_t *kept, double *discarded,
+                                       double *gap) {
+  if (!s) return fail(-1, "NULL session");
+  const int ne = (int)s->eng->problem().edges.size() / 2;
+  for (int e = 0; e < ne; ++e) {
+    if (kept) kept[e] = -1;
+    if (discarded) discarded[e] = NAN;
+    if (gap) gap[e] = NAN;
+  }
+  for (const auto &c : s->eng->layer_cuts()) {
+    if (kept) kept[c.e] = c.kept;
+    if (discarded) discarded[c.e] = c.discarded;
+    if (gap) gap[c.e] = c.gap;
+  }
+  return 0;
 }
 
 extern "C" int bpki_session_bp(bpki_session *s, int32_t max_iter, int32_t *iters, double *res) {
@@ -666,8 +716,8 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
                      const std::vector<int> &pauli0) {
   const int R = (int)jobs.size();
   struct Acc {
-    std::vector<double> z, ent, res, disc;
-    std::vector<int32_t> iters;
+    std::vector<double> z, ent, res, disc, gap;
+    std::vector<int32_t> iters, ndeg, bdim;
     int warn = 0;
     bool fin = false;
   };
@@ -685,7 +735,10 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
     acc[j].iters.assign(q.depth, 0);
     acc[j].res.assign(q.depth, 0.0);
     acc[j].disc.assign(q.depth, 0.0);
+    acc[j].gap.assign(q.depth, INFINITY);
+    acc[j].ndeg.assign(q.depth, 0);
     const int ne = (int)q.edges.size() / 2;
+    acc[j].bdim.assign((size_t)rows * ne, 1);
     for (int e = 0; e < ne; ++e) edge_member[e0 + e] = j;
     e0 += ne;
     edge0[j + 1] = e0;
@@ -709,9 +762,14 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
     if (!open) return;
     eng.apply_rx();
     std::fill(dj.begin(), dj.end(), 0.0);
+    std::vector<StepCuts> scj(R);
     for (int col : cols) {
       eng.apply_layer(col);
-      for (auto &ed : eng.layer_discarded()) dj[edge_member[ed.first]] += ed.second;
+      for (auto &cut : eng.layer_cuts()) {
+        const int j = edge_member[cut.e];
+        dj[j] += cut.discarded;
+        scj[j].add({cut});
+      }
     }
     eng.bp_members(U.bp_max_iter, sweeps.data(), rr.data());
     bool need_z = false, need_e = false;
@@ -737,17 +795,20 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
       a.iters[t] = sweeps[j];
       a.res[t] = rr[j];
       a.disc[t] = dj[j];
+      a.gap[t] = scj[j].gap;
+      a.ndeg[t] = scj[j].degenerate;
       if (!(rr[j] < q.bp_tol)) a.warn = 1;
       const int s0 = U.member_site0[j];
       if (q.record_every_step || t == q.depth - 1) {
         const int row = q.record_every_step ? t : 0;
         std::copy(zall.begin() + s0, zall.begin() + s0 + q.n_sites,
                   a.z.begin() + (size_t)row * q.n_sites);
-        if (!a.ent.empty()) {
-          const int ne = edge0[j + 1] - edge0[j];
+        const int ne = edge0[j + 1] - edge0[j];
+        if (!a.ent.empty())
           std::copy(eall.begin() + edge0[j], eall.begin() + edge0[j + 1],
                     a.ent.begin() + (size_t)row * ne);
-        }
+        std::copy(eng.bond_dims().begin() + edge0[j], eng.bond_dims().begin() + edge0[j + 1],
+                  a.bdim.begin() + (size_t)row * ne);
       }
       if (t < q.depth - 1) continue;
       std::vector<double> pv(pauli0[j + 1] - pauli0[j], 0.0);
@@ -770,6 +831,10 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
       if (r->bp_iters) std::memcpy(r->bp_iters, a.iters.data(), a.iters.size() * sizeof(int32_t));
       if (r->bp_residual) std::memcpy(r->bp_residual, a.res.data(), a.res.size() * sizeof(double));
       if (r->discarded) std::memcpy(r->discarded, a.disc.data(), a.disc.size() * sizeof(double));
+      if (r->bond_dims) std::memcpy(r->bond_dims, a.bdim.data(), a.bdim.size() * sizeof(int32_t));
+      if (r->min_cut_gap) std::memcpy(r->min_cut_gap, a.gap.data(), a.gap.size() * sizeof(double));
+      if (r->degenerate_cuts)
+        std::memcpy(r->degenerate_cuts, a.ndeg.data(), a.ndeg.size() * sizeof(int32_t));
       fin(j, a.warn);
     }
   }
@@ -780,6 +845,19 @@ static void run_pack(bpki_ctx *c, Backend *be, Engine &eng, const Problem &U,
 static void slot_loop(bpki_ctx *c, int slot) {
   Backend *be = c->slot_be[slot].get();
   for (;;) {
+    // A backend's error state is sticky (a failed allocation leaves null buffers behind, a
+    // device error poisons its stream): after the job that hit it has been failed with its
+    // code, the slot takes a fresh backend before it takes another job.
+    if (be->check(nullptr)) {
+      std::string err;
+      Backend *fresh = make_hip_backend(c->device, nullptr, &err);
+      if (fresh) {
+        fresh->set_allocator(c->ualloc, c->ufree, c->uuser);
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->slot_be[slot].reset(fresh);
+        be = fresh;
+      }
+    }
     std::shared_ptr<bpki_ctx::Job> job;
     std::vector<std::shared_ptr<bpki_ctx::Job>> pack;
     size_t pack_bytes = 0;

@@ -106,8 +106,10 @@ struct Backend {
   virtual void theta(int rB, int rS, int chi, const double *const *RB, const double *const *RS,
                      double *const *Th, double g_same_re, double g_same_im, double g_diff_re,
                      double g_diff_im, int nprob) = 0;
-  // Truncation from eigh(Theta^H Theta): k, S, discarded weight, new diagonal messages and the
-  // scaled right vectors Vs[c][a] = V[c][a]/sigma_a (a < k).
+  // Truncation from eigh(Theta^H Theta): k = min(chi, #{lambda_i > cutoff * lambda_1}), S,
+  // new diagonal messages and the scaled right vectors Vs[c][a] = V[c][a]/sigma_a (a < k);
+  // disc[2p] = discarded weight, disc[2p+1] = (sigma_k - sigma_{k+1}) / sigma_1 when chi (not the
+  // cutoff) set k, else +inf.
   virtual void svd_finish(int n, int chi, const double *const *evals, const double *const *vecs,
                           double *const *Vs, double *const *S, int *kout, double *disc,
                           double *const *msg_a, double *const *msg_b, double cutoff,
@@ -191,8 +193,15 @@ class Engine {
   // follows its own BP schedule; per member: sweeps and final residual.
   void bp_members(int max_iter, int *sweeps, double *residual);
   int n_members() const;
-  // (edge, discarded weight) for every edge of the last apply_layer
-  const std::vector<std::pair<int, double>> &layer_discarded() const { return layer_disc_; }
+  // Every edge of the last apply_layer: its kept bond dimension, discarded weight and cut gap
+  // (sigma_k - sigma_{k+1}) / sigma_1 when chi limited the bond (+inf when the cutoff did).
+  struct Cut {
+    int e = -1, kept = 0;
+    double discarded = 0, gap = 0;
+  };
+  const std::vector<Cut> &layer_cuts() const { return layer_cuts_; }
+  // Current bond dimension of every edge (host copy).
+  const std::vector<int> &bond_dims() const;
   int n_colours() const;
   const Problem &problem() const { return prob_; }
 
@@ -206,7 +215,7 @@ class Engine {
   Problem prob_;
   Plan *plan_;
   int bp_prec_ = 0;
-  std::vector<std::pair<int, double>> layer_disc_;
+  std::vector<Cut> layer_cuts_;
   void sweep_classes();
   // The gate updates stay FP64 in every mode: the Gram-based bond isolation amplifies rounding
   // by the condition number of the isolated tensor, which FP32 cannot absorb.

@@ -374,7 +374,7 @@ void Engine::build() {
   P.resmax = (double *)A(8);
   P.rho = (double *)A((size_t)P.n * 8 * 8);
   P.kbuf = (int *)A((size_t)std::max(1, P.max_layer_edges) * 4);
-  P.disc = (double *)A((size_t)std::max(1, P.max_layer_edges) * 8);
+  P.disc = (double *)A((size_t)std::max(1, P.max_layer_edges) * 16);   // (discarded, gap) pairs
   P.bond_h.assign(P.E, 1);
 
   auto Tp = [&](int v) { return (const void *)(P.T + 2 * P.toff[v]); };
@@ -1124,7 +1124,7 @@ double Engine::apply_layer(int colour, int zz_sign) {
   for (auto &T : LP.types) {
     be_->svd_finish(T.n, chi, ar.at<const double *const *>(T.ev),
                     ar.at<const double *const *>(T.vec), ar.at<double *const *>(T.Vs),
-                    ar.at<double *const *>(T.S), P.kbuf + T.slot0, P.disc + T.slot0,
+                    ar.at<double *const *>(T.S), P.kbuf + T.slot0, P.disc + 2 * T.slot0,
                     ar.at<double *const *>(T.mA), ar.at<double *const *>(T.mB), prob_.svd_cutoff,
                     T.count);
     run(be_, ar, T.ugemm, 0);
@@ -1137,18 +1137,18 @@ double Engine::apply_layer(int colour, int zz_sign) {
   // degree <= 2: T~' = R' (already in A-layout); point remove ops at R' directly
   for (auto &op : LP.remove) run(be_, ar, op, su_prec());
   for (auto &t : LP.d2d_out) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
-  // bookkeeping: discarded weight and bond dimensions
+  // bookkeeping: discarded weight, cut gap and bond dimension of every edge of the layer
   int ne = (int)LP.edges.size();
-  std::vector<double> disc(ne);
+  std::vector<double> disc(2 * (size_t)ne);
   std::vector<int> k(ne);
-  be_->d2h(disc.data(), P.disc, ne * 8);
+  be_->d2h(disc.data(), P.disc, (size_t)ne * 16);
   be_->d2h(k.data(), P.kbuf, ne * 4);
   double dsum = 0;
-  layer_disc_.resize(ne);
+  layer_cuts_.resize(ne);
   for (int i = 0; i < ne; ++i) {
-    dsum += disc[i];
+    dsum += disc[2 * i];
     P.bond_h[LP.edges[i].e] = k[i];
-    layer_disc_[i] = {LP.edges[i].e, disc[i]};
+    layer_cuts_[i] = {LP.edges[i].e, k[i], disc[2 * i], disc[2 * i + 1]};
   }
   return dsum;
 }
@@ -1620,6 +1620,8 @@ double Engine::pauli_value(int k, bool with_ops) {
   for (void *q : tmp) be_->release(q);
   return result;
 }
+
+const std::vector<int> &Engine::bond_dims() const { return plan_->bond_h; }
 
 void Engine::get_state(double *tensors, double *messages, int32_t *bond_dims) {
   Plan &P = *plan_;

@@ -2072,10 +2072,14 @@ __global__ void svd_finish_kernel(int n, int chi, const double *const *evals,
   for (int i = threadIdx.x; i < n; i += blockDim.x) sig[i] = sqrt(fmax(l[i], 0.0));
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s0 = sig[0];
-    int k = 0;
-    for (int i = 0; i < n && k < chi; ++i)
-      if (sig[i] > cutoff * s0) ++k;
+    // Keep min(chi, #{lambda_i > cutoff * lambda_1}): the cutoff acts on the Schmidt weights
+    // lambda = sigma^2, which the FP64 eigenvalues of Theta^H Theta resolve to ~eps * lambda_1
+    // (sigma itself only to ~sqrt(eps) * sigma_1).
+    const double l0 = fmax(l[0], 0.0);
+    int above = 0;
+    for (int i = 0; i < n; ++i)
+      if (fmax(l[i], 0.0) > cutoff * l0) ++above;
+    const int k = above < chi ? above : chi;
     double tot = 0, kept = 0, sum = 0;
     for (int i = 0; i < n; ++i) tot += sig[i] * sig[i];
     for (int i = 0; i < k; ++i) kept += sig[i] * sig[i];
@@ -2085,7 +2089,10 @@ __global__ void svd_finish_kernel(int n, int chi, const double *const *evals,
     nrm = nr;
     ssum = sum;
     kout[p] = k;
-    disc[p] = tot > 0 ? (tot - kept) / tot : 0.0;
+    disc[2 * p] = tot > 0 ? (tot - kept) / tot : 0.0;
+    // gap of a chi-limited cut relative to sigma_1 (infinite when the cutoff set k)
+    disc[2 * p + 1] = (above > k && k > 0 && sig[0] > 0.0) ? (sig[k - 1] - sig[k]) / sig[0]
+                                                           : INFINITY;
   }
   __syncthreads();
   const int k = ks;
@@ -2261,7 +2268,7 @@ __global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *con
   double acc = 0.0, cnt = 0.0;
   for (int i = tid; i < n; i += 256) {
     const double li = sqrt(fmax(l[i], 0.0));
-    const bool keep = li > 0.0 && li > cut * l0;
+    const bool keep = li > 0.0 && li * li > cut * l0 * l0;    // cutoff on the Schmidt weights
     sv[i] = keep ? li : 0.0;
     acc += keep ? li * li : 0.0;
     cnt += keep ? 1.0 : 0.0;

@@ -167,3 +167,37 @@ def test_allocator_failures():
     ctx.close()
     assert not given
     assert torch.cuda.memory_allocated(0) == base
+
+
+def test_serving_slot_recovers_after_allocation_failure():
+    """A request whose memory the allocator refuses fails with -4, and the requests that the same
+    serving slot takes afterwards still succeed (the slot replaces its backend once a job has
+    left it in an error state) with the results of their solves alone."""
+    import torch
+    from paper_2306_14887_amd import bpki as B
+    print("[allocator] serving slot after a refused allocation", flush=True)
+    ta, tf = B.torch_allocator(0)
+    limit = 8 << 20
+
+    def alloc(n, s):
+        return None if n > limit else ta(n, s)
+
+    big = B.spec_from_lattice(L.eagle(), 0.5, 3, 32)
+    small = [_spec(seed=20 + i, theta=0.3 + 0.2 * i, depth=3, chi=8) for i in range(3)]
+    with B.Context() as ref_ctx:
+        alone = [ref_ctx.solve(s) for s in small]
+    torch.cuda.synchronize(0)
+    base = torch.cuda.memory_allocated(0)
+    ctx = B.Context()
+    ctx.set_allocator(alloc, tf)
+    ctx.serving_config(1)
+    t_big = ctx.submit(big)
+    with pytest.raises(B.BpkiError) as ex:
+        t_big.wait()
+    assert ex.value.code == -4
+    outs = [ctx.submit(s).wait() for s in small]
+    ctx.close()
+    for o, a in zip(outs, alone):
+        _same(o, a)
+    torch.cuda.synchronize(0)
+    assert torch.cuda.memory_allocated(0) == base
