@@ -38,6 +38,9 @@ typedef struct {
                         alpha_im == 0, beta == 0): the lower triangle is computed, the diagonal
                         stored real, the upper triangle written as its conjugate mirror
                         (exactly Hermitian output) */
+  int32_t store32;   /* operands held on the device as complex FP32 (prec = 1 only): bit 0 A,
+                        bit 1 B, bit 2 C; 5 (A, C) and 3 (A, B) are the supported sets.  Host
+                        buffers stay complex128 (converted on upload and download). */
 } bpki_test_gemm_desc;
 
 /* Runs the FP64 MFMA GEMM on nprob problems; problem p uses A + 2*a_elems*p etc.  C is read

@@ -54,7 +54,7 @@ class TestGemmDesc(C.Structure):
                                          "c_b")] + \
                [(n, C.c_int32) for n in ("batch", "conjA", "conjB", "beta")] + \
                [("alpha_re", C.c_double), ("alpha_im", C.c_double), ("prec", C.c_int32),
-                ("herm", C.c_int32)]
+                ("herm", C.c_int32), ("store32", C.c_int32)]
 
 
 _lib = None

@@ -1065,7 +1065,12 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
   d.alpha_re = td->alpha_re; d.alpha_im = td->alpha_im;
   d.prec = td->prec;
   d.herm = td->herm;
+  d.a32 = td->store32 & 1;
+  d.b32 = (td->store32 >> 1) & 1;
+  d.c32 = (td->store32 >> 2) & 1;
   if (d.prec != 0 && d.prec != 1) return fail(-1, "prec must be 0 (FP64) or 1 (FP32)");
+  if (td->store32 && (d.prec != 1 || (td->store32 != 5 && td->store32 != 3)))
+    return fail(-1, "store32 must be 0, 5 (A and C) or 3 (A and B), with prec = 1");
   if (d.herm && (d.M != d.N || d.Mi != d.M || d.Ni != d.N || d.alpha_im != 0 || d.beta))
     return fail(-1, "herm needs M == N, single-stride M and N, real alpha and beta = 0");
   if (d.M < 1 || d.N < 1 || d.K < 1 || d.Mi < 1 || d.Ni < 1 || d.Ki < 1 || d.batch < 1 ||
@@ -1089,24 +1094,43 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
   if ((size_t)amax >= a_elems || (size_t)bmax >= b_elems || (size_t)cmax >= c_elems)
     return fail(-1, "descriptor addresses outside the buffers");
   std::lock_guard<std::mutex> lk(c->mu);
-  double *dA = (double *)be->alloc(a_elems * 16 * nprob);
-  double *dB = (double *)be->alloc(b_elems * 16 * nprob);
-  double *dC = (double *)be->alloc(c_elems * 16 * nprob);
+  // device copy of an operand (complex FP64, or complex FP32 when flagged) and its base pointers
+  auto upload = [&](const double *h, size_t elems, bool f32, char **dev) -> bool {
+    const size_t esz = f32 ? 8 : 16;
+    *dev = (char *)be->alloc(elems * esz * nprob);
+    if (!*dev) return false;
+    if (f32) {
+      std::vector<float> t(2 * elems * nprob);
+      for (size_t i = 0; i < t.size(); ++i) t[i] = (float)h[i];
+      be->h2d(*dev, t.data(), t.size() * 4);
+    } else {
+      be->h2d(*dev, h, elems * 16 * nprob);
+    }
+    return true;
+  };
+  char *dA = nullptr, *dB = nullptr, *dC = nullptr;
   void **ptrs = (void **)be->alloc(3 * nprob * sizeof(void *));
-  if (!dA || !dB || !dC || !ptrs) return fail(-4, "allocation failed");
-  be->h2d(dA, A, a_elems * 16 * nprob);
-  be->h2d(dB, B, b_elems * 16 * nprob);
-  be->h2d(dC, C, c_elems * 16 * nprob);
+  if (!ptrs || !upload(A, a_elems, d.a32, &dA) || !upload(B, b_elems, d.b32, &dB) ||
+      !upload(C, c_elems, d.c32, &dC)) {
+    for (void *q : {(void *)dA, (void *)dB, (void *)dC, (void *)ptrs}) be->release(q);
+    return fail(-4, "allocation failed");
+  }
   std::vector<void *> h(3 * nprob);
   for (int p = 0; p < nprob; ++p) {
-    h[p] = dA + 2 * a_elems * p;
-    h[nprob + p] = dB + 2 * b_elems * p;
-    h[2 * nprob + p] = dC + 2 * c_elems * p;
+    h[p] = dA + a_elems * (d.a32 ? 8 : 16) * p;
+    h[nprob + p] = dB + b_elems * (d.b32 ? 8 : 16) * p;
+    h[2 * nprob + p] = dC + c_elems * (d.c32 ? 8 : 16) * p;
   }
   be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
   be->gemm(d, (const double *const *)ptrs, (const double *const *)(ptrs + nprob),
            (double *const *)(ptrs + 2 * nprob), nprob);
-  be->d2h(C, dC, c_elems * 16 * nprob);
+  if (d.c32) {
+    std::vector<float> t(2 * c_elems * nprob);
+    be->d2h(t.data(), dC, t.size() * 4);
+    for (size_t i = 0; i < t.size(); ++i) C[i] = t[i];
+  } else {
+    be->d2h(C, dC, c_elems * 16 * nprob);
+  }
   be->release(dA);
   be->release(dB);
   be->release(dC);

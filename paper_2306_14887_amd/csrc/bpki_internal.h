@@ -32,6 +32,10 @@ struct GemmDesc {
   // lower triangle is computed, the diagonal is stored real and the upper triangle is written
   // as the conjugate mirror
   int herm = 0;
+  // Storage of the operands (prec = 1 only): 1 = complex FP32 (float pairs) instead of FP64.
+  // Supported: A and C FP32 with B FP64 (a leg absorption into an FP32 buffer), and A and B FP32
+  // with C FP64 (a closing contraction into a message).
+  int a32 = 0, b32 = 0, c32 = 0;
 };
 
 // Simple composite-index helpers for descriptors.
@@ -118,6 +122,8 @@ struct Backend {
   virtual void split_sqrt(int rowsB, int rowsS, int n, int chi, const double *const *U,
                           const double *const *V, const double *const *S, double *const *RBn,
                           double *const *RSn, int nprob) = 0;
+  // dst[i] = (float)src[i] for n complex elements (the FP32 copy of the site tensors).
+  virtual void to_f32(const double *src, float *dst, size_t n) = 0;
   // BP: M_new <- M_new / tr(M_new); res[p] = ||M_new - M_old||_F.
   virtual void normalize_residual(int chi, double *const *Mnew, const double *const *Mold,
                                   double *res, int nprob) = 0;
@@ -215,6 +221,7 @@ class Engine {
   Problem prob_;
   Plan *plan_;
   int bp_prec_ = 0;
+  bool t32_stale_ = true;         // the FP32 copy of the site tensors needs refreshing
   std::vector<Cut> layer_cuts_;
   void sweep_classes();
   // The gate updates stay FP64 in every mode: the Gram-based bond isolation amplifies rounding

@@ -56,7 +56,15 @@ inline long ipow(long b, int e) { long r = 1; while (e-- > 0) r *= b; return r; 
 constexpr double kGramCut = 1e-15;
 
 // Residual below which FP32 message contractions stop making progress (their rounding level).
+// Within kFp32Near times that level, a sweep that reduces the residual by less than kFp32Stall
+// also ends the FP32 phase (it has reached the noise of the FP32 products).
 constexpr double kFp32BpFloor = 2e-6;
+constexpr double kFp32Near = 100.0;
+constexpr double kFp32Stall = 0.9;
+
+inline bool fp32_done(double r, double prev) {
+  return r < kFp32BpFloor || (r < kFp32Near * kFp32BpFloor && r > kFp32Stall * prev);
+}
 
 }  // namespace
 
@@ -151,6 +159,10 @@ struct Plan {
     int nmsg = 0, res_off = 0;
   };
   std::vector<BpClass> bp_classes;
+  // mixed precision: the same sweep on FP32 copies of the site tensors and FP32 intermediates
+  // (FP32 MFMA; messages, normalisation and residual stay FP64)
+  std::vector<BpClass> bp_classes32;
+  float *T32 = nullptr, *bpws32 = nullptr;
   // packed solves: member of every residual slot (CSR by member), member of every message,
   // active flags (ping-pong) and per-member residuals
   int nmem = 1;
@@ -269,7 +281,10 @@ static GemmDesc close_desc(int deg, int leg, const Layout &L, int chi) {
 
 // ------------------------------------------------------------------------------------------
 
-Engine::Engine(Backend *be, const Problem &p) : be_(be), prob_(p), plan_(new Plan) { build(); }
+Engine::Engine(Backend *be, const Problem &p)
+    : be_(be), prob_(p), plan_(new Plan), bp_prec_(p.precision ? 1 : 0) {
+  build();
+}
 
 Engine::~Engine() {
   for (void *a : plan_->allocs) be_->release(a);
@@ -300,6 +315,8 @@ size_t Engine::estimate_bytes(const Problem &p) {
   }
   size_t m = (size_t)2 * p.edges.size() / 2 * chi * chi;
   size_t elems = t + 2 * m + su + bp + (size_t)p.edges.size() * 64 * chi * chi;
+  // mixed precision: FP32 copies of the site tensors and of the BP intermediates
+  if (p.precision == 1) elems += (t + bp + 64 * (size_t)n) / 2;
   return elems * 16 + (8u << 20);
 }
 
@@ -827,16 +844,50 @@ void Engine::build() {
     P.bpws_elems = top;
     P.bpws = (double *)A(top * 16);
     auto B = [&](size_t o) { return (const void *)(P.bpws + 2 * o); };
+    const bool mixed = prob_.precision == 1;
+    if (mixed) {
+      P.T32 = (float *)A(tensor_elems() * 8);
+      P.bpws32 = (float *)A(top * 8);
+    }
+    // the FP32 copy of an address in the site tensors or the BP workspace (complex element i is
+    // at double offset 2 i there and float offset 2 i here); messages keep their FP64 address
+    auto to32 = [&](const void *q) -> const void * {
+      const double *x = (const double *)q;
+      if (x >= P.T && x < P.T + 2 * tensor_elems()) return (const void *)(P.T32 + (x - P.T));
+      if (x >= P.bpws && x < P.bpws + 2 * top) return (const void *)(P.bpws32 + (x - P.bpws));
+      return q;
+    };
+    auto map32 = [&](const std::vector<const void *> &v) {
+      std::vector<const void *> r;
+      for (const void *q : v) r.push_back(to32(q));
+      return r;
+    };
 
-    auto add_op = [&](std::vector<GemmOp> &ops, const GemmDesc &d,
-                      const std::vector<const void *> &a, const std::vector<const void *> &b,
-                      const std::vector<const void *> &c) {
+    auto add_op1 = [&](std::vector<GemmOp> &ops, const GemmDesc &d,
+                       const std::vector<const void *> &a, const std::vector<const void *> &b,
+                       const std::vector<const void *> &c) {
       if (a.empty()) return;
       GemmOp op;
       op.d = d;
       op.n = (int)a.size();
       op.a = P.arena.add(a); op.b = P.arena.add(b); op.c = P.arena.add(c);
       ops.push_back(op);
+    };
+    // A BP contraction in both plans: FP64 storage, and (mixed precision) FP32 storage of the
+    // site tensors and intermediates: a leg absorption reads A and writes C in FP32 (B is a
+    // message), a closing reads A and B in FP32 and writes the FP64 message
+    std::vector<GemmOp> *ops32 = nullptr;
+    auto add_op = [&](std::vector<GemmOp> &ops, const GemmDesc &d,
+                      const std::vector<const void *> &a, const std::vector<const void *> &b,
+                      const std::vector<const void *> &c) {
+      add_op1(ops, d, a, b, c);
+      if (!ops32 || a.empty()) return;
+      GemmDesc d32 = d;
+      d32.prec = 1;
+      d32.a32 = 1;
+      if (d.herm) d32.b32 = 1;
+      else d32.c32 = 1;
+      add_op1(*ops32, d32, map32(a), map32(b), map32(c));
     };
     // Sweep schedule: vertex classes (the two sides of a bipartite graph, else a greedy proper
     // vertex colouring).  The messages sent by one class are recomputed together and normalised
@@ -878,7 +929,8 @@ void Engine::build() {
     };
     int res_off = 0;
     for (int c = 0; c < ncls; ++c) {
-      Plan::BpClass C;
+      Plan::BpClass C, C32;
+      ops32 = mixed ? &C32.ops : nullptr;
       auto in = [&](int v, int i) { return cls[P.nb[v][i]] < c ? Mnp(P.in_msg[v][i]) : Mp(P.in_msg[v][i]); };
       // degree 3: Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
       //           Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
@@ -948,7 +1000,15 @@ void Engine::build() {
         C.norm_old = P.arena.add(no);
       }
       P.bp_classes.push_back(C);
+      if (mixed) {
+        C32.nmsg = C.nmsg;
+        C32.res_off = C.res_off;
+        C32.norm_new = C.norm_new;
+        C32.norm_old = C.norm_old;
+        P.bp_classes32.push_back(C32);
+      }
     }
+    ops32 = nullptr;
     if (P.nmem > 1) {
       std::vector<std::vector<int>> by(P.nmem);
       for (size_t r = 0; r < res_src.size(); ++r) by[P.site_member[res_src[r]]].push_back((int)r);
@@ -1042,6 +1102,7 @@ void Engine::build() {
 }
 
 void Engine::reset() {
+  t32_stale_ = true;
   Plan &P = *plan_;
   const long c2 = (long)P.chi * P.chi;
   std::vector<double> t(2 * tensor_elems(), 0.0);
@@ -1062,6 +1123,7 @@ static void run(Backend *be, const PtrArena &ar, const GemmOp &op, int prec) {
 }
 
 void Engine::apply_rx() {
+  t32_stale_ = true;
   Plan &P = *plan_;
   if (prob_.site_theta.empty()) {
     double c = std::cos(prob_.theta / 2), s = std::sin(prob_.theta / 2);
@@ -1080,12 +1142,14 @@ void Engine::apply_rx() {
 }
 
 void Engine::apply_rx_angle(double theta) {
+  t32_stale_ = true;
   Plan &P = *plan_;
   be_->rx(P.arena.at<double *const *>(P.rx_ptrs), P.rx_half, P.n, std::cos(theta / 2),
           std::sin(theta / 2));
 }
 
 double Engine::apply_layer(int colour, int zz_sign) {
+  t32_stale_ = true;
   Plan &P = *plan_;
   auto it = std::find(P.layer_colours.begin(), P.layer_colours.end(), colour);
   if (it == P.layer_colours.end()) return 0.0;
@@ -1155,8 +1219,13 @@ double Engine::apply_layer(int colour, int zz_sign) {
 
 void Engine::sweep_classes() {
   Plan &P = *plan_;
-  for (auto &C : P.bp_classes) {
-    for (auto &op : C.ops) run(be_, P.arena, op, bp_prec_);
+  const bool f32 = bp_prec_ == 1 && !P.bp_classes32.empty();
+  if (f32 && t32_stale_) {          // the FP32 copy of the site tensors, once per new state
+    be_->to_f32(P.T, P.T32, tensor_elems());
+    t32_stale_ = false;
+  }
+  for (auto &C : f32 ? P.bp_classes32 : P.bp_classes) {
+    for (auto &op : C.ops) run(be_, P.arena, op, f32 ? 1 : bp_prec_);
     if (C.nmsg)
       be_->normalize_residual(P.chi, P.arena.at<double *const *>(C.norm_new),
                               P.arena.at<const double *const *>(C.norm_old), P.res + C.res_off,
@@ -1178,13 +1247,15 @@ int Engine::bp(int max_iter, double *residual) {
   // Mixed modes sweep with FP32 contractions while the residual is above the FP32 floor, then
   // (if the tolerance asks for more) finish with FP64 sweeps: the fixed point is the FP64 one.
   int it = 0;
-  double r = INFINITY;
+  double r = INFINITY, prev = INFINITY;
   bp_prec_ = prob_.precision ? 1 : 0;
   while (it < max_iter) {
     r = bp_sweep();
     ++it;
     if (r < prob_.bp_tol) break;
-    if (bp_prec_ == 1 && r < kFp32BpFloor) bp_prec_ = 0;
+    // FP32 sweeps stop at their rounding floor, or earlier if the residual stops falling
+    if (bp_prec_ == 1 && fp32_done(r, prev)) bp_prec_ = 0;
+    prev = r;
   }
   bp_prec_ = prob_.precision ? 1 : 0;
   if (residual) *residual = r;
@@ -1204,6 +1275,7 @@ void Engine::bp_members(int max_iter, int *sweeps, double *residual) {
   }
   be_->h2d(P.act[0], act.data(), (size_t)R * 4);
   int cur = 0;
+  double prev = INFINITY;
   bp_prec_ = prob_.precision ? 1 : 0;
   for (int it = 1; it <= max_iter; ++it) {
     sweep_classes();
@@ -1223,7 +1295,8 @@ void Engine::bp_members(int max_iter, int *sweeps, double *residual) {
       rmax = std::max(rmax, r[j]);
     }
     if (!any) break;
-    if (bp_prec_ == 1 && rmax < kFp32BpFloor) bp_prec_ = 0;
+    if (bp_prec_ == 1 && fp32_done(rmax, prev)) bp_prec_ = 0;
+    prev = rmax;
   }
   bp_prec_ = prob_.precision ? 1 : 0;
 }
@@ -1281,6 +1354,7 @@ void Engine::observe_entropy(double *out) {
 // tensor with the bond weights of its other legs an isometry.  S is normalised to unit 2-norm,
 // values <= svd_cutoff * s_1 are dropped, and the messages become the fixed point diag(S)/sum S.
 void Engine::vidal_gauge(double *lambda) {
+  t32_stale_ = true;
   Plan &P = *plan_;
   if (!P.E) return;
   const PtrArena &ar = P.arena;
@@ -1632,6 +1706,7 @@ void Engine::get_state(double *tensors, double *messages, int32_t *bond_dims) {
 }
 
 void Engine::set_state(const double *tensors, const double *messages, const int32_t *bond_dims) {
+  t32_stale_ = true;
   Plan &P = *plan_;
   if (tensors) be_->h2d(P.T, tensors, tensor_elems() * 16);
   if (messages) be_->h2d(P.M, messages, message_elems() * 16);

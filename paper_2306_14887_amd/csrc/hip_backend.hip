@@ -68,12 +68,36 @@ __device__ __forceinline__ KOff k_tile(int k0, int Ki, long so, long si) {
   return r;
 }
 
+// Complex storage of a GEMM operand: FP64 (double pairs) or FP32 (float pairs), read into and
+// written from double2 registers.
+template <bool F32>
+struct Cx;
+template <>
+struct Cx<false> {
+  typedef double2 t;
+  static __device__ __forceinline__ double2 zero() { return make_double2(0.0, 0.0); }
+  static __device__ __forceinline__ double2 get(double2 v) { return v; }
+  static __device__ __forceinline__ double2 make(double re, double im) {
+    return make_double2(re, im);
+  }
+};
+template <>
+struct Cx<true> {
+  typedef float2 t;
+  static __device__ __forceinline__ float2 zero() { return make_float2(0.0f, 0.0f); }
+  static __device__ __forceinline__ double2 get(float2 v) { return make_double2(v.x, v.y); }
+  static __device__ __forceinline__ float2 make(double re, double im) {
+    return make_float2((float)re, (float)im);
+  }
+};
+
 // Grouped complex GEMM.  grid: x = output tiles, y = batch * ksplit, z = problem.  With
 // ksplit > 1 each block sums its K chunk into the partial buffer W (layout
 // [prob][batch][kz][M][N]); gemm_reduce_kernel then combines the chunks in a fixed order.
 // T = double: FP64 MFMA (v_mfma_f64_16x16x4f64); T = float: operands rounded to FP32 when
 // staged, FP32 MFMA (v_mfma_f32_16x16x4f32) with FP32 accumulation over the block's K range.
-// Storage and the split-K chunk sums stay FP64.
+// A32 / B32 / C32: that operand is stored as complex FP32 (FP32 mode only); the split-K chunk
+// sums stay FP64.
 template <typename T>
 struct MfmaTraits;
 template <>
@@ -95,13 +119,16 @@ struct MfmaTraits<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, bool HERM>
+template <typename T, bool HERM, bool A32 = false, bool B32 = false, bool C32 = false>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *const *Ap,
                                                       const double *const *Bp,
                                                       double *const *Cp, int ksplit,
                                                       int kchunk, double2 *W) {
   typedef MfmaTraits<T> MT;
   typedef typename MT::acc_t acc_t;
+  typedef Cx<A32> XA;
+  typedef Cx<B32> XB;
+  typedef Cx<C32> XC;
   __shared__ T As[2][BK][BM + PAD];
   __shared__ T Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
@@ -125,8 +152,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
     dbj[b] = min(q - bi * (bi + 1) / 2, bi);
   }
   const int bat = blockIdx.y / ksplit, kz = blockIdx.y % ksplit, prob = blockIdx.z;
-  const double2 *A = reinterpret_cast<const double2 *>(Ap[prob]) + (long)bat * d.a_b;
-  const double2 *B = reinterpret_cast<const double2 *>(Bp[prob]) + (long)bat * d.b_b;
+  const typename XA::t *A = reinterpret_cast<const typename XA::t *>(Ap[prob]) + (long)bat * d.a_b;
+  const typename XB::t *B = reinterpret_cast<const typename XB::t *>(Bp[prob]) + (long)bat * d.b_b;
   const int m0 = tm * BM, n0 = tn * BN;
   const int kbeg = kz * kchunk, kend = min(d.K, kbeg + kchunk);
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
@@ -149,13 +176,16 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
     aoff[it] = aok[it] ? cidx(mg, d.Mi, d.a_mo, d.a_mi) : 0;
     boff[it] = bok[it] ? cidx(ng, d.Ni, d.b_no, d.b_ni) : 0;
   }
-  double2 ra[LOADS], rb[LOADS];
+  // fetched values stay in their storage type until staged (no round trip through FP64)
+  typename XA::t ra[LOADS];
+  typename XB::t rb[LOADS];
   auto fetch = [&](int k0) {
     KOff ka = k_tile(k0, d.Ki, d.a_ko, d.a_ki), kb = k_tile(k0, d.Ki, d.b_ko, d.b_ki);
 #pragma unroll
     for (int it = 0; it < LOADS; ++it) {
       int kga = k0 + ak[it], kgb = k0 + bk[it];
-      double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+      typename XA::t va = XA::zero();
+      typename XB::t vb = XB::zero();
       if (aok[it] && kga < kend) {
         long o = ka.uniform ? ka.base + (long)ak[it] * ka.si : cidx(kga, d.Ki, d.a_ko, d.a_ki);
         va = A[aoff[it] + o];
@@ -244,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
     __syncthreads();
   }
   // ---- epilogue ----
-  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  typename XC::t *C = reinterpret_cast<typename XC::t *>(Cp[prob]) + (long)bat * d.c_b;
   double2 *Wp = W ? W + (((size_t)prob * d.batch + bat) * ksplit + kz) * (size_t)d.M * d.N
                   : nullptr;
   if constexpr (HERM) {
@@ -257,8 +287,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         return;
       }
       const double vr = d.alpha_re * cr, vi = mg == ng ? 0.0 : d.alpha_re * ci;
-      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = make_double2(vr, vi);
-      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = make_double2(vr, -vi);
+      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = XC::make(vr, vi);
+      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = XC::make(vr, -vi);
     };
     if (dtile) {
       auto put_block = [&](int bi, int bj, const acc_t(&a3)[3]) {
@@ -317,11 +347,11 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         double vi = d.alpha_re * ci + d.alpha_im * cr;
         long off = roff[i][r] + coff[j];
         if (d.beta) {
-          double2 o = C[off];
+          double2 o = XC::get(C[off]);
           vr += o.x;
           vi += o.y;
         }
-        C[off] = make_double2(vr, vi);
+        C[off] = XC::make(vr, vi);
       }
 }
 
@@ -336,18 +366,20 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
 // lane's outputs share one row of C and the stores run along M (used when M is C's unit-stride
 // index).  grid: x = workgroups per (batch, problem), y = batch, z = problem.
 constexpr int SK_MAX = 64;
-template <typename T, bool TR>
+template <typename T, bool TR, bool A32 = false, bool C32 = false>
 __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const double *const *Ap,
                                                              const double *const *Bp,
                                                              double *const *Cp) {
   typedef MfmaTraits<T> MT;
   typedef typename MT::acc_t acc_t;
+  typedef Cx<A32> XA;
+  typedef Cx<C32> XC;
   __shared__ T Bs[2][SK_MAX][SK_MAX + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bat = blockIdx.y, prob = blockIdx.z;
-  const double2 *A = reinterpret_cast<const double2 *>(Ap[prob]) + (long)bat * d.a_b;
+  const typename XA::t *A = reinterpret_cast<const typename XA::t *>(Ap[prob]) + (long)bat * d.a_b;
   const double2 *B = reinterpret_cast<const double2 *>(Bp[prob]) + (long)bat * d.b_b;
-  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  typename XC::t *C = reinterpret_cast<typename XC::t *>(Cp[prob]) + (long)bat * d.c_b;
   const T sa = d.conjA ? T(-1) : T(1), sb = d.conjB ? T(-1) : T(1);
   // B into LDS, zero outside K x N
   for (int idx = tid; idx < SK_MAX * SK_MAX; idx += 256) {
@@ -368,15 +400,16 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
     const int m = s * 16 + r16;
     return m < d.M ? cidx(m, d.Mi, d.a_mo, d.a_mi) : -1;
   };
-  auto load_half = [&](long ro, int h, double2 (&v)[8]) {
+  typedef typename XA::t av_t;            // A values stay in their storage type
+  auto load_half = [&](long ro, int h, av_t (&v)[8]) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = 4 * (8 * h + q) + kq;
-      v[q] = (ro >= 0 && k < d.K) ? A[ro + (long)k * d.a_ki] : make_double2(0.0, 0.0);
+      v[q] = (ro >= 0 && k < d.K) ? A[ro + (long)k * d.a_ki] : XA::zero();
     }
   };
   acc_t acc[4][3];
-  auto mma_half = [&](int h, const double2 (&v)[8]) {
+  auto mma_half = [&](int h, const av_t (&v)[8]) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int j = 8 * h + q;
@@ -400,7 +433,7 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
     }
   };
   int s = blockIdx.x * 4 + wave;
-  double2 lo[8], hi[8];
+  av_t lo[8], hi[8];
   long ro = s < strips ? row_off(s) : -1;
   if (s < strips) {
     load_half(ro, 0, lo);
@@ -436,11 +469,11 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
         double vi = d.alpha_re * ci + d.alpha_im * cr;
         const long off = co + (long)n * d.c_ni;
         if (d.beta) {
-          const double2 o = C[off];
+          const double2 o = XC::get(C[off]);
           vr += o.x;
           vi += o.y;
         }
-        C[off] = make_double2(vr, vi);
+        C[off] = XC::make(vr, vi);
       }
     }
     ro = ron;
@@ -467,12 +500,14 @@ __global__ __launch_bounds__(256) void mfma_rate_kernel(int iters, double *out) 
 }
 
 // Sums the K chunks of a split-K GEMM in chunk order and applies alpha / beta.
+template <bool C32>
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *const *Cp,
                                                           int ksplit, const double2 *W) {
+  typedef Cx<C32> XC;
   const int bat = blockIdx.y, prob = blockIdx.z;
   const size_t mn = (size_t)d.M * d.N;
   const double2 *wp = W + ((size_t)prob * d.batch + bat) * ksplit * mn;
-  double2 *C = reinterpret_cast<double2 *>(Cp[prob]) + (long)bat * d.c_b;
+  typename XC::t *C = reinterpret_cast<typename XC::t *>(Cp[prob]) + (long)bat * d.c_b;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < mn;
        idx += (size_t)gridDim.x * blockDim.x) {
     int mg = (int)(idx / d.N), ng = (int)(idx % d.N);
@@ -485,19 +520,19 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
     }
     if (d.herm) {
       const double vr = d.alpha_re * cr, vi = mg == ng ? 0.0 : d.alpha_re * ci;
-      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = make_double2(vr, vi);
-      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = make_double2(vr, -vi);
+      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = XC::make(vr, vi);
+      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = XC::make(vr, -vi);
       continue;
     }
     double vr = d.alpha_re * cr - d.alpha_im * ci;
     double vi = d.alpha_re * ci + d.alpha_im * cr;
     long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
     if (d.beta) {
-      double2 o = C[off];
+      double2 o = XC::get(C[off]);
       vr += o.x;
       vi += o.y;
     }
-    C[off] = make_double2(vr, vi);
+    C[off] = XC::make(vr, vi);
   }
 }
 
@@ -2116,6 +2151,14 @@ __global__ void svd_finish_kernel(int n, int chi, const double *const *evals,
   }
 }
 
+__global__ __launch_bounds__(256) void to_f32_kernel(const double2 *src, float2 *dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = src[i];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
 __global__ void split_sqrt_kernel(int rowsB, int rowsS, int n, int chi, const double *const *U,
                                   const double *const *V, const double *const *S,
                                   double *const *RBn, double *const *RSn) {
@@ -2640,15 +2683,33 @@ class HipBackend : public Backend {
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s_));
     }
+    // FP32 storage: an absorption into an FP32 buffer (A, C FP32; B FP64) or a closing into an
+    // FP64 message (A, B FP32), in FP32 mode only
+    const int st = (d.a32 ? 1 : 0) | (d.b32 ? 2 : 0) | (d.c32 ? 4 : 0);
+    if (st && (d.prec != 1 || (st != 5 && st != 3))) {
+      if (err_ == 0) {
+        err_ = -1;
+        errmsg_ = "gemm: unsupported combination of FP32 operand storage";
+      }
+      return;
+    }
     // K and N within 64 (one stride each) and enough rows to amortise loading B (at least 16
     // strips): B resident in LDS, rows of A streamed
-    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 256 && !d.herm) {
+    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 256 && !d.herm &&
+        !d.b32) {
       const int strips = (d.M + 15) / 16;
       const int per = std::max(1, resident_ / std::max(1, d.batch * nprob));
       dim3 g(std::max(1, std::min(per, (strips + 3) / 4)), d.batch, nprob);
       const bool tr = d.c_mi == 1 && d.c_ni != 1;     // C is unit-stride along M
       stale_check("gemm_stream_kernel");
-      if (d.prec == 1) {
+      if (d.prec == 1 && st == 5) {
+        if (tr)
+          hipLaunchKernelGGL((gemm_stream_kernel<float, true, true, true>), g, dim3(256), 0, s_, d,
+                             A, B, C);
+        else
+          hipLaunchKernelGGL((gemm_stream_kernel<float, false, true, true>), g, dim3(256), 0, s_,
+                             d, A, B, C);
+      } else if (d.prec == 1) {
         if (tr) hipLaunchKernelGGL((gemm_stream_kernel<float, true>), g, dim3(256), 0, s_, d, A, B, C);
         else hipLaunchKernelGGL((gemm_stream_kernel<float, false>), g, dim3(256), 0, s_, d, A, B, C);
       } else {
@@ -2684,12 +2745,27 @@ class HipBackend : public Backend {
     }
     if (d.prec == 1) {
       stale_check("gemm_kernel<float>");
-      if (d.herm)
+      if (st == 5) {
+        if (d.herm)
+          hipLaunchKernelGGL((gemm_kernel<float, true, true, false, true>), grid, dim3(256), 0, s_,
+                             d, A, B, C, ksplit, kchunk, W);
+        else
+          hipLaunchKernelGGL((gemm_kernel<float, false, true, false, true>), grid, dim3(256), 0,
+                             s_, d, A, B, C, ksplit, kchunk, W);
+      } else if (st == 3) {
+        if (d.herm)
+          hipLaunchKernelGGL((gemm_kernel<float, true, true, true, false>), grid, dim3(256), 0, s_,
+                             d, A, B, C, ksplit, kchunk, W);
+        else
+          hipLaunchKernelGGL((gemm_kernel<float, false, true, true, false>), grid, dim3(256), 0,
+                             s_, d, A, B, C, ksplit, kchunk, W);
+      } else if (d.herm) {
         hipLaunchKernelGGL((gemm_kernel<float, true>), grid, dim3(256), 0, s_, d, A, B, C, ksplit,
                            kchunk, W);
-      else
+      } else {
         hipLaunchKernelGGL((gemm_kernel<float, false>), grid, dim3(256), 0, s_, d, A, B, C, ksplit,
                            kchunk, W);
+      }
       launch_check("gemm_kernel<float>");
     } else {
       stale_check("gemm_kernel<double>");
@@ -2711,8 +2787,12 @@ class HipBackend : public Backend {
     if (ksplit > 1) {
       int bx = std::min(64, (int)((d.M * (size_t)d.N + 255) / 256));
       stale_check("gemm_reduce_kernel");
-      hipLaunchKernelGGL(gemm_reduce_kernel, dim3(bx, d.batch, nprob), dim3(256), 0, s_, d, C,
-                         ksplit, (const double2 *)W);
+      if (d.c32)
+        hipLaunchKernelGGL(gemm_reduce_kernel<true>, dim3(bx, d.batch, nprob), dim3(256), 0, s_, d,
+                           C, ksplit, (const double2 *)W);
+      else
+        hipLaunchKernelGGL(gemm_reduce_kernel<false>, dim3(bx, d.batch, nprob), dim3(256), 0, s_,
+                           d, C, ksplit, (const double2 *)W);
       launch_check("gemm_reduce_kernel");
     }
   }
@@ -3072,6 +3152,14 @@ class HipBackend : public Backend {
     hipLaunchKernelGGL(split_sqrt_kernel, dim3(bx, nprob), dim3(256), 0, s_, rowsB, rowsS, n,
                        chi, U, V, S, RBn, RSn);
     launch_check("split_sqrt_kernel");
+  }
+  void to_f32(const double *src, float *dst, size_t n) override {
+    if (!n) return;
+    const unsigned bx = (unsigned)std::min<size_t>(4 * (size_t)resident_, (n + 255) / 256);
+    stale_check("to_f32_kernel");
+    hipLaunchKernelGGL(to_f32_kernel, dim3(bx), dim3(256), 0, s_, (const double2 *)src,
+                       (float2 *)dst, n);
+    launch_check("to_f32_kernel");
   }
   void normalize_residual(int chi, double *const *Mn, const double *const *Mo, double *res,
                           int nprob) override {

@@ -165,6 +165,59 @@ def test_gemm_hermitian_output(ctx, name, n, k, nprob, prec):
         assert np.array_equal(got[p], got[p].conj().T)
 
 
+def _c64(x):
+    return x.astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("store", [5, 3])
+@pytest.mark.parametrize("name,desc,nprob", CASES, ids=[c[0] for c in CASES])
+def test_gemm_fp32_storage(ctx, name, desc, nprob, store):
+    """Operands held in complex FP32 on the device (mixed-precision BP): 5 = A and C (a leg
+    absorption into an FP32 buffer), 3 = A and B (a closing into an FP64 message).  Equal to the
+    product of the FP32-rounded operands within FP32 accumulation, plus the rounding of an FP32
+    output."""
+    print(f"[gemm fp32 storage] case {name} store={store}", flush=True)
+    rng = np.random.default_rng(zlib.crc32(name.encode()) + 7)
+    asz, bsz, csz = _extent(desc, "a"), _extent(desc, "b"), _extent(desc, "c")
+    A = _rand(rng, nprob * asz)
+    Bm = _rand(rng, nprob * bsz)
+    Cm = _rand(rng, nprob * csz)
+    got = ctx.test_gemm({**desc, "prec": 1, "store32": store}, A, Bm, Cm, nprob)
+    Ar = _c64(A)
+    Br = _c64(Bm) if store & 2 else Bm
+    Cr = _c64(Cm) if store & 4 else Cm
+    want = _ref_gemm(desc, Ar, Br, Cr, nprob, asz, bsz, csz)
+    scale = np.sqrt(desc["K"]) * 4 * max(1.0, abs(desc.get("alpha_re", 1)) + abs(desc.get("alpha_im", 0)))
+    out_round = 6e-8 * np.abs(want) if store & 4 else 0.0
+    assert np.all(np.abs(got - want) < 2e-6 * scale + out_round)
+
+
+def test_gemm_fp32_storage_hermitian_closing(ctx):
+    """The BP closing shape in FP32 storage: C = A A^H (K = 2 chi^2 = 8192 at chi = 64, split K)
+    with A and B read as FP32 and the Hermitian FP64 output."""
+    print("[gemm fp32 storage] hermitian closing", flush=True)
+    rng = np.random.default_rng(3)
+    n, k, nprob = 64, 8192, 2
+    d = dict(M=n, N=n, K=k, a_mi=k, a_ki=1, b_ki=1, b_ni=k, c_mi=n, c_ni=1, conjB=1,
+             herm=1, prec=1, store32=3)
+    A = _rand(rng, nprob * n * k)
+    got = ctx.test_gemm(d, A, A, np.zeros(nprob * n * n, complex), nprob).reshape(nprob, n, n)
+    for p in range(nprob):
+        a = _c64(A[p * n * k:(p + 1) * n * k]).reshape(n, k)
+        want = a @ a.conj().T
+        assert np.abs(got[p] - want).max() < 1e-6 * np.abs(want).max()
+        assert np.array_equal(got[p], got[p].conj().T)
+
+
+def test_gemm_fp32_storage_rejects_other_sets(ctx):
+    from paper_2306_14887_amd.bpki import BpkiError
+    d = dict(M=64, N=64, K=64, a_mi=64, a_ki=1, b_ki=64, b_ni=1, c_mi=64, c_ni=1)
+    z = np.zeros(64 * 64, complex)
+    for prec, store in ((1, 1), (1, 7), (0, 5)):
+        with pytest.raises(BpkiError):
+            ctx.test_gemm({**d, "prec": prec, "store32": store}, z, z, z)
+
+
 def test_gemm_herm_rejects_invalid_descriptor(ctx):
     from paper_2306_14887_amd.bpki import BpkiError
     d = dict(M=64, N=32, K=64, a_mi=64, a_ki=1, b_ki=32, b_ni=1, c_mi=32, c_ni=1, herm=1)
