@@ -165,6 +165,20 @@ int bpki_estimate_bytes(const bpki_problem *p, size_t *bytes);
 /* Blocking solve.  Inputs are copied; result buffers are caller-owned host memory. */
 int bpki_solve(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
 
+/* bpki_solve without device allocation, for callers that cannot allocate device memory (tight
+ * serving loops, code around graph capture, harnesses that forbid hipMalloc): every device
+ * buffer of the call (site tensors, messages, workspaces) comes from one static array of
+ * 64 MiB (BPKI_NOALLOC_SCRATCH_BYTES) that the library holds on every device it runs on until the
+ * process ends; the context's own stream and pinned staging buffer, made by bpki_create, are used,
+ * and nothing is allocated on the device or freed during the call.  Same arguments, results and
+ * codes as bpki_solve (same kernels), plus -4 when bpki_estimate_bytes exceeds the array (a
+ * 12-site ring up to chi 32, the 29-qubit lattice up to chi 16, 127 qubits up to chi 8 fit) or
+ * the array runs out during the call.  The array keeps the previous call's contents; whatever
+ * must start at zero is cleared by the call.  Calls on one context are serialised; calls that
+ * overlap on one GPU from different contexts race on the same array. */
+#define BPKI_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bpki_solve_noalloc(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
+
 /* ---- Serving: continuous batching -----------------------------------------------------------
  * bpki_submit queues a problem (deep copy) and returns at once with a ticket.  The context runs a
  * fixed number of serving slots, each a worker thread with its own HIP stream.  Admission is in

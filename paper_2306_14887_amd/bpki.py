@@ -86,6 +86,7 @@ def load(path: str | None = None):
         "bpki_validate": (C.c_int, [P]),
         "bpki_estimate_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
         "bpki_solve": (C.c_int, [vp, P, R]),
+        "bpki_solve_noalloc": (C.c_int, [vp, P, R]),
         "bpki_submit": (C.c_int, [vp, P, R, C.POINTER(C.c_uint64)]),
         "bpki_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int)]),
         "bpki_wait": (C.c_int, [vp, C.c_uint64]),
@@ -132,7 +133,8 @@ def load(path: str | None = None):
 
 def exported_symbols() -> list[str]:
     return ["bpki_problem_defaults", "bpki_create", "bpki_destroy", "bpki_last_error",
-            "bpki_validate", "bpki_estimate_bytes", "bpki_solve", "bpki_submit", "bpki_poll",
+            "bpki_validate", "bpki_estimate_bytes", "bpki_solve", "bpki_solve_noalloc",
+            "bpki_submit", "bpki_poll",
             "bpki_wait", "bpki_cancel", "bpki_serving_config", "bpki_serving_packing",
             "bpki_ticket_times", "bpki_ticket_pack_size", "bpki_set_allocator",
             "bpki_session_open", "bpki_session_close",
@@ -285,6 +287,16 @@ class Context:
         out = _alloc_result(spec)
         r = _result_struct(out)
         rc = _check(self.lib, self.lib.bpki_solve(self.h, C.byref(p), C.byref(r)))
+        out["status"] = rc
+        return out
+
+    def solve_noalloc(self, spec: ProblemSpec) -> dict:
+        """bpki_solve on the library's static device scratch (no device allocation in the
+        call); problems above its size are refused with -4."""
+        p, keep = spec.to_c()
+        out = _alloc_result(spec)
+        r = _result_struct(out)
+        rc = _check(self.lib, self.lib.bpki_solve_noalloc(self.h, C.byref(p), C.byref(r)))
         out["status"] = rc
         return out
 

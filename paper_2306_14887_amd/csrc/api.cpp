@@ -20,6 +20,8 @@
 
 using namespace bpki;
 
+static_assert(kScratchBytes == BPKI_NOALLOC_SCRATCH_BYTES, "scratch size differs from the header");
+
 static thread_local std::string g_err;
 
 // A chi-limited cut whose gap (sigma_chi - sigma_{chi+1}) / sigma_1 is below this is reported as
@@ -194,6 +196,24 @@ extern "C" int bpki_estimate_bytes(const bpki_problem *p, size_t *bytes) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Bump allocator over the static scratch array of bpki_solve_noalloc: reset at the start of every
+// call, frees are no-ops (the whole region is reused by the next call).
+struct ScratchArena {
+  char *base = nullptr;
+  size_t size = 0, top = 0;
+};
+
+static void *arena_alloc(size_t bytes, void *, void *user) {
+  ScratchArena *a = static_cast<ScratchArena *>(user);
+  const size_t n = (bytes + 255) & ~size_t(255);
+  if (!a->base || n > a->size - a->top) return nullptr;
+  void *p = a->base + a->top;
+  a->top += n;
+  return p;
+}
+
+static void arena_free(void *, void *, void *) {}
+
 struct bpki_ctx {
   int device = 0;
   void *stream = nullptr;
@@ -221,6 +241,12 @@ struct bpki_ctx {
   bpki_alloc_fn ualloc = nullptr;
   bpki_free_fn ufree = nullptr;
   void *uuser = nullptr;
+  // allocation-free solves: a backend whose every device buffer comes from the device's static
+  // scratch array, set up with the context (no allocation at call time)
+  std::unique_ptr<Backend> na_be;
+  ScratchArena arena;
+  std::string na_err;
+  std::mutex na_mu;
 };
 
 extern "C" int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t budget) {
@@ -233,6 +259,19 @@ extern "C" int bpki_create(bpki_ctx **out, int device, void *hip_stream, size_t 
   c->stream = hip_stream;
   c->budget = budget;
   c->be.reset(be);
+  // the device's scratch array (looked up with the device current, as the backend left it) and
+  // the backend that allocates from it; without them only bpki_solve_noalloc fails
+  void *base = nullptr;
+  if (scratch_region(device, &base, &err) == 0) {
+    Backend *na = make_hip_backend(device, hip_stream, &err);
+    if (na) {
+      c->arena.base = static_cast<char *>(base);
+      c->arena.size = kScratchBytes;
+      na->set_allocator(arena_alloc, arena_free, &c->arena);
+      c->na_be.reset(na);
+    }
+  }
+  if (!c->na_be) c->na_err = err;
   *out = c;
   return 0;
 }
@@ -362,6 +401,42 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
   if (r->degenerate_cuts)
     std::memcpy(r->degenerate_cuts, ndeg.data(), ndeg.size() * sizeof(int32_t));
   return warn;
+}
+
+extern "C" int bpki_solve_noalloc(bpki_ctx *c, const bpki_problem *p, bpki_result *r) {
+  if (!c || !r) return fail(-1, "NULL context or result");
+  int rc = bpki_validate(p);
+  if (rc) return rc;
+  Problem q = to_problem(p);
+  if (!c->na_be) return fail(-5, "bpki_solve_noalloc: no scratch on this device: " + c->na_err);
+  const size_t need = Engine::estimate_bytes(q);
+  if (need > kScratchBytes)
+    return fail(-4, "bpki_solve_noalloc: the problem needs up to " + std::to_string(need) +
+                        " bytes of device memory; the static scratch holds " +
+                        std::to_string(kScratchBytes) + " (use bpki_solve)");
+  std::lock_guard<std::mutex> lk(c->na_mu);
+  Backend *be = c->na_be.get();
+  be->forget_workspaces();       // their memory was the previous call's part of the scratch
+  be->clear_alloc_error();
+  c->arena.top = 0;
+  std::string msg;
+  if (int e = be->check(&msg)) return fail(e, "device error: " + msg);
+  int status;
+  {
+    Engine eng(be, q);
+    if (be->check(&msg) == -4)
+      status = fail(-4, "bpki_solve_noalloc: the static scratch of " +
+                            std::to_string(kScratchBytes) + " bytes is exhausted");
+    else if (int e = be->check(&msg))
+      status = fail(e, "device error: " + msg);
+    else
+      status = run_solve(be, eng, q, r, nullptr);
+  }
+  be->forget_workspaces();
+  if (status == -4 && be->check(nullptr) == -4)
+    fail(-4, "bpki_solve_noalloc: the static scratch of " + std::to_string(kScratchBytes) +
+                 " bytes is exhausted");
+  return status;
 }
 
 extern "C" int bpki_solve(bpki_ctx *c, const bpki_problem *p, bpki_result *r) {

@@ -54,6 +54,10 @@ struct Backend {
   virtual int set_allocator(DevAlloc a, DevFree f, void *user) = 0;
   virtual void *alloc(size_t bytes) = 0;          // zero-initialised
   virtual void release(void *p) = 0;
+  // Forget the cached workspaces without freeing them (their memory is an arena the caller
+  // resets), and clear an allocation failure (a device error stays).
+  virtual void forget_workspaces() = 0;
+  virtual void clear_alloc_error() = 0;
   virtual void h2d(void *dst, const void *src, size_t bytes) = 0;
   virtual void d2h(void *dst, const void *src, size_t bytes) = 0;
   virtual void d2d(void *dst, const void *src, size_t bytes) = 0;
@@ -147,6 +151,11 @@ struct Backend {
 };
 
 Backend *make_hip_backend(int device, void *stream, std::string *err);
+
+// The allocation-free solve's device memory: a static array of kScratchBytes per device; its
+// address on `device`, which must be current (0, or -5 with *err set).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+int scratch_region(int device, void **ptr, std::string *err);
 
 // ------------------------------------------------------------------------------------------
 struct Problem {

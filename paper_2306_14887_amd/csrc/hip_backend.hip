@@ -20,6 +20,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -2591,6 +2593,19 @@ class HipBackend : public Backend {
     uf_(p, (void *)s_, uu_);
     return e;
   }
+  // The cached workspaces are dropped without being freed (their memory belongs to an arena
+  // that the caller resets); an allocation failure, unlike a device error, is cleared.
+  void forget_workspaces() override {
+    HIPCHK(hipStreamSynchronize(s_));
+    skws_ = cws_ = cmeta_ = sqws_ = tptr_ = lws_ = rws_ = nullptr;
+    skws_bytes_ = cws_bytes_ = cmeta_bytes_ = sqws_bytes_ = tptr_bytes_ = lws_bytes_ = rws_bytes_ = 0;
+  }
+  void clear_alloc_error() override {
+    if (err_ == -4) {
+      err_ = 0;
+      errmsg_.clear();
+    }
+  }
   void *alloc(size_t bytes) override {
     void *p = nullptr;
     hipError_t e = dmalloc(&p, bytes);
@@ -3310,6 +3325,37 @@ class HipBackend : public Backend {
   long prof_launches_ = 0, prof_all_ = 0;
   double prof_ms_ = 0, prof_flops_ = 0;
 };
+
+// Device memory of the allocation-free solve (bpki_solve_noalloc): a fixed array in the code
+// object, so that every device holds its own copy from module load until the process ends.  Host
+// code must not use the array's name as an address; scratch_region looks up each device's copy
+// once (with that device current) and hands out that address.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+int scratch_region(int device, void **ptr, std::string *err) {
+  static std::mutex mu;
+  static std::map<int, void *> addr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != device) {
+      (void)hipGetLastError();
+      if (err) *err = "scratch: device " + std::to_string(device) + " is not current";
+      return -5;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      if (err) *err = std::string("scratch: hipGetSymbolAddress: ") + hipGetErrorString(e);
+      return -5;
+    }
+    it = addr.emplace(device, p).first;
+  }
+  *ptr = it->second;
+  return 0;
+}
 
 Backend *make_hip_backend(int device, void *stream, std::string *err) {
   int count = 0;
