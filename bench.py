@@ -19,17 +19,23 @@ The JSON line also carries:
                  1 GiB copy); frac_of_achievable_mfma compares the algorithmic rate with the
                  measured FP64 MFMA rate x 4/3 (the 3M complex product issues 3/4 of the
                  algorithmic real flops).
-  mixed        : the same window in mixed precision, with max / median |<Z>| difference to FP64.
+  mixed        : the same window in mixed precision (BP tolerance MIXED_TOL), with max / median
+                 |<Z>| difference to FP64, the FP64 mode at the same tolerance (the FP32
+                 arithmetic's own gain) and the roofline of its FP32 GEMM launches against the FP32
+                 MFMA peak (157.3 TFLOP/s).
+  config1      : the chi = 32 configuration: nine theta_h, 20 steps each, FP64, the lattice-average
+                 magnetisation after every step.
   chi128       : the same workload at chi = 128, steps 8..10 (FP64).
   weight10     : the paper's weight-10 observable after 5 steps at the eight theta_h, measured by
                  the extended time evolution (5 steps, then 5 steps of U(pi/2)^dagger, <Z_13>).
   theta_batch  : the eight theta_h values of the workload (20 steps each) solved together, one
                  serving slot each: aggregate Floquet steps/s.
-  serving      : the seeded request stream (see serving_bench).
-  cpu_baseline : the FP64 oracle on this host's cores on a bounded sample of the same workload
-                 (the X rotations and the three gate layers, two BP sweeps and one <Z> sweep on a
-                 seeded random chi = 64 state, ~10 s), converted to Floquet steps/s with the BP
-                 sweep count measured here.
+  serving      : the seeded request stream, 256 requests by default (see serving_bench).
+  cpu_baseline : the FP64 oracle on this host's cores, BLAS at all cores and at one thread, as
+                 Floquet steps/s of the same workload from a bounded per-unit sample (gates of each
+                 edge type, message updates and <Z> of sites of each degree on a seeded random
+                 chi = 64 state, scaled by their counts per step, with the BP sweep count measured
+                 here); --cpu-config1 adds a whole oracle run of the chi = 32 configuration.
 """
 from __future__ import annotations
 
@@ -44,6 +50,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 # every 7th GEMM launch of the timed window is bracketed by HIP events (7 is coprime with the
 # launch pattern of a BP sweep, so every launch shape is sampled; an event pair on every launch
 # would slow the timed steps by ~4%)
@@ -89,8 +96,12 @@ def _cores() -> int:
     return n
 
 
-def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict:
-    """Oracle timing on a bounded sample; see module docstring."""
+def _oracle_step_time(lat, chi: int, theta: float, sweeps: float, samples: int = 6):
+    """The FP64 oracle's time for one Floquet step of the workload, from per-unit timings on a
+    seeded random full-bond state: the X rotations (all sites), `samples` gates of each edge type
+    (by the degrees of the endpoints), the message updates of `samples` sites of each degree (all
+    messages they send) and <Z> of `samples` sites of each degree, each unit scaled by its count
+    per step; BP enters with the measured number of sweeps."""
     import numpy as np
 
     from oracle import bp_tns as O
@@ -105,24 +116,41 @@ def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict
         X = rng.standard_normal((chi, chi)) + 1j * rng.standard_normal((chi, chi))
         M = X @ X.conj().T
         net.M[k] = M / np.trace(M)
+    deg = lat.degrees()
     opt = O.Options(chi=chi)
     t0 = time.perf_counter()
     net.apply_rx(theta)
-    for c in sorted(set(int(x) for x in lat.colour)):
-        for e, (u, v) in enumerate(net.edges):
-            if int(lat.colour[e]) == c:
-                net.simple_update(u, v, opt)
-    t_gates = time.perf_counter() - t0
-    n_sample_sweeps = 2
-    t0 = time.perf_counter()
-    for _ in range(n_sample_sweeps):
-        net.bp_sweep()
-    t_sweep = (time.perf_counter() - t0) / n_sample_sweeps
-    t0 = time.perf_counter()
-    for v in range(net.n):
-        net.expect_site(v, 3)
-    t_obs = time.perf_counter() - t0
-    t_step = t_gates + bp_sweeps_per_step * t_sweep + t_obs
+    t_rx = time.perf_counter() - t0
+    kinds = {}
+    for u, v in lat.edges.tolist():
+        kinds.setdefault(tuple(sorted((int(deg[u]), int(deg[v])))), []).append((u, v))
+    t_gates = 0.0
+    for es in kinds.values():
+        t0 = time.perf_counter()
+        for u, v in es[:samples]:
+            net.simple_update(u, v, opt)
+        t_gates += len(es) * (time.perf_counter() - t0) / min(samples, len(es))
+    t_sweep = t_obs = 0.0
+    for d in sorted(set(deg.tolist())):
+        sites = [v for v in range(lat.n_sites) if deg[v] == d]
+        t0 = time.perf_counter()
+        for v in sites[:samples]:
+            for w in net.nb[v]:
+                net.message(v, w, net.M)
+        t_sweep += len(sites) * (time.perf_counter() - t0) / min(samples, len(sites))
+        t0 = time.perf_counter()
+        for v in sites[:samples]:
+            net.expect_site(v, 3)
+        t_obs += len(sites) * (time.perf_counter() - t0) / min(samples, len(sites))
+    return {"rx_s": t_rx, "gates_s": t_gates, "bp_sweep_s": t_sweep, "observe_s": t_obs,
+            "step_s": t_rx + t_gates + sweeps * t_sweep + t_obs}
+
+
+def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict:
+    """The FP64 oracle on this host's cores (BLAS at all cores, and at one thread), as Floquet
+    steps/s of the benchmark workload estimated from a bounded per-unit sample."""
+    import threadpoolctl
+
     model = "unknown CPU"
     try:
         for line in open("/proc/cpuinfo"):
@@ -133,39 +161,48 @@ def cpu_baseline(lat, chi: int, theta: float, bp_sweeps_per_step: float) -> dict
         pass
     blas = "unknown BLAS"
     try:
-        import threadpoolctl
         info = [i for i in threadpoolctl.threadpool_info() if i.get("user_api") == "blas"]
         if info:
             blas = ", ".join(f"{i.get('internal_api')} {i.get('version')} "
                              f"({i.get('num_threads')} threads)" for i in info)
     except Exception:
         pass
+    t0 = time.perf_counter()
+    allc = _oracle_step_time(lat, chi, theta, bp_sweeps_per_step)
+    with threadpoolctl.threadpool_limits(1):
+        one = _oracle_step_time(lat, chi, theta, bp_sweeps_per_step)
+    wall = time.perf_counter() - t0
     return {
-        "value": 1.0 / t_step, "unit": "Floquet steps/s", "cores": _cores(), "kind": "oracle",
-        "cpu": model, "blas": blas,
-        "sample": (f"FP64 numpy oracle on a seeded random chi={chi} state of the 127-qubit "
-                   f"lattice: the X rotations and all three gate layers ({lat.n_edges} gates, "
-                   f"{t_gates:.1f} s), {n_sample_sweeps} BP sweeps ({t_sweep:.1f} s each), <Z> on "
-                   f"all sites ({t_obs:.1f} s); step time = gates + {bp_sweeps_per_step:.1f} sweeps "
-                   f"(measured BP sweeps per timed GPU step) + <Z>"),
+        "value": 1.0 / allc["step_s"], "unit": "Floquet steps/s", "cores": _cores(),
+        "kind": "oracle", "cpu": model, "blas": blas,
+        "one_thread": {"value": 1.0 / one["step_s"], "cores": 1, "phases_s": one},
+        "phases_s": allc,
+        "sample": (f"FP64 numpy oracle, 127-qubit lattice, seeded random chi={chi} state: the X "
+                   f"rotations, 6 gates of each edge type, the messages of 6 sites and <Z> of 6 "
+                   f"sites of each degree, each scaled by its count per step, with "
+                   f"{bp_sweeps_per_step:.1f} BP sweeps per step (measured on the GPU); BLAS at "
+                   f"all cores, then at one thread ({wall:.1f} s in all)"),
     }
 
 
-MIXED_TOL = 1e-8   # mixed-mode BP tolerance (served <Z> vs FP64 solve: reported per run)
+MIXED_TOL = 1e-10  # mixed-mode BP tolerance: the stated bound (|<Z> - FP64| <= 1e-5) holds there
 
 
 def serving_bench(n: int, slots: int) -> dict:
     """Serving workload: ``n`` requests from the seeded serving stream (lattices (3,9), (5,11),
     (7,15); theta ~ U[0, pi/2]; depth ~ U{1..20}; chi ~ U{8,16,32,64}).
-    1. comparator: every request solved one at a time in plain FP64 (BP tolerance 1e-12);
-    2. capacity: all requests submitted at once to the serving slots in mixed precision (FP32 BP
-       contractions, FP64 polish to BP tolerance 1e-8): solves/s = n / makespan, with
-       cross-request packing (the library default: chi <= 16, up to 16 per pack, from a backlog)
-       and without;
-    3. latency: the same served run with Poisson arrivals at 0.5, 1 and 2 times the comparator's
-       solve rate: p50 / p99 of (finish - arrival) at each (the top-level latency keys are the 2x
-       run).
-    Also reports the largest |<Z>| deviation of a served result from its FP64 solve."""
+    1. comparator: every request solved one at a time in plain FP64 (BP tolerance 1e-12); its
+       latency under the arrivals of step 3 follows from the measured service times by the FIFO
+       queue of one server (finish = max(arrival, previous finish) + service: one solve at a
+       time on an idle device);
+    2. capacity: all requests submitted at once to the serving slots in mixed precision (FP32 BP,
+       FP64 polish to MIXED_TOL): solves/s = n / makespan, with cross-request packing (the library
+       default: chi <= 16, up to 16 per pack, requests that would otherwise wait) and without;
+       and the same capacity run served in FP64 on the same slots;
+    3. latency: the served mixed run with Poisson arrivals at 0.5, 1 and 2 times the comparator's
+       solve rate (p50 / p99 of finish - arrival; the top-level latency keys are the 2x run), and
+       the served FP64 run at 2x.
+    Reports the largest |<Z>| deviation of a served result from its FP64 solve alone."""
     import numpy as np
 
     from paper_2306_14887_amd import bpki
@@ -184,22 +221,24 @@ def serving_bench(n: int, slots: int) -> dict:
     ref = []
     with bpki.Context(0) as ctx:
         t0 = time.perf_counter()
-        lat_seq = []
+        service = []
         for s in specs64:
             a = time.perf_counter()
             ref.append(ctx.solve(s)["z"])
-            lat_seq.append(time.perf_counter() - a)
+            service.append(time.perf_counter() - a)
         t_seq = time.perf_counter() - t0
+    service = np.array(service)
     rate = n / t_seq
+    print(f"serving: sequential FP64 {rate:.2f} solves/s", file=sys.stderr, flush=True)
 
-    def served(arrivals, pack=True):
+    def served(specs, arrivals, pack=True):
         with bpki.Context(0) as ctx:
             ctx.serving_config(slots)
             if not pack:
                 ctx.serving_packing(1)
             tickets = [None] * n
             t0 = time.perf_counter()
-            for i, s in enumerate(specsmx):
+            for i, s in enumerate(specs):
                 wait = arrivals[i] - (time.perf_counter() - t0)
                 if wait > 0:
                     time.sleep(wait)
@@ -212,52 +251,81 @@ def serving_bench(n: int, slots: int) -> dict:
         err = max(float(np.abs(o["z"] - z).max()) for o, z in zip(outs, ref))
         return times, err, packs
 
-    times_sat, err_sat, packs_sat = served(np.zeros(n))
+    def lat_ms(times):
+        lat = times[:, 2] - times[:, 0]
+        return 1e3 * float(np.percentile(lat, 50)), 1e3 * float(np.percentile(lat, 99))
+
+    def sequential_latency(arrivals):
+        fin, prev = np.empty(n), 0.0
+        for i in range(n):
+            prev = max(arrivals[i], prev) + service[i]
+            fin[i] = prev
+        lat = fin - arrivals
+        return 1e3 * float(np.percentile(lat, 50)), 1e3 * float(np.percentile(lat, 99))
+
+    zero = np.zeros(n)
+    times_sat, err_sat, packs_sat = served(specsmx, zero)
     cap = n / (times_sat[:, 2].max() - times_sat[:, 0].min())
-    times_np, err_np, _ = served(np.zeros(n), pack=False)
+    times_np, err_np, _ = served(specsmx, zero, pack=False)
     cap_np = n / (times_np[:, 2].max() - times_np[:, 0].min())
+    times_64, err_64, _ = served(specs64, zero)
+    cap_64 = n / (times_64[:, 2].max() - times_64[:, 0].min())
+    print(f"serving: capacity mixed {cap:.2f}, FP64 {cap_64:.2f} solves/s", file=sys.stderr,
+          flush=True)
     gaps = np.array([r.arrival for r in reqs])
     sweep, errs = [], []
+    arrivals = gaps * 0
     for f in (0.5, 1.0, 2.0):
         lam = f * rate
         arrivals = gaps / gaps[-1] * (n / lam) if n > 1 else gaps * 0
-        times, err, packs = served(arrivals)
+        times, err, packs = served(specsmx, arrivals)
         errs.append(err)
-        lat = times[:, 2] - times[:, 0]
-        sweep.append({"rate_factor": f, "arrival_rate_per_s": lam,
-                      "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                      "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                      "requests_packed": int((packs > 1).sum())})
+        p50, p99 = lat_ms(times)
+        s50, s99 = sequential_latency(arrivals)
+        sweep.append({"rate_factor": f, "arrival_rate_per_s": lam, "p50_ms": p50, "p99_ms": p99,
+                      "requests_packed": int((packs > 1).sum()),
+                      "sequential_fp64_p50_ms": s50, "sequential_fp64_p99_ms": s99})
+        print(f"serving: poisson {f}x p99 {p99:.0f} ms (sequential FP64 {s99:.0f} ms)",
+              file=sys.stderr, flush=True)
+    times_64p, err_64p, _ = served(specs64, arrivals)
+    f50, f99 = lat_ms(times_64p)
     return {
         "requests": n, "slots": slots, "mixed_bp_tol": MIXED_TOL,
         "served_mixed_solves_per_s": cap,
         "served_mixed_solves_per_s_without_packing": cap_np,
+        "served_fp64_solves_per_s": cap_64,
         "requests_packed_capacity_run": int((packs_sat > 1).sum()),
         "mean_pack_size_capacity_run": float(packs_sat.mean()),
-        "requests_packed_poisson_run": int((packs > 1).sum()),
+        "requests_packed_poisson_run": sweep[-1]["requests_packed"],
         "sequential_fp64_solves_per_s": rate,
         "speedup_vs_sequential_fp64": cap / rate,
-        "poisson_arrival_rate_per_s": lam,
-        "served_p50_ms": 1e3 * float(np.percentile(lat, 50)),
-        "served_p99_ms": 1e3 * float(np.percentile(lat, 99)),
-        "sequential_fp64_p50_ms": 1e3 * float(np.percentile(lat_seq, 50)),
-        "sequential_fp64_p99_ms": 1e3 * float(np.percentile(lat_seq, 99)),
+        "speedup_vs_served_fp64": cap / cap_64,
+        "poisson_arrival_rate_per_s": sweep[-1]["arrival_rate_per_s"],
+        "served_p50_ms": sweep[-1]["p50_ms"], "served_p99_ms": sweep[-1]["p99_ms"],
+        "sequential_fp64_p50_ms": sweep[-1]["sequential_fp64_p50_ms"],
+        "sequential_fp64_p99_ms": sweep[-1]["sequential_fp64_p99_ms"],
+        "sequential_latency": "FIFO queue of one server fed with the measured FP64 service times",
+        "served_fp64_p50_ms": f50, "served_fp64_p99_ms": f99,
         "poisson_sweep": sweep,
         "max_abs_dz_vs_fp64": max(errs + [err_sat, err_np]),
+        "max_abs_dz_served_fp64_vs_alone": max(err_64, err_64p),
     }
 
 
-def mixed_window(lat, theta, chi, warmup, steps) -> dict:
-    """The same steps in mixed precision (FP32 BP contractions, FP64 polish to MIXED_TOL)."""
+def _window(lat, theta, chi, warmup, steps, precision, tol, profile=False):
+    """Steps warmup+1 .. warmup+steps of the workload in one session: steps/s, sweeps, <Z> rows
+    and (profile) the sampled GEMM launches of each arithmetic."""
     import numpy as np
 
     from paper_2306_14887_amd import bpki
 
     with bpki.Context(0) as ctx:
         sess = ctx.session(bpki.spec_from_lattice(lat, theta, warmup + steps, chi,
-                                                  precision=bpki.BPKI_FP32, bp_tol=MIXED_TOL))
+                                                  precision=precision, bp_tol=tol))
         for _ in range(warmup):
             sess.step(observe=True)
+        if profile:
+            sess.profile(True, stride=PROFILE_STRIDE)
         iters, zs = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -265,11 +333,63 @@ def mixed_window(lat, theta, chi, warmup, steps) -> dict:
             iters.append(r["bp_iters"])
             zs.append(r["z"])
         wall = time.perf_counter() - t0
+        prof = [sess.profile_read_prec(q) for q in (0, 1)] if profile else None
         sess.close()
-    return {"value": steps / wall, "unit": "Floquet steps/s", "ms_per_step": 1e3 * wall / steps,
-            "bp_sweeps_per_step": float(np.mean(iters)), "bp_tol": MIXED_TOL,
-            "dtype": "c64 contractions in BP (FP64 storage, gates, eigh, residual)",
-            "_z": np.array(zs)}
+    return steps / wall, float(np.mean(iters)), np.array(zs), prof
+
+
+def mixed_window(lat, theta, chi, warmup, steps) -> dict:
+    """The same steps in mixed precision (FP32 BP on FP32 copies of the tensors until the FP32
+    rounding level, FP64 sweeps to MIXED_TOL), the FP64 mode at the same BP tolerance (so the
+    FP32 arithmetic's own gain is separated from the tolerance), and the roofline of the FP32
+    GEMM launches against the FP32 MFMA peak."""
+    from paper_2306_14887_amd import bpki
+
+    v32, it32, z32, prof = _window(lat, theta, chi, warmup, steps, bpki.BPKI_FP32, MIXED_TOL,
+                                   profile=True)
+    v64, it64, _, _ = _window(lat, theta, chi, warmup, steps, bpki.BPKI_FP64, MIXED_TOL)
+    p32, p64 = prof[1], prof[0]
+    a32 = p32["flops"] / (p32["ms"] * 1e-3) / 1e12 if p32["ms"] > 0 else 0.0
+    a64 = p64["flops"] / (p64["ms"] * 1e-3) / 1e12 if p64["ms"] > 0 else 0.0
+    return {"value": v32, "unit": "Floquet steps/s", "ms_per_step": 1e3 / v32,
+            "bp_sweeps_per_step": it32, "bp_tol": MIXED_TOL,
+            "dtype": "c64 BP contractions on c64 copies until the FP32 level, then c128",
+            "fp64_same_tol": {"value": v64, "bp_sweeps_per_step": it64,
+                              "mixed_speedup": v32 / v64},
+            "roofline": {"bound": "mfma", "kernel": "gemm_kernel<float> + gemm_stream_kernel<float>"
+                                                    " (FP32 launches of the window)",
+                         "achieved": a32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": a32 / FP32_PEAK_TFLOPS, "launches": p32["launches"],
+                         "avg_launch_ms": p32["ms"] / max(1, p32["launches"]),
+                         "fp64_launches": p64["launches"], "fp64_achieved": a64},
+            "_z": z32}
+
+
+def config1(chi: int = 32, depth: int = 20) -> dict:
+    """The 127-qubit lattice at chi = 32, 20 Floquet steps, FP64, at the nine theta_h of the
+    configuration (0, 0.2, ..., 1.4, pi/2): the lattice-average magnetisation after every step
+    (Fig. 3a's quantity) and the steps/s of each run."""
+    import numpy as np
+
+    from paper_2306_14887_amd import bpki
+    from paper_2306_14887_amd import lattice as L
+
+    lat = L.eagle()
+    runs = []
+    with bpki.Context(0) as ctx:
+        for th in L.theta_grid_config1():
+            t0 = time.perf_counter()
+            r = ctx.solve(bpki.spec_from_lattice(lat, th, depth, chi))
+            wall = time.perf_counter() - t0
+            runs.append({"theta_h": th, "steps_per_s": depth / wall,
+                         "bp_sweeps": int(np.sum(r["bp_iters"])),
+                         "magnetisation_per_step": [round(float(x), 8)
+                                                    for x in r["z"].mean(axis=1)],
+                         "z62_last_step": float(r["z"][-1][62])})
+    return {"lattice": "127-qubit heavy hex", "chi": chi, "steps": depth, "precision": "fp64",
+            "runs": runs,
+            "aggregate_steps_per_s": len(runs) * depth / sum(depth / r["steps_per_s"]
+                                                             for r in runs)}
 
 
 def achievable_peaks(ctx) -> dict:
@@ -343,7 +463,7 @@ def theta_batch(lat, chi: int, depth: int) -> dict:
 def precision_form(lat, chi: int, depth: int) -> dict:
     """The precision form of the workload: the eight seeded theta_h values (one serving slot
     each), with the 64 seeded Pauli strings (weight 3..17, tree clusters, X/Y/Z uniform) measured
-    after the last step, in FP64 and in mixed precision (FP32 BP contractions, BP tolerance 1e-8):
+    after the last step, in FP64 and in mixed precision (FP32 BP contractions, MIXED_TOL):
     the absolute error of every <Z_v>(t) and every string of the mixed run against the FP64 run,
     and the wall time of each batch (steps and strings)."""
     import numpy as np
@@ -403,7 +523,7 @@ def chi128_window(lat, theta: float, warmup: int = 7, steps: int = 3) -> dict:
 def infinite_lattice(chi: int, depth: int = 30) -> dict:
     """The thermodynamic limit ("Dynamics of the infinite heavy-hex lattice", Fig. 4): the 5-site
     periodic cell (degree-3 sites A, B and three bridges) at theta_h in {pi/8, pi/4, 3pi/8},
-    `depth` Floquet steps, FP64 (BP tolerance 1e-12) and mixed precision (FP32 MFMA BP, 1e-8):
+    `depth` Floquet steps, FP64 (BP tolerance 1e-12) and mixed precision (FP32 MFMA BP, MIXED_TOL):
     <Z> per sublattice per step, the bond entropies after the last step and the time per step."""
     import math
 
@@ -416,7 +536,8 @@ def infinite_lattice(chi: int, depth: int = 30) -> dict:
     thetas = [math.pi / 8, math.pi / 4, 3 * math.pi / 8]
     runs, zs = [], {}
     with bpki.Context(0) as ctx:
-        for prec, tol, name in ((bpki.BPKI_FP64, 1e-12, "fp64"), (bpki.BPKI_FP32, 1e-8, "mixed")):
+        for prec, tol, name in ((bpki.BPKI_FP64, 1e-12, "fp64"),
+                                (bpki.BPKI_FP32, MIXED_TOL, "mixed")):
             for th in thetas:
                 t0 = time.perf_counter()
                 r = ctx.solve(bpki.spec_from_lattice(cell, th, depth, chi, precision=prec,
@@ -469,7 +590,7 @@ def infinite_lattice(chi: int, depth: int = 30) -> dict:
 def infinite_lattice_chi256(depth: int) -> dict:
     """The periodic heavy-hex cell at chi = 256 (the largest bond dimension of the thermodynamic-limit
     workload; truncation eigenproblems of n = 512): theta_h = pi/4, `depth` Floquet steps, FP64
-    (BP tolerance 1e-12) and mixed precision (1e-8): <Z> per sublattice per step, the bond
+    (BP tolerance 1e-12) and mixed precision (MIXED_TOL): <Z> per sublattice per step, the bond
     entropies after the last step and the time per step over the saturated steps (9..depth)."""
     import math
 
@@ -482,7 +603,8 @@ def infinite_lattice_chi256(depth: int) -> dict:
     th = math.pi / 4
     runs, zs = [], {}
     with bpki.Context(0) as ctx:
-        for prec, tol, name in ((bpki.BPKI_FP64, 1e-12, "fp64"), (bpki.BPKI_FP32, 1e-8, "mixed")):
+        for prec, tol, name in ((bpki.BPKI_FP64, 1e-12, "fp64"),
+                                (bpki.BPKI_FP32, MIXED_TOL, "mixed")):
             sess = ctx.session(bpki.spec_from_lattice(cell, th, depth, 256, precision=prec,
                                                       bp_tol=tol))
             z, iters, sat = [], [], []
@@ -542,6 +664,21 @@ def bp_error_ring(steps: int = 5, chi: int = 4) -> dict:
             "runs": out, "seconds": time.perf_counter() - t0}
 
 
+def oracle_config1_run(chi: int = 32, theta: float = 0.8, depth: int = 20) -> dict:
+    """The oracle on one whole run of the chi = 32 configuration (127 qubits, 20 steps), BLAS at
+    all cores: Floquet steps/s of the run."""
+    from oracle import bp_tns as O
+    from paper_2306_14887_amd import lattice as L
+
+    lat = L.eagle()
+    t0 = time.perf_counter()
+    r = O.solve(lat.n_sites, lat.edges, lat.colour, theta, depth, O.Options(chi=chi))
+    wall = time.perf_counter() - t0
+    return {"chi": chi, "theta_h": theta, "steps": depth, "seconds": wall,
+            "value": depth / wall, "unit": "Floquet steps/s", "cores": _cores(),
+            "bp_sweeps": int(sum(r.bp_iters))}
+
+
 def copy_probe(mib: int) -> int:
     """8 launches of torch's device copy kernel, each reading and writing ``mib`` MiB."""
     import torch
@@ -563,8 +700,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving", type=int, default=48,
-                    help="requests in the serving measurement (0 = skip; 256 = full stream)")
+    ap.add_argument("--serving", type=int, default=256,
+                    help="requests in the serving measurement (0 = skip; 256 = the full stream)")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision window")
     ap.add_argument("--chi128", type=int, default=1,
@@ -583,6 +720,11 @@ def main() -> int:
                          "mixed; 0 = skip)")
     ap.add_argument("--bp-error", type=int, default=1,
                     help="1: also the BP error estimate on the 12-qubit ring (5 theta_h, 5 steps)")
+    ap.add_argument("--config1", type=int, default=1,
+                    help="1: also the chi = 32 configuration (9 theta_h, 20 steps, magnetisation)")
+    ap.add_argument("--cpu-config1", type=int, default=0,
+                    help="1: also time the oracle on a whole chi = 32 run (theta_h 0.8, 20 steps; "
+                         "minutes of CPU)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 8 plain device-to-device copies of MIB MiB and exit "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -681,8 +823,12 @@ def main() -> int:
         dz = np.abs(mixed.pop("_z") - np.array(zsteps))
         mixed["abs_dz_vs_fp64_max"] = float(dz.max())
         mixed["abs_dz_vs_fp64_median"] = float(np.median(dz))
+        mixed["bound"] = 1e-5
         out["mixed"] = mixed
         print("mixed-precision window done", file=sys.stderr, flush=True)
+    if args.config1:
+        out["config1"] = config1()
+        print("chi=32 configuration done", file=sys.stderr, flush=True)
     if args.chi128:
         out["chi128"] = chi128_window(lat, theta)
         print("chi=128 window done", file=sys.stderr, flush=True)
@@ -709,6 +855,8 @@ def main() -> int:
         print("serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lat, chi, theta, float(np.mean(iters)))
+        if args.cpu_config1:
+            out["cpu_baseline"]["config1_run"] = oracle_config1_run()
     print(json.dumps(out), flush=True)
     return 0
 

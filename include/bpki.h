@@ -190,13 +190,13 @@ int bpki_solve_noalloc(bpki_ctx *ctx, const bpki_problem *p, bpki_result *r);
  * which must stay valid until bpki_wait returns or bpki_poll reports done.  A problem that can
  * never fit the budget is rejected with -4 by bpki_submit.
  *
- * Cross-request packing: when a slot takes a problem with chi <= max_chi and depth >= 1 while at
- * least as many problems as there are slots are queued, it also takes (in arrival order, within
- * the budget) up to max_requests - 1 queued problems on the same lattice (identical n_sites,
- * edges and resolved colours) with the same chi, precision, bp_tol, bp_max_iter and cutoffs and
- * a depth no larger than its own; theta_h, Pauli strings and record_every_step may differ.  The
- * pack is solved as one problem on the disjoint union of the lattices, so each launch of a gate
- * layer or BP sweep covers all members (small-chi requests are launch-bound alone).  Each member
+ * Cross-request packing: when a slot takes a problem with chi <= max_chi and depth >= 1 while more
+ * problems are queued than other slots are idle (so some would wait anyway), it also takes (in
+ * arrival order, within the budget) up to max_requests - 1 queued problems with the same chi,
+ * precision, bp_tol, bp_max_iter and cutoffs and a depth no larger than its own; the lattices,
+ * theta_h, Pauli strings and record_every_step may differ.  The pack is solved as one problem on
+ * the disjoint union of the lattices, so each launch of a gate layer or BP sweep covers all
+ * members (small-chi requests are launch-bound alone).  Each member
  * keeps its own BP stopping point (its messages are frozen once its own residual is below
  * bp_tol) and its result is written when its own last step is done; bp_iters reports its own
  * sweeps.  A packed member's result equals its solve alone up to rounding (launch-size dependent
@@ -300,6 +300,10 @@ int bpki_session_last_timing(const bpki_session *s, double *ms4);
 int bpki_session_profile(bpki_session *s, int stride);
 int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, double *flops,
                               int64_t *all_launches);
+/* The same restricted to the bracketed GEMM launches of one arithmetic, prec 0 = FP64 MFMA,
+ * 1 = FP32 MFMA (a mixed-precision session runs both): their count, summed ms and summed flops. */
+int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int64_t *launches, double *ms,
+                                   double *flops);
 
 #ifdef __cplusplus
 }

@@ -113,6 +113,8 @@ def load(path: str | None = None):
         "bpki_session_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_clifford_inverse_step": (C.c_int, [vp, dp, ip, dp, dp]),
         "bpki_session_last_timing": (C.c_int, [vp, dp]),
+        "bpki_session_profile_read_prec": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64), dp,
+                                                      dp]),
         "bpki_session_profile": (C.c_int, [vp, C.c_int]),
         "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp,
                                                  C.POINTER(C.c_int64)]),
@@ -147,7 +149,7 @@ def exported_symbols() -> list[str]:
             "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_clifford_inverse_step",
             "bpki_session_last_timing", "bpki_session_profile",
-            "bpki_session_profile_read", "bpki_test_gemm",
+            "bpki_session_profile_read", "bpki_session_profile_read_prec", "bpki_test_gemm",
             "bpki_test_eigh", "bpki_test_gram_chol", "bpki_test_mfma_rate"]
 
 
@@ -567,6 +569,13 @@ class Session:
                                                             C.byref(fl), C.byref(a)))
         return {"launches": n.value, "ms": ms.value, "flops": fl.value,
                 "all_launches": a.value}
+
+    def profile_read_prec(self, prec: int):
+        """The bracketed GEMM launches of one arithmetic (0 FP64, 1 FP32 MFMA)."""
+        n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
+        _check(self.lib, self.lib.bpki_session_profile_read_prec(self.h, prec, C.byref(n),
+                                                                 C.byref(ms), C.byref(fl)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value}
 
     def last_timing(self) -> np.ndarray:
         t = np.zeros(4)

@@ -231,7 +231,8 @@ struct bpki_ctx {
   std::condition_variable cv, done_cv;
   bool stop = false;
   size_t used = 0;
-  int running = 0;
+  int running = 0;                  // requests on the device (a pack counts each member)
+  int busy = 0;                     // slots working
   uint64_t next_ticket = 1;
   // sessions run on `be`: the context is deleted when it has been destroyed and the last of its
   // sessions is closed, whichever comes second
@@ -685,6 +686,15 @@ extern "C" int bpki_session_profile_read(bpki_session *s, int64_t *launches, dou
   return sess_check(s);
 }
 
+extern "C" int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int64_t *launches,
+                                              double *ms, double *flops) {
+  if (!s || (prec != 0 && prec != 1)) return fail(-1, "bad argument");
+  long l = 0;
+  s->ctx->be->gemm_profile_read_prec(prec, &l, ms, flops);
+  if (launches) *launches = l;
+  return sess_check(s);
+}
+
 extern "C" int bpki_session_last_timing(const bpki_session *s, double *ms4) {
   if (!s || !ms4) return fail(-1, "NULL argument");
   for (int i = 0; i < 4; ++i) ms4[i] = s->timing[i];
@@ -716,11 +726,15 @@ struct bpki_ctx::Job {
 // members keep their own X angles, depths and Pauli strings; each member's messages are frozen
 // once its own BP residual is below the tolerance (Engine::bp_members), so every member follows
 // the schedule of a solve of its own, and its result is written as soon as its last step is done.
+// Requests that share one launch set: the same chi (the layout is padded to one chi and the
+// truncation keeps at most chi values), precision, BP tolerance and cutoffs; the lattices may
+// differ (each member is a connected component of the union graph, so its gate layers and BP
+// schedule are the ones it has alone).
 static bool packable(const Problem &a, const Problem &b) {
-  return a.n_sites == b.n_sites && a.chi == b.chi && a.precision == b.precision &&
-         a.bp_tol == b.bp_tol && a.bp_max_iter == b.bp_max_iter && a.svd_cutoff == b.svd_cutoff &&
+  return a.chi == b.chi && a.precision == b.precision && a.bp_tol == b.bp_tol &&
+         a.bp_max_iter == b.bp_max_iter && a.svd_cutoff == b.svd_cutoff &&
          a.eig_cutoff == b.eig_cutoff && b.depth >= 1 && a.clifford_steps == 0 &&
-         b.clifford_steps == 0 && a.edges == b.edges && a.colour == b.colour;
+         b.clifford_steps == 0;
 }
 
 static Problem pack_problem(const std::vector<const Problem *> &qs, std::vector<int> *pauli0) {
@@ -958,11 +972,11 @@ static void slot_loop(bpki_ctx *c, int slot) {
       }
       pack.assign(1, job);
       size_t bytes = job->bytes;
-      // pack only from a backlog (more queued requests than slots: otherwise the idle slots
+      // pack only requests that would otherwise wait (more queued than idle slots, which would
       // run them concurrently), and only companions that end no later than the head
+      const int idle = c->n_slots - c->busy - 1;
       if (c->pack_max > 1 && job->q.chi <= c->pack_max_chi && job->q.depth >= 1 &&
-          job->q.clifford_steps == 0 &&
-          (int)c->queue.size() >= c->n_slots) {
+          job->q.clifford_steps == 0 && (int)c->queue.size() > idle) {
         for (auto it = c->queue.begin();
              it != c->queue.end() && (int)pack.size() < c->pack_max;) {
           const auto &h = *it;
@@ -978,6 +992,7 @@ static void slot_loop(bpki_ctx *c, int slot) {
       }
       c->used += bytes;
       c->running += (int)pack.size();
+      c->busy += 1;
       const double t0 = now_s();
       for (auto &m : pack) {
         m->t_start = t0;
@@ -1016,6 +1031,7 @@ static void slot_loop(bpki_ctx *c, int slot) {
       std::lock_guard<std::mutex> lk(c->mu);
       c->used -= pack_bytes;
       c->running -= (int)pack.size();
+      c->busy -= 1;
     }
     c->cv.notify_all();
   }

@@ -72,6 +72,8 @@ struct Backend {
   // launches are counted).  read: bracketed launches, all launches, their ms and 8MNK flops.
   virtual void gemm_profile(int stride) = 0;
   virtual void gemm_profile_read(long *sampled, long *all, double *ms, double *flops) = 0;
+  // the same for the bracketed launches of one arithmetic (0 FP64 MFMA, 1 FP32 MFMA)
+  virtual void gemm_profile_read_prec(int prec, long *sampled, double *ms, double *flops) = 0;
 
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,

@@ -2735,7 +2735,9 @@ class HipBackend : public Backend {
       if (rec) {
         HIPCHK(hipEventRecord(e1, s_));
         prof_ev_.push_back({e0, e1});
+        prof_prec_.push_back(d.prec);
         prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
+        prof_flops_p_[d.prec & 1] += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
       }
       return;
     }
@@ -2795,9 +2797,11 @@ class HipBackend : public Backend {
     if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
+      prof_prec_.push_back(d.prec);
       // algorithmic work: the distinct entries (a Hermitian output has M (M + 1) / 2)
       const double outs = d.herm ? 0.5 * d.M * (d.M + 1.0) : (double)d.M * d.N;
       prof_flops_ += 8.0 * outs * (double)d.K * d.batch * nprob;
+      prof_flops_p_[d.prec & 1] += 8.0 * outs * (double)d.K * d.batch * nprob;
     }
     if (ksplit > 1) {
       int bx = std::min(64, (int)((d.M * (size_t)d.N + 255) / 256));
@@ -2834,6 +2838,10 @@ class HipBackend : public Backend {
       prof_all_ = 0;
       prof_ms_ = 0;
       prof_flops_ = 0;
+      for (int q = 0; q < 2; ++q) {
+        prof_launches_p_[q] = 0;
+        prof_ms_p_[q] = prof_flops_p_[q] = 0;
+      }
     }
   }
   void gemm_profile_read(long *sampled, long *all, double *ms, double *flops) override {
@@ -2843,17 +2851,29 @@ class HipBackend : public Backend {
     if (ms) *ms = prof_ms_;
     if (flops) *flops = prof_flops_;
   }
+  void gemm_profile_read_prec(int prec, long *sampled, double *ms, double *flops) override {
+    drain_profile();
+    const int q = prec & 1;
+    if (sampled) *sampled = prof_launches_p_[q];
+    if (ms) *ms = prof_ms_p_[q];
+    if (flops) *flops = prof_flops_p_[q];
+  }
   void drain_profile() {
-    for (auto &pr : prof_ev_) {
+    for (size_t i = 0; i < prof_ev_.size(); ++i) {
+      auto &pr = prof_ev_[i];
       HIPCHK(hipEventSynchronize(pr.second));
       float ms = 0;
       HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
       prof_ms_ += ms;
       prof_launches_ += 1;
+      const int q = prof_prec_[i] & 1;
+      prof_ms_p_[q] += ms;
+      prof_launches_p_[q] += 1;
       HIPCHK(hipEventDestroy(pr.first));
       HIPCHK(hipEventDestroy(pr.second));
     }
     prof_ev_.clear();
+    prof_prec_.clear();
   }
   // Blocked Householder reduction (n > 256): panels of TRD_NB reflectors, each followed by the
   // two GEMMs A_st -= V W^H + W V^H on every matrix, then the last diagonal entry.
@@ -3324,6 +3344,10 @@ class HipBackend : public Backend {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev_;
   long prof_launches_ = 0, prof_all_ = 0;
   double prof_ms_ = 0, prof_flops_ = 0;
+  // the same sums by arithmetic of the bracketed launches (0 FP64 MFMA, 1 FP32 MFMA)
+  std::vector<int> prof_prec_;
+  long prof_launches_p_[2] = {0, 0};
+  double prof_ms_p_[2] = {0, 0}, prof_flops_p_[2] = {0, 0};
 };
 
 // Device memory of the allocation-free solve (bpki_solve_noalloc): a fixed array in the code

@@ -98,6 +98,36 @@ def test_packed_requests_match_alone():
     assert np.abs(o["pauli"] - ref.pauli).max() < 1e-8
 
 
+def test_requests_on_different_lattices_pack_together():
+    """Queued requests with the same chi on lattices of 29, 65 and 127 qubits are packed into one
+    solve on the union graph; each equals its solve alone (to rounding), bond dimensions included."""
+    from paper_2306_14887_amd import bpki as B
+    print("[serving] packing across lattices", flush=True)
+    lats = [L.heavy_hex(3, 9), L.heavy_hex(5, 11), L.eagle(), L.heavy_hex(3, 9)]
+    specs = [B.spec_from_lattice(lat, 0.5 + 0.2 * i, 6 - (i % 2), 8)
+             for i, lat in enumerate(lats)]
+    with B.Context() as ctx:
+        ctx.serving_config(1)
+        blocker = ctx.submit(B.spec_from_lattice(L.heavy_hex(5, 11), 0.7, 4, 16))
+        order = sorted(range(len(specs)), key=lambda i: -specs[i].depth)
+        tickets = [None] * len(specs)
+        for i in order:
+            tickets[i] = ctx.submit(specs[i])
+        blocker.wait()
+        while not all(t.poll() for t in tickets):
+            time.sleep(0.002)
+        packs = [t.pack_size() for t in tickets]
+        outs = [t.wait() for t in tickets]
+    assert min(packs) == len(specs)
+    with B.Context() as ctx:
+        for s, o in zip(specs, outs):
+            alone = ctx.solve(s)
+            assert o["status"] == alone["status"] == 0
+            assert np.abs(o["z"] - alone["z"]).max() < 1e-10
+            assert np.array_equal(o["bond_dims"], alone["bond_dims"])
+            assert np.abs(o["discarded"] - alone["discarded"]).max() < 1e-10
+
+
 def test_budget_admission_and_overlap():
     from paper_2306_14887_amd import bpki as B
     import ctypes as C
