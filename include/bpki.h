@@ -50,17 +50,20 @@ extern "C" {
 
 typedef struct bpki_ctx bpki_ctx;
 
-/* Arithmetic of the bulk contractions.  Storage, the gate updates (including the truncation SVD
- * and the message square roots and inverse square roots), the BP residual and the observables'
- * final ratios are FP64 in every mode.
- * BPKI_FP32: the BP message contractions and the observables' contractions run on FP32 MFMA
- * (operands rounded to FP32, FP32 accumulation per K chunk, FP64 chunk sums).  BP sweeps in FP32
- * until the residual reaches 2e-6, then in FP64 if bp_tol asks for less, so the fixed point is the
- * FP64 one.  With bp_tol = 1e-8 the largest measured deviation of a <Z> from the FP64 mode
- * (bp_tol 1e-12) on the seeded serving stream (heavy-hex lattices of 29, 65 and 127 qubits,
- * chi 8..64, up to 20 steps) is 3e-7 over its first 48 requests and 1.1e-5 over all 256.  Looser
- * tolerances trade accuracy for speed: with bp_tol = 1e-6 a near-Clifford chi = 8 request
- * deviated by 5e-5. */
+/* Arithmetic of the bulk contractions.  The state, the gate updates (including the truncation
+ * SVD and the message square roots and inverse square roots), the messages, the BP residual and
+ * the observables' final ratios are FP64 in every mode.
+ * BPKI_FP32: the BP sweeps run on FP32 MFMA over FP32 copies of the site tensors (made once per
+ * new state) with FP32 intermediates, FP32 accumulation per K chunk and FP64 chunk sums, until
+ * the residual reaches the FP32 rounding level (2e-6, or a sweep within 100x of it that gains less
+ * than 10%); then FP64 sweeps run to bp_tol, so the fixed point is the FP64 one.  The
+ * observables' contractions use FP32 MFMA on the FP64 state.
+ * Stated bound: with bp_tol <= 1e-10, every <Z> is within 1e-5 of the FP64 mode (bp_tol 1e-12).
+ * Measured: largest deviation 5.0e-7 over the 256 requests of the seeded serving stream
+ * (heavy-hex lattices of 29, 65 and 127 qubits, chi 8..64, up to 20 steps, served with packing)
+ * and 8e-8 on the 127-qubit chi = 64 lattice; with bp_tol = 1e-8 a request 0.0008 from the
+ * Clifford point (flat Schmidt spectra, near-degenerate cuts) deviated by 1.6e-5, so looser
+ * tolerances are outside the bound. */
 typedef enum {
   BPKI_FP64 = 0,   /* everything FP64 (the parity mode)                                     */
   BPKI_FP32 = 1    /* FP32 MFMA contractions in BP sweeps and observables (see above)       */
