@@ -394,13 +394,15 @@ static int run_solve(Backend *be, Engine &eng, const Problem &q, bpki_result *r,
   if (r->z) std::memcpy(r->z, z.data(), (size_t)rows * n * sizeof(double));
   if (!ent.empty()) std::memcpy(r->bond_entropy, ent.data(), ent.size() * sizeof(double));
   if (r->pauli && !pv.empty()) std::memcpy(r->pauli, pv.data(), pv.size() * sizeof(double));
-  if (r->bp_iters) std::memcpy(r->bp_iters, iters.data(), iters.size() * sizeof(int32_t));
-  if (r->bp_residual) std::memcpy(r->bp_residual, res.data(), res.size() * sizeof(double));
-  if (r->discarded) std::memcpy(r->discarded, disc.data(), disc.size() * sizeof(double));
+  if (steps > 0) {                  // the per-step arrays are empty for a zero-step solve
+    if (r->bp_iters) std::memcpy(r->bp_iters, iters.data(), iters.size() * sizeof(int32_t));
+    if (r->bp_residual) std::memcpy(r->bp_residual, res.data(), res.size() * sizeof(double));
+    if (r->discarded) std::memcpy(r->discarded, disc.data(), disc.size() * sizeof(double));
+    if (r->min_cut_gap) std::memcpy(r->min_cut_gap, gap.data(), gap.size() * sizeof(double));
+    if (r->degenerate_cuts)
+      std::memcpy(r->degenerate_cuts, ndeg.data(), ndeg.size() * sizeof(int32_t));
+  }
   if (r->bond_dims) std::memcpy(r->bond_dims, bdim.data(), bdim.size() * sizeof(int32_t));
-  if (r->min_cut_gap) std::memcpy(r->min_cut_gap, gap.data(), gap.size() * sizeof(double));
-  if (r->degenerate_cuts)
-    std::memcpy(r->degenerate_cuts, ndeg.data(), ndeg.size() * sizeof(int32_t));
   return warn;
 }
 
