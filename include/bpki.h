@@ -276,10 +276,18 @@ int bpki_session_vidal_gauge(bpki_session *s, double *lambda);
  * bpki_session_vidal_gauge, left so afterwards), the norm network is cut along the edge and the
  * rest contracted exactly into the chi^2 x chi^2 edge environment E, and
  * error = 1 - sqrt(s_1^2 / sum_i s_i^2) over the singular values s_i of E (0 when the environment
- * is rank one, as BP assumes).  Built for ring lattices (every site of degree 2, connected: the
- * contraction is the chain of the sites' norm transfer matrices) with chi <= 16; other graphs or
- * larger chi return -1.  spectrum: [chi^2] host, s_i / ||s|| descending, or NULL.  Allocates
- * its work buffers (n + 4 matrices of chi^4 complex) for the call. */
+ * is rank one, as BP assumes).  Built for chi <= 16 and three kinds of network, with the rest
+ * returning -1:
+ *   - `edge` a bridge (its removal disconnects the network): E is an outer product, error 0 and
+ *     spectrum (1, 0, ...);
+ *   - networks whose 2-core (what remains after removing sites of degree 1 repeatedly) is one
+ *     loop, such as one heavy hexagon with or without pendant sites: the branches are contracted
+ *     into the loop sites' chi^2 x chi^2 norm transfer matrices and E is their open chain;
+ *   - networks whose 2-core is two junction sites joined by three paths, such as two heavy
+ *     hexagons sharing a side: the three path chains and the two junction tensors are contracted
+ *     exactly (chi^8 complex multiply-adds).
+ * spectrum: [chi^2] host, s_i / ||s|| descending, or NULL.  Allocates its work buffers for the
+ * call (up to 4 chi^6 complex, 1.1 GB at chi = 16, for the two-junction case). */
 int bpki_session_bp_error(bpki_session *s, int32_t edge, double *error, double *spectrum);
 int bpki_session_observe_pauli(bpki_session *s, double *pauli);
 /* One whole Floquet step: X rotations, all gate layers, BP, then z (may be NULL). */

@@ -595,11 +595,13 @@ extern "C" int bpki_session_bp_error(bpki_session *s, int32_t edge, double *erro
   if (!s || !error) return fail(-1, "NULL argument");
   const Problem &q = s->eng->problem();
   if (edge < 0 || edge >= (int)q.edges.size() / 2) return fail(-1, "edge out of range");
-  if (!s->eng->is_ring()) return fail(-1, "the BP error estimate is built for ring lattices");
   if (q.chi > 16) return fail(-1, "the BP error estimate needs chi <= 16 (chi^2 <= 256)");
   const double err = s->eng->bp_error(edge, spectrum);
   int rc = sess_check(s);
   if (rc < 0) return rc;
+  if (err == -1.0)
+    return fail(-1, "the BP error estimate is built for bridges and for networks whose 2-core is "
+                    "one loop or two junctions joined by three paths");
   if (!std::isfinite(err)) return fail(-5, "BP error estimate: zero norm or allocation failure");
   *error = err;
   return 0;

@@ -7,6 +7,8 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -93,16 +95,12 @@ struct Backend {
   // Entropy -sum p log2 p of the Schmidt weights p = max(evals, 0) / sum (n per problem); out
   // [nprob] device, NaN for an all-zero spectrum.
   virtual void bond_entropy(int n, const double *const *evals, double *out, int nprob) = 0;
+  // out[0..1] = trace of the n x n complex matrix R (device).
+  virtual void trace(const double *R, int n, double *out) = 0;
   // Symmetric Vidal gauge factors of nprob edges from the eigenpairs of C^H C (C = X^T Y):
   // D1 = V diag(s^{1/2} / lambda), D2 = conj(V) diag(s^{1/2}) (s = lambda above cut * lambda_1,
   // unit 2-norm), both messages of the edge set to diag(s) / sum(s); lam [nprob][n] = s,
   // kept [nprob] (device).
-  // out[0..1] = trace of the n x n complex matrix R (device).
-  virtual void trace(const double *R, int n, double *out) = 0;
-  // Norm transfer matrices of degree-2 sites, F [chi^2][chi^2] per problem (flip: legs swapped),
-  // each multiplied by scale[p] (device).
-  virtual void transfer(int chi, const double *const *T, const int *flip, const double *scale,
-                        double *const *F, int nprob) = 0;
   virtual void vidal_svd(int n, const double *const *evals, const double *const *vecs,
                          double *const *D1, double *const *D2, double *const *Mu,
                          double *const *Mv, double *lam, int *kept, double cut, int nprob) = 0;
@@ -183,6 +181,7 @@ struct Problem {
 
 // Host-side graph plan (degrees, neighbours, layers) and device workspace sizes.
 struct Plan;
+struct EngineScratch;      // device buffers of one host-driven contraction
 
 class Engine {
  public:
@@ -202,8 +201,9 @@ class Engine {
   void observe_pauli_range(int k0, int k1, double *out);   // strings k0 .. k1-1
   void observe_entropy(double *out);              // host out [n_edges]: bond entropies (bits)
   void vidal_gauge(double *lambda);               // in place; host out [n_edges][chi] or NULL
-  bool is_ring() const;                           // connected, every site of degree 2
-  // BP error estimate on edge e of a ring (symmetric gauge first); spectrum [chi^2] or NULL
+  // BP error estimate on edge e (symmetric gauge first); spectrum [chi^2] or NULL.  Built for
+  // bridges, networks whose 2-core is one loop and networks whose 2-core is two junction sites
+  // joined by three paths; -1 for other networks.
   double bp_error(int e, double *spectrum);
   // Packed solves: sweeps until every member's residual is below bp_tol.  A member's messages
   // are frozen after the sweep that brought its own residual below the tolerance, so each member
@@ -240,6 +240,19 @@ class Engine {
   int su_prec() const { return 0; }
   void build();
   double pauli_value(int k, bool with_ops);
+  // Pieces of the host-driven exact contractions (Pauli strings, BP error estimate).
+  struct OpenLeg {                // chi^2 matrices X_x[a][a'] = base[x sx + a sk + a' sn]
+    const double *base;
+    long sx, sk, sn;
+  };
+  double *site_ket(int v, int opcode, EngineScratch &S);
+  double *branch_env(int v, int parent, const std::set<int> &cs, const std::map<int, int> &op,
+                     EngineScratch &S);
+  void site_transfer(int v, int prev, int next, const std::set<int> &cs,
+                     const std::map<int, int> &op, EngineScratch &S, double *dst,
+                     const OpenLeg *open);
+  std::vector<int> cycle_of(const std::set<int> &cs) const;
+  double *chain(const std::vector<int> &walk, int before, int after, EngineScratch &S);
 };
 
 }  // namespace bpki

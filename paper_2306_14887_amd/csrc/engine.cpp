@@ -1384,114 +1384,245 @@ void Engine::vidal_gauge(double *lambda) {
   if (lambda) be_->d2h(lambda, P.vg_lam, (size_t)P.E * chi * 8);
 }
 
-bool Engine::is_ring() const {
-  const Plan &P = *plan_;
-  if (P.n < 3 || P.E != P.n) return false;
-  for (int v = 0; v < P.n; ++v)
-    if (P.deg[v] != 2) return false;
-  int prev = -1, cur = 0, steps = 0;
-  do {
-    const int next = P.nb[cur][0] != prev ? P.nb[cur][0] : P.nb[cur][1];
-    prev = cur;
-    cur = next;
-    ++steps;
-  } while (cur != 0 && steps <= P.n);
-  return steps == P.n;
+// C = A B for chi^2 x chi^2 matrices (row-major).
+static GemmDesc square_desc(long n) {
+  GemmDesc c;
+  c.M = c.N = c.K = c.Mi = c.Ni = c.Ki = (int)n;
+  c.a_mi = n; c.a_ki = 1;
+  c.b_ki = n; c.b_ni = 1;
+  c.c_mi = n; c.c_ni = 1;
+  return c;
 }
 
-// BP error estimate (Eq. "BPErrorEstimate") on edge e = (u, v) of a ring, in the symmetric gauge
-// (vidal_gauge first).  Cutting the edge leaves an open chain of norm transfer matrices: walking
-// from v away from u around to u, E = F_v ... F_u (chi^2 x chi^2: v's side of the cut as rows,
-// u's as columns).  The singular values come from eigh(E^H E); the estimate is
-// 1 - sqrt(s_1^2 / sum s_i^2).  Work buffers are allocated for the call (chi^2 <= 256).
+// Device buffers of one host-driven contraction (a Pauli string, a BP error estimate): allocated
+// for the call, released (after the stream drains) at its end.  Single-problem launches take
+// their pointer triple through one small device array, rewritten in stream order.
+struct EngineScratch {
+  Backend *be;
+  int prec;                       // GemmDesc::prec of every contraction
+  std::vector<void *> bufs;
+  void **parr = nullptr;
+  EngineScratch(Backend *b, int precision) : be(b), prec(precision) {
+    parr = (void **)be->alloc(3 * sizeof(void *));
+    bufs.push_back(parr);
+  }
+  ~EngineScratch() {
+    be->sync();
+    for (void *q : bufs) be->release(q);
+  }
+  double *alloc(size_t elems) {
+    void *q = be->alloc(elems * 16);
+    bufs.push_back(q);
+    return (double *)q;
+  }
+  // a device array holding the given pointers
+  void **ptrs(const std::vector<const void *> &v) {
+    void **q = (void **)be->alloc(std::max<size_t>(1, v.size()) * sizeof(void *));
+    bufs.push_back(q);
+    be->h2d(q, v.data(), v.size() * sizeof(void *));
+    return q;
+  }
+  void gemm(GemmDesc d, const std::vector<const void *> &a, const std::vector<const void *> &b,
+            const std::vector<const void *> &c) {
+    d.prec = prec;
+    void **pa = ptrs(a), **pb = ptrs(b), **pc = ptrs(c);
+    be->gemm(d, (const double *const *)pa, (const double *const *)pb, (double *const *)pc,
+             (int)a.size());
+  }
+  void gemm1(GemmDesc d, const double *a, const double *b, double *c) {
+    d.prec = prec;
+    const void *h[3] = {a, b, c};
+    be->h2d(parr, h, sizeof(h));
+    be->gemm(d, (const double *const *)parr, (const double *const *)(parr + 1),
+             (double *const *)(parr + 2), 1);
+  }
+};
+
+// BP error estimate (Eq. "BPErrorEstimate") on edge e = (u, v), in the symmetric gauge
+// (vidal_gauge first): the norm network with the edge cut and every other bond contracted exactly
+// is the chi^2 x chi^2 edge environment E; with s_i its singular values the estimate is
+// 1 - sqrt(s_1^2 / sum s_i^2).  The singular values come from eigh(E^H E).
+// * e a bridge: E is an outer product, the estimate 0 and the spectrum (1, 0, ...).
+// * The 2-core of the network (what is left after removing sites of degree 1 repeatedly) one
+//   loop: the branches fold into the transfer matrices of the loop sites, and E is the open chain
+//   F_v ... F_u walking from v around the loop to u.
+// * The 2-core two junction sites a, b joined by three paths (two heavy hexagons sharing a side),
+//   the cut on one of them: Q_u is the chain from a to u on that path, Q_v the chain from v to b,
+//   M_1 and M_2 the chains along the other two paths from a to b.  G_a(x) is a's transfer matrix
+//   between its legs to M_1 and M_2 with its third leg closed with column x of Q_u, G_b(y) the same
+//   at b with row y of Q_v, and E[x][y] = sum_jk (M_1^T G_a(x) M_2)[j][k] G_b(y)[j][k].
+// Other networks return -1.  Each transfer matrix is divided by ||T||^2 (positive factors leave
+// the estimate unchanged).
 double Engine::bp_error(int e, double *spectrum) {
   Plan &P = *plan_;
   vidal_gauge(nullptr);
-  const int chi = P.chi, n = P.n, c2 = chi * chi;
-  const size_t c4 = (size_t)c2 * c2;
+  const int chi = P.chi, n = P.n;
+  const long c2 = (long)chi * chi;
+  const long c4 = c2 * c2;
   const int u = prob_.edges[2 * e], v = prob_.edges[2 * e + 1];
-  // walk: w_0 = v (coming from u), ..., w_{n-1} = u
-  std::vector<int> walk{v}, flip;
-  std::vector<int> from{u};
-  while ((int)walk.size() < n) {
-    const int w = walk.back(), pw = from.back();
-    const int nx = P.nb[w][0] != pw ? P.nb[w][0] : P.nb[w][1];
-    from.push_back(w);
-    walk.push_back(nx);
+  auto unit = [&]() {
+    if (spectrum)
+      for (long i = 0; i < c2; ++i) spectrum[i] = i == 0 ? 1.0 : 0.0;
+    return 0.0;
+  };
+  // a bridge: v is not reached from u without the edge
+  {
+    std::vector<char> seen(n, 0);
+    std::vector<int> st{u};
+    seen[u] = 1;
+    while (!st.empty()) {
+      const int w = st.back();
+      st.pop_back();
+      for (int x : P.nb[w])
+        if (!seen[x] && !((w == u && x == v) || (w == v && x == u))) {
+          seen[x] = 1;
+          st.push_back(x);
+        }
+    }
+    if (!seen[v]) return unit();
   }
-  // buffers: n transfer matrices, two chain products, E^H E, eigenpairs; pointer arrays
-  const size_t mat = c4 * 16;
-  const size_t nptr = 5 * (size_t)n + 8;
-  char *buf = (char *)be_->alloc(mat * (n + 4) + (size_t)c2 * 8 + nptr * sizeof(void *) +
-                                 (size_t)n * 12);
-  if (!buf) return NAN;
-  auto M_ = [&](int i) { return (double *)(buf + mat * i); };
-  double *R0 = M_(n), *R1 = M_(n + 1), *H = M_(n + 2), *V = M_(n + 3);
-  double *ev = (double *)(buf + mat * (n + 4));
-  const void **pp = (const void **)((char *)ev + (size_t)c2 * 8);
-  double *sc = (double *)((char *)pp + nptr * sizeof(void *));
-  int *fl = (int *)(sc + n);
-  std::vector<const void *> ptrs;
-  std::vector<int> flips;
-  // each transfer matrix is divided by ||T_w||^2 (positive factors leave the estimate unchanged
-  // and keep the product of n of them in range)
-  std::vector<double> scales(n), th((size_t)2 * P.tsize[walk[0]]);
-  for (int k = 0; k < n; ++k) {
-    const int w = walk[k];
-    ptrs.push_back(P.T + 2 * P.toff[w]);
-    flips.push_back(P.nb[w][0] != from[k] ? 1 : 0);     // incoming leg is T's leg 1
-    be_->d2h(th.data(), P.T + 2 * P.toff[w], (size_t)P.tsize[w] * 16);
-    double nrm2 = 0.0;
-    for (double x : th) nrm2 += x * x;
-    scales[k] = nrm2 > 0.0 ? 1.0 / nrm2 : 1.0;
+  // the 2-core and its junctions
+  std::vector<int> cdeg(n);
+  for (int w = 0; w < n; ++w) cdeg[w] = P.deg[w];
+  std::vector<char> core(n, 1);
+  {
+    std::vector<int> leaves;
+    for (int w = 0; w < n; ++w)
+      if (cdeg[w] <= 1) leaves.push_back(w);
+    while (!leaves.empty()) {
+      const int w = leaves.back();
+      leaves.pop_back();
+      if (!core[w]) continue;
+      core[w] = 0;
+      for (int x : P.nb[w])
+        if (core[x] && --cdeg[x] == 1) leaves.push_back(x);
+    }
   }
-  for (int k = 0; k < n; ++k) ptrs.push_back(M_(k));
-  // chain: R_1 = F_0 F_1, R_k = R_{k-1} F_k (ping-pong), then E^H E, then eigh in/out
-  const size_t chain0 = ptrs.size();
-  double *prev = M_(0);
-  for (int k = 1; k < n; ++k) {
-    double *out = (k & 1) ? R0 : R1;
-    ptrs.push_back(prev);
-    ptrs.push_back(M_(k));
-    ptrs.push_back(out);
-    prev = out;
+  std::vector<int> junctions;
+  int ncore = 0;
+  for (int w = 0; w < n; ++w) {
+    if (!core[w]) continue;
+    ++ncore;
+    if (cdeg[w] == 3) junctions.push_back(w);
+    else if (cdeg[w] != 2) return -1.0;
   }
-  const size_t herm0 = ptrs.size();
-  ptrs.push_back(prev);
-  ptrs.push_back(prev);
-  ptrs.push_back(H);
-  ptrs.push_back(H);
-  ptrs.push_back(ev);
-  ptrs.push_back(V);
-  be_->h2d(pp, ptrs.data(), ptrs.size() * sizeof(void *));
-  be_->h2d(fl, flips.data(), flips.size() * 4);
-  be_->h2d(sc, scales.data(), scales.size() * 8);
-  auto at = [&](size_t i) { return (const double *const *)(pp + i); };
-  auto atw = [&](size_t i) { return (double *const *)(pp + i); };
-  be_->transfer(chi, at(0), fl, sc, atw(n), n);
-  GemmDesc d;
-  d.M = d.N = d.K = d.Mi = d.Ni = d.Ki = c2;
-  d.a_mi = c2; d.a_ki = 1;
-  d.b_ki = c2; d.b_ni = 1;
-  d.c_mi = c2; d.c_ni = 1;
-  for (int k = 1; k < n; ++k) {
-    const size_t o = chain0 + 3 * (size_t)(k - 1);
-    be_->gemm(d, at(o), at(o + 1), atw(o + 2), 1);
+  // walk along core sites of core degree 2 from `from` through `first` to the next junction (or
+  // back to `from`): the interior sites and the end
+  auto walk_path = [&](int from, int first, std::vector<int> *inner) {
+    int prev = from, w = first;
+    while (cdeg[w] == 2 && w != from) {
+      inner->push_back(w);
+      int nx = -1;
+      for (int x : P.nb[w])
+        if (core[x] && x != prev) nx = x;
+      prev = w;
+      w = nx;
+    }
+    return w;
+  };
+  EngineScratch S(be_, 0);
+  double *E = nullptr;
+  if (junctions.empty()) {
+    // one loop (the 2-core is connected: the network is, or the edge would have been a bridge
+    // inside a tree component)
+    std::vector<int> loop;
+    const int end = walk_path(u, v, &loop);
+    if (end != u || (int)loop.size() + 1 != ncore) return -1.0;
+    loop.push_back(u);
+    E = chain(loop, u, v, S);                   // F_v ... F_u
+  } else if (junctions.size() == 2) {
+    const int a = junctions[0], b = junctions[1];
+    std::vector<std::vector<int>> paths;
+    int covered = 2;
+    for (int x : P.nb[a]) {
+      if (!core[x]) continue;
+      std::vector<int> inner;
+      if (walk_path(a, x, &inner) != b) return -1.0;
+      covered += (int)inner.size();
+      paths.push_back(inner);
+    }
+    if (paths.size() != 3 || covered != ncore) return -1.0;
+    // the path of the cut, as a = s_0, s_1, ..., s_L = b, cut between s_t and s_{t+1}
+    int pc = -1, t = -1;
+    for (int k = 0; k < 3 && pc < 0; ++k) {
+      std::vector<int> s{a};
+      s.insert(s.end(), paths[k].begin(), paths[k].end());
+      s.push_back(b);
+      for (int i = 0; i + 1 < (int)s.size(); ++i)
+        if ((s[i] == u && s[i + 1] == v) || (s[i] == v && s[i + 1] == u)) {
+          pc = k;
+          t = i;
+        }
+    }
+    if (pc < 0) return -1.0;
+    std::vector<int> sp{a};
+    sp.insert(sp.end(), paths[pc].begin(), paths[pc].end());
+    sp.push_back(b);
+    const int L = (int)sp.size() - 1;
+    std::vector<int> wu(sp.begin() + 1, sp.begin() + t + 1);        // s_1 .. s_t
+    std::vector<int> wv(sp.begin() + t + 1, sp.begin() + L);        // s_{t+1} .. s_{L-1}
+    double *Qu = chain(wu, a, sp[t + 1], S);     // rows: a's cut-path leg, cols: cut (s_t side)
+    double *Qv = chain(wv, sp[t], b, S);         // rows: cut (s_{t+1} side), cols: b's leg
+    const std::vector<int> &p1 = paths[(pc + 1) % 3], &p2 = paths[(pc + 2) % 3];
+    double *M1 = chain(p1, a, b, S), *M2 = chain(p2, a, b, S);
+    const int a1 = p1.empty() ? b : p1.front(), a2 = p2.empty() ? b : p2.front();
+    const int b1 = p1.empty() ? a : p1.back(), b2 = p2.empty() ? a : p2.back();
+    std::set<int> all;
+    for (int w = 0; w < n; ++w) all.insert(w);
+    const std::map<int, int> none;
+    double *Ga = S.alloc((size_t)c2 * c4), *Gb = S.alloc((size_t)c2 * c4);
+    const OpenLeg xu{Qu, 1, c2 * chi, c2};       // X_x[a][a'] = Qu[(a a')][x]
+    const OpenLeg yv{Qv, c2, chi, 1};            // X_y[b][b'] = Qv[y][(b b')]
+    site_transfer(a, a1, a2, all, none, S, Ga, &xu);
+    site_transfer(b, b1, b2, all, none, S, Gb, &yv);
+    // H(x) = M_1^T G_a(x) M_2, batched over x
+    double *H1 = S.alloc((size_t)c2 * c4), *H = S.alloc((size_t)c2 * c4);
+    std::vector<const void *> pa, pb, pc1, qa, qb, qc;
+    for (long x = 0; x < c2; ++x) {
+      pa.push_back(M1);
+      pb.push_back(Ga + 2 * (size_t)x * c4);
+      pc1.push_back(H1 + 2 * (size_t)x * c4);
+      qa.push_back(pc1.back());
+      qb.push_back(M2);
+      qc.push_back(H + 2 * (size_t)x * c4);
+    }
+    GemmDesc tA = square_desc(c2);
+    tA.a_mi = 1;
+    tA.a_ki = c2;
+    S.gemm(tA, pa, pb, pc1);
+    S.gemm(square_desc(c2), qa, qb, qc);
+    // E[x][y] = sum_{(j k)} H[x][(j k)] G_b[y][(j k)]
+    GemmDesc f;
+    f.M = f.Mi = (int)c2;
+    f.N = f.Ni = (int)c2;
+    f.K = f.Ki = (int)c4;
+    f.a_mi = c4; f.a_ki = 1;
+    f.b_ki = 1; f.b_ni = c4;
+    f.c_mi = c2; f.c_ni = 1;
+    E = S.alloc(c4);
+    S.gemm1(f, H, Gb, E);
+  } else {
+    return -1.0;
   }
-  GemmDesc h = d;                        // E^H E
-  h.a_mi = 1; h.a_ki = c2;
+  // E^H E, then its eigenvalues s_i^2 (descending)
+  GemmDesc h = square_desc(c2);
+  h.a_mi = 1;
+  h.a_ki = c2;
   h.conjA = 1;
   h.herm = 1;
-  be_->gemm(h, at(herm0), at(herm0 + 1), atw(herm0 + 2), 1);
-  be_->eigh(c2, c2, at(herm0 + 3), atw(herm0 + 4), atw(herm0 + 5), 1);
+  double *G = S.alloc(c4), *V = S.alloc(c4), *ev = S.alloc(c2);
+  S.gemm1(h, E, E, G);
+  const void *ep[3] = {G, ev, V};
+  S.be->h2d(S.parr, ep, sizeof(ep));
+  S.be->eigh((int)c2, (int)c2, (const double *const *)S.parr, (double *const *)(S.parr + 1),
+             (double *const *)(S.parr + 2), 1);
   std::vector<double> l(c2);
-  be_->d2h(l.data(), ev, (size_t)c2 * 8);
-  be_->release(buf);
+  S.be->d2h(l.data(), ev, (size_t)c2 * 8);
   double tot = 0.0;
   for (double x : l) tot += std::max(x, 0.0);
   const double l1 = std::max(l[0], 0.0);
   if (spectrum)
-    for (int i = 0; i < c2; ++i)
+    for (long i = 0; i < c2; ++i)
       spectrum[i] = tot > 0 ? std::sqrt(std::max(l[i], 0.0) / tot) : 0.0;
   return tot > 0 ? 1.0 - std::sqrt(l1 / tot) : NAN;
 }
@@ -1506,6 +1637,159 @@ void Engine::observe_pauli(double *out) {
 }
 
 // Exact contraction of a tree cluster with BP messages on the cut legs; Re(value).
+namespace {
+// 2x2 complex Pauli matrices (row-major re, im): I, X, Y, Z
+const double kPauli[4][8] = {
+    {1, 0, 0, 0, 0, 0, 1, 0},
+    {0, 0, 1, 0, 1, 0, 0, 0},
+    {0, 0, 0, -1, 0, 1, 0, 0},
+    {1, 0, 0, 0, 0, 0, -1, 0}};
+}  // namespace
+
+// The ket of site v with its operator (0 = identity) applied on the physical leg.
+double *Engine::site_ket(int v, int opcode, EngineScratch &S) {
+  Plan &P = *plan_;
+  double *cur = S.alloc((size_t)P.tsize[v]);
+  double *opbuf = S.alloc(4);
+  int64_t *hbuf = (int64_t *)S.alloc(1);
+  const int64_t half = P.tsize[v] / 2;
+  S.be->h2d(opbuf, kPauli[opcode], sizeof(kPauli[opcode]));
+  S.be->h2d(hbuf, &half, 8);
+  const void *pp[2] = {P.T + 2 * P.toff[v], cur};
+  S.be->h2d(S.parr, pp, sizeof(pp));
+  S.be->apply_op((const double *const *)S.parr, (double *const *)(S.parr + 1), hbuf, opbuf, 1);
+  return cur;
+}
+
+// Environment of the subtree at v seen from `parent` (a chi x chi matrix on v's leg to parent):
+// the ket with the site's operator, the bra, every leg to another cluster site closed with that
+// site's own subtree environment, every leg leaving the cluster with its incoming BP message.
+double *Engine::branch_env(int v, int parent, const std::set<int> &cs, const std::map<int, int> &op,
+                           EngineScratch &S) {
+  Plan &P = *plan_;
+  const int chi = P.chi, d = P.deg[v];
+  const long c2 = (long)chi * chi;
+  Layout L = t_layout(d, chi);
+  auto o = op.find(v);
+  double *cur = site_ket(v, o == op.end() ? 0 : o->second, S);
+  int pleg = -1;
+  for (int i = 0; i < d; ++i) {
+    const int u = P.nb[v][i];
+    if (u == parent) {
+      pleg = i;
+      continue;
+    }
+    const double *E = cs.count(u) ? branch_env(u, v, cs, op, S)
+                                  : P.M + 2 * (size_t)P.in_msg[v][i] * c2;
+    double *nxt = S.alloc((size_t)P.tsize[v]);
+    S.gemm1(leg_desc(d, i, L, L, chi), cur, E, nxt);
+    cur = nxt;
+  }
+  double *out = S.alloc(c2);
+  S.gemm1(close_desc(d, pleg, L, chi), cur, P.T + 2 * P.toff[v], out);
+  return out;
+}
+
+// Norm transfer matrix of site v between its legs to `prev` and `next`:
+// F[(a a'), (b b')] = sum T'[s][a][b][x] conj(T[s][a'][b'][x]) / ||T_v||^2, a the leg to prev, b to
+// next, x the remaining leg (if any) closed with its cluster environment or message; T' the ket
+// with the site's operator.  `open`: instead, chi^2 transfer matrices, the x-th with the remaining
+// leg closed with the chi x chi matrix X_x of `open`, written at dst + x chi^4.
+void Engine::site_transfer(int v, int prev, int next, const std::set<int> &cs,
+                           const std::map<int, int> &op, EngineScratch &S, double *dst,
+                           const OpenLeg *open) {
+  Plan &P = *plan_;
+  const int chi = P.chi, d = P.deg[v];
+  const long c2 = (long)chi * chi;
+  const size_t c4 = (size_t)c2 * c2;
+  Layout L = t_layout(d, chi);
+  const double *Tv = P.T + 2 * P.toff[v];
+  auto o = op.find(v);
+  double *cur = site_ket(v, o == op.end() ? 0 : o->second, S);
+  int lp = -1, ln = -1, lx = -1;
+  for (int i = 0; i < d; ++i) {
+    const int u = P.nb[v][i];
+    if (u == prev) lp = i;
+    else if (u == next) ln = i;
+    else lx = i;
+  }
+  std::vector<double> th((size_t)2 * P.tsize[v]);
+  S.be->d2h(th.data(), Tv, (size_t)P.tsize[v] * 16);
+  double nrm2 = 0.0;
+  for (double x : th) nrm2 += x * x;
+  GemmDesc g;
+  g.M = (int)c2; g.Mi = chi; g.a_mo = L.leg[lp]; g.a_mi = L.leg[ln];
+  g.N = (int)c2; g.Ni = chi; g.b_no = L.leg[lp]; g.b_ni = L.leg[ln];
+  g.c_mo = c2 * chi; g.c_mi = chi; g.c_no = c2; g.c_ni = 1;
+  g.conjB = 1;
+  if (lx < 0) {                      // K = s
+    g.K = 2; g.Ki = 2; g.a_ki = L.s; g.b_ki = L.s;
+  } else {                           // K = (s, x)
+    g.K = 2 * chi; g.Ki = chi;
+    g.a_ko = L.s; g.a_ki = L.leg[lx];
+    g.b_ko = L.s; g.b_ki = L.leg[lx];
+  }
+  g.alpha_re = nrm2 > 0.0 ? 1.0 / nrm2 : 1.0;
+  if (!open) {
+    if (lx >= 0) {
+      const int u = P.nb[v][lx];
+      const double *E = cs.count(u) ? branch_env(u, v, cs, op, S)
+                                    : P.M + 2 * (size_t)P.in_msg[v][lx] * c2;
+      double *nxt = S.alloc((size_t)P.tsize[v]);
+      S.gemm1(leg_desc(d, lx, L, L, chi), cur, E, nxt);
+      cur = nxt;
+    }
+    S.gemm1(g, cur, Tv, dst);
+    return;
+  }
+  // batched over the chi^2 matrices X_x: the ket's leg x closed with X_x, then the transfer
+  double *curs = S.alloc((size_t)c2 * P.tsize[v]);
+  std::vector<const void *> a, b, c, a2, b2, c2v;
+  for (long x = 0; x < c2; ++x) {
+    a.push_back(cur);
+    b.push_back(open->base + 2 * (size_t)(x * open->sx));
+    c.push_back(curs + 2 * (size_t)x * P.tsize[v]);
+    a2.push_back(c.back());
+    b2.push_back(Tv);
+    c2v.push_back(dst + 2 * (size_t)x * c4);
+  }
+  GemmDesc ab = leg_desc(d, lx, L, L, chi);
+  ab.b_ki = open->sk;
+  ab.b_ni = open->sn;
+  S.gemm(ab, a, b, c);
+  S.gemm(g, a2, b2, c2v);
+}
+
+// Product of the transfer matrices of the sites of `walk`, each between its legs to the site
+// before it (`before` for the first) and after it (`after` for the last); the identity for an
+// empty walk.  A chi^2 x chi^2 matrix, rows the first site's leg to `before`.
+double *Engine::chain(const std::vector<int> &walk, int before, int after, EngineScratch &S) {
+  const int chi = plan_->chi;
+  const long c2 = (long)chi * chi;
+  const size_t c4 = (size_t)c2 * c2;
+  std::set<int> all;
+  for (int w = 0; w < plan_->n; ++w) all.insert(w);
+  const std::map<int, int> none;
+  double *acc = S.alloc(c4);
+  if (walk.empty()) {
+    std::vector<double> id(2 * c4, 0.0);
+    for (long i = 0; i < c2; ++i) id[2 * (i * c2 + i)] = 1.0;
+    S.be->h2d(acc, id.data(), c4 * 16);
+    return acc;
+  }
+  const int m = (int)walk.size();
+  double *F = m > 1 ? S.alloc(c4) : nullptr, *other = m > 1 ? S.alloc(c4) : nullptr;
+  for (int k = 0; k < m; ++k) {
+    const int pv = k ? walk[k - 1] : before, nx = k + 1 < m ? walk[k + 1] : after;
+    site_transfer(walk[k], pv, nx, all, none, S, k ? F : acc, nullptr);
+    if (k) {
+      S.gemm1(square_desc(c2), acc, F, other);
+      std::swap(acc, other);
+    }
+  }
+  return acc;
+}
+
 double Engine::pauli_value(int k, bool with_ops) {
   Plan &P = *plan_;
   const int chi = P.chi;
@@ -1513,186 +1797,96 @@ double Engine::pauli_value(int k, bool with_ops) {
   int b0 = prob_.pauli_offsets[k], b1 = prob_.pauli_offsets[k + 1];
   std::vector<int> sites(prob_.pauli_sites.begin() + b0, prob_.pauli_sites.begin() + b1);
   std::map<int, int> op;
-  for (int i = b0; i < b1; ++i) op[prob_.pauli_sites[i]] = prob_.pauli_ops[i];
-  // scratch in the BP workspace region is not used concurrently: allocate per call
-  std::vector<void *> tmp;
-  auto alloc = [&](size_t elems) {
-    void *q = be_->alloc(elems * 16);
-    tmp.push_back(q);
-    return (double *)q;
-  };
-  // pointer arrays for single-problem launches
-  void **parr = (void **)be_->alloc(3 * sizeof(void *));
-  tmp.push_back(parr);
-  auto gemm1 = [&](const GemmDesc &d0, const double *a, const double *b, double *c) {
-    GemmDesc d = d0;
-    d.prec = prob_.precision;
-    const void *h[3] = {a, b, c};
-    be_->h2d(parr, h, sizeof(h));
-    be_->gemm(d, (const double *const *)parr, (const double *const *)(parr + 1),
-              (double *const *)(parr + 2), 1);
-  };
-  static const double PM[4][8] = {
-      {1, 0, 0, 0, 0, 0, 1, 0},
-      {0, 0, 1, 0, 1, 0, 0, 0},
-      {0, 0, 0, -1, 0, 1, 0, 0},
-      {1, 0, 0, 0, 0, 0, -1, 0}};
-  double *opbuf = alloc(4);
-  int64_t *hbuf = (int64_t *)be_->alloc(8);
-  tmp.push_back(hbuf);
-  double *rho = alloc(4);
-  std::function<double *(int, int)> env;
-  double result = 0;
-  env = [&](int v, int parent) -> double * {
-    int d = P.deg[v];
-    Layout L = t_layout(d, chi);
-    const double *Tv = P.T + 2 * P.toff[v];
-    double *cur = alloc((size_t)P.tsize[v]);
-    int o = with_ops ? op[v] : 0;
-    be_->h2d(opbuf, PM[o], sizeof(PM[o]));
-    int64_t half = P.tsize[v] / 2;
-    be_->h2d(hbuf, &half, 8);
-    const void *pp[2] = {Tv, cur};
-    be_->h2d(parr, pp, sizeof(pp));
-    be_->apply_op((const double *const *)parr, (double *const *)(parr + 1), hbuf, opbuf, 1);
-    int pleg = -1;
-    for (int i = 0; i < d; ++i) {
-      int u = P.nb[v][i];
-      if (u == parent) { pleg = i; continue; }
-      const double *E;
-      if (op.count(u)) E = env(u, v);
-      else E = P.M + 2 * (size_t)P.in_msg[v][i] * c2;
-      double *nxt = alloc((size_t)P.tsize[v]);
-      gemm1(leg_desc(d, i, L, L, chi), cur, E, nxt);
-      cur = nxt;
-    }
-    if (parent >= 0) {
-      double *out = alloc(c2);
-      gemm1(close_desc(d, pleg, L, chi), cur, Tv, out);
-      return out;
-    }
-    const void *rp[2] = {cur, Tv};
-    be_->h2d(parr, rp, sizeof(rp));
-    be_->h2d(hbuf, &half, 8);
-    be_->rho_dot((const double *const *)parr, (const double *const *)(parr + 1), hbuf, rho, 1);
-    double r[8];
-    be_->d2h(r, rho, sizeof(r));
-    result = r[0] + r[6];       // Re(rho00 + rho11); imaginary part ~ 0 for Hermitian ops
-    return nullptr;
-  };
-  // a tree cluster: contract towards its first site
+  if (with_ops)
+    for (int i = b0; i < b1; ++i) op[prob_.pauli_sites[i]] = prob_.pauli_ops[i];
+  EngineScratch S(be_, prob_.precision);
   std::set<int> cs(sites.begin(), sites.end());
   int inner = 0;
   for (int v : sites)
     for (int u : P.nb[v]) inner += cs.count(u) ? 1 : 0;
   inner /= 2;
   if (inner == (int)sites.size() - 1) {
-    env(sites[0], -1);
-    be_->sync();
-    for (void *q : tmp) be_->release(q);
-    return result;
+    // a tree cluster: every neighbour of the root closed with its subtree, then rho at the root
+    const int v = sites[0], d = P.deg[v];
+    Layout L = t_layout(d, chi);
+    double *cur = site_ket(v, with_ops ? op[v] : 0, S);
+    for (int i = 0; i < d; ++i) {
+      const int u = P.nb[v][i];
+      const double *E = cs.count(u) ? branch_env(u, v, cs, op, S)
+                                    : P.M + 2 * (size_t)P.in_msg[v][i] * c2;
+      double *nxt = S.alloc((size_t)P.tsize[v]);
+      S.gemm1(leg_desc(d, i, L, L, chi), cur, E, nxt);
+      cur = nxt;
+    }
+    double *rho = S.alloc(4);
+    int64_t *hbuf = (int64_t *)S.alloc(1);
+    const int64_t half = P.tsize[v] / 2;
+    S.be->h2d(hbuf, &half, 8);
+    const void *rp[2] = {cur, P.T + 2 * P.toff[v]};
+    S.be->h2d(S.parr, rp, sizeof(rp));
+    S.be->rho_dot((const double *const *)S.parr, (const double *const *)(S.parr + 1), hbuf, rho,
+                  1);
+    double r[8];
+    S.be->d2h(r, rho, sizeof(r));
+    return r[0] + r[6];        // Re(rho00 + rho11); imaginary part ~ 0 for Hermitian ops
   }
   // a cluster with one loop: the branches hanging off the loop are contracted into
-  // environments as above; every loop site becomes its norm transfer matrix
-  // F[(a a'), (b b')] = sum T'[s][a][b][x] conj(T[s][a'][b'][x]) (a: leg to the previous loop
-  // site, b: to the next, x: the remaining leg, already closed with its environment, T' the
-  // operator applied to the ket), scaled by 1 / ||T||^2; the value is Tr(F_0 F_1 ... F_{m-1}).
+  // environments; every loop site becomes its norm transfer matrix (scaled by 1 / ||T||^2) and
+  // the value is Tr(F_0 F_1 ... F_{m-1}).
+  std::vector<int> loop = cycle_of(cs);
+  if (loop.empty()) return NAN;             // not a single loop (rejected on input)
+  const int m = (int)loop.size();
+  const size_t c4 = (size_t)c2 * c2;
+  double *F = S.alloc(c4), *Ra = S.alloc(c4), *Rb = S.alloc(c4), *acc = nullptr;
+  for (int i = 0; i < m; ++i) {
+    double *dst = i == 0 ? Ra : F;
+    site_transfer(loop[i], loop[(i + m - 1) % m], loop[(i + 1) % m], cs, op, S, dst, nullptr);
+    if (i > 0) {
+      double *out = acc == Ra ? Rb : Ra;
+      S.gemm1(square_desc(c2), acc, F, out);
+      acc = out;
+    } else {
+      acc = Ra;
+    }
+  }
+  double *tr = S.alloc(1);
+  S.be->trace(acc, (int)c2, tr);
+  double t2[2];
+  S.be->d2h(t2, tr, sizeof(t2));
+  return t2[0];
+}
+
+// The cycle of a set of sites whose induced subgraph has exactly one loop (the branches peeled
+// off), in walk order from its smallest site; empty if there is not exactly one loop.
+std::vector<int> Engine::cycle_of(const std::set<int> &cs) const {
+  const Plan &P = *plan_;
   std::map<int, int> cdeg;
-  for (int v : sites)
+  for (int v : cs)
     for (int u : P.nb[v]) cdeg[v] += cs.count(u) ? 1 : 0;
   std::set<int> cyc = cs;
   std::vector<int> leaves;
-  for (int v : sites)
-    if (cdeg[v] == 1) leaves.push_back(v);
+  for (int v : cs)
+    if (cdeg[v] <= 1) leaves.push_back(v);
   while (!leaves.empty()) {
     const int v = leaves.back();
     leaves.pop_back();
-    cyc.erase(v);
+    if (!cyc.erase(v)) continue;
     for (int u : P.nb[v])
       if (cyc.count(u) && --cdeg[u] == 1) leaves.push_back(u);
   }
+  if (cyc.size() < 3) return {};
   std::vector<int> loop{*cyc.begin()};
   for (int prev = -1;;) {
     const int w = loop.back();
     int nx = -1;
     for (int u : P.nb[w])
       if (cyc.count(u) && u != prev && (nx < 0 || u < nx)) nx = u;
-    if (nx < 0 || loop.size() > cyc.size()) {      // not a single loop (rejected on input)
-      for (void *q : tmp) be_->release(q);
-      return NAN;
-    }
+    if (nx < 0 || loop.size() > cyc.size()) return {};
     if (nx == loop.front() && loop.size() > 2) break;
     prev = w;
     loop.push_back(nx);
   }
-  const int m = (int)loop.size();
-  const size_t c4 = (size_t)c2 * c2;
-  double *F = alloc(c4), *Ra = alloc(c4), *Rb = alloc(c4), *acc = nullptr;
-  std::vector<double> th;
-  for (int k = 0; k < m; ++k) {
-    const int v = loop[k], pv = loop[(k + m - 1) % m], nx = loop[(k + 1) % m];
-    const int d = P.deg[v];
-    Layout L = t_layout(d, chi);
-    const double *Tv = P.T + 2 * P.toff[v];
-    double *cur = alloc((size_t)P.tsize[v]);
-    const int o = with_ops ? op[v] : 0;
-    be_->h2d(opbuf, PM[o], sizeof(PM[o]));
-    int64_t half = P.tsize[v] / 2;
-    be_->h2d(hbuf, &half, 8);
-    const void *pp[2] = {Tv, cur};
-    be_->h2d(parr, pp, sizeof(pp));
-    be_->apply_op((const double *const *)parr, (double *const *)(parr + 1), hbuf, opbuf, 1);
-    int lp = -1, ln = -1, lx = -1;
-    for (int i = 0; i < d; ++i) {
-      const int u = P.nb[v][i];
-      if (u == pv) { lp = i; continue; }
-      if (u == nx) { ln = i; continue; }
-      lx = i;
-      const double *E = cs.count(u) ? env(u, v) : P.M + 2 * (size_t)P.in_msg[v][i] * c2;
-      double *nxt = alloc((size_t)P.tsize[v]);
-      gemm1(leg_desc(d, i, L, L, chi), cur, E, nxt);
-      cur = nxt;
-    }
-    th.resize((size_t)2 * P.tsize[v]);
-    be_->d2h(th.data(), Tv, (size_t)P.tsize[v] * 16);
-    double nrm2 = 0.0;
-    for (double x : th) nrm2 += x * x;
-    GemmDesc g;
-    g.M = (int)c2; g.Mi = chi; g.a_mo = L.leg[lp]; g.a_mi = L.leg[ln];
-    g.N = (int)c2; g.Ni = chi; g.b_no = L.leg[lp]; g.b_ni = L.leg[ln];
-    g.c_mo = c2 * chi; g.c_mi = chi; g.c_no = c2; g.c_ni = 1;
-    g.conjB = 1;
-    if (lx < 0) {                      // K = s
-      g.K = 2; g.Ki = 2; g.a_ki = L.s; g.b_ki = L.s;
-    } else {                           // K = (s, x)
-      g.K = 2 * chi; g.Ki = chi;
-      g.a_ko = L.s; g.a_ki = L.leg[lx];
-      g.b_ko = L.s; g.b_ki = L.leg[lx];
-    }
-    g.alpha_re = nrm2 > 0.0 ? 1.0 / nrm2 : 1.0;
-    double *dst = k == 0 ? Ra : F;
-    gemm1(g, cur, Tv, dst);
-    if (k > 0) {
-      double *out = acc == Ra ? Rb : Ra;
-      GemmDesc c;
-      c.M = c.N = c.K = c.Mi = c.Ni = c.Ki = (int)c2;
-      c.a_mi = c2; c.a_ki = 1;
-      c.b_ki = c2; c.b_ni = 1;
-      c.c_mi = c2; c.c_ni = 1;
-      gemm1(c, acc, F, out);
-      acc = out;
-    } else {
-      acc = Ra;
-    }
-  }
-  double *tr = alloc(1);
-  be_->trace(acc, (int)c2, tr);
-  double t2[2];
-  be_->d2h(t2, tr, sizeof(t2));
-  result = t2[0];
-  be_->sync();
-  for (void *q : tmp) be_->release(q);
-  return result;
+  return loop.size() == cyc.size() ? loop : std::vector<int>{};
 }
 
 const std::vector<int> &Engine::bond_dims() const { return plan_->bond_h; }

@@ -2359,33 +2359,6 @@ __global__ __launch_bounds__(256) void vidal_svd_kernel(int n, const double *con
   if (tid == 0) kept[e] = (int)cnt_s;
 }
 
-// Norm transfer matrix of a degree-2 site (Methods, "Estimating the error of BP for general
-// tensor networks"): F[(a a'), (b b')] = sum_s T[s][a][b] conj(T[s][a'][b']), a the leg towards the
-// previous site of a walk around a ring and b towards the next (flip: they are T's legs 1 and 0),
-// times scale[p] (the caller's 1 / ||T||^2 keeps long products in range).
-// Grid (ceil(chi^4 / 256), nprob).
-__global__ __launch_bounds__(256) void transfer_kernel(int chi, const double *const *T,
-                                                       const int *flip, const double *scale,
-                                                       double *const *F) {
-  const int p = blockIdx.y;
-  const long c2 = (long)chi * chi, c4 = c2 * c2;
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= c4) return;
-  const double2 *t = reinterpret_cast<const double2 *>(T[p]);
-  const long row = idx / c2, col = idx % c2;
-  const int a = (int)(row / chi), ap = (int)(row % chi), b = (int)(col / chi), bp = (int)(col % chi);
-  const bool f = flip[p] != 0;
-  const long o1 = f ? (long)b * chi + a : (long)a * chi + b;
-  const long o2 = f ? (long)bp * chi + ap : (long)ap * chi + bp;
-  double re = 0.0, im = 0.0;
-  for (int s = 0; s < 2; ++s) {
-    const double2 x = t[s * c2 + o1], y = t[s * c2 + o2];
-    re += x.x * y.x + x.y * y.y;           // x * conj(y)
-    im += x.y * y.x - x.x * y.y;
-  }
-  reinterpret_cast<double2 *>(F[p])[idx] = make_double2(re * scale[p], im * scale[p]);
-}
-
 // Trace of an n x n complex matrix: out = (Re, Im).  One workgroup.
 __global__ __launch_bounds__(256) void trace_kernel(const double *R, int n, double *out) {
   __shared__ double sh[4];
@@ -3242,15 +3215,6 @@ class HipBackend : public Backend {
     hipLaunchKernelGGL(vidal_svd_kernel, dim3(nprob), dim3(256), 0, s_, n, evals, vecs, D1, D2,
                        Mu, Mv, lam, kept, cut);
     launch_check("vidal_svd_kernel");
-  }
-  void transfer(int chi, const double *const *T, const int *flip, const double *scale,
-                double *const *F, int nprob) override {
-    if (nprob <= 0) return;
-    const long c4 = (long)chi * chi * chi * chi;
-    stale_check("transfer_kernel");
-    hipLaunchKernelGGL(transfer_kernel, dim3((unsigned)((c4 + 255) / 256), nprob), dim3(256), 0,
-                       s_, chi, T, flip, scale, F);
-    launch_check("transfer_kernel");
   }
   void trace(const double *R, int n, double *out) override {
     stale_check("trace_kernel");

@@ -153,6 +153,28 @@ def hexagon_ring() -> Lattice:
                    name="hexring12")
 
 
+def heavy_hexagons(k: int) -> Lattice:
+    """The first ``k`` (1, 2 or 3) heavy hexagons of the Eagle lattice's top row as a lattice of
+    their own (the small systems of Fig. 2a-c): 12, 21 and 30 qubits.  Neighbouring hexagons share
+    a side (a bridge qubit and its two row neighbours).  Sites are relabelled in increasing Eagle
+    order and every edge keeps its Eagle colour."""
+    if k not in (1, 2, 3):
+        raise ValueError("k must be 1, 2 or 3")
+    e = eagle()
+    # top row columns 0..4k (qubits 0..4k), bridges of the first gap at columns 0, 4, .., 4k
+    # (qubits 14 + j), second row columns 0..4k (qubits 18..18 + 4k)
+    keep = list(range(4 * k + 1)) + [14 + j for j in range(k + 1)] + \
+        [18 + c for c in range(4 * k + 1)]
+    new = {q: i for i, q in enumerate(sorted(keep))}
+    edges, colours = [], []
+    for (a, b), c in zip(e.edges.tolist(), e.colour.tolist()):
+        if a in new and b in new:
+            edges.append((new[a], new[b]))
+            colours.append(c)
+    return Lattice(len(keep), np.array(edges, dtype=np.int32), np.array(colours, dtype=np.int32),
+                   name=f"heavyhex{k}")
+
+
 def ring(n: int) -> Lattice:
     """Periodic ring of ``n`` (even) sites with the alternating 2-colouring."""
     if n < 3:

@@ -206,7 +206,10 @@ int main() {
     EXPECT(bpki_session_set_state(s, t.data(), m.data(), bd.data()) == 0);
     EXPECT(bpki_session_observe_pauli(s, pv.data()) == 0);
     EXPECT(bpki_session_vidal_gauge(s, lam.data()) == 0);
-    EXPECT(bpki_session_bp_error(s, 0, &err, spec.data()) == -1);   // not a ring
+    EXPECT(bpki_session_bp_error(s, 0, &err, spec.data()) == 0);    // an edge of the loop
+    err = -1.0;
+    EXPECT(bpki_session_bp_error(s, 12, &err, spec.data()) == 0);   // a pendant: a bridge
+    EXPECT(err == 0.0 && spec[0] == 1.0 && spec[1] == 0.0);
     EXPECT(bpki_session_profile(s, 3) == 0);
     EXPECT(bpki_session_step(s, nullptr, &it, &r, &d) == 0);
     int64_t n1 = 0, n2 = 0;
@@ -214,6 +217,29 @@ int main() {
     EXPECT(bpki_session_profile_read(s, &n1, &ms, &fl, &n2) == 0);
     EXPECT(bpki_session_profile_read_prec(s, 1, &n1, &ms, &fl) == 0);
     EXPECT(bpki_session_last_timing(s, ms4.data()) == 0);
+  }
+  {
+    // BP error estimate on a network whose 2-core is two junctions (0, 3) joined by three paths,
+    // then its refusal once a third loop is added
+    Lattice T;
+    T.n = 9;
+    T.edges = {0, 1, 1, 2, 2, 3, 3, 4, 4, 5, 5, 0, 0, 6, 6, 7, 7, 8, 8, 3};
+    bpki_session *st = nullptr;
+    std::vector<double> sp(16);
+    double e2 = 0.0;
+    {
+      Run a(T, 1, 4);
+      EXPECT(bpki_session_open(ctx, &a.p, &st) == 0);
+      for (int e = 0; e < a.p.n_edges; ++e)
+        EXPECT(bpki_session_bp_error(st, e, &e2, sp.data()) == 0);
+      bpki_session_close(st);
+    }
+    T.n = 10;
+    for (int x : {1, 9, 9, 4}) T.edges.push_back(x);
+    Run b(T, 1, 4);
+    EXPECT(bpki_session_open(ctx, &b.p, &st) == 0);
+    EXPECT(bpki_session_bp_error(st, 0, &e2, sp.data()) == -1);
+    bpki_session_close(st);
   }
   bpki_destroy(ctx);                                          // the session keeps it alive
   {

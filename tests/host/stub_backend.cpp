@@ -101,8 +101,6 @@ class StubBackend : public Backend {
     out[0] = 1.0;
     out[1] = 0.0;
   }
-  void transfer(int, const double *const *, const int *, const double *, double *const *,
-                int) override {}
   void vidal_svd(int n, const double *const *, const double *const *, double *const *,
                  double *const *, double *const *, double *const *, double *lam, int *kept,
                  double, int nprob) override {

@@ -514,6 +514,85 @@ def test_bp_error_ring_vs_oracle(ctx, theta, chi):
     s.close()
 
 
+def _bp_error_vs_oracle(ctx, lat, theta, depth, chi, edges, tol_sp=1e-7):
+    """The same evolved state on both sides; per edge the estimate and the spectrum."""
+    import copy
+    net = O.Network(lat.n_sites, lat.edges, lat.colour)
+    O.solve(lat.n_sites, lat.edges, lat.colour, theta, depth, O.Options(chi=chi), net=net)
+    t, m, b = to_flat(net, chi)
+    s = _session(ctx, lat, theta, depth, chi)
+    s.set_state(t, m, b)
+    errs = []
+    for e in edges:
+        err_g, sp_g = s.bp_error(e)
+        err_o, sp_o = copy.deepcopy(net).bp_error(*net.edges[e])
+        assert abs(err_g - err_o) < 1e-12, (e, err_g, err_o)
+        k = len(sp_o)
+        assert np.abs(sp_g[:k] - sp_o).max() < tol_sp, e
+        assert np.all(np.abs(sp_g[k:]) < tol_sp)
+        errs.append(err_o)
+    s.close()
+    return errs
+
+
+def _bridges(lat):
+    """Edges whose removal disconnects the lattice."""
+    out = []
+    for e in range(lat.n_edges):
+        keep = [x for i, x in enumerate(lat.edges.tolist()) if i != e]
+        nb = {v: [] for v in range(lat.n_sites)}
+        for a, b in keep:
+            nb[a].append(b)
+            nb[b].append(a)
+        seen, st = {int(lat.edges[e][0])}, [int(lat.edges[e][0])]
+        while st:
+            x = st.pop()
+            for y in nb[x]:
+                if y not in seen:
+                    seen.add(y)
+                    st.append(y)
+        if int(lat.edges[e][1]) not in seen:
+            out.append(e)
+    return out
+
+
+def test_bp_error_ring_with_pendants_vs_oracle(ctx):
+    """A 12-ring with two pendant sites (the 2-core is the ring; the branches fold into the
+    transfer matrices of the sites they hang from): every loop edge against the oracle's exact
+    contraction, and the two pendant edges, which are bridges, give 0 with the spectrum (1, 0..)."""
+    print("[parity] BP error on a 12-ring with pendants", flush=True)
+    lat = _ring_with_pendants()
+    br = _bridges(lat)
+    assert sorted(br) == [12, 13]
+    errs = _bp_error_vs_oracle(ctx, lat, 1.2, 5, 4, range(lat.n_edges))
+    assert min(errs[:12]) > 1e-6 and max(errs[12:]) < 1e-12
+
+
+@pytest.mark.parametrize("chi,depth,edges", [(4, 7, "all"), (16, 8, "sample")])
+def test_bp_error_two_hexagons_vs_oracle(ctx, chi, depth, edges):
+    """Two heavy hexagons sharing a side (21 qubits, the middle system of Fig. 2a-c) at
+    theta_h = pi/4: the 2-core is two junction sites joined by three paths.  With the cut on the
+    shared side, on either outer path, next to either junction or in the middle of a path, the
+    estimate within 1e-12 of the oracle's exact contraction and the spectrum within 1e-7."""
+    print(f"[parity] BP error on two heavy hexagons chi={chi}", flush=True)
+    lat = L.heavy_hexagons(2)
+    deg = lat.degrees()
+    junction = set(np.nonzero(deg == 3)[0].tolist())
+    shared = [e for e, (a, b) in enumerate(lat.edges.tolist()) if {a, b} & junction and
+              any(deg[x] == 2 and all(y in junction for y in lat.neighbours()[x])
+                  for x in (a, b))]
+    assert len(shared) == 2
+    at_junction = [e for e, (a, b) in enumerate(lat.edges.tolist()) if {a, b} & junction]
+    inner = [e for e in range(lat.n_edges) if e not in at_junction]
+    if edges == "all":
+        pick = list(range(lat.n_edges))
+    else:
+        pick = shared[:1] + [e for e in at_junction if e not in shared][:2] + inner[::6]
+    assert not _bridges(lat)
+    errs = _bp_error_vs_oracle(ctx, lat, math.pi / 4, depth, chi, pick)
+    assert min(errs) > 1e-7
+
+
 def test_bp_error_edge_cases(ctx):
     from paper_2306_14887_amd import bpki as B
     print("[parity] BP error edge cases", flush=True)
@@ -526,7 +605,16 @@ def test_bp_error_edge_cases(ctx):
     with pytest.raises(B.BpkiError):
         s.bp_error(99)
     s.close()
-    s = _session(ctx, L.eagle(), 0.3, 1, 4)      # not a ring
+    e = L.eagle()
+    s = _session(ctx, e, 0.3, 1, 4)
+    s.step()
+    pend = [i for i, (a, b) in enumerate(e.edges.tolist()) if 13 in (a, b)]
+    err, sp = s.bp_error(pend[0])                # qubit 13 hangs off the lattice: a bridge
+    assert err == 0.0 and sp[0] == 1.0 and not sp[1:].any()
+    with pytest.raises(B.BpkiError):             # 2-core with many loops
+        s.bp_error(0)
+    s.close()
+    s = _session(ctx, L.heavy_hexagons(3), 0.3, 1, 4)   # three loops
     with pytest.raises(B.BpkiError):
         s.bp_error(0)
     s.close()
