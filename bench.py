@@ -8,17 +8,19 @@ The first --warmup steps (default 6: bonds saturate at chi = 64 after 6 steps) a
 next --steps steps are timed, so the default run is steps 7..20 of the 20-step circuit.
 
 The JSON line also carries:
-  roofline     : the complex GEMM kernels (every contraction of the step runs in them: the tiled
-                 gemm_kernel, and gemm_stream_kernel for the leg contractions with K, N <= 64),
-                 algorithmic flops 8*M*N*K per launch (8*K*M(M+1)/2 for the Hermitian outputs,
-                 whose upper triangle is a mirror) over the HIP-event-timed launch durations
-                 (every 7th launch of the timed window), against the
-                 MI355X FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the
-                 committed rocprofv3 counter summary (null once the kernel source has changed);
-                 achievable = measured roofs on this GPU (MFMA chains without memory traffic, a
-                 1 GiB copy); frac_of_achievable_mfma compares the algorithmic rate with the
-                 measured FP64 MFMA rate x 4/3 (the 3M complex product issues 3/4 of the
-                 algorithmic real flops).
+  roofline     : the dominant kernel of the step, the fused degree-3 BP closing
+                 (bp_close_kernel<double>: one leg absorption and the Hermitian closing of a
+                 message, chunk by chunk, without writing the intermediate), algorithmic flops
+                 8*(2 chi^4 + chi^3 (chi + 1)) per message over the HIP-event-timed launch
+                 durations (every 7th contraction launch of the timed window), against the MI355X
+                 FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the committed
+                 rocprofv3 counter summary (null once the kernel source has changed); achievable =
+                 measured roofs on this GPU (MFMA chains without memory traffic, a 1 GiB copy);
+                 frac_of_achievable_mfma compares the algorithmic rate with the measured FP64 MFMA
+                 rate x 4/3 (the 3M complex product issues 3/4 of the algorithmic real flops).
+                 gemm_kernels: the same for the complex GEMM kernels (gemm_kernel and
+                 gemm_stream_kernel: every other contraction), 8*M*N*K flops per launch
+                 (8*K*M(M+1)/2 for a Hermitian output, whose upper triangle is a mirror).
   mixed        : the same window in mixed precision (BP tolerance MIXED_TOL), with max / median
                  |<Z>| difference to FP64, the FP64 mode at the same tolerance (the FP32
                  arithmetic's own gain) and the roofline of its FP32 GEMM launches against the FP32
@@ -55,29 +57,37 @@ FP32_PEAK_TFLOPS = 157.3
 # launch pattern of a BP sweep, so every launch shape is sampled; an event pair on every launch
 # would slow the timed steps by ~4%)
 PROFILE_STRIDE = 7
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_hbm_traffic.md")
-GEMM_SOURCE = os.path.join(ROOT, "paper_2306_14887_amd", "csrc", "hip_backend.hip")
+GEMM_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_hbm_traffic.md")
+CLOSE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bp_close_kernel_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_14887_amd", "csrc", "hip_backend.hip")
+# the source spans (kernel, host launch code) that the recorded counters belong to
+GEMM_SPANS = (("constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;",
+               "// Twelve independent MFMA accumulation chains per wave"),
+              ("  void gemm(const GemmDesc &d, const double *const *A",
+               "  void bp_close(const BpCloseDesc &d,"))
+CLOSE_SPANS = (("// Fused BP closing of degree-3 sites at chi = 64 (BpCloseDesc).",
+                "// Hermitian Jacobi eigensolver"),
+               ("  void bp_close(const BpCloseDesc &d,", "  void *splitk_ws(size_t need) {"))
 
 
-def gemm_traffic():
-    """HBM bytes per GEMM launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when
-    the GEMM kernel or its launch code has changed since those counters were taken (their hash is
-    recorded)."""
+def kernel_source_hash(spans) -> str:
     import hashlib
+    src = open(KERNEL_SOURCE).read()
+    return hashlib.sha256("".join(src[src.index(a):src.index(b)] for a, b in spans)
+                          .encode()).hexdigest()
+
+
+def recorded_traffic(profile: str, spans):
+    """HBM bytes per launch from a committed FETCH_SIZE / WRITE_SIZE summary, or None when the
+    kernel or its launch code has changed since those counters were taken (their hash is
+    recorded)."""
     try:
-        src = open(GEMM_SOURCE).read()
-        # the kernel and its launch configuration (tiling, split-K choice)
-        a = src.index("constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;")
-        b = src.index("// Twelve independent MFMA accumulation chains per wave")
-        c = src.index("  void gemm(const GemmDesc &d, const double *const *A")
-        e = src.index("  void *splitk_ws(size_t need) {")
-        h = hashlib.sha256((src[a:b] + src[c:e]).encode()).hexdigest()
         rec = {}
-        for line in open(TRAFFIC_PROFILE):
+        for line in open(profile):
             if ":" in line:
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-        if rec.get("kernel_source_sha256") != h:
+        if rec.get("kernel_source_sha256") != kernel_source_hash(spans):
             return None
         return float(rec["traffic_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -333,7 +343,8 @@ def _window(lat, theta, chi, warmup, steps, precision, tol, profile=False):
             iters.append(r["bp_iters"])
             zs.append(r["z"])
         wall = time.perf_counter() - t0
-        prof = [sess.profile_read_prec(q) for q in (0, 1)] if profile else None
+        prof = ({(k, q): sess.profile_read_kernel(k, q) for k in (0, 1) for q in (0, 1)}
+                if profile else None)
         sess.close()
     return steps / wall, float(np.mean(iters)), np.array(zs), prof
 
@@ -348,20 +359,25 @@ def mixed_window(lat, theta, chi, warmup, steps) -> dict:
     v32, it32, z32, prof = _window(lat, theta, chi, warmup, steps, bpki.BPKI_FP32, MIXED_TOL,
                                    profile=True)
     v64, it64, _, _ = _window(lat, theta, chi, warmup, steps, bpki.BPKI_FP64, MIXED_TOL)
-    p32, p64 = prof[1], prof[0]
-    a32 = p32["flops"] / (p32["ms"] * 1e-3) / 1e12 if p32["ms"] > 0 else 0.0
-    a64 = p64["flops"] / (p64["ms"] * 1e-3) / 1e12 if p64["ms"] > 0 else 0.0
+    def rate(p):
+        return p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+
+    c32, g32, c64 = prof[(1, 1)], prof[(0, 1)], prof[(1, 0)]
+    a32 = rate(c32)
     return {"value": v32, "unit": "Floquet steps/s", "ms_per_step": 1e3 / v32,
             "bp_sweeps_per_step": it32, "bp_tol": MIXED_TOL,
             "dtype": "c64 BP contractions on c64 copies until the FP32 level, then c128",
             "fp64_same_tol": {"value": v64, "bp_sweeps_per_step": it64,
                               "mixed_speedup": v32 / v64},
-            "roofline": {"bound": "mfma", "kernel": "gemm_kernel<float> + gemm_stream_kernel<float>"
-                                                    " (FP32 launches of the window)",
+            "roofline": {"bound": "mfma",
+                         "kernel": "bp_close_kernel<float> (FP32 launches of the window)",
                          "achieved": a32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": a32 / FP32_PEAK_TFLOPS, "launches": p32["launches"],
-                         "avg_launch_ms": p32["ms"] / max(1, p32["launches"]),
-                         "fp64_launches": p64["launches"], "fp64_achieved": a64},
+                         "frac": a32 / FP32_PEAK_TFLOPS, "launches": c32["launches"],
+                         "avg_launch_ms": c32["ms"] / max(1, c32["launches"]),
+                         "gemm_kernels_fp32": {"achieved": rate(g32),
+                                               "launches": g32["launches"],
+                                               "avg_launch_ms": g32["ms"] / max(1, g32["launches"])},
+                         "fp64_launches": c64["launches"], "fp64_achieved": rate(c64)},
             "_z": z32}
 
 
@@ -774,6 +790,8 @@ def main() -> int:
         torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = sess.profile_read()
+    pclose = sess.profile_read_kernel(1, 0)
+    pgemm = sess.profile_read_kernel(0, 0)
     sess.profile(False)
     z = r["z"]
     sess.close()
@@ -781,9 +799,12 @@ def main() -> int:
     ctx.close()
 
     steps_per_s = args.steps / wall
-    launches = max(prof["launches"], 1)
-    avg_ms = prof["ms"] / launches
-    achieved = prof["flops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
+    def rate(p):
+        return p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+
+    achieved = rate(pclose)
+    avg_ms = pclose["ms"] / max(1, pclose["launches"])
+    gemm_rate = rate(pgemm)
     out = {
         "metric": "Floquet steps/s at 127q chi=64",
         "value": steps_per_s,
@@ -807,15 +828,22 @@ def main() -> int:
             "mean_z_last_step": float(np.mean(z)),
         },
         "roofline": {
-            "bound": "mfma", "kernel": "gemm_kernel<double> + gemm_stream_kernel<double>",
+            "bound": "mfma", "kernel": "bp_close_kernel<double>",
             "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "launches": prof["launches"], "launches_in_window": prof["all_launches"],
+            "launches": pclose["launches"], "launches_in_window": prof["all_launches"],
             "sampling_stride": PROFILE_STRIDE, "avg_launch_ms": avg_ms,
-            "traffic": gemm_traffic(), "traffic_unit": "bytes per launch (HBM, calibrated)",
+            "traffic": recorded_traffic(CLOSE_TRAFFIC_PROFILE, CLOSE_SPANS),
+            "traffic_unit": "bytes per launch (HBM, calibrated)",
             "achievable": peaks,
             "frac_of_achievable_mfma": (achieved / (peaks["mfma_f64_tflops"] * 4.0 / 3.0)
                                         if peaks["mfma_f64_tflops"] else None),
+            "gemm_kernels": {
+                "kernel": "gemm_kernel<double> + gemm_stream_kernel<double>",
+                "achieved": gemm_rate, "frac": gemm_rate / FP64_PEAK_TFLOPS,
+                "launches": pgemm["launches"],
+                "avg_launch_ms": pgemm["ms"] / max(1, pgemm["launches"]),
+                "traffic": recorded_traffic(GEMM_TRAFFIC_PROFILE, GEMM_SPANS)},
         },
     }
     if not args.no_mixed:

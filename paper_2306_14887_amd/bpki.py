@@ -115,6 +115,8 @@ def load(path: str | None = None):
         "bpki_session_last_timing": (C.c_int, [vp, dp]),
         "bpki_session_profile_read_prec": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64), dp,
                                                       dp]),
+        "bpki_session_profile_read_kernel": (C.c_int, [vp, C.c_int32, C.c_int32,
+                                                        C.POINTER(C.c_int64), dp, dp]),
         "bpki_session_profile": (C.c_int, [vp, C.c_int]),
         "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp,
                                                  C.POINTER(C.c_int64)]),
@@ -123,6 +125,8 @@ def load(path: str | None = None):
         "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
         "bpki_test_gram_chol": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_double, dp, dp]),
         "bpki_test_mfma_rate": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, dp]),
+        "bpki_test_bp_close": (C.c_int, [vp, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64,
+                                         C.c_int64, C.c_int, dp, dp, C.c_size_t, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -149,8 +153,10 @@ def exported_symbols() -> list[str]:
             "bpki_session_observe_pauli",
             "bpki_session_step", "bpki_session_clifford_inverse_step",
             "bpki_session_last_timing", "bpki_session_profile",
-            "bpki_session_profile_read", "bpki_session_profile_read_prec", "bpki_test_gemm",
-            "bpki_test_eigh", "bpki_test_gram_chol", "bpki_test_mfma_rate"]
+            "bpki_session_profile_read", "bpki_session_profile_read_prec",
+            "bpki_session_profile_read_kernel", "bpki_test_gemm",
+            "bpki_test_eigh", "bpki_test_gram_chol", "bpki_test_mfma_rate",
+            "bpki_test_bp_close"]
 
 
 def _ptr(a, ct):
@@ -357,6 +363,21 @@ class Context:
         _check(self.lib, self.lib.bpki_test_mfma_rate(self.h, precision, blocks, iters,
                                                       C.byref(out)))
         return out.value
+
+    def test_bp_close(self, Y, T, M, rs: int, qs: int, cs: int, ss: int, precision: int = 0,
+                      store32: int = 0):
+        """Fused degree-3 BP message at chi = 64 (see bpki_testing.h): Y, T [nprob][elems],
+        M [nprob][64][64] -> out [nprob][64][64]."""
+        Y = np.ascontiguousarray(Y, dtype=np.complex128)
+        T = np.ascontiguousarray(T, dtype=np.complex128)
+        M = np.ascontiguousarray(M, dtype=np.complex128)
+        nprob = Y.shape[0]
+        out = np.zeros((nprob, 64, 64), dtype=np.complex128)
+        dp = C.POINTER(C.c_double)
+        _check(self.lib, self.lib.bpki_test_bp_close(
+            self.h, precision, store32, rs, qs, cs, ss, nprob, Y.ctypes.data_as(dp),
+            T.ctypes.data_as(dp), Y.size // nprob, M.ctypes.data_as(dp), out.ctypes.data_as(dp)))
+        return out
 
     def test_eigh(self, A: np.ndarray):
         A = np.ascontiguousarray(A, dtype=np.complex128)
@@ -575,6 +596,14 @@ class Session:
         n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
         _check(self.lib, self.lib.bpki_session_profile_read_prec(self.h, prec, C.byref(n),
                                                                  C.byref(ms), C.byref(fl)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value}
+
+    def profile_read_kernel(self, kernel: int, prec: int = 0):
+        """The bracketed launches of one kernel (0 the GEMM kernels, 1 the fused degree-3 BP
+        closing) in one arithmetic (0 FP64, 1 FP32 MFMA)."""
+        n, ms, fl = C.c_int64(), C.c_double(), C.c_double()
+        _check(self.lib, self.lib.bpki_session_profile_read_kernel(
+            self.h, kernel, prec, C.byref(n), C.byref(ms), C.byref(fl)))
         return {"launches": n.value, "ms": ms.value, "flops": fl.value}
 
     def last_timing(self) -> np.ndarray:

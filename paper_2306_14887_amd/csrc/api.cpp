@@ -699,6 +699,16 @@ extern "C" int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int
   return sess_check(s);
 }
 
+extern "C" int bpki_session_profile_read_kernel(bpki_session *s, int32_t kernel, int32_t prec,
+                                                int64_t *launches, double *ms, double *flops) {
+  if (!s || (kernel != 0 && kernel != 1) || (prec != 0 && prec != 1))
+    return fail(-1, "bad argument");
+  long l = 0;
+  s->ctx->be->gemm_profile_read_kernel(kernel, prec, &l, ms, flops);
+  if (launches) *launches = l;
+  return sess_check(s);
+}
+
 extern "C" int bpki_session_last_timing(const bpki_session *s, double *ms4) {
   if (!s || !ms4) return fail(-1, "NULL argument");
   for (int i = 0; i < 4; ++i) ms4[i] = s->timing[i];
@@ -1230,6 +1240,63 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
   be->release(dB);
   be->release(dC);
   be->release(ptrs);
+  std::string msg;
+  int e = be->check(&msg);
+  return e ? fail(e, msg) : 0;
+}
+
+extern "C" int bpki_test_bp_close(bpki_ctx *c, int precision, int store32, int64_t rs,
+                                  int64_t qs, int64_t cs, int64_t ss, int nprob, const double *Y,
+                                  const double *T, size_t y_elems, const double *M, double *out) {
+  if (!c || !Y || !T || !M || !out || nprob < 1 ||
+      (precision != BPKI_FP64 && precision != BPKI_FP32) || (store32 != 0 && store32 != 1) ||
+      (store32 && precision != BPKI_FP32))
+    return fail(-1, "bad argument");
+  if (rs < 0 || qs < 0 || cs < 0 || ss < 0) return fail(-1, "negative stride");
+  const long C = kBpCloseChi;
+  if ((size_t)((C - 1) * (rs + qs + cs) + ss) >= y_elems)
+    return fail(-1, "strides address outside the tensors");
+  Backend *be = c->be.get();
+  std::lock_guard<std::mutex> lk(c->mu);
+  const size_t esz = store32 ? 8 : 16, cc = (size_t)C * C;
+  char *dY = (char *)be->alloc(y_elems * esz * nprob);
+  char *dT = (char *)be->alloc(y_elems * esz * nprob);
+  double *dM = (double *)be->alloc(cc * 16 * nprob);
+  double *dO = (double *)be->alloc(cc * 16 * nprob);
+  void **ptrs = (void **)be->alloc(4 * nprob * sizeof(void *));
+  if (!dY || !dT || !dM || !dO || !ptrs) {
+    for (void *q : {(void *)dY, (void *)dT, (void *)dM, (void *)dO, (void *)ptrs}) be->release(q);
+    return fail(-4, "allocation failed");
+  }
+  auto up = [&](char *d, const double *h) {
+    if (store32) {
+      std::vector<float> t(2 * y_elems * nprob);
+      for (size_t i = 0; i < t.size(); ++i) t[i] = (float)h[i];
+      be->h2d(d, t.data(), t.size() * 4);
+    } else {
+      be->h2d(d, h, y_elems * 16 * nprob);
+    }
+  };
+  up(dY, Y);
+  up(dT, T);
+  be->h2d(dM, M, cc * 16 * nprob);
+  std::vector<void *> h(4 * nprob);
+  for (int p = 0; p < nprob; ++p) {
+    h[p] = dY + y_elems * esz * p;
+    h[nprob + p] = dT + y_elems * esz * p;
+    h[2 * nprob + p] = dM + 2 * cc * p;
+    h[3 * nprob + p] = dO + 2 * cc * p;
+  }
+  be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
+  BpCloseDesc d;
+  d.rs = rs; d.qs = qs; d.cs = cs; d.ss = ss;
+  d.prec = precision == BPKI_FP32 ? 1 : 0;
+  d.s32 = store32;
+  be->bp_close(d, (const double *const *)ptrs, (const double *const *)(ptrs + nprob),
+               (const double *const *)(ptrs + 2 * nprob), (double *const *)(ptrs + 3 * nprob),
+               nprob);
+  be->d2h(out, dO, cc * 16 * nprob);
+  for (void *q : {(void *)dY, (void *)dT, (void *)dM, (void *)dO, (void *)ptrs}) be->release(q);
   std::string msg;
   int e = be->check(&msg);
   return e ? fail(e, msg) : 0;

@@ -40,6 +40,20 @@ struct GemmDesc {
   int a32 = 0, b32 = 0, c32 = 0;
 };
 
+// The BP message of a degree-3 site towards one leg, in one fused pass (chi = 64 only):
+// out[b][b'] = sum_{s, x, a} W[b][a] conj(T[s; b', a, x]),  W[b][a] = sum_{a0} Y[s; b, a0, x] M[a0][a],
+// with Y the site tensor T after the message of the chunk leg x was absorbed, M the incoming
+// message of the applied leg a and b the outgoing leg.  Strides (complex elements) of the
+// outgoing, applied and chunk legs and of s, shared by Y and T.  The output is exactly Hermitian
+// (lower triangle summed, upper triangle its mirror, real diagonal).
+struct BpCloseDesc {
+  int chi = 64;
+  long rs = 0, qs = 0, cs = 0, ss = 0;
+  int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA
+  int s32 = 0;                           // Y and T stored as complex FP32 (prec = 1 only)
+};
+constexpr int kBpCloseChi = 64;
+
 // Simple composite-index helpers for descriptors.
 inline void set_simple_m(GemmDesc &d, int M, long sa, long sc) { d.M = M; d.Mi = M; d.a_mi = sa; d.c_mi = sc; }
 
@@ -76,10 +90,16 @@ struct Backend {
   virtual void gemm_profile_read(long *sampled, long *all, double *ms, double *flops) = 0;
   // the same for the bracketed launches of one arithmetic (0 FP64 MFMA, 1 FP32 MFMA)
   virtual void gemm_profile_read_prec(int prec, long *sampled, double *ms, double *flops) = 0;
+  // kernel 0: the GEMM kernels, 1: the fused degree-3 BP closing; prec as above
+  virtual void gemm_profile_read_kernel(int kernel, int prec, long *sampled, double *ms,
+                                        double *flops) = 0;
 
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,
                     double *const *C, int nprob) = 0;
+  // Fused degree-3 BP closings of nprob sites (BpCloseDesc); out: FP64 chi x chi messages.
+  virtual void bp_close(const BpCloseDesc &d, const double *const *Y, const double *const *T,
+                        const double *const *M, double *const *out, int nprob) = 0;
   // Batched Hermitian eigendecomposition (FP64).  in[p]: n x n (lda), read only; its Hermitian
   // part is used.
   // evals[p]: n reals, descending; vecs[p]: n x n, column i = eigenvector i (ld = n).

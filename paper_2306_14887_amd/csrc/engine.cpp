@@ -34,6 +34,11 @@ struct GemmOp {
   GemmDesc d;
   size_t a = 0, b = 0, c = 0;      // offsets into the pointer arena
   int n = 0;
+  // fused: a fused degree-3 BP closing (BpCloseDesc f): Y at a, the message applied at b, the
+  // output at c, the site tensor at t
+  int fused = 0;
+  BpCloseDesc f;
+  size_t t = 0;
 };
 
 // Device arrays of pointers, built on the host and uploaded once.
@@ -889,6 +894,25 @@ void Engine::build() {
       else d32.c32 = 1;
       add_op1(*ops32, d32, map32(a), map32(b), map32(c));
     };
+    // A fused degree-3 closing in both plans (FP32 plan: Y and T from their FP32 copies)
+    auto add_fused = [&](std::vector<GemmOp> &ops, const BpCloseDesc &f,
+                         const std::vector<const void *> &y, const std::vector<const void *> &t,
+                         const std::vector<const void *> &m, const std::vector<const void *> &o) {
+      if (y.empty()) return;
+      GemmOp op;
+      op.fused = 1;
+      op.f = f;
+      op.n = (int)y.size();
+      op.a = P.arena.add(y); op.t = P.arena.add(t); op.b = P.arena.add(m); op.c = P.arena.add(o);
+      ops.push_back(op);
+      if (!ops32) return;
+      GemmOp o32 = op;
+      o32.f.prec = 1;
+      o32.f.s32 = 1;
+      o32.a = P.arena.add(map32(y));
+      o32.t = P.arena.add(map32(t));
+      ops32->push_back(o32);
+    };
     // Sweep schedule: vertex classes (the two sides of a bipartite graph, else a greedy proper
     // vertex colouring).  The messages sent by one class are recomputed together and normalised
     // before the next class; a site reads the message of a neighbour whose class has already
@@ -932,9 +956,41 @@ void Engine::build() {
       Plan::BpClass C, C32;
       ops32 = mixed ? &C32.ops : nullptr;
       auto in = [&](int v, int i) { return cls[P.nb[v][i]] < c ? Mnp(P.in_msg[v][i]) : Mp(P.in_msg[v][i]); };
-      // degree 3: Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
-      //           Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
-      {
+      // degree 3 at chi = 64, fused: Y1 = T x1 M1 ; Y0 = T x0 M0 (two leg absorptions), then
+      //   out0 = close(Y1, apply M2, chunks over leg 1), out2 = close(Y1, apply M0, chunks over
+      //   leg 1), out1 = close(Y0, apply M2, chunks over leg 0)
+      // so that the slices of every chunk run along a unit-stride leg.  Otherwise:
+      // Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
+      // Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
+      if (chi == kBpCloseChi) {
+        std::vector<const void *> a[2], b[2], cc[2], fy[3], ft[3], fm[3], fo[3];
+        for (int v = 0; v < P.n; ++v) {
+          if (P.deg[v] != 3 || cls[v] != c) continue;
+          const auto &y = sws[v].y;
+          a[0].push_back(Tp(v)); b[0].push_back(in(v, 1)); cc[0].push_back(B(y[0]));
+          a[1].push_back(Tp(v)); b[1].push_back(in(v, 0)); cc[1].push_back(B(y[1]));
+          const void *ys[3] = {B(y[0]), B(y[1]), B(y[0])};
+          const void *ms[3] = {in(v, 2), in(v, 2), in(v, 0)};
+          for (int o = 0; o < 3; ++o) {
+            fy[o].push_back(ys[o]);
+            ft[o].push_back(Tp(v));
+            fm[o].push_back(ms[o]);
+            fo[o].push_back(Mnp(P.out_msg[v][o]));
+          }
+        }
+        add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[0], b[0], cc[0]);
+        add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[1], b[1], cc[1]);
+        const int qleg[3] = {2, 2, 0}, cleg[3] = {1, 0, 1};
+        for (int o = 0; o < 3; ++o) {
+          BpCloseDesc f;
+          f.chi = chi;
+          f.rs = L3.leg[o];
+          f.qs = L3.leg[qleg[o]];
+          f.cs = L3.leg[cleg[o]];
+          f.ss = L3.s;
+          add_fused(C.ops, f, fy[o], ft[o], fm[o], fo[o]);
+        }
+      } else {
         std::vector<const void *> a[8], b[8], cc[8];
         for (int v = 0; v < P.n; ++v) {
           if (P.deg[v] != 3 || cls[v] != c) continue;
@@ -1116,6 +1172,13 @@ void Engine::reset() {
 
 static void run(Backend *be, const PtrArena &ar, const GemmOp &op, int prec) {
   if (op.n == 0) return;
+  if (op.fused) {
+    BpCloseDesc f = op.f;
+    f.prec = prec;
+    be->bp_close(f, ar.at<const double *const *>(op.a), ar.at<const double *const *>(op.t),
+                 ar.at<const double *const *>(op.b), ar.at<double *const *>(op.c), op.n);
+    return;
+  }
   GemmDesc d = op.d;
   d.prec = prec;
   be->gemm(d, ar.at<const double *const *>(op.a), ar.at<const double *const *>(op.b),

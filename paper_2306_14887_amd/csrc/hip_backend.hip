@@ -23,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -536,6 +537,203 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
     }
     C[off] = XC::make(vr, vi);
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused BP closing of degree-3 sites at chi = 64 (BpCloseDesc).  The message towards the
+// outgoing leg b sums, over chunks (s, x) of the chunk leg,
+//   W[b][a] = sum_{a0} Y[b][a0] M[a0][a]          (Y, T: the chunk's 64 x 64 slices)
+//   out[b][b'] += sum_a W[b][a] conj(T[b'][a]).
+// A workgroup owns a contiguous range of the chunks of all problems (a problem's 128 chunks may
+// be split between two workgroups).  Per chunk, wave w forms the 64 x 16 strip W^T[.][b-block w]
+// on MFMA: A = M^T from LDS, B = Y from registers.  The MFMA accumulator of that strip holds, in
+// lane l and register r of tile i, W[16 w + l % 16][16 i + row(l, r)]: exactly the A operand of
+// the second product for k step (i, r) when the k index of that step is taken as
+// 16 i + row(l, r) (the B operand, conj(T), uses the same k map).  So W never leaves the
+// registers and the intermediates of the chain never reach memory.  The second product covers
+// the ten 16 x 16 blocks of the Hermitian output once each: wave w computes blocks (w, w),
+// (w, w + 1 mod 4) and, for w < 2, (w, w + 2); blocks above the diagonal are stored as their
+// mirrors.  The chunk's T slice sits in LDS (transposed, [a][b']), and the next chunk's Y values
+// and T slice are loaded into registers while this chunk is multiplied.  Complex products by the
+// 3M method as in gemm_kernel.  The workgroup's partial sums (lower triangle) go to
+// part[wg][slot] (slot 0: its first problem, 1: the next); bp_close_reduce_kernel adds them in
+// workgroup order.  FP64: one workgroup per CU (LDS and registers); FP32: two.
+// grid: workgroups, each `per` chunks.
+template <typename T>
+struct BpCloseCfg {
+  static constexpr int PAD = std::is_same<T, double>::value ? 8 : 4;    // LDS row padding
+  static constexpr int WGS = std::is_same<T, double>::value ? 1 : 2;    // workgroups per CU
+};
+template <typename T, bool S32>
+__global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
+    BpCloseDesc d, const double *const *Yp, const double *const *Tp, const double *const *Mp,
+    long total, int per, double2 *part) {
+  typedef MfmaTraits<T> MT;
+  typedef typename MT::acc_t acc_t;
+  typedef Cx<S32> X;
+  typedef typename X::t st_t;
+  constexpr int C = kBpCloseChi, J = 2 * kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  constexpr int P = BpCloseCfg<T>::PAD;
+  __shared__ T Ms[2][C][C + P];       // M[a0][a]
+  __shared__ T Ts[2][C][C + P];       // T[b'][a] of the chunk, stored as [a][b']
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(w);
+  const int nb = wv < 2 ? 3 : 2;
+  int bj[3];
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj) bj[jj] = (wv + jj) & 3;
+  const long yrow = (long)(16 * w + c) * d.rs;
+  // this thread's 16 elements u of a T slice: lane along whichever of b', a is unit-stride,
+  // w + 4 u along the other
+  const bool a_fast = d.qs == 1;
+  const int ta = a_fast ? lane : w, tb = a_fast ? w : lane;      // element 0; u adds 4 u to the other
+  const long toff0 = (long)tb * d.rs + (long)ta * d.qs, tstep = 4 * (a_fast ? d.rs : d.qs);
+  acc_t acc2[3][3];
+  auto clear2 = [&]() {
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc2[jj][t] = (acc_t){T(0), T(0), T(0), T(0)};
+  };
+  // the workgroup's lower-triangle partial sum of one problem
+  auto flush = [&](int slot) {
+    double2 *Pp = part + ((size_t)blockIdx.x * 2 + slot) * CC;
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      if (jj >= nb) break;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = 16 * w + MT::row(lane, r), bp = 16 * bj[jj] + c;
+        const double re = (double)acc2[jj][0][r] - (double)acc2[jj][1][r];
+        const double im = (double)acc2[jj][2][r] - (double)acc2[jj][0][r] - (double)acc2[jj][1][r];
+        if (b >= bp) Pp[b * C + bp] = make_double2(re, im);
+        else if (bj[jj] != wv) Pp[bp * C + b] = make_double2(re, -im);
+      }
+    }
+  };
+  auto chunk_base = [&](long k) {
+    const int j = (int)(k % J);
+    return (long)(j / C) * d.ss + (long)(j % C) * d.cs;
+  };
+  st_t yv[16], tn[16];
+  auto load_y = [&](const st_t *Y, long base) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) yv[t] = Y[base + yrow + (long)(4 * t + g) * d.qs];
+  };
+  auto load_t = [&](const st_t *Tt, long base) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) tn[u] = Tt[base + toff0 + u * tstep];
+  };
+  auto store_t = [&]() {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int a = a_fast ? ta : ta + 4 * u, b = a_fast ? tb + 4 * u : tb;
+      Ts[0][a][b] = T(tn[u].x);
+      Ts[1][a][b] = -T(tn[u].y);          // conj(T)
+    }
+  };
+  clear2();
+  const long k0 = (long)blockIdx.x * per, k1 = min(k0 + per, total);
+  int cur = -1, slot = 0;
+  const st_t *Y = nullptr, *Tt = nullptr;
+  bool ready = false;                    // this chunk's Y values and T slice are in place
+  for (long k = k0; k < k1; ++k) {
+    const int p = (int)(k / J);
+    if (!ready) {                        // first chunk, or a new problem (workgroup-uniform)
+      if (cur >= 0) {
+        flush(slot++);
+        clear2();
+      }
+      cur = p;
+      Y = reinterpret_cast<const st_t *>(Yp[p]);
+      Tt = reinterpret_cast<const st_t *>(Tp[p]);
+      const double2 *M = reinterpret_cast<const double2 *>(Mp[p]);
+      const long base = chunk_base(k);
+      load_y(Y, base);
+      load_t(Tt, base);
+      __syncthreads();
+      for (int idx = tid; idx < CC; idx += 256) {
+        const double2 v = M[idx];
+        Ms[0][idx / C][idx % C] = T(v.x);
+        Ms[1][idx / C][idx % C] = T(v.y);
+      }
+      store_t();
+      __syncthreads();
+    }
+    // the next chunk of the same problem: its T slice is loaded while this chunk is multiplied,
+    // its Y values once this chunk's first product has used the current ones
+    ready = k + 1 < k1 && (k + 1) / J == p;
+    const long nbase = ready ? chunk_base(k + 1) : 0;
+    if (ready) load_t(Tt, nbase);
+    // W^T[a][b] = sum_a0 M[a0][a] Y[b][a0], four a tiles by this wave's 16 columns b
+    acc_t acc1[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc1[i][t] = (acc_t){T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int a0 = 4 * t + g;
+      const T br = T(yv[t].x), bi = T(yv[t].y), bs = br + bi;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T ar = Ms[0][a0][16 * i + c], ai = Ms[1][a0][16 * i + c], as = ar + ai;
+        acc1[i][0] = MT::mma(ar, br, acc1[i][0]);
+        acc1[i][1] = MT::mma(ai, bi, acc1[i][1]);
+        acc1[i][2] = MT::mma(as, bs, acc1[i][2]);
+      }
+    }
+    if (ready) load_y(Y, nbase);
+    // out[b][b'] += sum_a W[b][a] conj(T[b'][a]), k step (i, r) <-> a = 16 i + row(lane, r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const T wr = acc1[i][0][r] - acc1[i][1][r];
+        const T wi = acc1[i][2][r] - acc1[i][0][r] - acc1[i][1][r];
+        const T ws = wr + wi;
+        const int a = 16 * i + MT::row(lane, r);
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+          if (jj >= nb) break;
+          const T br = Ts[0][a][16 * bj[jj] + c], bi = Ts[1][a][16 * bj[jj] + c], bs = br + bi;
+          acc2[jj][0] = MT::mma(wr, br, acc2[jj][0]);
+          acc2[jj][1] = MT::mma(wi, bi, acc2[jj][1]);
+          acc2[jj][2] = MT::mma(ws, bs, acc2[jj][2]);
+        }
+      }
+    }
+    if (ready) {
+      __syncthreads();                   // every wave is done with this chunk's T slice
+      store_t();
+      __syncthreads();
+    }
+  }
+  if (cur >= 0) flush(slot);
+}
+
+// Message p of a fused BP closing: the partial sums of the workgroups that covered its chunks,
+// in workgroup order; lower triangle, its mirror above, real diagonal.  grid (16, nprob).
+__global__ __launch_bounds__(256) void bp_close_reduce_kernel(int per, const double2 *part,
+                                                              double *const *Op) {
+  constexpr int C = kBpCloseChi, J = 2 * kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  const int p = blockIdx.y;
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= CC) return;
+  const int b = idx / C, bp = idx % C;
+  if (b < bp) return;
+  const long first = (long)p * J, last = first + J - 1;
+  double re = 0.0, im = 0.0;
+  for (long wg = first / per; wg <= last / per; ++wg) {
+    const int slot = (wg * per) / J == p ? 0 : 1;
+    const double2 v = part[((size_t)wg * 2 + slot) * CC + idx];
+    re += v.x;
+    im += v.y;
+  }
+  double2 *O = reinterpret_cast<double2 *>(Op[p]);
+  O[b * C + bp] = make_double2(re, b == bp ? 0.0 : im);
+  if (b > bp) O[bp * C + b] = make_double2(re, -im);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2788,6 +2986,60 @@ class HipBackend : public Backend {
       launch_check("gemm_reduce_kernel");
     }
   }
+  void bp_close(const BpCloseDesc &d, const double *const *Y, const double *const *T,
+                const double *const *M, double *const *out, int nprob) override {
+    if (nprob <= 0) return;
+    if (d.chi != kBpCloseChi || (d.s32 && d.prec != 1) || d.rs < 0 || d.qs < 0 || d.cs < 0 ||
+        d.ss < 0) {
+      if (err_ == 0) {
+        err_ = -1;
+        errmsg_ = "bp_close: unsupported descriptor";
+      }
+      return;
+    }
+    // one round of resident workgroups (FP64: one per CU, FP32: two), each a contiguous run of
+    // `per` chunks (at most one problem's 128, so a workgroup touches at most two problems)
+    const long J = 2L * kBpCloseChi, total = J * nprob;
+    const long slots = d.prec == 1 ? resident_ : std::max(1, resident_ / 2);
+    const int per = (int)std::max(1L, std::min(J, (total + slots - 1) / slots));
+    const int nwg = (int)((total + per - 1) / per);
+    double2 *W = (double2 *)splitk_ws((size_t)nwg * 2 * kBpCloseChi * kBpCloseChi *
+                                      sizeof(double2));
+    if (!W) return;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool rec = prof_stride_ > 0 && (prof_all_++ % prof_stride_) == 0;
+    if (rec) {
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, s_));
+    }
+    stale_check("bp_close_kernel");
+    if (d.prec == 1 && d.s32)
+      hipLaunchKernelGGL((bp_close_kernel<float, true>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,
+                         total, per, W);
+    else if (d.prec == 1)
+      hipLaunchKernelGGL((bp_close_kernel<float, false>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,
+                         total, per, W);
+    else
+      hipLaunchKernelGGL((bp_close_kernel<double, false>), dim3(nwg), dim3(256), 0, s_, d, Y, T,
+                         M, total, per, W);
+    launch_check("bp_close_kernel");
+    if (rec) {
+      HIPCHK(hipEventRecord(e1, s_));
+      prof_ev_.push_back({e0, e1});
+      prof_prec_.push_back(2 + (d.prec & 1));
+      // algorithmic work per message: the absorption (2 chi^4) and the distinct entries of the
+      // Hermitian closing (chi (chi + 1) / 2 of them, K = 2 chi^2)
+      const double c = kBpCloseChi;
+      const double fl = 8.0 * nprob * (2.0 * c * c * c * c + c * c * c * (c + 1.0));
+      prof_flops_ += fl;
+      prof_flops_p_[2 + (d.prec & 1)] += fl;
+    }
+    stale_check("bp_close_reduce_kernel");
+    hipLaunchKernelGGL(bp_close_reduce_kernel, dim3(kBpCloseChi * kBpCloseChi / 256, nprob),
+                       dim3(256), 0, s_, per, (const double2 *)W, out);
+    launch_check("bp_close_reduce_kernel");
+  }
   void *splitk_ws(size_t need) {
     if (need > skws_bytes_) {
       HIPCHK(hipStreamSynchronize(s_));
@@ -2811,7 +3063,7 @@ class HipBackend : public Backend {
       prof_all_ = 0;
       prof_ms_ = 0;
       prof_flops_ = 0;
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < 4; ++q) {
         prof_launches_p_[q] = 0;
         prof_ms_p_[q] = prof_flops_p_[q] = 0;
       }
@@ -2827,6 +3079,14 @@ class HipBackend : public Backend {
   void gemm_profile_read_prec(int prec, long *sampled, double *ms, double *flops) override {
     drain_profile();
     const int q = prec & 1;
+    if (sampled) *sampled = prof_launches_p_[q] + prof_launches_p_[2 + q];
+    if (ms) *ms = prof_ms_p_[q] + prof_ms_p_[2 + q];
+    if (flops) *flops = prof_flops_p_[q] + prof_flops_p_[2 + q];
+  }
+  void gemm_profile_read_kernel(int kernel, int prec, long *sampled, double *ms,
+                                double *flops) override {
+    drain_profile();
+    const int q = 2 * (kernel & 1) + (prec & 1);
     if (sampled) *sampled = prof_launches_p_[q];
     if (ms) *ms = prof_ms_p_[q];
     if (flops) *flops = prof_flops_p_[q];
@@ -2839,7 +3099,7 @@ class HipBackend : public Backend {
       HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
       prof_ms_ += ms;
       prof_launches_ += 1;
-      const int q = prof_prec_[i] & 1;
+      const int q = prof_prec_[i] & 3;
       prof_ms_p_[q] += ms;
       prof_launches_p_[q] += 1;
       HIPCHK(hipEventDestroy(pr.first));
@@ -3309,9 +3569,9 @@ class HipBackend : public Backend {
   long prof_launches_ = 0, prof_all_ = 0;
   double prof_ms_ = 0, prof_flops_ = 0;
   // the same sums by arithmetic of the bracketed launches (0 FP64 MFMA, 1 FP32 MFMA)
-  std::vector<int> prof_prec_;
-  long prof_launches_p_[2] = {0, 0};
-  double prof_ms_p_[2] = {0, 0}, prof_flops_p_[2] = {0, 0};
+  std::vector<int> prof_prec_;     // per bracketed launch: 2 * (fused BP closing) + FP32 MFMA
+  long prof_launches_p_[4] = {0, 0, 0, 0};
+  double prof_ms_p_[4] = {0, 0, 0, 0}, prof_flops_p_[4] = {0, 0, 0, 0};
 };
 
 // Device memory of the allocation-free solve (bpki_solve_noalloc): a fixed array in the code

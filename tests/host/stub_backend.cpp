@@ -84,6 +84,11 @@ class StubBackend : public Backend {
     if (ms) *ms = 0;
     if (f) *f = 0;
   }
+  void gemm_profile_read_kernel(int, int, long *s, double *ms, double *f) override {
+    gemm_profile_read_prec(0, s, ms, f);
+  }
+  void bp_close(const BpCloseDesc &, const double *const *, const double *const *,
+                const double *const *, double *const *, int) override {}
   void gemm(const GemmDesc &, const double *const *, const double *const *, double *const *,
             int) override {}
   void eigh(int n, int, const double *const *, double *const *evals, double *const *,

@@ -303,3 +303,68 @@ def test_mfma_rate_probe(ctx):
         ctx.test_mfma_rate(2)
     with pytest.raises(B.BpkiError):
         ctx.test_mfma_rate(0, blocks=0)
+
+
+# --- fused degree-3 BP message (chi = 64) ------------------------------------------------------
+
+_C = 64
+# (outgoing leg, applied leg, chunk leg) as the BP sweep uses them, site tensors [s][l0][l1][l2]
+_LEG_STRIDE = (_C * _C, _C, 1)
+BP_CLOSE_CASES = [("out0", 0, 2, 1), ("out1", 1, 2, 0), ("out2", 2, 0, 1)]
+
+
+def _hermitian(rng, n):
+    X = _rand(rng, n, n)
+    H = X @ X.conj().T
+    return H / np.trace(H).real
+
+
+def _bp_close_case(rng, nprob, o, q, cl):
+    """Site tensors T, the chunk leg's message absorbed (Y = T x_cl M_cl), the applied leg's
+    message M_q, and the reference message out[b][b'] = sum T M_cl M_q conj(T) over s, a, x."""
+    Ts, Ys, Ms, refs = [], [], [], []
+    for _ in range(nprob):
+        T = _rand(rng, 2, _C, _C, _C) / _C
+        Mc, Mq = _hermitian(rng, _C), _hermitian(rng, _C)
+        Y = np.moveaxis(np.tensordot(np.moveaxis(T, 1 + cl, -1), Mc, axes=([3], [0])), -1, 1 + cl)
+        # views [s][b][a][x] of Y and T
+        perm = [0, 1 + o, 1 + q, 1 + cl]
+        Yv, Tv = np.transpose(Y, perm), np.transpose(T, perm)
+        W = np.tensordot(Yv, Mq, axes=([2], [0]))              # [s][b][x][a]
+        ref = np.tensordot(W, np.transpose(Tv, (0, 1, 3, 2)).conj(), axes=([0, 2, 3], [0, 2, 3]))
+        Ts.append(T.reshape(-1)); Ys.append(Y.reshape(-1)); Ms.append(Mq); refs.append(ref)
+    return np.array(Ys), np.array(Ts), np.array(Ms), np.array(refs)
+
+
+@pytest.mark.parametrize("name,o,q,cl", BP_CLOSE_CASES, ids=[c[0] for c in BP_CLOSE_CASES])
+def test_bp_close_matches_numpy(ctx, name, o, q, cl):
+    """The fused message of a degree-3 site against numpy complex128, for the three leg
+    configurations of the sweep: FP64 MFMA to 1e-12 of the largest entry, FP32 MFMA (FP64 and
+    FP32 operand storage) to 2e-5; exactly Hermitian output.  Nine problems for out0 make the
+    workgroups' chunk runs straddle problems (128 chunks each, runs of 3)."""
+    print(f"[bp_close] {name}", flush=True)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    nprob = 9 if name == "out0" else 2
+    Y, T, M, ref = _bp_close_case(rng, nprob, o, q, cl)
+    st = dict(rs=_LEG_STRIDE[o], qs=_LEG_STRIDE[q], cs=_LEG_STRIDE[cl], ss=_C ** 3)
+    scale = np.abs(ref).max()
+    got = ctx.test_bp_close(Y, T, M, **st)
+    assert np.abs(got - ref).max() < 1e-12 * scale
+    assert np.array_equal(got, np.conj(np.transpose(got, (0, 2, 1))))
+    for store32 in (0, 1):
+        g32 = ctx.test_bp_close(Y, T, M, precision=1, store32=store32, **st)
+        err = np.abs(g32 - ref).max() / scale
+        print(f"  FP32 store32={store32}: {err:.1e}", flush=True)
+        assert 1e-10 < err < 2e-5
+        assert np.array_equal(g32, np.conj(np.transpose(g32, (0, 2, 1))))
+
+
+def test_bp_close_rejects_bad_arguments(ctx):
+    from paper_2306_14887_amd import bpki as B
+    rng = np.random.default_rng(5)
+    Y = _rand(rng, 1, 2 * _C ** 3)
+    M = _rand(rng, 1, _C, _C)
+    with pytest.raises(B.BpkiError):              # reaches past the tensors
+        ctx.test_bp_close(Y, Y, M, rs=_C * _C, qs=1, cs=_C, ss=_C ** 3 + 1)
+    with pytest.raises(B.BpkiError):              # FP32 storage needs FP32 MFMA
+        ctx.test_bp_close(Y, Y, M, rs=_C * _C, qs=1, cs=_C, ss=_C ** 3, store32=1)
