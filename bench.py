@@ -28,6 +28,9 @@ The JSON line also carries:
   config1      : the chi = 32 configuration: nine theta_h, 20 steps each, FP64, the lattice-average
                  magnetisation after every step.
   chi128       : the same workload at chi = 128, steps 8..10 (FP64).
+  precision_form, precision_form_chi128 (opt-in): the eight seeded theta_h with 64 seeded Pauli
+                 strings each, 20 steps, FP64 and mixed, the mixed run's error in every <Z> and
+                 string; at chi = 64 and (opt-in) chi = 128.
   weight10     : the paper's weight-10 observable after 5 steps at the eight theta_h, measured by
                  the extended time evolution (5 steps, then 5 steps of U(pi/2)^dagger, <Z_13>).
   theta_batch  : the eight theta_h values of the workload (20 steps each) solved together, one
@@ -687,12 +690,18 @@ def oracle_config1_run(chi: int = 32, theta: float = 0.8, depth: int = 20) -> di
     from paper_2306_14887_amd import lattice as L
 
     lat = L.eagle()
+    net = O.Network(lat.n_sites, lat.edges, lat.colour)
+    sweeps = 0
     t0 = time.perf_counter()
-    r = O.solve(lat.n_sites, lat.edges, lat.colour, theta, depth, O.Options(chi=chi))
+    for t in range(depth):                # one step at a time on the same network
+        r = O.solve(lat.n_sites, lat.edges, lat.colour, theta, 1, O.Options(chi=chi), net=net)
+        sweeps += int(sum(r.bp_iters))
+        print(f"oracle chi={chi} step {t + 1}/{depth}: {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     return {"chi": chi, "theta_h": theta, "steps": depth, "seconds": wall,
             "value": depth / wall, "unit": "Floquet steps/s", "cores": _cores(),
-            "bp_sweeps": int(sum(r.bp_iters))}
+            "bp_sweeps": sweeps}
 
 
 def copy_probe(mib: int) -> int:
@@ -731,6 +740,8 @@ def main() -> int:
                          "3 theta_h x 30 steps, FP64 and mixed; 0 = skip)")
     ap.add_argument("--precision-form", type=int, default=1,
                     help="1: also the 8 theta_h with 64 Pauli strings each, FP64 vs mixed errors")
+    ap.add_argument("--precision-form-chi128", type=int, default=0,
+                    help="1: also the precision form at chi = 128 (minutes of GPU time)")
     ap.add_argument("--infinite256", type=int, default=30, metavar="STEPS",
                     help="steps of the infinite-lattice cell at chi = 256 (theta_h = pi/4, FP64 and "
                          "mixed; 0 = skip)")
@@ -869,6 +880,9 @@ def main() -> int:
     if args.precision_form:
         out["precision_form"] = precision_form(lat, chi, args.warmup + args.steps)
         print("precision form done", file=sys.stderr, flush=True)
+    if args.precision_form_chi128:
+        out["precision_form_chi128"] = precision_form(lat, 128, 20)
+        print("precision form at chi = 128 done", file=sys.stderr, flush=True)
     if args.bp_error:
         out["bp_error_ring"] = bp_error_ring()
         print("BP error estimate done", file=sys.stderr, flush=True)

@@ -54,7 +54,8 @@ typedef struct bpki_ctx bpki_ctx;
  * SVD and the message square roots and inverse square roots), the messages, the BP residual and
  * the observables' final ratios are FP64 in every mode.
  * BPKI_FP32: the BP sweeps run on FP32 MFMA over FP32 copies of the site tensors (made once per
- * new state) with FP32 intermediates, FP32 accumulation per K chunk and FP64 chunk sums, until
+ * new state) with FP32 intermediates, FP32 accumulation per K chunk (per workgroup run of chunks in
+ * the fused degree-3 closing) and FP64 chunk sums, until
  * the residual reaches the FP32 rounding level (2e-6, or a sweep within 100x of it that gains less
  * than 10%); then FP64 sweeps run to bp_tol, so the fixed point is the FP64 one.  The
  * observables' contractions use FP32 MFMA on the FP64 state.
