@@ -76,6 +76,10 @@ struct Backend {
   virtual void clear_alloc_error() = 0;
   virtual void h2d(void *dst, const void *src, size_t bytes) = 0;
   virtual void d2h(void *dst, const void *src, size_t bytes) = 0;
+  // One double read in stream order into slot 0 or 1 without waiting; wait_read(slot) returns it
+  // once the stream has reached that read.
+  virtual void read_async(const double *src, int slot) = 0;
+  virtual double wait_read(int slot) = 0;
   virtual void d2d(void *dst, const void *src, size_t bytes) = 0;
   virtual void sync() = 0;
   virtual int check(std::string *msg) = 0;          // 0 or negative error code

@@ -66,6 +66,9 @@ constexpr double kGramCut = 1e-15;
 constexpr double kFp32BpFloor = 2e-6;
 constexpr double kFp32Near = 100.0;
 constexpr double kFp32Stall = 0.9;
+// A sweep is launched ahead of the previous residual only if the residual extrapolated from the two
+// before stays this many times above the point where the loop would stop or change arithmetic.
+constexpr double kSpecMargin = 8.0;
 
 inline bool fp32_done(double r, double prev) {
   return r < kFp32BpFloor || (r < kFp32Near * kFp32BpFloor && r > kFp32Stall * prev);
@@ -145,7 +148,7 @@ struct Plan {
   double *ws = nullptr;            // SU workspace (max over layers)
   double *bpws = nullptr;          // BP / observable workspace
   double *res = nullptr;           // per-message residual [2E]
-  double *resmax = nullptr;        // [1]
+  double *resmax = nullptr;        // [2]: the largest residual of a sweep (two in flight)
   double *rho = nullptr;           // [n][4] complex
   int *kbuf = nullptr;             // [max edges per layer]
   double *disc = nullptr;          // [max edges per layer]
@@ -393,7 +396,7 @@ void Engine::build() {
   P.M = (double *)A(message_elems() * 16);
   P.Mn = (double *)A(message_elems() * 16);
   P.res = (double *)A((size_t)std::max(1, 2 * P.E) * 8);
-  P.resmax = (double *)A(8);
+  P.resmax = (double *)A(16);
   P.rho = (double *)A((size_t)P.n * 8 * 8);
   P.kbuf = (int *)A((size_t)std::max(1, P.max_layer_edges) * 4);
   P.disc = (double *)A((size_t)std::max(1, P.max_layer_edges) * 16);   // (discarded, gap) pairs
@@ -1309,16 +1312,45 @@ double Engine::bp_sweep() {
 int Engine::bp(int max_iter, double *residual) {
   // Mixed modes sweep with FP32 contractions while the residual is above the FP32 floor, then
   // (if the tolerance asks for more) finish with FP64 sweeps: the fixed point is the FP64 one.
-  int it = 0;
-  double r = INFINITY, prev = INFINITY;
+  // While the residual is predicted to stay well above the tolerance, the next sweep's launches
+  // are enqueued before this sweep's residual has come back to the host; its message copy (the
+  // commit) is enqueued only once that residual says it is needed, so a sweep that is not needed
+  // is never committed and the messages are those of one sweep at a time.
+  Plan &P = *plan_;
+  const size_t mbytes = message_elems() * 16;
+  auto launch = [&](int slot) {
+    sweep_classes();
+    be_->reduce_max(P.res, 2 * P.E, P.resmax + slot);
+    be_->read_async(P.resmax + slot, slot);
+  };
+  auto commit = [&]() { be_->d2d(P.M, P.Mn, mbytes); };
+  double r = INFINITY, prev = INFINITY, prev2 = INFINITY;
   bp_prec_ = prob_.precision ? 1 : 0;
+  int it = 0, slot = 0;
+  if (max_iter > 0) {
+    launch(slot);
+    commit();
+  }
   while (it < max_iter) {
-    r = bp_sweep();
-    ++it;
-    if (r < prob_.bp_tol) break;
-    // FP32 sweeps stop at their rounding floor, or earlier if the residual stops falling
+    ++it;                                // sweep `it` is committed; its residual is in `slot`
+    // speculate only with two residuals to extrapolate from, predicted well above the point
+    // where the loop stops or changes arithmetic
+    bool spec = false;
+    if (it < max_iter && std::isfinite(prev2) && prev2 > 0.0) {
+      const double pred = prev * std::min(1.0, prev / prev2);
+      const double stop = bp_prec_ == 1 ? kFp32Near * kFp32BpFloor : prob_.bp_tol;
+      spec = pred > kSpecMargin * stop;
+    }
+    const int pprec = bp_prec_;
+    if (spec) launch(slot ^ 1);
+    r = be_->wait_read(slot);
+    if (r < prob_.bp_tol || it >= max_iter) break;    // a speculated sweep stays uncommitted
     if (bp_prec_ == 1 && fp32_done(r, prev)) bp_prec_ = 0;
+    prev2 = prev;
     prev = r;
+    slot ^= 1;
+    if (!spec || bp_prec_ != pprec) launch(slot);     // (re)launch in the current arithmetic
+    commit();
   }
   bp_prec_ = prob_.precision ? 1 : 0;
   if (residual) *residual = r;

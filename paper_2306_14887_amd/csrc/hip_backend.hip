@@ -2722,6 +2722,8 @@ class HipBackend : public Backend {
   ~HipBackend() override {
     for (auto &e : ev_)
       if (e) hipEventDestroy(e);
+    for (auto &e : rd_ev_)
+      if (e) hipEventDestroy(e);
     if (skws_) HIPCHK(dfree(skws_));
     if (cws_) HIPCHK(dfree(cws_));
     if (cmeta_) HIPCHK(dfree(cmeta_));
@@ -2804,7 +2806,7 @@ class HipBackend : public Backend {
   // the bubble between BP sweeps.
   void d2h(void *h, const void *d, size_t b) override {
     if (err_) return;
-    if (b && b <= kPinBytes && pin_) {
+    if (b && b <= kPinBytes - kPinAsync && pin_) {
       HIPCHK(hipMemcpyAsync(pin_, d, b, hipMemcpyDeviceToHost, s_));
       hipError_t e;
       while ((e = hipStreamQuery(s_)) == hipErrorNotReady) {
@@ -2818,7 +2820,31 @@ class HipBackend : public Backend {
     }
     if (b) HIPCHK(hipMemcpyAsync(h, d, b, hipMemcpyDeviceToHost, s_));
     HIPCHK(hipStreamSynchronize(s_));
+  }  // One double into slot 0 or 1 at the end of the pinned buffer, in stream order; wait_read spins on
+  // the copy's event (the host resumes as soon as the stream reaches it).
+  void read_async(const double *d, int slot) override {
+    if (err_) return;
+    double *h = pin_ ? (double *)((char *)pin_ + kPinBytes - kPinAsync) + (slot & 1) : nullptr;
+    if (!h) {
+      d2h(&rd_val_[slot & 1], d, 8);
+      return;
+    }
+    if (!rd_ev_[slot & 1]) HIPCHK(hipEventCreateWithFlags(&rd_ev_[slot & 1], hipEventDisableTiming));
+    HIPCHK(hipMemcpyAsync(h, d, 8, hipMemcpyDeviceToHost, s_));
+    HIPCHK(hipEventRecord(rd_ev_[slot & 1], s_));
   }
+  double wait_read(int slot) override {
+    if (err_) return NAN;
+    if (!pin_) return rd_val_[slot & 1];
+    hipError_t e;
+    while ((e = hipEventQuery(rd_ev_[slot & 1])) == hipErrorNotReady) {
+    }
+    const hipError_t le = hipGetLastError();
+    if (e != hipSuccess) HIPCHK(e);
+    if (le != hipSuccess && le != hipErrorNotReady) HIPCHK(le);
+    return ((const double *)((const char *)pin_ + kPinBytes - kPinAsync))[slot & 1];
+  }
+
   void d2d(void *d, const void *s, size_t b) override {
     if (err_) return;
     if (b) HIPCHK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, s_));
@@ -3548,6 +3574,9 @@ class HipBackend : public Backend {
   void *rws_ = nullptr;
   size_t rws_bytes_ = 0;
   static constexpr size_t kPinBytes = 16384;
+  static constexpr size_t kPinAsync = 64;      // the tail of pin_ holds the read_async slots
+  hipEvent_t rd_ev_[2] = {nullptr, nullptr};
+  double rd_val_[2] = {0, 0};
   int resident_ = 512;             // gemm_kernel workgroups resident at once (2 per CU)
   void *pin_ = nullptr;
   void *cws_ = nullptr;

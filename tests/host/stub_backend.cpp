@@ -18,6 +18,8 @@ namespace bpki {
 namespace {
 
 class StubBackend : public Backend {
+  double rd_[2] = {0, 0};
+
  public:
   int set_allocator(DevAlloc a, DevFree f, void *user) override {
     if (touched_ || !a != !f) return -1;
@@ -62,6 +64,10 @@ class StubBackend : public Backend {
   void d2h(void *h, const void *d, size_t b) override {
     if (!err_ && b) std::memcpy(h, d, b);
   }
+  void read_async(const double *src, int slot) override {
+    if (!err_) std::memcpy(&rd_[slot & 1], src, 8);
+  }
+  double wait_read(int slot) override { return rd_[slot & 1]; }
   void d2d(void *d, const void *s, size_t b) override {
     if (!err_ && b) std::memmove(d, s, b);
   }

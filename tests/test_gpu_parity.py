@@ -760,3 +760,38 @@ def test_degree3_pair_chi72_tree_exact(ctx):
     assert np.abs(g["z"] - want).max() < 1e-10
     o = _ora(h, 0.8, 4, 72)
     assert np.abs(g["z"] - o.z).max() < TOL
+
+
+# --- BP to convergence: pipelined sweeps against one sweep at a time ----------------------------
+
+@pytest.mark.parametrize("chi,warm", [(16, 10), (64, 8)])
+def test_bp_pipelined_equals_one_sweep_at_a_time(ctx, chi, warm):
+    """`bp` launches a sweep before the previous residual is back on the host when the residual is
+    predicted to stay above the tolerance, and commits it only once that residual asks for it.
+    From the same state (127 qubits after the gate layers of a step, chi = 16 and chi = 64, the
+    latter through the fused closing; late enough that the light cone has wrapped the loops and
+    BP needs many sweeps) it must give exactly the sweeps, residual and messages of `bp_sweep`
+    called until the residual is below the tolerance."""
+    print(f"[parity] pipelined BP vs single sweeps, chi={chi}", flush=True)
+    lat = L.eagle()
+    s = _session(ctx, lat, 0.8, warm + 1, chi)
+    for _ in range(warm):
+        s.step()
+    s.apply_rx()
+    for c in range(3):
+        s.apply_layer(c)
+    t, m, b = s.get_state()
+    it, r, rc = s.bp()
+    _, m_a, _ = s.get_state()
+    s.set_state(t, m, b)
+    n, rr = 0, math.inf
+    while n < 1000:
+        rr = s.bp_sweep()
+        n += 1
+        if rr < 1e-12:
+            break
+    _, m_b, _ = s.get_state()
+    s.close()
+    assert rc == 0 and it > 5
+    assert n == it and rr == r
+    assert np.array_equal(m_a, m_b)
