@@ -1289,7 +1289,8 @@ extern "C" int bpki_test_bp_close(bpki_ctx *c, int precision, int store32, int64
   }
   be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
   BpCloseDesc d;
-  d.rs = rs; d.qs = qs; d.cs = cs; d.ss = ss;
+  d.rs[0] = rs; d.qs[0] = qs; d.cs[0] = cs; d.ss = ss;
+  d.group = nprob;
   d.prec = precision == BPKI_FP32 ? 1 : 0;
   d.s32 = store32;
   be->bp_close(d, (const double *const *)ptrs, (const double *const *)(ptrs + nprob),

@@ -44,11 +44,14 @@ struct GemmDesc {
 // out[b][b'] = sum_{s, x, a} W[b][a] conj(T[s; b', a, x]),  W[b][a] = sum_{a0} Y[s; b, a0, x] M[a0][a],
 // with Y the site tensor T after the message of the chunk leg x was absorbed, M the incoming
 // message of the applied leg a and b the outgoing leg.  Strides (complex elements) of the
-// outgoing, applied and chunk legs and of s, shared by Y and T.  The output is exactly Hermitian
-// (lower triangle summed, upper triangle its mirror, real diagonal).
+// outgoing, applied and chunk legs (one set per group of `group` consecutive problems, up to three
+// sets: the three outgoing legs of a site in one launch) and of s, shared by Y and T.  The output is
+// exactly Hermitian (lower triangle summed, upper triangle its mirror, real diagonal).
 struct BpCloseDesc {
   int chi = 64;
-  long rs = 0, qs = 0, cs = 0, ss = 0;
+  int nsets = 1, group = 1;              // problem p uses stride set min(p / group, nsets - 1)
+  long rs[3] = {0, 0, 0}, qs[3] = {0, 0, 0}, cs[3] = {0, 0, 0};
+  long ss = 0;
   int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA
   int s32 = 0;                           // Y and T stored as complex FP32 (prec = 1 only)
 };

@@ -983,16 +983,24 @@ void Engine::build() {
         }
         add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[0], b[0], cc[0]);
         add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[1], b[1], cc[1]);
+        // the three outgoing legs in one launch: problems [36 o, 36 o + 36) take stride set o
         const int qleg[3] = {2, 2, 0}, cleg[3] = {1, 0, 1};
+        BpCloseDesc f;
+        f.chi = chi;
+        f.nsets = 3;
+        f.group = (int)fy[0].size();
+        f.ss = L3.s;
+        std::vector<const void *> ay, at, am, ao;
         for (int o = 0; o < 3; ++o) {
-          BpCloseDesc f;
-          f.chi = chi;
-          f.rs = L3.leg[o];
-          f.qs = L3.leg[qleg[o]];
-          f.cs = L3.leg[cleg[o]];
-          f.ss = L3.s;
-          add_fused(C.ops, f, fy[o], ft[o], fm[o], fo[o]);
+          f.rs[o] = L3.leg[o];
+          f.qs[o] = L3.leg[qleg[o]];
+          f.cs[o] = L3.leg[cleg[o]];
+          ay.insert(ay.end(), fy[o].begin(), fy[o].end());
+          at.insert(at.end(), ft[o].begin(), ft[o].end());
+          am.insert(am.end(), fm[o].begin(), fm[o].end());
+          ao.insert(ao.end(), fo[o].begin(), fo[o].end());
         }
+        add_fused(C.ops, f, ay, at, am, ao);
       } else {
         std::vector<const void *> a[8], b[8], cc[8];
         for (int v = 0; v < P.n; ++v) {

@@ -583,12 +583,24 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
   int bj[3];
 #pragma unroll
   for (int jj = 0; jj < 3; ++jj) bj[jj] = (wv + jj) & 3;
-  const long yrow = (long)(16 * w + c) * d.rs;
-  // this thread's 16 elements u of a T slice: lane along whichever of b', a is unit-stride,
-  // w + 4 u along the other
-  const bool a_fast = d.qs == 1;
-  const int ta = a_fast ? lane : w, tb = a_fast ? w : lane;      // element 0; u adds 4 u to the other
-  const long toff0 = (long)tb * d.rs + (long)ta * d.qs, tstep = 4 * (a_fast ? d.rs : d.qs);
+  // strides of the current problem (workgroup-uniform), set when a problem starts
+  long rs = 0, qs = 0, cs = 0, yrow = 0, toff0 = 0, tstep = 0;
+  bool a_fast = true;
+  int ta = 0, tb = 0;
+  auto set_strides = [&](int p) {
+    const int k = min(p / d.group, d.nsets - 1);
+    rs = d.rs[k];
+    qs = d.qs[k];
+    cs = d.cs[k];
+    yrow = (long)(16 * w + c) * rs;
+    // this thread's 16 elements u of a T slice: lane along whichever of b', a is unit-stride,
+    // w + 4 u along the other
+    a_fast = qs == 1;
+    ta = a_fast ? lane : w;
+    tb = a_fast ? w : lane;            // element 0; u adds 4 u to the other
+    toff0 = (long)tb * rs + (long)ta * qs;
+    tstep = 4 * (a_fast ? rs : qs);
+  };
   acc_t acc2[3][3];
   auto clear2 = [&]() {
 #pragma unroll
@@ -614,12 +626,12 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
   };
   auto chunk_base = [&](long k) {
     const int j = (int)(k % J);
-    return (long)(j / C) * d.ss + (long)(j % C) * d.cs;
+    return (long)(j / C) * d.ss + (long)(j % C) * cs;
   };
   st_t yv[16], tn[16];
   auto load_y = [&](const st_t *Y, long base) {
 #pragma unroll
-    for (int t = 0; t < 16; ++t) yv[t] = Y[base + yrow + (long)(4 * t + g) * d.qs];
+    for (int t = 0; t < 16; ++t) yv[t] = Y[base + yrow + (long)(4 * t + g) * qs];
   };
   auto load_t = [&](const st_t *Tt, long base) {
 #pragma unroll
@@ -646,6 +658,7 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
         clear2();
       }
       cur = p;
+      set_strides(p);
       Y = reinterpret_cast<const st_t *>(Yp[p]);
       Tt = reinterpret_cast<const st_t *>(Tp[p]);
       const double2 *M = reinterpret_cast<const double2 *>(Mp[p]);
@@ -3015,8 +3028,11 @@ class HipBackend : public Backend {
   void bp_close(const BpCloseDesc &d, const double *const *Y, const double *const *T,
                 const double *const *M, double *const *out, int nprob) override {
     if (nprob <= 0) return;
-    if (d.chi != kBpCloseChi || (d.s32 && d.prec != 1) || d.rs < 0 || d.qs < 0 || d.cs < 0 ||
-        d.ss < 0) {
+    bool bad = d.chi != kBpCloseChi || (d.s32 && d.prec != 1) || d.ss < 0 || d.nsets < 1 ||
+               d.nsets > 3 || d.group < 1;
+    for (int k = 0; k < 3 && !bad; ++k)
+      bad = k < d.nsets && (d.rs[k] < 0 || d.qs[k] < 0 || d.cs[k] < 0);
+    if (bad) {
       if (err_ == 0) {
         err_ = -1;
         errmsg_ = "bp_close: unsupported descriptor";
