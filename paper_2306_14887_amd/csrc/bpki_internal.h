@@ -40,10 +40,11 @@ struct GemmDesc {
   int a32 = 0, b32 = 0, c32 = 0;
 };
 
-// The BP message of a degree-3 site towards one leg, in one fused pass (chi = 64 only):
+// The BP message of a site towards one leg, in one fused pass (chi = 64 only):
 // out[b][b'] = sum_{s, x, a} W[b][a] conj(T[s; b', a, x]),  W[b][a] = sum_{a0} Y[s; b, a0, x] M[a0][a],
-// with Y the site tensor T after the message of the chunk leg x was absorbed, M the incoming
-// message of the applied leg a and b the outgoing leg.  Strides (complex elements) of the
+// with Y the site tensor T after the message of the chunk leg x was absorbed (degree 3), or T itself
+// with no chunk leg (degree 2: xdim = 1), M the incoming message of the applied leg a and b the
+// outgoing leg.  Strides (complex elements) of the
 // outgoing, applied and chunk legs (one set per group of `group` consecutive problems, up to three
 // sets: the three outgoing legs of a site in one launch) and of s, shared by Y and T.  The output is
 // exactly Hermitian (lower triangle summed, upper triangle its mirror, real diagonal).
@@ -52,6 +53,7 @@ struct BpCloseDesc {
   int nsets = 1, group = 1;              // problem p uses stride set min(p / group, nsets - 1)
   long rs[3] = {0, 0, 0}, qs[3] = {0, 0, 0}, cs[3] = {0, 0, 0};
   long ss = 0;
+  int xdim = 64;                         // extent of the chunk leg (64), or 1 without one
   int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA
   int s32 = 0;                           // Y and T stored as complex FP32 (prec = 1 only)
 };
@@ -104,7 +106,7 @@ struct Backend {
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,
                     double *const *C, int nprob) = 0;
-  // Fused degree-3 BP closings of nprob sites (BpCloseDesc); out: FP64 chi x chi messages.
+  // Fused BP closings of nprob messages (BpCloseDesc); out: FP64 chi x chi messages.
   virtual void bp_close(const BpCloseDesc &d, const double *const *Y, const double *const *T,
                         const double *const *M, double *const *out, int nprob) = 0;
   // Batched Hermitian eigendecomposition (FP64).  in[p]: n x n (lda), read only; its Hermitian

@@ -1027,7 +1027,29 @@ void Engine::build() {
         add_op(C.ops, hclose(3, 1, L3), a[6], b[6], cc[6]);
         add_op(C.ops, hclose(3, 2, L3), a[7], b[7], cc[7]);
       }
-      {
+      if (chi == kBpCloseChi) {
+        // degree 2 at chi = 64, fused: out_o = close(T, apply the other leg's message), the chunks
+        // being the two values of s (no chunk leg); both legs of every site in one launch
+        std::vector<const void *> ft, fm, fo;
+        BpCloseDesc f;
+        f.chi = chi;
+        f.nsets = 2;
+        f.xdim = 1;
+        f.ss = L2.s;
+        for (int o = 0; o < 2; ++o) {
+          f.rs[o] = L2.leg[o];
+          f.qs[o] = L2.leg[1 - o];
+          f.cs[o] = 0;
+          for (int v = 0; v < P.n; ++v) {
+            if (P.deg[v] != 2 || cls[v] != c) continue;
+            ft.push_back(Tp(v));
+            fm.push_back(in(v, 1 - o));
+            fo.push_back(Mnp(P.out_msg[v][o]));
+          }
+        }
+        f.group = (int)ft.size() / 2;
+        add_fused(C.ops, f, ft, ft, fm, fo);
+      } else {
         std::vector<const void *> a[4], b[4], cc[4];
         for (int v = 0; v < P.n; ++v) {
           if (P.deg[v] != 2 || cls[v] != c) continue;

@@ -544,8 +544,8 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
 // outgoing leg b sums, over chunks (s, x) of the chunk leg,
 //   W[b][a] = sum_{a0} Y[b][a0] M[a0][a]          (Y, T: the chunk's 64 x 64 slices)
 //   out[b][b'] += sum_a W[b][a] conj(T[b'][a]).
-// A workgroup owns a contiguous range of the chunks of all problems (a problem's 128 chunks may
-// be split between two workgroups).  Per chunk, wave w forms the 64 x 16 strip W^T[.][b-block w]
+// A workgroup owns a contiguous range of the chunks of all problems (a problem's chunks, 128 for a
+// degree-3 site and 2 for a degree-2 site, may be split between two workgroups).  Per chunk, wave w forms the 64 x 16 strip W^T[.][b-block w]
 // on MFMA: A = M^T from LDS, B = Y from registers.  The MFMA accumulator of that strip holds, in
 // lane l and register r of tile i, W[16 w + l % 16][16 i + row(l, r)]: exactly the A operand of
 // the second product for k step (i, r) when the k index of that step is taken as
@@ -572,7 +572,8 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
   typedef typename MT::acc_t acc_t;
   typedef Cx<S32> X;
   typedef typename X::t st_t;
-  constexpr int C = kBpCloseChi, J = 2 * kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  constexpr int C = kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  const int J = 2 * d.xdim;              // chunks per problem: (s, x)
   constexpr int P = BpCloseCfg<T>::PAD;
   __shared__ T Ms[2][C][C + P];       // M[a0][a]
   __shared__ T Ts[2][C][C + P];       // T[b'][a] of the chunk, stored as [a][b']
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
   };
   auto chunk_base = [&](long k) {
     const int j = (int)(k % J);
-    return (long)(j / C) * d.ss + (long)(j % C) * cs;
+    return (long)(j / d.xdim) * d.ss + (long)(j % d.xdim) * cs;
   };
   st_t yv[16], tn[16];
   auto load_y = [&](const st_t *Y, long base) {
@@ -726,11 +727,11 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
   if (cur >= 0) flush(slot);
 }
 
-// Message p of a fused BP closing: the partial sums of the workgroups that covered its chunks,
-// in workgroup order; lower triangle, its mirror above, real diagonal.  grid (16, nprob).
-__global__ __launch_bounds__(256) void bp_close_reduce_kernel(int per, const double2 *part,
+// Message p of a fused BP closing: the partial sums of the workgroups that covered its chunks (J per
+// problem), in workgroup order; lower triangle, its mirror above, real diagonal.  grid (16, nprob).
+__global__ __launch_bounds__(256) void bp_close_reduce_kernel(int per, int J, const double2 *part,
                                                               double *const *Op) {
-  constexpr int C = kBpCloseChi, J = 2 * kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  constexpr int C = kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
   const int p = blockIdx.y;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= CC) return;
@@ -3029,7 +3030,7 @@ class HipBackend : public Backend {
                 const double *const *M, double *const *out, int nprob) override {
     if (nprob <= 0) return;
     bool bad = d.chi != kBpCloseChi || (d.s32 && d.prec != 1) || d.ss < 0 || d.nsets < 1 ||
-               d.nsets > 3 || d.group < 1;
+               d.nsets > 3 || d.group < 1 || (d.xdim != 1 && d.xdim != kBpCloseChi);
     for (int k = 0; k < 3 && !bad; ++k)
       bad = k < d.nsets && (d.rs[k] < 0 || d.qs[k] < 0 || d.cs[k] < 0);
     if (bad) {
@@ -3041,7 +3042,7 @@ class HipBackend : public Backend {
     }
     // one round of resident workgroups (FP64: one per CU, FP32: two), each a contiguous run of
     // `per` chunks (at most one problem's 128, so a workgroup touches at most two problems)
-    const long J = 2L * kBpCloseChi, total = J * nprob;
+    const long J = 2L * d.xdim, total = J * nprob;
     const long slots = d.prec == 1 ? resident_ : std::max(1, resident_ / 2);
     const int per = (int)std::max(1L, std::min(J, (total + slots - 1) / slots));
     const int nwg = (int)((total + per - 1) / per);
@@ -3079,7 +3080,7 @@ class HipBackend : public Backend {
     }
     stale_check("bp_close_reduce_kernel");
     hipLaunchKernelGGL(bp_close_reduce_kernel, dim3(kBpCloseChi * kBpCloseChi / 256, nprob),
-                       dim3(256), 0, s_, per, (const double2 *)W, out);
+                       dim3(256), 0, s_, per, (int)J, (const double2 *)W, out);
     launch_check("bp_close_reduce_kernel");
   }
   void *splitk_ws(size_t need) {
