@@ -8,10 +8,11 @@ The first --warmup steps (default 6: bonds saturate at chi = 64 after 6 steps) a
 next --steps steps are timed, so the default run is steps 7..20 of the 20-step circuit.
 
 The JSON line also carries:
-  roofline     : the dominant kernel of the step, the fused degree-3 BP closing
-                 (bp_close_kernel<double>: one leg absorption and the Hermitian closing of a
-                 message, chunk by chunk, without writing the intermediate), algorithmic flops
-                 8*(2 chi^4 + chi^3 (chi + 1)) per message over the HIP-event-timed launch
+  roofline     : the dominant kernel of the step, the fused BP closing (bp_close_kernel<double>:
+                 the leg absorption and the Hermitian closing of a message, chunk by chunk, without
+                 writing the intermediate; degree-3 and degree-2 sites), algorithmic flops
+                 8*(2 chi^4 + chi^3 (chi + 1)) per degree-3 message (8*(2 chi^3 + chi^2 (chi + 1))
+                 per degree-2 one) over the HIP-event-timed launch
                  durations (every 7th contraction launch of the timed window), against the MI355X
                  FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the committed
                  rocprofv3 counter summary (null once the kernel source has changed); achievable =

@@ -302,13 +302,15 @@ int bpki_session_clifford_inverse_step(bpki_session *s, double *z, int32_t *iter
  * BP, observables.  Measured with HIP events on the session's stream. */
 int bpki_session_last_timing(const bpki_session *s, double *ms4);
 /* Kernel-level timing of the contraction kernels (every contraction of the method runs in them:
- * the complex GEMM kernels and, for degree-3 sites at chi = 64, the fused BP closing): with stride
+ * the complex GEMM kernels and, for the BP messages of degree-2 and degree-3 sites at chi = 64, the
+ * fused BP closing): with stride
  * k >= 1, every k-th launch on the session's stream is bracketed by HIP events (each event pair
  * costs a few microseconds of stream time, so a stride above 1 keeps the measurement from slowing
  * the run it measures); stride 0 turns it off.  read returns the bracketed launch count, the
  * summed kernel time in ms and the summed algorithmic flops of those launches (complex
  * multiply-adds at 8 real flops: 8*M*N*K for a GEMM, 8*K*M(M+1)/2 for a Hermitian output, of which
- * only the lower triangle is computed; 8*(2 chi^4 + chi^3 (chi + 1)) per fused message), and
+ * only the lower triangle is computed; 8*(2 chi^4 + chi^3 (chi + 1)) per fused degree-3 message,
+ * 8*(2 chi^3 + chi^2 (chi + 1)) per fused degree-2 message), and
  * optionally the count of all launches since enabling.  Enabling resets the counters. */
 int bpki_session_profile(bpki_session *s, int stride);
 int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, double *flops,
@@ -318,7 +320,7 @@ int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, do
 int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int64_t *launches, double *ms,
                                    double *flops);
 /* The same restricted to one kernel and one arithmetic: kernel 0 = the GEMM kernels, 1 = the fused
- * degree-3 BP closing; prec as above. */
+ * BP closing; prec as above. */
 int bpki_session_profile_read_kernel(bpki_session *s, int32_t kernel, int32_t prec,
                                      int64_t *launches, double *ms, double *flops);
 

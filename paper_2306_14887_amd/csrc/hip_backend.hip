@@ -3071,10 +3071,11 @@ class HipBackend : public Backend {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
       prof_prec_.push_back(2 + (d.prec & 1));
-      // algorithmic work per message: the absorption (2 chi^4) and the distinct entries of the
-      // Hermitian closing (chi (chi + 1) / 2 of them, K = 2 chi^2)
+      // algorithmic work per message, per chunk (2 xdim of them): the absorption W = Y M (chi^3)
+      // and the distinct entries of the Hermitian closing (chi (chi + 1) / 2 of them, K = chi);
+      // a degree-3 site (xdim = chi): 2 chi^4 + chi^3 (chi + 1)
       const double c = kBpCloseChi;
-      const double fl = 8.0 * nprob * (2.0 * c * c * c * c + c * c * c * (c + 1.0));
+      const double fl = 8.0 * nprob * 2.0 * d.xdim * (c * c * c + 0.5 * c * c * (c + 1.0));
       prof_flops_ += fl;
       prof_flops_p_[2 + (d.prec & 1)] += fl;
     }
