@@ -69,7 +69,7 @@ GEMM_SPANS = (("constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;",
                "// Twelve independent MFMA accumulation chains per wave"),
               ("  void gemm(const GemmDesc &d, const double *const *A",
                "  void bp_close(const BpCloseDesc &d,"))
-CLOSE_SPANS = (("// Fused BP closing of degree-3 sites at chi = 64 (BpCloseDesc).",
+CLOSE_SPANS = (("// Fused BP closing at chi = CH = 64 or 32 (BpCloseDesc).",
                 "// Hermitian Jacobi eigensolver"),
                ("  void bp_close(const BpCloseDesc &d,", "  void *splitk_ws(size_t need) {"))
 

@@ -49,16 +49,16 @@ int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const
                    size_t a_elems, const double *B, size_t b_elems, double *C, size_t c_elems);
 
 /* The fused BP message of a site (Methods, "Belief propagation on a tensor network state", Eq.
- * "MessageTensorSelfConsistency") at chi = 64, on nprob problems: with Y, T [nprob][y_elems]
- * site-sized tensors and M [nprob][64][64],
+ * "MessageTensorSelfConsistency") at chi = 32 or 64, on nprob problems: with Y, T [nprob][y_elems]
+ * site-sized tensors and M [nprob][chi][chi],
  *   out[p][b][b'] = sum_{s, x, a} W[b][a] conj(T[p][s ss + b' rs + a qs + x cs]),
  *   W[b][a] = sum_{a0} Y[p][s ss + b rs + a0 qs + x cs] M[p][a0][a],
- * s in {0, 1}, x in [0, xdim), b, b', a, a0 in [0, 64); strides in complex elements; xdim = 64 (a
+ * s in {0, 1}, x in [0, xdim), b, b', a, a0 in [0, chi); strides in complex elements; xdim = chi (a
  * degree-3 site, Y holding the chunk leg's message already) or 1 (a degree-2 site, Y = T).  out
- * [nprob][64][64] is exactly Hermitian.  precision BPKI_FP64 or BPKI_FP32 (FP32 MFMA); store32 = 1
+ * [nprob][chi][chi] is exactly Hermitian.  precision BPKI_FP64 or BPKI_FP32 (FP32 MFMA); store32 = 1
  * holds Y and T as complex FP32 on the device (BPKI_FP32 only). */
-int bpki_test_bp_close(bpki_ctx *ctx, int precision, int store32, int64_t rs, int64_t qs,
-                       int64_t cs, int64_t ss, int32_t xdim, int nprob, const double *Y,
+int bpki_test_bp_close(bpki_ctx *ctx, int32_t chi, int precision, int store32, int64_t rs,
+                       int64_t qs, int64_t cs, int64_t ss, int32_t xdim, int nprob, const double *Y,
                        const double *T, size_t y_elems, const double *M, double *out);
 
 /* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32, Householder

@@ -1245,16 +1245,16 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
   return e ? fail(e, msg) : 0;
 }
 
-extern "C" int bpki_test_bp_close(bpki_ctx *c, int precision, int store32, int64_t rs,
-                                  int64_t qs, int64_t cs, int64_t ss, int32_t xdim, int nprob,
-                                  const double *Y, const double *T, size_t y_elems,
+extern "C" int bpki_test_bp_close(bpki_ctx *c, int32_t chi, int precision, int store32,
+                                  int64_t rs, int64_t qs, int64_t cs, int64_t ss, int32_t xdim,
+                                  int nprob, const double *Y, const double *T, size_t y_elems,
                                   const double *M, double *out) {
-  if (!c || !Y || !T || !M || !out || nprob < 1 ||
+  if (!c || !Y || !T || !M || !out || nprob < 1 || !bp_close_chi(chi) ||
       (precision != BPKI_FP64 && precision != BPKI_FP32) || (store32 != 0 && store32 != 1) ||
-      (store32 && precision != BPKI_FP32) || (xdim != 1 && xdim != kBpCloseChi))
+      (store32 && precision != BPKI_FP32) || (xdim != 1 && xdim != chi))
     return fail(-1, "bad argument");
   if (rs < 0 || qs < 0 || cs < 0 || ss < 0) return fail(-1, "negative stride");
-  const long C = kBpCloseChi;
+  const long C = chi;
   if ((size_t)((C - 1) * (rs + qs) + (xdim - 1) * cs + ss) >= y_elems)
     return fail(-1, "strides address outside the tensors");
   Backend *be = c->be.get();
@@ -1290,6 +1290,7 @@ extern "C" int bpki_test_bp_close(bpki_ctx *c, int precision, int store32, int64
   }
   be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
   BpCloseDesc d;
+  d.chi = chi;
   d.rs[0] = rs; d.qs[0] = qs; d.cs[0] = cs; d.ss = ss;
   d.xdim = xdim;
   d.group = nprob;

@@ -40,7 +40,7 @@ struct GemmDesc {
   int a32 = 0, b32 = 0, c32 = 0;
 };
 
-// The BP message of a site towards one leg, in one fused pass (chi = 64 only):
+// The BP message of a site towards one leg, in one fused pass (chi = 32 or 64):
 // out[b][b'] = sum_{s, x, a} W[b][a] conj(T[s; b', a, x]),  W[b][a] = sum_{a0} Y[s; b, a0, x] M[a0][a],
 // with Y the site tensor T after the message of the chunk leg x was absorbed (degree 3), or T itself
 // with no chunk leg (degree 2: xdim = 1), M the incoming message of the applied leg a and b the
@@ -53,11 +53,12 @@ struct BpCloseDesc {
   int nsets = 1, group = 1;              // problem p uses stride set min(p / group, nsets - 1)
   long rs[3] = {0, 0, 0}, qs[3] = {0, 0, 0}, cs[3] = {0, 0, 0};
   long ss = 0;
-  int xdim = 64;                         // extent of the chunk leg (64), or 1 without one
+  int xdim = 64;                         // extent of the chunk leg (chi), or 1 without one
   int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA
   int s32 = 0;                           // Y and T stored as complex FP32 (prec = 1 only)
 };
-constexpr int kBpCloseChi = 64;
+// The bond dimensions the fused closing is built for.
+inline bool bp_close_chi(int chi) { return chi == 64 || chi == 32; }
 
 // Simple composite-index helpers for descriptors.
 inline void set_simple_m(GemmDesc &d, int M, long sa, long sc) { d.M = M; d.Mi = M; d.a_mi = sa; d.c_mi = sc; }

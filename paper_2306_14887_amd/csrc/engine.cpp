@@ -959,13 +959,13 @@ void Engine::build() {
       Plan::BpClass C, C32;
       ops32 = mixed ? &C32.ops : nullptr;
       auto in = [&](int v, int i) { return cls[P.nb[v][i]] < c ? Mnp(P.in_msg[v][i]) : Mp(P.in_msg[v][i]); };
-      // degree 3 at chi = 64, fused: Y1 = T x1 M1 ; Y0 = T x0 M0 (two leg absorptions), then
+      // degree 3 at chi = 32 or 64, fused: Y1 = T x1 M1 ; Y0 = T x0 M0 (two leg absorptions), then
       //   out0 = close(Y1, apply M2, chunks over leg 1), out2 = close(Y1, apply M0, chunks over
       //   leg 1), out1 = close(Y0, apply M2, chunks over leg 0)
       // so that the slices of every chunk run along a unit-stride leg.  Otherwise:
       // Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
       // Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
-      if (chi == kBpCloseChi) {
+      if (bp_close_chi(chi)) {
         std::vector<const void *> a[2], b[2], cc[2], fy[3], ft[3], fm[3], fo[3];
         for (int v = 0; v < P.n; ++v) {
           if (P.deg[v] != 3 || cls[v] != c) continue;
@@ -987,6 +987,7 @@ void Engine::build() {
         const int qleg[3] = {2, 2, 0}, cleg[3] = {1, 0, 1};
         BpCloseDesc f;
         f.chi = chi;
+        f.xdim = chi;
         f.nsets = 3;
         f.group = (int)fy[0].size();
         f.ss = L3.s;
@@ -1027,8 +1028,8 @@ void Engine::build() {
         add_op(C.ops, hclose(3, 1, L3), a[6], b[6], cc[6]);
         add_op(C.ops, hclose(3, 2, L3), a[7], b[7], cc[7]);
       }
-      if (chi == kBpCloseChi) {
-        // degree 2 at chi = 64, fused: out_o = close(T, apply the other leg's message), the chunks
+      if (bp_close_chi(chi)) {
+        // degree 2 at chi = 32 or 64, fused: out_o = close(T, apply the other leg's message), the chunks
         // being the two values of s (no chunk leg); both legs of every site in one launch
         std::vector<const void *> ft, fm, fo;
         BpCloseDesc f;

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -540,120 +541,137 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused BP closing of degree-3 sites at chi = 64 (BpCloseDesc).  The message towards the
-// outgoing leg b sums, over chunks (s, x) of the chunk leg,
-//   W[b][a] = sum_{a0} Y[b][a0] M[a0][a]          (Y, T: the chunk's 64 x 64 slices)
+// Fused BP closing at chi = CH = 64 or 32 (BpCloseDesc).  The message towards the outgoing leg b
+// sums, over chunks (s, x) of the chunk leg (s alone for a degree-2 site),
+//   W[b][a] = sum_{a0} Y[b][a0] M[a0][a]          (Y, T: the chunk's CH x CH slices)
 //   out[b][b'] += sum_a W[b][a] conj(T[b'][a]).
-// A workgroup owns a contiguous range of the chunks of all problems (a problem's chunks, 128 for a
-// degree-3 site and 2 for a degree-2 site, may be split between two workgroups).  Per chunk, wave w forms the 64 x 16 strip W^T[.][b-block w]
-// on MFMA: A = M^T from LDS, B = Y from registers.  The MFMA accumulator of that strip holds, in
-// lane l and register r of tile i, W[16 w + l % 16][16 i + row(l, r)]: exactly the A operand of
-// the second product for k step (i, r) when the k index of that step is taken as
-// 16 i + row(l, r) (the B operand, conj(T), uses the same k map).  So W never leaves the
-// registers and the intermediates of the chain never reach memory.  The second product covers
-// the ten 16 x 16 blocks of the Hermitian output once each: wave w computes blocks (w, w),
-// (w, w + 1 mod 4) and, for w < 2, (w, w + 2); blocks above the diagonal are stored as their
-// mirrors.  The chunk's T slice sits in LDS (transposed, [a][b']), and the next chunk's Y values
-// and T slice are loaded into registers while this chunk is multiplied.  Complex products by the
-// 3M method as in gemm_kernel.  The workgroup's partial sums (lower triangle) go to
-// part[wg][slot] (slot 0: its first problem, 1: the next); bp_close_reduce_kernel adds them in
-// workgroup order.  FP64: one workgroup per CU (LDS and registers); FP32: two.
-// grid: workgroups, each `per` chunks.
-template <typename T>
+// A workgroup owns a contiguous range of the chunks of all problems (a problem's 2 xdim chunks may
+// be split between two workgroups) and works on G = 64 / CH chunks at a time, NT = CH / 16 waves
+// each.  Per chunk, wave wl of its group forms the CH x 16 strip W^T[.][b-block wl] on MFMA:
+// A = M^T from LDS, B = Y from registers.  The MFMA accumulator of that strip holds, in lane l and
+// register r of tile i, W[16 wl + l % 16][16 i + row(l, r)]: exactly the A operand of the second
+// product for k step (i, r) when the k index of that step is taken as 16 i + row(l, r) (the B
+// operand, conj(T), uses the same k map).  So W never leaves the registers and the intermediates of
+// the chain never reach memory.  The second product covers the 16 x 16 blocks of the Hermitian
+// output on or below the diagonal once each: wave wl computes blocks (wl, wl + d mod NT) for
+// d = 0 .. NT / 2, the last one only for wl < NT / 2; blocks above the diagonal are stored as their
+// mirrors.  The chunks' T slices sit in LDS (transposed, [a][b']), and the next chunks' Y values and
+// T slices are loaded into registers while these chunks are multiplied.  Complex products by the
+// 3M method as in gemm_kernel.  Each wave group's partial sums (lower triangle) go to
+// part[wg][slot][group] (slot 0: the workgroup's first problem, 1: the next);
+// bp_close_reduce_kernel adds them in workgroup order.  FP64 at CH = 64: one workgroup per CU (LDS
+// and registers); otherwise two.  grid: workgroups, each `per` chunks (a multiple of G).
+template <typename T, int CH>
 struct BpCloseCfg {
-  static constexpr int PAD = std::is_same<T, double>::value ? 8 : 4;    // LDS row padding
-  static constexpr int WGS = std::is_same<T, double>::value ? 1 : 2;    // workgroups per CU
+  static constexpr bool F64 = std::is_same<T, double>::value;
+  static constexpr int PAD = F64 ? 8 : 4;                 // LDS row padding
+  static constexpr int WGS = (F64 && CH == 64) ? 1 : 2;   // workgroups per CU
+  static constexpr int NT = CH / 16;                      // 16-row tiles per side
+  static constexpr int KS = CH / 4;                       // k steps of the first product
+  static constexpr int G = 64 / CH;                       // chunks in flight, NT waves each
+  static constexpr int NB = NT / 2 + 1;                   // most output blocks of one wave
 };
-template <typename T, bool S32>
-__global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
+template <typename T, bool S32, int CH>
+__global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel(
     BpCloseDesc d, const double *const *Yp, const double *const *Tp, const double *const *Mp,
-    long total, int per, double2 *part) {
+    int total, int per, double2 *part) {
   typedef MfmaTraits<T> MT;
   typedef typename MT::acc_t acc_t;
   typedef Cx<S32> X;
   typedef typename X::t st_t;
-  constexpr int C = kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  typedef BpCloseCfg<T, CH> Cfg;
+  constexpr int CC = CH * CH, NT = Cfg::NT, KS = Cfg::KS, G = Cfg::G, NB = Cfg::NB;
+  constexpr int P = Cfg::PAD;
   const int J = 2 * d.xdim;              // chunks per problem: (s, x)
-  constexpr int P = BpCloseCfg<T>::PAD;
-  __shared__ T Ms[2][C][C + P];       // M[a0][a]
-  __shared__ T Ts[2][C][C + P];       // T[b'][a] of the chunk, stored as [a][b']
+  __shared__ T Ms[2][CH][CH + P];        // M[a0][a]
+  __shared__ T Ts[G][2][CH][CH + P];     // per chunk in flight: T[b'][a], stored as [a][b']
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
   const int wv = __builtin_amdgcn_readfirstlane(w);
-  const int nb = wv < 2 ? 3 : 2;
-  int bj[3];
+  const int q = G == 1 ? 0 : wv / NT;    // this wave's chunk in flight
+  const int wl = G == 1 ? wv : wv % NT;  // and its 16 rows b
+  const int nb = NT / 2 + (wl < NT / 2 ? 1 : 0);
+  int bj[NB];
 #pragma unroll
-  for (int jj = 0; jj < 3; ++jj) bj[jj] = (wv + jj) & 3;
+  for (int jj = 0; jj < NB; ++jj) bj[jj] = (wl + jj) % NT;
   // strides of the current problem (workgroup-uniform), set when a problem starts
   long rs = 0, qs = 0, cs = 0, yrow = 0, toff0 = 0, tstep = 0;
   bool a_fast = true;
-  int ta = 0, tb = 0;
+  // this thread's TU elements u of a chunk's T slice: tid % CH along whichever of b', a is
+  // unit-stride, tid / CH + HS u along the other
+  constexpr int TU = CC / 256, HS = 256 / CH;
+  const int tlo = tid % CH, thi = tid / CH;
   auto set_strides = [&](int p) {
     const int k = min(p / d.group, d.nsets - 1);
     rs = d.rs[k];
     qs = d.qs[k];
     cs = d.cs[k];
-    yrow = (long)(16 * w + c) * rs;
-    // this thread's 16 elements u of a T slice: lane along whichever of b', a is unit-stride,
-    // w + 4 u along the other
+    yrow = (long)(16 * wl + c) * rs;
     a_fast = qs == 1;
-    ta = a_fast ? lane : w;
-    tb = a_fast ? w : lane;            // element 0; u adds 4 u to the other
-    toff0 = (long)tb * rs + (long)ta * qs;
-    tstep = 4 * (a_fast ? rs : qs);
+    toff0 = a_fast ? (long)thi * rs + tlo : (long)tlo * rs + (long)thi * qs;
+    tstep = HS * (a_fast ? rs : qs);
   };
-  acc_t acc2[3][3];
+  acc_t acc2[NB][3];
   auto clear2 = [&]() {
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj)
+    for (int jj = 0; jj < NB; ++jj)
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc2[jj][t] = (acc_t){T(0), T(0), T(0), T(0)};
   };
-  // the workgroup's lower-triangle partial sum of one problem
+  // the lower-triangle partial sum of one problem over this wave group's chunks
   auto flush = [&](int slot) {
-    double2 *Pp = part + ((size_t)blockIdx.x * 2 + slot) * CC;
+    double2 *Pp = part + (((size_t)blockIdx.x * 2 + slot) * G + q) * CC;
 #pragma unroll
-    for (int jj = 0; jj < 3; ++jj) {
+    for (int jj = 0; jj < NB; ++jj) {
       if (jj >= nb) break;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int b = 16 * w + MT::row(lane, r), bp = 16 * bj[jj] + c;
+        const int b = 16 * wl + MT::row(lane, r), bp = 16 * bj[jj] + c;
         const double re = (double)acc2[jj][0][r] - (double)acc2[jj][1][r];
         const double im = (double)acc2[jj][2][r] - (double)acc2[jj][0][r] - (double)acc2[jj][1][r];
-        if (b >= bp) Pp[b * C + bp] = make_double2(re, im);
-        else if (bj[jj] != wv) Pp[bp * C + b] = make_double2(re, -im);
+        if (b >= bp) Pp[b * CH + bp] = make_double2(re, im);
+        else if (bj[jj] != wl) Pp[bp * CH + b] = make_double2(re, -im);
       }
     }
   };
-  auto chunk_base = [&](long k) {
-    const int j = (int)(k % J);
+  auto chunk_base = [&](int k) {
+    const int j = k % J;
     return (long)(j / d.xdim) * d.ss + (long)(j % d.xdim) * cs;
   };
-  st_t yv[16], tn[16];
-  auto load_y = [&](const st_t *Y, long base) {
+  st_t yv[KS], tn[G][TU];
+  auto load_y = [&](const st_t *Y, int k) {      // this wave's Y values of chunk k + q
+    const long base = chunk_base(k + q);
 #pragma unroll
-    for (int t = 0; t < 16; ++t) yv[t] = Y[base + yrow + (long)(4 * t + g) * qs];
+    for (int t = 0; t < KS; ++t) yv[t] = Y[base + yrow + (long)(4 * t + g) * qs];
   };
-  auto load_t = [&](const st_t *Tt, long base) {
+  auto load_t = [&](const st_t *Tt, int k) {     // the T slices of chunks k .. k + G - 1
 #pragma unroll
-    for (int u = 0; u < 16; ++u) tn[u] = Tt[base + toff0 + u * tstep];
+    for (int qq = 0; qq < G; ++qq) {
+      const st_t *src = Tt + chunk_base(k + qq) + toff0;
+#pragma unroll
+      for (int u = 0; u < TU; ++u) tn[qq][u] = src[u * tstep];
+    }
   };
   auto store_t = [&]() {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int a = a_fast ? ta : ta + 4 * u, b = a_fast ? tb + 4 * u : tb;
-      Ts[0][a][b] = T(tn[u].x);
-      Ts[1][a][b] = -T(tn[u].y);          // conj(T)
-    }
+    for (int qq = 0; qq < G; ++qq)
+#pragma unroll
+      for (int u = 0; u < TU; ++u) {
+        const int a = a_fast ? tlo : thi + HS * u, b = a_fast ? thi + HS * u : tlo;
+        Ts[qq][0][a][b] = T(tn[qq][u].x);
+        Ts[qq][1][a][b] = -T(tn[qq][u].y);    // conj(T)
+      }
   };
   clear2();
-  const long k0 = (long)blockIdx.x * per, k1 = min(k0 + per, total);
+  // a workgroup's run of chunks is a multiple of G long and starts at a multiple of G, and so does
+  // every problem (J is even), so the G chunks in flight always belong to one problem
+  const int k0 = blockIdx.x * per, k1 = min(k0 + per, total);
   int cur = -1, slot = 0;
   const st_t *Y = nullptr, *Tt = nullptr;
-  bool ready = false;                    // this chunk's Y values and T slice are in place
-  for (long k = k0; k < k1; ++k) {
-    const int p = (int)(k / J);
-    if (!ready) {                        // first chunk, or a new problem (workgroup-uniform)
+  bool ready = false;                    // this iteration's Y values and T slices are in place
+  for (int k = k0; k < k1; k += G) {
+    const int p = k / J;
+    if (!ready) {                        // first chunks, or a new problem (workgroup-uniform)
       if (cur >= 0) {
         flush(slot++);
         clear2();
@@ -663,45 +681,43 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
       Y = reinterpret_cast<const st_t *>(Yp[p]);
       Tt = reinterpret_cast<const st_t *>(Tp[p]);
       const double2 *M = reinterpret_cast<const double2 *>(Mp[p]);
-      const long base = chunk_base(k);
-      load_y(Y, base);
-      load_t(Tt, base);
+      load_y(Y, k);
+      load_t(Tt, k);
       __syncthreads();
       for (int idx = tid; idx < CC; idx += 256) {
         const double2 v = M[idx];
-        Ms[0][idx / C][idx % C] = T(v.x);
-        Ms[1][idx / C][idx % C] = T(v.y);
+        Ms[0][idx / CH][idx % CH] = T(v.x);
+        Ms[1][idx / CH][idx % CH] = T(v.y);
       }
       store_t();
       __syncthreads();
     }
-    // the next chunk of the same problem: its T slice is loaded while this chunk is multiplied,
-    // its Y values once this chunk's first product has used the current ones
-    ready = k + 1 < k1 && (k + 1) / J == p;
-    const long nbase = ready ? chunk_base(k + 1) : 0;
-    if (ready) load_t(Tt, nbase);
-    // W^T[a][b] = sum_a0 M[a0][a] Y[b][a0], four a tiles by this wave's 16 columns b
-    acc_t acc1[4][3];
+    // the next chunks of the same problem: their T slices are loaded while these chunks are
+    // multiplied, their Y values once this iteration's first product has used the current ones
+    ready = k + G < k1 && (k + G) / J == p;
+    if (ready) load_t(Tt, k + G);
+    // W^T[a][b] = sum_a0 M[a0][a] Y[b][a0], NT a tiles by this wave's 16 columns b
+    acc_t acc1[NT][3];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NT; ++i)
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc1[i][t] = (acc_t){T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
+    for (int t = 0; t < KS; ++t) {
       const int a0 = 4 * t + g;
       const T br = T(yv[t].x), bi = T(yv[t].y), bs = br + bi;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < NT; ++i) {
         const T ar = Ms[0][a0][16 * i + c], ai = Ms[1][a0][16 * i + c], as = ar + ai;
         acc1[i][0] = MT::mma(ar, br, acc1[i][0]);
         acc1[i][1] = MT::mma(ai, bi, acc1[i][1]);
         acc1[i][2] = MT::mma(as, bs, acc1[i][2]);
       }
     }
-    if (ready) load_y(Y, nbase);
+    if (ready) load_y(Y, k + G);
     // out[b][b'] += sum_a W[b][a] conj(T[b'][a]), k step (i, r) <-> a = 16 i + row(lane, r)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NT; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const T wr = acc1[i][0][r] - acc1[i][1][r];
@@ -709,9 +725,10 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
         const T ws = wr + wi;
         const int a = 16 * i + MT::row(lane, r);
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
+        for (int jj = 0; jj < NB; ++jj) {
           if (jj >= nb) break;
-          const T br = Ts[0][a][16 * bj[jj] + c], bi = Ts[1][a][16 * bj[jj] + c], bs = br + bi;
+          const T br = Ts[q][0][a][16 * bj[jj] + c], bi = Ts[q][1][a][16 * bj[jj] + c];
+          const T bs = br + bi;
           acc2[jj][0] = MT::mma(wr, br, acc2[jj][0]);
           acc2[jj][1] = MT::mma(wi, bi, acc2[jj][1]);
           acc2[jj][2] = MT::mma(ws, bs, acc2[jj][2]);
@@ -719,7 +736,7 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
       }
     }
     if (ready) {
-      __syncthreads();                   // every wave is done with this chunk's T slice
+      __syncthreads();                   // every wave is done with these chunks' T slices
       store_t();
       __syncthreads();
     }
@@ -727,27 +744,31 @@ __global__ __launch_bounds__(256, BpCloseCfg<T>::WGS) void bp_close_kernel(
   if (cur >= 0) flush(slot);
 }
 
-// Message p of a fused BP closing: the partial sums of the workgroups that covered its chunks (J per
-// problem), in workgroup order; lower triangle, its mirror above, real diagonal.  grid (16, nprob).
-__global__ __launch_bounds__(256) void bp_close_reduce_kernel(int per, int J, const double2 *part,
+// Message p of a fused BP closing: the partial sums of the workgroups (and their G chunk groups)
+// that covered its chunks (J per problem), in workgroup order; lower triangle, its mirror above,
+// real diagonal.  grid (ceil(chi^2 / 256), nprob).
+__global__ __launch_bounds__(256) void bp_close_reduce_kernel(int ch, int G, int per, int J,
+                                                              const double2 *part,
                                                               double *const *Op) {
-  constexpr int C = kBpCloseChi, CC = kBpCloseChi * kBpCloseChi;
+  const int CC = ch * ch;
   const int p = blockIdx.y;
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= CC) return;
-  const int b = idx / C, bp = idx % C;
+  const int b = idx / ch, bp = idx % ch;
   if (b < bp) return;
   const long first = (long)p * J, last = first + J - 1;
   double re = 0.0, im = 0.0;
   for (long wg = first / per; wg <= last / per; ++wg) {
     const int slot = (wg * per) / J == p ? 0 : 1;
-    const double2 v = part[((size_t)wg * 2 + slot) * CC + idx];
-    re += v.x;
-    im += v.y;
+    for (int qq = 0; qq < G; ++qq) {
+      const double2 v = part[(((size_t)wg * 2 + slot) * G + qq) * CC + idx];
+      re += v.x;
+      im += v.y;
+    }
   }
   double2 *O = reinterpret_cast<double2 *>(Op[p]);
-  O[b * C + bp] = make_double2(re, b == bp ? 0.0 : im);
-  if (b > bp) O[bp * C + b] = make_double2(re, -im);
+  O[b * ch + bp] = make_double2(re, b == bp ? 0.0 : im);
+  if (b > bp) O[bp * ch + b] = make_double2(re, -im);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -3029,8 +3050,8 @@ class HipBackend : public Backend {
   void bp_close(const BpCloseDesc &d, const double *const *Y, const double *const *T,
                 const double *const *M, double *const *out, int nprob) override {
     if (nprob <= 0) return;
-    bool bad = d.chi != kBpCloseChi || (d.s32 && d.prec != 1) || d.ss < 0 || d.nsets < 1 ||
-               d.nsets > 3 || d.group < 1 || (d.xdim != 1 && d.xdim != kBpCloseChi);
+    bool bad = (d.chi != 64 && d.chi != 32) || (d.s32 && d.prec != 1) || d.ss < 0 ||
+               d.nsets < 1 || d.nsets > 3 || d.group < 1 || (d.xdim != 1 && d.xdim != d.chi);
     for (int k = 0; k < 3 && !bad; ++k)
       bad = k < d.nsets && (d.rs[k] < 0 || d.qs[k] < 0 || d.cs[k] < 0);
     if (bad) {
@@ -3040,14 +3061,23 @@ class HipBackend : public Backend {
       }
       return;
     }
-    // one round of resident workgroups (FP64: one per CU, FP32: two), each a contiguous run of
-    // `per` chunks (at most one problem's 128, so a workgroup touches at most two problems)
+    // one round of resident workgroups (FP64 at chi 64: one per CU, otherwise two), each a
+    // contiguous run of `per` chunks: a multiple of the G chunks in flight, and at most one
+    // problem's 2 xdim (so a workgroup touches at most two problems)
+    const int ch = d.chi, G = 64 / ch;
     const long J = 2L * d.xdim, total = J * nprob;
-    const long slots = d.prec == 1 ? resident_ : std::max(1, resident_ / 2);
-    const int per = (int)std::max(1L, std::min(J, (total + slots - 1) / slots));
+    if (total > INT_MAX - 256) {
+      if (err_ == 0) {
+        err_ = -1;
+        errmsg_ = "bp_close: too many chunks in one call (2^31 - 257 at most)";
+      }
+      return;
+    }
+    const long slots = (d.prec == 0 && ch == 64) ? std::max(1, resident_ / 2) : resident_;
+    long per = std::max<long>(1, std::min(J, (total + slots - 1) / slots));
+    per = (per + G - 1) / G * G;
     const int nwg = (int)((total + per - 1) / per);
-    double2 *W = (double2 *)splitk_ws((size_t)nwg * 2 * kBpCloseChi * kBpCloseChi *
-                                      sizeof(double2));
+    double2 *W = (double2 *)splitk_ws((size_t)nwg * 2 * G * ch * ch * sizeof(double2));
     if (!W) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool rec = prof_stride_ > 0 && (prof_all_++ % prof_stride_) == 0;
@@ -3057,15 +3087,19 @@ class HipBackend : public Backend {
       HIPCHK(hipEventRecord(e0, s_));
     }
     stale_check("bp_close_kernel");
-    if (d.prec == 1 && d.s32)
-      hipLaunchKernelGGL((bp_close_kernel<float, true>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,
-                         total, per, W);
-    else if (d.prec == 1)
-      hipLaunchKernelGGL((bp_close_kernel<float, false>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,
-                         total, per, W);
-    else
-      hipLaunchKernelGGL((bp_close_kernel<double, false>), dim3(nwg), dim3(256), 0, s_, d, Y, T,
-                         M, total, per, W);
+#define BPC_LAUNCH(TT, S, C)                                                                      \
+  hipLaunchKernelGGL((bp_close_kernel<TT, S, C>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,         \
+                     (int)total, (int)per, W)
+    if (ch == 64) {
+      if (d.prec == 1 && d.s32) BPC_LAUNCH(float, true, 64);
+      else if (d.prec == 1) BPC_LAUNCH(float, false, 64);
+      else BPC_LAUNCH(double, false, 64);
+    } else {
+      if (d.prec == 1 && d.s32) BPC_LAUNCH(float, true, 32);
+      else if (d.prec == 1) BPC_LAUNCH(float, false, 32);
+      else BPC_LAUNCH(double, false, 32);
+    }
+#undef BPC_LAUNCH
     launch_check("bp_close_kernel");
     if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
@@ -3074,14 +3108,14 @@ class HipBackend : public Backend {
       // algorithmic work per message, per chunk (2 xdim of them): the absorption W = Y M (chi^3)
       // and the distinct entries of the Hermitian closing (chi (chi + 1) / 2 of them, K = chi);
       // a degree-3 site (xdim = chi): 2 chi^4 + chi^3 (chi + 1)
-      const double c = kBpCloseChi;
+      const double c = ch;
       const double fl = 8.0 * nprob * 2.0 * d.xdim * (c * c * c + 0.5 * c * c * (c + 1.0));
       prof_flops_ += fl;
       prof_flops_p_[2 + (d.prec & 1)] += fl;
     }
     stale_check("bp_close_reduce_kernel");
-    hipLaunchKernelGGL(bp_close_reduce_kernel, dim3(kBpCloseChi * kBpCloseChi / 256, nprob),
-                       dim3(256), 0, s_, per, (int)J, (const double2 *)W, out);
+    hipLaunchKernelGGL(bp_close_reduce_kernel, dim3((ch * ch + 255) / 256, nprob), dim3(256), 0,
+                       s_, ch, G, (int)per, (int)J, (const double2 *)W, out);
     launch_check("bp_close_reduce_kernel");
   }
   void *splitk_ws(size_t need) {

@@ -305,11 +305,9 @@ def test_mfma_rate_probe(ctx):
         ctx.test_mfma_rate(0, blocks=0)
 
 
-# --- fused degree-3 BP message (chi = 64) ------------------------------------------------------
+# --- fused BP message (chi = 32 and 64) -----------------------------------------------------------
 
-_C = 64
 # (outgoing leg, applied leg, chunk leg) as the BP sweep uses them, site tensors [s][l0][l1][l2]
-_LEG_STRIDE = (_C * _C, _C, 1)
 BP_CLOSE_CASES = [("out0", 0, 2, 1), ("out1", 1, 2, 0), ("out2", 2, 0, 1)]
 
 
@@ -319,13 +317,13 @@ def _hermitian(rng, n):
     return H / np.trace(H).real
 
 
-def _bp_close_case(rng, nprob, o, q, cl):
+def _bp_close_case(rng, nprob, o, q, cl, chi):
     """Site tensors T, the chunk leg's message absorbed (Y = T x_cl M_cl), the applied leg's
     message M_q, and the reference message out[b][b'] = sum T M_cl M_q conj(T) over s, a, x."""
     Ts, Ys, Ms, refs = [], [], [], []
     for _ in range(nprob):
-        T = _rand(rng, 2, _C, _C, _C) / _C
-        Mc, Mq = _hermitian(rng, _C), _hermitian(rng, _C)
+        T = _rand(rng, 2, chi, chi, chi) / chi
+        Mc, Mq = _hermitian(rng, chi), _hermitian(rng, chi)
         Y = np.moveaxis(np.tensordot(np.moveaxis(T, 1 + cl, -1), Mc, axes=([3], [0])), -1, 1 + cl)
         # views [s][b][a][x] of Y and T
         perm = [0, 1 + o, 1 + q, 1 + cl]
@@ -336,17 +334,19 @@ def _bp_close_case(rng, nprob, o, q, cl):
     return np.array(Ys), np.array(Ts), np.array(Ms), np.array(refs)
 
 
+@pytest.mark.parametrize("chi", [64, 32])
 @pytest.mark.parametrize("name,o,q,cl", BP_CLOSE_CASES, ids=[c[0] for c in BP_CLOSE_CASES])
-def test_bp_close_matches_numpy(ctx, name, o, q, cl):
+def test_bp_close_matches_numpy(ctx, name, o, q, cl, chi):
     """The fused message of a degree-3 site against numpy complex128, for the three leg
     configurations of the sweep: FP64 MFMA to 1e-12 of the largest entry, FP32 MFMA (FP64 and
-    FP32 operand storage) to 2e-5; exactly Hermitian output.  Nine problems for out0 make the
-    workgroups' chunk runs straddle problems (128 chunks each, runs of 3)."""
-    print(f"[bp_close] {name}", flush=True)
-    rng = np.random.default_rng(zlib.crc32(name.encode()))
-    nprob = 9 if name == "out0" else 2
-    Y, T, M, ref = _bp_close_case(rng, nprob, o, q, cl)
-    st = dict(rs=_LEG_STRIDE[o], qs=_LEG_STRIDE[q], cs=_LEG_STRIDE[cl], ss=_C ** 3)
+    FP32 operand storage) to 2e-5; exactly Hermitian output.  For out0 enough problems that the
+    workgroups' chunk runs straddle problems."""
+    print(f"[bp_close] {name} chi={chi}", flush=True)
+    rng = np.random.default_rng(zlib.crc32(f"{name}{chi}".encode()))
+    nprob = (9 if chi == 64 else 20) if name == "out0" else 2
+    Y, T, M, ref = _bp_close_case(rng, nprob, o, q, cl, chi)
+    stride = (chi * chi, chi, 1)
+    st = dict(rs=stride[o], qs=stride[q], cs=stride[cl], ss=chi ** 3)
     scale = np.abs(ref).max()
     got = ctx.test_bp_close(Y, T, M, **st)
     assert np.abs(got - ref).max() < 1e-12 * scale
@@ -362,28 +362,32 @@ def test_bp_close_matches_numpy(ctx, name, o, q, cl):
 def test_bp_close_rejects_bad_arguments(ctx):
     from paper_2306_14887_amd import bpki as B
     rng = np.random.default_rng(5)
-    Y = _rand(rng, 1, 2 * _C ** 3)
-    M = _rand(rng, 1, _C, _C)
+    C = 64
+    Y = _rand(rng, 1, 2 * C ** 3)
+    M = _rand(rng, 1, C, C)
     with pytest.raises(B.BpkiError):              # reaches past the tensors
-        ctx.test_bp_close(Y, Y, M, rs=_C * _C, qs=1, cs=_C, ss=_C ** 3 + 1)
+        ctx.test_bp_close(Y, Y, M, rs=C * C, qs=1, cs=C, ss=C ** 3 + 1)
     with pytest.raises(B.BpkiError):              # FP32 storage needs FP32 MFMA
-        ctx.test_bp_close(Y, Y, M, rs=_C * _C, qs=1, cs=_C, ss=_C ** 3, store32=1)
+        ctx.test_bp_close(Y, Y, M, rs=C * C, qs=1, cs=C, ss=C ** 3, store32=1)
+    with pytest.raises(B.BpkiError):              # chi 48 is not built
+        ctx.test_bp_close(Y, Y, _rand(rng, 1, 48, 48), rs=48 * 48, qs=1, cs=48, ss=48 ** 3)
 
 
+@pytest.mark.parametrize("chi", [64, 32])
 @pytest.mark.parametrize("o", [0, 1])
-def test_bp_close_degree2_matches_numpy(ctx, o):
+def test_bp_close_degree2_matches_numpy(ctx, o, chi):
     """The fused message of a degree-2 site (no chunk leg: the chunks are the two values of s, Y = T):
     out[b][b'] = sum_{s, a, a'} T[s][b][a] M[a][a'] conj(T[s][b'][a']) for both legs against numpy,
     FP64 to 1e-12 and FP32 to 2e-5, on 300 problems (several per workgroup)."""
-    print(f"[bp_close] degree 2 leg {o}", flush=True)
-    rng = np.random.default_rng(40 + o)
+    print(f"[bp_close] degree 2 leg {o} chi={chi}", flush=True)
+    rng = np.random.default_rng(40 + o + chi)
     n = 300
-    T = _rand(rng, n, 2, _C, _C) / _C
-    M = np.array([_hermitian(rng, _C) for _ in range(n)])
+    T = _rand(rng, n, 2, chi, chi) / chi
+    M = np.array([_hermitian(rng, chi) for _ in range(n)])
     Tv = T if o == 0 else np.transpose(T, (0, 1, 3, 2))        # [p][s][b][a]
     W = Tv @ M[:, None]                                         # [p][s][b][a']
     ref = np.einsum("psba,psca->pbc", W, Tv.conj())
-    st = dict(rs=_C if o == 0 else 1, qs=1 if o == 0 else _C, cs=0, ss=_C * _C, xdim=1)
+    st = dict(rs=chi if o == 0 else 1, qs=1 if o == 0 else chi, cs=0, ss=chi * chi, xdim=1)
     Y = T.reshape(n, -1)
     scale = np.abs(ref).max()
     got = ctx.test_bp_close(Y, Y, M, **st)
