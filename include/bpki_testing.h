@@ -63,8 +63,10 @@ int bpki_test_bp_close(bpki_ctx *ctx, int32_t chi, int precision, int store32, i
 
 /* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32, Householder
  * tridiagonalisation + divide and conquer otherwise) of nprob n x n matrices (n <= 512):
- * evals [nprob][n] descending, vecs [nprob][n][n] with column i the eigenvector of evals[i]. */
-int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, const double *A, double *evals,
+ * evals [nprob][n] descending, vecs [nprob][n][n] (in/out) with column i the eigenvector of
+ * evals[i] for i < ncols (1 <= ncols <= n); from n = 32 up, columns from ncols on keep the
+ * values vecs held on entry. */
+int bpki_test_eigh(bpki_ctx *ctx, int n, int nprob, int ncols, const double *A, double *evals,
                    double *vecs);
 
 /* Pivoted Cholesky factor of nprob Hermitian PSD n x n Gram matrices G (n <= 512): R [n][n]

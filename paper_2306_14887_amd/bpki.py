@@ -122,7 +122,7 @@ def load(path: str | None = None):
                                                  C.POINTER(C.c_int64)]),
         "bpki_test_gemm": (C.c_int, [vp, C.POINTER(TestGemmDesc), C.c_int, dp, C.c_size_t, dp,
                                      C.c_size_t, dp, C.c_size_t]),
-        "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, dp, dp, dp]),
+        "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, dp, dp, dp]),
         "bpki_test_gram_chol": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_double, dp, dp]),
         "bpki_test_mfma_rate": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, dp]),
         "bpki_test_bp_close": (C.c_int, [vp, C.c_int32, C.c_int, C.c_int, C.c_int64, C.c_int64,
@@ -382,14 +382,17 @@ class Context:
             T.ctypes.data_as(dp), Y.size // nprob, M.ctypes.data_as(dp), out.ctypes.data_as(dp)))
         return out
 
-    def test_eigh(self, A: np.ndarray):
+    def test_eigh(self, A: np.ndarray, ncols: int | None = None):
+        """Eigenvalues (descending) and eigenvectors; with ncols only the leading ncols columns
+        are computed from n = 32 up (the others stay zero)."""
         A = np.ascontiguousarray(A, dtype=np.complex128)
         nprob, n, _ = A.shape
         ev = np.zeros((nprob, n))
         V = np.zeros((nprob, n, n), dtype=np.complex128)
         dp = C.POINTER(C.c_double)
-        _check(self.lib, self.lib.bpki_test_eigh(self.h, n, nprob, A.ctypes.data_as(dp),
-                                                 ev.ctypes.data_as(dp), V.ctypes.data_as(dp)))
+        _check(self.lib, self.lib.bpki_test_eigh(self.h, n, nprob, n if ncols is None else ncols,
+                                                 A.ctypes.data_as(dp), ev.ctypes.data_as(dp),
+                                                 V.ctypes.data_as(dp)))
         return ev, V
 
 

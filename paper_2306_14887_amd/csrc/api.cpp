@@ -1306,9 +1306,10 @@ extern "C" int bpki_test_bp_close(bpki_ctx *c, int32_t chi, int precision, int s
   return e ? fail(e, msg) : 0;
 }
 
-extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, double *evals,
-                              double *vecs) {
-  if (!c || n < 1 || n > 512 || nprob < 1) return fail(-1, "bad argument");
+extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, int ncols, const double *A,
+                              double *evals, double *vecs) {
+  if (!c || n < 1 || n > 512 || nprob < 1 || ncols < 1 || ncols > n)
+    return fail(-1, "bad argument");
   Backend *be = c->be.get();
   std::lock_guard<std::mutex> lk(c->mu);
   size_t nn = (size_t)n * n;
@@ -1318,6 +1319,7 @@ extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, do
   void **ptrs = (void **)be->alloc(3 * nprob * sizeof(void *));
   if (!dA || !dE || !dV || !ptrs) return fail(-4, "allocation failed");
   be->h2d(dA, A, nn * 16 * nprob);
+  be->h2d(dV, vecs, nn * 16 * nprob);      // columns from ncols on keep these values
   std::vector<void *> h(3 * nprob);
   for (int p = 0; p < nprob; ++p) {
     h[p] = dA + 2 * nn * p;
@@ -1326,7 +1328,7 @@ extern "C" int bpki_test_eigh(bpki_ctx *c, int n, int nprob, const double *A, do
   }
   be->h2d(ptrs, h.data(), h.size() * sizeof(void *));
   be->eigh(n, n, (const double *const *)ptrs, (double *const *)(ptrs + nprob),
-           (double *const *)(ptrs + 2 * nprob), nprob);
+           (double *const *)(ptrs + 2 * nprob), nprob, ncols);
   be->d2h(evals, dE, (size_t)n * 8 * nprob);
   be->d2h(vecs, dV, nn * 16 * nprob);
   be->release(dA);

@@ -112,9 +112,10 @@ struct Backend {
                         const double *const *M, double *const *out, int nprob) = 0;
   // Batched Hermitian eigendecomposition (FP64).  in[p]: n x n (lda), read only; its Hermitian
   // part is used.
-  // evals[p]: n reals, descending; vecs[p]: n x n, column i = eigenvector i (ld = n).
+  // evals[p]: n reals, descending; vecs[p]: n x n, column i = eigenvector i (ld = n), written
+  // for the ncols largest eigenvalues (columns from ncols on are left as they were; n >= 32).
   virtual void eigh(int n, int lda, const double *const *in, double *const *evals,
-                    double *const *vecs, int nprob) = 0;
+                    double *const *vecs, int nprob, int ncols) = 0;
 
   // --- elementwise / small kernels -------------------------------------------------------
   // T_v <- RX(theta) on the physical leg for all sites; tensors[p] holds 2*half[p] complex.

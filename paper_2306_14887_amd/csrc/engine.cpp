@@ -1256,7 +1256,7 @@ double Engine::apply_layer(int colour, int zz_sign) {
   // 1. X, X+ of the environment messages
   if (LP.n_msg) {
     be_->eigh(chi, chi, ar.at<const double *const *>(LP.m_in), ar.at<double *const *>(LP.m_ev),
-              ar.at<double *const *>(LP.m_vec), LP.n_msg);
+              ar.at<double *const *>(LP.m_vec), LP.n_msg, chi);
     be_->msg_sqrt(chi, ar.at<const double *const *>(LP.m_ev),
                   ar.at<const double *const *>(LP.m_vec), ar.at<double *const *>(LP.m_X),
                   ar.at<double *const *>(LP.m_Xp), prob_.eig_cutoff, LP.n_msg);
@@ -1281,7 +1281,7 @@ double Engine::apply_layer(int colour, int zz_sign) {
   }
   for (auto &G : LP.eig_groups)
     be_->eigh(G.n, G.n, ar.at<const double *const *>(G.in), ar.at<double *const *>(G.ev),
-              ar.at<double *const *>(G.vec), G.count);
+              ar.at<double *const *>(G.vec), G.count, std::min(G.n, chi));   // kept columns only
   for (auto &T : LP.types) {
     be_->svd_finish(T.n, chi, ar.at<const double *const *>(T.ev),
                     ar.at<const double *const *>(T.vec), ar.at<double *const *>(T.Vs),
@@ -1460,7 +1460,7 @@ void Engine::observe_entropy(double *out) {
   const PtrArena &ar = P.arena;
   const int chi = P.chi;
   be_->eigh(chi, chi, ar.at<const double *const *>(P.ent_m), ar.at<double *const *>(P.ent_ev),
-            ar.at<double *const *>(P.ent_vec), P.E);
+            ar.at<double *const *>(P.ent_vec), P.E, chi);
   // the pseudo-inverse root lands in the Y buffer and is overwritten by the product below
   be_->msg_sqrt(chi, ar.at<const double *const *>(P.ent_ev), ar.at<const double *const *>(P.ent_vec),
                 ar.at<double *const *>(P.ent_X), ar.at<double *const *>(P.ent_Y),
@@ -1468,7 +1468,7 @@ void Engine::observe_entropy(double *out) {
   run(be_, ar, P.ent_xm, 0);
   run(be_, ar, P.ent_b, 0);
   be_->eigh(chi, chi, ar.at<const double *const *>(P.ent_B), ar.at<double *const *>(P.ent_ev),
-            ar.at<double *const *>(P.ent_vec), P.E);
+            ar.at<double *const *>(P.ent_vec), P.E, 1);   // eigenvalues only
   be_->bond_entropy(chi, ar.at<const double *const *>(P.ent_ev), P.ent_out, P.E);
   be_->d2h(out, P.ent_out, (size_t)P.E * 8);
 }
@@ -1486,14 +1486,14 @@ void Engine::vidal_gauge(double *lambda) {
   const PtrArena &ar = P.arena;
   const int chi = P.chi;
   be_->eigh(chi, chi, ar.at<const double *const *>(P.vg_m), ar.at<double *const *>(P.vg_ev),
-            ar.at<double *const *>(P.vg_vec), 2 * P.E);
+            ar.at<double *const *>(P.vg_vec), 2 * P.E, chi);
   be_->msg_sqrt(chi, ar.at<const double *const *>(P.vg_ev), ar.at<const double *const *>(P.vg_vec),
                 ar.at<double *const *>(P.vg_X), ar.at<double *const *>(P.vg_Xp),
                 prob_.eig_cutoff, 2 * P.E);
   run(be_, ar, P.vg_c, 0);
   run(be_, ar, P.vg_h, 0);
   be_->eigh(chi, chi, ar.at<const double *const *>(P.vg_h.c), ar.at<double *const *>(P.vg_ev3),
-            ar.at<double *const *>(P.vg_vec3), P.E);
+            ar.at<double *const *>(P.vg_vec3), P.E, chi);
   be_->vidal_svd(chi, ar.at<const double *const *>(P.vg_ev3),
                  ar.at<const double *const *>(P.vg_vec3), ar.at<double *const *>(P.vg_D1),
                  ar.at<double *const *>(P.vg_D2), ar.at<double *const *>(P.vg_Mu),
@@ -1741,7 +1741,7 @@ double Engine::bp_error(int e, double *spectrum) {
   const void *ep[3] = {G, ev, V};
   S.be->h2d(S.parr, ep, sizeof(ep));
   S.be->eigh((int)c2, (int)c2, (const double *const *)S.parr, (double *const *)(S.parr + 1),
-             (double *const *)(S.parr + 2), 1);
+             (double *const *)(S.parr + 2), 1, 1);   // eigenvalues only
   std::vector<double> l(c2);
   S.be->d2h(l.data(), ev, (size_t)c2 * 8);
   double tot = 0.0;

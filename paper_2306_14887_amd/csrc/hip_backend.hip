@@ -940,13 +940,12 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 //     The diagonal d and off-diagonal e go to the workspace (eigenvalue and staging areas).
 //  2. eigh_dc_kernel (512 threads): divide and conquer on T (Cuppen's rank-one tearing;
 //     eigenvectors by the Gu-Eisenstat construction).  The index range is cut into the binary
-//     tree of ranges [floor(q n / 2^D), floor((q+1) n / 2^D)); the couplings beta at the cuts
-//     above the leaves (depth 3 for n <= 128, depth 4 above) are torn off (T = diag(T_1 ..
-//     T_L) + sum |beta| u u^T with u = e_{k-1} + sign(beta) e_k and the two diagonal entries
-//     lowered by |beta|).  The leaves (8..16 entries) are diagonalised by cyclic Jacobi, one
-//     wave each, and merged back pairwise by the whole workgroup.  A merge of two solved
-//     halves with eigenvectors Q = diag(Q1, Q2) solves D + rho z z^T (z = Q^T u / sqrt 2,
-//     rho = 2|beta|):
+//     tree of ranges [floor(q n / 2^D), floor((q+1) n / 2^D)) down to single entries (depth
+//     ceil(log2 n)); every coupling beta is torn off at the level whose merge joins its two
+//     sides (T = diag(T_1 .. T_L) + sum |beta| u u^T with u = e_{k-1} + sign(beta) e_k and the
+//     two diagonal entries lowered by |beta|), and the levels are merged back bottom-up by the
+//     whole workgroup, all merges of a level at once.  A merge of two solved halves with
+//     eigenvectors Q = diag(Q1, Q2) solves D + rho z z^T (z = Q^T u / sqrt 2, rho = 2|beta|):
 //       - deflation: components with rho |z_i| <= tol keep (d_i, q_i); pairs of eigenvalues
 //         closer than tol are rotated so that one z component vanishes
 //         (tol = 8 eps max(|d|_max, rho));
@@ -960,7 +959,8 @@ __device__ __forceinline__ size_t pk_idx(int i, int j) {
 //         v_j = (zhat_i / (d_i - lambda_j))_i are numerically orthogonal; the new eigenvector
 //         matrix is Q_K V.
 //  3. eigh_backtransform_kernel (grid: 16-column blocks x matrices): V = Q Z by applying
-//     H_{n-2}, ..., H_0 to each column block in LDS; sorts into descending eigenvalue order.
+//     H_{n-2}, ..., H_0 to each column block in LDS, the columns taken in descending
+//     eigenvalue order and only as many as the caller needs.
 //
 // Workspace per matrix (doubles): reflectors n*n complex (column k = v_k), tau n complex,
 // Z n*n real (column-major), eigenvalues n, an n*n staging area for the merges, and for
@@ -977,80 +977,141 @@ __host__ __device__ __forceinline__ size_t trd_panel_offset(int n) {   // double
   return (size_t)6 * n * n + (size_t)3 * n;
 }
 
+// Cross-lane reductions on the DPP network (no LDS round trips).  dpp_d<CTRL> moves a double
+// from the lane that the DPP control CTRL names: 0xB1 lane ^ 1, 0x4E lane ^ 2 (quad permutes),
+// 0x141 the mirror within 8 lanes, 0x140 the mirror within 16 lanes.  Every lane of the groups
+// involved must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// sum over the 4 lanes of a quad, the same value in each of them
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  return v + dpp_d<0x4E>(v);
+}
+__device__ __forceinline__ double quad_prod(double v) {
+  v *= dpp_d<0xB1>(v);
+  return v * dpp_d<0x4E>(v);
+}
+// sum over the 8 lanes of an aligned group of 8
+__device__ __forceinline__ double oct_sum(double v) {
+  v = quad_sum(v);
+  return v + dpp_d<0x141>(v);
+}
+// sum / max over the wave (all 64 lanes active), the same value in every lane
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = oct_sum(v);
+  v += dpp_d<0x140>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 
-// Scratch of one merge (LDS), indexed by position in the merged range.
+__device__ __forceinline__ int dc_bound(int q, int n, int depth) {
+  return (int)(((long)q * n) >> depth);
+}
+
+// Scratch of the merges of one level (LDS): per-position arrays indexed by the position i in
+// [0, n) (each merge uses the positions of its own range), per-merge values by the merge q.
 struct DcScratch {
-  double *z, *dd, *zK, *dK, *tau, *dorg, *zh, *lam, *rc, *rs, *red;
-  int *perm, *K, *defl, *ra, *rb, *cnt;
+  double *z, *dd, *zK, *dK, *tau, *dorg, *zh, *lam, *rc, *rs, *tol;
+  int *perm, *K, *defl, *ra, *rb, *cnk, *cnr;
 };
 
-__device__ double block_max512(double v, double *red) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = red[0];
-  for (int i = 1; i < 8; ++i) r = fmax(r, red[i]);
-  __syncthreads();
-  return r;
-}
-
-// Merges the solved ranges [lo, k) and [k, hi) coupled by beta (all 512 threads).
-// d: eigenvalues (LDS), Z: eigenvectors (column-major, leading dimension n; LDS or global);
-// Vg, Wg: n x n global staging areas of this matrix.
-__device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, double *Z,
-                         const DcScratch &S, double *Vg, double *Wg) {
+// Merges, for every q < 2^D at once, the solved ranges [lo, k) and [k, hi) coupled by
+// beta = e[k - 1], where lo = floor(q n / 2^D), k = floor((2q + 1) n / 2^(D+1)),
+// hi = floor((q + 1) n / 2^D); ranges with lo = k or k = hi are not split at this level.
+// All 512 threads; every loop runs over the positions (or position pairs) of all merges of the
+// level, so a level costs about what its largest merge costs.  d: eigenvalues (LDS), Z:
+// eigenvectors (column-major, leading dimension n; LDS or global); Vg, Wg: n x n global staging
+// areas of this matrix.
+__device__ void dc_level(int n, int D, const double *e, double *d, double *Z, const DcScratch &S,
+                         double *Vg, double *Wg) {
   const double eps = 2.220446049250313e-16;
-  const int tid = threadIdx.x;
-  constexpr int NT = 512;
-  const int s = hi - lo;
-  const double rho = 2.0 * fabs(beta);
-  const double sg = beta >= 0.0 ? 1.0 : -1.0;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int NT = 512, NW = 8;
+  const int nq = 1 << D;
+  const int smax = (n + nq - 1) / nq + 1;        // a bound on the size of a range
+  // the merge holding position i: the largest q with floor(q n / 2^D) <= i
+  auto merge_of = [&](int i) { return (((i + 1) << D) + n - 1) / n - 1; };
+  struct Rg { int lo, k, hi; bool on; };
+  auto range = [&](int q) {
+    Rg r;
+    r.lo = dc_bound(q, n, D);
+    r.hi = dc_bound(q + 1, n, D);
+    r.k = dc_bound(2 * q + 1, n, D + 1);
+    r.on = r.lo < r.k && r.k < r.hi;
+    return r;
+  };
   // z = (last row of Q1, sign(beta) first row of Q2) / sqrt 2
-  double dmax = 0.0;
-  for (int t = tid; t < s; t += NT) {
-    const int i = lo + t;
-    S.z[t] = (i < k ? Z[(size_t)i * n + k - 1] : sg * Z[(size_t)i * n + k]) * 0.70710678118654752440;
-    S.dd[t] = d[i];
-    dmax = fmax(dmax, fabs(d[i]));
+  for (int i = tid; i < n; i += NT) {
+    const Rg g = range(merge_of(i));
+    if (!g.on) continue;
+    const double sg = e[g.k - 1] >= 0.0 ? 1.0 : -1.0;
+    S.z[i] = (i < g.k ? Z[(size_t)i * n + g.k - 1] : sg * Z[(size_t)i * n + g.k]) *
+             0.70710678118654752440;
+    S.dd[i] = d[i];
   }
-  dmax = block_max512(dmax, S.red);
-  const double tol = 8.0 * eps * fmax(dmax, rho);
-  // ascending order of dd (ties by position)
-  for (int t = tid; t < s; t += NT) {
-    const double v = S.dd[t];
-    int r = 0;
-    for (int u = 0; u < s; ++u) {
-      const double w = S.dd[u];
-      r += (w < v) || (w == v && u < t);
-    }
-    S.perm[r] = t;
-    S.zK[r] = S.z[t];      // sorted copies for the scan (dK is free until the gather below)
-    S.dK[r] = v;
+  // deflation tolerance of each merge: 8 eps max(|d|_max, rho), one wave per merge
+  for (int q = wave; q < nq; q += NW) {
+    const Rg g = range(q);
+    if (!g.on) continue;
+    double m = 0.0;
+    for (int i = g.lo + lane; i < g.hi; i += 64) m = fmax(m, fabs(d[i]));
+    m = wave_max(m);
+    if (lane == 0) S.tol[q] = 8.0 * eps * fmax(m, 2.0 * fabs(e[g.k - 1]));
   }
   __syncthreads();
-  // deflation scan in ascending order (one thread).  The last kept entry's d and z live in
-  // registers and the sorted copies are read one entry ahead, so no iteration waits on a load
-  // that depends on the previous one.
-  if (tid == 0) {
+  // ascending order of dd within each merge (ties by position)
+  for (int i = tid; i < n; i += NT) {
+    const Rg g = range(merge_of(i));
+    if (!g.on) continue;
+    const double v = S.dd[i];
+    int r = 0;
+    for (int u = g.lo; u < g.hi; ++u) {
+      const double w = S.dd[u];
+      r += (w < v) || (w == v && u < i);
+    }
+    S.perm[g.lo + r] = i;
+    S.zK[g.lo + r] = S.z[i];    // sorted copies for the scan (dK is free until the gather below)
+    S.dK[g.lo + r] = v;
+  }
+  __syncthreads();
+  // deflation scan of each merge in ascending order (one thread per merge).  The last kept
+  // entry's d and z live in registers and the sorted copies are read one entry ahead, so no
+  // iteration waits on a load that depends on the previous one.  K: kept positions, defl:
+  // deflated positions, (ra, rb, rc, rs): rotations of close pairs, all at the merge's offset.
+  for (int q = tid; q < nq; q += NT) {
+    const Rg g = range(q);
+    if (!g.on) continue;
+    const int lo = g.lo, s = g.hi - g.lo;
+    const double rho = 2.0 * fabs(e[g.k - 1]), tol = S.tol[q];
     int nk = 0, nd = 0, nr = 0, prev = -1;
     double zp = 0.0, dp = 0.0;
-    int tn = S.perm[0];
-    double zn = S.zK[0], dn = S.dK[0];
+    int tn = S.perm[lo];
+    double zn = S.zK[lo], dn = S.dK[lo];
     for (int r = 0; r < s; ++r) {
       const int t = tn;
       const double zt = zn, dt = dn;
       if (r + 1 < s) {
-        tn = S.perm[r + 1];
-        zn = S.zK[r + 1];
-        dn = S.dK[r + 1];
+        tn = S.perm[lo + r + 1];
+        zn = S.zK[lo + r + 1];
+        dn = S.dK[lo + r + 1];
       }
       if (rho * fabs(zt) <= tol) {
-        S.defl[nd++] = t;
+        S.defl[lo + nd++] = t;
         continue;
       }
       if (prev >= 0 && fabs(dt - dp) <= tol) {
@@ -1061,173 +1122,197 @@ __device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, d
         S.dd[t] = dtn;
         S.z[prev] = 0.0;
         S.z[t] = rr;
-        S.ra[nr] = prev;
-        S.rb[nr] = t;
-        S.rc[nr] = c;
-        S.rs[nr] = sn;
+        S.ra[lo + nr] = prev;
+        S.rb[lo + nr] = t;
+        S.rc[lo + nr] = c;
+        S.rs[lo + nr] = sn;
         ++nr;
-        S.defl[nd++] = prev;
+        S.defl[lo + nd++] = prev;
         prev = t;
         zp = rr;
         dp = dtn;
         continue;
       }
-      if (prev >= 0) S.K[nk++] = prev;
+      if (prev >= 0) S.K[lo + nk++] = prev;
       prev = t;
       zp = zt;
       dp = dt;
     }
-    if (prev >= 0) S.K[nk++] = prev;
-    S.cnt[0] = nk;
-    S.cnt[1] = nd;
-    S.cnt[2] = nr;
+    if (prev >= 0) S.K[lo + nk++] = prev;
+    S.cnk[q] = nk;
+    S.cnr[q] = nr;
   }
   __syncthreads();
-  const int nk = S.cnt[0], nr = S.cnt[2];
   // the deflation rotations act on the columns of Q; each row evolves independently
-  for (int r = lo + tid; r < hi; r += NT)
-    for (int q = 0; q < nr; ++q) {
-      const size_t ca = (size_t)(lo + S.ra[q]) * n + r, cb = (size_t)(lo + S.rb[q]) * n + r;
-      const double c = S.rc[q], sn = S.rs[q];
+  for (int r = tid; r < n; r += NT) {
+    const int q = merge_of(r);
+    const Rg g = range(q);
+    if (!g.on) continue;
+    const int nr = S.cnr[q];
+    for (int p = 0; p < nr; ++p) {
+      const size_t ca = (size_t)S.ra[g.lo + p] * n + r, cb = (size_t)S.rb[g.lo + p] * n + r;
+      const double c = S.rc[g.lo + p], sn = S.rs[g.lo + p];
       const double qa = Z[ca], qb = Z[cb];
       Z[ca] = c * qa - sn * qb;
       Z[cb] = sn * qa + c * qb;
     }
+  }
   __syncthreads();
   // gather: kept columns of Q (in ascending eigenvalue order), then the deflated ones, to Wg;
   // kept z and d contiguous
-  for (int idx = tid; idx < s * s; idx += NT) {
-    const int c = idx / s, r = lo + idx % s;
-    const int col = c < nk ? S.K[c] : S.defl[c - nk];
-    Wg[(size_t)(lo + c) * n + r] = Z[(size_t)(lo + col) * n + r];
+  for (int idx = tid; idx < n * smax; idx += NT) {
+    const int cg = idx / smax, q = merge_of(cg);
+    const Rg g = range(q);
+    const int r = g.lo + idx % smax;
+    if (!g.on || r >= g.hi) continue;
+    const int c = cg - g.lo, nk = S.cnk[q];
+    const int col = c < nk ? S.K[g.lo + c] : S.defl[g.lo + c - nk];
+    Wg[(size_t)cg * n + r] = Z[(size_t)col * n + r];
   }
-  for (int c = tid; c < nk; c += NT) {
-    S.zK[c] = S.z[S.K[c]];
-    S.dK[c] = S.dd[S.K[c]];
+  for (int i = tid; i < n; i += NT) {
+    const int q = merge_of(i);
+    const Rg g = range(q);
+    if (!g.on || i - g.lo >= S.cnk[q]) continue;
+    S.zK[i] = S.z[S.K[i]];
+    S.dK[i] = S.dd[S.K[i]];
   }
   __syncthreads();
-  // secular roots: four lanes per root, each summing a quarter of the terms
-  {
-    const int q4 = tid & 3;
-    const double *zK = S.zK, *dK = S.dK;
-    for (int j = tid >> 2; j < nk; j += NT / 4) {
-      double zs = 0.0;
-      for (int t = q4; t < nk; t += 4) zs += zK[t] * zK[t];
-      zs += __shfl_xor(zs, 1, 64);
-      zs += __shfl_xor(zs, 2, 64);
-      const double dj = dK[j];
-      int o = j;
-      double a, b;
-      if (j + 1 < nk) {
-        const double half = 0.5 * (dK[j + 1] - dj);
-        double f = 0.0;
-        for (int t = q4; t < nk; t += 4) f += zK[t] * zK[t] / ((dK[t] - dj) - half);
-        f += __shfl_xor(f, 1, 64);
-        f += __shfl_xor(f, 2, 64);
-        f = 1.0 + rho * f;
-        if (f >= 0.0) { a = 0.0; b = half; }
-        else { o = j + 1; a = -half; b = 0.0; }
-      } else {
-        a = 0.0;
-        b = rho * zs;
-      }
-      // Safeguarded rational iteration: near tau, the poles at or left of d_j (psi) and right
-      // of it (phi) are modelled as p + q/(dL - x) and r + s/(dR - x), matched in value and
-      // slope; the model's root (a quadratic) is taken when it lies inside the bracket [a, b],
-      // else the bracket midpoint.  Stops when f vanishes to rounding or the bracket closes.
-      const double dorg = dK[o];
-      const bool hasR = j + 1 < nk;
-      const double dL = dK[j] - dorg, dR = hasR ? dK[j + 1] - dorg : 0.0;
-      double tau = 0.5 * (a + b);
-      for (int it = 0; it < 96; ++it) {
-        double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-        for (int t = q4; t < nk; t += 4) {
-          const double r = 1.0 / ((dK[t] - dorg) - tau);
-          const double w = zK[t] * zK[t] * r;
-          if (t <= j) {
-            psi += w;
-            dpsi += w * r;
-          } else {
-            phi += w;
-            dphi += w * r;
-          }
-        }
-        psi += __shfl_xor(psi, 1, 64);
-        dpsi += __shfl_xor(dpsi, 1, 64);
-        phi += __shfl_xor(phi, 1, 64);
-        dphi += __shfl_xor(dphi, 1, 64);
-        psi += __shfl_xor(psi, 2, 64);
-        dpsi += __shfl_xor(dpsi, 2, 64);
-        phi += __shfl_xor(phi, 2, 64);
-        dphi += __shfl_xor(dphi, 2, 64);
-        psi *= rho;
-        dpsi *= rho;
-        phi *= rho;
-        dphi *= rho;
-        const double f = 1.0 + psi + phi;
-        if (fabs(f) <= eps * (1.0 + fabs(psi) + phi)) break;
-        if (f > 0.0) b = tau;
-        else a = tau;
-        if (!(b - a > 4.0 * eps * fmax(fabs(a), fabs(b)))) break;
-        const double hL = dL - tau;
-        const double Qm = dpsi * hL * hL, Pm = psi - dpsi * hL;
-        double x = 0.5 * (a + b);
-        if (hasR) {
-          const double hR = dR - tau;
-          const double Sm = dphi * hR * hR, Rm = phi - dphi * hR;
-          const double C = 1.0 + Pm + Rm;
-          const double B = C * (dL + dR) + Qm + Sm, Dq = C * dL * dR + Qm * dR + Sm * dL;
-          const double disc = B * B - 4.0 * C * Dq;
-          if (C != 0.0 && disc >= 0.0) {
-            const double sq = sqrt(disc), den = B >= 0.0 ? B + sq : B - sq;
-            const double u1 = den / (2.0 * C);
-            const double u2 = den != 0.0 ? 2.0 * Dq / den : u1;
-            if (u1 > a && u1 < b) x = u1;
-            else if (u2 > a && u2 < b) x = u2;
-          }
+  // secular roots: four lanes per root, each summing a quarter of the terms (a quad shares its
+  // root, so its lanes agree on every branch)
+  for (int i = tid >> 2; i < n; i += NT / 4) {
+    const int q4 = tid & 3, q = merge_of(i);
+    const Rg g = range(q);
+    if (!g.on) continue;
+    const int nk = S.cnk[q], j = i - g.lo;
+    if (j >= nk) continue;
+    const double rho = 2.0 * fabs(e[g.k - 1]);
+    const double *zK = S.zK + g.lo, *dK = S.dK + g.lo;
+    double zs = 0.0;
+    for (int t = q4; t < nk; t += 4) zs += zK[t] * zK[t];
+    zs = quad_sum(zs);
+    const double dj = dK[j];
+    int o = j;
+    double a, b;
+    if (j + 1 < nk) {
+      const double half = 0.5 * (dK[j + 1] - dj);
+      double f = 0.0;
+      for (int t = q4; t < nk; t += 4) f += zK[t] * zK[t] / ((dK[t] - dj) - half);
+      f = quad_sum(f);
+      f = 1.0 + rho * f;
+      if (f >= 0.0) { a = 0.0; b = half; }
+      else { o = j + 1; a = -half; b = 0.0; }
+    } else {
+      a = 0.0;
+      b = rho * zs;
+    }
+    // Safeguarded rational iteration: near tau, the poles at or left of d_j (psi) and right
+    // of it (phi) are modelled as p + q/(dL - x) and r + s/(dR - x), matched in value and
+    // slope; the model's root (a quadratic) is taken when it lies inside the bracket [a, b],
+    // else the bracket midpoint.  Stops when f vanishes to rounding or the bracket closes.
+    const double dorg = dK[o];
+    const bool hasR = j + 1 < nk;
+    const double dL = dK[j] - dorg, dR = hasR ? dK[j + 1] - dorg : 0.0;
+    double tau = 0.5 * (a + b);
+    for (int it = 0; it < 96; ++it) {
+      double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
+      for (int t = q4; t < nk; t += 4) {
+        const double r = 1.0 / ((dK[t] - dorg) - tau);
+        const double w = zK[t] * zK[t] * r;
+        if (t <= j) {
+          psi += w;
+          dpsi += w * r;
         } else {
-          const double C = 1.0 + Pm + phi;
-          if (C > 0.0) {
-            const double u = dL + Qm / C;
-            if (u > a && u < b) x = u;
-          }
+          phi += w;
+          dphi += w * r;
         }
-        if (x == tau) break;
-        tau = x;
       }
-      if (q4 == 0) {
-        S.dorg[j] = dorg;
-        S.tau[j] = tau;
+      psi = rho * quad_sum(psi);
+      dpsi = rho * quad_sum(dpsi);
+      phi = rho * quad_sum(phi);
+      dphi = rho * quad_sum(dphi);
+      const double f = 1.0 + psi + phi;
+      if (fabs(f) <= eps * (1.0 + fabs(psi) + phi)) break;
+      if (f > 0.0) b = tau;
+      else a = tau;
+      if (!(b - a > 4.0 * eps * fmax(fabs(a), fabs(b)))) break;
+      const double hL = dL - tau;
+      const double Qm = dpsi * hL * hL, Pm = psi - dpsi * hL;
+      double x = 0.5 * (a + b);
+      if (hasR) {
+        const double hR = dR - tau;
+        const double Sm = dphi * hR * hR, Rm = phi - dphi * hR;
+        const double C = 1.0 + Pm + Rm;
+        const double B = C * (dL + dR) + Qm + Sm, Dq = C * dL * dR + Qm * dR + Sm * dL;
+        const double disc = B * B - 4.0 * C * Dq;
+        if (C != 0.0 && disc >= 0.0) {
+          const double sq = sqrt(disc), den = B >= 0.0 ? B + sq : B - sq;
+          const double u1 = den / (2.0 * C);
+          const double u2 = den != 0.0 ? 2.0 * Dq / den : u1;
+          if (u1 > a && u1 < b) x = u1;
+          else if (u2 > a && u2 < b) x = u2;
+        }
+      } else {
+        const double C = 1.0 + Pm + phi;
+        if (C > 0.0) {
+          const double u = dL + Qm / C;
+          if (u > a && u < b) x = u;
+        }
       }
+      if (x == tau) break;
+      tau = x;
+    }
+    if (q4 == 0) {
+      S.dorg[i] = dorg;
+      S.tau[i] = tau;
     }
   }
   __syncthreads();
   // zhat_t^2 = (lambda_{nk-1} - d_t)/rho * prod_{j<t} (lambda_j - d_t)/(d_j - d_t)
   //            * prod_{t<=j<nk-1} (lambda_j - d_t)/(d_{j+1} - d_t)      (d = kept, ascending)
-  for (int t = tid >> 2; t < nk; t += NT / 4) {
-    const int q4 = tid & 3;
-    const double dt = S.dK[t];
-    double prod = q4 == 0 ? (S.tau[nk - 1] - (dt - S.dorg[nk - 1])) / rho : 1.0;
-    for (int j = q4; j < t; j += 4) prod *= (S.tau[j] - (dt - S.dorg[j])) / (S.dK[j] - dt);
-    for (int j = t + q4; j < nk - 1; j += 4) prod *= (S.tau[j] - (dt - S.dorg[j])) / (S.dK[j + 1] - dt);
-    prod *= __shfl_xor(prod, 1, 64);
-    prod *= __shfl_xor(prod, 2, 64);
-    if (q4 == 0) S.zh[t] = copysign(sqrt(fmax(prod, 0.0)), S.zK[t]);
+  for (int i = tid >> 2; i < n; i += NT / 4) {
+    const int q4 = tid & 3, q = merge_of(i);
+    const Rg g = range(q);
+    if (!g.on) continue;
+    const int nk = S.cnk[q], t = i - g.lo;
+    if (t >= nk) continue;
+    const double rho = 2.0 * fabs(e[g.k - 1]);
+    const double *dK = S.dK + g.lo, *tau = S.tau + g.lo, *dorg = S.dorg + g.lo;
+    const double dt = dK[t];
+    double prod = q4 == 0 ? (tau[nk - 1] - (dt - dorg[nk - 1])) / rho : 1.0;
+    for (int j = q4; j < t; j += 4) prod *= (tau[j] - (dt - dorg[j])) / (dK[j] - dt);
+    for (int j = t + q4; j < nk - 1; j += 4) prod *= (tau[j] - (dt - dorg[j])) / (dK[j + 1] - dt);
+    prod = quad_prod(prod);
+    if (q4 == 0) S.zh[i] = copysign(sqrt(fmax(prod, 0.0)), S.zK[i]);
   }
   __syncthreads();
-  // coefficient vectors v_j (unnormalised; the norms are taken in the product below), column j
-  // at Vg[(lo + j) n + lo ..]
-  for (int idx = tid; idx < nk * nk; idx += NT) {
-    const int j = idx / nk, t = idx % nk;
-    Vg[(size_t)(lo + j) * n + lo + t] = S.zh[t] / ((S.dK[t] - S.dorg[j]) - S.tau[j]);
+  // coefficient vectors v_j (unnormalised; the norms are taken in the product below), column
+  // lo + j at Vg[(lo + j) n + lo ..]
+  for (int idx = tid; idx < n * smax; idx += NT) {
+    const int jg = idx / smax, q = merge_of(jg);
+    const Rg g = range(q);
+    if (!g.on) continue;
+    const int nk = S.cnk[q], j = jg - g.lo, t = idx % smax;
+    if (j >= nk || t >= nk) continue;
+    Vg[(size_t)jg * n + g.lo + t] =
+        S.zh[g.lo + t] / ((S.dK[g.lo + t] - S.dorg[jg]) - S.tau[jg]);
   }
-  for (int j = tid; j < nk; j += NT) S.lam[j] = S.dorg[j] + S.tau[j];
+  for (int i = tid; i < n; i += NT) {
+    const int q = merge_of(i);
+    const Rg g = range(q);
+    if (g.on && i - g.lo < S.cnk[q]) S.lam[i] = S.dorg[i] + S.tau[i];
+  }
   __syncthreads();
   // new eigenvectors Q_K V (4 x 4 register tiles), then the deflated columns
   {
-    const int tr = (s + 3) >> 2, tc = (nk + 3) >> 2;
-    for (int tile = tid; tile < tr * tc; tile += NT) {
-      const int r0 = lo + (tile % tr) * 4, j0 = (tile / tr) * 4;
+    const int tm = (smax + 3) >> 2, tpm = tm * tm;   // tiles per merge, at most
+    for (int tile = tid; tile < nq * tpm; tile += NT) {
+      const int q = tile / tpm, tl = tile % tpm;
+      const Rg g = range(q);
+      if (!g.on) continue;
+      const int lo = g.lo, hi = g.hi, s = hi - lo, nk = S.cnk[q];
+      const int tr = (s + 3) >> 2, tc = (nk + 3) >> 2;
+      if (tl >= tr * tc) continue;
+      const int r0 = lo + (tl % tr) * 4, j0 = (tl / tr) * 4;
       double acc[4][4];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -1261,17 +1346,22 @@ __device__ void dc_merge(int n, int lo, int k, int hi, double beta, double *d, d
           if (j0 + v < nk && r0 + u < hi) Z[(size_t)(lo + j0 + v) * n + r0 + u] = acc[u][v] * inv;
       }
     }
-    for (int idx = tid; idx < s * (s - nk); idx += NT) {
-      const int j = nk + idx / s, r = lo + idx % s;
-      Z[(size_t)(lo + j) * n + r] = Wg[(size_t)(lo + j) * n + r];
+    for (int idx = tid; idx < n * smax; idx += NT) {
+      const int cg = idx / smax, q = merge_of(cg);
+      const Rg g = range(q);
+      const int r = g.lo + idx % smax;
+      if (!g.on || r >= g.hi || cg - g.lo < S.cnk[q]) continue;
+      Z[(size_t)cg * n + r] = Wg[(size_t)cg * n + r];
     }
-    for (int j = tid; j < s; j += NT) d[lo + j] = j < nk ? S.lam[j] : S.dd[S.defl[j - nk]];
+    for (int i = tid; i < n; i += NT) {
+      const int q = merge_of(i);
+      const Rg g = range(q);
+      if (!g.on) continue;
+      const int j = i - g.lo, nk = S.cnk[q];
+      d[i] = j < nk ? S.lam[i] : S.dd[S.defl[g.lo + j - nk]];
+    }
   }
   __syncthreads();
-}
-
-__device__ __forceinline__ int dc_bound(int q, int n, int depth) {
-  return (int)(((long)q * n) >> depth);
 }
 
 // eigh_tridiag_kernel: stage 1 (Householder reduction), NT threads per matrix; writes the
@@ -1288,6 +1378,7 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
   __shared__ double d_s[NMAX], e_s[NMAX];
   __shared__ __attribute__((aligned(16))) double sbuf[(6 + 2 * HALVES) * NMAX];
   __shared__ double2 tau_sh;
+  __shared__ double2 dot_s[NT / 64];
   double2 *v_s = reinterpret_cast<double2 *>(sbuf), *w_s = v_s + NMAX;
   double2 *x1_s = w_s + NMAX, *x2_s = x1_s + NMAX;   // BIG: row part, HALVES column partials
   const int prob = blockIdx.x;
@@ -1351,30 +1442,44 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
     const double2 tau = tau_sh;
     if (tau.x == 0.0 && tau.y == 0.0) continue;   // H_k = I (uniform over the block)
     if constexpr (!BIG) {
-      // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): TPR threads per row;
-      // row gi of S is row gi of the packed triangle up to the diagonal, then column gi
+      // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): TPR = 8 threads per
+      // row; row gi of S is row gi of the packed triangle up to the diagonal, then column gi
+      // (packed index of (k+1+c, gi) stepped by c += 8: + 8 (k+1+c) + 36)
+      static_assert(TPR == 8, "the row sums are reductions over aligned groups of 8 lanes");
       const int r = tid / TPR, q = tid % TPR;
       double2 acc = make_double2(0.0, 0.0);
       if (r < m) {
         const int gi = k + 1 + r;
         const double2 *prow = smem + pk_idx(gi, k + 1);
+#pragma unroll 4
         for (int c = q; c <= r; c += TPR) {
           const double2 a = prow[c], vc = v_s[c];
           acc.x += a.x * vc.x - a.y * vc.y;
           acc.y += a.x * vc.y + a.y * vc.x;
         }
+        int i = gi + 1 + q, idx = i * (i + 1) / 2 + gi;
+#pragma unroll 4
         for (int c = r + 1 + q; c < m; c += TPR) {
-          const double2 a = smem[pk_idx(k + 1 + c, gi)], vc = v_s[c];   // conj(a) vc
+          const double2 a = smem[idx], vc = v_s[c];   // conj(a) vc
           acc.x += a.x * vc.x + a.y * vc.y;
           acc.y += a.x * vc.y - a.y * vc.x;
+          idx += 8 * i + 36;
+          i += 8;
         }
       }
-#pragma unroll
-      for (int o = 1; o < TPR; o <<= 1) {
-        acc.x += __shfl_xor(acc.x, o, 64);
-        acc.y += __shfl_xor(acc.y, o, 64);
+      acc.x = oct_sum(acc.x);
+      acc.y = oct_sum(acc.y);
+      // this wave's share of v^H x (rows r < m), for a = -(1/2) Re(conj(tau) v^H x)
+      double pr = 0.0, pi = 0.0;
+      if (r < m && q == 0) {
+        const double2 x = cmul(tau, acc), vr = v_s[r];
+        w_s[r] = x;
+        pr = vr.x * x.x + vr.y * x.y;
+        pi = vr.x * x.y - vr.y * x.x;
       }
-      if (r < m && q == 0) w_s[r] = cmul(tau, acc);
+      pr = wave_sum(pr);
+      pi = wave_sum(pi);
+      if (lane == 0) dot_s[wave] = make_double2(pr, pi);
     } else {
       // S v from the lower triangle in two coalesced passes: the row part (diagonal included)
       // with 16 lanes per row, and the strictly upper part as conj(S)^T v with one lane per
@@ -1432,13 +1537,21 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
       }
     };
     double dr = 0.0, di = 0.0;
-    for (int i = lane; i < m; i += 64) {
-      const double2 vi = v_s[i], xi = xval(i);
-      dr += vi.x * xi.x + vi.y * xi.y;
-      di += vi.x * xi.y - vi.y * xi.x;
+    if constexpr (BIG) {
+      for (int i = lane; i < m; i += 64) {
+        const double2 vi = v_s[i], xi = xval(i);
+        dr += vi.x * xi.x + vi.y * xi.y;
+        di += vi.x * xi.y - vi.y * xi.x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+    } else {
+#pragma unroll
+      for (int w2 = 0; w2 < nw; ++w2) {        // the waves' shares in a fixed order
+        dr += dot_s[w2].x;
+        di += dot_s[w2].y;
+      }
     }
-    dr = wave_sum(dr);
-    di = wave_sum(di);
     const double aw = -0.5 * (tau.x * dr + tau.y * di);
     // w at this lane's columns (c = lane + 64 t)
     double2 wl[NMAX / 64];
@@ -1673,19 +1786,20 @@ __global__ void eigh_trd_last_kernel(int n, double *ws, int nprob) {
 }
 
 // eigh_dc_kernel: stage 2 (divide and conquer on the tridiagonal d, e left by
-// eigh_tridiag_kernel), 512 threads per matrix.  NMAX = 128: Z in LDS, leaves at depth 3.
-// NMAX = 256 (512): Z in the workspace, leaves at depth 4 (5).
+// eigh_tridiag_kernel), 512 threads per matrix.  The leaves are single entries (depth
+// ceil(log2 n)); every coupling is torn at its level and the levels are merged bottom-up, all
+// merges of a level at once (dc_level).  NMAX = 128: Z in LDS; NMAX = 256, 512: Z in the
+// workspace.
 template <int NMAX>
 __global__ __launch_bounds__(512) void eigh_dc_kernel(int n, double *ws) {
   constexpr bool BIG = NMAX > 128;
-  constexpr int LD = NMAX > 256 ? 5 : BIG ? 4 : 3;   // depth of the leaves (8..16 entries)
   extern __shared__ double2 smem[];
   __shared__ double d_s[NMAX], e_s[NMAX];
-  // phase-local scratch: leaf matrices (leaves), merge arrays
-  __shared__ __attribute__((aligned(16))) double sbuf[13 * NMAX];
+  // merge scratch: 11 per-position double arrays (10 full, tol per merge), 5 per-position int
+  // arrays and 2 per-merge int arrays
+  __shared__ __attribute__((aligned(16))) double sbuf[11 * NMAX + 4 * NMAX];
   const int prob = blockIdx.x;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  constexpr int nw = 8;
+  const int tid = threadIdx.x;
   double *base = ws + (size_t)prob * tql_ws_doubles(n);
   double2 *hh = reinterpret_cast<double2 *>(base);
   double2 *tau_g = hh + (size_t)n * n;
@@ -1697,131 +1811,36 @@ __global__ __launch_bounds__(512) void eigh_dc_kernel(int n, double *ws) {
     d_s[i] = dg[i];
     e_s[i] = Wg[i];
   }
-  __syncthreads();
-
-  // ---- 2. divide and conquer on (d, e) ----
-  // Z = I (column-major); tear the couplings at the split points above the leaves
+  int LD = 0;                                   // leaves of at most one entry: n <= 2^LD
+  while ((1 << LD) < n) ++LD;
+  // Z = I (column-major): the eigenvectors of the single-entry leaves
   double *Z = BIG ? Zg : reinterpret_cast<double *>(smem);
   double *Vg = BIG ? reinterpret_cast<double *>(Pg) : Zg;
   for (int idx = tid; idx < n * n; idx += blockDim.x) Z[idx] = (idx % (n + 1)) == 0 ? 1.0 : 0.0;
   __syncthreads();
+  // tear every coupling at the level whose merge it joins: T = diag(T_1 .. T_L) +
+  // sum |beta| u u^T with u = e_{k-1} + sign(beta) e_k, the two diagonal entries lowered by |beta|
   if (tid == 0)
     for (int D = 0; D < LD; ++D)
       for (int q = 0; q < (1 << D); ++q) {
+        const int lo = dc_bound(q, n, D), hi = dc_bound(q + 1, n, D);
         const int k = dc_bound(2 * q + 1, n, D + 1);
-        if (k <= 0 || k >= n) continue;
+        if (!(lo < k && k < hi)) continue;
         const double r = fabs(e_s[k - 1]);
         d_s[k - 1] -= r;
         d_s[k] -= r;
       }
   __syncthreads();
-  // leaves: the ranges of depth LD (8..16 entries), cyclic Jacobi by one wave each on the
-  // packed 16 x 16 tridiagonal block (padding indices have no coupling and never rotate)
-  for (int leaf = wave; leaf < (1 << LD); leaf += nw) {
-    const double eps = 2.220446049250313e-16;
-    const int lo = dc_bound(leaf, n, LD), m = dc_bound(leaf + 1, n, LD) - lo;
-    double *A = sbuf + wave * 136;
-    double *rcs = sbuf + 1088 + wave * 16;          // c[8], s[8]
-    auto at = [&](int i, int j) -> double & { return i >= j ? A[pk_idx(i, j)] : A[pk_idx(j, i)]; };
-    for (int idx = lane; idx < 136; idx += 64) A[idx] = 0.0;
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    double fro2 = 0.0;
-    if (lane < m) {
-      A[pk_idx(lane, lane)] = d_s[lo + lane];
-      fro2 = d_s[lo + lane] * d_s[lo + lane];
-      if (lane + 1 < m) {
-        A[pk_idx(lane + 1, lane)] = e_s[lo + lane];
-        fro2 += 2.0 * e_s[lo + lane] * e_s[lo + lane];
-      }
-    }
-    const double thr_abs = 0.5 * eps * sqrt(wave_sum(fro2));
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    for (int sweep = 0; sweep < 40; ++sweep) {
-      bool rotated = false;
-      for (int r = 0; r < 15; ++r) {
-        if (lane < 8) {
-          int p, q;
-          pair_of(r, lane, 16, p, q);
-          double c = 1.0, sn = 0.0;
-          if (p < m && q < m) {
-            const double app = at(p, p), aqq = at(q, q), apq = at(p, q);
-            if (fabs(apq) > thr_abs && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
-              const double tau = (aqq - app) / (2.0 * apq);
-              const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-              c = 1.0 / sqrt(1.0 + t * t);
-              sn = t * c;
-              rotated = true;
-            }
-          }
-          rcs[lane] = c;
-          rcs[8 + lane] = sn;
-        }
-        __threadfence_block();
-        __builtin_amdgcn_wave_barrier();
-        {
-          const int I = lane >> 3, J = lane & 7;
-          const double ci = rcs[I], si = rcs[8 + I], cj = rcs[J], sj = rcs[8 + J];
-          if (I >= J && (si != 0.0 || sj != 0.0)) {
-            int pi, qi, pj, qj;
-            pair_of(r, I, 16, pi, qi);
-            pair_of(r, J, 16, pj, qj);
-            const double b00 = at(pi, pj), b01 = at(pi, qj), b10 = at(qi, pj), b11 = at(qi, qj);
-            const double t00 = cj * b00 - sj * b01, t01 = sj * b00 + cj * b01;
-            const double t10 = cj * b10 - sj * b11, t11 = sj * b10 + cj * b11;
-            const double n00 = ci * t00 - si * t10, n01 = ci * t01 - si * t11;
-            const double n10 = si * t00 + ci * t10, n11 = si * t01 + ci * t11;
-            if (I == J) {
-              at(pi, pi) = n00;
-              at(qi, qi) = n11;
-              at(qi, pi) = si != 0.0 ? 0.0 : n10;
-            } else {
-              at(pi, pj) = n00;
-              at(pi, qj) = n01;
-              at(qi, pj) = n10;
-              at(qi, qj) = n11;
-            }
-          }
-        }
-        for (int it = lane; it < 128; it += 64) {
-          const int row = it >> 3, J = it & 7;
-          const double c = rcs[J], sn = rcs[8 + J];
-          if (sn != 0.0 && row < m) {
-            int p, q;
-            pair_of(r, J, 16, p, q);
-            double &vp = Z[(size_t)(lo + p) * n + lo + row], &vq = Z[(size_t)(lo + q) * n + lo + row];
-            const double a = vp, b = vq;
-            vp = c * a - sn * b;
-            vq = sn * a + c * b;
-          }
-        }
-        __threadfence_block();
-        __builtin_amdgcn_wave_barrier();
-      }
-      if (__ballot(rotated) == 0) break;
-    }
-    if (lane < m) d_s[lo + lane] = A[pk_idx(lane, lane)];
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  // merges of the levels above the leaves by the whole workgroup
   {
     DcScratch S;
-    S.z = sbuf; S.dd = sbuf + NMAX; S.zK = sbuf + 2 * NMAX; S.dK = sbuf + 3 * NMAX;
-    S.tau = sbuf + 4 * NMAX; S.dorg = sbuf + 5 * NMAX; S.zh = sbuf + 6 * NMAX;
-    S.lam = sbuf + 7 * NMAX; S.rc = sbuf + 8 * NMAX; S.rs = sbuf + 9 * NMAX;
-    int *ib = reinterpret_cast<int *>(sbuf + 10 * NMAX);
+    double *f = sbuf;
+    S.z = f; S.dd = f + NMAX; S.zK = f + 2 * NMAX; S.dK = f + 3 * NMAX;
+    S.tau = f + 4 * NMAX; S.dorg = f + 5 * NMAX; S.zh = f + 6 * NMAX;
+    S.lam = f + 7 * NMAX; S.rc = f + 8 * NMAX; S.rs = f + 9 * NMAX; S.tol = f + 10 * NMAX;
+    int *ib = reinterpret_cast<int *>(f + 11 * NMAX);
     S.perm = ib; S.K = ib + NMAX; S.defl = ib + 2 * NMAX; S.ra = ib + 3 * NMAX;
-    S.rb = ib + 4 * NMAX; S.cnt = ib + 5 * NMAX;
-    S.red = sbuf + 10 * NMAX + 5 * NMAX / 2 + 8;
-    for (int D = LD - 1; D >= 0; --D)
-      for (int q = 0; q < (1 << D); ++q) {
-        const int lo = dc_bound(q, n, D), hi = dc_bound(q + 1, n, D);
-        const int k = dc_bound(2 * q + 1, n, D + 1);
-        if (lo < k && k < hi) dc_merge(n, lo, k, hi, e_s[k - 1], d_s, Z, S, Vg, Wg);
-      }
+    S.rb = ib + 4 * NMAX; S.cnk = ib + 5 * NMAX; S.cnr = ib + 6 * NMAX;
+    for (int D = LD - 1; D >= 0; --D) dc_level(n, D, e_s, d_s, Z, S, Vg, Wg);
   }
   if constexpr (!BIG)
     for (int idx = tid; idx < n * n; idx += blockDim.x) Zg[idx] = Z[idx];
@@ -1829,7 +1848,7 @@ __global__ __launch_bounds__(512) void eigh_dc_kernel(int n, double *ws) {
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const double *ws,
+__global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, int ncols, const double *ws,
                                                                  double *const *evals,
                                                                  double *const *vecs) {
   constexpr int CB = NMAX > 256 ? 4 : 16;          // eigenvector columns per workgroup
@@ -1838,6 +1857,7 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const do
   __shared__ double2 part[4][CB];
   __shared__ double2 wk[CB];
   __shared__ double dsh[NMAX];
+  __shared__ int src[NMAX];
   const int prob = blockIdx.y, c0 = blockIdx.x * CB;
   const int tid = threadIdx.x;
   const double *base = ws + (size_t)prob * tql_ws_doubles(n);
@@ -1845,12 +1865,27 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const do
   const double2 *tau_g = hh + (size_t)n * n;
   const double *Zg = reinterpret_cast<const double *>(tau_g + n);
   const double *dg = Zg + (size_t)n * n;
-  const int cols = min(CB, n - c0);
+  // descending order (rank sort, ties by index): output column rank holds Z column src[rank];
+  // this workgroup's columns are the ranks c0 .. c0 + cols - 1 (ranks below ncols only)
+  double *ev = evals[prob];
+  for (int i = tid; i < n; i += 256) dsh[i] = dg[i];
+  __syncthreads();
+  for (int j = tid; j < n; j += 256) {
+    const double lj = dsh[j];
+    int rank = 0;
+    for (int i = 0; i < n; ++i) {
+      const double li = dsh[i];
+      rank += (li > lj) || (li == lj && i < j);
+    }
+    src[rank] = j;
+    if (blockIdx.x == 0) ev[rank] = lj;
+  }
+  __syncthreads();
+  const int cols = min(CB, ncols - c0);
   for (int idx = tid; idx < n * CB; idx += 256) {
     const int r = idx / CB, c = idx % CB;
-    Vb[idx] = make_double2(c < cols ? Zg[(size_t)(c0 + c) * n + r] : 0.0, 0.0);
+    Vb[idx] = make_double2(c < cols ? Zg[(size_t)src[c0 + c] * n + r] : 0.0, 0.0);
   }
-  for (int i = tid; i < n; i += 256) dsh[i] = dg[i];
   __syncthreads();
   constexpr int RG = 256 / CB;                        // row groups per column
   const int c = tid & (CB - 1), part_id = tid / CB;
@@ -1887,19 +1922,10 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, const do
     }
     __syncthreads();
   }
-  // descending order (rank sort, ties by index) and output
-  double *ev = evals[prob];
   double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
-  for (int cc = 0; cc < cols; ++cc) {
-    const int j = c0 + cc;
-    const double lj = dsh[j];
-    int rank = 0;
-    for (int i = 0; i < n; ++i) {
-      const double li = dsh[i];
-      rank += (li > lj) || (li == lj && i < j);
-    }
-    for (int r = tid; r < n; r += 256) vo[(size_t)r * n + rank] = Vb[r * CB + cc];
-    if (tid == 0) ev[rank] = lj;
+  for (int idx = tid; idx < n * cols; idx += 256) {
+    const int r = idx / cols, cc = idx % cols;
+    vo[(size_t)r * n + c0 + cc] = Vb[r * CB + cc];
   }
 }
 
@@ -3238,13 +3264,14 @@ class HipBackend : public Backend {
     launch_check("eigh_trd_last_kernel");
   }
   void eigh(int n, int lda, const double *const *in, double *const *evals, double *const *vecs,
-            int nprob) override {
+            int nprob, int ncols) override {
     if (nprob <= 0) return;
     if (n < 1 || n > 512) {
       err_ = -1;
       errmsg_ = "eigh: n must be in 1..512";
       return;
     }
+    ncols = std::max(1, std::min(ncols, n));
     int np = n + (n & 1);
     if (n < 32) {
       size_t sm = (size_t)2 * np * np * sizeof(double2);
@@ -3291,14 +3318,14 @@ class HipBackend : public Backend {
       launch_check("eigh_dc_kernel");
       stale_check("eigh_backtransform_kernel");
       if (n <= 128)
-        hipLaunchKernelGGL(eigh_backtransform_kernel<128>, dim3((n + 15) / 16, nprob), dim3(256),
-                           0, s_, n, (const double *)lws_, evals, vecs);
+        hipLaunchKernelGGL(eigh_backtransform_kernel<128>, dim3((ncols + 15) / 16, nprob),
+                           dim3(256), 0, s_, n, ncols, (const double *)lws_, evals, vecs);
       else if (n <= 256)
-        hipLaunchKernelGGL(eigh_backtransform_kernel<256>, dim3((n + 15) / 16, nprob), dim3(256),
-                           0, s_, n, (const double *)lws_, evals, vecs);
+        hipLaunchKernelGGL(eigh_backtransform_kernel<256>, dim3((ncols + 15) / 16, nprob),
+                           dim3(256), 0, s_, n, ncols, (const double *)lws_, evals, vecs);
       else
-        hipLaunchKernelGGL(eigh_backtransform_kernel<512>, dim3((n + 3) / 4, nprob), dim3(256),
-                           0, s_, n, (const double *)lws_, evals, vecs);
+        hipLaunchKernelGGL(eigh_backtransform_kernel<512>, dim3((ncols + 3) / 4, nprob),
+                           dim3(256), 0, s_, n, ncols, (const double *)lws_, evals, vecs);
     }
     launch_check("eigh");
   }

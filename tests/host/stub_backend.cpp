@@ -98,7 +98,7 @@ class StubBackend : public Backend {
   void gemm(const GemmDesc &, const double *const *, const double *const *, double *const *,
             int) override {}
   void eigh(int n, int, const double *const *, double *const *evals, double *const *,
-            int nprob) override {
+            int nprob, int) override {
     for (int p = 0; p < nprob; ++p)
       for (int i = 0; i < n; ++i) evals[p][i] = i == 0 ? 1.0 : 0.0;
   }

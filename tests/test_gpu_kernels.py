@@ -267,6 +267,28 @@ def test_eigh_matches_numpy(ctx, n):
         assert np.abs(A[p] @ V[p] - V[p] * ev[p][None, :]).max() < 1e-12 * scale * max(1, n / 16)
 
 
+@pytest.mark.parametrize("n,ncols", [(64, 1), (128, 64), (100, 37), (256, 128), (300, 150)])
+def test_eigh_leading_columns(ctx, n, ncols):
+    """Only the eigenvectors of the ncols largest eigenvalues (the truncation keeps at most chi of
+    2 chi): all eigenvalues as with every column, those columns equal to the full solve's, the
+    others untouched.  Includes a degenerate spectrum that straddles the cut."""
+    print(f"[eigh] n={n} ncols={ncols}", flush=True)
+    rng = np.random.default_rng(7 * n + ncols)
+    X = _rand(rng, 3, n, n)
+    A = X + X.conj().transpose(0, 2, 1)
+    U, _ = np.linalg.qr(_rand(rng, n, n))
+    lam = np.where(np.arange(n) < ncols + 2, 1.0, np.linspace(0.5, -1.0, n))
+    A[1] = (U * lam[None, :]) @ U.conj().T
+    k = max(1, n // 2)
+    Y = _rand(rng, 2 * n, k) * np.logspace(0, -6, k)[None, :]
+    A[2] = (Y @ _rand(rng, k, n)).conj().T @ (Y @ _rand(rng, k, n))
+    ev_all, V_all = ctx.test_eigh(A)
+    ev, V = ctx.test_eigh(A, ncols=ncols)
+    assert np.array_equal(ev, ev_all)
+    assert np.array_equal(V[:, :, :ncols], V_all[:, :, :ncols])
+    assert not np.any(V[:, :, ncols:])
+
+
 @pytest.mark.parametrize("n,rank", [(8, 8), (16, 5), (128, 128), (128, 70), (130, 129), (160, 100),
                                     (200, 200), (256, 200), (256, 256), (384, 300),
                                     (512, 512)])
