@@ -108,7 +108,7 @@ struct LayerPlan {
   GemmOp gram;
   size_t g_in = 0, g_ev = 0, g_vec = 0, g_R = 0, g_Wsc = 0;
   int n_g = 0;
-  GemmOp qform;
+  GemmOp wr;                        // deg-3 endpoints: WR = Wsc R'
   // per (rB, rS) edge type
   struct Type {
     int rB = 0, rS = 0, n = 0;
@@ -126,7 +126,7 @@ struct LayerPlan {
     size_t in = 0, ev = 0, vec = 0;
   };
   std::vector<EighGroup> eig_groups;
-  GemmOp rebuild;                   // deg-3 endpoints: Tt = Q R'
+  GemmOp rebuild;                   // deg-3 endpoints: Tt = A WR (= Q R' with Q = A Wsc)
   std::vector<GemmOp> remove;       // grouped
   std::vector<std::pair<size_t, size_t>> copies_in, copies_out;  // deg-1 (dst, src, bytes) as ptr
   std::vector<std::tuple<double *, const double *, size_t>> d2d_in, d2d_out;
@@ -493,8 +493,8 @@ void Engine::build() {
       LP.m_in = P.arena.add(min); LP.m_ev = P.arena.add(mev); LP.m_vec = P.arena.add(mvec);
       LP.m_X = P.arena.add(mX); LP.m_Xp = P.arena.add(mXp);
     }
-    // 2. absorb into A-layout; allocate A, Q, Tt, Y1 per endpoint
-    std::vector<size_t> aoff(LP.eps.size()), qoff(LP.eps.size()), ttoff(LP.eps.size()),
+    // 2. absorb into A-layout; allocate A, WR, Tt, Y1 per endpoint
+    std::vector<size_t> aoff(LP.eps.size()), wroff(LP.eps.size()), ttoff(LP.eps.size()),
         y1off(LP.eps.size()), roff(LP.eps.size()), rnoff(LP.eps.size());
     for (size_t q = 0; q < LP.eps.size(); ++q) {
       const Endpoint &ep = LP.eps[q];
@@ -502,7 +502,7 @@ void Engine::build() {
       aoff[q] = bump.take(sz);
       ttoff[q] = bump.take(sz);
       y1off[q] = ep.deg == 3 ? bump.take(sz) : 0;
-      qoff[q] = ep.deg == 3 ? bump.take((size_t)c2 * 2 * chi) : 0;
+      wroff[q] = ep.deg == 3 ? bump.take((size_t)4 * c2) : 0;        // WR (2chi x 2chi)
       roff[q] = ep.deg == 3 ? bump.take((size_t)4 * c2) : aoff[q];   // R (r x 2chi)
       rnoff[q] = bump.take((size_t)ep.r * 2 * chi);                  // R' (r x 2 x chi)
     }
@@ -577,7 +577,7 @@ void Engine::build() {
     }
     // 3. Gram factor for degree-3 endpoints
     {
-      std::vector<const void *> ga, gc, gev, gvec, gR, gW, qa, qb, qc, ra, rb, rc;
+      std::vector<const void *> ga, gc, gev, gvec, gR, gW, wa, wb, wc, ra, rb, rc;
       for (size_t q = 0; q < LP.eps.size(); ++q) {
         const Endpoint &ep = LP.eps[q];
         if (ep.deg != 3) continue;
@@ -586,8 +586,8 @@ void Engine::build() {
         ga.push_back(W(aoff[q])); gc.push_back(W(o_G));
         gev.push_back(W(o_ev)); gvec.push_back(W(o_vec));
         gR.push_back(W(roff[q])); gW.push_back(W(o_W));
-        qa.push_back(W(aoff[q])); qb.push_back(W(o_W)); qc.push_back(W(qoff[q]));
-        ra.push_back(W(qoff[q])); rb.push_back(W(rnoff[q])); rc.push_back(W(ttoff[q]));
+        wa.push_back(W(o_W)); wb.push_back(W(rnoff[q])); wc.push_back(W(wroff[q]));
+        ra.push_back(W(aoff[q])); rb.push_back(W(wroff[q])); rc.push_back(W(ttoff[q]));
       }
       LP.n_g = (int)ga.size();
       GemmDesc g;                       // G = A^H A, A: [env][2chi]
@@ -597,19 +597,22 @@ void Engine::build() {
       g.c_mi = 2 * chi; g.c_ni = 1;
       g.herm = 1;                       // Hermitian: lower triangle, conjugate mirror
       LP.gram.d = g;
-      GemmDesc qd;                      // Q = A Wsc : [env][2chi] x [2chi][2chi]
-      qd.M = (int)c2; qd.Mi = (int)c2; qd.a_mi = 2 * chi; qd.c_mi = 2 * chi;
-      qd.K = 2 * chi; qd.Ki = 2 * chi; qd.a_ki = 1; qd.b_ki = 2 * chi;
-      qd.N = 2 * chi; qd.Ni = 2 * chi; qd.b_ni = 1; qd.c_ni = 1;
-      LP.qform.d = qd;
-      GemmDesc rd = qd;                 // Tt = Q R' : [env][2chi] x [2chi][2chi]
+      // The isometry Q = A Wsc is never formed: the rebuilt tensor Q R' is taken as A (Wsc R'),
+      // a small product first (2chi x 2chi x 2chi) and one environment-sized one instead of two.
+      GemmDesc wd;                      // WR = Wsc R' : [2chi][2chi] x [2chi][2chi]
+      wd.M = 2 * chi; wd.Mi = 2 * chi; wd.a_mi = 2 * chi; wd.c_mi = 2 * chi;
+      wd.K = 2 * chi; wd.Ki = 2 * chi; wd.a_ki = 1; wd.b_ki = 2 * chi;
+      wd.N = 2 * chi; wd.Ni = 2 * chi; wd.b_ni = 1; wd.c_ni = 1;
+      LP.wr.d = wd;
+      GemmDesc rd = wd;                 // Tt = A WR : [env][2chi] x [2chi][2chi]
+      rd.M = (int)c2; rd.Mi = (int)c2;
       LP.rebuild.d = rd;
-      LP.gram.n = LP.qform.n = LP.rebuild.n = LP.n_g;
+      LP.gram.n = LP.wr.n = LP.rebuild.n = LP.n_g;
       if (real) {
         LP.gram.a = P.arena.add(ga); LP.gram.b = LP.gram.a; LP.gram.c = P.arena.add(gc);
         LP.g_in = LP.gram.c; LP.g_ev = P.arena.add(gev); LP.g_vec = P.arena.add(gvec);
         LP.g_R = P.arena.add(gR); LP.g_Wsc = P.arena.add(gW);
-        LP.qform.a = P.arena.add(qa); LP.qform.b = P.arena.add(qb); LP.qform.c = P.arena.add(qc);
+        LP.wr.a = P.arena.add(wa); LP.wr.b = P.arena.add(wb); LP.wr.c = P.arena.add(wc);
         LP.rebuild.a = P.arena.add(ra); LP.rebuild.b = P.arena.add(rb);
         LP.rebuild.c = P.arena.add(rc);
       }
@@ -1269,7 +1272,6 @@ double Engine::apply_layer(int colour, int zz_sign) {
     run(be_, ar, LP.gram, su_prec());
     be_->gram_chol(2 * chi, ar.at<const double *const *>(LP.g_in), ar.at<double *const *>(LP.g_R),
                    ar.at<double *const *>(LP.g_Wsc), kGramCut, LP.n_g);
-    run(be_, ar, LP.qform, su_prec());
   }
   // 4-6. Theta, truncated SVD, new factors
   const double q = M_PI / 4;
@@ -1294,7 +1296,10 @@ double Engine::apply_layer(int colour, int zz_sign) {
                     ar.at<double *const *>(T.RBn), ar.at<double *const *>(T.RSn), T.count);
   }
   // 7. rebuild and remove the environment
-  if (LP.n_g) run(be_, ar, LP.rebuild, su_prec());
+  if (LP.n_g) {
+    run(be_, ar, LP.wr, su_prec());
+    run(be_, ar, LP.rebuild, su_prec());
+  }
   // degree <= 2: T~' = R' (already in A-layout); point remove ops at R' directly
   for (auto &op : LP.remove) run(be_, ar, op, su_prec());
   for (auto &t : LP.d2d_out) be_->d2d(std::get<0>(t), std::get<1>(t), std::get<2>(t));
