@@ -3337,7 +3337,7 @@ class HipBackend : public Backend {
   void msg_sqrt(int n, const double *const *ev, const double *const *vec, double *const *X,
                 double *const *Xp, double cut, int nprob) override {
     if (nprob <= 0) return;
-    if (n <= 64) {
+    if (n < 64) {
       stale_check("msg_sqrt_kernel");
       hipLaunchKernelGGL(msg_sqrt_kernel, dim3(nprob), dim3(256), 0, s_, n, ev, vec, X, Xp, cut);
       launch_check("msg_sqrt_kernel");
