@@ -1407,6 +1407,175 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
   __syncthreads();
 
   // ---- 1. tridiagonal reduction ----
+  if constexpr (!BIG) {
+    // n <= 128, matrix packed in LDS, with look-ahead: while waves 1.. apply the rank-2 update
+    // of step k to columns k+2.., wave 0 updates column k+1 and forms reflector k+1 from it in
+    // registers, so every step has two barriers and no serial reflector phase.  The reflector
+    // vector and tau are double buffered (vb[b], tau_b[b]).
+    __shared__ double2 tau_b[2];
+    double2 *vb[2] = {v_s, x1_s};
+    // reflector k from its column col[i] = A(k+1+i, k), i < m (this lane: i = lane + 64 t), and
+    // the diagonal dkk = A(k, k); wave 0 only
+    auto reflect = [&](int k, const double2 (&col)[2], double dkk, int b) {
+      const int m = n - 1 - k;
+      double sq = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = lane + 64 * t;
+        if (i >= 1 && i < m) sq += col[t].x * col[t].x + col[t].y * col[t].y;
+      }
+      sq = wave_sum(sq);
+      const double2 alpha = make_double2(readlane_d(col[0].x, 0), readlane_d(col[0].y, 0));
+      double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+      double beta = alpha.x;
+      if (sq > 0.0 || alpha.y != 0.0) {
+        beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sq), alpha.x);
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);   // 1 / (alpha - beta)
+        const double dn = den.x * den.x + den.y * den.y;
+        scale = make_double2(den.x / dn, -den.y / dn);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = lane + 64 * t;
+        if (i < m) {
+          const double2 vi = i == 0 ? make_double2(1.0, 0.0) : cmul(col[t], scale);
+          vb[b][i] = vi;
+          hh[(size_t)k * n + k + 1 + i] = vi;
+        }
+      }
+      if (lane == 0) {
+        tau_b[b] = tau;
+        tau_g[k] = tau;
+        e_s[k] = beta;
+        d_s[k] = dkk;
+      }
+    };
+    auto reflect_lds = [&](int k, int b) {
+      const int m = n - 1 - k;
+      double2 col[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = lane + 64 * t;
+        col[t] = i < m ? pel(k + 1 + i, k) : make_double2(0.0, 0.0);
+      }
+      reflect(k, col, pel(k, k).x, b);
+    };
+    int b = 0;
+    if (n >= 2 && wave == 0) reflect_lds(0, 0);
+    __syncthreads();
+    for (int k = 0; k + 1 < n; ++k, b ^= 1) {
+      const int m = n - 1 - k;          // length of the column below the diagonal
+      const double2 tau = tau_b[b];
+      if (tau.x == 0.0 && tau.y == 0.0) {   // H_k = I: column k+1 is as it was
+        if (k + 2 < n && wave == 0) reflect_lds(k + 1, b ^ 1);
+        __syncthreads();
+        continue;
+      }
+      const double2 *v = vb[b];
+      {
+        // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): TPR = 8 threads per
+        // row; row gi of S is row gi of the packed triangle up to the diagonal, then column gi
+        // (packed index of (k+1+c, gi) stepped by c += 8: + 8 (k+1+c) + 36)
+        static_assert(TPR == 8, "the row sums are reductions over aligned groups of 8 lanes");
+        const int r = tid / TPR, q = tid % TPR;
+        double2 acc = make_double2(0.0, 0.0);
+        if (r < m) {
+          const int gi = k + 1 + r;
+          const double2 *prow = smem + pk_idx(gi, k + 1);
+#pragma unroll 4
+          for (int c = q; c <= r; c += TPR) {
+            const double2 a = prow[c], vc = v[c];
+            acc.x += a.x * vc.x - a.y * vc.y;
+            acc.y += a.x * vc.y + a.y * vc.x;
+          }
+          int i = gi + 1 + q, idx = i * (i + 1) / 2 + gi;
+#pragma unroll 4
+          for (int c = r + 1 + q; c < m; c += TPR) {
+            const double2 a = smem[idx], vc = v[c];   // conj(a) vc
+            acc.x += a.x * vc.x + a.y * vc.y;
+            acc.y += a.x * vc.y - a.y * vc.x;
+            idx += 8 * i + 36;
+            i += 8;
+          }
+        }
+        acc.x = oct_sum(acc.x);
+        acc.y = oct_sum(acc.y);
+        // this wave's share of v^H x (rows r < m), for a = -(1/2) Re(conj(tau) v^H x)
+        double pr = 0.0, pi = 0.0;
+        if (r < m && q == 0) {
+          const double2 x = cmul(tau, acc), vr = v[r];
+          w_s[r] = x;
+          pr = vr.x * x.x + vr.y * x.y;
+          pi = vr.x * x.y - vr.y * x.x;
+        }
+        pr = wave_sum(pr);
+        pi = wave_sum(pi);
+        if (lane == 0) dot_s[wave] = make_double2(pr, pi);
+      }
+      __syncthreads();
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < nw; ++w2) {          // the waves' shares in a fixed order
+        dr += dot_s[w2].x;
+        di += dot_s[w2].y;
+      }
+      const double aw = -0.5 * (tau.x * dr + tau.y * di);
+      // S <- S - v w^H - w v^H on the lower triangle, w = x + aw v
+      auto wval = [&](int i) {
+        const double2 vi = v[i], xi = w_s[i];
+        return make_double2(xi.x + aw * vi.x, xi.y + aw * vi.y);
+      };
+      auto upd = [&](double2 a, double2 vi, double2 wi, double2 vc, double2 wc, bool diag) {
+        const double ur = vi.x * wc.x + vi.y * wc.y + wi.x * vc.x + wi.y * vc.y;
+        const double ui = vi.y * wc.x - vi.x * wc.y + wi.y * vc.x - wi.x * vc.y;
+        return make_double2(a.x - ur, diag ? 0.0 : a.y - ui);
+      };
+      if (wave == 0) {
+        // column k+1 (c = 0): the diagonal by lane 0, rows rr = 1 + lane + 64 t, then the next
+        // reflector from these values
+        const double2 v0 = v[0], w0 = wval(0);
+        double dnext = 0.0;
+        if (lane == 0) {
+          double2 &a = smem[pk_idx(k + 1, k + 1)];
+          const double2 y = upd(a, v0, w0, v0, w0, true);
+          a = y;
+          dnext = y.x;
+        }
+        double2 col[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int rr = 1 + lane + 64 * t;
+          col[t] = make_double2(0.0, 0.0);
+          if (rr < m) {
+            double2 &a = smem[pk_idx(k + 1 + rr, k + 1)];
+            col[t] = upd(a, v[rr], wval(rr), v0, w0, false);
+            a = col[t];
+          }
+        }
+        if (k + 2 < n) reflect(k + 1, col, readlane_d(dnext, 0), b ^ 1);
+      } else {
+        // columns c >= 1 of rows rr (waves 1 .. nw-1 in turn)
+        double2 wl[NMAX / 64], vl[NMAX / 64];
+#pragma unroll
+        for (int t = 0; t < NMAX / 64; ++t) {
+          const int c = lane + 64 * t;
+          vl[t] = c < m ? v[c] : make_double2(0.0, 0.0);
+          wl[t] = c < m ? wval(c) : make_double2(0.0, 0.0);
+        }
+        for (int rr = wave - 1; rr < m; rr += nw - 1) {
+          const double2 vi = v[rr], wi = wval(rr);
+          double2 *prow = smem + pk_idx(k + 1 + rr, k + 1);
+#pragma unroll
+          for (int t = 0; t < NMAX / 64; ++t) {
+            const int c = lane + 64 * t;
+            if (c >= 1 && c <= rr) prow[c] = upd(prow[c], vi, wi, vl[t], wl[t], c == rr);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else
   for (int k = 0; k + 1 < n; ++k) {
     const int m = n - 1 - k;          // length of the column below the diagonal
     if (wave == 0) {
