@@ -126,7 +126,8 @@ struct LayerPlan {
     size_t in = 0, ev = 0, vec = 0;
   };
   std::vector<EighGroup> eig_groups;
-  GemmOp rebuild;                   // deg-3 endpoints: Tt = A WR (= Q R' with Q = A Wsc)
+  // deg-3 endpoints: Tt = A WR (= Q R' with Q = A Wsc), written in T-order; one per bond leg
+  std::vector<GemmOp> rebuild;
   std::vector<GemmOp> remove;       // grouped
   std::vector<std::pair<size_t, size_t>> copies_in, copies_out;  // deg-1 (dst, src, bytes) as ptr
   std::vector<std::tuple<double *, const double *, size_t>> d2d_in, d2d_out;
@@ -239,9 +240,18 @@ static GemmDesc leg_desc(int deg, int leg, const Layout &in, const Layout &out, 
     d.M = chi; d.Mi = chi;
     d.a_mi = in.leg[others[0]]; d.c_mi = out.leg[others[0]];
   } else {
+    // M = (outer, inner) over the two other legs, in the order that lets both the loads (a unit
+    // stride along K or the inner M index) and the stores (along the inner M index or N) run on
+    // consecutive addresses when one order does; otherwise ascending leg order.  The order only
+    // decides which rows a workgroup owns, not how an element is summed.
+    auto coalesced = [&](int inner) {
+      return (in.leg[inner] == 1 || in.leg[leg] == 1) && (out.leg[inner] == 1 || out.leg[leg] == 1);
+    };
+    const bool swap = !coalesced(others[1]) && coalesced(others[0]);
+    const int mo = swap ? others[1] : others[0], mi = swap ? others[0] : others[1];
     d.M = chi * chi; d.Mi = chi;
-    d.a_mo = in.leg[others[0]]; d.a_mi = in.leg[others[1]];
-    d.c_mo = out.leg[others[0]]; d.c_mi = out.leg[others[1]];
+    d.a_mo = in.leg[mo]; d.a_mi = in.leg[mi];
+    d.c_mo = out.leg[mo]; d.c_mi = out.leg[mi];
   }
   d.K = chi; d.Ki = chi; d.a_ki = in.leg[leg];
   d.b_ki = chi;
@@ -553,7 +563,7 @@ void Engine::build() {
       GemmOp s1, s2, r1, r2;
       s1.d = leg_desc(3, ep0.env[0], Lt, Lt, chi);
       s2.d = leg_desc(3, ep0.env[1], Lt, La, chi);
-      r1.d = leg_desc(3, ep0.env[0], La, Lt, chi);
+      r1.d = leg_desc(3, ep0.env[0], Lt, Lt, chi);   // Tt is in T-order
       r2.d = leg_desc(3, ep0.env[1], Lt, Lt, chi);
       std::vector<const void *> a1, b1, c1, a2, b2, c2v, ra1, rb1, rc1, ra2, rb2, rc2;
       for (size_t q : g.second) {
@@ -577,7 +587,8 @@ void Engine::build() {
     }
     // 3. Gram factor for degree-3 endpoints
     {
-      std::vector<const void *> ga, gc, gev, gvec, gR, gW, wa, wb, wc, ra, rb, rc;
+      std::vector<const void *> ga, gc, gev, gvec, gR, gW, wa, wb, wc;
+      std::map<int, std::vector<const void *>> ra, rb, rc;          // by bond leg
       for (size_t q = 0; q < LP.eps.size(); ++q) {
         const Endpoint &ep = LP.eps[q];
         if (ep.deg != 3) continue;
@@ -587,7 +598,8 @@ void Engine::build() {
         gev.push_back(W(o_ev)); gvec.push_back(W(o_vec));
         gR.push_back(W(roff[q])); gW.push_back(W(o_W));
         wa.push_back(W(o_W)); wb.push_back(W(rnoff[q])); wc.push_back(W(wroff[q]));
-        ra.push_back(W(aoff[q])); rb.push_back(W(wroff[q])); rc.push_back(W(ttoff[q]));
+        ra[ep.j].push_back(W(aoff[q])); rb[ep.j].push_back(W(wroff[q]));
+        rc[ep.j].push_back(W(ttoff[q]));
       }
       LP.n_g = (int)ga.size();
       GemmDesc g;                       // G = A^H A, A: [env][2chi]
@@ -604,17 +616,34 @@ void Engine::build() {
       wd.K = 2 * chi; wd.Ki = 2 * chi; wd.a_ki = 1; wd.b_ki = 2 * chi;
       wd.N = 2 * chi; wd.Ni = 2 * chi; wd.b_ni = 1; wd.c_ni = 1;
       LP.wr.d = wd;
-      GemmDesc rd = wd;                 // Tt = A WR : [env][2chi] x [2chi][2chi]
-      rd.M = (int)c2; rd.Mi = (int)c2;
-      LP.rebuild.d = rd;
-      LP.gram.n = LP.wr.n = LP.rebuild.n = LP.n_g;
+      // Tt = A WR : [env][2chi] x [2chi][2chi], written straight into T-order (rows (env0, env1),
+      // columns (s, a_j)), so that the environment is removed with the loads and stores of the
+      // leg contractions running along unit-stride legs
+      const Layout Lt3 = t_layout(3, chi);
+      LP.rebuild.clear();
+      for (auto &jr : ra) {
+        const int j = jr.first;
+        int env[2], ne = 0;
+        for (int i = 0; i < 3; ++i)
+          if (i != j) env[ne++] = i;
+        GemmOp op;
+        GemmDesc rd = wd;
+        rd.M = (int)c2; rd.Mi = chi; rd.a_mo = 2L * chi * chi; rd.a_mi = 2 * chi;
+        rd.c_mo = Lt3.leg[env[0]]; rd.c_mi = Lt3.leg[env[1]];
+        rd.Ni = chi; rd.b_no = chi; rd.b_ni = 1; rd.c_no = Lt3.s; rd.c_ni = Lt3.leg[j];
+        op.d = rd;
+        op.n = (int)jr.second.size();
+        if (real) {
+          op.a = P.arena.add(jr.second); op.b = P.arena.add(rb[j]); op.c = P.arena.add(rc[j]);
+        }
+        LP.rebuild.push_back(op);
+      }
+      LP.gram.n = LP.wr.n = LP.n_g;
       if (real) {
         LP.gram.a = P.arena.add(ga); LP.gram.b = LP.gram.a; LP.gram.c = P.arena.add(gc);
         LP.g_in = LP.gram.c; LP.g_ev = P.arena.add(gev); LP.g_vec = P.arena.add(gvec);
         LP.g_R = P.arena.add(gR); LP.g_Wsc = P.arena.add(gW);
         LP.wr.a = P.arena.add(wa); LP.wr.b = P.arena.add(wb); LP.wr.c = P.arena.add(wc);
-        LP.rebuild.a = P.arena.add(ra); LP.rebuild.b = P.arena.add(rb);
-        LP.rebuild.c = P.arena.add(rc);
       }
     }
     // 4-6. per edge type
@@ -1298,7 +1327,7 @@ double Engine::apply_layer(int colour, int zz_sign) {
   // 7. rebuild and remove the environment
   if (LP.n_g) {
     run(be_, ar, LP.wr, su_prec());
-    run(be_, ar, LP.rebuild, su_prec());
+    for (auto &op : LP.rebuild) run(be_, ar, op, su_prec());
   }
   // degree <= 2: T~' = R' (already in A-layout); point remove ops at R' directly
   for (auto &op : LP.remove) run(be_, ar, op, su_prec());
