@@ -987,6 +987,10 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
 __device__ __forceinline__ double readlane_d(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                           __builtin_amdgcn_readlane(__double2loint(v), l));
@@ -1010,6 +1014,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   v = oct_sum(v);
   v += dpp_d<0x140>(v);
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+// the largest value over the wave and its index (the smallest index among equal values), in
+// every lane
+__device__ __forceinline__ void wave_argmax(double &best, int &bj) {
+  auto take = [&](double ob, int oj) {
+    if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+  };
+  take(dpp_d<0xB1>(best), dpp_i<0xB1>(bj));
+  take(dpp_d<0x4E>(best), dpp_i<0x4E>(bj));
+  take(dpp_d<0x141>(best), dpp_i<0x141>(bj));
+  take(dpp_d<0x140>(best), dpp_i<0x140>(bj));
+  const double r0 = readlane_d(best, 0), r1 = readlane_d(best, 16), r2 = readlane_d(best, 32),
+               r3 = readlane_d(best, 48);
+  const int j0 = __builtin_amdgcn_readlane(bj, 0), j1 = __builtin_amdgcn_readlane(bj, 16),
+            j2 = __builtin_amdgcn_readlane(bj, 32), j3 = __builtin_amdgcn_readlane(bj, 48);
+  best = r0;
+  bj = j0;
+  take(r1, j1);
+  take(r2, j2);
+  take(r3, j3);
 }
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_d<0xB1>(v));
@@ -2186,11 +2210,7 @@ __global__ __launch_bounds__(1024) void chol_panel_kernel(int n, int k0, double 
         const double v = dg_s[perm_s[q]];
         if (v > best) { best = v; bj = q; }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oj = __shfl_xor(bj, o, 64);
-        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
-      }
+      wave_argmax(best, bj);
       if (lane == 0) {
         if (!(best > cut * gmax) || !(gmax > 0)) {
           stop_s = 1;
@@ -2345,7 +2365,7 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
   if (wave == 0) {
     double m = 0;
     for (int i = lane; i < n; i += 64) m = fmax(m, dg[i]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    m = wave_max(m);
     if (lane == 0) {
       gmax_s = m;
       rank_s = n;
@@ -2361,11 +2381,7 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
         const double v = dg[perm[j]];
         if (v > best) { best = v; bj = j; }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oj = __shfl_xor(bj, o, 64);
-        if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; }
-      }
+      wave_argmax(best, bj);
       if (lane == 0) {
         if (!(best > cut * gmax) || !(gmax > 0)) {
           rank_s = k;
@@ -2433,10 +2449,8 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
         sr += a.x * x.x - a.y * x.y;
         si += a.x * x.y + a.y * x.x;
       }
-      for (int o = 1; o < 8; o <<= 1) {
-        sr += __shfl_xor(sr, o, 64);
-        si += __shfl_xor(si, o, 64);
-      }
+      sr = oct_sum(sr);
+      si = oct_sum(si);
       if (q == 0) X[pk_idx(i, j)] = make_double2(((i == j ? 1.0 : 0.0) - sr) * inv, -si * inv);
     }
     if (fetch) lrow[(i + 1) & 1][tid] = nxt;
