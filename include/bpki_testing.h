@@ -56,10 +56,14 @@ int bpki_test_gemm(bpki_ctx *ctx, const bpki_test_gemm_desc *d, int nprob, const
  * s in {0, 1}, x in [0, xdim), b, b', a, a0 in [0, chi); strides in complex elements; xdim = chi (a
  * degree-3 site, Y holding the chunk leg's message already) or 1 (a degree-2 site, Y = T).  out
  * [nprob][chi][chi] is exactly Hermitian.  precision BPKI_FP64 or BPKI_FP32 (FP32 MFMA); store32 = 1
- * holds Y and T as complex FP32 on the device (BPKI_FP32 only). */
-int bpki_test_bp_close(bpki_ctx *ctx, int32_t chi, int precision, int store32, int64_t rs,
-                       int64_t qs, int64_t cs, int64_t ss, int32_t xdim, int nprob, const double *Y,
-                       const double *T, size_t y_elems, const double *M, double *out);
+ * holds Y and T as complex FP32 on the device (BPKI_FP32 only).  pair = 1: no message is applied
+ * (M is not read) and out[p][b][b'] = sum_{s, x, a} Y[p][s ss + b rs + a qs + x cs]
+ * conj(T[p][s ss + b' rs + a qs + x cs]) for b >= b', its conjugate mirror above: the message when
+ * Y and T are the site tensor with the messages of the two summed legs absorbed, one in each. */
+int bpki_test_bp_close(bpki_ctx *ctx, int32_t chi, int precision, int store32, int32_t pair,
+                       int64_t rs, int64_t qs, int64_t cs, int64_t ss, int32_t xdim, int nprob,
+                       const double *Y, const double *T, size_t y_elems, const double *M,
+                       double *out);
 
 /* Batched Hermitian eigendecomposition (FP64; cyclic Jacobi for n < 32, Householder
  * tridiagonalisation + divide and conquer otherwise) of nprob n x n matrices (n <= 512):

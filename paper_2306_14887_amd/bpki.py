@@ -125,9 +125,9 @@ def load(path: str | None = None):
         "bpki_test_eigh": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, dp, dp, dp]),
         "bpki_test_gram_chol": (C.c_int, [vp, C.c_int, C.c_int, dp, C.c_double, dp, dp]),
         "bpki_test_mfma_rate": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, dp]),
-        "bpki_test_bp_close": (C.c_int, [vp, C.c_int32, C.c_int, C.c_int, C.c_int64, C.c_int64,
-                                         C.c_int64, C.c_int64, C.c_int32, C.c_int, dp, dp,
-                                         C.c_size_t, dp, dp]),
+        "bpki_test_bp_close": (C.c_int, [vp, C.c_int32, C.c_int, C.c_int, C.c_int32, C.c_int64,
+                                         C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int, dp,
+                                         dp, C.c_size_t, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -366,10 +366,10 @@ class Context:
         return out.value
 
     def test_bp_close(self, Y, T, M, rs: int, qs: int, cs: int, ss: int, precision: int = 0,
-                      store32: int = 0, xdim: int | None = None):
+                      store32: int = 0, xdim: int | None = None, pair: int = 0):
         """Fused BP message at chi = 32 or 64, chi = M.shape[-1] (see bpki_testing.h): Y, T
         [nprob][elems], M [nprob][chi][chi] -> out [nprob][chi][chi]; xdim chi (degree 3, the
-        default) or 1 (degree 2)."""
+        default) or 1 (degree 2); pair = 1: Y conj(T) with no message applied (M gives chi only)."""
         Y = np.ascontiguousarray(Y, dtype=np.complex128)
         T = np.ascontiguousarray(T, dtype=np.complex128)
         M = np.ascontiguousarray(M, dtype=np.complex128)
@@ -377,7 +377,8 @@ class Context:
         out = np.zeros((nprob, chi, chi), dtype=np.complex128)
         dp = C.POINTER(C.c_double)
         _check(self.lib, self.lib.bpki_test_bp_close(
-            self.h, chi, precision, store32, rs, qs, cs, ss, chi if xdim is None else xdim, nprob,
+            self.h, chi, precision, store32, pair, rs, qs, cs, ss, chi if xdim is None else xdim,
+            nprob,
             Y.ctypes.data_as(dp),
             T.ctypes.data_as(dp), Y.size // nprob, M.ctypes.data_as(dp), out.ctypes.data_as(dp)))
         return out

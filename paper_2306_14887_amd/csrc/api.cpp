@@ -1246,12 +1246,12 @@ extern "C" int bpki_test_gemm(bpki_ctx *c, const bpki_test_gemm_desc *td, int np
 }
 
 extern "C" int bpki_test_bp_close(bpki_ctx *c, int32_t chi, int precision, int store32,
-                                  int64_t rs, int64_t qs, int64_t cs, int64_t ss, int32_t xdim,
-                                  int nprob, const double *Y, const double *T, size_t y_elems,
-                                  const double *M, double *out) {
+                                  int32_t pair, int64_t rs, int64_t qs, int64_t cs, int64_t ss,
+                                  int32_t xdim, int nprob, const double *Y, const double *T,
+                                  size_t y_elems, const double *M, double *out) {
   if (!c || !Y || !T || !M || !out || nprob < 1 || !bp_close_chi(chi) ||
       (precision != BPKI_FP64 && precision != BPKI_FP32) || (store32 != 0 && store32 != 1) ||
-      (store32 && precision != BPKI_FP32) || (xdim != 1 && xdim != chi))
+      (store32 && precision != BPKI_FP32) || (xdim != 1 && xdim != chi) || (pair != 0 && pair != 1))
     return fail(-1, "bad argument");
   if (rs < 0 || qs < 0 || cs < 0 || ss < 0) return fail(-1, "negative stride");
   const long C = chi;
@@ -1296,6 +1296,7 @@ extern "C" int bpki_test_bp_close(bpki_ctx *c, int32_t chi, int precision, int s
   d.group = nprob;
   d.prec = precision == BPKI_FP32 ? 1 : 0;
   d.s32 = store32;
+  d.pair = pair;
   be->bp_close(d, (const double *const *)ptrs, (const double *const *)(ptrs + nprob),
                (const double *const *)(ptrs + 2 * nprob), (double *const *)(ptrs + 3 * nprob),
                nprob);

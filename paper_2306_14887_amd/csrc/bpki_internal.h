@@ -56,6 +56,9 @@ struct BpCloseDesc {
   int xdim = 64;                         // extent of the chunk leg (chi), or 1 without one
   int prec = 0;                          // 0: FP64 MFMA; 1: FP32 MFMA
   int s32 = 0;                           // Y and T stored as complex FP32 (prec = 1 only)
+  // 1: out[b][b'] = sum over chunks of sum_a Y[b][a] conj(T[b'][a]) with T (the second tensor) a
+  // second absorbed copy of the site tensor and no message applied (M unused)
+  int pair = 0;
 };
 // The bond dimensions the fused closing is built for.
 inline bool bp_close_chi(int chi) { return chi == 64 || chi == 32; }

@@ -992,8 +992,9 @@ void Engine::build() {
       ops32 = mixed ? &C32.ops : nullptr;
       auto in = [&](int v, int i) { return cls[P.nb[v][i]] < c ? Mnp(P.in_msg[v][i]) : Mp(P.in_msg[v][i]); };
       // degree 3 at chi = 32 or 64, fused: Y1 = T x1 M1 ; Y0 = T x0 M0 (two leg absorptions), then
-      //   out0 = close(Y1, apply M2, chunks over leg 1), out2 = close(Y1, apply M0, chunks over
-      //   leg 1), out1 = close(Y0, apply M2, chunks over leg 0)
+      //   out0 = close(Y1, apply M2, chunks over leg 1), out1 = close(Y0, apply M2, chunks over
+      //   leg 0), and out2 = pair(Y0, Y1, chunks over leg 1): both of its summed legs' messages are
+      //   already absorbed, one in each copy, so it needs no absorption of its own
       // so that the slices of every chunk run along a unit-stride leg.  Otherwise:
       // Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
       // Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
@@ -1004,27 +1005,29 @@ void Engine::build() {
           const auto &y = sws[v].y;
           a[0].push_back(Tp(v)); b[0].push_back(in(v, 1)); cc[0].push_back(B(y[0]));
           a[1].push_back(Tp(v)); b[1].push_back(in(v, 0)); cc[1].push_back(B(y[1]));
-          const void *ys[3] = {B(y[0]), B(y[1]), B(y[0])};
-          const void *ms[3] = {in(v, 2), in(v, 2), in(v, 0)};
+          const void *ys[3] = {B(y[0]), B(y[1]), B(y[1])};
+          const void *ts[3] = {Tp(v), Tp(v), B(y[0])};
+          const void *ms[3] = {in(v, 2), in(v, 2), in(v, 0)};     // (the pair reads no M)
           for (int o = 0; o < 3; ++o) {
             fy[o].push_back(ys[o]);
-            ft[o].push_back(Tp(v));
+            ft[o].push_back(ts[o]);
             fm[o].push_back(ms[o]);
             fo[o].push_back(Mnp(P.out_msg[v][o]));
           }
         }
         add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[0], b[0], cc[0]);
         add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[1], b[1], cc[1]);
-        // the three outgoing legs in one launch: problems [36 o, 36 o + 36) take stride set o
+        // outgoing legs 0 and 1 in one launch (problems [36 o, 36 o + 36) take stride set o), leg 2
+        // in one pair launch
         const int qleg[3] = {2, 2, 0}, cleg[3] = {1, 0, 1};
         BpCloseDesc f;
         f.chi = chi;
         f.xdim = chi;
-        f.nsets = 3;
+        f.nsets = 2;
         f.group = (int)fy[0].size();
         f.ss = L3.s;
         std::vector<const void *> ay, at, am, ao;
-        for (int o = 0; o < 3; ++o) {
+        for (int o = 0; o < 2; ++o) {
           f.rs[o] = L3.leg[o];
           f.qs[o] = L3.leg[qleg[o]];
           f.cs[o] = L3.leg[cleg[o]];
@@ -1034,6 +1037,13 @@ void Engine::build() {
           ao.insert(ao.end(), fo[o].begin(), fo[o].end());
         }
         add_fused(C.ops, f, ay, at, am, ao);
+        BpCloseDesc f2 = f;
+        f2.pair = 1;
+        f2.nsets = 1;
+        f2.rs[0] = L3.leg[2];
+        f2.qs[0] = L3.leg[qleg[2]];
+        f2.cs[0] = L3.leg[cleg[2]];
+        add_fused(C.ops, f2, fy[2], ft[2], fm[2], fo[2]);
       } else {
         std::vector<const void *> a[8], b[8], cc[8];
         for (int v = 0; v < P.n; ++v) {

@@ -561,6 +561,14 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
 // part[wg][slot][group] (slot 0: the workgroup's first problem, 1: the next);
 // bp_close_reduce_kernel adds them in workgroup order.  FP64 at CH = 64: one workgroup per CU (LDS
 // and registers); otherwise two.  grid: workgroups, each `per` chunks (a multiple of G).
+//
+// PAIR: the message from two absorbed copies of the site tensor, Y (Yp) and Y' (Tp), with the
+// messages of the two summed legs absorbed one in each: for a Hermitian M',
+// sum_{a'} M'[x][a'] conj(T[.., a', ..]) = conj(Y'[.., x, ..]) with Y' = T x M', so
+//   out[b][b'] = sum over chunks of sum_a Y[b][a] conj(Y'[b'][a])
+// is the same closing without the leg absorption of the chunk: W is Y's slice itself, loaded
+// straight into the A-operand layout of the product (the next chunk's while this one is
+// multiplied), and only the Hermitian product runs (Mp is not read).
 template <typename T, int CH>
 struct BpCloseCfg {
   static constexpr bool F64 = std::is_same<T, double>::value;
@@ -571,7 +579,7 @@ struct BpCloseCfg {
   static constexpr int G = 64 / CH;                       // chunks in flight, NT waves each
   static constexpr int NB = NT / 2 + 1;                   // most output blocks of one wave
 };
-template <typename T, bool S32, int CH>
+template <typename T, bool S32, int CH, bool PAIR>
 __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel(
     BpCloseDesc d, const double *const *Yp, const double *const *Tp, const double *const *Mp,
     int total, int per, double2 *part) {
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
   constexpr int CC = CH * CH, NT = Cfg::NT, KS = Cfg::KS, G = Cfg::G, NB = Cfg::NB;
   constexpr int P = Cfg::PAD;
   const int J = 2 * d.xdim;              // chunks per problem: (s, x)
-  __shared__ T Ms[2][CH][CH + P];        // M[a0][a]
+  __shared__ T Ms[PAIR ? 1 : 2][PAIR ? 1 : CH][PAIR ? 1 : CH + P];   // M[a0][a]
   __shared__ T Ts[G][2][CH][CH + P];     // per chunk in flight: T[b'][a], stored as [a][b']
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int c = lane & 15, g = lane >> 4;
@@ -639,10 +647,16 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
     return (long)(j / d.xdim) * d.ss + (long)(j % d.xdim) * cs;
   };
   st_t yv[KS], tn[G][TU];
-  auto load_y = [&](const st_t *Y, int k) {      // this wave's Y values of chunk k + q
+  // this wave's Y values of chunk k + q: the B operand of the first product (Y[b][a0],
+  // a0 = 4 t + g), or (PAIR) W itself in the A-operand layout of the product (Y[b][a],
+  // a = 16 i + row(lane, r) at t = 4 i + r)
+  auto load_y = [&](st_t (&dst)[KS], const st_t *Y, int k) {
     const long base = chunk_base(k + q);
 #pragma unroll
-    for (int t = 0; t < KS; ++t) yv[t] = Y[base + yrow + (long)(4 * t + g) * qs];
+    for (int t = 0; t < KS; ++t) {
+      const int a = PAIR ? 16 * (t >> 2) + MT::row(lane, t & 3) : 4 * t + g;
+      dst[t] = Y[base + yrow + (long)a * qs];
+    }
   };
   auto load_t = [&](const st_t *Tt, int k) {     // the T slices of chunks k .. k + G - 1
 #pragma unroll
@@ -680,14 +694,16 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
       set_strides(p);
       Y = reinterpret_cast<const st_t *>(Yp[p]);
       Tt = reinterpret_cast<const st_t *>(Tp[p]);
-      const double2 *M = reinterpret_cast<const double2 *>(Mp[p]);
-      load_y(Y, k);
+      load_y(yv, Y, k);
       load_t(Tt, k);
       __syncthreads();
-      for (int idx = tid; idx < CC; idx += 256) {
-        const double2 v = M[idx];
-        Ms[0][idx / CH][idx % CH] = T(v.x);
-        Ms[1][idx / CH][idx % CH] = T(v.y);
+      if constexpr (!PAIR) {
+        const double2 *M = reinterpret_cast<const double2 *>(Mp[p]);
+        for (int idx = tid; idx < CC; idx += 256) {
+          const double2 v = M[idx];
+          Ms[0][idx / CH][idx % CH] = T(v.x);
+          Ms[1][idx / CH][idx % CH] = T(v.y);
+        }
       }
       store_t();
       __syncthreads();
@@ -696,32 +712,44 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
     // multiplied, their Y values once this iteration's first product has used the current ones
     ready = k + G < k1 && (k + G) / J == p;
     if (ready) load_t(Tt, k + G);
-    // W^T[a][b] = sum_a0 M[a0][a] Y[b][a0], NT a tiles by this wave's 16 columns b
-    acc_t acc1[NT][3];
+    // W^T[a][b] = sum_a0 M[a0][a] Y[b][a0], NT a tiles by this wave's 16 columns b (PAIR: the
+    // next chunks' W values are loaded instead)
+    acc_t acc1[PAIR ? 1 : NT][3];
+    st_t yn[PAIR ? KS : 1];
+    if constexpr (PAIR) {
+      if (ready) load_y(yn, Y, k + G);
+    } else {
 #pragma unroll
-    for (int i = 0; i < NT; ++i)
+      for (int i = 0; i < NT; ++i)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) acc1[i][t] = (acc_t){T(0), T(0), T(0), T(0)};
+        for (int t = 0; t < 3; ++t) acc1[i][t] = (acc_t){T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int t = 0; t < KS; ++t) {
-      const int a0 = 4 * t + g;
-      const T br = T(yv[t].x), bi = T(yv[t].y), bs = br + bi;
+      for (int t = 0; t < KS; ++t) {
+        const int a0 = 4 * t + g;
+        const T br = T(yv[t].x), bi = T(yv[t].y), bs = br + bi;
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const T ar = Ms[0][a0][16 * i + c], ai = Ms[1][a0][16 * i + c], as = ar + ai;
-        acc1[i][0] = MT::mma(ar, br, acc1[i][0]);
-        acc1[i][1] = MT::mma(ai, bi, acc1[i][1]);
-        acc1[i][2] = MT::mma(as, bs, acc1[i][2]);
+        for (int i = 0; i < NT; ++i) {
+          const T ar = Ms[0][a0][16 * i + c], ai = Ms[1][a0][16 * i + c], as = ar + ai;
+          acc1[i][0] = MT::mma(ar, br, acc1[i][0]);
+          acc1[i][1] = MT::mma(ai, bi, acc1[i][1]);
+          acc1[i][2] = MT::mma(as, bs, acc1[i][2]);
+        }
       }
+      if (ready) load_y(yv, Y, k + G);
     }
-    if (ready) load_y(Y, k + G);
     // out[b][b'] += sum_a W[b][a] conj(T[b'][a]), k step (i, r) <-> a = 16 i + row(lane, r)
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const T wr = acc1[i][0][r] - acc1[i][1][r];
-        const T wi = acc1[i][2][r] - acc1[i][0][r] - acc1[i][1][r];
+        T wr, wi;
+        if constexpr (PAIR) {
+          wr = T(yv[4 * i + r].x);
+          wi = T(yv[4 * i + r].y);
+        } else {
+          wr = acc1[i][0][r] - acc1[i][1][r];
+          wi = acc1[i][2][r] - acc1[i][0][r] - acc1[i][1][r];
+        }
         const T ws = wr + wi;
         const int a = 16 * i + MT::row(lane, r);
 #pragma unroll
@@ -733,6 +761,12 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
           acc2[jj][1] = MT::mma(wi, bi, acc2[jj][1]);
           acc2[jj][2] = MT::mma(ws, bs, acc2[jj][2]);
         }
+      }
+    }
+    if constexpr (PAIR) {
+      if (ready) {
+#pragma unroll
+        for (int t = 0; t < KS; ++t) yv[t] = yn[t];
       }
     }
     if (ready) {
@@ -3260,6 +3294,7 @@ class HipBackend : public Backend {
                 const double *const *M, double *const *out, int nprob) override {
     if (nprob <= 0) return;
     bool bad = (d.chi != 64 && d.chi != 32) || (d.s32 && d.prec != 1) || d.ss < 0 ||
+               (d.pair != 0 && d.pair != 1) ||
                d.nsets < 1 || d.nsets > 3 || d.group < 1 || (d.xdim != 1 && d.xdim != d.chi);
     for (int k = 0; k < 3 && !bad; ++k)
       bad = k < d.nsets && (d.rs[k] < 0 || d.qs[k] < 0 || d.cs[k] < 0);
@@ -3296,29 +3331,35 @@ class HipBackend : public Backend {
       HIPCHK(hipEventRecord(e0, s_));
     }
     stale_check("bp_close_kernel");
-#define BPC_LAUNCH(TT, S, C)                                                                      \
-  hipLaunchKernelGGL((bp_close_kernel<TT, S, C>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,         \
+#define BPC_LAUNCH(TT, S, C, PR)                                                                  \
+  hipLaunchKernelGGL((bp_close_kernel<TT, S, C, PR>), dim3(nwg), dim3(256), 0, s_, d, Y, T, M,     \
                      (int)total, (int)per, W)
+#define BPC_PREC(C, PR)                                                                           \
+  do {                                                                                            \
+    if (d.prec == 1 && d.s32) BPC_LAUNCH(float, true, C, PR);                                    \
+    else if (d.prec == 1) BPC_LAUNCH(float, false, C, PR);                                       \
+    else BPC_LAUNCH(double, false, C, PR);                                                       \
+  } while (0)
     if (ch == 64) {
-      if (d.prec == 1 && d.s32) BPC_LAUNCH(float, true, 64);
-      else if (d.prec == 1) BPC_LAUNCH(float, false, 64);
-      else BPC_LAUNCH(double, false, 64);
+      if (d.pair) BPC_PREC(64, true);
+      else BPC_PREC(64, false);
     } else {
-      if (d.prec == 1 && d.s32) BPC_LAUNCH(float, true, 32);
-      else if (d.prec == 1) BPC_LAUNCH(float, false, 32);
-      else BPC_LAUNCH(double, false, 32);
+      if (d.pair) BPC_PREC(32, true);
+      else BPC_PREC(32, false);
     }
+#undef BPC_PREC
 #undef BPC_LAUNCH
     launch_check("bp_close_kernel");
     if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
       prof_prec_.push_back(2 + (d.prec & 1));
-      // algorithmic work per message, per chunk (2 xdim of them): the absorption W = Y M (chi^3)
-      // and the distinct entries of the Hermitian closing (chi (chi + 1) / 2 of them, K = chi);
-      // a degree-3 site (xdim = chi): 2 chi^4 + chi^3 (chi + 1)
+      // algorithmic work per message, per chunk (2 xdim of them): the absorption W = Y M (chi^3,
+      // none for a pair) and the distinct entries of the Hermitian closing (chi (chi + 1) / 2 of
+      // them, K = chi); a degree-3 site (xdim = chi): 2 chi^4 + chi^3 (chi + 1)
       const double c = ch;
-      const double fl = 8.0 * nprob * 2.0 * d.xdim * (c * c * c + 0.5 * c * c * (c + 1.0));
+      const double fl =
+          8.0 * nprob * 2.0 * d.xdim * ((d.pair ? 0.0 : c * c * c) + 0.5 * c * c * (c + 1.0));
       prof_flops_ += fl;
       prof_flops_p_[2 + (d.prec & 1)] += fl;
     }

@@ -381,6 +381,40 @@ def test_bp_close_matches_numpy(ctx, name, o, q, cl, chi):
         assert np.array_equal(g32, np.conj(np.transpose(g32, (0, 2, 1))))
 
 
+@pytest.mark.parametrize("chi", [64, 32])
+def test_bp_pair_matches_numpy(ctx, chi):
+    """The pair closing of a degree-3 site's third message: with Y0 = T x0 M0 and Y1 = T x1 M1 (the
+    two summed legs' Hermitian messages absorbed, one in each copy), sum Y0 conj(Y1) over s and
+    legs 0, 1 equals sum T M0 M1 conj(T), the message out of leg 2; against numpy complex128 (FP64
+    to 1e-12 of the largest entry, FP32 to 2e-5), exactly Hermitian, over enough problems that
+    workgroups straddle problems."""
+    print(f"[bp_close] pair chi={chi}", flush=True)
+    rng = np.random.default_rng(77 + chi)
+    nprob = 9 if chi == 64 else 20
+    Ys, Ts, refs = [], [], []
+    for _ in range(nprob):
+        T = _rand(rng, 2, chi, chi, chi) / chi
+        M0, M1 = _hermitian(rng, chi), _hermitian(rng, chi)
+        Y0 = np.einsum("saxc,ab->sbxc", T, M0)
+        Y1 = np.einsum("saxc,xy->sayc", T, M1)
+        Z = np.einsum("sbxc,xy->sbyc", Y0, M1)
+        refs.append(np.einsum("sbyc,sbyd->cd", Z, T.conj()))
+        Ys.append(Y0.reshape(-1)); Ts.append(Y1.reshape(-1))
+    Y, T, ref = np.array(Ys), np.array(Ts), np.array(refs)
+    M = np.zeros((nprob, chi, chi), complex)
+    st = dict(rs=1, qs=chi * chi, cs=chi, ss=chi ** 3, pair=1)
+    scale = np.abs(ref).max()
+    got = ctx.test_bp_close(Y, T, M, **st)
+    assert np.abs(got - ref).max() < 1e-12 * scale
+    assert np.array_equal(got, np.conj(np.transpose(got, (0, 2, 1))))
+    for store32 in (0, 1):
+        g32 = ctx.test_bp_close(Y, T, M, precision=1, store32=store32, **st)
+        err = np.abs(g32 - ref).max() / scale
+        print(f"  FP32 store32={store32}: {err:.1e}", flush=True)
+        assert 1e-10 < err < 2e-5
+        assert np.array_equal(g32, np.conj(np.transpose(g32, (0, 2, 1))))
+
+
 def test_bp_close_rejects_bad_arguments(ctx):
     from paper_2306_14887_amd import bpki as B
     rng = np.random.default_rng(5)
@@ -393,6 +427,8 @@ def test_bp_close_rejects_bad_arguments(ctx):
         ctx.test_bp_close(Y, Y, M, rs=C * C, qs=1, cs=C, ss=C ** 3, store32=1)
     with pytest.raises(B.BpkiError):              # chi 48 is not built
         ctx.test_bp_close(Y, Y, _rand(rng, 1, 48, 48), rs=48 * 48, qs=1, cs=48, ss=48 ** 3)
+    with pytest.raises(B.BpkiError):              # pair is 0 or 1
+        ctx.test_bp_close(Y, Y, M, rs=C * C, qs=1, cs=C, ss=C ** 3, pair=2)
 
 
 @pytest.mark.parametrize("chi", [64, 32])
