@@ -999,35 +999,41 @@ void Engine::build() {
       // Y2 = T x2 M2 ; Y21 = Y2 x1 M1 -> out0 ; Y20 = Y2 x0 M0 -> out1 ;
       // Y1 = T x1 M1 ; Y10 = Y1 x0 M0 -> out2
       if (bp_close_chi(chi)) {
-        std::vector<const void *> a[2], b[2], cc[2], fy[3], ft[3], fm[3], fo[3];
+        // Y1 = T x1 M1, Y0 = T x0 M0, Y2 = T x2 M2 (three leg absorptions), then every message is
+        // a pair closing of the two copies that hold its summed legs' messages:
+        //   out0 = pair(Y1, Y2), out1 = pair(Y0, Y2), out2 = pair(Y0, Y1)
+        // with the in-chunk sum along leg 2 (out0, out1) or leg 0 (out2) and the chunks over the
+        // remaining leg, so that every chunk's slices run along a unit-stride leg where they can
+        std::vector<const void *> a[3], b[3], cc[3], fy[3], ft[3], fm[3], fo[3];
         for (int v = 0; v < P.n; ++v) {
           if (P.deg[v] != 3 || cls[v] != c) continue;
           const auto &y = sws[v].y;
           a[0].push_back(Tp(v)); b[0].push_back(in(v, 1)); cc[0].push_back(B(y[0]));
           a[1].push_back(Tp(v)); b[1].push_back(in(v, 0)); cc[1].push_back(B(y[1]));
+          a[2].push_back(Tp(v)); b[2].push_back(in(v, 2)); cc[2].push_back(B(y[2]));
           const void *ys[3] = {B(y[0]), B(y[1]), B(y[1])};
-          const void *ts[3] = {Tp(v), Tp(v), B(y[0])};
-          const void *ms[3] = {in(v, 2), in(v, 2), in(v, 0)};     // (the pair reads no M)
+          const void *ts[3] = {B(y[2]), B(y[2]), B(y[0])};
           for (int o = 0; o < 3; ++o) {
             fy[o].push_back(ys[o]);
             ft[o].push_back(ts[o]);
-            fm[o].push_back(ms[o]);
+            fm[o].push_back(in(v, o));                 // (not read by a pair)
             fo[o].push_back(Mnp(P.out_msg[v][o]));
           }
         }
         add_op(C.ops, leg_desc(3, 1, L3, L3, chi), a[0], b[0], cc[0]);
         add_op(C.ops, leg_desc(3, 0, L3, L3, chi), a[1], b[1], cc[1]);
-        // outgoing legs 0 and 1 in one launch (problems [36 o, 36 o + 36) take stride set o), leg 2
-        // in one pair launch
+        add_op(C.ops, leg_desc(3, 2, L3, L3, chi), a[2], b[2], cc[2]);
+        // the three pairs in one launch: problems [36 o, 36 o + 36) take stride set o
         const int qleg[3] = {2, 2, 0}, cleg[3] = {1, 0, 1};
         BpCloseDesc f;
         f.chi = chi;
         f.xdim = chi;
-        f.nsets = 2;
+        f.pair = 1;
+        f.nsets = 3;
         f.group = (int)fy[0].size();
         f.ss = L3.s;
         std::vector<const void *> ay, at, am, ao;
-        for (int o = 0; o < 2; ++o) {
+        for (int o = 0; o < 3; ++o) {
           f.rs[o] = L3.leg[o];
           f.qs[o] = L3.leg[qleg[o]];
           f.cs[o] = L3.leg[cleg[o]];
@@ -1037,13 +1043,6 @@ void Engine::build() {
           ao.insert(ao.end(), fo[o].begin(), fo[o].end());
         }
         add_fused(C.ops, f, ay, at, am, ao);
-        BpCloseDesc f2 = f;
-        f2.pair = 1;
-        f2.nsets = 1;
-        f2.rs[0] = L3.leg[2];
-        f2.qs[0] = L3.leg[qleg[2]];
-        f2.cs[0] = L3.leg[cleg[2]];
-        add_fused(C.ops, f2, fy[2], ft[2], fm[2], fo[2]);
       } else {
         std::vector<const void *> a[8], b[8], cc[8];
         for (int v = 0; v < P.n; ++v) {
