@@ -567,20 +567,23 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
 // sum_{a'} M'[x][a'] conj(T[.., a', ..]) = conj(Y'[.., x, ..]) with Y' = T x M', so
 //   out[b][b'] = sum over chunks of sum_a Y[b][a] conj(Y'[b'][a])
 // is the same closing without the leg absorption of the chunk: W is Y's slice itself, loaded
-// straight into the A-operand layout of the product (the next chunk's while this one is
-// multiplied), and only the Hermitian product runs (Mp is not read).
-template <typename T, int CH>
+// straight into the A-operand layout of the product, and only the Hermitian product runs (Mp is
+// not read); the next chunks' W values and T slices are loaded after the product.
+template <typename T, int CH, bool PR = false>
 struct BpCloseCfg {
   static constexpr bool F64 = std::is_same<T, double>::value;
   static constexpr int PAD = F64 ? 8 : 4;                 // LDS row padding
-  static constexpr int WGS = (F64 && CH == 64) ? 1 : 2;   // workgroups per CU
+  // workgroups per CU: one for the FP64 chain at chi = 64 (LDS and registers), else two (the
+  // FP64 pair at chi = 64 is HBM-bound: two workgroups keep more loads in flight than the
+  // register prefetch of one)
+  static constexpr int WGS = (F64 && CH == 64 && !PR) ? 1 : 2;
   static constexpr int NT = CH / 16;                      // 16-row tiles per side
   static constexpr int KS = CH / 4;                       // k steps of the first product
   static constexpr int G = 64 / CH;                       // chunks in flight, NT waves each
   static constexpr int NB = NT / 2 + 1;                   // most output blocks of one wave
 };
 template <typename T, bool S32, int CH, bool PAIR>
-__global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel(
+__global__ __launch_bounds__(256, (BpCloseCfg<T, CH, PAIR>::WGS)) void bp_close_kernel(
     BpCloseDesc d, const double *const *Yp, const double *const *Tp, const double *const *Mp,
     int total, int per, double2 *part) {
   typedef MfmaTraits<T> MT;
@@ -711,14 +714,11 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
     // the next chunks of the same problem: their T slices are loaded while these chunks are
     // multiplied, their Y values once this iteration's first product has used the current ones
     ready = k + G < k1 && (k + G) / J == p;
-    if (ready) load_t(Tt, k + G);
+    if (!PAIR && ready) load_t(Tt, k + G);
     // W^T[a][b] = sum_a0 M[a0][a] Y[b][a0], NT a tiles by this wave's 16 columns b (PAIR: the
     // next chunks' W values are loaded instead)
     acc_t acc1[PAIR ? 1 : NT][3];
-    st_t yn[PAIR ? KS : 1];
-    if constexpr (PAIR) {
-      if (ready) load_y(yn, Y, k + G);
-    } else {
+    if constexpr (!PAIR) {
 #pragma unroll
       for (int i = 0; i < NT; ++i)
 #pragma unroll
@@ -763,10 +763,10 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH>::WGS)) void bp_close_kernel
         }
       }
     }
-    if constexpr (PAIR) {
+    if constexpr (PAIR) {           // the next chunks' W values and T slices, after this product
       if (ready) {
-#pragma unroll
-        for (int t = 0; t < KS; ++t) yv[t] = yn[t];
+        load_y(yv, Y, k + G);
+        load_t(Tt, k + G);
       }
     }
     if (ready) {
@@ -3317,7 +3317,8 @@ class HipBackend : public Backend {
       }
       return;
     }
-    const long slots = (d.prec == 0 && ch == 64) ? std::max(1, resident_ / 2) : resident_;
+    const long slots =
+        (d.prec == 0 && ch == 64 && !d.pair) ? std::max(1, resident_ / 2) : resident_;
     long per = std::max<long>(1, std::min(J, (total + slots - 1) / slots));
     per = (per + G - 1) / G * G;
     const int nwg = (int)((total + per - 1) / per);
