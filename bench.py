@@ -8,24 +8,26 @@ The first --warmup steps (default 6: bonds saturate at chi = 64 after 6 steps) a
 next --steps steps are timed, so the default run is steps 7..20 of the 20-step circuit.
 
 The JSON line also carries:
-  roofline     : the dominant kernel of the step, the fused BP closing (bp_close_kernel<double>:
-                 the leg absorption and the Hermitian closing of a message, chunk by chunk, without
-                 writing the intermediate; degree-3 and degree-2 sites), algorithmic flops
-                 8*(2 chi^4 + chi^3 (chi + 1)) per degree-3 message (8*(2 chi^3 + chi^2 (chi + 1))
-                 per degree-2 one) over the HIP-event-timed launch
-                 durations (every 7th contraction launch of the timed window), against the MI355X
-                 FP64 peak (78.6 TFLOP/s dense); traffic = HBM bytes per launch from the committed
-                 rocprofv3 counter summary (null once the kernel source has changed); achievable =
-                 measured roofs on this GPU (MFMA chains without memory traffic, a 1 GiB copy);
-                 frac_of_achievable_mfma compares the algorithmic rate with the measured FP64 MFMA
-                 rate x 4/3 (the 3M complex product issues 3/4 of the algorithmic real flops).
-                 gemm_kernels: the same for the complex GEMM kernels (gemm_kernel and
-                 gemm_stream_kernel: every other contraction), 8*M*N*K flops per launch
-                 (8*K*M(M+1)/2 for a Hermitian output, whose upper triangle is a mirror).
+  roofline     : the kernel with the most time in the step, chosen from three profiled kernels by
+                 their HIP-event-timed launch durations (every 7th contraction launch of the timed
+                 window): gemm_kernel (tiled GEMM), gemm_stream_kernel (the leg absorptions of BP
+                 and the gate layers) and bp_close_kernel (the BP messages: per degree-3 site a
+                 pair closing of two absorbed copies of its tensor, 8 chi^3 (chi + 1) flops and
+                 2 x 2 chi^3 x 16 bytes per message; per degree-2 site the absorption and closing
+                 fused).  Algorithmic flops (8 per complex multiply-add, a Hermitian output counted
+                 by its distinct entries) and algorithmic bytes (operands read once, outputs
+                 written once) of the sampled launches over their summed durations; bound "mfma"
+                 (TFLOP/s against the FP64 dense peak 78.6) when the flops per byte reach the
+                 ridge point 78.6 / 8, else "hbm" (GB/s against 8 TB/s).  traffic = HBM bytes per
+                 launch from the committed rocprofv3 counter summary of that kernel (null once its
+                 source has changed); achievable = measured roofs on this GPU (MFMA chains
+                 without memory traffic, a 1 GiB copy) and frac_of_achievable against them (MFMA:
+                 x 4/3, the 3M complex product issuing 3/4 of the algorithmic real flops).
+                 other_kernels: the same for the other two.
   mixed        : the same window in mixed precision (BP tolerance MIXED_TOL), with max / median
                  |<Z>| difference to FP64, the FP64 mode at the same tolerance (the FP32
-                 arithmetic's own gain) and the roofline of its FP32 GEMM launches against the FP32
-                 MFMA peak (157.3 TFLOP/s).
+                 arithmetic's own gain) and the roofline of its dominant FP32 kernel as above
+                 (against the FP32 MFMA peak 157.3 TFLOP/s or HBM).
   config1      : the chi = 32 configuration: nine theta_h, 20 steps each, FP64, the lattice-average
                  magnetisation after every step.
   chi128       : the same workload at chi = 128, steps 8..10 (FP64).
@@ -61,7 +63,9 @@ FP32_PEAK_TFLOPS = 157.3
 # launch pattern of a BP sweep, so every launch shape is sampled; an event pair on every launch
 # would slow the timed steps by ~4%)
 PROFILE_STRIDE = 7
+HBM_PEAK_GBPS = 8000.0
 GEMM_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_hbm_traffic.md")
+STREAM_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_stream_kernel_hbm_traffic.md")
 CLOSE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bp_close_kernel_hbm_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_14887_amd", "csrc", "hip_backend.hip")
 # the source spans (kernel, host launch code) that the recorded counters belong to
@@ -96,6 +100,55 @@ def recorded_traffic(profile: str, spans):
         return float(rec["traffic_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
+
+
+# the three profiled kernels: (name, committed HBM-traffic summary, source spans of its hash)
+PROFILED = {0: ("gemm_kernel", GEMM_TRAFFIC_PROFILE, GEMM_SPANS),
+            1: ("bp_close_kernel", CLOSE_TRAFFIC_PROFILE, CLOSE_SPANS),
+            2: ("gemm_stream_kernel", STREAM_TRAFFIC_PROFILE, GEMM_SPANS)}
+
+
+def kernel_roofline(p: dict, kernel: int, prec: int, peaks: dict | None) -> dict:
+    """Roofline of one profiled kernel's bracketed launches: algorithmic flops and bytes over their
+    summed HIP-event durations.  Bound by the MFMA when its flops per byte reach the ridge point of
+    the dense peak over the 8 TB/s HBM peak, else by HBM."""
+    name, prof_path, spans = PROFILED[kernel]
+    peak_tf = FP32_PEAK_TFLOPS if prec else FP64_PEAK_TFLOPS
+    sec = p["ms"] * 1e-3
+    tf = p["flops"] / sec / 1e12 if sec > 0 else 0.0
+    gbps = p["bytes"] / sec / 1e9 if sec > 0 else 0.0
+    intensity = p["flops"] / p["bytes"] if p["bytes"] > 0 else float("inf")
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBPS * 1e9)
+    mfma = intensity >= ridge
+    r = {"bound": "mfma" if mfma else "hbm",
+         "kernel": f"{name}<{'float' if prec else 'double'}>",
+         "achieved": tf if mfma else gbps, "peak": peak_tf if mfma else HBM_PEAK_GBPS,
+         "unit": "TFLOP/s" if mfma else "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    r.update({"tflops": tf, "gbps": gbps, "flops_per_byte": intensity,
+              "ridge_flops_per_byte": ridge, "launches": p["launches"],
+              "avg_launch_ms": p["ms"] / max(1, p["launches"]), "ms_sampled": p["ms"],
+              "traffic": recorded_traffic(prof_path, spans) if not prec else None,
+              "traffic_unit": "bytes per launch (HBM, calibrated)",
+              "algorithmic_bytes_per_launch": p["bytes"] / max(1, p["launches"])})
+    if peaks:
+        if mfma and peaks.get("mfma_f64_tflops") and not prec:
+            # the 3M complex product issues 3/4 of the algorithmic real flops
+            r["frac_of_achievable"] = tf / (peaks["mfma_f64_tflops"] * 4.0 / 3.0)
+        elif mfma and peaks.get("mfma_f32_tflops") and prec:
+            r["frac_of_achievable"] = tf / (peaks["mfma_f32_tflops"] * 4.0 / 3.0)
+        elif not mfma and peaks.get("hbm_copy_gbps"):
+            r["frac_of_achievable"] = gbps / peaks["hbm_copy_gbps"]
+    return r
+
+
+def dominant_roofline(prof: dict, prec: int, peaks: dict | None) -> dict:
+    """The roofline of the kernel with the most bracketed time, the other kernels beside it."""
+    rl = {k: kernel_roofline(prof[(k, prec)], k, prec, peaks) for k in PROFILED}
+    dom = max(rl, key=lambda k: prof[(k, prec)]["ms"])
+    out = dict(rl[dom])
+    out["other_kernels"] = {rl[k]["kernel"]: rl[k] for k in rl if k != dom}
+    return out
 
 
 def _cores() -> int:
@@ -347,7 +400,7 @@ def _window(lat, theta, chi, warmup, steps, precision, tol, profile=False):
             iters.append(r["bp_iters"])
             zs.append(r["z"])
         wall = time.perf_counter() - t0
-        prof = ({(k, q): sess.profile_read_kernel(k, q) for k in (0, 1) for q in (0, 1)}
+        prof = ({(k, q): sess.profile_read_kernel(k, q) for k in PROFILED for q in (0, 1)}
                 if profile else None)
         sess.close()
     return steps / wall, float(np.mean(iters)), np.array(zs), prof
@@ -363,25 +416,16 @@ def mixed_window(lat, theta, chi, warmup, steps) -> dict:
     v32, it32, z32, prof = _window(lat, theta, chi, warmup, steps, bpki.BPKI_FP32, MIXED_TOL,
                                    profile=True)
     v64, it64, _, _ = _window(lat, theta, chi, warmup, steps, bpki.BPKI_FP64, MIXED_TOL)
-    def rate(p):
-        return p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
-
-    c32, g32, c64 = prof[(1, 1)], prof[(0, 1)], prof[(1, 0)]
-    a32 = rate(c32)
+    rl32 = dominant_roofline(prof, 1, None)
+    rl32["fp64_launches_of_the_window"] = {
+        kernel_roofline(prof[(k, 0)], k, 0, None)["kernel"]: kernel_roofline(prof[(k, 0)], k, 0, None)
+        for k in PROFILED}
     return {"value": v32, "unit": "Floquet steps/s", "ms_per_step": 1e3 / v32,
             "bp_sweeps_per_step": it32, "bp_tol": MIXED_TOL,
             "dtype": "c64 BP contractions on c64 copies until the FP32 level, then c128",
             "fp64_same_tol": {"value": v64, "bp_sweeps_per_step": it64,
                               "mixed_speedup": v32 / v64},
-            "roofline": {"bound": "mfma",
-                         "kernel": "bp_close_kernel<float> (FP32 launches of the window)",
-                         "achieved": a32, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": a32 / FP32_PEAK_TFLOPS, "launches": c32["launches"],
-                         "avg_launch_ms": c32["ms"] / max(1, c32["launches"]),
-                         "gemm_kernels_fp32": {"achieved": rate(g32),
-                                               "launches": g32["launches"],
-                                               "avg_launch_ms": g32["ms"] / max(1, g32["launches"])},
-                         "fp64_launches": c64["launches"], "fp64_achieved": rate(c64)},
+            "roofline": rl32,
             "_z": z32}
 
 
@@ -802,8 +846,7 @@ def main() -> int:
         torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = sess.profile_read()
-    pclose = sess.profile_read_kernel(1, 0)
-    pgemm = sess.profile_read_kernel(0, 0)
+    pk = {(k, 0): sess.profile_read_kernel(k, 0) for k in PROFILED}
     sess.profile(False)
     z = r["z"]
     sess.close()
@@ -811,12 +854,9 @@ def main() -> int:
     ctx.close()
 
     steps_per_s = args.steps / wall
-    def rate(p):
-        return p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
-
-    achieved = rate(pclose)
-    avg_ms = pclose["ms"] / max(1, pclose["launches"])
-    gemm_rate = rate(pgemm)
+    roof = dominant_roofline(pk, 0, peaks)
+    roof.update({"launches_in_window": prof["all_launches"], "sampling_stride": PROFILE_STRIDE,
+                 "achievable": peaks})
     out = {
         "metric": "Floquet steps/s at 127q chi=64",
         "value": steps_per_s,
@@ -839,24 +879,7 @@ def main() -> int:
                                   zip(("rx", "gate_layers", "bp", "observe"), phase)},
             "mean_z_last_step": float(np.mean(z)),
         },
-        "roofline": {
-            "bound": "mfma", "kernel": "bp_close_kernel<double>",
-            "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS,
-            "launches": pclose["launches"], "launches_in_window": prof["all_launches"],
-            "sampling_stride": PROFILE_STRIDE, "avg_launch_ms": avg_ms,
-            "traffic": recorded_traffic(CLOSE_TRAFFIC_PROFILE, CLOSE_SPANS),
-            "traffic_unit": "bytes per launch (HBM, calibrated)",
-            "achievable": peaks,
-            "frac_of_achievable_mfma": (achieved / (peaks["mfma_f64_tflops"] * 4.0 / 3.0)
-                                        if peaks["mfma_f64_tflops"] else None),
-            "gemm_kernels": {
-                "kernel": "gemm_kernel<double> + gemm_stream_kernel<double>",
-                "achieved": gemm_rate, "frac": gemm_rate / FP64_PEAK_TFLOPS,
-                "launches": pgemm["launches"],
-                "avg_launch_ms": pgemm["ms"] / max(1, pgemm["launches"]),
-                "traffic": recorded_traffic(GEMM_TRAFFIC_PROFILE, GEMM_SPANS)},
-        },
+        "roofline": roof,
     }
     if not args.no_mixed:
         mixed = mixed_window(lat, theta, chi, args.warmup, args.steps)

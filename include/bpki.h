@@ -319,10 +319,14 @@ int bpki_session_profile_read(bpki_session *s, int64_t *launches, double *ms, do
  * 1 = FP32 MFMA (a mixed-precision session runs both): their count, summed ms and summed flops. */
 int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int64_t *launches, double *ms,
                                    double *flops);
-/* The same restricted to one kernel and one arithmetic: kernel 0 = the GEMM kernels, 1 = the fused
- * BP closing; prec as above. */
+/* The same restricted to one kernel and one arithmetic: kernel 0 = the tiled GEMM (gemm_kernel),
+ * 1 = the fused BP closing (bp_close_kernel: a message with its leg absorption, or a pair closing
+ * of two absorbed copies, 8*chi^3 (chi + 1) flops per degree-3 message), 2 = the streaming GEMM
+ * of the leg contractions (gemm_stream_kernel); prec as above.  bytes (may be NULL): the summed
+ * algorithmic HBM bytes of those launches (every operand read once and every output written once;
+ * split-K partial sums and re-reads not counted). */
 int bpki_session_profile_read_kernel(bpki_session *s, int32_t kernel, int32_t prec,
-                                     int64_t *launches, double *ms, double *flops);
+                                     int64_t *launches, double *ms, double *flops, double *bytes);
 
 #ifdef __cplusplus
 }

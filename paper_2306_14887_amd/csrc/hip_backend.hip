@@ -3210,9 +3210,11 @@ class HipBackend : public Backend {
       if (rec) {
         HIPCHK(hipEventRecord(e1, s_));
         prof_ev_.push_back({e0, e1});
-        prof_prec_.push_back(d.prec);
+        const int q = 4 + (d.prec & 1);
+        prof_prec_.push_back(q);
         prof_flops_ += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
-        prof_flops_p_[d.prec & 1] += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
+        prof_flops_p_[q] += 8.0 * d.M * d.N * (double)d.K * d.batch * nprob;
+        prof_bytes_p_[q] += gemm_bytes(d, nprob);
       }
       return;
     }
@@ -3272,11 +3274,13 @@ class HipBackend : public Backend {
     if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
-      prof_prec_.push_back(d.prec);
+      const int q = d.prec & 1;
+      prof_prec_.push_back(q);
       // algorithmic work: the distinct entries (a Hermitian output has M (M + 1) / 2)
       const double outs = d.herm ? 0.5 * d.M * (d.M + 1.0) : (double)d.M * d.N;
       prof_flops_ += 8.0 * outs * (double)d.K * d.batch * nprob;
-      prof_flops_p_[d.prec & 1] += 8.0 * outs * (double)d.K * d.batch * nprob;
+      prof_flops_p_[q] += 8.0 * outs * (double)d.K * d.batch * nprob;
+      prof_bytes_p_[q] += gemm_bytes(d, nprob);
     }
     if (ksplit > 1) {
       int bx = std::min(64, (int)((d.M * (size_t)d.N + 255) / 256));
@@ -3354,7 +3358,8 @@ class HipBackend : public Backend {
     if (rec) {
       HIPCHK(hipEventRecord(e1, s_));
       prof_ev_.push_back({e0, e1});
-      prof_prec_.push_back(2 + (d.prec & 1));
+      const int q = 2 + (d.prec & 1);
+      prof_prec_.push_back(q);
       // algorithmic work per message, per chunk (2 xdim of them): the absorption W = Y M (chi^3,
       // none for a pair) and the distinct entries of the Hermitian closing (chi (chi + 1) / 2 of
       // them, K = chi); a degree-3 site (xdim = chi): 2 chi^4 + chi^3 (chi + 1)
@@ -3362,7 +3367,11 @@ class HipBackend : public Backend {
       const double fl =
           8.0 * nprob * 2.0 * d.xdim * ((d.pair ? 0.0 : c * c * c) + 0.5 * c * c * (c + 1.0));
       prof_flops_ += fl;
-      prof_flops_p_[2 + (d.prec & 1)] += fl;
+      prof_flops_p_[q] += fl;
+      // algorithmic bytes: both site-sized operands read once (Y and T, or the pair), M, out
+      const double esz = d.s32 ? 8.0 : 16.0, cc = c * c;
+      prof_bytes_p_[q] += nprob * (2.0 * 2.0 * d.xdim * cc * esz + (d.pair ? 0.0 : 16.0 * cc) +
+                                   16.0 * cc);
     }
     stale_check("bp_close_reduce_kernel");
     hipLaunchKernelGGL(bp_close_reduce_kernel, dim3((ch * ch + 255) / 256, nprob), dim3(256), 0,
@@ -3392,9 +3401,9 @@ class HipBackend : public Backend {
       prof_all_ = 0;
       prof_ms_ = 0;
       prof_flops_ = 0;
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < kProfBuckets; ++q) {
         prof_launches_p_[q] = 0;
-        prof_ms_p_[q] = prof_flops_p_[q] = 0;
+        prof_ms_p_[q] = prof_flops_p_[q] = prof_bytes_p_[q] = 0;
       }
     }
   }
@@ -3407,18 +3416,32 @@ class HipBackend : public Backend {
   }
   void gemm_profile_read_prec(int prec, long *sampled, double *ms, double *flops) override {
     drain_profile();
-    const int q = prec & 1;
-    if (sampled) *sampled = prof_launches_p_[q] + prof_launches_p_[2 + q];
-    if (ms) *ms = prof_ms_p_[q] + prof_ms_p_[2 + q];
-    if (flops) *flops = prof_flops_p_[q] + prof_flops_p_[2 + q];
+    long l = 0;
+    double t = 0, f = 0;
+    for (int k = 0; k < kProfBuckets / 2; ++k) {
+      l += prof_launches_p_[2 * k + (prec & 1)];
+      t += prof_ms_p_[2 * k + (prec & 1)];
+      f += prof_flops_p_[2 * k + (prec & 1)];
+    }
+    if (sampled) *sampled = l;
+    if (ms) *ms = t;
+    if (flops) *flops = f;
   }
-  void gemm_profile_read_kernel(int kernel, int prec, long *sampled, double *ms,
-                                double *flops) override {
+  void gemm_profile_read_kernel(int kernel, int prec, long *sampled, double *ms, double *flops,
+                                double *bytes) override {
     drain_profile();
-    const int q = 2 * (kernel & 1) + (prec & 1);
+    const int q = 2 * kernel + (prec & 1);
     if (sampled) *sampled = prof_launches_p_[q];
     if (ms) *ms = prof_ms_p_[q];
     if (flops) *flops = prof_flops_p_[q];
+    if (bytes) *bytes = prof_bytes_p_[q];
+  }
+  // algorithmic bytes of a GEMM launch: A, B (once per problem unless batched) and C once each,
+  // C twice when accumulated into
+  static double gemm_bytes(const GemmDesc &d, int nprob) {
+    const double ea = d.a32 ? 8 : 16, eb = d.b32 ? 8 : 16, ec = d.c32 ? 8 : 16;
+    return nprob * (ea * d.M * (double)d.K * d.batch + eb * d.K * (double)d.N * (d.b_b ? d.batch : 1) +
+                    ec * d.M * (double)d.N * d.batch * (d.beta ? 2 : 1));
   }
   void drain_profile() {
     for (size_t i = 0; i < prof_ev_.size(); ++i) {
@@ -3428,7 +3451,7 @@ class HipBackend : public Backend {
       HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
       prof_ms_ += ms;
       prof_launches_ += 1;
-      const int q = prof_prec_[i] & 3;
+      const int q = prof_prec_[i];
       prof_ms_p_[q] += ms;
       prof_launches_p_[q] += 1;
       HIPCHK(hipEventDestroy(pr.first));
@@ -3902,9 +3925,13 @@ class HipBackend : public Backend {
   long prof_launches_ = 0, prof_all_ = 0;
   double prof_ms_ = 0, prof_flops_ = 0;
   // the same sums by arithmetic of the bracketed launches (0 FP64 MFMA, 1 FP32 MFMA)
-  std::vector<int> prof_prec_;     // per bracketed launch: 2 * (fused BP closing) + FP32 MFMA
-  long prof_launches_p_[4] = {0, 0, 0, 0};
-  double prof_ms_p_[4] = {0, 0, 0, 0}, prof_flops_p_[4] = {0, 0, 0, 0};
+  // per bracketed launch: 2 * kernel + FP32 MFMA, kernel 0 gemm_kernel, 1 bp_close_kernel,
+  // 2 gemm_stream_kernel
+  static constexpr int kProfBuckets = 6;
+  std::vector<int> prof_prec_;
+  long prof_launches_p_[kProfBuckets] = {};
+  double prof_ms_p_[kProfBuckets] = {}, prof_flops_p_[kProfBuckets] = {},
+         prof_bytes_p_[kProfBuckets] = {};
 };
 
 // Device memory of the allocation-free solve (bpki_solve_noalloc): a fixed array in the code
