@@ -9,8 +9,8 @@ next --steps steps are timed, so the default run is steps 7..20 of the 20-step c
 
 The JSON line also carries:
   roofline     : the kernel with the most time in the step, chosen from three profiled kernels by
-                 their HIP-event-timed launch durations (every 7th contraction launch of the timed
-                 window): gemm_kernel (tiled GEMM), gemm_stream_kernel (the leg absorptions of BP
+                 their HIP-event-timed launch durations (every 7th launch of each kernel in the
+                 timed window): gemm_kernel (tiled GEMM), gemm_stream_kernel (the leg absorptions of BP
                  and the gate layers) and bp_close_kernel (the BP messages: per degree-3 site a
                  pair closing of two absorbed copies of its tensor, 8 chi^3 (chi + 1) flops and
                  2 x 2 chi^3 x 16 bytes per message; per degree-2 site the absorption and closing
@@ -59,9 +59,8 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
-# every 7th GEMM launch of the timed window is bracketed by HIP events (7 is coprime with the
-# launch pattern of a BP sweep, so every launch shape is sampled; an event pair on every launch
-# would slow the timed steps by ~4%)
+# every 7th launch of each profiled kernel in the timed window is bracketed by HIP events (an
+# event pair on every launch would slow the timed steps by ~4%)
 PROFILE_STRIDE = 7
 HBM_PEAK_GBPS = 8000.0
 GEMM_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_hbm_traffic.md")
@@ -143,9 +142,13 @@ def kernel_roofline(p: dict, kernel: int, prec: int, peaks: dict | None) -> dict
 
 
 def dominant_roofline(prof: dict, prec: int, peaks: dict | None) -> dict:
-    """The roofline of the kernel with the most bracketed time, the other kernels beside it."""
+    """The roofline of the kernel with the most time (its average sampled launch duration times
+    all its launches), the other kernels beside it."""
     rl = {k: kernel_roofline(prof[(k, prec)], k, prec, peaks) for k in PROFILED}
-    dom = max(rl, key=lambda k: prof[(k, prec)]["ms"])
+    for k in rl:
+        rl[k]["all_launches"] = prof[(k, prec)]["all_launches"]
+        rl[k]["est_total_ms"] = rl[k]["avg_launch_ms"] * prof[(k, prec)]["all_launches"]
+    dom = max(rl, key=lambda k: rl[k]["est_total_ms"])
     out = dict(rl[dom])
     out["other_kernels"] = {rl[k]["kernel"]: rl[k] for k in rl if k != dom}
     return out

@@ -324,9 +324,12 @@ int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int64_t *launc
  * of two absorbed copies, 8*chi^3 (chi + 1) flops per degree-3 message), 2 = the streaming GEMM
  * of the leg contractions (gemm_stream_kernel); prec as above.  bytes (may be NULL): the summed
  * algorithmic HBM bytes of those launches (every operand read once and every output written once;
- * split-K partial sums and re-reads not counted). */
+ * split-K partial sums and re-reads not counted); all_launches (may be NULL): every launch of
+ * that kernel and arithmetic since enabling.  The sampling stride counts the launches of each
+ * kernel and arithmetic separately. */
 int bpki_session_profile_read_kernel(bpki_session *s, int32_t kernel, int32_t prec,
-                                     int64_t *launches, double *ms, double *flops, double *bytes);
+                                     int64_t *launches, double *ms, double *flops, double *bytes,
+                                     int64_t *all_launches);
 
 #ifdef __cplusplus
 }

@@ -116,7 +116,8 @@ def load(path: str | None = None):
         "bpki_session_profile_read_prec": (C.c_int, [vp, C.c_int32, C.POINTER(C.c_int64), dp,
                                                       dp]),
         "bpki_session_profile_read_kernel": (C.c_int, [vp, C.c_int32, C.c_int32,
-                                                        C.POINTER(C.c_int64), dp, dp, dp]),
+                                                        C.POINTER(C.c_int64), dp, dp, dp,
+                                                        C.POINTER(C.c_int64)]),
         "bpki_session_profile": (C.c_int, [vp, C.c_int]),
         "bpki_session_profile_read": (C.c_int, [vp, C.POINTER(C.c_int64), dp, dp,
                                                  C.POINTER(C.c_int64)]),
@@ -608,11 +609,14 @@ class Session:
     def profile_read_kernel(self, kernel: int, prec: int = 0):
         """The bracketed launches of one kernel (0 gemm_kernel, 1 the fused BP closing
         bp_close_kernel, 2 gemm_stream_kernel) in one arithmetic (0 FP64, 1 FP32 MFMA): count,
-        summed ms, algorithmic flops and algorithmic HBM bytes."""
-        n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        summed ms, algorithmic flops and algorithmic HBM bytes, and the count of all its
+        launches."""
+        n, ms, fl, by, al = C.c_int64(), C.c_double(), C.c_double(), C.c_double(), C.c_int64()
         _check(self.lib, self.lib.bpki_session_profile_read_kernel(
-            self.h, kernel, prec, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
-        return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+            self.h, kernel, prec, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by),
+            C.byref(al)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value,
+                "all_launches": al.value}
 
     def last_timing(self) -> np.ndarray:
         t = np.zeros(4)

@@ -701,11 +701,12 @@ extern "C" int bpki_session_profile_read_prec(bpki_session *s, int32_t prec, int
 
 extern "C" int bpki_session_profile_read_kernel(bpki_session *s, int32_t kernel, int32_t prec,
                                                 int64_t *launches, double *ms, double *flops,
-                                                double *bytes) {
+                                                double *bytes, int64_t *all_launches) {
   if (!s || kernel < 0 || kernel > 2 || (prec != 0 && prec != 1)) return fail(-1, "bad argument");
-  long l = 0;
-  s->ctx->be->gemm_profile_read_kernel(kernel, prec, &l, ms, flops, bytes);
+  long l = 0, a = 0;
+  s->ctx->be->gemm_profile_read_kernel(kernel, prec, &l, ms, flops, bytes, &a);
   if (launches) *launches = l;
+  if (all_launches) *all_launches = a;
   return sess_check(s);
 }
 

@@ -104,9 +104,10 @@ struct Backend {
   // the same for the bracketed launches of one arithmetic (0 FP64 MFMA, 1 FP32 MFMA)
   virtual void gemm_profile_read_prec(int prec, long *sampled, double *ms, double *flops) = 0;
   // kernel 0: gemm_kernel, 1: the fused BP closing (bp_close_kernel), 2: gemm_stream_kernel; prec
-  // as above; bytes: the launches' algorithmic HBM bytes (operands read once, outputs written once)
+  // as above; bytes: the sampled launches' algorithmic HBM bytes (operands read once, outputs
+  // written once); all: every launch of that kernel and arithmetic since enabling
   virtual void gemm_profile_read_kernel(int kernel, int prec, long *sampled, double *ms,
-                                        double *flops, double *bytes) = 0;
+                                        double *flops, double *bytes, long *all) = 0;
 
   // complex FP64 grouped GEMM; A/B/C are device arrays of nprob pointers to double pairs
   virtual void gemm(const GemmDesc &d, const double *const *A, const double *const *B,

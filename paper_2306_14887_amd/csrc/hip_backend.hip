@@ -3167,7 +3167,11 @@ class HipBackend : public Backend {
     int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
     dim3 grid(tiles, d.batch, nprob);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool rec = prof_stride_ > 0 && (prof_all_++ % prof_stride_) == 0;
+    // K and N within 64 (one stride each) and enough rows to amortise loading B (at least 16
+    // strips): B resident in LDS, rows of A streamed
+    const bool stream = d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni &&
+                        d.M >= 256 && !d.herm && !d.b32;
+    const bool rec = prof_sample(stream ? 2 : 0, d.prec);
     if (rec) {
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
@@ -3183,10 +3187,7 @@ class HipBackend : public Backend {
       }
       return;
     }
-    // K and N within 64 (one stride each) and enough rows to amortise loading B (at least 16
-    // strips): B resident in LDS, rows of A streamed
-    if (d.K <= SK_MAX && d.N <= SK_MAX && d.K == d.Ki && d.N == d.Ni && d.M >= 256 && !d.herm &&
-        !d.b32) {
+    if (stream) {
       const int strips = (d.M + 15) / 16;
       const int per = std::max(1, resident_ / std::max(1, d.batch * nprob));
       dim3 g(std::max(1, std::min(per, (strips + 3) / 4)), d.batch, nprob);
@@ -3329,7 +3330,7 @@ class HipBackend : public Backend {
     double2 *W = (double2 *)splitk_ws((size_t)nwg * 2 * G * ch * ch * sizeof(double2));
     if (!W) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool rec = prof_stride_ > 0 && (prof_all_++ % prof_stride_) == 0;
+    const bool rec = prof_sample(1, d.prec);
     if (rec) {
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
@@ -3399,6 +3400,7 @@ class HipBackend : public Backend {
       drain_profile();
       prof_launches_ = 0;
       prof_all_ = 0;
+      for (int q = 0; q < kProfBuckets; ++q) prof_all_p_[q] = 0;
       prof_ms_ = 0;
       prof_flops_ = 0;
       for (int q = 0; q < kProfBuckets; ++q) {
@@ -3428,13 +3430,21 @@ class HipBackend : public Backend {
     if (flops) *flops = f;
   }
   void gemm_profile_read_kernel(int kernel, int prec, long *sampled, double *ms, double *flops,
-                                double *bytes) override {
+                                double *bytes, long *all) override {
     drain_profile();
     const int q = 2 * kernel + (prec & 1);
+    if (all) *all = prof_all_p_[q];
     if (sampled) *sampled = prof_launches_p_[q];
     if (ms) *ms = prof_ms_p_[q];
     if (flops) *flops = prof_flops_p_[q];
     if (bytes) *bytes = prof_bytes_p_[q];
+  }
+  // Profiling: every prof_stride_-th launch of each kernel and arithmetic is bracketed by events
+  // (counted per kernel, so every kernel is sampled whatever the launch pattern)
+  bool prof_sample(int kernel, int prec) {
+    if (prof_stride_ <= 0) return false;
+    ++prof_all_;
+    return (prof_all_p_[2 * kernel + (prec & 1)]++ % prof_stride_) == 0;
   }
   // algorithmic bytes of a GEMM launch: A, B (once per problem unless batched) and C once each,
   // C twice when accumulated into
@@ -3929,7 +3939,7 @@ class HipBackend : public Backend {
   // 2 gemm_stream_kernel
   static constexpr int kProfBuckets = 6;
   std::vector<int> prof_prec_;
-  long prof_launches_p_[kProfBuckets] = {};
+  long prof_launches_p_[kProfBuckets] = {}, prof_all_p_[kProfBuckets] = {};
   double prof_ms_p_[kProfBuckets] = {}, prof_flops_p_[kProfBuckets] = {},
          prof_bytes_p_[kProfBuckets] = {};
 };

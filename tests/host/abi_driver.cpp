@@ -217,9 +217,9 @@ int main() {
     EXPECT(bpki_session_profile_read(s, &n1, &ms, &fl, &n2) == 0);
     EXPECT(bpki_session_profile_read_prec(s, 1, &n1, &ms, &fl) == 0);
     double by = 0;
-    EXPECT(bpki_session_profile_read_kernel(s, 1, 0, &n1, &ms, &fl, &by) == 0);
-    EXPECT(bpki_session_profile_read_kernel(s, 2, 0, &n1, &ms, &fl, nullptr) == 0);
-    EXPECT(bpki_session_profile_read_kernel(s, 3, 0, &n1, &ms, &fl, &by) == -1);
+    EXPECT(bpki_session_profile_read_kernel(s, 1, 0, &n1, &ms, &fl, &by, &n2) == 0);
+    EXPECT(bpki_session_profile_read_kernel(s, 2, 0, &n1, &ms, &fl, nullptr, nullptr) == 0);
+    EXPECT(bpki_session_profile_read_kernel(s, 3, 0, &n1, &ms, &fl, &by, &n2) == -1);
     EXPECT(bpki_session_last_timing(s, ms4.data()) == 0);
   }
   {

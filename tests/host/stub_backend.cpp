@@ -90,9 +90,11 @@ class StubBackend : public Backend {
     if (ms) *ms = 0;
     if (f) *f = 0;
   }
-  void gemm_profile_read_kernel(int, int, long *s, double *ms, double *f, double *b) override {
+  void gemm_profile_read_kernel(int, int, long *s, double *ms, double *f, double *b,
+                                long *a) override {
     gemm_profile_read_prec(0, s, ms, f);
     if (b) *b = 0;
+    if (a) *a = 0;
   }
   void bp_close(const BpCloseDesc &, const double *const *, const double *const *,
                 const double *const *, double *const *, int) override {}
