@@ -72,6 +72,35 @@ __device__ __forceinline__ KOff k_tile(int k0, int Ki, long so, long si) {
   return r;
 }
 
+// Loads and stores in the global address space.  The kernels reach their operands through device
+// arrays of pointers, which the compiler can only treat as generic (flat) addresses; a flat load
+// counts against both the vector-memory and the LDS counters, so every wait for an LDS read then
+// also waits for all loads in flight (prefetches included).  Accessed through these, the same
+// addresses become global loads with their own counter.
+#define BPKI_GLOBAL __attribute__((address_space(1)))
+typedef double gd2_t __attribute__((ext_vector_type(2)));
+typedef float gf2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gld(const double2 *p, long i) {
+  const gd2_t v = ((const BPKI_GLOBAL gd2_t *)p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 gld(const float2 *p, long i) {
+  const gf2_t v = ((const BPKI_GLOBAL gf2_t *)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(double2 *p, long i, double2 x) {
+  gd2_t v;
+  v.x = x.x;
+  v.y = x.y;
+  ((BPKI_GLOBAL gd2_t *)p)[i] = v;
+}
+__device__ __forceinline__ void gst(float2 *p, long i, float2 x) {
+  gf2_t v;
+  v.x = x.x;
+  v.y = x.y;
+  ((BPKI_GLOBAL gf2_t *)p)[i] = v;
+}
+
 // Complex storage of a GEMM operand: FP64 (double pairs) or FP32 (float pairs), read into and
 // written from double2 registers.
 template <bool F32>
@@ -370,7 +399,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
 // lane's outputs share one row of C and the stores run along M (used when M is C's unit-stride
 // index).  grid: x = workgroups per (batch, problem), y = batch, z = problem.
 constexpr int SK_MAX = 64;
-template <typename T, bool TR, bool A32 = false, bool C32 = false>
+template <typename T, bool TR, bool A32 = false, bool C32 = false, bool FULL = false>
 __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const double *const *Ap,
                                                              const double *const *Bp,
                                                              double *const *Cp) {
@@ -389,27 +418,31 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
   for (int idx = tid; idx < SK_MAX * SK_MAX; idx += 256) {
     const int k = idx / SK_MAX, n = idx % SK_MAX;
     double2 v = make_double2(0.0, 0.0);
-    if (k < d.K && n < d.N) v = B[(long)k * d.b_ki + (long)n * d.b_ni];
+    if (k < d.K && n < d.N) v = gld(B, (long)k * d.b_ki + (long)n * d.b_ni);
     Bs[0][k][n] = T(v.x);
     Bs[1][k][n] = sb * T(v.y);
   }
   __syncthreads();
-  const int ksteps = (d.K + 3) >> 2;            // 1 .. 16
-  const int ntiles = (d.N + 15) >> 4;           // 1 .. 4
+  const int ksteps = FULL ? 16 : (d.K + 3) >> 2;      // 1 .. 16
+  const int ntiles = FULL ? 4 : (d.N + 15) >> 4;      // 1 .. 4
   const int strips = (d.M + 15) >> 4;
   const int stride = gridDim.x * 4;
   const int r16 = lane & 15, kq = lane >> 4;
-  // A fragment of k-step j for this lane: row (strip * 16 + r16), k = 4 j + kq
-  auto row_off = [&](int s) -> long {
-    const int m = s * 16 + r16;
-    return m < d.M ? cidx(m, d.Mi, d.a_mo, d.a_mi) : -1;
-  };
+  // A fragment of k-step j for this lane: row (strip * 16 + r16), k = 4 j + kq.  Every load is
+  // issued: a row beyond M reads row M - 1 (its products only reach output rows that are not
+  // stored), a k beyond K reads k = K - 1 and is replaced by zero.
+  auto row_off = [&](int s) -> long { return cidx(min(s * 16 + r16, d.M - 1), d.Mi, d.a_mo, d.a_mi); };
   typedef typename XA::t av_t;            // A values stay in their storage type
   auto load_half = [&](long ro, int h, av_t (&v)[8]) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = 4 * (8 * h + q) + kq;
-      v[q] = (ro >= 0 && k < d.K) ? A[ro + (long)k * d.a_ki] : XA::zero();
+      if constexpr (FULL) {
+        v[q] = gld(A, ro + (long)k * d.a_ki);
+      } else {
+        const av_t x = gld(A, ro + (long)min(k, d.K - 1) * d.a_ki);
+        v[q] = k < d.K ? x : XA::zero();
+      }
     }
   };
   acc_t acc[4][3];
@@ -434,11 +467,14 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
           acc[t][2] = MT::mma(as, bs, acc[t][2]);
         }
       }
+      // one k step at a time: the next step's LDS reads are issued behind these MFMAs, not
+      // hoisted all at once (which would exceed the registers of two waves per SIMD)
+      if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
     }
   };
   int s = blockIdx.x * 4 + wave;
   av_t lo[8], hi[8];
-  long ro = s < strips ? row_off(s) : -1;
+  long ro = row_off(s);
   if (s < strips) {
     load_half(ro, 0, lo);
     load_half(ro, 1, hi);
@@ -449,7 +485,7 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[t][c] = (acc_t){T(0), T(0), T(0), T(0)};
     const int sn = s + stride;
-    const long ron = sn < strips ? row_off(sn) : -1;
+    const long ron = row_off(sn);
     mma_half(0, lo);
     if (sn < strips) load_half(ron, 0, lo);     // the next strip's first half is in flight ...
     mma_half(1, hi);                              // ... while this strip's second half is used
@@ -473,11 +509,11 @@ __global__ __launch_bounds__(256, 2) void gemm_stream_kernel(GemmDesc d, const d
         double vi = d.alpha_re * ci + d.alpha_im * cr;
         const long off = co + (long)n * d.c_ni;
         if (d.beta) {
-          const double2 o = XC::get(C[off]);
+          const double2 o = XC::get(gld(C, off));
           vr += o.x;
           vi += o.y;
         }
-        C[off] = XC::make(vr, vi);
+        gst(C, off, XC::make(vr, vi));
       }
     }
     ro = ron;
@@ -3193,20 +3229,28 @@ class HipBackend : public Backend {
       dim3 g(std::max(1, std::min(per, (strips + 3) / 4)), d.batch, nprob);
       const bool tr = d.c_mi == 1 && d.c_ni != 1;     // C is unit-stride along M
       stale_check("gemm_stream_kernel");
+      // K = N = 64 (the leg contractions at chi = 64): loop bounds fixed at compile time
+      const bool full = d.K == SK_MAX && d.N == SK_MAX;
+#define GSK_LAUNCH(TT, TRV, S32)                                                                  \
+  do {                                                                                            \
+    if (full)                                                                                     \
+      hipLaunchKernelGGL((gemm_stream_kernel<TT, TRV, S32, S32, true>), g, dim3(256), 0, s_, d, A, \
+                         B, C);                                                                   \
+    else                                                                                          \
+      hipLaunchKernelGGL((gemm_stream_kernel<TT, TRV, S32, S32, false>), g, dim3(256), 0, s_, d,   \
+                         A, B, C);                                                                \
+  } while (0)
       if (d.prec == 1 && st == 5) {
-        if (tr)
-          hipLaunchKernelGGL((gemm_stream_kernel<float, true, true, true>), g, dim3(256), 0, s_, d,
-                             A, B, C);
-        else
-          hipLaunchKernelGGL((gemm_stream_kernel<float, false, true, true>), g, dim3(256), 0, s_,
-                             d, A, B, C);
+        if (tr) GSK_LAUNCH(float, true, true);
+        else GSK_LAUNCH(float, false, true);
       } else if (d.prec == 1) {
-        if (tr) hipLaunchKernelGGL((gemm_stream_kernel<float, true>), g, dim3(256), 0, s_, d, A, B, C);
-        else hipLaunchKernelGGL((gemm_stream_kernel<float, false>), g, dim3(256), 0, s_, d, A, B, C);
+        if (tr) GSK_LAUNCH(float, true, false);
+        else GSK_LAUNCH(float, false, false);
       } else {
-        if (tr) hipLaunchKernelGGL((gemm_stream_kernel<double, true>), g, dim3(256), 0, s_, d, A, B, C);
-        else hipLaunchKernelGGL((gemm_stream_kernel<double, false>), g, dim3(256), 0, s_, d, A, B, C);
+        if (tr) GSK_LAUNCH(double, true, false);
+        else GSK_LAUNCH(double, false, false);
       }
+#undef GSK_LAUNCH
       launch_check("gemm_stream_kernel");
       if (rec) {
         HIPCHK(hipEventRecord(e1, s_));
