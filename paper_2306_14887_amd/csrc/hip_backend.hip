@@ -88,6 +88,10 @@ __device__ __forceinline__ float2 gld(const float2 *p, long i) {
   const gf2_t v = ((const BPKI_GLOBAL gf2_t *)p)[i];
   return make_float2(v.x, v.y);
 }
+__device__ __forceinline__ double gld(const double *p, long i) {
+  return ((const BPKI_GLOBAL double *)p)[i];
+}
+__device__ __forceinline__ void gst(double *p, long i, double x) { ((BPKI_GLOBAL double *)p)[i] = x; }
 __device__ __forceinline__ void gst(double2 *p, long i, double2 x) {
   gd2_t v;
   v.x = x.x;
@@ -221,11 +225,11 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
       typename XB::t vb = XB::zero();
       if (aok[it] && kga < kend) {
         long o = ka.uniform ? ka.base + (long)ak[it] * ka.si : cidx(kga, d.Ki, d.a_ko, d.a_ki);
-        va = A[aoff[it] + o];
+        va = gld(A, aoff[it] + o);
       }
       if (bok[it] && kgb < kend) {
         long o = kb.uniform ? kb.base + (long)bk[it] * kb.si : cidx(kgb, d.Ki, d.b_ko, d.b_ki);
-        vb = B[boff[it] + o];
+        vb = gld(B, boff[it] + o);
       }
       ra[it] = va;
       rb[it] = vb;
@@ -320,8 +324,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         return;
       }
       const double vr = d.alpha_re * cr, vi = mg == ng ? 0.0 : d.alpha_re * ci;
-      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = XC::make(vr, vi);
-      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = XC::make(vr, -vi);
+      gst(C, (long)mg * d.c_mi + (long)ng * d.c_ni, XC::make(vr, vi));
+      if (mg > ng) gst(C, (long)ng * d.c_mi + (long)mg * d.c_ni, XC::make(vr, -vi));
     };
     if (dtile) {
       auto put_block = [&](int bi, int bj, const acc_t(&a3)[3]) {
@@ -380,11 +384,11 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDesc d, const double *
         double vi = d.alpha_re * ci + d.alpha_im * cr;
         long off = roff[i][r] + coff[j];
         if (d.beta) {
-          double2 o = XC::get(C[off]);
+          double2 o = XC::get(gld(C, off));
           vr += o.x;
           vi += o.y;
         }
-        C[off] = XC::make(vr, vi);
+        gst(C, off, XC::make(vr, vi));
       }
 }
 
@@ -560,19 +564,19 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmDesc d, double *co
     }
     if (d.herm) {
       const double vr = d.alpha_re * cr, vi = mg == ng ? 0.0 : d.alpha_re * ci;
-      C[(long)mg * d.c_mi + (long)ng * d.c_ni] = XC::make(vr, vi);
-      if (mg > ng) C[(long)ng * d.c_mi + (long)mg * d.c_ni] = XC::make(vr, -vi);
+      gst(C, (long)mg * d.c_mi + (long)ng * d.c_ni, XC::make(vr, vi));
+      if (mg > ng) gst(C, (long)ng * d.c_mi + (long)mg * d.c_ni, XC::make(vr, -vi));
       continue;
     }
     double vr = d.alpha_re * cr - d.alpha_im * ci;
     double vi = d.alpha_re * ci + d.alpha_im * cr;
     long off = cidx(mg, d.Mi, d.c_mo, d.c_mi) + cidx(ng, d.Ni, d.c_no, d.c_ni);
     if (d.beta) {
-      double2 o = XC::get(C[off]);
+      double2 o = XC::get(gld(C, off));
       vr += o.x;
       vi += o.y;
     }
-    C[off] = XC::make(vr, vi);
+    gst(C, off, XC::make(vr, vi));
   }
 }
 
@@ -694,7 +698,7 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH, PAIR>::WGS)) void bp_close_
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
       const int a = PAIR ? 16 * (t >> 2) + MT::row(lane, t & 3) : 4 * t + g;
-      dst[t] = Y[base + yrow + (long)a * qs];
+      dst[t] = gld(Y, base + yrow + (long)a * qs);
     }
   };
   auto load_t = [&](const st_t *Tt, int k) {     // the T slices of chunks k .. k + G - 1
@@ -702,7 +706,7 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH, PAIR>::WGS)) void bp_close_
     for (int qq = 0; qq < G; ++qq) {
       const st_t *src = Tt + chunk_base(k + qq) + toff0;
 #pragma unroll
-      for (int u = 0; u < TU; ++u) tn[qq][u] = src[u * tstep];
+      for (int u = 0; u < TU; ++u) tn[qq][u] = gld(src, (long)u * tstep);
     }
   };
   auto store_t = [&]() {
@@ -739,7 +743,7 @@ __global__ __launch_bounds__(256, (BpCloseCfg<T, CH, PAIR>::WGS)) void bp_close_
       if constexpr (!PAIR) {
         const double2 *M = reinterpret_cast<const double2 *>(Mp[p]);
         for (int idx = tid; idx < CC; idx += 256) {
-          const double2 v = M[idx];
+          const double2 v = gld(M, idx);
           Ms[0][idx / CH][idx % CH] = T(v.x);
           Ms[1][idx / CH][idx % CH] = T(v.y);
         }
@@ -837,8 +841,8 @@ __global__ __launch_bounds__(256) void bp_close_reduce_kernel(int ch, int G, int
     }
   }
   double2 *O = reinterpret_cast<double2 *>(Op[p]);
-  O[b * ch + bp] = make_double2(re, b == bp ? 0.0 : im);
-  if (b > bp) O[bp * ch + b] = make_double2(re, -im);
+  gst(O, (long)b * ch + bp, make_double2(re, b == bp ? 0.0 : im));
+  if (b > bp) gst(O, (long)bp * ch + b, make_double2(re, -im));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1495,7 +1499,7 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
   // Hermitian part of the input, lower triangle
   for (int i = wave; i < n; i += nw)
     for (int j = lane; j <= i; j += 64) {
-      double2 a = src[(size_t)i * lda + j], b = src[(size_t)j * lda + i];
+      double2 a = gld(src, (long)i * lda + j), b = gld(src, (long)j * lda + i);
       pel(i, j) = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
     }
   __syncthreads();
@@ -1505,9 +1509,11 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
     // n <= 128, matrix packed in LDS, with look-ahead: while waves 1.. apply the rank-2 update
     // of step k to columns k+2.., wave 0 updates column k+1 and forms reflector k+1 from it in
     // registers, so every step has two barriers and no serial reflector phase.  The reflector
-    // vector and tau are double buffered (vb[b], tau_b[b]).
+    // vector and tau are double buffered: v_s[b VB + i] (b = 0: v_s, b = 1: x1_s) and tau_b[b].
+    // (The buffer is chosen by an offset from v_s, not by a pointer picked at run time, which
+    // the compiler could not keep in LDS and would access as flat memory.)
     __shared__ double2 tau_b[2];
-    double2 *vb[2] = {v_s, x1_s};
+    constexpr int VB = 2 * NMAX;
     // reflector k from its column col[i] = A(k+1+i, k), i < m (this lane: i = lane + 64 t), and
     // the diagonal dkk = A(k, k); wave 0 only
     auto reflect = [&](int k, const double2 (&col)[2], double dkk, int b) {
@@ -1534,7 +1540,7 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
         const int i = lane + 64 * t;
         if (i < m) {
           const double2 vi = i == 0 ? make_double2(1.0, 0.0) : cmul(col[t], scale);
-          vb[b][i] = vi;
+          v_s[b * VB + i] = vi;
           hh[(size_t)k * n + k + 1 + i] = vi;
         }
       }
@@ -1566,7 +1572,7 @@ __global__ __launch_bounds__(NT) void eigh_tridiag_kernel(int n, int lda, const 
         __syncthreads();
         continue;
       }
-      const double2 *v = vb[b];
+      const double2 *v = v_s + b * VB;
       {
         // x = tau S v over the trailing block S (rows / columns k+1 .. n-1): TPR = 8 threads per
         // row; row gi of S is row gi of the packed triangle up to the diagonal, then column gi
@@ -2141,7 +2147,7 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, int ncol
       rank += (li > lj) || (li == lj && i < j);
     }
     src[rank] = j;
-    if (blockIdx.x == 0) ev[rank] = lj;
+    if (blockIdx.x == 0) gst(ev, rank, lj);
   }
   __syncthreads();
   const int cols = min(CB, ncols - c0);
@@ -2188,7 +2194,7 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, int ncol
   double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
   for (int idx = tid; idx < n * cols; idx += 256) {
     const int r = idx / cols, cc = idx % cols;
-    vo[(size_t)r * n + c0 + cc] = Vb[r * CB + cc];
+    gst(vo, (long)r * n + c0 + cc, Vb[r * CB + cc]);
   }
 }
 
@@ -2223,7 +2229,7 @@ __global__ __launch_bounds__(1024) void chol_init_kernel(int n, const double *co
   const double2 *g = reinterpret_cast<const double2 *>(G[prob]);
   for (int idx = tid; idx < n * n; idx += nt) {
     const int i = idx / n, j = idx % n;
-    const double2 x = g[(size_t)i * n + j], y = g[(size_t)j * n + i];
+    const double2 x = gld(g, (long)i * n + j), y = gld(g, (long)j * n + i);
     W[idx] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
     L[idx] = make_double2(0.0, 0.0);
     X[idx] = make_double2(0.0, 0.0);
@@ -2231,7 +2237,7 @@ __global__ __launch_bounds__(1024) void chol_init_kernel(int n, const double *co
   double m = 0.0;
   for (int i = tid; i < n; i += nt) {
     perm[i] = i;
-    const double d = g[(size_t)i * n + i].x;
+    const double d = gld(g, (long)i * n + i).x;
     dg[i] = d;
     m = fmax(m, d);
   }
@@ -2391,14 +2397,14 @@ __global__ __launch_bounds__(1024) void chol_out_kernel(int n, double *const *R,
   for (int idx = tid; idx < n * n; idx += nt) {
     const int k = idx / n, c = idx % n;
     const double2 l = L[(size_t)c * n + k];
-    Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
-    Wo[idx] = make_double2(0.0, 0.0);
+    gst(Ro, idx, k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0));
+    gst(Wo, idx, make_double2(0.0, 0.0));
   }
   __syncthreads();
   for (int idx = tid; idx < r * r; idx += nt) {
     const int kk = idx / r, k = idx % r;
     const double2 x = X[(size_t)k * n + kk];
-    Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
+    gst(Wo, (long)perm[kk] * n + k, make_double2(x.x, -x.y));
   }
 }
 
@@ -2423,13 +2429,13 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
   const double2 *g = reinterpret_cast<const double2 *>(G[prob]);
   for (int i = wave; i < n; i += nw)
     for (int j = lane; j <= i; j += 64) {
-      const double2 a = g[(size_t)i * n + j], b = g[(size_t)j * n + i];
+      const double2 a = gld(g, (long)i * n + j), b = gld(g, (long)j * n + i);
       P[pk_idx(i, j)] = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
     }
   for (int idx = tid; idx < n * n; idx += nt) L[idx] = make_double2(0.0, 0.0);
   for (int i = tid; i < n; i += nt) {
     perm[i] = i;
-    dg[i] = g[(size_t)i * n + i].x;
+    dg[i] = gld(g, (long)i * n + i).x;
   }
   __syncthreads();
   if (wave == 0) {
@@ -2531,15 +2537,15 @@ __global__ __launch_bounds__(1024) void gram_chol_lds_kernel(int n, const double
   for (int idx = tid; idx < n * n; idx += nt) {
     const int k = idx / n, c = idx % n;
     const double2 l = L[(size_t)c * n + k];
-    Ro[idx] = k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0);
-    Wo[idx] = make_double2(0.0, 0.0);
+    gst(Ro, idx, k < r ? make_double2(l.x, -l.y) : make_double2(0.0, 0.0));
+    gst(Wo, idx, make_double2(0.0, 0.0));
   }
   __syncthreads();
   for (int idx = tid; idx < r * r; idx += nt) {
     const int kk = idx / r, k = idx % r;     // Wsc[perm[kk]][k] = conj(X[k][kk]), kk <= k
     if (kk > k) continue;
     const double2 x = X[pk_idx(k, kk)];
-    Wo[(size_t)perm[kk] * n + k] = make_double2(x.x, -x.y);
+    gst(Wo, (long)perm[kk] * n + k, make_double2(x.x, -x.y));
   }
 }
 
@@ -2551,10 +2557,10 @@ __global__ void rx_kernel(double *const *T, const int64_t *half, double c, doubl
   int64_t h = half[blockIdx.y];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < h;
        i += (int64_t)gridDim.x * blockDim.x) {
-    double2 a = t[i], b = t[h + i];
+    double2 a = gld(t, i), b = gld(t, h + i);
     // [c, -is; -is, c]
-    t[i] = make_double2(c * a.x + s * b.y, c * a.y - s * b.x);
-    t[h + i] = make_double2(s * a.y + c * b.x, -s * a.x + c * b.y);
+    gst(t, i, make_double2(c * a.x + s * b.y, c * a.y - s * b.x));
+    gst(t, h + i, make_double2(s * a.y + c * b.x, -s * a.x + c * b.y));
   }
 }
 
@@ -2569,9 +2575,9 @@ __global__ __launch_bounds__(256) void msg_sqrt_kernel(int n, const double *cons
   const double2 *W = reinterpret_cast<const double2 *>(vecs[blockIdx.x]);
   double2 *x = reinterpret_cast<double2 *>(X[blockIdx.x]);
   double2 *xp = reinterpret_cast<double2 *>(Xp[blockIdx.x]);
-  const double lmax = l[0] > 0 ? l[0] : 0.0;
+  const double l0 = gld(l, 0), lmax = l0 > 0 ? l0 : 0.0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double lk = l[k];
+    const double lk = gld(l, k);
     fs[k] = lk > 0 ? sqrt(lk) : 0.0;
     gs[k] = (lk > cut * lmax && lk > 0) ? 1.0 / sqrt(lk) : 0.0;
   }
@@ -2581,7 +2587,7 @@ __global__ __launch_bounds__(256) void msg_sqrt_kernel(int n, const double *cons
     const double2 *wi = W + (size_t)i * n, *wj = W + (size_t)j * n;
     double sr = 0, si = 0, pr = 0, pi = 0;
     for (int k = 0; k < n; ++k) {
-      const double2 a = wi[k], b = wj[k];
+      const double2 a = gld(wi, k), b = gld(wj, k);
       // a * conj(b)
       const double re = a.x * b.x + a.y * b.y, im = a.y * b.x - a.x * b.y;
       const double f = fs[k], g = gs[k];
@@ -2590,8 +2596,8 @@ __global__ __launch_bounds__(256) void msg_sqrt_kernel(int n, const double *cons
       pr += g * re;
       pi += g * im;
     }
-    x[idx] = make_double2(sr, si);
-    xp[idx] = make_double2(pr, pi);
+    gst(x, idx, make_double2(sr, si));
+    gst(xp, idx, make_double2(pr, pi));
   }
 }
 
@@ -2604,8 +2610,8 @@ __global__ void theta_phase_kernel(int rB, int rS, double *const *Th, double gsr
     const int row = idx / cols, col = idx - row * cols;
     const bool same = (row & 1) == (col & 1);
     const double gr = same ? gsr : gdr, gi = same ? gsi : gdi;
-    const double2 v = t[idx];
-    t[idx] = make_double2(gr * v.x - gi * v.y, gr * v.y + gi * v.x);
+    const double2 v = gld(t, idx);
+    gst(t, idx, make_double2(gr * v.x - gi * v.y, gr * v.y + gi * v.x));
   }
 }
 
@@ -2613,12 +2619,15 @@ __global__ void svd_finish_kernel(int n, int chi, const double *const *evals,
                                   const double *const *vecs, double *const *Vs, double *const *S,
                                   int *kout, double *disc, double *const *mA, double *const *mB,
                                   double cutoff) {
-  __shared__ double sig[512];
+  __shared__ double sig[512], l[512];      // the eigenvalues staged in LDS for the serial scan
   __shared__ int ks;
   __shared__ double nrm, ssum;
   const int p = blockIdx.x;
-  const double *l = evals[p];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) sig[i] = sqrt(fmax(l[i], 0.0));
+  const double *lg = evals[p];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    l[i] = gld(lg, i);
+    sig[i] = sqrt(fmax(l[i], 0.0));
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     // Keep min(chi, #{lambda_i > cutoff * lambda_1}): the cutoff acts on the Schmidt weights
@@ -2646,22 +2655,22 @@ __global__ void svd_finish_kernel(int n, int chi, const double *const *evals,
   __syncthreads();
   const int k = ks;
   double *Sp = S[p];
-  for (int a = threadIdx.x; a < chi; a += blockDim.x) Sp[a] = a < k ? sig[a] / nrm : 0.0;
+  for (int a = threadIdx.x; a < chi; a += blockDim.x) gst(Sp, a, a < k ? sig[a] / nrm : 0.0);
   const double2 *V = reinterpret_cast<const double2 *>(vecs[p]);
   double2 *vs = reinterpret_cast<double2 *>(Vs[p]);
   for (int idx = threadIdx.x; idx < n * chi; idx += blockDim.x) {
     int c = idx / chi, a = idx % chi;
     double2 v = make_double2(0.0, 0.0);
-    if (a < k) { double2 w = V[(size_t)c * n + a]; v = make_double2(w.x / sig[a], w.y / sig[a]); }
-    vs[idx] = v;
+    if (a < k) { double2 w = gld(V, (long)c * n + a); v = make_double2(w.x / sig[a], w.y / sig[a]); }
+    gst(vs, idx, v);
   }
   double2 *ma = reinterpret_cast<double2 *>(mA[p]);
   double2 *mb = reinterpret_cast<double2 *>(mB[p]);
   for (int idx = threadIdx.x; idx < chi * chi; idx += blockDim.x) {
     int i = idx / chi, j = idx % chi;
     double v = (i == j && i < k) ? (sig[i] / nrm) / ssum : 0.0;
-    ma[idx] = make_double2(v, 0.0);
-    mb[idx] = make_double2(v, 0.0);
+    gst(ma, idx, make_double2(v, 0.0));
+    gst(mb, idx, make_double2(v, 0.0));
   }
 }
 
@@ -2687,19 +2696,19 @@ __global__ void split_sqrt_kernel(int rowsB, int rowsS, int n, int chi, const do
        idx += gridDim.x * blockDim.x) {
     if (idx < totB) {
       int a = idx % chi;
-      double q = sqrt(s[a]);
-      double2 x = u[idx];
-      rb[idx] = make_double2(q * x.x, q * x.y);
+      double q = sqrt(gld(s, a));
+      double2 x = gld(u, idx);
+      gst(rb, idx, make_double2(q * x.x, q * x.y));
     } else {
       int j = idx - totB;
       int row = j / chi, a = j % chi;
       double2 o = make_double2(0.0, 0.0);
       if (a < n) {
-        double q = sqrt(s[a]);
-        double2 x = v[(size_t)row * n + a];
+        double q = sqrt(gld(s, a));
+        double2 x = gld(v, (long)row * n + a);
         o = make_double2(q * x.x, -q * x.y);
       }
-      rs[j] = o;
+      gst(rs, j, o);
     }
   }
 }
@@ -2727,7 +2736,7 @@ __global__ __launch_bounds__(1024) void normalize_residual_kernel(int chi, doubl
   const double2 *o = reinterpret_cast<const double2 *>(Mo[p]);
   double tr = 0, ti = 0;
   for (int i = threadIdx.x; i < chi; i += blockDim.x) {
-    double2 v = m[(size_t)i * chi + i];
+    double2 v = gld(m, (long)i * chi + i);
     tr += v.x;
     ti += v.y;
   }
@@ -2740,10 +2749,10 @@ __global__ __launch_bounds__(1024) void normalize_residual_kernel(int chi, doubl
   double acc = 0;
 #pragma unroll 8
   for (int idx = threadIdx.x; idx < chi * chi; idx += blockDim.x) {
-    double2 v = m[idx];
+    double2 v = gld(m, idx);
     double2 w = make_double2(v.x * ir - v.y * ii, v.x * ii + v.y * ir);
-    m[idx] = w;
-    double2 q = o[idx];
+    gst(m, idx, w);
+    double2 q = gld(o, idx);
     double dx = w.x - q.x, dy = w.y - q.y;
     acc += dx * dx + dy * dy;
   }
@@ -2762,16 +2771,16 @@ __global__ __launch_bounds__(256) void sqrt_scale_kernel(int n, const double *co
   const double *l = evals[p];
   const double2 *W = reinterpret_cast<const double2 *>(vecs[p]);
   double2 *wf = ws + (size_t)p * 2 * n * n, *wg = wf + (size_t)n * n;
-  const double lmax = l[0] > 0 ? l[0] : 0.0;
+  const double l0 = gld(l, 0), lmax = l0 > 0 ? l0 : 0.0;
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double lk = l[k];
+    const double lk = gld(l, k);
     fs[k] = lk > 0 ? sqrt(lk) : 0.0;
     gs[k] = (lk > cut * lmax && lk > 0) ? 1.0 / sqrt(lk) : 0.0;
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
     const int k = idx % n;
-    const double2 w = W[idx];
+    const double2 w = gld(W, idx);
     wf[idx] = make_double2(w.x * fs[k], w.y * fs[k]);
     wg[idx] = make_double2(w.x * gs[k], w.y * gs[k]);
   }
@@ -2960,7 +2969,7 @@ __global__ __launch_bounds__(256) void rho_dot_kernel(const double *const *Y,
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double2 y0 = y[i], y1 = y[L + i], t0 = t[i], t1 = t[L + i];
+    const double2 y0 = gld(y, i), y1 = gld(y, L + i), t0 = gld(t, i), t1 = gld(t, L + i);
     // y_s * conj(t_s')
     acc[0] += y0.x * t0.x + y0.y * t0.y; acc[1] += y0.y * t0.x - y0.x * t0.y;
     acc[2] += y0.x * t1.x + y0.y * t1.y; acc[3] += y0.y * t1.x - y0.x * t1.y;
