@@ -2122,9 +2122,8 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, int ncol
                                                                  double *const *vecs) {
   constexpr int CB = NMAX > 256 ? 4 : 16;          // eigenvector columns per workgroup
   __shared__ double2 Vb[NMAX * CB];
-  __shared__ double2 vk[NMAX];
+  __shared__ double2 vk[2][NMAX];
   __shared__ double2 part[4][CB];
-  __shared__ double2 wk[CB];
   __shared__ double dsh[NMAX];
   __shared__ int src[NMAX];
   const int prob = blockIdx.y, c0 = blockIdx.x * CB;
@@ -2158,37 +2157,62 @@ __global__ __launch_bounds__(256) void eigh_backtransform_kernel(int n, int ncol
   __syncthreads();
   constexpr int RG = 256 / CB;                        // row groups per column
   const int c = tid & (CB - 1), part_id = tid / CB;
-  for (int k = n - 2; k >= 0; --k) {
-    const double2 tau = tau_g[k];
-    if (tau.x == 0.0 && tau.y == 0.0) continue;
-    const int m = n - 1 - k;
-    for (int i = tid; i < m; i += 256) vk[i] = hh[(size_t)k * n + k + 1 + i];
-    __syncthreads();
-    double2 acc = make_double2(0.0, 0.0);
-    for (int i = part_id; i < m; i += RG) {
-      const double2 v = vk[i], x = Vb[(k + 1 + i) * CB + c];
-      acc.x += v.x * x.x + v.y * x.y;      // conj(v) x
-      acc.y += v.x * x.y - v.y * x.x;
-    }
+  // The reflectors are applied in reverse order.  Reflector k - 1's vector (and tau) is loaded
+  // from the workspace while reflector k is applied and staged in the other vk buffer at the
+  // end of the step, so no step waits on a global load; every thread forms w = tau v^H x for its
+  // own column from the four waves' partial sums, so a step has two barriers.
+  constexpr int VPT = (NMAX + 255) / 256;           // vector elements per thread
+  auto vload = [&](int k, double2 (&dst)[VPT]) {   // reflector k's vector (0 past its end)
 #pragma unroll
-    for (int o = CB; o < 64; o <<= 1) {    // the wave's lanes of this column
-      acc.x += __shfl_xor(acc.x, o, 64);
-      acc.y += __shfl_xor(acc.y, o, 64);
+    for (int e = 0; e < VPT; ++e) {
+      const int i = tid + 256 * e;
+      dst[e] = (k >= 0 && i < n - 1 - k) ? gld(hh, (long)k * n + k + 1 + i) : make_double2(0.0, 0.0);
     }
-    if ((tid & 63) < CB) part[tid >> 6][c] = acc;
-    __syncthreads();
-    if (tid < CB) {
-      double2 t = make_double2(part[0][tid].x + part[1][tid].x + part[2][tid].x + part[3][tid].x,
-                               part[0][tid].y + part[1][tid].y + part[2][tid].y + part[3][tid].y);
-      wk[tid] = cmul(tau, t);
+  };
+  auto vstore = [&](int buf, const double2 (&src)[VPT]) {
+#pragma unroll
+    for (int e = 0; e < VPT; ++e)
+      if (tid + 256 * e < NMAX) vk[buf][tid + 256 * e] = src[e];
+  };
+  auto tload = [&](int k) -> double2 { return k >= 0 ? gld(tau_g, k) : make_double2(0.0, 0.0); };
+  double2 vn[VPT];
+  vload(n - 2, vn);
+  vstore(0, vn);
+  vload(n - 3, vn);
+  double2 taun = tload(n - 3), tau = tload(n - 2);
+  __syncthreads();
+  int b = 0;
+  for (int k = n - 2; k >= 0; --k, b ^= 1) {
+    const int m = n - 1 - k;
+    if (tau.x != 0.0 || tau.y != 0.0) {
+      const double2 *v = vk[b];
+      double2 acc = make_double2(0.0, 0.0);
+      for (int i = part_id; i < m; i += RG) {
+        const double2 vv = v[i], x = Vb[(k + 1 + i) * CB + c];
+        acc.x += vv.x * x.x + vv.y * x.y;      // conj(v) x
+        acc.y += vv.x * x.y - vv.y * x.x;
+      }
+#pragma unroll
+      for (int o = CB; o < 64; o <<= 1) {    // the wave's lanes of this column
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+      }
+      if ((tid & 63) < CB) part[tid >> 6][c] = acc;
+      __syncthreads();
+      const double2 t = make_double2(part[0][c].x + part[1][c].x + part[2][c].x + part[3][c].x,
+                                     part[0][c].y + part[1][c].y + part[2][c].y + part[3][c].y);
+      const double2 w = cmul(tau, t);
+      for (int idx = tid; idx < m * CB; idx += 256) {
+        const int i = idx / CB;             // (idx % CB == c: 256 is a multiple of CB)
+        const double2 u = cmul(v[i], w);
+        double2 &x = Vb[(k + 1 + i) * CB + c];
+        x = make_double2(x.x - u.x, x.y - u.y);
+      }
     }
-    __syncthreads();
-    for (int idx = tid; idx < m * CB; idx += 256) {
-      const int i = idx / CB, cc = idx % CB;
-      const double2 u = cmul(vk[i], wk[cc]);
-      double2 &x = Vb[(k + 1 + i) * CB + cc];
-      x = make_double2(x.x - u.x, x.y - u.y);
-    }
+    vstore(b ^ 1, vn);
+    tau = taun;
+    vload(k - 2, vn);
+    taun = tload(k - 2);
     __syncthreads();
   }
   double2 *vo = reinterpret_cast<double2 *>(vecs[prob]);
