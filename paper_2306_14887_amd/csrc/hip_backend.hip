@@ -2750,38 +2750,48 @@ __device__ double block_sum(double v, double *sh) {
   return r;   // valid on thread 0
 }
 
-__global__ __launch_bounds__(1024) void normalize_residual_kernel(int chi, double *const *Mn,
-                                                                 const double *const *Mo,
-                                                                 double *res) {
-  __shared__ double sh[16];
-  __shared__ double trr, tri;
-  const int p = blockIdx.x;
+// Message p: divide by its complex trace, then the residual |new - old|_F.  256 threads, wave sums
+// by DPP, the four waves' sums added in a fixed order (two barriers in all).
+__global__ __launch_bounds__(256) void normalize_residual_kernel(int chi, double *const *Mn,
+                                                                const double *const *Mo,
+                                                                double *res) {
+  __shared__ double sh[3][4];
+  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double2 *m = reinterpret_cast<double2 *>(Mn[p]);
   const double2 *o = reinterpret_cast<const double2 *>(Mo[p]);
   double tr = 0, ti = 0;
-  for (int i = threadIdx.x; i < chi; i += blockDim.x) {
-    double2 v = gld(m, (long)i * chi + i);
+  for (int i = tid; i < chi; i += 256) {
+    const double2 v = gld(m, (long)i * chi + i);
     tr += v.x;
     ti += v.y;
   }
-  double a = block_sum<1024>(tr, sh);
-  double b = block_sum<1024>(ti, sh);
-  if (threadIdx.x == 0) { trr = a; tri = b; }
+  tr = wave_sum(tr);
+  ti = wave_sum(ti);
+  if (lane == 0) {
+    sh[0][w] = tr;
+    sh[1][w] = ti;
+  }
   __syncthreads();
-  double den = trr * trr + tri * tri;
-  double ir = trr / den, ii = -tri / den;   // 1/tr
+  const double trr = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+  const double tri = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  const double den = trr * trr + tri * tri;
+  const double ir = trr / den, ii = -tri / den;   // 1/tr
   double acc = 0;
-#pragma unroll 8
-  for (int idx = threadIdx.x; idx < chi * chi; idx += blockDim.x) {
-    double2 v = gld(m, idx);
-    double2 w = make_double2(v.x * ir - v.y * ii, v.x * ii + v.y * ir);
-    gst(m, idx, w);
-    double2 q = gld(o, idx);
-    double dx = w.x - q.x, dy = w.y - q.y;
+#pragma unroll 4
+  for (int idx = tid; idx < chi * chi; idx += 256) {
+    const double2 v = gld(m, idx), q = gld(o, idx);
+    const double2 nw = make_double2(v.x * ir - v.y * ii, v.x * ii + v.y * ir);
+    gst(m, idx, nw);
+    const double dx = nw.x - q.x, dy = nw.y - q.y;
     acc += dx * dx + dy * dy;
   }
-  double s = block_sum<1024>(acc, sh);
-  if (threadIdx.x == 0) res[p] = (trr > 0 && isfinite(s)) ? sqrt(s) : INFINITY;
+  acc = wave_sum(acc);
+  if (lane == 0) sh[2][w] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    const double sq = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
+    res[p] = (trr > 0 && isfinite(sq)) ? sqrt(sq) : INFINITY;
+  }
 }
 
 // For n > 64 the two products of msg_sqrt_kernel run on the GEMM: this kernel forms
@@ -3872,7 +3882,7 @@ class HipBackend : public Backend {
   void normalize_residual(int chi, double *const *Mn, const double *const *Mo, double *res,
                           int nprob) override {
     stale_check("normalize_residual_kernel");
-    hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(1024), 0, s_, chi, Mn, Mo,
+    hipLaunchKernelGGL(normalize_residual_kernel, dim3(nprob), dim3(256), 0, s_, chi, Mn, Mo,
                        res);
     launch_check("normalize_residual_kernel");
   }
