@@ -81,6 +81,13 @@ CASES = [
     ("stream_mfast_out", dict(M=1000, N=50, K=64, a_mi=1, a_ki=1000, b_ki=50, b_ni=1,
                               c_mi=1, c_ni=1000, conjB=1, beta=1, alpha_re=-0.5,
                               alpha_im=1.25), 2),
+    # K = N = 64 (the fixed-bound variant) with M not a multiple of the 16-row strip (the last
+    # strip's rows past M read a clamped row), in both output orientations
+    ("stream_full_ragged", dict(M=1000, N=64, K=64, a_mi=64, a_ki=1, b_ki=64, b_ni=1,
+                                c_mi=64, c_ni=1, conjA=1, beta=1, alpha_re=0.5,
+                                alpha_im=-1.0), 2),
+    ("stream_full_ragged_mfast", dict(M=1000, N=64, K=64, a_mi=1, a_ki=1000, b_ki=1, b_ni=64,
+                                      c_mi=1, c_ni=1000, conjB=1), 3),
 ]
 
 
